@@ -1,0 +1,228 @@
+"""CPU oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never calls it, and the
+two share no code.  The C source is ``oracle.c``; this module compiles it with
+gcc into ``liboracle.so`` next to it and wraps it with ctypes.
+
+Every function computes what the paper's definition of sorting fixes (stable,
+ascending, ties in input order) by the plainest available route; see the header
+comment of ``oracle.c`` for the section each part follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MLP_HIDDEN = 64
+MLP_NUM_PARAMS = 4353
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` with gcc (fp64, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11",
+             "-shared", "-fPIC", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    lib.oracle_less_f64.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.oracle_less_f64.restype = ctypes.c_int
+    lib.oracle_sort_f64.argtypes = [P, I64]
+    lib.oracle_sort_f64.restype = ctypes.c_int
+    lib.oracle_sort_kv.argtypes = [P, P, I64]
+    lib.oracle_sort_kv.restype = ctypes.c_int
+    lib.oracle_segsort_f64.argtypes = [P, P, I64]
+    lib.oracle_segsort_f64.restype = ctypes.c_int
+    lib.oracle_segsort_kv.argtypes = [P, P, P, I64]
+    lib.oracle_segsort_kv.restype = ctypes.c_int
+    lib.oracle_rank_f64.argtypes = [P, I64, P, I64, P]
+    lib.oracle_rank_f64.restype = None
+    lib.oracle_rank_u64.argtypes = [P, I64, P, I64, P]
+    lib.oracle_rank_u64.restype = None
+    lib.oracle_frog_model.argtypes = [P, I64, ctypes.c_int, P, P, P, P, I64, P]
+    lib.oracle_frog_model.restype = I64
+    lib.oracle_frog_geometry.argtypes = [I64, ctypes.c_int, P]
+    lib.oracle_frog_geometry.restype = I64
+    lib.oracle_mlp_num_params.argtypes = []
+    lib.oracle_mlp_num_params.restype = ctypes.c_int
+    lib.oracle_mlp_forward.argtypes = [P, P, I64, P]
+    lib.oracle_mlp_forward.restype = None
+    lib.oracle_mlp_loss_grad.argtypes = [P, P, P, I64, P]
+    lib.oracle_mlp_loss_grad.restype = ctypes.c_double
+    lib.oracle_adam_step.argtypes = [P, P, P, P, I64, I64, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.oracle_adam_step.restype = None
+    assert lib.oracle_mlp_num_params() == MLP_NUM_PARAMS
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+def less_f64(a: float, b: float) -> bool:
+    """The comparison every f64 result is defined by (NaN last, -0 == +0)."""
+    return bool(_load().oracle_less_f64(float(a), float(b)))
+
+
+def sort_f64(x: np.ndarray) -> np.ndarray:
+    """Stable ascending sort of float64 keys; returns a new array."""
+    y = np.array(x, dtype=np.float64, copy=True, order="C")
+    if _load().oracle_sort_f64(_ptr(y), y.size) != 0:
+        raise MemoryError("oracle_sort_f64: allocation failed")
+    return y
+
+
+def sort_kv(keys: np.ndarray, vals: np.ndarray):
+    """Stable ascending sort of uint64 keys carrying uint32 values."""
+    k = np.array(keys, dtype=np.uint64, copy=True, order="C")
+    v = np.array(vals, dtype=np.uint32, copy=True, order="C")
+    if k.shape != v.shape:
+        raise ValueError("keys and vals differ in shape")
+    if _load().oracle_sort_kv(_ptr(k), _ptr(v), k.size) != 0:
+        raise MemoryError("oracle_sort_kv: allocation failed")
+    return k, v
+
+
+def segsort_f64(x: np.ndarray, offsets: np.ndarray) -> np.ndarray:
+    """Sort every segment x[offsets[i]:offsets[i+1]] on its own."""
+    y = np.array(x, dtype=np.float64, copy=True, order="C")
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    if off.size and off[-1] > y.size:
+        raise ValueError("offsets beyond the array")
+    rc = _load().oracle_segsort_f64(_ptr(y), _ptr(off), max(off.size - 1, 0))
+    if rc == -2:
+        raise ValueError("offsets must be non-decreasing and start at >= 0")
+    if rc != 0:
+        raise MemoryError("oracle_segsort_f64: allocation failed")
+    return y
+
+
+def segsort_kv(keys: np.ndarray, vals: np.ndarray, offsets: np.ndarray):
+    k = np.array(keys, dtype=np.uint64, copy=True, order="C")
+    v = np.array(vals, dtype=np.uint32, copy=True, order="C")
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    if off.size and off[-1] > k.size:
+        raise ValueError("offsets beyond the array")
+    rc = _load().oracle_segsort_kv(_ptr(k), _ptr(v), _ptr(off), max(off.size - 1, 0))
+    if rc == -2:
+        raise ValueError("offsets must be non-decreasing and start at >= 0")
+    if rc != 0:
+        raise MemoryError("oracle_segsort_kv: allocation failed")
+    return k, v
+
+
+def rank_f64(x: np.ndarray, idx) -> np.ndarray:
+    """Output position of each x[idx[q]] under the stable ascending definition."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros(idx.size, dtype=np.int64)
+    _load().oracle_rank_f64(_ptr(x), x.size, _ptr(idx), idx.size, _ptr(out))
+    return out
+
+
+def rank_u64(x: np.ndarray, idx) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros(idx.size, dtype=np.int64)
+    _load().oracle_rank_u64(_ptr(x), x.size, _ptr(idx), idx.size, _ptr(out))
+    return out
+
+
+def frog_model(keys: np.ndarray, g: int = 1, max_snap: int = 0):
+    """Run the instrumented Frogsort model (g=1: Frogsort1, g=2: Frogsort0
+    triplets) as a top-level left node.
+
+    Returns a dict with the sorted keys, the input index of every output
+    element, the slot labels after setup, the label snapshots taken after every
+    merge (and, for g=2, every triplet), and the comparison/move counts.
+    """
+    keys = np.ascontiguousarray(keys, dtype=np.float64)
+    n = keys.size
+    if n % g:
+        raise ValueError("n must be a multiple of g")
+    u = n // g
+    nslots = n + n // 2
+    out_k = np.zeros(n, dtype=np.float64)
+    out_l = np.zeros(n, dtype=np.int64)
+    setup = np.zeros(max(nslots, 1), dtype=np.int64)
+    trace = np.zeros((max(max_snap, 1), max(nslots, 1)), dtype=np.int64)
+    counts = np.zeros(3, dtype=np.int64)
+    ns = _load().oracle_frog_model(_ptr(keys), u, g, _ptr(out_k), _ptr(out_l),
+                                   _ptr(setup), _ptr(trace), max_snap, _ptr(counts))
+    if ns < 0:
+        raise MemoryError("oracle_frog_model: allocation failed")
+    return {
+        "keys": out_k, "labels": out_l, "setup": setup[:nslots],
+        "trace": trace[: int(counts[2]), :nslots], "compares": int(counts[0]),
+        "moves": int(counts[1]), "nslots": int(ns),
+    }
+
+
+def frog_geometry(n: int, depth: int) -> np.ndarray:
+    """Nodes of the Frogsort1 tree at `depth` (left to right), each as
+    (region start, data size, is_left, data start, input offset)."""
+    out = np.zeros((1 << depth, 5), dtype=np.int64)
+    k = _load().oracle_frog_geometry(n, depth, _ptr(out))
+    return out[:k]
+
+
+def mlp_forward(params: np.ndarray, u: np.ndarray) -> np.ndarray:
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    assert p.size == MLP_NUM_PARAMS
+    y = np.zeros(u.size, dtype=np.float64)
+    _load().oracle_mlp_forward(_ptr(p), _ptr(u), u.size, _ptr(y))
+    return y
+
+
+def mlp_loss_grad(params: np.ndarray, u: np.ndarray, t: np.ndarray, want_grad=True):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    assert p.size == MLP_NUM_PARAMS and u.size == t.size
+    g = np.zeros(MLP_NUM_PARAMS, dtype=np.float64) if want_grad else None
+    loss = _load().oracle_mlp_loss_grad(_ptr(p), _ptr(u), _ptr(t), u.size,
+                                        _ptr(g) if want_grad else ctypes.c_void_p(0))
+    return loss, g
+
+
+def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of float64 arrays params, m, v."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    _load().oracle_adam_step(_ptr(params), _ptr(g), _ptr(m), _ptr(v), params.size,
+                             int(step), lr, beta1, beta2, eps)
+
+
+# parameter slices (same layout as the C code)
+def mlp_slices(h: int = MLP_HIDDEN):
+    o = 0
+    sl = {}
+    for name, size in (("W1", h), ("b1", h), ("W2", h * h), ("b2", h), ("w3", h), ("b3", 1)):
+        sl[name] = slice(o, o + size)
+        o += size
+    return sl

@@ -1,0 +1,510 @@
+/*
+ * CPU oracle for the greeNsort stable-sorting path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this file's library.  It shares no
+ * code, header, helper or constant with the GPU library and must never be
+ * used as a fallback for it.
+ *
+ * Everything here is written to be slow and obviously correct:
+ *
+ *   - oracle_sort_*  : the result the paper's task defines ("Definition of
+ *     sorting": stable ascending order with ties kept in input order read from
+ *     left to right, the AscLeft target; "Values and principles / Stability").
+ *     It is computed by the prototypical stable mergesort of the section
+ *     "Merging or partitioning?" (one full-size buffer, top-down, take the left
+ *     element unless the right one is strictly smaller).  Frogsort reaches this
+ *     same result; the oracle does not implement Frogsort.
+ *   - oracle_rank_*  : the same definition written as a count, usable one
+ *     element at a time on arrays too large to sort on the CPU in a test.
+ *   - oracle_frog_*  : an instrumented model of the paper's Frogsort0/Frogsort1
+ *     recursion ("Symmetric merging", "Frogsort0", "Frogsort1") used only to
+ *     pin the memory layout and the adaptivity counts the paper states.
+ *   - oracle_mlp_*   : an fp64 forward pass, MSE loss, backward pass and Adam
+ *     step for the 1-64-64-1 ReLU network used by the learned bucket path
+ *     (not part of the paper; parity of the GPU gradients is checked here).
+ *
+ * Comparison (the paper only asks for comparison sorting of doubles): less(a,b)
+ * is IEEE a<b, except that every NaN is greater than every non-NaN and NaNs tie
+ * with each other.  -0.0 and +0.0 therefore tie and keep their input order.
+ * Unsigned 64-bit keys compare with unsigned <.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* comparison                                                                */
+/* ------------------------------------------------------------------------ */
+
+int oracle_less_f64(double a, double b)
+{
+    if (isnan(a)) return 0;          /* NaN is never less than anything */
+    if (isnan(b)) return 1;          /* non-NaN is less than NaN        */
+    return a < b;                    /* IEEE: -0 < +0 is false          */
+}
+
+static int less_u64(uint64_t a, uint64_t b) { return a < b; }
+
+/* ------------------------------------------------------------------------ */
+/* prototypical stable mergesort with a 100% buffer                          */
+/* ------------------------------------------------------------------------ */
+
+/* Sort x[lo,hi) stably using tmp[lo,hi) as scratch. */
+static void msort_f64(double *x, double *tmp, int64_t lo, int64_t hi)
+{
+    if (hi - lo < 2) return;
+    int64_t mid = lo + (hi - lo) / 2;
+    msort_f64(x, tmp, lo, mid);
+    msort_f64(x, tmp, mid, hi);
+    int64_t i = lo, j = mid, k = lo;
+    while (i < mid && j < hi) {
+        /* a right element is taken only if it is strictly smaller: ties keep
+           the left (earlier) element first */
+        if (oracle_less_f64(x[j], x[i])) tmp[k++] = x[j++];
+        else                             tmp[k++] = x[i++];
+    }
+    while (i < mid) tmp[k++] = x[i++];
+    while (j < hi)  tmp[k++] = x[j++];
+    memcpy(x + lo, tmp + lo, (size_t)(hi - lo) * sizeof(double));
+}
+
+static void msort_kv(uint64_t *k, uint32_t *v, uint64_t *tk, uint32_t *tv,
+                     int64_t lo, int64_t hi)
+{
+    if (hi - lo < 2) return;
+    int64_t mid = lo + (hi - lo) / 2;
+    msort_kv(k, v, tk, tv, lo, mid);
+    msort_kv(k, v, tk, tv, mid, hi);
+    int64_t i = lo, j = mid, o = lo;
+    while (i < mid && j < hi) {
+        if (less_u64(k[j], k[i])) { tk[o] = k[j]; tv[o] = v[j]; o++; j++; }
+        else                      { tk[o] = k[i]; tv[o] = v[i]; o++; i++; }
+    }
+    while (i < mid) { tk[o] = k[i]; tv[o] = v[i]; o++; i++; }
+    while (j < hi)  { tk[o] = k[j]; tv[o] = v[j]; o++; j++; }
+    memcpy(k + lo, tk + lo, (size_t)(hi - lo) * sizeof(uint64_t));
+    memcpy(v + lo, tv + lo, (size_t)(hi - lo) * sizeof(uint32_t));
+}
+
+/* Returns 0 on success, -1 if the scratch buffer could not be allocated. */
+int oracle_sort_f64(double *x, int64_t n)
+{
+    if (n < 2) return 0;
+    double *tmp = (double *)malloc((size_t)n * sizeof(double));
+    if (!tmp) return -1;
+    msort_f64(x, tmp, 0, n);
+    free(tmp);
+    return 0;
+}
+
+int oracle_sort_kv(uint64_t *k, uint32_t *v, int64_t n)
+{
+    if (n < 2) return 0;
+    uint64_t *tk = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    uint32_t *tv = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    if (!tk || !tv) { free(tk); free(tv); return -1; }
+    msort_kv(k, v, tk, tv, 0, n);
+    free(tk); free(tv);
+    return 0;
+}
+
+/* Segment i is x[off[i], off[i+1]); each segment is sorted on its own.
+   Returns -2 if the offsets are not non-decreasing or off[0] < 0. */
+int oracle_segsort_f64(double *x, const int64_t *off, int64_t nseg)
+{
+    if (nseg <= 0) return 0;
+    if (off[0] < 0) return -2;
+    int64_t maxlen = 0;
+    for (int64_t s = 0; s < nseg; s++) {
+        if (off[s + 1] < off[s]) return -2;
+        if (off[s + 1] - off[s] > maxlen) maxlen = off[s + 1] - off[s];
+    }
+    if (maxlen < 2) return 0;
+    double *tmp = (double *)malloc((size_t)maxlen * sizeof(double));
+    if (!tmp) return -1;
+    for (int64_t s = 0; s < nseg; s++) {
+        int64_t lo = off[s], len = off[s + 1] - off[s];
+        if (len >= 2) msort_f64(x + lo, tmp, 0, len);
+    }
+    free(tmp);
+    return 0;
+}
+
+int oracle_segsort_kv(uint64_t *k, uint32_t *v, const int64_t *off, int64_t nseg)
+{
+    if (nseg <= 0) return 0;
+    if (off[0] < 0) return -2;
+    int64_t maxlen = 0;
+    for (int64_t s = 0; s < nseg; s++) {
+        if (off[s + 1] < off[s]) return -2;
+        if (off[s + 1] - off[s] > maxlen) maxlen = off[s + 1] - off[s];
+    }
+    if (maxlen < 2) return 0;
+    uint64_t *tk = (uint64_t *)malloc((size_t)maxlen * sizeof(uint64_t));
+    uint32_t *tv = (uint32_t *)malloc((size_t)maxlen * sizeof(uint32_t));
+    if (!tk || !tv) { free(tk); free(tv); return -1; }
+    for (int64_t s = 0; s < nseg; s++) {
+        int64_t lo = off[s], len = off[s + 1] - off[s];
+        if (len >= 2) msort_kv(k + lo, v + lo, tk, tv, 0, len);
+    }
+    free(tk); free(tv);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* the definition as a count                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Output position of input element j under the stable ascending definition:
+   the number of elements strictly less than x[j], plus the number of earlier
+   elements tied with x[j].  One pass over x answers m queries at once. */
+void oracle_rank_f64(const double *x, int64_t n, const int64_t *idx, int64_t m,
+                     int64_t *rank)
+{
+    for (int64_t q = 0; q < m; q++) rank[q] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        double xi = x[i];
+        for (int64_t q = 0; q < m; q++) {
+            double xq = x[idx[q]];
+            if (oracle_less_f64(xi, xq)) rank[q]++;
+            else if (i < idx[q] && !oracle_less_f64(xq, xi)) rank[q]++;
+        }
+    }
+}
+
+void oracle_rank_u64(const uint64_t *x, int64_t n, const int64_t *idx, int64_t m,
+                     int64_t *rank)
+{
+    for (int64_t q = 0; q < m; q++) rank[q] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        uint64_t xi = x[i];
+        for (int64_t q = 0; q < m; q++) {
+            uint64_t xq = x[idx[q]];
+            if (xi < xq || (xi == xq && i < idx[q])) rank[q]++;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* instrumented model of the Frogsort recursion                             */
+/* ------------------------------------------------------------------------ */
+/*
+ * Memory is a logical array of slots.  Data elements are carried as (key,
+ * label) pairs so that the layout tables of the paper can be reproduced: the
+ * label of an element is the position it had after setup.  Slot contents that
+ * are buffer hold label -1.
+ *
+ * A node covers `u` units; a unit is `g` data slots (g = 1: Frogsort1, single
+ * elements; g = 2: Frogsort0 triplets, two data and one buffer slot).  A node
+ * of u units has n = g*u data elements and a region of n + floor(n/2) slots
+ * (for g = 2 this is 3u slots, one buffer slot per triplet).
+ *
+ * A left node leaves its sorted data at the left end of its region, a right
+ * node at the right end.  Its outer child (the left child of a left node, the
+ * right child of a right node) receives the surplus unit when u is odd
+ * (Frogsort1 rule 1; Frogsort0 rule), so the inner child is never larger than
+ * the gap between the two children's data (Frogsort1 rule 2: the buffer is
+ * floor(n/2)).  Merging proceeds from the inner ends of the two runs towards
+ * the outer border ("Symmetric merging"): a left node writes its output from
+ * the top (next to the gap) down to its left border, a right node from the
+ * bottom up to its right border.
+ */
+
+typedef struct {
+    double  *key;      /* slot keys                                          */
+    int64_t *lab;      /* slot labels (-1 = buffer)                           */
+    int64_t  cmp;      /* merge comparisons                                   */
+    int64_t  mov;      /* merge element moves (writes to a different slot)    */
+    int      g;        /* data slots per unit                                 */
+    /* trace: after every merge, a snapshot of the labels if trace != NULL   */
+    int64_t *trace;    /* [max_snap][nslots]                                   */
+    int64_t  nslots, nsnap, max_snap;
+} frog_model;
+
+static int64_t frog_region(const frog_model *M, int64_t u)
+{
+    int64_t n = (int64_t)M->g * u;
+    return n + n / 2;
+}
+
+static void frog_snapshot(frog_model *M)
+{
+    if (!M->trace || M->nsnap >= M->max_snap) return;
+    memcpy(M->trace + M->nsnap * M->nslots, M->lab, (size_t)M->nslots * sizeof(int64_t));
+    M->nsnap++;
+}
+
+static void frog_put(frog_model *M, int64_t dst, int64_t src)
+{
+    if (dst != src) {
+        M->key[dst] = M->key[src];
+        M->lab[dst] = M->lab[src];
+        M->mov++;
+    }
+}
+
+static void frog_left(frog_model *M, int64_t s, int64_t u);
+static void frog_right(frog_model *M, int64_t s, int64_t u);
+
+/* A leaf unit: for g = 1 a single element, already in place.  For g = 2 the
+   unit is a triplet whose two data slots are sorted to the left (left leaf) or
+   to the right (right leaf); its middle slot is the buffer. */
+static void frog_leaf(frog_model *M, int64_t s, int left)
+{
+    if (M->g == 1) return;
+    /* setup put the two data elements at s and s+2, buffer at s+1 */
+    int64_t a = s, b = s + 2;
+    M->cmp++;
+    int swap = oracle_less_f64(M->key[b], M->key[a]);
+    double ka = M->key[a], kb = M->key[b];
+    int64_t la = M->lab[a], lb = M->lab[b];
+    if (swap) { double t = ka; ka = kb; kb = t; int64_t tl = la; la = lb; lb = tl; }
+    if (left) {   /* data to s, s+1 */
+        M->key[s] = ka; M->lab[s] = la; M->key[s + 1] = kb; M->lab[s + 1] = lb;
+        M->lab[s + 2] = -1;
+    } else {      /* data to s+1, s+2 */
+        M->key[s + 1] = ka; M->lab[s + 1] = la; M->key[s + 2] = kb; M->lab[s + 2] = lb;
+        M->lab[s] = -1;
+    }
+    M->mov += 1 + (swap ? 1 : 0);
+    frog_snapshot(M);
+}
+
+/* Left node over [s, s+region): outer = left child gets ceil(u/2) units. */
+static void frog_left(frog_model *M, int64_t s, int64_t u)
+{
+    if (u == 1) { frog_leaf(M, s, 1); return; }
+    int64_t ul = (u + 1) / 2, ur = u / 2;
+    int64_t nl = (int64_t)M->g * ul, nr = (int64_t)M->g * ur, n = nl + nr;
+    int64_t reg = frog_region(M, u);
+    frog_left(M, s, ul);                                   /* L at [s, s+nl)     */
+    frog_right(M, s + reg - frog_region(M, ur), ur);       /* R at [s+reg-nr, .) */
+    int64_t Lb = s, Rb = s + reg - nr;
+    int64_t i = nl - 1, j = nr - 1, w = s + n - 1;
+    /* descending: the larger element goes to the top; on a tie the later
+       (right-run) element takes the higher slot */
+    while (j >= 0) {
+        if (i < 0) { frog_put(M, w--, Rb + j); j--; continue; }
+        M->cmp++;
+        if (oracle_less_f64(M->key[Rb + j], M->key[Lb + i])) { frog_put(M, w--, Lb + i); i--; }
+        else                                                 { frog_put(M, w--, Rb + j); j--; }
+    }
+    /* L's remaining prefix is already in place */
+    for (int64_t p = s + n; p < s + reg; p++) M->lab[p] = -1;
+    frog_snapshot(M);
+}
+
+/* Right node over [s, s+region): outer = right child gets ceil(u/2) units. */
+static void frog_right(frog_model *M, int64_t s, int64_t u)
+{
+    if (u == 1) { frog_leaf(M, s, 0); return; }
+    int64_t ul = u / 2, ur = (u + 1) / 2;
+    int64_t nl = (int64_t)M->g * ul, nr = (int64_t)M->g * ur, n = nl + nr;
+    int64_t reg = frog_region(M, u);
+    frog_left(M, s, ul);
+    frog_right(M, s + reg - frog_region(M, ur), ur);
+    int64_t Lb = s, Rb = s + reg - nr;
+    int64_t i = 0, j = 0, w = s + reg - n;
+    /* ascending: the smaller element goes to the bottom; on a tie the earlier
+       (left-run) element takes the lower slot */
+    while (i < nl) {
+        if (j >= nr) { frog_put(M, w++, Lb + i); i++; continue; }
+        M->cmp++;
+        if (oracle_less_f64(M->key[Rb + j], M->key[Lb + i])) { frog_put(M, w++, Rb + j); j++; }
+        else                                                 { frog_put(M, w++, Lb + i); i++; }
+    }
+    for (int64_t p = s; p < s + reg - n; p++) M->lab[p] = -1;
+    frog_snapshot(M);
+}
+
+/* Setup recursion: place the input elements (in input order) into the leaf
+   slots of the frog tree.  For g = 1 a leaf is one slot; for g = 2 a leaf is a
+   triplet whose data go to its first and last slot. */
+static int64_t frog_setup(frog_model *M, const double *in, int64_t next,
+                          int64_t s, int64_t u, int left)
+{
+    if (u == 1) {
+        if (M->g == 1) {
+            M->key[s] = in[next]; M->lab[s] = next; return next + 1;
+        }
+        M->key[s] = in[next]; M->lab[s] = next;
+        M->lab[s + 1] = -1;
+        M->key[s + 2] = in[next + 1]; M->lab[s + 2] = next + 1;
+        return next + 2;
+    }
+    int64_t ul = left ? (u + 1) / 2 : u / 2;
+    int64_t ur = u - ul;
+    int64_t reg = frog_region(M, u);
+    next = frog_setup(M, in, next, s, ul, 1);
+    next = frog_setup(M, in, next, s + reg - frog_region(M, ur), ur, 0);
+    return next;
+}
+
+/*
+ * Run the model on `in[0, g*u)` as a top-level left node.
+ *   out_key   : n sorted keys (the data region after the top merge)
+ *   out_label : n labels: the input index each output element came from
+ *   setup_lab : nslots labels right after setup (may be NULL)
+ *   trace     : max_snap x nslots label snapshots after every merge (may be NULL)
+ *   counts    : {comparisons, moves, snapshots taken}
+ * Returns the number of slots (n + floor(n/2)), or -1 on allocation failure.
+ */
+int64_t oracle_frog_model(const double *in, int64_t u, int g, double *out_key,
+                          int64_t *out_label, int64_t *setup_lab, int64_t *trace,
+                          int64_t max_snap, int64_t *counts)
+{
+    frog_model M;
+    memset(&M, 0, sizeof M);
+    M.g = g;
+    if (u <= 0) { if (counts) counts[0] = counts[1] = counts[2] = 0; return 0; }
+    M.nslots = frog_region(&M, u);
+    M.key = (double *)calloc((size_t)M.nslots, sizeof(double));
+    M.lab = (int64_t *)malloc((size_t)M.nslots * sizeof(int64_t));
+    if (!M.key || !M.lab) { free(M.key); free(M.lab); return -1; }
+    for (int64_t p = 0; p < M.nslots; p++) M.lab[p] = -1;
+    frog_setup(&M, in, 0, 0, u, 1);
+    if (setup_lab) memcpy(setup_lab, M.lab, (size_t)M.nslots * sizeof(int64_t));
+    M.trace = trace; M.max_snap = max_snap;
+    frog_left(&M, 0, u);
+    int64_t n = (int64_t)g * u;
+    if (out_key) memcpy(out_key, M.key, (size_t)n * sizeof(double));
+    if (out_label) memcpy(out_label, M.lab, (size_t)n * sizeof(int64_t));
+    if (counts) { counts[0] = M.cmp; counts[1] = M.mov; counts[2] = M.nsnap; }
+    int64_t ns = M.nslots;
+    free(M.key); free(M.lab);
+    return ns;
+}
+
+/* Geometry of the Frogsort1 tree (g = 1) walked down to depth `depth`:
+   for every node at that depth, in left-to-right order, writes
+   {region start, data elements, is_left, data start, input offset}.
+   Returns the number of nodes written (2^depth). */
+static int64_t frog_geom(int64_t s, int64_t n, int left, int depth, int64_t in_off,
+                         int64_t *out, int64_t k)
+{
+    if (depth == 0) {
+        int64_t reg = n + n / 2;
+        out[5 * k + 0] = s;
+        out[5 * k + 1] = n;
+        out[5 * k + 2] = left;
+        out[5 * k + 3] = left ? s : s + reg - n;
+        out[5 * k + 4] = in_off;
+        return k + 1;
+    }
+    int64_t nl = left ? (n + 1) / 2 : n / 2, nr = n - nl;
+    int64_t reg = n + n / 2, regr = nr + nr / 2;
+    k = frog_geom(s, nl, 1, depth - 1, in_off, out, k);
+    k = frog_geom(s + reg - regr, nr, 0, depth - 1, in_off + nl, out, k);
+    return k;
+}
+
+int64_t oracle_frog_geometry(int64_t n, int depth, int64_t *out)
+{
+    return frog_geom(0, n, 1, depth, 0, out, 0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* fp64 reference for the 1-64-64-1 ReLU network (learned bucket path)       */
+/* ------------------------------------------------------------------------ */
+/*
+ * Parameter vector layout (4353 values), for hidden width H = 64:
+ *   W1[H]      first layer weights (input is a scalar)
+ *   b1[H]
+ *   W2[H*H]    row-major: W2[i*H + j] multiplies hidden-1 unit j into unit i
+ *   b2[H]
+ *   w3[H]
+ *   b3[1]
+ * y(u) = w3 . relu(W2 relu(W1 u + b1) + b2) + b3
+ * loss = mean over the batch of (y - t)^2
+ */
+#define MLP_H 64
+#define OFF_W1 0
+#define OFF_B1 (OFF_W1 + MLP_H)
+#define OFF_W2 (OFF_B1 + MLP_H)
+#define OFF_B2 (OFF_W2 + MLP_H * MLP_H)
+#define OFF_W3 (OFF_B2 + MLP_H)
+#define OFF_B3 (OFF_W3 + MLP_H)
+#define MLP_NP (OFF_B3 + 1)
+
+int oracle_mlp_num_params(void) { return MLP_NP; }
+
+static double relu(double v) { return v > 0.0 ? v : 0.0; }
+
+void oracle_mlp_forward(const double *p, const double *u, int64_t B, double *y)
+{
+    double h1[MLP_H], h2[MLP_H];
+    for (int64_t b = 0; b < B; b++) {
+        for (int i = 0; i < MLP_H; i++) h1[i] = relu(p[OFF_W1 + i] * u[b] + p[OFF_B1 + i]);
+        for (int i = 0; i < MLP_H; i++) {
+            double a = p[OFF_B2 + i];
+            for (int j = 0; j < MLP_H; j++) a += p[OFF_W2 + i * MLP_H + j] * h1[j];
+            h2[i] = relu(a);
+        }
+        double out = p[OFF_B3];
+        for (int i = 0; i < MLP_H; i++) out += p[OFF_W3 + i] * h2[i];
+        y[b] = out;
+    }
+}
+
+/* Loss and its gradient with respect to every parameter (same layout).
+   ReLU'(0) is taken as 0. */
+double oracle_mlp_loss_grad(const double *p, const double *u, const double *t,
+                            int64_t B, double *grad)
+{
+    double h1[MLP_H], z1[MLP_H], h2[MLP_H], z2[MLP_H], g2[MLP_H], g1[MLP_H];
+    double loss = 0.0;
+    if (grad) for (int k = 0; k < MLP_NP; k++) grad[k] = 0.0;
+    for (int64_t b = 0; b < B; b++) {
+        for (int i = 0; i < MLP_H; i++) {
+            z1[i] = p[OFF_W1 + i] * u[b] + p[OFF_B1 + i];
+            h1[i] = relu(z1[i]);
+        }
+        for (int i = 0; i < MLP_H; i++) {
+            double a = p[OFF_B2 + i];
+            for (int j = 0; j < MLP_H; j++) a += p[OFF_W2 + i * MLP_H + j] * h1[j];
+            z2[i] = a;
+            h2[i] = relu(a);
+        }
+        double y = p[OFF_B3];
+        for (int i = 0; i < MLP_H; i++) y += p[OFF_W3 + i] * h2[i];
+        double r = y - t[b];
+        loss += r * r;
+        if (!grad) continue;
+        double dy = 2.0 * r / (double)B;
+        grad[OFF_B3] += dy;
+        for (int i = 0; i < MLP_H; i++) {
+            grad[OFF_W3 + i] += dy * h2[i];
+            g2[i] = (z2[i] > 0.0) ? dy * p[OFF_W3 + i] : 0.0;   /* d loss / d z2 */
+        }
+        for (int j = 0; j < MLP_H; j++) g1[j] = 0.0;
+        for (int i = 0; i < MLP_H; i++) {
+            grad[OFF_B2 + i] += g2[i];
+            for (int j = 0; j < MLP_H; j++) {
+                grad[OFF_W2 + i * MLP_H + j] += g2[i] * h1[j];
+                g1[j] += p[OFF_W2 + i * MLP_H + j] * g2[i];
+            }
+        }
+        for (int j = 0; j < MLP_H; j++) {
+            double d = (z1[j] > 0.0) ? g1[j] : 0.0;               /* d loss / d z1 */
+            grad[OFF_B1 + j] += d;
+            grad[OFF_W1 + j] += d * u[b];
+        }
+    }
+    return loss / (double)B;
+}
+
+/* One Adam step (Kingma & Ba 2015) at step number `step` (1-based). */
+void oracle_adam_step(double *p, const double *g, double *m, double *v, int64_t np,
+                      int64_t step, double lr, double beta1, double beta2, double eps)
+{
+    double c1 = 1.0 - pow(beta1, (double)step);
+    double c2 = 1.0 - pow(beta2, (double)step);
+    for (int64_t k = 0; k < np; k++) {
+        m[k] = beta1 * m[k] + (1.0 - beta1) * g[k];
+        v[k] = beta2 * v[k] + (1.0 - beta2) * g[k] * g[k];
+        double mh = m[k] / c1, vh = v[k] / c2;
+        p[k] -= lr * mh / (sqrt(vh) + eps);
+    }
+}

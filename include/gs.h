@@ -1,0 +1,156 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) greeNsort library, libgs.so.
+ *
+ * The library sorts contiguous device arrays stably and in ascending order
+ * (the paper's "Definition of sorting": the AscLeft target, ties kept in input
+ * order read from left to right; "Values and principles / Stability"), by the
+ * half-buffer symmetric mergesort of the sections "Symmetric merging" and
+ * "Frogsort1": the extra memory is a buffer of floor(n/2) elements, and the two
+ * children of every merge are sorted into mirrored positions (data left/buffer
+ * right vs buffer left/data right) so that merging needs no extra moves.
+ *
+ * Conventions for every call below
+ *   - Pointers named `keys`, `vals`, `offsets`, `ws` are DEVICE pointers
+ *     (hipMalloc / torch CUDA tensors) on the current HIP device; pointers in
+ *     structs are device pointers unless their comment says host.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *     asynchronous on that stream unless `rep` is non-NULL, in which case the
+ *     call synchronises the stream before filling the report.
+ *   - Sorting is in place: the result replaces `keys` (and `vals`).
+ *   - The caller owns all memory.  The library makes no device allocation; the
+ *     workspace `ws` (at least gs_workspace_bytes_*() bytes, 256-byte aligned)
+ *     holds the half buffer and a small control area, so the paper's %RAM KPI
+ *     ("Sustainability measures") is exactly 1 + ws_bytes / data_bytes.
+ *   - Errors are returned, never thrown.  Argument errors are detected before
+ *     any device work is enqueued, so the input is untouched on any error.
+ *   - `buffer_fraction` is the cap on extra buffer as a fraction of the data.
+ *     Values >= 0.5 select Frogsort1 (buffer floor(n/2); never more).  Values in
+ *     (0, 0.5) would select Frogsort2 ("Frogsort2": inner branch p*n) and return
+ *     GS_EUNSUPPORTED in this version.  NaN, <= 0 -> GS_EINVAL.
+ *   - Calls on different streams with different workspaces may run
+ *     concurrently; two calls sharing one workspace must be ordered.
+ *
+ * Comparison: float64 keys compare as IEEE `<` except that NaNs are greater
+ * than every other value and tie with each other; -0.0 and +0.0 tie.  Keys are
+ * moved bit for bit and never rounded or transformed.  uint64 keys compare
+ * unsigned.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS_OK = 0,
+    GS_EINVAL = 1,        /* bad argument (null pointer with n > 0, n < 0, bad fraction, bad offsets) */
+    GS_EUNSUPPORTED = 2,  /* valid request this version does not implement (buffer_fraction < 0.5) */
+    GS_EWORKSPACE = 3,    /* ws_bytes below the size the matching gs_workspace_bytes_* returns */
+    GS_ENODEVICE = 4,     /* no HIP device visible */
+    GS_EDEVICE = 5        /* a HIP runtime call failed; see gs_last_error_detail() */
+} gs_status;
+
+/* Optional out-parameter.  If non-NULL the call synchronises its stream. */
+typedef struct {
+    double   ram_fraction;          /* %RAM = (data bytes + workspace bytes) / data bytes */
+    uint64_t workspace_bytes_used;  /* bytes of ws the call may touch */
+    uint32_t levels;                /* merge levels (tree depth) of the largest sort done */
+    uint32_t fallback;              /* learned: 1 if the bucket order failed verification */
+    uint32_t overflow_buckets;      /* learned: buckets above the in-LDS capacity */
+    uint32_t max_bucket;            /* learned: largest bucket (keys) */
+    float    train_loss_first;      /* learned: training loss of the first / last step */
+    float    train_loss_last;
+    uint32_t feature;               /* learned: 0 = linear in x, 1 = linear in the key bits */
+    uint32_t invalid_offsets;       /* segsort: 1 if the device check rejected the offsets */
+    double   elapsed_ms;            /* wall time of the call measured with HIP events */
+} gs_report;
+
+/* Parameters of the learned CDF bucket path (not from the paper). */
+typedef struct {
+    uint32_t num_buckets;    /* buckets, power of two in [2, 65536]; default 4096 */
+    uint32_t sample_size;    /* keys sampled for training; default 65536 */
+    uint32_t train_steps;    /* Adam steps; default 200 */
+    uint32_t batch;          /* minibatch per step; default 2048 */
+    uint32_t knots;          /* knots of the tabulated model; default 16384 */
+    float    lr;             /* Adam learning rate; default 1e-2 */
+    uint64_t seed;           /* sample positions, weight init and minibatches */
+    uint32_t mode;           /* 0 = trained network, 1 = untrained linear CDF (table[i] = i/knots) */
+    const float *weights_override;    /* device, 4353 floats: skip training, use these weights; may be NULL */
+    const float *test_bucket_table;   /* device, `knots`+1 floats: raw table, bypasses the running max
+                                         (test hook to force an order violation); may be NULL */
+} gs_learned_params;
+
+/* Fills `p` with the defaults above. */
+void gs_learned_default_params(gs_learned_params *p);
+
+/* Workspace sizes in bytes (0 for n <= 1); SIZE_MAX for invalid arguments. */
+size_t gs_workspace_bytes_f64(int64_t n, double buffer_fraction);
+size_t gs_workspace_bytes_kv(int64_t n, double buffer_fraction);
+size_t gs_workspace_bytes_seg(int64_t num_keys, int64_t num_segments, double buffer_fraction);
+size_t gs_workspace_bytes_learned(int64_t n, const gs_learned_params *p);
+
+/* Stable ascending sort of n float64 keys in place ("Frogsort1").  The top
+   merge writes the result straight into `keys`; ws holds the floor(n/2)
+   half buffer. */
+gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction,
+                      void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+
+/* Stable ascending sort of n uint64 keys; vals[i] (uint32) travels with
+   keys[i].  Stability is observable through vals ("Stability"). */
+gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fraction,
+                     void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+
+/* Sort every segment keys[offsets[i], offsets[i+1]) on its own, for
+   i in [0, num_segments); `offsets` holds num_segments+1 int64 values (device).
+   Offsets must be non-decreasing with offsets[0] >= 0 and
+   offsets[num_segments] <= num_keys; keys outside every segment are untouched.
+   The offsets are checked on the device: on a violation nothing is written and
+   the report (if any) shows invalid_offsets = 1 and the call returns GS_EINVAL;
+   without a report the call returns GS_OK and the keys are left unchanged. */
+gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets,
+                     int64_t num_segments, double buffer_fraction,
+                     void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+
+/* Stable ascending sort of n float64 keys with the same result as
+   gs_sort_f64, using a small FP32 CDF network trained on the device to bucket
+   the keys first.  The bucket order is verified before any key moves; on a
+   violation the plain path sorts the untouched input (report.fallback = 1).
+   `p` is a host pointer (NULL = defaults). */
+gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p,
+                          void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+
+const char *gs_status_string(gs_status s);
+/* Detail of the last error on the calling thread (never NULL). */
+const char *gs_last_error_detail(void);
+/* Library version string, e.g. "0.1.0 gfx950". */
+const char *gs_version(void);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Launch tracing for profiling tools: while enabled on the calling thread,
+   every kernel launch made by the calls above is bracketed by HIP events on
+   the call's stream.  Returns the previous setting. */
+int gs_trace_enable(int on);
+/* Waits for the recorded events, writes up to `max` records (host arrays):
+   kinds[i] (0 fill, 1 leaf sort, 2 partition, 3 merge, 4 other) and ms[i]
+   (launch duration), clears the record list and returns the count written. */
+int gs_trace_read(int *kinds, double *ms, int max);
+
+/* ---- introspection for tests (host only, no device work) ---------------- */
+
+/* Depth of the frog tree the plain path builds for n keys with leaves of at
+   most the library's leaf size (elements); *leaf_max receives that size. */
+int gs_plan_depth(int64_t n, int is_kv, int64_t *leaf_max);
+/* Geometry of node `idx` at `depth` of the frog tree over n elements:
+   out[0..4] = region start, data size, is_left, data start, input offset. */
+void gs_plan_node(int64_t n, int depth, int64_t idx, int64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

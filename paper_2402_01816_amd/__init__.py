@@ -1,0 +1,290 @@
+"""Python binding of libgs.so (include/gs.h): argument marshalling only.
+
+Every sorting step runs in the library's HIP kernels; this module only turns
+torch tensors into device pointers, allocates the caller-owned workspace with
+torch, passes the current HIP stream and converts status codes into
+exceptions.  There is no fallback: if libgs.so is missing, importing this
+module raises.
+
+The functions carry the C names: gs_sort_f64, gs_sort_kv, gs_segsort,
+gs_learned_sort and the gs_workspace_bytes_* queries.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -m paper_2402_01816_amd.build` "
+        "(hipcc, gfx950) first")
+
+# torch brings its own copy of the HIP runtime (same soname as the system one).
+# Loading torch first makes libgs.so bind to that already-loaded runtime, so the
+# process holds exactly one HIP runtime and torch's memory and streams are valid
+# handles for the library.
+import torch  # noqa: E402,F401  (must precede loading libgs.so)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+GS_OK, GS_EINVAL, GS_EUNSUPPORTED, GS_EWORKSPACE, GS_ENODEVICE, GS_EDEVICE = range(6)
+STATUS_NAMES = {0: "GS_OK", 1: "GS_EINVAL", 2: "GS_EUNSUPPORTED", 3: "GS_EWORKSPACE",
+                4: "GS_ENODEVICE", 5: "GS_EDEVICE"}
+MLP_NUM_PARAMS = 4353
+SIZE_MAX = ctypes.c_size_t(-1).value
+
+
+class GsReport(ctypes.Structure):
+    _fields_ = [
+        ("ram_fraction", ctypes.c_double),
+        ("workspace_bytes_used", ctypes.c_uint64),
+        ("levels", ctypes.c_uint32),
+        ("fallback", ctypes.c_uint32),
+        ("overflow_buckets", ctypes.c_uint32),
+        ("max_bucket", ctypes.c_uint32),
+        ("train_loss_first", ctypes.c_float),
+        ("train_loss_last", ctypes.c_float),
+        ("feature", ctypes.c_uint32),
+        ("invalid_offsets", ctypes.c_uint32),
+        ("elapsed_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class GsLearnedParams(ctypes.Structure):
+    _fields_ = [
+        ("num_buckets", ctypes.c_uint32),
+        ("sample_size", ctypes.c_uint32),
+        ("train_steps", ctypes.c_uint32),
+        ("batch", ctypes.c_uint32),
+        ("knots", ctypes.c_uint32),
+        ("lr", ctypes.c_float),
+        ("seed", ctypes.c_uint64),
+        ("mode", ctypes.c_uint32),
+        ("weights_override", ctypes.c_void_p),
+        ("test_bucket_table", ctypes.c_void_p),
+    ]
+
+
+class GsError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        self.status_name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{where}: {self.status_name}: {detail}")
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_SZ = ctypes.c_size_t
+
+_SIGS = {
+    "gs_workspace_bytes_f64": ([_I64, _D], _SZ),
+    "gs_workspace_bytes_kv": ([_I64, _D], _SZ),
+    "gs_sort_f64": ([_P, _I64, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)], ctypes.c_int),
+    "gs_sort_kv": ([_P, _P, _I64, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)], ctypes.c_int),
+    "gs_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "gs_last_error_detail": ([], ctypes.c_char_p),
+    "gs_version": ([], ctypes.c_char_p),
+    "gs_plan_depth": ([_I64, ctypes.c_int, ctypes.POINTER(_I64)], ctypes.c_int),
+    "gs_plan_node": ([_I64, ctypes.c_int, _I64, ctypes.POINTER(_I64)], None),
+}
+_OPTIONAL = {
+    "gs_workspace_bytes_seg": ([_I64, _I64, _D], _SZ),
+    "gs_workspace_bytes_learned": ([_I64, ctypes.POINTER(GsLearnedParams)], _SZ),
+    "gs_segsort": ([_P, _I64, _P, _I64, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)], ctypes.c_int),
+    "gs_learned_sort": ([_P, _I64, ctypes.POINTER(GsLearnedParams), _P, _SZ, _P,
+                         ctypes.POINTER(GsReport)], ctypes.c_int),
+    "gs_learned_default_params": ([ctypes.POINTER(GsLearnedParams)], None),
+}
+for _name, (_args, _res) in {**_SIGS, **_OPTIONAL}.items():
+    if _name in _SIGS or hasattr(_lib, _name):
+        _fn = getattr(_lib, _name)
+        _fn.argtypes = _args
+        _fn.restype = _res
+
+lib = _lib
+
+
+def version() -> str:
+    return _lib.gs_version().decode()
+
+
+def _detail() -> str:
+    return _lib.gs_last_error_detail().decode(errors="replace")
+
+
+def _check(status: int, where: str):
+    if status != GS_OK:
+        raise GsError(status, where, _detail())
+
+
+# ---------------------------------------------------------------------------
+# workspace queries
+# ---------------------------------------------------------------------------
+def gs_workspace_bytes_f64(n: int, buffer_fraction: float = 0.5) -> int:
+    return int(_lib.gs_workspace_bytes_f64(n, buffer_fraction))
+
+
+def gs_workspace_bytes_kv(n: int, buffer_fraction: float = 0.5) -> int:
+    return int(_lib.gs_workspace_bytes_kv(n, buffer_fraction))
+
+
+def gs_workspace_bytes_seg(num_keys: int, num_segments: int, buffer_fraction: float = 0.5) -> int:
+    return int(_lib.gs_workspace_bytes_seg(num_keys, num_segments, buffer_fraction))
+
+
+def gs_learned_default_params() -> GsLearnedParams:
+    p = GsLearnedParams()
+    _lib.gs_learned_default_params(ctypes.byref(p))
+    return p
+
+
+def gs_workspace_bytes_learned(n: int, params: GsLearnedParams | None = None) -> int:
+    p = params if params is not None else gs_learned_default_params()
+    return int(_lib.gs_workspace_bytes_learned(n, ctypes.byref(p)))
+
+
+def plan_depth(n: int, kv: bool = False):
+    leaf = _I64(0)
+    d = _lib.gs_plan_depth(n, 1 if kv else 0, ctypes.byref(leaf))
+    return d, leaf.value
+
+
+def plan_node(n: int, depth: int, idx: int):
+    out = (_I64 * 5)()
+    _lib.gs_plan_node(n, depth, idx, out)
+    return tuple(out)
+
+
+# ---------------------------------------------------------------------------
+# torch marshalling
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _workspace(nbytes: int, device, workspace=None):
+    torch = _torch()
+    if nbytes == 0:
+        return None, 0
+    if workspace is not None:
+        if workspace.device != device or workspace.dtype != torch.uint8:
+            raise ValueError("workspace must be a uint8 tensor on the keys' device")
+        return workspace, workspace.numel()
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off: off + nbytes], nbytes
+
+
+def _stream_ptr(stream, device):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, what, dtypes):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{what} must have dtype in {dtypes}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() else ctypes.c_void_p(0)
+
+
+def _rep(report):
+    return GsReport() if report else None
+
+
+def _rep_ptr(r):
+    return ctypes.byref(r) if r is not None else ctypes.POINTER(GsReport)()
+
+
+def gs_sort_f64(keys, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False):
+    """Stable ascending in-place sort of a contiguous float64 device tensor."""
+    torch = _torch()
+    kp = _dev_ptr(keys, "keys", (torch.float64,))
+    n = keys.numel()
+    need = gs_workspace_bytes_f64(n, buffer_fraction)
+    if need == SIZE_MAX:
+        need = 0
+    ws, wsb = _workspace(need, keys.device, workspace)
+    r = _rep(report)
+    st = _lib.gs_sort_f64(kp, n, buffer_fraction,
+                          ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                          _stream_ptr(stream, keys.device), _rep_ptr(r))
+    _check(st, "gs_sort_f64")
+    return r.as_dict() if r is not None else None
+
+
+def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False):
+    """Stable ascending in-place sort of 64-bit keys (int64 or uint64 storage,
+    compared as unsigned) carrying 32-bit values (int32 or uint32 storage)."""
+    torch = _torch()
+    k64 = tuple(d for d in (torch.int64, getattr(torch, "uint64", None)) if d is not None)
+    v32 = tuple(d for d in (torch.int32, getattr(torch, "uint32", None)) if d is not None)
+    kp = _dev_ptr(keys, "keys", k64)
+    vp = _dev_ptr(vals, "vals", v32)
+    if keys.numel() != vals.numel():
+        raise ValueError("keys and vals differ in length")
+    n = keys.numel()
+    need = gs_workspace_bytes_kv(n, buffer_fraction)
+    if need == SIZE_MAX:
+        need = 0
+    ws, wsb = _workspace(need, keys.device, workspace)
+    r = _rep(report)
+    st = _lib.gs_sort_kv(kp, vp, n, buffer_fraction,
+                         ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                         _stream_ptr(stream, keys.device), _rep_ptr(r))
+    _check(st, "gs_sort_kv")
+    return r.as_dict() if r is not None else None
+
+
+def gs_segsort(keys, offsets, buffer_fraction: float = 0.5, workspace=None, stream=None,
+               report=False):
+    """Sort every segment keys[offsets[i]:offsets[i+1]] of a float64 device
+    tensor in place; offsets is an int64 device tensor of num_segments+1."""
+    torch = _torch()
+    kp = _dev_ptr(keys, "keys", (torch.float64,))
+    op = _dev_ptr(offsets, "offsets", (torch.int64,))
+    nseg = max(offsets.numel() - 1, 0)
+    n = keys.numel()
+    need = gs_workspace_bytes_seg(n, nseg, buffer_fraction)
+    if need == SIZE_MAX:
+        need = 0
+    ws, wsb = _workspace(need, keys.device, workspace)
+    r = _rep(report)
+    st = _lib.gs_segsort(kp, n, op, nseg, buffer_fraction,
+                         ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                         _stream_ptr(stream, keys.device), _rep_ptr(r))
+    _check(st, "gs_segsort")
+    return r.as_dict() if r is not None else None
+
+
+def gs_learned_sort(keys, params: GsLearnedParams | None = None, workspace=None, stream=None,
+                    report=False, **overrides):
+    """Stable ascending in-place sort of a float64 device tensor through the
+    learned CDF bucket path (same result as gs_sort_f64)."""
+    torch = _torch()
+    kp = _dev_ptr(keys, "keys", (torch.float64,))
+    p = params if params is not None else gs_learned_default_params()
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    n = keys.numel()
+    need = gs_workspace_bytes_learned(n, p)
+    if need == SIZE_MAX:
+        need = 0
+    ws, wsb = _workspace(need, keys.device, workspace)
+    r = _rep(report)
+    st = _lib.gs_learned_sort(kp, n, ctypes.byref(p),
+                              ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                              _stream_ptr(stream, keys.device), _rep_ptr(r))
+    _check(st, "gs_learned_sort")
+    return r.as_dict() if r is not None else None

@@ -1,0 +1,98 @@
+// Geometry of the Frogsort1 tree ("Symmetric merging", "Frogsort1").
+//
+// A node sorts `n` data elements inside a region of m(n) = n + floor(n/2)
+// slots of the logical frog space.  A left node leaves its data at the left
+// end of its region, a right node at the right end.  Its outer child (left
+// child of a left node, right child of a right node) takes ceil(n/2) elements
+// (rule 1: the surplus goes outward); the inner child takes floor(n/2), which
+// always fits the floor(n/2)-slot gap between the two children's data (rule 2:
+// the buffer is floor(n/2)).  The left child is a left node at the start of
+// the region, the right child a right node at its end.  The top node is a left
+// node over [0, m(n)), so the sorted result ends in slots [0, n) with no copy.
+//
+// The GPU path processes the tree breadth first: all leaves (depth D, at most
+// `leaf_max` elements each) in one launch, then one merge launch per level from
+// depth D-1 up to 0.  Every node's geometry is recomputed on the fly by walking
+// from the root, so no descriptor table is ever uploaded.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define GS_HD __host__ __device__ __forceinline__
+#else
+#define GS_HD inline
+#endif
+
+namespace gs {
+
+GS_HD int64_t frog_region(int64_t n) { return n + n / 2; }
+
+struct FrogNode {
+    int64_t s;        // region start (logical slot)
+    int64_t n;        // data elements
+    int64_t in_off;   // offset of its elements in the input order
+    int     left;     // 1: data at the left end of the region, 0: right end
+};
+
+// Node `idx` (0 = leftmost) at depth `depth` of the tree over `n_total`.
+GS_HD FrogNode frog_node(int64_t n_total, int depth, int64_t idx)
+{
+    FrogNode f{0, n_total, 0, 1};
+    for (int d = depth - 1; d >= 0; --d) {
+        int64_t nl = f.left ? (f.n + 1) / 2 : f.n / 2;
+        int64_t nr = f.n - nl;
+        if ((idx >> d) & 1) {
+            f.s += frog_region(f.n) - frog_region(nr);
+            f.in_off += nl;
+            f.n = nr;
+            f.left = 0;
+        } else {
+            f.n = nl;
+            f.left = 1;
+        }
+    }
+    return f;
+}
+
+// First slot of the node's data.
+GS_HD int64_t frog_data_start(const FrogNode &f)
+{
+    return f.left ? f.s : f.s + frog_region(f.n) - f.n;
+}
+
+// The merge a node performs: outer/inner runs and where the output goes.
+struct FrogMerge {
+    int64_t l0, nl;   // left child's data   [l0, l0+nl)
+    int64_t r0, nr;   // right child's data  [r0, r0+nr)
+    int64_t out0;     // output              [out0, out0+nl+nr)
+    int     left;     // node direction: 1 = output written top-down
+};
+
+GS_HD FrogMerge frog_merge_of(const FrogNode &f)
+{
+    FrogMerge m;
+    m.nl = f.left ? (f.n + 1) / 2 : f.n / 2;
+    m.nr = f.n - m.nl;
+    m.l0 = f.s;
+    m.r0 = f.s + frog_region(f.n) - m.nr;
+    m.out0 = frog_data_start(f);
+    m.left = f.left;
+    return m;
+}
+
+// Depth at which every node holds at most leaf_max elements (sizes at depth d
+// are floor(n/2^d) or ceil(n/2^d)).
+GS_HD int frog_depth(int64_t n, int64_t leaf_max)
+{
+    int d = 0;
+    while (((n + ((int64_t)1 << d) - 1) >> d) > leaf_max) ++d;
+    return d;
+}
+
+// Largest node size at depth d.
+GS_HD int64_t frog_max_node(int64_t n, int d)
+{
+    return (n + ((int64_t)1 << d) - 1) >> d;
+}
+
+}  // namespace gs

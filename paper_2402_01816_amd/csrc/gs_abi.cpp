@@ -1,0 +1,313 @@
+// C ABI of libgs.so: argument checks, workspace accounting, dispatch, reports.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gs.h"
+#include "frog_geometry.h"
+#include "gs_internal.h"
+
+namespace {
+
+thread_local std::string g_detail = "";
+
+gs_status fail(gs_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+gs_status fail(gs_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_detail = buf;
+    return s;
+}
+
+gs_status hip_fail(hipError_t e, const char *where)
+{
+    return fail(GS_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// 0 if a HIP device is visible
+gs_status check_device()
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(GS_ENODEVICE, "no HIP device visible (%s)",
+                    e == hipSuccess ? "count is 0" : hipGetErrorString(e));
+    }
+    return GS_OK;
+}
+
+gs_status check_fraction(double f)
+{
+    if (!(f > 0.0)) return fail(GS_EINVAL, "buffer_fraction must be > 0 (got %g)", f);
+    if (f < 0.5)
+        return fail(GS_EUNSUPPORTED,
+                    "buffer_fraction %g < 0.5 needs imbalanced splits (Frogsort2), not built", f);
+    return GS_OK;
+}
+
+bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+// Optional timing/report around an asynchronous body.
+struct Reporter {
+    gs_report *rep;
+    hipStream_t st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    Reporter(gs_report *r, hipStream_t s) : rep(r), st(s)
+    {
+        if (!rep) return;
+        memset(rep, 0, sizeof *rep);
+        if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
+            (void)hipEventRecord(e0, st);
+    }
+    gs_status finish(gs_status s)
+    {
+        if (!rep) return s;
+        if (e1) (void)hipEventRecord(e1, st);
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess && s == GS_OK) s = hip_fail(e, "hipStreamSynchronize");
+        float ms = 0.f;
+        if (e0 && e1 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) rep->elapsed_ms = ms;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return s;
+    }
+};
+
+// Reads the kernels' bounded-wait error word after the stream is synchronised.
+gs_status check_err_word(const char *ws, const gs::SortPlan &p)
+{
+    unsigned w = 0;
+    hipError_t e = hipMemcpy(&w, ws + p.off_tickets + 4 * gs::kErrWord, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the error word");
+    if (w) return fail(GS_EDEVICE, "an ordered-store wait exceeded its spin limit");
+    return GS_OK;
+}
+
+struct TraceRec {
+    int kind;
+    hipEvent_t a, b;
+};
+thread_local bool g_trace = false;
+thread_local std::vector<TraceRec> g_recs;
+
+}  // namespace
+
+namespace gs {
+bool trace_on() { return g_trace; }
+void trace_begin(int kind, hipStream_t st)
+{
+    TraceRec r{kind, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    (void)hipEventRecord(r.a, st);
+    g_recs.push_back(r);
+}
+void trace_end(hipStream_t st)
+{
+    if (!g_recs.empty()) (void)hipEventRecord(g_recs.back().b, st);
+}
+}  // namespace gs
+
+extern "C" {
+
+int gs_trace_enable(int on)
+{
+    int was = g_trace ? 1 : 0;
+    g_trace = on != 0;
+    return was;
+}
+
+int gs_trace_read(int *kinds, double *ms, int max)
+{
+    int k = 0;
+    for (auto &r : g_recs) {
+        float t = 0.f;
+        (void)hipEventSynchronize(r.b);
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) t = -1.f;
+        if (k < max) {
+            kinds[k] = r.kind;
+            ms[k] = t;
+        }
+        ++k;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_recs.clear();
+    return k < max ? k : max;
+}
+
+const char *gs_status_string(gs_status s)
+{
+    switch (s) {
+        case GS_OK: return "GS_OK";
+        case GS_EINVAL: return "GS_EINVAL";
+        case GS_EUNSUPPORTED: return "GS_EUNSUPPORTED";
+        case GS_EWORKSPACE: return "GS_EWORKSPACE";
+        case GS_ENODEVICE: return "GS_ENODEVICE";
+        case GS_EDEVICE: return "GS_EDEVICE";
+    }
+    return "GS_UNKNOWN";
+}
+
+const char *gs_last_error_detail(void) { return g_detail.c_str(); }
+
+const char *gs_version(void) { return "0.1.0 gfx950"; }
+
+size_t gs_workspace_bytes_f64(int64_t n, double buffer_fraction)
+{
+    if (n < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
+    if (n <= 1) return 0;
+    return (size_t)gs::plan_f64(n).bytes;
+}
+
+size_t gs_workspace_bytes_kv(int64_t n, double buffer_fraction)
+{
+    if (n < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
+    if (n <= 1) return 0;
+    return (size_t)gs::plan_kv(n).bytes;
+}
+
+int gs_plan_depth(int64_t n, int is_kv, int64_t *leaf_max)
+{
+    gs::SortPlan p = is_kv ? gs::plan_kv(n > 1 ? n : 2) : gs::plan_f64(n > 1 ? n : 2);
+    if (leaf_max) *leaf_max = p.leaf;
+    return n > 1 ? p.depth : 0;
+}
+
+void gs_plan_node(int64_t n, int depth, int64_t idx, int64_t *out)
+{
+    gs::FrogNode f = gs::frog_node(n, depth, idx);
+    out[0] = f.s;
+    out[1] = f.n;
+    out[2] = f.left;
+    out[3] = gs::frog_data_start(f);
+    out[4] = f.in_off;
+}
+
+gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws, size_t ws_bytes,
+                      void *hip_stream, gs_report *rep)
+{
+    g_detail.clear();
+    if (n < 0) return fail(GS_EINVAL, "n < 0");
+    if (n > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
+    gs_status s = check_fraction(buffer_fraction);
+    if (s != GS_OK) return s;
+    if (n > ((int64_t)1 << 40)) return fail(GS_EINVAL, "n above 2^40");
+    gs::SortPlan p = gs::plan_f64(n);
+    if (n > 1) {
+        if ((int64_t)ws_bytes < p.bytes || !ws)
+            return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);
+        if (!aligned256(ws)) return fail(GS_EINVAL, "workspace not 256-byte aligned");
+    }
+    if (n <= 1) {
+        if (rep) { memset(rep, 0, sizeof *rep); rep->ram_fraction = 1.0; }
+        return GS_OK;
+    }
+    if ((s = check_device()) != GS_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Reporter r(rep, st);
+    hipError_t e = gs::sort_f64_async(keys, n, (char *)ws, p, st);
+    if (e != hipSuccess) return r.finish(hip_fail(e, "gs_sort_f64 launch"));
+    if (rep) {
+        rep->levels = (uint32_t)p.depth;
+        rep->workspace_bytes_used = (uint64_t)p.bytes;
+        rep->ram_fraction = n > 0 ? 1.0 + (double)p.bytes / (8.0 * (double)n) : 1.0;
+    }
+    s = r.finish(GS_OK);
+    if (rep && s == GS_OK) s = check_err_word((const char *)ws, p);
+    return s;
+}
+
+gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fraction, void *ws,
+                     size_t ws_bytes, void *hip_stream, gs_report *rep)
+{
+    g_detail.clear();
+    if (n < 0) return fail(GS_EINVAL, "n < 0");
+    if (n > 0 && (!keys || !vals)) return fail(GS_EINVAL, "keys or vals is NULL");
+    gs_status s = check_fraction(buffer_fraction);
+    if (s != GS_OK) return s;
+    if (n > ((int64_t)1 << 40)) return fail(GS_EINVAL, "n above 2^40");
+    gs::SortPlan p = gs::plan_kv(n);
+    if (n > 1) {
+        if ((int64_t)ws_bytes < p.bytes || !ws)
+            return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);
+        if (!aligned256(ws)) return fail(GS_EINVAL, "workspace not 256-byte aligned");
+    }
+    if (n <= 1) {
+        if (rep) { memset(rep, 0, sizeof *rep); rep->ram_fraction = 1.0; }
+        return GS_OK;
+    }
+    if ((s = check_device()) != GS_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Reporter r(rep, st);
+    hipError_t e = gs::sort_kv_async(keys, vals, n, (char *)ws, p, st);
+    if (e != hipSuccess) return r.finish(hip_fail(e, "gs_sort_kv launch"));
+    if (rep) {
+        rep->levels = (uint32_t)p.depth;
+        rep->workspace_bytes_used = (uint64_t)p.bytes;
+        rep->ram_fraction = n > 0 ? 1.0 + (double)p.bytes / (12.0 * (double)n) : 1.0;
+    }
+    s = r.finish(GS_OK);
+    if (rep && s == GS_OK) s = check_err_word((const char *)ws, p);
+    return s;
+}
+
+}  // extern "C"
+
+// ---- entry points whose device path is not built yet ----------------------
+extern "C" {
+
+void gs_learned_default_params(gs_learned_params *p)
+{
+    memset(p, 0, sizeof *p);
+    p->num_buckets = 4096;
+    p->sample_size = 65536;
+    p->train_steps = 200;
+    p->batch = 2048;
+    p->knots = 16384;
+    p->lr = 1e-2f;
+    p->seed = 0x5eed;
+    p->mode = 0;
+}
+
+size_t gs_workspace_bytes_seg(int64_t num_keys, int64_t num_segments, double buffer_fraction)
+{
+    if (num_keys < 0 || num_segments < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
+    return 0;
+}
+
+size_t gs_workspace_bytes_learned(int64_t n, const gs_learned_params *p)
+{
+    (void)p;
+    if (n < 0) return SIZE_MAX;
+    return 0;
+}
+
+gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets, int64_t num_segments,
+                     double buffer_fraction, void *ws, size_t ws_bytes, void *hip_stream,
+                     gs_report *rep)
+{
+    (void)keys; (void)num_keys; (void)offsets; (void)num_segments; (void)buffer_fraction;
+    (void)ws; (void)ws_bytes; (void)hip_stream; (void)rep;
+    return fail(GS_EUNSUPPORTED, "gs_segsort: not built in this version");
+}
+
+gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p, void *ws,
+                          size_t ws_bytes, void *hip_stream, gs_report *rep)
+{
+    (void)keys; (void)n; (void)p; (void)ws; (void)ws_bytes; (void)hip_stream; (void)rep;
+    return fail(GS_EUNSUPPORTED, "gs_learned_sort: not built in this version");
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Device-side building blocks shared by the sorting kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "frog_geometry.h"
+
+namespace gs {
+
+// ---------------------------------------------------------------------------
+// key types
+// ---------------------------------------------------------------------------
+// float64: IEEE `<`, NaN greater than everything and tied with every NaN,
+// -0.0 tied with +0.0.  less(a,b) = a is not NaN and not (a >= b).
+struct KeyF64 {
+    using T = double;
+    static __device__ __forceinline__ bool less(double a, double b) { return (a == a) && !(a >= b); }
+    static __device__ __forceinline__ double pad() { return __builtin_nan(""); }
+};
+
+struct KeyU64 {
+    using T = uint64_t;
+    static __device__ __forceinline__ bool less(uint64_t a, uint64_t b) { return a < b; }
+    static __device__ __forceinline__ uint64_t pad() { return ~(uint64_t)0; }
+};
+
+struct NoVal {};
+
+// ---------------------------------------------------------------------------
+// the logical frog space: slots [0, n) live in the caller's array, slots
+// [n, n + n/2) in the half buffer
+// ---------------------------------------------------------------------------
+template <class T>
+struct Space {
+    T *D;
+    T *H;
+    int64_t n;
+    __device__ __forceinline__ T *at(int64_t p) const { return p < n ? D + p : H + (p - n); }
+};
+
+// ---------------------------------------------------------------------------
+// ordered-store protocol
+// ---------------------------------------------------------------------------
+// A frog merge writes into slots still holding unread elements of its outer
+// run.  Tiles of one node take tickets in the node's write order (top-down for
+// a left node, bottom-up for a right node); an outer-run element is always read
+// by a tile that is not later in that order than the tile that overwrites its
+// slot.  So a tile may store once every earlier tile of its node has loaded.
+// Status words: (epoch << 2) | state, state 1 = loaded, 2 = loaded and every
+// earlier tile loaded ("prefix").  Epochs are distinct per launch of a call and
+// the words are cleared at the start of every call.
+enum : unsigned { ST_LOADED = 1u, ST_PREFIX = 2u };
+
+__device__ __forceinline__ unsigned ld_status(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_status(unsigned *p, unsigned v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by one full wavefront after the work-group's loads have completed and
+// its loaded status is published.  Returns once every ticket in [first, t) has
+// loaded; then publishes `prefix` for t.  Every wait is bounded: a wait that
+// exceeds kSpinLimit polls sets *err (the call then reports a device error)
+// and gives up, so no wave can spin forever.
+constexpr unsigned kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void lookback_wait(unsigned *status, int64_t first, int64_t t,
+                                              unsigned epoch, unsigned *err)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned want = epoch << 2;
+    int64_t hi = t - 1;
+    while (hi >= first) {
+        const int64_t idx = hi - lane;
+        const bool valid = idx >= first;
+        unsigned st = 0;
+        if (valid) {
+            unsigned spins = 0;
+            st = ld_status(status + idx);
+            while (((st & ~3u) != want || (st & 3u) == 0u) && spins < kSpinLimit) {
+                __builtin_amdgcn_s_sleep(1);
+                st = ld_status(status + idx);
+                ++spins;
+            }
+            if (spins >= kSpinLimit) {
+                st = want | ST_PREFIX;         // give up waiting
+                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        const unsigned long long pre = __ballot(valid && (st & 3u) == ST_PREFIX);
+        if (pre != 0ull || hi - 63 <= first) break;
+        hi -= 64;
+    }
+    if (lane == 0) st_status(status + t, want | ST_PREFIX);
+}
+
+// ---------------------------------------------------------------------------
+// merge path
+// ---------------------------------------------------------------------------
+// Stable merge of runs A (first in input order) and B: on a tie the A element
+// comes first.  For an output prefix of length k, the number of A elements in
+// it is the first a in [max(0,k-nb), min(k,na)] with less(B[k-1-a], A[a]).
+template <class KT, class GetA, class GetB>
+__device__ __forceinline__ int merge_path_lds(int k, int na, int nb, GetA A, GetB B)
+{
+    int lo = k > nb ? k - nb : 0;
+    int hi = k < na ? k : na;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (KT::less(B(k - 1 - mid), A(mid))) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+}  // namespace gs

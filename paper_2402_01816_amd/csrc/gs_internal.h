@@ -1,0 +1,42 @@
+// Internal interface between the C ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+// Index (in the ticket-counter block) of the word the kernels set when a
+// bounded wait gave up; it is cleared with the counters on every call.
+constexpr int kErrWord = 63;
+
+// Workspace layout and tree shape of one plain sort.
+struct SortPlan {
+    int64_t n;            // keys
+    int64_t leaf;         // largest leaf (elements)
+    int64_t tile;         // merge output tile (elements)
+    int depth;            // tree depth = number of merge levels
+    int64_t off_hkeys;    // half buffer for keys: floor(n/2) elements
+    int64_t off_hvals;    // half buffer for values (kv only)
+    int64_t off_tickets;  // per-launch ticket counters
+    int64_t n_tickets;
+    int64_t off_status;   // per-tile status words
+    int64_t n_status;
+    int64_t off_splits;   // merge-path splits of the current level
+    int64_t bytes;        // total workspace
+};
+
+SortPlan plan_f64(int64_t n);
+SortPlan plan_kv(int64_t n);
+hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st);
+hipError_t sort_kv_async(uint64_t *keys, uint32_t *vals, int64_t n, char *ws, const SortPlan &p,
+                         hipStream_t st);
+void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st);
+
+// Launch tracing (measurement only).  When enabled on the calling thread,
+// launchers bracket every kernel launch with HIP events on its stream.
+enum TraceKind : int { TK_FILL = 0, TK_LEAF = 1, TK_PARTITION = 2, TK_MERGE = 3, TK_OTHER = 4 };
+bool trace_on();
+void trace_begin(int kind, hipStream_t st);
+void trace_end(hipStream_t st);
+
+}  // namespace gs

@@ -1,0 +1,94 @@
+"""Host-side checks of libgs.so that need no GPU: it loads, exports every
+symbol include/gs.h declares, validates arguments before touching the device,
+reports GS_ENODEVICE without a device, and its planner reproduces the oracle's
+frog geometry."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2402_01816_amd as g
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "gs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert "gs_sort_f64" in names and "gs_learned_sort" in names
+    lib = ctypes.CDLL(g.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_strings():
+    assert "gfx950" in g.version()
+    for s in range(6):
+        assert g.lib.gs_status_string(s).decode() == g.STATUS_NAMES[s]
+
+
+def test_workspace_sizes():
+    assert g.gs_workspace_bytes_f64(0) == 0 and g.gs_workspace_bytes_f64(1) == 0
+    for n in [2, 3, 1000, 4097, 1 << 20, 1 << 28]:
+        b = g.gs_workspace_bytes_f64(n)
+        assert b >= 8 * (n // 2)
+        assert b <= 8 * (n // 2) + 4096 + n // 64 + 64 * 1024
+    n = 1 << 28
+    assert 1.5 < 1 + g.gs_workspace_bytes_f64(n) / (8 * n) < 1.5015
+    assert g.gs_workspace_bytes_kv(n) >= 12 * (n // 2)
+    assert g.gs_workspace_bytes_f64(-1) == g.SIZE_MAX
+
+
+def _call_f64(keys, n, frac, ws, wsb):
+    return g.lib.gs_sort_f64(keys, n, frac, ws, wsb, None, None)
+
+
+def test_argument_errors_before_device():
+    fake = ctypes.c_void_p(0x100000)
+    need = g.gs_workspace_bytes_f64(1000)
+    assert _call_f64(fake, -1, 0.5, fake, need) == g.GS_EINVAL
+    assert _call_f64(None, 10, 0.5, fake, need) == g.GS_EINVAL
+    assert _call_f64(fake, 1000, 0.0, fake, need) == g.GS_EINVAL
+    assert _call_f64(fake, 1000, float("nan"), fake, need) == g.GS_EINVAL
+    assert _call_f64(fake, 1000, 0.25, fake, need) == g.GS_EUNSUPPORTED
+    assert _call_f64(fake, 1000, 0.5, fake, need - 1) == g.GS_EWORKSPACE
+    assert _call_f64(fake, 1000, 0.5, None, need) == g.GS_EWORKSPACE
+    assert _call_f64(fake, 1000, 0.5, ctypes.c_void_p(0x100010), need) == g.GS_EINVAL
+    assert "aligned" in g.lib.gs_last_error_detail().decode()
+    assert g.lib.gs_sort_kv(fake, None, 10, 0.5, fake, 1 << 20, None, None) == g.GS_EINVAL
+    # n <= 1 is a no-op that needs no workspace and no device
+    assert _call_f64(None, 0, 0.5, None, 0) == g.GS_OK
+    assert _call_f64(fake, 1, 0.5, None, 0) == g.GS_OK
+
+
+def test_no_device_reported():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is visible")
+    except ImportError:
+        pass
+    fake = ctypes.c_void_p(0x100000)
+    need = g.gs_workspace_bytes_f64(1000)
+    assert _call_f64(fake, 1000, 0.5, fake, need) == g.GS_ENODEVICE
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 100, 4096, 4097, 12345, 1 << 20, (1 << 20) + 7,
+                               (1 << 28) + 3])
+def test_planner_matches_oracle_geometry(orc, n):
+    depth, leaf = g.plan_depth(n)
+    assert -(-n // (1 << depth)) <= leaf
+    assert depth == 0 or -(-n // (1 << (depth - 1))) > leaf
+    for d in range(min(depth, 12) + 1):
+        geo = orc.frog_geometry(n, d)
+        step = max(1, geo.shape[0] // 200)
+        for i in range(0, geo.shape[0], step):
+            assert tuple(int(v) for v in geo[i]) == g.plan_node(n, d, i)

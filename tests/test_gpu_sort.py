@@ -1,0 +1,117 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Small and medium sizes are compared element by element, bit for bit, with the
+oracle's full result.  Sizes span one leaf, several leaves and merge tiles, and
+ragged tails.  At the full benchmark size the oracle's counting form of the
+definition fixes sampled output positions, and the rest is checked by
+properties (sorted, same multiset).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import announce, bits, multiset_hash_dev, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 2, 3, 17, 255, 4095, 4096, 4097, 8191, 8193, 12345, 65536, 100003,
+         1 << 20, (1 << 20) + 7]
+PATTERNS = ["uniform", "tied", "presorted", "reversed", "perturbed", "zeros_signed"]
+
+
+@pytest.fixture(scope="module")
+def gs():
+    need_gpu()
+    import paper_2402_01816_amd as g
+    return g
+
+
+@pytest.mark.parametrize("pattern", PATTERNS)
+@pytest.mark.parametrize("n", SIZES)
+def test_sort_f64_parity(gs, orc, pattern, n):
+    announce("sort_f64", pattern, n)
+    x = W.f64_pattern(pattern, n, seed=11)
+    t = to_dev(x)
+    gs.gs_sort_f64(t)
+    ref = orc.sort_f64(x)
+    assert np.array_equal(bits(t), bits(ref))
+
+
+def test_sort_f64_special_values(gs, orc):
+    announce("sort_f64 special")
+    rng = np.random.default_rng(7)
+    n = 50_000
+    pool = np.array([np.nan, -np.nan, np.inf, -np.inf, 0.0, -0.0, 5e-324, -5e-324,
+                     2.2250738585072014e-308, 1.0, -1.0, 1e308], dtype=np.float64)
+    x = pool[rng.integers(0, pool.size, n)]
+    x[::97] = np.frombuffer(np.uint64(0x7FF0000000000ABC).tobytes(), dtype=np.float64)[0]
+    t = to_dev(x)
+    gs.gs_sort_f64(t)
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+def test_sort_f64_report_and_ram(gs):
+    torch = need_gpu()
+    n = 1 << 20
+    t = to_dev(W.f64_pattern("uniform", n))
+    rep = gs.gs_sort_f64(t, report=True)
+    assert rep["levels"] == gs.plan_depth(n)[0]
+    assert 1.5 <= rep["ram_fraction"] < 1.52
+    assert rep["workspace_bytes_used"] == gs.gs_workspace_bytes_f64(n)
+    assert rep["elapsed_ms"] > 0
+    del torch
+
+
+@pytest.mark.parametrize("pattern", ["uniform", "zipf", "few"])
+@pytest.mark.parametrize("n", [0, 1, 2, 5, 2047, 2048, 2049, 4097, 10000, 65537, 1 << 20])
+def test_sort_kv_parity(gs, orc, pattern, n):
+    announce("sort_kv", pattern, n)
+    k, v = W.kv_pattern(pattern, n, seed=5)
+    tk = to_dev(k.view(np.int64))
+    tv = to_dev(v.view(np.int32))
+    gs.gs_sort_kv(tk, tv)
+    rk, rv = orc.sort_kv(k, v)
+    assert np.array_equal(tk.cpu().numpy().view(np.uint64), rk)
+    assert np.array_equal(tv.cpu().numpy().view(np.uint32), rv)
+
+
+def test_repeated_calls_share_workspace(gs, orc):
+    torch = need_gpu()
+    n = 300_001
+    need = gs.gs_workspace_bytes_f64(n)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    wsv = ws[off:off + need]
+    for seed in range(3):
+        x = W.f64_pattern("zeros_signed", n, seed=seed)
+        t = to_dev(x)
+        gs.gs_sort_f64(t, workspace=wsv)
+        assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+    # a smaller sort afterwards on the same workspace
+    x = W.f64_pattern("tied", 5000, seed=9)
+    t = to_dev(x)
+    gs.gs_sort_f64(t, workspace=wsv[: gs.gs_workspace_bytes_f64(5000)])
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+FULL_N = 1 << 28
+
+
+@pytest.mark.parametrize("pattern", W.PATTERNS)
+def test_sort_f64_full_size_sampled(gs, orc, pattern):
+    """n = 2^28: sampled positions from the oracle's counting definition, plus
+    sortedness and multiset equality over the whole output."""
+    torch = need_gpu()
+    announce("sort_f64 full", pattern, FULL_N)
+    x = W.f64_pattern(pattern, FULL_N, seed=0)
+    t = to_dev(x)
+    h_in = multiset_hash_dev(t)
+    gs.gs_sort_f64(t)
+    torch.cuda.synchronize()
+    assert multiset_hash_dev(t) == h_in
+    assert bool((t[1:] >= t[:-1]).all().item())
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([[0, FULL_N - 1], rng.integers(0, FULL_N, 14)])
+    ranks = orc.rank_f64(x, idx)
+    got = t[torch.from_numpy(ranks).to("cuda")].cpu().numpy()
+    assert np.array_equal(bits(got), bits(x[idx]))

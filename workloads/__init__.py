@@ -155,7 +155,7 @@ def f64_pattern(pattern: str, n: int, seed: int = 0, workload: int = 2,
     if pattern in ("presorted", "reversed", "perturbed"):
         x = (np.arange(n, dtype=np.float64) + uniform01(n, key)) / float(max(n, 1))
         if pattern == "reversed":
-            return np.ascontiguousarray(x[::-1])
+            return x[::-1].copy()
         if pattern == "perturbed":
             k = int(math.floor(perturb * n))
             pos = permute_indices(np.arange(k), n, key ^ 0x1234)

@@ -94,6 +94,22 @@ def main():
         rep = gs.gs_sort_f64(buf, workspace=ws, report=True)
     del buf
 
+    # empirical ceiling: a device-to-device copy moves the same 16n bytes as
+    # one merge pass (8n read + 8n write)
+    dst = torch.empty_like(pristine)
+    for _ in range(2):
+        dst.copy_(pristine)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        dst.copy_(pristine)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = c0.elapsed_time(c1) / 5
+    copy_gbs = 16.0 * n / (copy_ms * 1e-3) / 1e9
+    del dst
+
     log(f"preparing {args.steps} input copies")
     copies = [pristine.clone() for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -161,6 +177,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "kernel": "merge_kernel",
                      "bytes_per_launch": merge_bytes, "avg_launch_ms": round(merge_avg, 5)},
+        "copy_ceiling_gbs": round(copy_gbs, 1),
+        "merge_frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None,
         "ram_fraction": round(ram, 5),
         "t_footprint_ram_s": round(ram * ms_per_step * 1e-3, 6),
         "whole_sort_hbm_frac": round(whole_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -12,8 +12,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
-LIB = os.path.join(HERE, "libgs.so")
-OBJDIR = os.path.join(HERE, "_build")
+LIB = os.environ.get("GS_LIB_OUT", os.path.join(HERE, "libgs.so"))
+OBJDIR = os.environ.get("GS_OBJ_DIR", os.path.join(HERE, "_build"))
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["gs_abi.cpp", "gs_sort.hip"]
@@ -25,7 +25,7 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-]
+] + os.environ.get("GS_EXTRA_CFLAGS", "").split()
 
 
 def _compile(src: str) -> str:

@@ -80,6 +80,27 @@ GS_HD FrogMerge frog_merge_of(const FrogNode &f)
     return m;
 }
 
+// Leaf (node index at `depth`) whose input chunk holds input position p.
+GS_HD int64_t frog_leaf_of(int64_t n_total, int depth, int64_t p)
+{
+    int64_t n = n_total, in_off = 0, idx = 0;
+    int left = 1;
+    for (int d = 0; d < depth; ++d) {
+        const int64_t nl = left ? (n + 1) / 2 : n / 2;
+        if (p < in_off + nl) {
+            n = nl;
+            left = 1;
+            idx = idx * 2;
+        } else {
+            in_off += nl;
+            n -= nl;
+            left = 0;
+            idx = idx * 2 + 1;
+        }
+    }
+    return idx;
+}
+
 // Depth at which every node holds at most leaf_max elements (sizes at depth d
 // are floor(n/2^d) or ceil(n/2^d)).
 GS_HD int frog_depth(int64_t n, int64_t leaf_max)

@@ -41,15 +41,16 @@ struct Space {
 // ---------------------------------------------------------------------------
 // ordered-store protocol
 // ---------------------------------------------------------------------------
-// A frog merge writes into slots still holding unread elements of its outer
-// run.  Tiles of one node take tickets in the node's write order (top-down for
-// a left node, bottom-up for a right node); an outer-run element is always read
-// by a tile that is not later in that order than the tile that overwrites its
-// slot.  So a tile may store once every earlier tile of its node has loaded.
-// Status words: (epoch << 2) | state, state 1 = loaded, 2 = loaded and every
-// earlier tile loaded ("prefix").  Epochs are distinct per launch of a call and
-// the words are cleared at the start of every call.
-enum : unsigned { ST_LOADED = 1u, ST_PREFIX = 2u };
+// A frog merge writes into slots that still hold unread elements of its outer
+// run (the leaf launch likewise writes over input chunks of other leaves).
+// Every work item publishes a status word once its inputs sit in LDS, and
+// before storing it waits for exactly the work items that read the slots it is
+// about to overwrite (its dependency window, a range of tickets).  Those always
+// hold smaller tickets, so they are already running and publish without
+// waiting on anything: the waits cannot deadlock.
+// Status words: (epoch << 2) | 1; epochs differ between launches of one call
+// and the words are cleared at the start of every call.
+enum : unsigned { ST_LOADED = 1u };
 
 __device__ __forceinline__ unsigned ld_status(const unsigned *p)
 {
@@ -61,41 +62,31 @@ __device__ __forceinline__ void st_status(unsigned *p, unsigned v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Called by one full wavefront after the work-group's loads have completed and
-// its loaded status is published.  Returns once every ticket in [first, t) has
-// loaded; then publishes `prefix` for t.  Every wait is bounded: a wait that
-// exceeds kSpinLimit polls sets *err (the call then reports a device error)
-// and gives up, so no wave can spin forever.
+// Every wait is bounded: a wait that exceeds kSpinLimit polls sets *err (the
+// call then reports a device error) and gives up, so no wave spins forever.
 constexpr unsigned kSpinLimit = 1u << 22;
 
-__device__ __forceinline__ void lookback_wait(unsigned *status, int64_t first, int64_t t,
-                                              unsigned epoch, unsigned *err)
+// Called by one full wavefront: returns once every ticket in [lo, hi] other
+// than `self` has published its loaded status for `epoch`.
+__device__ __forceinline__ void wait_window(const unsigned *status, int64_t lo, int64_t hi,
+                                            int64_t self, unsigned epoch, unsigned *err)
 {
     const int lane = threadIdx.x & 63;
     const unsigned want = epoch << 2;
-    int64_t hi = t - 1;
-    while (hi >= first) {
-        const int64_t idx = hi - lane;
-        const bool valid = idx >= first;
-        unsigned st = 0;
-        if (valid) {
+    for (int64_t base = lo; base <= hi; base += 64) {
+        const int64_t idx = base + lane;
+        if (idx <= hi && idx != self) {
             unsigned spins = 0;
-            st = ld_status(status + idx);
-            while (((st & ~3u) != want || (st & 3u) == 0u) && spins < kSpinLimit) {
+            unsigned st = ld_status(status + idx);
+            while ((st & ~3u) != want && spins < kSpinLimit) {
                 __builtin_amdgcn_s_sleep(1);
                 st = ld_status(status + idx);
                 ++spins;
             }
-            if (spins >= kSpinLimit) {
-                st = want | ST_PREFIX;         // give up waiting
+            if (spins >= kSpinLimit)
                 __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
         }
-        const unsigned long long pre = __ballot(valid && (st & 3u) == ST_PREFIX);
-        if (pre != 0ull || hi - 63 <= first) break;
-        hi -= 64;
     }
-    if (lane == 0) st_status(status + t, want | ST_PREFIX);
 }
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,7 @@ struct SortPlan {
     int64_t off_status;   // per-tile status words
     int64_t n_status;
     int64_t off_splits;   // merge-path splits of the current level
+    int64_t off_deps;     // dependency window (two tickets) of every merge tile
     int64_t bytes;        // total workspace
 };
 

@@ -1,5 +1,6 @@
 // Plain frog mergesort for one array: leaf block sort fused with the setup
-// placement, merge-path partition, and the in-place frog merge per level.
+// placement, merge-path partition, dependency windows, and the in-place frog
+// merge per level.
 //
 // Paper: "Symmetric merging" (mirrored child placement, merge from the inner
 // ends outward), "Frogsort1" (rule 1: surplus to the outer side; rule 2:
@@ -40,14 +41,50 @@ struct ValOps<NoVal> {
     static constexpr bool has = false;
 };
 
+// LDS index with one pad slot per 16 elements: a thread's IPT consecutive
+// outputs, and merge heads spaced about 8 apart, land in distinct banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// slots for TILE elements plus one readable slot past the end
+template <int TILE>
+constexpr int lds_slots() { return TILE + TILE / 16 + 2; }
+
+// Serial stable merge of IPT outputs from LDS runs A = [a_base, a_base+na) and
+// B = [b_base, b_base+nb) (logical LDS indices) starting at A index ai and B
+// index bi; on a tie the A element goes first.  Branch free: the heads of both
+// runs stay in registers, every step costs one comparison and one LDS read,
+// and reads past a run's end (clamped to `limit`, a readable slot) are never
+// selected.  Outputs beyond the runs' total are garbage and must be ignored.
+template <class KT, int IPT, bool WANT_SRC>
+__device__ __forceinline__ void serial_merge(const typename KT::T *sk, int a_base, int na, int b_base,
+                                             int nb, int ai, int bi, int limit,
+                                             typename KT::T (&k)[IPT], int (&src)[IPT])
+{
+    using K = typename KT::T;
+    K va = sk[lpad(min(a_base + ai, limit))];
+    K vb = sk[lpad(min(b_base + bi, limit))];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const bool takeB = (bi < nb) & ((ai >= na) | KT::less(vb, va));
+        k[i] = takeB ? vb : va;
+        if constexpr (WANT_SRC) src[i] = takeB ? b_base + bi : a_base + ai;
+        bi += takeB ? 1 : 0;
+        ai += takeB ? 0 : 1;
+        const int nidx = min(takeB ? b_base + bi : a_base + ai, limit);
+        const K nv = sk[lpad(nidx)];
+        va = takeB ? va : nv;
+        vb = takeB ? nv : vb;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // leaf kernel: sort each leaf's input chunk and place it at its frog slot
 // ---------------------------------------------------------------------------
 // Leaf i takes the i-th contiguous chunk of the input (the order the setup
 // recursion visits elements) and leaves it sorted at its data start, which is
 // never before its input offset.  A leaf's output can therefore only cover
-// input chunks of leaves with a larger index, so leaves are processed in
-// descending index order under the ordered-store protocol.
+// input chunks of leaves with a larger index: leaves take tickets in
+// descending index order, and each waits for the leaves whose chunks its
+// output covers.
 template <class KT, class V, int NT, int IPT>
 __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Space<V> vals,
                                                   int64_t n_total, int depth, int64_t nleaves,
@@ -56,29 +93,46 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Sp
 {
     using K = typename KT::T;
     constexpr bool HV = ValOps<V>::has;
+    using VS = typename std::conditional<HV, V, char>::type;
     constexpr int TILE = NT * IPT;
-    __shared__ K sk[TILE];
-    __shared__ typename std::conditional<HV, V, char>::type sv[HV ? TILE : 1];
+    constexpr int SLOTS = lds_slots<TILE>();
+    __shared__ K sk[SLOTS];
+    __shared__ VS sv[HV ? SLOTS : 1];
     __shared__ unsigned s_ticket;
 
     const int tid = threadIdx.x;
     if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
     __syncthreads();
-    const int64_t t = s_ticket;
+    const int64_t t = __builtin_amdgcn_readfirstlane(s_ticket);
     const int64_t leaf = nleaves - 1 - t;
     const FrogNode f = frog_node(n_total, depth, leaf);
     const int len = (int)f.n;
     const int64_t src = f.in_off;
     const int64_t dst = frog_data_start(f);
 
-    // load the chunk (input elements all live in the caller's array)
-    for (int i = tid; i < TILE; i += NT) {
-        if (i < len) {
-            sk[i] = keys.D[src + i];
-            if constexpr (HV) sv[i] = vals.D[src + i];
-        } else {
-            sk[i] = KT::pad();
-            if constexpr (HV) sv[i] = V();
+    // load the chunk (input elements all live in the caller's array); all
+    // loads are issued before the first LDS write
+    {
+        K lk[IPT];
+        VS lv[IPT];
+        // straight-line loads from clamped indices; slots past the chunk get
+        // the padding key, which sorts after every real key
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int i = tid + r * NT;
+            const int ic = min(i, len - 1);
+            const K kv = keys.D[src + ic];
+            lk[r] = i < len ? kv : KT::pad();
+            if constexpr (HV) {
+                const V vv = vals.D[src + ic];
+                lv[r] = i < len ? vv : V();
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int i = tid + r * NT;
+            sk[lpad(i)] = lk[r];
+            if constexpr (HV) sv[lpad(i)] = lv[r];
         }
     }
     __syncthreads();
@@ -87,86 +141,93 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Sp
     // per-thread odd-even transposition sort: only adjacent strict inversions
     // are exchanged, so equal keys keep their order
     K k[IPT];
-    typename std::conditional<HV, V, char>::type v[IPT];
+    VS v[IPT];
+    int srcix[IPT];
     const int base = tid * IPT;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        k[i] = sk[base + i];
-        if constexpr (HV) v[i] = sv[base + i];
+        k[i] = sk[lpad(base + i)];
+        if constexpr (HV) v[i] = sv[lpad(base + i)];
     }
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
 #pragma unroll
         for (int i = (r & 1); i + 1 < IPT; i += 2) {
-            if (KT::less(k[i + 1], k[i])) {
-                K tk = k[i]; k[i] = k[i + 1]; k[i + 1] = tk;
-                if constexpr (HV) { auto tv = v[i]; v[i] = v[i + 1]; v[i + 1] = tv; }
+            const bool sw = KT::less(k[i + 1], k[i]);
+            const K lo = sw ? k[i + 1] : k[i];
+            const K hi = sw ? k[i] : k[i + 1];
+            k[i] = lo;
+            k[i + 1] = hi;
+            if constexpr (HV) {
+                const VS vlo = sw ? v[i + 1] : v[i];
+                const VS vhi = sw ? v[i] : v[i + 1];
+                v[i] = vlo;
+                v[i + 1] = vhi;
             }
         }
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        sk[base + i] = k[i];
-        if constexpr (HV) sv[base + i] = v[i];
+        sk[lpad(base + i)] = k[i];
+        if constexpr (HV) sv[lpad(base + i)] = v[i];
     }
     __syncthreads();
 
     // merge rounds in LDS: runs of w -> 2w
     for (int w = IPT; w < TILE; w *= 2) {
-        const int pair = base / (2 * w);
-        const int a0 = pair * 2 * w;
+        const int a0 = (base / (2 * w)) * 2 * w;
         const int b0 = a0 + w;
         const int kd = base - a0;
-        int ai = merge_path_lds<KT>(kd, w, w, [&](int i) { return sk[a0 + i]; },
-                                    [&](int i) { return sk[b0 + i]; });
-        int bi = kd - ai;
+        const int ai = merge_path_lds<KT>(kd, w, w, [&](int i) { return sk[lpad(a0 + i)]; },
+                                          [&](int i) { return sk[lpad(b0 + i)]; });
+        serial_merge<KT, IPT, HV>(sk, a0, w, b0, w, ai, kd - ai, TILE, k, srcix);
+        if constexpr (HV) {
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            bool takeB;
-            if (ai >= w) takeB = true;
-            else if (bi >= w) takeB = false;
-            else takeB = KT::less(sk[b0 + bi], sk[a0 + ai]);
-            const int idx = takeB ? b0 + bi : a0 + ai;
-            k[i] = sk[idx];
-            if constexpr (HV) v[i] = sv[idx];
-            if (takeB) ++bi; else ++ai;
+            for (int i = 0; i < IPT; ++i) v[i] = sv[lpad(srcix[i])];
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            sk[base + i] = k[i];
-            if constexpr (HV) sv[base + i] = v[i];
+            sk[lpad(base + i)] = k[i];
+            if constexpr (HV) sv[lpad(base + i)] = v[i];
         }
         __syncthreads();
     }
 
-    // wait until every leaf with a larger index has loaded its chunk
-    if (tid < 64) lookback_wait(status, 0, t, epoch, err);
+    // wait for the leaves whose input chunks the destination covers
+    if (tid < 64 && dst < n_total) {
+        const int64_t end = (dst + len < n_total ? dst + len : n_total) - 1;
+        const int64_t lo_leaf = frog_leaf_of(n_total, depth, dst);
+        const int64_t hi_leaf = frog_leaf_of(n_total, depth, end);
+        wait_window(status, nleaves - 1 - hi_leaf, nleaves - 1 - lo_leaf, t, epoch, err);
+    }
     __syncthreads();
 
-    for (int i = tid; i < len; i += NT) {
-        *keys.at(dst + i) = sk[i];
-        if constexpr (HV) *vals.at(dst + i) = sv[i];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const int i = tid + r * NT;
+        if (i < len) {
+            *keys.at(dst + i) = sk[lpad(i)];
+            if constexpr (HV) *vals.at(dst + i) = sv[lpad(i)];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // partition kernel: merge-path splits at every tile boundary of every node
 // ---------------------------------------------------------------------------
-// One wavefront per (node, boundary j): a 64-ary search for the number of
-// left-run elements among the first j*TILE outputs of the node's stable merge.
+// One thread per (node, boundary j): binary search for the number of left-run
+// elements among the first j*TILE outputs of the node's stable merge.
 template <class KT, int TILE>
 __global__ __launch_bounds__(256) void partition_kernel(Space<typename KT::T> keys, int64_t n_total,
                                                         int depth, int64_t nnodes, int64_t tpn,
                                                         int64_t *splits)
 {
-    using K = typename KT::T;
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nnodes * (tpn + 1)) return;
     const int64_t node = w / (tpn + 1);
-    const int64_t j = w % (tpn + 1);
+    const int64_t j = w - node * (tpn + 1);
     const FrogNode f = frog_node(n_total, depth, node);
     const FrogMerge m = frog_merge_of(f);
     int64_t kk = j * TILE;
@@ -174,50 +235,53 @@ __global__ __launch_bounds__(256) void partition_kernel(Space<typename KT::T> ke
     int64_t lo = kk > m.nr ? kk - m.nr : 0;
     int64_t hi = kk < m.nl ? kk : m.nl;
     while (lo < hi) {
-        const int64_t span = hi - lo;
-        const int64_t step = (span + 63) / 64;
-        const int64_t a = lo + (int64_t)lane * step;
-        bool need_more_a = false;
-        if (a < hi) {
-            const K av = *keys.at(m.l0 + a);
-            const K bv = *keys.at(m.r0 + (kk - 1 - a));
-            need_more_a = !KT::less(bv, av);
-        }
-        const int c = __popcll(__ballot(need_more_a));
-        if (step == 1) { lo += c; break; }
-        if (c == 0) break;                      // first candidate already settles it
-        const int64_t nlo = lo + (int64_t)(c - 1) * step + 1;
-        const int64_t nhi = lo + (int64_t)c * step;
-        lo = nlo;
-        hi = nhi < hi ? nhi : hi;
+        const int64_t mid = (lo + hi) >> 1;
+        if (KT::less(*keys.at(m.r0 + (kk - 1 - mid)), *keys.at(m.l0 + mid))) hi = mid;
+        else lo = mid + 1;
     }
-    if (lane == 0) splits[w] = lo;
+    splits[w] = lo;
 }
 
 // ---------------------------------------------------------------------------
-// merge kernel: one output tile of one node per work-group
+// dependency windows of every merge tile
 // ---------------------------------------------------------------------------
-// A left node writes its output top-down (its outer run is the left child's
-// data, which only moves right); a right node bottom-up (its outer run is the
-// right child's data, which only moves left).  Inner runs lie outside the
-// output.  Tickets are handed out in each node's write order.
-template <class KT, class V, int NT, int IPT>
-__global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, Space<V> vals,
-                                                   int64_t n_total, int depth, int64_t tpn,
-                                                   const int64_t *splits, unsigned *ticket_ctr,
-                                                   unsigned *status, unsigned epoch, unsigned *err)
+// A left node's tile with output ranks [k0,k1) overwrites the outer-run (left
+// child) elements with indices [k0, min(k1,nl)); a right node's tile overwrites
+// the outer-run (right child) elements with indices [k0-nl, k1-nl) clipped to
+// [0,nr).  The tiles that read those elements follow from the splits; their
+// tickets form one contiguous range that never starts after the tile's own.
+__device__ __forceinline__ int64_t upper_bound_splits(const int64_t *sp, int64_t count, int64_t x)
 {
-    using K = typename KT::T;
-    constexpr bool HV = ValOps<V>::has;
-    constexpr int TILE = NT * IPT;
-    __shared__ K sk[TILE];
-    __shared__ typename std::conditional<HV, V, char>::type sv[HV ? TILE : 1];
-    __shared__ unsigned s_ticket;
+    int64_t lo = 0, hi = count;          // first j with sp[j] > x
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (sp[mid] > x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
 
-    const int tid = threadIdx.x;
-    if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
-    __syncthreads();
-    const int64_t t = s_ticket;
+template <int TILE>
+__device__ __forceinline__ int64_t upper_bound_bsplits(const int64_t *sp, int64_t count, int64_t n,
+                                                       int64_t x)
+{
+    int64_t lo = 0, hi = count;          // first j with min(j*TILE,n) - sp[j] > x
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int64_t k = mid * TILE < n ? mid * TILE : n;
+        if (k - sp[mid] > x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+template <int TILE>
+__global__ __launch_bounds__(256) void depwin_kernel(int64_t n_total, int depth, int64_t nnodes,
+                                                     int64_t tpn, const int64_t *splits,
+                                                     int64_t *deps)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnodes * tpn) return;
     const int64_t node = t / tpn;
     const int64_t q = t - node * tpn;
     const int64_t first = node * tpn;
@@ -228,63 +292,186 @@ __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, S
     if (k0 > f.n) k0 = f.n;
     int64_t k1 = k0 + TILE;
     if (k1 > f.n) k1 = f.n;
-    if (k0 >= k1) {                              // empty tile (node shorter than tpn tiles)
-        if (tid == 0) st_status(status + t, (epoch << 2) | ST_LOADED);
-        return;
+    const int64_t *sp = splits + node * (tpn + 1);
+    int64_t lo = 1, hi = 0;              // empty window
+    if (k0 < k1) {
+        if (m.left) {
+            if (k0 < m.nl) {
+                const int64_t e = (k1 < m.nl ? k1 : m.nl) - 1;
+                const int64_t j0 = upper_bound_splits(sp, tpn + 1, k0) - 1;
+                const int64_t j1 = upper_bound_splits(sp, tpn + 1, e) - 1;
+                lo = first + (tpn - 1 - j1);
+                hi = first + (tpn - 1 - j0);
+            }
+        } else if (k1 > m.nl) {
+            const int64_t b0 = k0 > m.nl ? k0 - m.nl : 0;
+            const int64_t b1 = (k1 - m.nl < m.nr ? k1 - m.nl : m.nr) - 1;
+            const int64_t j0 = upper_bound_bsplits<TILE>(sp, tpn + 1, f.n, b0) - 1;
+            const int64_t j1 = upper_bound_bsplits<TILE>(sp, tpn + 1, f.n, b1) - 1;
+            lo = first + j0;
+            hi = first + j1;
+        }
     }
-    const int64_t a0 = splits[node * (tpn + 1) + j];
-    const int64_t a1 = splits[node * (tpn + 1) + j + 1];
-    const int la = (int)(a1 - a0);
-    const int lb = (int)((k1 - a1) - (k0 - a0));
-    const int64_t b0 = k0 - a0;
-    const int cnt = la + lb;
+    deps[2 * t] = lo;
+    deps[2 * t + 1] = hi;
+}
 
-    for (int i = tid; i < cnt; i += NT) {
-        const int64_t p = i < la ? m.l0 + a0 + i : m.r0 + b0 + (i - la);
-        sk[i] = *keys.at(p);
-        if constexpr (HV) sv[i] = *vals.at(p);
+// ---------------------------------------------------------------------------
+// merge kernel: persistent work-groups, one output tile per iteration
+// ---------------------------------------------------------------------------
+// A left node writes its output top-down (its outer run is the left child's
+// data, which only moves right); a right node bottom-up (its outer run is the
+// right child's data, which only moves left).  Inner runs lie outside the
+// output.  Tickets are handed out in each node's write order.  A work-group
+// takes the next ticket and issues that tile's loads while it merges and
+// stores the current one.
+struct MergeTile {
+    int64_t t;        // ticket
+    int64_t pa, pb;   // logical slots of the first left-run / right-run input
+    int64_t o;        // logical slot of the first output
+    int64_t dlo, dhi; // dependency window (tickets)
+    int la, cnt;      // left-run inputs, total inputs (= outputs)
+};
+
+template <int TILE>
+__device__ __forceinline__ MergeTile merge_tile_setup(int64_t t, int64_t n_total, int depth,
+                                                      int64_t tpn, const int64_t *splits,
+                                                      const int64_t *deps)
+{
+    MergeTile T;
+    T.t = t;
+    const int64_t node = (int64_t)((uint64_t)t / (uint64_t)tpn);
+    const int64_t q = t - node * tpn;
+    const FrogNode f = frog_node(n_total, depth, node);
+    const FrogMerge m = frog_merge_of(f);
+    const int64_t j = m.left ? (tpn - 1 - q) : q;
+    int64_t k0 = j * TILE;
+    if (k0 > f.n) k0 = f.n;
+    int64_t k1 = k0 + TILE;
+    if (k1 > f.n) k1 = f.n;
+    T.cnt = (int)(k1 - k0);
+    T.la = 0;
+    T.pa = T.pb = T.o = 0;
+    T.dlo = 1;
+    T.dhi = 0;
+    if (T.cnt > 0) {
+        const int64_t a0 = splits[node * (tpn + 1) + j];
+        const int64_t a1 = splits[node * (tpn + 1) + j + 1];
+        T.la = (int)(a1 - a0);
+        T.pa = m.l0 + a0;
+        T.pb = m.r0 + (k0 - a0);
+        T.o = m.out0 + k0;
+        T.dlo = deps[2 * t];
+        T.dhi = deps[2 * t + 1];
     }
+    return T;
+}
+
+template <class KT, class V, int NT, int IPT>
+__global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, Space<V> vals,
+                                                   int64_t n_total, int depth, int64_t tpn,
+                                                   int64_t ntiles, const int64_t *splits,
+                                                   const int64_t *deps, unsigned *ticket_ctr,
+                                                   unsigned *status, unsigned epoch, unsigned *err)
+{
+    using K = typename KT::T;
+    constexpr bool HV = ValOps<V>::has;
+    using VS = typename std::conditional<HV, V, char>::type;
+    constexpr int TILE = NT * IPT;
+    constexpr int SLOTS = lds_slots<TILE>();
+    __shared__ K sk[SLOTS];
+    __shared__ VS sv[HV ? SLOTS : 1];
+    __shared__ unsigned s_next;
+
+    const int tid = threadIdx.x;
+    if (tid == 0) s_next = atomicAdd(ticket_ctr, 1u);
     __syncthreads();
-    if (tid == 0) st_status(status + t, (epoch << 2) | ST_LOADED);
+    int64_t t = __builtin_amdgcn_readfirstlane(s_next);
+    if (t >= ntiles) return;
 
-    K k[IPT];
-    typename std::conditional<HV, V, char>::type v[IPT];
-    const int d = tid * IPT;
-    int nout = cnt - d;
-    nout = nout < 0 ? 0 : (nout > IPT ? IPT : nout);
-    if (nout > 0) {
-        int ai = merge_path_lds<KT>(d, la, lb, [&](int i) { return sk[i]; },
-                                    [&](int i) { return sk[la + i]; });
-        int bi = d - ai;
+    MergeTile cur = merge_tile_setup<TILE>(t, n_total, depth, tpn, splits, deps);
+    K lk[IPT];
+    VS lv[IPT];
+    // Straight-line loads: indices past the tile are clamped to its last input
+    // (an empty tile reads slot 0), so every load is valid and none needs a
+    // branch; the values loaded for clamped indices are never stored.
+    auto issue_loads = [&](const MergeTile &T) {
+        const int last = T.cnt > 0 ? T.cnt - 1 : 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int i = min(tid + r * NT, last);
+            const int64_t p = i < T.la ? T.pa + i : T.pb + (i - T.la);
+            lk[r] = *keys.at(p);
+            if constexpr (HV) lv[r] = *vals.at(p);
+        }
+    };
+    issue_loads(cur);
+
+    for (;;) {
+        // stage the current tile in LDS and publish that its inputs are read
+        // (slots past the tile receive ignored values)
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            const int i = tid + r * NT;
+            sk[lpad(i)] = lk[r];
+            if constexpr (HV) sv[lpad(i)] = lv[r];
+        }
+        __syncthreads();
+        unsigned nt = 0;
+        if (tid == 0) {
+            st_status(status + cur.t, (epoch << 2) | ST_LOADED);
+            nt = atomicAdd(ticket_ctr, 1u);
+        }
+
+        // merge: thread tid produces outputs [tid*IPT, tid*IPT + nout)
+        K k[IPT];
+        VS v[IPT];
+        int srcix[IPT];
+        const int d = tid * IPT;
+        int nout = cur.cnt - d;
+        nout = nout < 0 ? 0 : (nout > IPT ? IPT : nout);
+        const int la = cur.la, lb = cur.cnt - cur.la;
+        if (nout > 0) {
+            const int ai = merge_path_lds<KT>(d, la, lb, [&](int i) { return sk[lpad(i)]; },
+                                              [&](int i) { return sk[lpad(la + i)]; });
+            serial_merge<KT, IPT, HV>(sk, 0, la, la, lb, ai, d - ai, TILE, k, srcix);
+            if constexpr (HV) {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) v[i] = sv[lpad(min(srcix[i], TILE))];
+            }
+        }
+        if (tid == 0) s_next = nt;
+        __syncthreads();
+
+        // prefetch the next tile while this one waits and stores
+        const int64_t t2 = __builtin_amdgcn_readfirstlane(s_next);
+        const bool more = t2 < ntiles;
+        MergeTile nxt;
+        if (more) {
+            nxt = merge_tile_setup<TILE>(t2, n_total, depth, tpn, splits, deps);
+            issue_loads(nxt);
+        }
+        if (tid < 64) wait_window(status, cur.dlo, cur.dhi, cur.t, epoch, err);
+        __syncthreads();
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             if (i < nout) {
-                bool takeB;
-                if (ai >= la) takeB = true;
-                else if (bi >= lb) takeB = false;
-                else takeB = KT::less(sk[la + bi], sk[ai]);
-                const int idx = takeB ? la + bi : ai;
-                k[i] = sk[idx];
-                if constexpr (HV) v[i] = sv[idx];
-                if (takeB) ++bi; else ++ai;
+                sk[lpad(d + i)] = k[i];
+                if constexpr (HV) sv[lpad(d + i)] = v[i];
             }
         }
-    }
-
-    if (tid < 64) lookback_wait(status, first, t, epoch, err);
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        if (i < nout) {
-            sk[d + i] = k[i];
-            if constexpr (HV) sv[d + i] = v[i];
+        for (int r = 0; r < IPT; ++r) {
+            const int i = tid + r * NT;
+            if (i < cur.cnt) {
+                *keys.at(cur.o + i) = sk[lpad(i)];
+                if constexpr (HV) *vals.at(cur.o + i) = sv[lpad(i)];
+            }
         }
-    }
-    __syncthreads();
-    const int64_t o = m.out0 + k0;
-    for (int i = tid; i < cnt; i += NT) {
-        *keys.at(o + i) = sk[i];
-        if constexpr (HV) *vals.at(o + i) = sv[i];
+        if (!more) break;
+        __syncthreads();                 // LDS reads done before the next staging
+        cur = nxt;
     }
 }
 
@@ -293,10 +480,22 @@ __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, S
 // ---------------------------------------------------------------------------
 template <class KT, class V>
 struct SortCfg;
+#ifndef GS_F64_LEAF_NT
+#define GS_F64_LEAF_NT 512
+#endif
+#ifndef GS_F64_LEAF_IPT
+#define GS_F64_LEAF_IPT 16
+#endif
+#ifndef GS_F64_MERGE_NT
+#define GS_F64_MERGE_NT 256
+#endif
+#ifndef GS_F64_MERGE_IPT
+#define GS_F64_MERGE_IPT 16
+#endif
 template <>
 struct SortCfg<KeyF64, NoVal> {
-    static constexpr int LEAF_NT = 256, LEAF_IPT = 16;
-    static constexpr int MERGE_NT = 256, MERGE_IPT = 16;
+    static constexpr int LEAF_NT = GS_F64_LEAF_NT, LEAF_IPT = GS_F64_LEAF_IPT;
+    static constexpr int MERGE_NT = GS_F64_MERGE_NT, MERGE_IPT = GS_F64_MERGE_IPT;
 };
 template <>
 struct SortCfg<KeyU64, uint32_t> {
@@ -339,9 +538,26 @@ SortPlan make_plan(int64_t n)
     p.off_status = p.off_tickets + align256(p.n_tickets * 4);
     p.n_status = max_tickets;
     p.off_splits = p.off_status + align256(max_tickets * 4);
-    p.bytes = p.off_splits + align256(max_splits * 8);
+    p.off_deps = p.off_splits + align256(max_splits * 8);
+    p.bytes = p.off_deps + align256(max_tickets * 16);
     if (n <= 1) p.bytes = 0;
     return p;
+}
+
+// Resident work-groups of a kernel over the whole device (cached by caller).
+template <class F>
+static int64_t resident_groups(F kernel, int threads, int64_t &cache)
+{
+    if (cache > 0) return cache;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    cache = (int64_t)cus * per_cu;
+    return cache;
 }
 
 template <class KT, class V>
@@ -358,6 +574,10 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
     unsigned *tickets = (unsigned *)(ws + p.off_tickets);
     unsigned *status = (unsigned *)(ws + p.off_status);
     int64_t *splits = (int64_t *)(ws + p.off_splits);
+    int64_t *deps = (int64_t *)(ws + p.off_deps);
+    auto merge_fn = merge_kernel<KT, V, C::MERGE_NT, C::MERGE_IPT>;
+    static int64_t merge_groups = 0;
+    const int64_t resident = resident_groups(merge_fn, C::MERGE_NT, merge_groups);
 
     const bool tr = trace_on();
     // tickets and status words start at zero on every call
@@ -377,14 +597,18 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
         const int64_t nn = (int64_t)1 << d;
         const int64_t tpn = (frog_max_node(n, d) + TILE - 1) / TILE;
         const int64_t nsplit = nn * (tpn + 1);
+        const int64_t ntiles = nn * tpn;
         if (tr) trace_begin(TK_PARTITION, st);
-        hipLaunchKernelGGL((partition_kernel<KT, TILE>), dim3((unsigned)((nsplit + 3) / 4)), dim3(256),
+        hipLaunchKernelGGL((partition_kernel<KT, TILE>), dim3((unsigned)((nsplit + 255) / 256)), dim3(256),
                            0, st, sk, n, d, nn, tpn, splits);
+        hipLaunchKernelGGL((depwin_kernel<TILE>), dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st,
+                           n, d, nn, tpn, (const int64_t *)splits, deps);
         if (tr) trace_end(st);
         if (tr) trace_begin(TK_MERGE, st);
-        hipLaunchKernelGGL((merge_kernel<KT, V, C::MERGE_NT, C::MERGE_IPT>), dim3((unsigned)(nn * tpn)),
-                           dim3(C::MERGE_NT), 0, st, sk, sv, n, d, tpn, (const int64_t *)splits,
-                           tickets + (D - d), status, epoch, tickets + kErrWord);
+        const int64_t grid = ntiles < resident ? ntiles : resident;
+        hipLaunchKernelGGL(merge_fn, dim3((unsigned)grid), dim3(C::MERGE_NT), 0, st, sk, sv, n, d, tpn, ntiles,
+                           (const int64_t *)splits, (const int64_t *)deps, tickets + (D - d), status,
+                           epoch, tickets + kErrWord);
         if (tr) trace_end(st);
     }
     return hipGetLastError();

@@ -142,7 +142,7 @@ def main():
         assert bool((c[1:] >= c[:-1]).all().item()), "bench output not sorted"
     del copies
 
-    names = {0: "fill", 1: "leaf", 2: "partition", 3: "merge", 4: "other"}
+    names = {0: "fill", 1: "leaf", 2: "partition", 3: "merge", 4: "other", 5: "depwin"}
     per_kind = {}
     for i in range(nrec):
         per_kind.setdefault(names.get(kinds[i], "other"), []).append(mss[i])

@@ -136,7 +136,7 @@ const char *gs_version(void);
    the call's stream.  Returns the previous setting. */
 int gs_trace_enable(int on);
 /* Waits for the recorded events, writes up to `max` records (host arrays):
-   kinds[i] (0 fill, 1 leaf sort, 2 partition, 3 merge, 4 other) and ms[i]
+   kinds[i] (0 fill, 1 leaf sort, 2 partition, 3 merge, 4 other, 5 dependency windows) and ms[i]
    (launch duration), clears the record list and returns the count written. */
 int gs_trace_read(int *kinds, double *ms, int max);
 

@@ -229,6 +229,51 @@ gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws,
     return s;
 }
 
+size_t gs_workspace_bytes_seg(int64_t num_keys, int64_t num_segments, double buffer_fraction)
+{
+    if (num_keys < 0 || num_segments < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
+    if (num_segments == 0) return 0;
+    return (size_t)gs::plan_seg(num_keys, num_segments).bytes;
+}
+
+gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets, int64_t num_segments,
+                     double buffer_fraction, void *ws, size_t ws_bytes, void *hip_stream,
+                     gs_report *rep)
+{
+    g_detail.clear();
+    if (num_keys < 0 || num_segments < 0) return fail(GS_EINVAL, "num_keys or num_segments < 0");
+    if (num_segments > ((int64_t)1 << 31) - 2) return fail(GS_EINVAL, "num_segments above 2^31-2");
+    if (num_keys > ((int64_t)1 << 40)) return fail(GS_EINVAL, "num_keys above 2^40");
+    gs_status s = check_fraction(buffer_fraction);
+    if (s != GS_OK) return s;
+    if (num_segments == 0) {
+        if (rep) { memset(rep, 0, sizeof *rep); rep->ram_fraction = 1.0; }
+        return GS_OK;
+    }
+    if (!offsets) return fail(GS_EINVAL, "offsets is NULL");
+    if (num_keys > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
+    gs::SegPlan p = gs::plan_seg(num_keys, num_segments);
+    if ((int64_t)ws_bytes < p.bytes || !ws)
+        return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);
+    if (!aligned256(ws)) return fail(GS_EINVAL, "workspace not 256-byte aligned");
+    if ((s = check_device()) != GS_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Reporter r(rep, st);
+    hipError_t e = gs::segsort_f64_async(keys, offsets, p, (char *)ws, st);
+    if (e != hipSuccess) return r.finish(hip_fail(e, "gs_segsort launch"));
+    s = r.finish(GS_OK);
+    if (rep && s == GS_OK) {
+        rep->workspace_bytes_used = (uint64_t)p.bytes;
+        rep->ram_fraction = num_keys > 0 ? 1.0 + (double)p.bytes / (8.0 * (double)num_keys) : 1.0;
+        unsigned inval = 0;
+        hipError_t e2 = hipMemcpy(&inval, (const char *)ws + p.off_ctrl, 4, hipMemcpyDeviceToHost);
+        if (e2 != hipSuccess) return hip_fail(e2, "reading the offsets flag");
+        rep->invalid_offsets = inval ? 1u : 0u;
+        if (inval) return fail(GS_EINVAL, "offsets not non-decreasing within [0, num_keys]");
+    }
+    return s;
+}
+
 gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fraction, void *ws,
                      size_t ws_bytes, void *hip_stream, gs_report *rep)
 {
@@ -281,26 +326,11 @@ void gs_learned_default_params(gs_learned_params *p)
     p->mode = 0;
 }
 
-size_t gs_workspace_bytes_seg(int64_t num_keys, int64_t num_segments, double buffer_fraction)
-{
-    if (num_keys < 0 || num_segments < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
-    return 0;
-}
-
 size_t gs_workspace_bytes_learned(int64_t n, const gs_learned_params *p)
 {
     (void)p;
     if (n < 0) return SIZE_MAX;
     return 0;
-}
-
-gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets, int64_t num_segments,
-                     double buffer_fraction, void *ws, size_t ws_bytes, void *hip_stream,
-                     gs_report *rep)
-{
-    (void)keys; (void)num_keys; (void)offsets; (void)num_segments; (void)buffer_fraction;
-    (void)ws; (void)ws_bytes; (void)hip_stream; (void)rep;
-    return fail(GS_EUNSUPPORTED, "gs_segsort: not built in this version");
 }
 
 gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p, void *ws,

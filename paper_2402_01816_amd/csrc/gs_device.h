@@ -18,6 +18,14 @@ struct KeyF64 {
     static __device__ __forceinline__ double pad() { return __builtin_nan(""); }
 };
 
+// float64 keys of a block known to hold no NaN: plain IEEE `<` (still ties
+// -0.0 with +0.0).  Used where a block checked its keys first.
+struct KeyF64NoNaN {
+    using T = double;
+    static __device__ __forceinline__ bool less(double a, double b) { return a < b; }
+    static __device__ __forceinline__ double pad() { return __builtin_inf(); }
+};
+
 struct KeyU64 {
     using T = uint64_t;
     static __device__ __forceinline__ bool less(uint64_t a, uint64_t b) { return a < b; }

@@ -26,6 +26,19 @@ struct SortPlan {
     int64_t bytes;        // total workspace
 };
 
+// Workspace layout of one segmented sort.
+struct SegPlan {
+    int64_t num_keys, nseg;
+    int64_t tile;         // keys per LDS tile
+    int64_t off_h;        // half buffer: floor(num_keys/2) doubles
+    int64_t off_ctrl;     // 64 control words
+    int64_t off_cls, off_rank, off_list;   // per-segment class, rank in class, class-ordered list
+    int64_t bytes;
+};
+SegPlan plan_seg(int64_t num_keys, int64_t nseg);
+hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan &p, char *ws,
+                             hipStream_t st);
+
 SortPlan plan_f64(int64_t n);
 SortPlan plan_kv(int64_t n);
 hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st);
@@ -35,7 +48,7 @@ void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st);
 
 // Launch tracing (measurement only).  When enabled on the calling thread,
 // launchers bracket every kernel launch with HIP events on its stream.
-enum TraceKind : int { TK_FILL = 0, TK_LEAF = 1, TK_PARTITION = 2, TK_MERGE = 3, TK_OTHER = 4 };
+enum TraceKind : int { TK_FILL = 0, TK_LEAF = 1, TK_PARTITION = 2, TK_MERGE = 3, TK_OTHER = 4, TK_DEPWIN = 5, TK_SEGSORT = 6 };
 bool trace_on();
 void trace_begin(int kind, hipStream_t st);
 void trace_end(hipStream_t st);

@@ -9,6 +9,7 @@
 
 #include <type_traits>
 
+#include "gs_block.h"
 #include "gs_device.h"
 #include "gs_internal.h"
 
@@ -32,50 +33,6 @@ void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st)
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, count, v);
 }
 
-template <class V>
-struct ValOps {
-    static constexpr bool has = true;
-};
-template <>
-struct ValOps<NoVal> {
-    static constexpr bool has = false;
-};
-
-// LDS index with one pad slot per 16 elements: a thread's IPT consecutive
-// outputs, and merge heads spaced about 8 apart, land in distinct banks.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
-// slots for TILE elements plus one readable slot past the end
-template <int TILE>
-constexpr int lds_slots() { return TILE + TILE / 16 + 2; }
-
-// Serial stable merge of IPT outputs from LDS runs A = [a_base, a_base+na) and
-// B = [b_base, b_base+nb) (logical LDS indices) starting at A index ai and B
-// index bi; on a tie the A element goes first.  Branch free: the heads of both
-// runs stay in registers, every step costs one comparison and one LDS read,
-// and reads past a run's end (clamped to `limit`, a readable slot) are never
-// selected.  Outputs beyond the runs' total are garbage and must be ignored.
-template <class KT, int IPT, bool WANT_SRC>
-__device__ __forceinline__ void serial_merge(const typename KT::T *sk, int a_base, int na, int b_base,
-                                             int nb, int ai, int bi, int limit,
-                                             typename KT::T (&k)[IPT], int (&src)[IPT])
-{
-    using K = typename KT::T;
-    K va = sk[lpad(min(a_base + ai, limit))];
-    K vb = sk[lpad(min(b_base + bi, limit))];
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const bool takeB = (bi < nb) & ((ai >= na) | KT::less(vb, va));
-        k[i] = takeB ? vb : va;
-        if constexpr (WANT_SRC) src[i] = takeB ? b_base + bi : a_base + ai;
-        bi += takeB ? 1 : 0;
-        ai += takeB ? 0 : 1;
-        const int nidx = min(takeB ? b_base + bi : a_base + ai, limit);
-        const K nv = sk[lpad(nidx)];
-        va = takeB ? va : nv;
-        vb = takeB ? nv : vb;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // leaf kernel: sort each leaf's input chunk and place it at its frog slot
 // ---------------------------------------------------------------------------
@@ -92,6 +49,7 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Sp
                                                   unsigned epoch, unsigned *err)
 {
     using K = typename KT::T;
+    using KF = typename FastKey<KT>::type;
     constexpr bool HV = ValOps<V>::has;
     using VS = typename std::conditional<HV, V, char>::type;
     constexpr int TILE = NT * IPT;
@@ -110,90 +68,39 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Sp
     const int64_t src = f.in_off;
     const int64_t dst = frog_data_start(f);
 
-    // load the chunk (input elements all live in the caller's array); all
-    // loads are issued before the first LDS write
+    // load the chunk (input elements all live in the caller's array) with
+    // straight-line loads from clamped indices, all issued before the first
+    // LDS write
+    bool nan_here = false;
     {
         K lk[IPT];
         VS lv[IPT];
-        // straight-line loads from clamped indices; slots past the chunk get
-        // the padding key, which sorts after every real key
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const int i = tid + r * NT;
             const int ic = min(i, len - 1);
-            const K kv = keys.D[src + ic];
-            lk[r] = i < len ? kv : KT::pad();
-            if constexpr (HV) {
-                const V vv = vals.D[src + ic];
-                lv[r] = i < len ? vv : V();
-            }
+            lk[r] = keys.D[src + ic];
+            if constexpr (HV) lv[r] = vals.D[src + ic];
         }
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) nan_here |= is_nan_key(lk[r]);
+        const bool any_nan = __syncthreads_or(nan_here) != 0;
+        // slots past the chunk get a padding key that sorts after every real
+        // key (ties with it stay behind the real keys)
+        const K pad = any_nan ? KT::pad() : KF::pad();
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const int i = tid + r * NT;
-            sk[lpad(i)] = lk[r];
-            if constexpr (HV) sv[lpad(i)] = lv[r];
+            sk[lpad(i)] = i < len ? lk[r] : pad;
+            if constexpr (HV) sv[lpad(i)] = i < len ? lv[r] : VS();
         }
+        nan_here = any_nan;
     }
     __syncthreads();
     if (tid == 0) st_status(status + t, (epoch << 2) | ST_LOADED);
 
-    // per-thread odd-even transposition sort: only adjacent strict inversions
-    // are exchanged, so equal keys keep their order
-    K k[IPT];
-    VS v[IPT];
-    int srcix[IPT];
-    const int base = tid * IPT;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        k[i] = sk[lpad(base + i)];
-        if constexpr (HV) v[i] = sv[lpad(base + i)];
-    }
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-#pragma unroll
-        for (int i = (r & 1); i + 1 < IPT; i += 2) {
-            const bool sw = KT::less(k[i + 1], k[i]);
-            const K lo = sw ? k[i + 1] : k[i];
-            const K hi = sw ? k[i] : k[i + 1];
-            k[i] = lo;
-            k[i + 1] = hi;
-            if constexpr (HV) {
-                const VS vlo = sw ? v[i + 1] : v[i];
-                const VS vhi = sw ? v[i] : v[i + 1];
-                v[i] = vlo;
-                v[i + 1] = vhi;
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        sk[lpad(base + i)] = k[i];
-        if constexpr (HV) sv[lpad(base + i)] = v[i];
-    }
-    __syncthreads();
-
-    // merge rounds in LDS: runs of w -> 2w
-    for (int w = IPT; w < TILE; w *= 2) {
-        const int a0 = (base / (2 * w)) * 2 * w;
-        const int b0 = a0 + w;
-        const int kd = base - a0;
-        const int ai = merge_path_lds<KT>(kd, w, w, [&](int i) { return sk[lpad(a0 + i)]; },
-                                          [&](int i) { return sk[lpad(b0 + i)]; });
-        serial_merge<KT, IPT, HV>(sk, a0, w, b0, w, ai, kd - ai, TILE, k, srcix);
-        if constexpr (HV) {
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) v[i] = sv[lpad(srcix[i])];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            sk[lpad(base + i)] = k[i];
-            if constexpr (HV) sv[lpad(base + i)] = v[i];
-        }
-        __syncthreads();
-    }
+    if (nan_here) block_sort_lds<KT, VS, HV, NT, IPT>(sk, sv);
+    else block_sort_lds<KF, VS, HV, NT, IPT>(sk, sv);
 
     // wait for the leaves whose input chunks the destination covers
     if (tid < 64 && dst < n_total) {
@@ -218,7 +125,9 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Sp
 // partition kernel: merge-path splits at every tile boundary of every node
 // ---------------------------------------------------------------------------
 // One thread per (node, boundary j): binary search for the number of left-run
-// elements among the first j*TILE outputs of the node's stable merge.
+// elements among the first j*TILE outputs of the node's stable merge.  (The
+// searches are bound by the rate of random reads, so one probe per step is
+// the cheapest form.)
 template <class KT, int TILE>
 __global__ __launch_bounds__(256) void partition_kernel(Space<typename KT::T> keys, int64_t n_total,
                                                         int depth, int64_t nnodes, int64_t tpn,
@@ -601,6 +510,8 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
         if (tr) trace_begin(TK_PARTITION, st);
         hipLaunchKernelGGL((partition_kernel<KT, TILE>), dim3((unsigned)((nsplit + 255) / 256)), dim3(256),
                            0, st, sk, n, d, nn, tpn, splits);
+        if (tr) trace_end(st);
+        if (tr) trace_begin(TK_DEPWIN, st);
         hipLaunchKernelGGL((depwin_kernel<TILE>), dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st,
                            n, d, nn, tpn, (const int64_t *)splits, deps);
         if (tr) trace_end(st);

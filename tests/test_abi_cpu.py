@@ -92,3 +92,18 @@ def test_planner_matches_oracle_geometry(orc, n):
         step = max(1, geo.shape[0] // 200)
         for i in range(0, geo.shape[0], step):
             assert tuple(int(v) for v in geo[i]) == g.plan_node(n, d, i)
+
+
+def test_segsort_argument_errors():
+    fake = ctypes.c_void_p(0x100000)
+    need = g.gs_workspace_bytes_seg(1000, 10)
+    assert need >= 8 * 500 and need != g.SIZE_MAX
+    f = g.lib.gs_segsort
+    assert f(fake, 1000, None, 10, 0.5, fake, need, None, None) == g.GS_EINVAL
+    assert f(fake, 1000, fake, -1, 0.5, fake, need, None, None) == g.GS_EINVAL
+    assert f(fake, -5, fake, 10, 0.5, fake, need, None, None) == g.GS_EINVAL
+    assert f(fake, 1000, fake, 10, 0.3, fake, need, None, None) == g.GS_EUNSUPPORTED
+    assert f(fake, 1000, fake, 10, 0.5, fake, need - 1, None, None) == g.GS_EWORKSPACE
+    assert f(None, 0, None, 0, 0.5, None, 0, None, None) == g.GS_OK
+    assert g.gs_workspace_bytes_seg(10, 0) == 0
+    assert g.gs_workspace_bytes_seg(-1, 3) == g.SIZE_MAX

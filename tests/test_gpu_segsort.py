@@ -1,0 +1,173 @@
+"""Parity of gs_segsort (through the C ABI) with the CPU oracle's segmented sort.
+
+Lengths cover every size class of the device path (empty, single, short
+batched blocks, exactly one tile, multi-leaf frog sorts), ragged tails, NaN and
+signed-zero ties.  The full workload (100,000 segments, 2^28 keys, mixed
+patterns) is compared element by element with the oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import announce, bits, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    need_gpu()
+    import paper_2402_01816_amd as g
+    return g
+
+
+def _run(gs, x, off, **kw):
+    t = to_dev(x)
+    o = to_dev(off.astype(np.int64))
+    rep = gs.gs_segsort(t, o, **kw)
+    return t, rep
+
+
+def _check(orc, t, x, off):
+    ref = orc.segsort_f64(x, off)
+    assert np.array_equal(bits(t), bits(ref))
+
+
+@pytest.mark.parametrize("lengths", [
+    [0], [1], [2], [3, 0, 1, 2],
+    [15, 16, 17, 31, 32, 33, 255, 256, 257],
+    [4095, 4096, 4097],
+    [8191, 8192, 8193, 12289],
+    [20000, 1, 0, 5, 40000],
+    [65537],
+])
+@pytest.mark.parametrize("pattern", ["uniform", "zeros_signed", "tied"])
+def test_segsort_lengths(gs, orc, lengths, pattern):
+    announce("segsort", pattern, lengths)
+    n = int(sum(lengths))
+    x = W.f64_pattern(pattern, n, seed=len(lengths) + n)
+    off = np.zeros(len(lengths) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lengths)
+    t, _ = _run(gs, x, off)
+    _check(orc, t, x, off)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_segsort_random_mix(gs, orc, seed):
+    announce("segsort mix", seed)
+    x, off = W.segmented(3000, 1, 30000, seed=seed)
+    x = x.copy()
+    x[::101] = -0.0
+    x[::103] = 0.0
+    t, _ = _run(gs, x, off)
+    _check(orc, t, x, off)
+
+
+def test_segsort_special_values(gs, orc):
+    announce("segsort special")
+    rng = np.random.default_rng(3)
+    pool = np.array([np.nan, np.inf, -np.inf, 0.0, -0.0, 5e-324, 1.0, -1.0])
+    lens = rng.integers(0, 9000, 60)
+    off = np.zeros(lens.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    x = pool[rng.integers(0, pool.size, int(off[-1]))]
+    t, _ = _run(gs, x, off)
+    _check(orc, t, x, off)
+
+
+def test_segsort_leaves_outside_untouched(gs, orc):
+    announce("segsort outside")
+    x = W.f64_pattern("uniform", 30000, seed=4)
+    off = np.array([1000, 1000, 5000, 5001, 22000], dtype=np.int64)
+    t, rep = _run(gs, x, off, report=True)
+    got = t.cpu().numpy()
+    assert np.array_equal(bits(got[:1000]), bits(x[:1000]))
+    assert np.array_equal(bits(got[22000:]), bits(x[22000:]))
+    ref = orc.segsort_f64(x, off)
+    assert np.array_equal(bits(got), bits(ref))
+    assert rep["invalid_offsets"] == 0
+
+
+@pytest.mark.parametrize("bad", [[0, 5, 3, 10], [-1, 4, 10], [0, 4, 10 + 1]])
+def test_segsort_invalid_offsets_reported(gs, bad):
+    announce("segsort invalid", bad)
+    x = W.f64_pattern("uniform", 10, seed=5)
+    t = to_dev(x)
+    o = to_dev(np.array(bad, dtype=np.int64))
+    with pytest.raises(gs.GsError) as e:
+        gs.gs_segsort(t, o, report=True)
+    assert e.value.status == gs.GS_EINVAL
+    assert np.array_equal(bits(t), bits(x))
+
+
+def _weak_orders(n):
+    grid = np.indices((n,) * n).reshape(n, -1).T
+    present = np.zeros((grid.shape[0], n), dtype=bool)
+    np.put_along_axis(present, grid, True, axis=1)
+    return grid[present.sum(axis=1) == grid.max(axis=1) + 1]
+
+
+def test_segsort_exhaustive_weak_orders(gs, orc):
+    """Every weak order of n <= 8 keys (598,445 arrays) as one segmented call;
+    tie class 0 written as mixed-sign zeros so stability is visible."""
+    announce("segsort exhaustive")
+    xs, lens = [], []
+    for n in range(0, 9):
+        a = _weak_orders(n) if n else np.zeros((1, 0), dtype=np.int64)
+        xs.append(a.reshape(-1).astype(np.float64))
+        lens.extend([n] * a.shape[0])
+    x = np.concatenate(xs)
+    sign = (np.arange(x.size) * 2654435761 >> 3) & 1
+    x[(x == 0) & (sign == 1)] = -0.0
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    assert len(lens) == 1 + 1 + 3 + 13 + 75 + 541 + 4683 + 47293 + 545835
+    t, _ = _run(gs, x, off)
+    _check(orc, t, x, off)
+
+
+def test_segsort_graph_capture_replay(gs, orc):
+    """gs_segsort captured once into a HIP graph (torch's graph API) and
+    replayed on fresh inputs copied into the captured buffer; every replay is
+    checked against the oracle, with eager work between replays."""
+    torch = need_gpu()
+    announce("segsort graph")
+    x0, off = W.segmented(2000, 1, 20000, seed=7)
+    n = x0.size
+    keys = to_dev(x0)
+    offs = to_dev(off)
+    need = gs.gs_workspace_bytes_seg(n, off.size - 1)
+    ws_raw = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    o = (-ws_raw.data_ptr()) % 256
+    ws = ws_raw[o:o + need]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):                      # warm-up outside capture
+        gs.gs_segsort(keys, offs, workspace=ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        gs.gs_segsort(keys, offs, workspace=ws, stream=s)
+    for seed in (11, 12, 13):
+        x, off2 = W.segmented(2000, 1, 20000, seed=7)
+        x = x + seed                                # same offsets, new keys
+        keys.copy_(torch.from_numpy(x))
+        _ = (keys * 2).sum()                        # unrelated eager work
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _check(orc, keys, x, off)
+
+
+def test_segsort_full_workload(gs, orc):
+    """100,000 segments, log-uniform lengths in [16, 19023] rescaled to total
+    2^28 keys, patterns uniform/tied/presorted/reversed per segment."""
+    announce("segsort full")
+    x, off = W.segmented(100_000, 16, 19023, seed=0, total=1 << 28)
+    t, rep = _run(gs, x, off, report=True)
+    assert rep["invalid_offsets"] == 0
+    got = t.cpu().numpy()
+    del t
+    ref = orc.segsort_f64(x, off)
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))

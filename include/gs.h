@@ -71,11 +71,11 @@ typedef struct {
 
 /* Parameters of the learned CDF bucket path (not from the paper). */
 typedef struct {
-    uint32_t num_buckets;    /* buckets, power of two in [2, 65536]; default 4096 */
-    uint32_t sample_size;    /* keys sampled for training; default 65536 */
-    uint32_t train_steps;    /* Adam steps; default 200 */
-    uint32_t batch;          /* minibatch per step; default 2048 */
-    uint32_t knots;          /* knots of the tabulated model; default 16384 */
+    uint32_t num_buckets;    /* buckets, power of two in [2, 4096]; default 4096 */
+    uint32_t sample_size;    /* keys sampled for training, in [1024, 2^24]; default 65536 */
+    uint32_t train_steps;    /* Adam steps; default 100 */
+    uint32_t batch;          /* minibatch per step, multiple of 32 in [32, 8192]; default 2048 */
+    uint32_t knots;          /* knots of the tabulated model, in [2, 16384]; default 4096 */
     float    lr;             /* Adam learning rate; default 1e-2 */
     uint64_t seed;           /* sample positions, weight init and minibatches */
     uint32_t mode;           /* 0 = trained network, 1 = untrained linear CDF (table[i] = i/knots) */
@@ -117,9 +117,12 @@ gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets,
 
 /* Stable ascending sort of n float64 keys with the same result as
    gs_sort_f64, using a small FP32 CDF network trained on the device to bucket
-   the keys first.  The bucket order is verified before any key moves; on a
-   violation the plain path sorts the untouched input (report.fallback = 1).
-   `p` is a host pointer (NULL = defaults). */
+   the keys first.  The key-to-bucket map is verified monotone before any key
+   moves; if it is not, or a bucket would exceed 2^20 keys, or the sample has
+   no usable range, the plain path sorts the untouched input
+   (report.fallback = 1).  Inputs shorter than 4 * sample_size run the plain
+   path directly.  Extra memory stays at the half buffer (plus O(buckets *
+   waves) counters).  `p` is a host pointer (NULL = defaults). */
 gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p,
                           void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 
@@ -139,6 +142,23 @@ int gs_trace_enable(int on);
    kinds[i] (0 fill, 1 leaf sort, 2 partition, 3 merge, 4 other, 5 dependency windows) and ms[i]
    (launch duration), clears the record list and returns the count written. */
 int gs_trace_read(int *kinds, double *ms, int max);
+
+/* ---- the CDF network on its own (device pointers; for tests and tools) --- */
+/* Loss (mean squared error) and gradient of the 1-64-64-1 ReLU network
+   (4353 parameters: W1[64] b1[64] W2[64*64] row-major b2[64] w3[64] b3) on a
+   batch (multiple of 32) of inputs u and targets t; the reductions run in a
+   fixed order.  work: (batch/32)*4354 floats. */
+gs_status gs_mlp_loss_grad(const float *params, const float *u, const float *t, int batch,
+                           float *grad, float *loss, void *work, size_t work_bytes, void *hip_stream);
+/* `steps` Adam steps (beta 0.9/0.999, eps 1e-8) in place on params/m/v over
+   `count` samples; full_batch = 1 takes the first `batch` samples every step,
+   else 32 per work-group drawn by a seeded hash.  losses[0], losses[1]: mean
+   loss of the first and last step.  work: (batch/32)*4354 floats + 256 bytes. */
+gs_status gs_mlp_train(float *params, float *adam_m, float *adam_v, const float *u, const float *t,
+                       int64_t count, int steps, int batch, float lr, uint64_t seed, int full_batch,
+                       float *losses, void *work, size_t work_bytes, void *hip_stream);
+/* y[i] = network(u[i]) for i < count. */
+gs_status gs_mlp_forward(const float *params, const float *u, int64_t count, float *y, void *hip_stream);
 
 /* ---- introspection for tests (host only, no device work) ---------------- */
 

@@ -101,6 +101,13 @@ _OPTIONAL = {
     "gs_learned_sort": ([_P, _I64, ctypes.POINTER(GsLearnedParams), _P, _SZ, _P,
                          ctypes.POINTER(GsReport)], ctypes.c_int),
     "gs_learned_default_params": ([ctypes.POINTER(GsLearnedParams)], None),
+    "gs_mlp_loss_grad": ([_P, _P, _P, ctypes.c_int, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "gs_mlp_train": ([_P, _P, _P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                      ctypes.c_uint64, ctypes.c_int, _P, _P, _SZ, _P], ctypes.c_int),
+    "gs_mlp_forward": ([_P, _P, _I64, _P, _P], ctypes.c_int),
+    "gs_trace_enable": ([ctypes.c_int], ctypes.c_int),
+    "gs_trace_read": ([ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), ctypes.c_int],
+                      ctypes.c_int),
 }
 for _name, (_args, _res) in {**_SIGS, **_OPTIONAL}.items():
     if _name in _SIGS or hasattr(_lib, _name):
@@ -288,3 +295,49 @@ def gs_learned_sort(keys, params: GsLearnedParams | None = None, workspace=None,
                               _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_learned_sort")
     return r.as_dict() if r is not None else None
+
+
+# ---------------------------------------------------------------------------
+# the CDF network on its own (float32 device tensors)
+# ---------------------------------------------------------------------------
+def _f32(t, what):
+    torch = _torch()
+    return _dev_ptr(t, what, (torch.float32,))
+
+
+def gs_mlp_loss_grad(params, u, t, stream=None):
+    """(loss tensor [1], grad tensor [4353]) of the network on a batch."""
+    torch = _torch()
+    batch = u.numel()
+    grad = torch.empty(MLP_NUM_PARAMS, dtype=torch.float32, device=params.device)
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    work = torch.empty((batch // 32 + 1) * (MLP_NUM_PARAMS + 1), dtype=torch.float32, device=params.device)
+    st = _lib.gs_mlp_loss_grad(_f32(params, "params"), _f32(u, "u"), _f32(t, "t"), batch,
+                               _f32(grad, "grad"), _f32(loss, "loss"), _f32(work, "work"),
+                               work.numel() * 4, _stream_ptr(stream, params.device))
+    _check(st, "gs_mlp_loss_grad")
+    return loss, grad
+
+
+def gs_mlp_train(params, adam_m, adam_v, u, t, steps, batch, lr, seed=0, full_batch=False,
+                 stream=None):
+    """In-place Adam training; returns a [2] tensor (first, last step loss)."""
+    torch = _torch()
+    losses = torch.zeros(2, dtype=torch.float32, device=params.device)
+    work = torch.empty((batch // 32) * (MLP_NUM_PARAMS + 1) + 64, dtype=torch.float32,
+                       device=params.device)
+    st = _lib.gs_mlp_train(_f32(params, "params"), _f32(adam_m, "m"), _f32(adam_v, "v"),
+                           _f32(u, "u"), _f32(t, "t"), u.numel(), steps, batch, lr, seed,
+                           1 if full_batch else 0, _f32(losses, "losses"), _f32(work, "work"),
+                           work.numel() * 4, _stream_ptr(stream, params.device))
+    _check(st, "gs_mlp_train")
+    return losses
+
+
+def gs_mlp_forward(params, u, stream=None):
+    torch = _torch()
+    y = torch.empty_like(u)
+    st = _lib.gs_mlp_forward(_f32(params, "params"), _f32(u, "u"), u.numel(), _f32(y, "y"),
+                             _stream_ptr(stream, params.device))
+    _check(st, "gs_mlp_forward")
+    return y

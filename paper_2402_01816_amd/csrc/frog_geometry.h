@@ -60,12 +60,19 @@ GS_HD int64_t frog_data_start(const FrogNode &f)
     return f.left ? f.s : f.s + frog_region(f.n) - f.n;
 }
 
-// The merge a node performs: outer/inner runs and where the output goes.
+// The merge a node performs: the two runs and where the output goes.  The
+// first run wins ties (it holds the earlier input).  One run may lie inside
+// the output ("outer"); its elements only move away from the side the output
+// is written from:
+//   outer 0: first run at [out0, out0+nl), output written top-down (left node)
+//   outer 1: second run at [out0+nl, out0+n), written bottom-up (right node)
+//   outer 2: first run at [out0+nr, out0+n), written bottom-up
 struct FrogMerge {
-    int64_t l0, nl;   // left child's data   [l0, l0+nl)
-    int64_t r0, nr;   // right child's data  [r0, r0+nr)
-    int64_t out0;     // output              [out0, out0+nl+nr)
-    int     left;     // node direction: 1 = output written top-down
+    int64_t l0, nl;   // first run  [l0, l0+nl)
+    int64_t r0, nr;   // second run [r0, r0+nr)
+    int64_t out0;     // output     [out0, out0+nl+nr)
+    int     left;     // 1 = output written top-down
+    int     outer;    // which run lies inside the output (see above)
 };
 
 GS_HD FrogMerge frog_merge_of(const FrogNode &f)
@@ -77,6 +84,7 @@ GS_HD FrogMerge frog_merge_of(const FrogNode &f)
     m.r0 = f.s + frog_region(f.n) - m.nr;
     m.out0 = frog_data_start(f);
     m.left = f.left;
+    m.outer = f.left ? 0 : 1;
     return m;
 }
 

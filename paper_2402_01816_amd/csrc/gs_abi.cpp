@@ -13,6 +13,8 @@
 #include "../../include/gs.h"
 #include "frog_geometry.h"
 #include "gs_internal.h"
+#include "gs_learned.h"
+#include "gs_mlp.h"
 
 namespace {
 
@@ -310,7 +312,7 @@ gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fr
 
 }  // extern "C"
 
-// ---- entry points whose device path is not built yet ----------------------
+// ---- learned path -----------------------------------------------------------
 extern "C" {
 
 void gs_learned_default_params(gs_learned_params *p)
@@ -318,26 +320,125 @@ void gs_learned_default_params(gs_learned_params *p)
     memset(p, 0, sizeof *p);
     p->num_buckets = 4096;
     p->sample_size = 65536;
-    p->train_steps = 200;
+    p->train_steps = 100;
     p->batch = 2048;
-    p->knots = 16384;
+    p->knots = 4096;
     p->lr = 1e-2f;
     p->seed = 0x5eed;
     p->mode = 0;
 }
 
-size_t gs_workspace_bytes_learned(int64_t n, const gs_learned_params *p)
+static gs_status check_learned_params(const gs_learned_params &p)
 {
-    (void)p;
-    if (n < 0) return SIZE_MAX;
-    return 0;
+    auto pow2 = [](uint32_t v) { return v >= 2 && (v & (v - 1)) == 0; };
+    if (!pow2(p.num_buckets) || p.num_buckets > 4096)
+        return fail(GS_EINVAL, "num_buckets must be a power of two in [2, 4096]");
+    if (p.sample_size < 1024 || p.sample_size > (1u << 24)) return fail(GS_EINVAL, "sample_size out of [1024, 2^24]");
+    if (p.knots < 2 || p.knots > 16384) return fail(GS_EINVAL, "knots out of [2, 16384]");
+    if (p.batch < 32 || p.batch % 32 || p.batch > 8192) return fail(GS_EINVAL, "batch must be a multiple of 32 in [32, 8192]");
+    if (p.mode > 1) return fail(GS_EINVAL, "mode must be 0 or 1");
+    if (!(p.lr > 0.f) || !(p.lr < 1.f)) return fail(GS_EINVAL, "lr out of (0, 1)");
+    if (p.train_steps > 100000) return fail(GS_EINVAL, "train_steps above 100000");
+    return GS_OK;
 }
 
-gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p, void *ws,
-                          size_t ws_bytes, void *hip_stream, gs_report *rep)
+size_t gs_workspace_bytes_learned(int64_t n, const gs_learned_params *p)
 {
-    (void)keys; (void)n; (void)p; (void)ws; (void)ws_bytes; (void)hip_stream; (void)rep;
-    return fail(GS_EUNSUPPORTED, "gs_learned_sort: not built in this version");
+    gs_learned_params d;
+    gs_learned_default_params(&d);
+    const gs_learned_params &q = p ? *p : d;
+    if (n < 0) return SIZE_MAX;
+    if (n <= 1) return 0;
+    if (check_learned_params(q) != GS_OK) return SIZE_MAX;
+    return (size_t)gs::plan_learned(n, q).bytes;
+}
+
+gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p, void *ws, size_t ws_bytes,
+                          void *hip_stream, gs_report *rep)
+{
+    g_detail.clear();
+    gs_learned_params d;
+    gs_learned_default_params(&d);
+    const gs_learned_params &q = p ? *p : d;
+    if (n < 0) return fail(GS_EINVAL, "n < 0");
+    if (n > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
+    gs_status s = check_learned_params(q);
+    if (s != GS_OK) return s;
+    if (n > ((int64_t)1 << 40)) return fail(GS_EINVAL, "n above 2^40");
+    if (n <= 1) {
+        if (rep) { memset(rep, 0, sizeof *rep); rep->ram_fraction = 1.0; }
+        return GS_OK;
+    }
+    gs::LearnedPlan L = gs::plan_learned(n, q);
+    if ((int64_t)ws_bytes < L.bytes || !ws)
+        return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)L.bytes);
+    if (!aligned256(ws)) return fail(GS_EINVAL, "workspace not 256-byte aligned");
+    if ((s = check_device()) != GS_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Reporter r(rep, st);
+    hipError_t e = gs::learned_sort_async(keys, n, q, (char *)ws, L, st);
+    if (e != hipSuccess) return r.finish(hip_fail(e, "gs_learned_sort launch"));
+    s = r.finish(GS_OK);
+    if (rep && s == GS_OK) {
+        gs::LearnedReport lr{};
+        hipError_t e2 = gs::learned_read_report((const char *)ws, L, &lr);
+        if (e2 != hipSuccess) return hip_fail(e2, "reading the learned report");
+        rep->levels = (uint32_t)L.plain.depth;
+        rep->workspace_bytes_used = (uint64_t)L.bytes;
+        rep->ram_fraction = 1.0 + (double)L.bytes / (8.0 * (double)n);
+        rep->fallback = lr.fallback;
+        rep->overflow_buckets = lr.overflow_buckets;
+        rep->max_bucket = lr.max_bucket;
+        rep->train_loss_first = lr.loss_first;
+        rep->train_loss_last = lr.loss_last;
+        rep->feature = lr.feature;
+        if (lr.err) return fail(GS_EDEVICE, "a bounded device wait gave up during training");
+        s = check_err_word((const char *)ws, L.plain);
+    }
+    return s;
+}
+
+// ---- test hooks for the network (device pointers) ---------------------------
+gs_status gs_mlp_loss_grad(const float *params, const float *u, const float *t, int batch, float *grad,
+                           float *loss, void *work, size_t work_bytes, void *hip_stream)
+{
+    if (!params || !u || !t || !grad || !loss || batch < 32 || batch % 32)
+        return fail(GS_EINVAL, "bad gs_mlp_loss_grad arguments");
+    const size_t need = (size_t)(batch / 32) * (gs::kMlpParams + 1) * 4;
+    if (!work || work_bytes < need) return fail(GS_EWORKSPACE, "gs_mlp_loss_grad needs %zu bytes", need);
+    gs_status s = check_device();
+    if (s != GS_OK) return s;
+    hipError_t e = gs::mlp_loss_grad(params, u, t, batch, (float *)work, grad, loss, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_mlp_loss_grad");
+}
+
+gs_status gs_mlp_train(float *params, float *adam_m, float *adam_v, const float *u, const float *t,
+                       int64_t count, int steps, int batch, float lr, uint64_t seed, int full_batch,
+                       float *losses, void *work, size_t work_bytes, void *hip_stream)
+{
+    if (!params || !adam_m || !adam_v || !u || !t || count < 1 || steps < 0 || batch < 32 || batch % 32 ||
+        batch > 8192 || !(lr > 0.f))
+        return fail(GS_EINVAL, "bad gs_mlp_train arguments");
+    const size_t need = (size_t)(batch / 32) * (gs::kMlpParams + 1) * 4 + 256;
+    if (!work || work_bytes < need) return fail(GS_EWORKSPACE, "gs_mlp_train needs %zu bytes", need);
+    gs_status s = check_device();
+    if (s != GS_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    unsigned *ctl = (unsigned *)((char *)work + (size_t)(batch / 32) * (gs::kMlpParams + 1) * 4);
+    gs::launch_fill_u32(ctl, 64, 0u, st);
+    hipError_t e = gs::mlp_train(params, adam_m, adam_v, u, t, count, steps, batch, lr, seed, full_batch,
+                                 (float *)work, losses, ctl, ctl + 1, nullptr, st);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_mlp_train");
+}
+
+gs_status gs_mlp_forward(const float *params, const float *u, int64_t count, float *y, void *hip_stream)
+{
+    if (!params || !u || !y || count < 0) return fail(GS_EINVAL, "bad gs_mlp_forward arguments");
+    if (count == 0) return GS_OK;
+    gs_status s = check_device();
+    if (s != GS_OK) return s;
+    hipError_t e = gs::mlp_forward(params, u, count, y, 0, nullptr, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_mlp_forward");
 }
 
 }  // extern "C"

@@ -47,6 +47,30 @@ struct Space {
 };
 
 // ---------------------------------------------------------------------------
+// device-side gate: a launch whose gate word differs from `run_if` exits at
+// once, so a call can enqueue alternative paths and let a device flag decide
+// ---------------------------------------------------------------------------
+struct Gate {
+    const unsigned *p;
+    unsigned run_if;
+    __device__ __forceinline__ bool closed() const { return p != nullptr && *p != run_if; }
+};
+
+// ---------------------------------------------------------------------------
+// merges of one launch: every node of one frog-tree level, or one explicit node
+// ---------------------------------------------------------------------------
+struct MergeGeo {
+    int64_t n_total;
+    int depth;
+    int single;       // 1: the launch merges exactly the node m1
+    FrogMerge m1;
+    __device__ __forceinline__ FrogMerge node(int64_t idx) const
+    {
+        return single ? m1 : frog_merge_of(frog_node(n_total, depth, idx));
+    }
+};
+
+// ---------------------------------------------------------------------------
 // ordered-store protocol
 // ---------------------------------------------------------------------------
 // A frog merge writes into slots that still hold unread elements of its outer

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "frog_geometry.h"
+
 namespace gs {
 
 // Index (in the ticket-counter block) of the word the kernels set when a
@@ -38,17 +40,29 @@ struct SegPlan {
 SegPlan plan_seg(int64_t num_keys, int64_t nseg);
 hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan &p, char *ws,
                              hipStream_t st);
+// The same with every buffer given: hbuf holds floor((offsets[nseg]-offsets[0])/2)
+// doubles, ctrl 64 words, cls/rank/list nseg ints each.
+hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys,
+                              double *hbuf, unsigned *ctrl, int *cls, int *rank, int *list,
+                              const unsigned *gate, unsigned run_if, hipStream_t st);
 
 SortPlan plan_f64(int64_t n);
 SortPlan plan_kv(int64_t n);
-hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st);
+// gate (may be null): every launch exits at once unless *gate == run_if.
+hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st,
+                          const unsigned *gate = nullptr, unsigned run_if = 0u);
 hipError_t sort_kv_async(uint64_t *keys, uint32_t *vals, int64_t n, char *ws, const SortPlan &p,
                          hipStream_t st);
 void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st);
+// One explicit merge node over the logical space {D, H, n_space}, using the
+// control area of a plain plan at least as large as the node.
+hipError_t merge_one_f64_async(double *D, double *H, int64_t n_space, const FrogMerge &m, char *ws,
+                               const SortPlan &p, hipStream_t st, const unsigned *gate, unsigned run_if);
 
 // Launch tracing (measurement only).  When enabled on the calling thread,
 // launchers bracket every kernel launch with HIP events on its stream.
-enum TraceKind : int { TK_FILL = 0, TK_LEAF = 1, TK_PARTITION = 2, TK_MERGE = 3, TK_OTHER = 4, TK_DEPWIN = 5, TK_SEGSORT = 6 };
+enum TraceKind : int { TK_FILL = 0, TK_LEAF = 1, TK_PARTITION = 2, TK_MERGE = 3, TK_OTHER = 4, TK_DEPWIN = 5, TK_SEGSORT = 6,
+                       TK_LEARN_PREP = 7, TK_LEARN_TRAIN = 8, TK_LEARN_BUCKET = 9 };
 bool trace_on();
 void trace_begin(int kind, hipStream_t st);
 void trace_end(hipStream_t st);

@@ -1,0 +1,358 @@
+// Device training and evaluation of the 1-64-64-1 ReLU CDF network used by
+// the learned bucket path (not part of the paper).
+//
+// Parameters (4353 floats, one device vector):
+//   W1[64] b1[64] W2[64*64] (row-major: W2[i*64+j] feeds hidden-1 unit j into
+//   hidden-2 unit i) b2[64] w3[64] b3
+//   y(u) = w3 . relu(W2 relu(W1 u + b1) + b2) + b3,   loss = mean (y - t)^2
+//
+// Training is data parallel over work-groups of one cooperative launch: every
+// work-group takes 32 samples per step, computes its partial gradient in LDS
+// with every sum in a fixed order, writes it out; after a grid barrier every
+// work-group sums a slice of the parameters over all partials in work-group
+// order and applies Adam (Kingma & Ba) to it; a second barrier publishes the
+// new parameters.  No floating-point atomics anywhere, so a run is bit
+// reproducible.
+#include <hip/hip_runtime.h>
+
+#include "gs_device.h"
+#include "gs_internal.h"
+#include "gs_mlp.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int HID = 64;
+constexpr int OW1 = 0, OB1 = 64, OW2 = 128, OB2 = 128 + 64 * 64, OW3 = OB2 + 64, OB3 = OW3 + 64;
+static_assert(OB3 + 1 == kMlpParams, "parameter layout");
+constexpr int TR_NT = 256;
+constexpr int SPW = 32;                 // samples per work-group per step
+constexpr int RS = HID + 1;             // padded LDS row stride (no bank conflicts)
+
+struct TrainLds {
+    float p[kMlpParams + 3];
+    float g[kMlpParams + 3];
+    float u[SPW], t[SPW], dy[SPW], y[SPW];
+    float z1[SPW * RS], h1[SPW * RS];
+    float z2[SPW * RS], h2[SPW * RS];
+    float g2[SPW * RS], g1[SPW * RS];
+    float loss;
+};
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Partial loss (sum of squared errors) and gradient (sums over this group's
+// `ns` samples, in sample order) into L.g / L.loss.  inv_batch = 1 / total
+// batch over all work-groups.
+__device__ void wg_loss_grad(TrainLds &L, int ns, float inv_batch)
+{
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < ns * HID; idx += TR_NT) {
+        const int s = idx / HID, j = idx % HID;
+        const float z = fmaf(L.p[OW1 + j], L.u[s], L.p[OB1 + j]);
+        L.z1[s * RS + j] = z;
+        L.h1[s * RS + j] = z > 0.f ? z : 0.f;
+    }
+    __syncthreads();
+    // hidden layer 2: lanes share the W2 row (broadcast) and read distinct h1 rows
+    for (int idx = tid; idx < ns * HID; idx += TR_NT) {
+        const int i = idx / ns, s = idx % ns;
+        float a = L.p[OB2 + i];
+        for (int j = 0; j < HID; ++j) a = fmaf(L.p[OW2 + i * HID + j], L.h1[s * RS + j], a);
+        L.z2[s * RS + i] = a;
+        L.h2[s * RS + i] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    if (tid < ns) {
+        const int s = tid;
+        float y = L.p[OB3];
+        for (int i = 0; i < HID; ++i) y = fmaf(L.p[OW3 + i], L.h2[s * RS + i], y);
+        const float r = y - L.t[s];
+        L.y[s] = r * r;
+        L.dy[s] = 2.f * r * inv_batch;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float acc = 0.f;
+        for (int s = 0; s < ns; ++s) acc += L.y[s];
+        L.loss = acc;
+    }
+    for (int idx = tid; idx < ns * HID; idx += TR_NT) {
+        const int s = idx / HID, i = idx % HID;
+        L.g2[s * RS + i] = L.z2[s * RS + i] > 0.f ? L.dy[s] * L.p[OW3 + i] : 0.f;
+    }
+    __syncthreads();
+    // dW2[i][j] = sum_s g2[s][i] h1[s][j]
+    for (int idx = tid; idx < HID * HID; idx += TR_NT) {
+        const int i = idx / HID, j = idx % HID;
+        float a = 0.f;
+        for (int s = 0; s < ns; ++s) a = fmaf(L.g2[s * RS + i], L.h1[s * RS + j], a);
+        L.g[OW2 + idx] = a;
+    }
+    // g1[s][j] = [z1 > 0] sum_i W2[i][j] g2[s][i]
+    for (int idx = tid; idx < ns * HID; idx += TR_NT) {
+        const int s = idx / HID, j = idx % HID;
+        float a = 0.f;
+        for (int i = 0; i < HID; ++i) a = fmaf(L.p[OW2 + i * HID + j], L.g2[s * RS + i], a);
+        L.g1[s * RS + j] = L.z1[s * RS + j] > 0.f ? a : 0.f;
+    }
+    if (tid < HID) {
+        const int i = tid;
+        float db2 = 0.f, dw3 = 0.f;
+        for (int s = 0; s < ns; ++s) {
+            db2 += L.g2[s * RS + i];
+            dw3 = fmaf(L.dy[s], L.h2[s * RS + i], dw3);
+        }
+        L.g[OB2 + i] = db2;
+        L.g[OW3 + i] = dw3;
+    }
+    if (tid == HID) {
+        float db3 = 0.f;
+        for (int s = 0; s < ns; ++s) db3 += L.dy[s];
+        L.g[OB3] = db3;
+    }
+    __syncthreads();
+    if (tid < HID) {
+        const int j = tid;
+        float dw1 = 0.f, db1 = 0.f;
+        for (int s = 0; s < ns; ++s) {
+            dw1 = fmaf(L.g1[s * RS + j], L.u[s], dw1);
+            db1 += L.g1[s * RS + j];
+        }
+        L.g[OW1 + j] = dw1;
+        L.g[OB1 + j] = db1;
+    }
+    __syncthreads();
+}
+
+// Grid barrier for a cooperative launch: agent-scope fences on both sides so
+// the partial gradients and parameters written before it are visible after
+// it on every XCD.  Bounded: a barrier that does not complete sets *err.
+__device__ void grid_barrier(unsigned *bar, unsigned nwg, unsigned &gen, unsigned *err)
+{
+    __threadfence();                    // every thread releases its own writes
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ++gen;
+        atomicAdd(bar, 1u);
+        const unsigned target = gen * nwg;
+        unsigned spins = 0;
+        while (ld_status(bar) < target && spins < kSpinLimit) {
+            __builtin_amdgcn_s_sleep(2);
+            ++spins;
+        }
+        if (spins >= kSpinLimit) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    __threadfence();                    // and acquires everyone else's
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// initialisation: He-normal hidden weights (N(0, 2/fan_in)) from the seed;
+// the first layer's biases put unit j's ReLU kink at u = (j + 0.5) / 64,
+// spreading the kinks over the input range [0, 1] instead of stacking them all
+// at 0 (a 1-D input otherwise gives a network that starts out linear on
+// (0, 1]); the output layer starts at zero, so an untrained network predicts
+// exactly 0 (the learned path fits a correction to the linear CDF)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float he_normal(uint64_t seed, int p, float sd)
+{
+    const uint64_t a = mix64(seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(2 * p + 1)));
+    const uint64_t b = mix64(a ^ 0xD1B54A32D192ED03ull);
+    const double u1 = ((double)(a >> 11) + 1.0) * (1.0 / 9007199254740992.0);   // (0, 1]
+    const double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);
+    return (float)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2)) * sd;
+}
+
+__global__ void mlp_init_kernel(float *params, uint64_t seed)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlpParams) return;
+    float v = 0.f;
+    if (p < OB1) v = he_normal(seed, p, sqrtf(2.f));                        // W1, fan_in 1
+    else if (p < OW2) {
+        const int j = p - OB1;
+        v = -he_normal(seed, OW1 + j, sqrtf(2.f)) * ((float)j + 0.5f) / (float)HID;
+    } else if (p < OB2) v = he_normal(seed, p, sqrtf(2.f / HID));
+    params[p] = v;
+}
+
+// ---------------------------------------------------------------------------
+// cooperative training kernel
+// ---------------------------------------------------------------------------
+// Grid: nwg work-groups of TR_NT threads; batch = nwg * 32.  If full_batch,
+// step samples are the first `batch` samples in order, else 32 per group are
+// drawn (with replacement) by a counter-based hash of (seed, step, slot).
+__global__ __launch_bounds__(TR_NT) void mlp_train_kernel(float *params, float *adam_m, float *adam_v,
+                                                          const float *su, const float *st, int64_t S,
+                                                          int steps, float lr, uint64_t seed,
+                                                          int full_batch, float *partial,
+                                                          float *losses, unsigned *bar, unsigned *err,
+                                                          const unsigned *gate)
+{
+    __shared__ TrainLds L;
+    if (gate && *gate) return;
+    const unsigned nwg = gridDim.x;
+    const int wg = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int batch = (int)nwg * SPW;
+    const float inv_batch = 1.f / (float)batch;
+    const int per = (kMlpParams + (int)nwg - 1) / (int)nwg;
+    const int p0 = wg * per, p1 = min(p0 + per, kMlpParams);
+    unsigned gen = 0;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+
+    for (int step = 0; step < steps; ++step) {
+        for (int k = tid; k < kMlpParams; k += TR_NT) L.p[k] = params[k];
+        if (tid < SPW) {
+            const int slot = wg * SPW + tid;
+            int64_t idx;
+            if (full_batch) idx = slot < S ? slot : S - 1;
+            else idx = (int64_t)(mix64(seed ^ ((uint64_t)(step + 1) << 32) ^ (uint64_t)slot) % (uint64_t)S);
+            L.u[tid] = su[idx];
+            L.t[tid] = st[idx];
+        }
+        __syncthreads();
+        wg_loss_grad(L, SPW, inv_batch);
+        float *pw = partial + (size_t)wg * (kMlpParams + 1);
+        for (int k = tid; k < kMlpParams; k += TR_NT) pw[k] = L.g[k];
+        if (tid == 0) pw[kMlpParams] = L.loss;
+        grid_barrier(bar, nwg, gen, err);
+
+        // reduce this group's parameter slice over all groups, in group order
+        const float c1 = 1.f - powf(b1, (float)(step + 1));
+        const float c2 = 1.f - powf(b2, (float)(step + 1));
+        for (int k = p0 + tid; k < p1; k += TR_NT) {
+            float g = 0.f;
+            for (unsigned w = 0; w < nwg; ++w) g += partial[(size_t)w * (kMlpParams + 1) + k];
+            const float m = b1 * adam_m[k] + (1.f - b1) * g;
+            const float v = b2 * adam_v[k] + (1.f - b2) * g * g;
+            adam_m[k] = m;
+            adam_v[k] = v;
+            params[k] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+        }
+        if (wg == 0 && tid == 0 && losses && (step == 0 || step == steps - 1)) {
+            float l = 0.f;
+            for (unsigned w = 0; w < nwg; ++w) l += partial[(size_t)w * (kMlpParams + 1) + kMlpParams];
+            losses[step == 0 ? 0 : 1] = l * inv_batch;
+            if (steps == 1) losses[1] = losses[0];
+        }
+        grid_barrier(bar, nwg, gen, err);
+    }
+}
+
+// Loss and gradient of one batch (test hook and building block): same code as
+// training; nwg = batch / 32 groups, then an ordered reduction.
+__global__ __launch_bounds__(TR_NT) void mlp_grad_partial_kernel(const float *params, const float *u,
+                                                                 const float *t, int batch,
+                                                                 float *partial)
+{
+    __shared__ TrainLds L;
+    const int wg = blockIdx.x, tid = threadIdx.x;
+    for (int k = tid; k < kMlpParams; k += TR_NT) L.p[k] = params[k];
+    if (tid < SPW) {
+        L.u[tid] = u[wg * SPW + tid];
+        L.t[tid] = t[wg * SPW + tid];
+    }
+    __syncthreads();
+    wg_loss_grad(L, SPW, 1.f / (float)batch);
+    float *pw = partial + (size_t)wg * (kMlpParams + 1);
+    for (int k = tid; k < kMlpParams; k += TR_NT) pw[k] = L.g[k];
+    if (tid == 0) pw[kMlpParams] = L.loss;
+}
+
+__global__ void mlp_grad_reduce_kernel(const float *partial, int nwg, int batch, float *grad, float *loss)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > kMlpParams) return;
+    float g = 0.f;
+    for (int w = 0; w < nwg; ++w) g += partial[(size_t)w * (kMlpParams + 1) + k];
+    if (k < kMlpParams) grad[k] = g;
+    else *loss = g / (float)batch;
+}
+
+// ---------------------------------------------------------------------------
+// network evaluation (knot table and test hook)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float mlp_eval(const float *p, float u)
+{
+    float h1[HID];
+#pragma unroll
+    for (int j = 0; j < HID; ++j) {
+        const float z = fmaf(p[OW1 + j], u, p[OB1 + j]);
+        h1[j] = z > 0.f ? z : 0.f;
+    }
+    float y = p[OB3];
+    for (int i = 0; i < HID; ++i) {
+        float a = p[OB2 + i];
+#pragma unroll
+        for (int j = 0; j < HID; ++j) a = fmaf(p[OW2 + i * HID + j], h1[j], a);
+        y = fmaf(p[OW3 + i], a > 0.f ? a : 0.f, y);
+    }
+    return y;
+}
+
+__global__ __launch_bounds__(256) void mlp_forward_kernel(const float *params, const float *u, int64_t count,
+                                                          float *y, int64_t knots, const unsigned *gate)
+{
+    __shared__ float p[kMlpParams];
+    if (gate && *gate) return;
+    for (int k = threadIdx.x; k < kMlpParams; k += blockDim.x) p[k] = params[k];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    // knots > 0: evaluate at u = i / knots; else at the given inputs
+    const float x = knots > 0 ? (float)((double)i / (double)knots) : u[i];
+    y[i] = mlp_eval(p, x);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t mlp_init(float *params, uint64_t seed, hipStream_t st)
+{
+    hipLaunchKernelGGL(mlp_init_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, params, seed);
+    return hipGetLastError();
+}
+
+hipError_t mlp_train(float *params, float *m, float *v, const float *su, const float *stgt, int64_t S,
+                     int steps, int batch, float lr, uint64_t seed, int full_batch, float *partial,
+                     float *losses, unsigned *bar, unsigned *err, const unsigned *gate, hipStream_t st)
+{
+    const int nwg = batch / SPW;
+    void *args[] = {&params, &m, &v, (void *)&su, (void *)&stgt, &S, &steps, &lr, &seed,
+                    &full_batch, &partial, &losses, &bar, &err, (void *)&gate};
+    return hipLaunchCooperativeKernel((const void *)mlp_train_kernel, dim3(nwg), dim3(TR_NT), args, 0, st);
+}
+
+hipError_t mlp_loss_grad(const float *params, const float *u, const float *t, int batch, float *partial,
+                         float *grad, float *loss, hipStream_t st)
+{
+    const int nwg = batch / SPW;
+    hipLaunchKernelGGL(mlp_grad_partial_kernel, dim3(nwg), dim3(TR_NT), 0, st, params, u, t, batch, partial);
+    hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, st,
+                       (const float *)partial, nwg, batch, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward(const float *params, const float *u, int64_t count, float *y, int64_t knots,
+                       const unsigned *gate, hipStream_t st)
+{
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, params, u,
+                       count, y, knots, gate);
+    return hipGetLastError();
+}
+
+int mlp_samples_per_group() { return SPW; }
+
+}  // namespace gs

@@ -52,8 +52,9 @@ __device__ __forceinline__ int seg_class(int64_t len)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t *offsets, int64_t nseg,
                                                            int64_t num_keys, unsigned *ctrl,
-                                                           int *cls, int *rank)
+                                                           int *cls, int *rank, Gate gate)
 {
+    if (gate.closed()) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nseg) return;
     const int64_t lo = offsets[s], hi = offsets[s + 1];
@@ -84,8 +85,9 @@ __device__ __forceinline__ int64_t class_base(const unsigned *ctrl, int c)
 
 __global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t nseg, const unsigned *ctrl,
                                                           const int *cls, const int *rank,
-                                                          int *list)
+                                                          int *list, Gate gate)
 {
+    if (gate.closed()) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nseg || ctrl[C_INVALID]) return;
     const int c = cls[s];
@@ -284,7 +286,7 @@ __device__ void wg_frog_sort(typename KT::T *sk, const Space<typename KT::T> &sp
 template <class KT>
 __global__ __launch_bounds__(SEG_NT) void seg_sort_kernel(typename KT::T *keys, const int64_t *offsets,
                                                           typename KT::T *hbuf, unsigned *ctrl,
-                                                          const int *list)
+                                                          const int *list, Gate gate)
 {
     using K = typename KT::T;
     __shared__ K sk[SEG_SLOTS];
@@ -293,7 +295,7 @@ __global__ __launch_bounds__(SEG_NT) void seg_sort_kernel(typename KT::T *keys, 
     __shared__ int64_t s_off[SEG_NT];
     __shared__ int s_len[SEG_NT];
     __shared__ int64_t s_base[10], s_end[10];     // per work-list position
-    if (ctrl[C_INVALID]) return;
+    if (gate.closed() || ctrl[C_INVALID]) return;
 
     // list start and cumulative work items of every class (work-list order)
     if (threadIdx.x == 0) {
@@ -393,22 +395,20 @@ SegPlan plan_seg(int64_t num_keys, int64_t nseg)
     return p;
 }
 
-hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan &p, char *ws,
-                             hipStream_t st)
+hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys,
+                              double *hbuf, unsigned *ctrl, int *cls, int *rank, int *list,
+                              const unsigned *gate, unsigned run_if, hipStream_t st)
 {
-    if (p.nseg <= 0) return hipSuccess;
-    unsigned *ctrl = (unsigned *)(ws + p.off_ctrl);
-    int *cls = (int *)(ws + p.off_cls);
-    int *rank = (int *)(ws + p.off_rank);
-    int *list = (int *)(ws + p.off_list);
+    if (nseg <= 0) return hipSuccess;
+    const Gate g{gate, run_if};
     const bool tr = trace_on();
     if (tr) trace_begin(TK_OTHER, st);
     launch_fill_u32(ctrl, 64, 0u, st);
-    const unsigned g = (unsigned)((p.nseg + 255) / 256);
-    hipLaunchKernelGGL(seg_classify_kernel, dim3(g), dim3(256), 0, st, offsets, p.nseg, p.num_keys, ctrl,
-                       cls, rank);
-    hipLaunchKernelGGL(seg_scatter_kernel, dim3(g), dim3(256), 0, st, p.nseg, (const unsigned *)ctrl,
-                       (const int *)cls, (const int *)rank, list);
+    const unsigned grid = (unsigned)((nseg + 255) / 256);
+    hipLaunchKernelGGL(seg_classify_kernel, dim3(grid), dim3(256), 0, st, offsets, nseg, num_keys, ctrl, cls,
+                       rank, g);
+    hipLaunchKernelGGL(seg_scatter_kernel, dim3(grid), dim3(256), 0, st, nseg, (const unsigned *)ctrl,
+                       (const int *)cls, (const int *)rank, list, g);
     if (tr) trace_end(st);
     static int64_t groups = 0;
     if (groups <= 0) {
@@ -422,10 +422,18 @@ hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan
         groups = (int64_t)cus * per_cu;
     }
     if (tr) trace_begin(TK_SEGSORT, st);
-    hipLaunchKernelGGL(seg_sort_kernel<KeyF64>, dim3((unsigned)groups), dim3(SEG_NT), 0, st, keys, offsets,
-                       (double *)(ws + p.off_h), ctrl, (const int *)list);
+    hipLaunchKernelGGL(seg_sort_kernel<KeyF64>, dim3((unsigned)groups), dim3(SEG_NT), 0, st, keys, offsets, hbuf,
+                       ctrl, (const int *)list, g);
     if (tr) trace_end(st);
     return hipGetLastError();
+}
+
+hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan &p, char *ws,
+                             hipStream_t st)
+{
+    return segsort_core_async(keys, offsets, p.nseg, p.num_keys, (double *)(ws + p.off_h),
+                              (unsigned *)(ws + p.off_ctrl), (int *)(ws + p.off_cls), (int *)(ws + p.off_rank),
+                              (int *)(ws + p.off_list), nullptr, 0u, st);
 }
 
 }  // namespace gs

@@ -46,7 +46,7 @@ template <class KT, class V, int NT, int IPT>
 __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Space<V> vals,
                                                   int64_t n_total, int depth, int64_t nleaves,
                                                   unsigned *ticket_ctr, unsigned *status,
-                                                  unsigned epoch, unsigned *err)
+                                                  unsigned epoch, unsigned *err, Gate gate)
 {
     using K = typename KT::T;
     using KF = typename FastKey<KT>::type;
@@ -57,6 +57,7 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Sp
     __shared__ K sk[SLOTS];
     __shared__ VS sv[HV ? SLOTS : 1];
     __shared__ unsigned s_ticket;
+    if (gate.closed()) return;
 
     const int tid = threadIdx.x;
     if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
@@ -129,18 +130,19 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Sp
 // searches are bound by the rate of random reads, so one probe per step is
 // the cheapest form.)
 template <class KT, int TILE>
-__global__ __launch_bounds__(256) void partition_kernel(Space<typename KT::T> keys, int64_t n_total,
-                                                        int depth, int64_t nnodes, int64_t tpn,
-                                                        int64_t *splits)
+__global__ __launch_bounds__(256) void partition_kernel(Space<typename KT::T> keys, MergeGeo geo,
+                                                        int64_t nnodes, int64_t tpn, int64_t *splits,
+                                                        Gate gate)
 {
+    if (gate.closed()) return;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nnodes * (tpn + 1)) return;
     const int64_t node = w / (tpn + 1);
     const int64_t j = w - node * (tpn + 1);
-    const FrogNode f = frog_node(n_total, depth, node);
-    const FrogMerge m = frog_merge_of(f);
+    const FrogMerge m = geo.node(node);
+    const int64_t nn = m.nl + m.nr;
     int64_t kk = j * TILE;
-    if (kk > f.n) kk = f.n;
+    if (kk > nn) kk = nn;
     int64_t lo = kk > m.nr ? kk - m.nr : 0;
     int64_t hi = kk < m.nl ? kk : m.nl;
     while (lo < hi) {
@@ -185,26 +187,26 @@ __device__ __forceinline__ int64_t upper_bound_bsplits(const int64_t *sp, int64_
 }
 
 template <int TILE>
-__global__ __launch_bounds__(256) void depwin_kernel(int64_t n_total, int depth, int64_t nnodes,
-                                                     int64_t tpn, const int64_t *splits,
-                                                     int64_t *deps)
+__global__ __launch_bounds__(256) void depwin_kernel(MergeGeo geo, int64_t nnodes, int64_t tpn,
+                                                     const int64_t *splits, int64_t *deps, Gate gate)
 {
+    if (gate.closed()) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nnodes * tpn) return;
     const int64_t node = t / tpn;
     const int64_t q = t - node * tpn;
     const int64_t first = node * tpn;
-    const FrogNode f = frog_node(n_total, depth, node);
-    const FrogMerge m = frog_merge_of(f);
+    const FrogMerge m = geo.node(node);
+    const int64_t nn = m.nl + m.nr;
     const int64_t j = m.left ? (tpn - 1 - q) : q;
     int64_t k0 = j * TILE;
-    if (k0 > f.n) k0 = f.n;
+    if (k0 > nn) k0 = nn;
     int64_t k1 = k0 + TILE;
-    if (k1 > f.n) k1 = f.n;
+    if (k1 > nn) k1 = nn;
     const int64_t *sp = splits + node * (tpn + 1);
     int64_t lo = 1, hi = 0;              // empty window
     if (k0 < k1) {
-        if (m.left) {
+        if (m.outer == 0) {              // first run at [out0, out0+nl), top-down
             if (k0 < m.nl) {
                 const int64_t e = (k1 < m.nl ? k1 : m.nl) - 1;
                 const int64_t j0 = upper_bound_splits(sp, tpn + 1, k0) - 1;
@@ -212,13 +214,24 @@ __global__ __launch_bounds__(256) void depwin_kernel(int64_t n_total, int depth,
                 lo = first + (tpn - 1 - j1);
                 hi = first + (tpn - 1 - j0);
             }
-        } else if (k1 > m.nl) {
-            const int64_t b0 = k0 > m.nl ? k0 - m.nl : 0;
-            const int64_t b1 = (k1 - m.nl < m.nr ? k1 - m.nl : m.nr) - 1;
-            const int64_t j0 = upper_bound_bsplits<TILE>(sp, tpn + 1, f.n, b0) - 1;
-            const int64_t j1 = upper_bound_bsplits<TILE>(sp, tpn + 1, f.n, b1) - 1;
-            lo = first + j0;
-            hi = first + j1;
+        } else if (m.outer == 1) {       // second run at [out0+nl, out0+n), bottom-up
+            if (k1 > m.nl) {
+                const int64_t b0 = k0 > m.nl ? k0 - m.nl : 0;
+                const int64_t b1 = (k1 - m.nl < m.nr ? k1 - m.nl : m.nr) - 1;
+                const int64_t j0 = upper_bound_bsplits<TILE>(sp, tpn + 1, nn, b0) - 1;
+                const int64_t j1 = upper_bound_bsplits<TILE>(sp, tpn + 1, nn, b1) - 1;
+                lo = first + j0;
+                hi = first + j1;
+            }
+        } else {                         // first run at [out0+nr, out0+n), bottom-up
+            if (k1 > m.nr) {
+                const int64_t a0 = k0 > m.nr ? k0 - m.nr : 0;
+                const int64_t a1 = (k1 - m.nr < m.nl ? k1 - m.nr : m.nl) - 1;
+                const int64_t j0 = upper_bound_splits(sp, tpn + 1, a0) - 1;
+                const int64_t j1 = upper_bound_splits(sp, tpn + 1, a1) - 1;
+                lo = first + j0;
+                hi = first + j1;
+            }
         }
     }
     deps[2 * t] = lo;
@@ -243,21 +256,20 @@ struct MergeTile {
 };
 
 template <int TILE>
-__device__ __forceinline__ MergeTile merge_tile_setup(int64_t t, int64_t n_total, int depth,
-                                                      int64_t tpn, const int64_t *splits,
-                                                      const int64_t *deps)
+__device__ __forceinline__ MergeTile merge_tile_setup(int64_t t, const MergeGeo &geo, int64_t tpn,
+                                                      const int64_t *splits, const int64_t *deps)
 {
     MergeTile T;
     T.t = t;
     const int64_t node = (int64_t)((uint64_t)t / (uint64_t)tpn);
     const int64_t q = t - node * tpn;
-    const FrogNode f = frog_node(n_total, depth, node);
-    const FrogMerge m = frog_merge_of(f);
+    const FrogMerge m = geo.node(node);
+    const int64_t nn = m.nl + m.nr;
     const int64_t j = m.left ? (tpn - 1 - q) : q;
     int64_t k0 = j * TILE;
-    if (k0 > f.n) k0 = f.n;
+    if (k0 > nn) k0 = nn;
     int64_t k1 = k0 + TILE;
-    if (k1 > f.n) k1 = f.n;
+    if (k1 > nn) k1 = nn;
     T.cnt = (int)(k1 - k0);
     T.la = 0;
     T.pa = T.pb = T.o = 0;
@@ -278,10 +290,10 @@ __device__ __forceinline__ MergeTile merge_tile_setup(int64_t t, int64_t n_total
 
 template <class KT, class V, int NT, int IPT>
 __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, Space<V> vals,
-                                                   int64_t n_total, int depth, int64_t tpn,
-                                                   int64_t ntiles, const int64_t *splits,
-                                                   const int64_t *deps, unsigned *ticket_ctr,
-                                                   unsigned *status, unsigned epoch, unsigned *err)
+                                                   MergeGeo geo, int64_t tpn, int64_t ntiles,
+                                                   const int64_t *splits, const int64_t *deps,
+                                                   unsigned *ticket_ctr, unsigned *status,
+                                                   unsigned epoch, unsigned *err, Gate gate)
 {
     using K = typename KT::T;
     constexpr bool HV = ValOps<V>::has;
@@ -291,6 +303,7 @@ __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, S
     __shared__ K sk[SLOTS];
     __shared__ VS sv[HV ? SLOTS : 1];
     __shared__ unsigned s_next;
+    if (gate.closed()) return;
 
     const int tid = threadIdx.x;
     if (tid == 0) s_next = atomicAdd(ticket_ctr, 1u);
@@ -298,7 +311,7 @@ __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, S
     int64_t t = __builtin_amdgcn_readfirstlane(s_next);
     if (t >= ntiles) return;
 
-    MergeTile cur = merge_tile_setup<TILE>(t, n_total, depth, tpn, splits, deps);
+    MergeTile cur = merge_tile_setup<TILE>(t, geo, tpn, splits, deps);
     K lk[IPT];
     VS lv[IPT];
     // Straight-line loads: indices past the tile are clamped to its last input
@@ -357,7 +370,7 @@ __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, S
         const bool more = t2 < ntiles;
         MergeTile nxt;
         if (more) {
-            nxt = merge_tile_setup<TILE>(t2, n_total, depth, tpn, splits, deps);
+            nxt = merge_tile_setup<TILE>(t2, geo, tpn, splits, deps);
             issue_loads(nxt);
         }
         if (tid < 64) wait_window(status, cur.dlo, cur.dhi, cur.t, epoch, err);
@@ -469,9 +482,39 @@ static int64_t resident_groups(F kernel, int threads, int64_t &cache)
     return cache;
 }
 
+// Enqueues partition, dependency windows and the merge for one level (or one
+// explicit node) whose control words start at `tickets`.
+template <class KT, class V>
+static void launch_level(Space<typename KT::T> sk, Space<V> sv, const MergeGeo &geo, int64_t nn, int64_t tpn,
+                         int64_t *splits, int64_t *deps, unsigned *ticket, unsigned *status,
+                         unsigned *errw, unsigned epoch, Gate gate, hipStream_t st)
+{
+    using C = SortCfg<KT, V>;
+    constexpr int TILE = C::MERGE_NT * C::MERGE_IPT;
+    auto merge_fn = merge_kernel<KT, V, C::MERGE_NT, C::MERGE_IPT>;
+    static int64_t merge_groups = 0;
+    const int64_t resident = resident_groups(merge_fn, C::MERGE_NT, merge_groups);
+    const bool tr = trace_on();
+    const int64_t nsplit = nn * (tpn + 1);
+    const int64_t ntiles = nn * tpn;
+    if (tr) trace_begin(TK_PARTITION, st);
+    hipLaunchKernelGGL((partition_kernel<KT, TILE>), dim3((unsigned)((nsplit + 255) / 256)), dim3(256), 0, st,
+                       sk, geo, nn, tpn, splits, gate);
+    if (tr) trace_end(st);
+    if (tr) trace_begin(TK_DEPWIN, st);
+    hipLaunchKernelGGL((depwin_kernel<TILE>), dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st, geo, nn,
+                       tpn, (const int64_t *)splits, deps, gate);
+    if (tr) trace_end(st);
+    if (tr) trace_begin(TK_MERGE, st);
+    const int64_t grid = ntiles < resident ? ntiles : resident;
+    hipLaunchKernelGGL(merge_fn, dim3((unsigned)grid), dim3(C::MERGE_NT), 0, st, sk, sv, geo, tpn, ntiles,
+                       (const int64_t *)splits, (const int64_t *)deps, ticket, status, epoch, errw, gate);
+    if (tr) trace_end(st);
+}
+
 template <class KT, class V>
 hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const SortPlan &p,
-                    hipStream_t st)
+                    hipStream_t st, Gate gate)
 {
     using K = typename KT::T;
     using C = SortCfg<KT, V>;
@@ -484,9 +527,6 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
     unsigned *status = (unsigned *)(ws + p.off_status);
     int64_t *splits = (int64_t *)(ws + p.off_splits);
     int64_t *deps = (int64_t *)(ws + p.off_deps);
-    auto merge_fn = merge_kernel<KT, V, C::MERGE_NT, C::MERGE_IPT>;
-    static int64_t merge_groups = 0;
-    const int64_t resident = resident_groups(merge_fn, C::MERGE_NT, merge_groups);
 
     const bool tr = trace_on();
     // tickets and status words start at zero on every call
@@ -499,28 +539,18 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
     if (tr) trace_begin(TK_LEAF, st);
     hipLaunchKernelGGL((leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT>), dim3((unsigned)((int64_t)1 << D)),
                        dim3(C::LEAF_NT), 0, st, sk, sv, n, D, (int64_t)1 << D, tickets + 0, status,
-                       epoch, tickets + kErrWord);
+                       epoch, tickets + kErrWord, gate);
     if (tr) trace_end(st);
     for (int d = D - 1; d >= 0; --d) {
         ++epoch;
+        MergeGeo geo{};
+        geo.n_total = n;
+        geo.depth = d;
+        geo.single = 0;
         const int64_t nn = (int64_t)1 << d;
         const int64_t tpn = (frog_max_node(n, d) + TILE - 1) / TILE;
-        const int64_t nsplit = nn * (tpn + 1);
-        const int64_t ntiles = nn * tpn;
-        if (tr) trace_begin(TK_PARTITION, st);
-        hipLaunchKernelGGL((partition_kernel<KT, TILE>), dim3((unsigned)((nsplit + 255) / 256)), dim3(256),
-                           0, st, sk, n, d, nn, tpn, splits);
-        if (tr) trace_end(st);
-        if (tr) trace_begin(TK_DEPWIN, st);
-        hipLaunchKernelGGL((depwin_kernel<TILE>), dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st,
-                           n, d, nn, tpn, (const int64_t *)splits, deps);
-        if (tr) trace_end(st);
-        if (tr) trace_begin(TK_MERGE, st);
-        const int64_t grid = ntiles < resident ? ntiles : resident;
-        hipLaunchKernelGGL(merge_fn, dim3((unsigned)grid), dim3(C::MERGE_NT), 0, st, sk, sv, n, d, tpn, ntiles,
-                           (const int64_t *)splits, (const int64_t *)deps, tickets + (D - d), status,
-                           epoch, tickets + kErrWord);
-        if (tr) trace_end(st);
+        launch_level<KT, V>(sk, sv, geo, nn, tpn, splits, deps, tickets + (D - d), status,
+                            tickets + kErrWord, epoch, gate, st);
     }
     return hipGetLastError();
 }
@@ -529,15 +559,41 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
 SortPlan plan_f64(int64_t n) { return make_plan<KeyF64, NoVal>(n); }
 SortPlan plan_kv(int64_t n) { return make_plan<KeyU64, uint32_t>(n); }
 
-hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st)
+hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st,
+                          const unsigned *gate, unsigned run_if)
 {
-    return run_sort<KeyF64, NoVal>(keys, nullptr, n, ws, p, st);
+    return run_sort<KeyF64, NoVal>(keys, nullptr, n, ws, p, st, Gate{gate, run_if});
 }
 
 hipError_t sort_kv_async(uint64_t *keys, uint32_t *vals, int64_t n, char *ws, const SortPlan &p,
                          hipStream_t st)
 {
-    return run_sort<KeyU64, uint32_t>(keys, vals, n, ws, p, st);
+    return run_sort<KeyU64, uint32_t>(keys, vals, n, ws, p, st, Gate{nullptr, 0u});
+}
+
+hipError_t merge_one_f64_async(double *D, double *H, int64_t n_space, const FrogMerge &m, char *ws,
+                               const SortPlan &p, hipStream_t st, const unsigned *gate, unsigned run_if)
+{
+    using C = SortCfg<KeyF64, NoVal>;
+    constexpr int TILE = C::MERGE_NT * C::MERGE_IPT;
+    const int64_t n = m.nl + m.nr;
+    if (n <= 0) return hipSuccess;
+    Space<double> sk{D, H, n_space};
+    Space<NoVal> sv{nullptr, nullptr, n_space};
+    unsigned *tickets = (unsigned *)(ws + p.off_tickets);
+    unsigned *status = (unsigned *)(ws + p.off_status);
+    int64_t *splits = (int64_t *)(ws + p.off_splits);
+    int64_t *deps = (int64_t *)(ws + p.off_deps);
+    launch_fill_u32(tickets, (p.off_splits - p.off_tickets) / 4, 0u, st);
+    MergeGeo geo{};
+    geo.n_total = n;
+    geo.depth = 0;
+    geo.single = 1;
+    geo.m1 = m;
+    const int64_t tpn = (n + TILE - 1) / TILE;
+    launch_level<KeyF64, NoVal>(sk, sv, geo, 1, tpn, splits, deps, tickets + 1, status, tickets + kErrWord, 1u,
+                                Gate{gate, run_if}, st);
+    return hipGetLastError();
 }
 
 }  // namespace gs

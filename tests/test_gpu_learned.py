@@ -1,0 +1,226 @@
+"""The learned CDF bucket path on the GPU.
+
+Network: forward, loss and gradient of the device kernels against the fp64
+oracle (norm-wise relative error per parameter tensor), one Adam step against
+the oracle's Adam on the oracle's gradient, and training lowering the loss.
+Sort: bit-exact parity with the oracle on the learned workloads and on ties,
+signed zeros and NaNs; the fallback paths (non-monotone table via the test
+hook, a bucket above the limit, a degenerate sample); and a gain test: the
+trained network balances buckets better than the untrained linear CDF.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import announce, bits, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TENSORS = ("W1", "b1", "W2", "b2", "w3", "b3")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    need_gpu()
+    import paper_2402_01816_amd as g
+    return g
+
+
+def _he_params(orc, seed):
+    rng = np.random.default_rng(seed)
+    sl = orc.mlp_slices()
+    p = np.zeros(orc.MLP_NUM_PARAMS)
+    p[sl["W1"]] = rng.normal(0, math.sqrt(2.0), 64)
+    p[sl["b1"]] = rng.normal(0, 0.2, 64)
+    p[sl["W2"]] = rng.normal(0, math.sqrt(2.0 / 64), 64 * 64)
+    p[sl["b2"]] = rng.normal(0, 0.2, 64)
+    p[sl["w3"]] = rng.normal(0, math.sqrt(2.0 / 64), 64)
+    p[sl["b3"]] = rng.normal(0, 0.2, 1)
+    return p.astype(np.float32)
+
+
+def _batch(seed, n):
+    rng = np.random.default_rng(seed)
+    u = rng.random(n).astype(np.float32)
+    t = np.sqrt(u).astype(np.float32)          # a CDF-like target
+    return u, t
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("batch", [32, 256, 2048])
+def test_gradient_matches_oracle(gs, orc, batch):
+    announce("mlp grad", batch)
+    p = _he_params(orc, batch)
+    u, t = _batch(batch + 1, batch)
+    loss, grad = gs.gs_mlp_loss_grad(to_dev(p), to_dev(u), to_dev(t))
+    ref_loss, ref_grad = orc.mlp_loss_grad(p.astype(np.float64), u.astype(np.float64), t.astype(np.float64))
+    assert abs(float(loss.item()) - ref_loss) <= 1e-5 * max(1.0, abs(ref_loss))
+    g = grad.cpu().numpy().astype(np.float64)
+    for name, sl in orc.mlp_slices().items():
+        assert _relerr(g[sl], ref_grad[sl]) <= 1e-4, name
+
+
+def test_forward_matches_oracle(gs, orc):
+    announce("mlp forward")
+    p = _he_params(orc, 7)
+    u = np.linspace(-0.5, 1.5, 4099).astype(np.float32)
+    y = gs.gs_mlp_forward(to_dev(p), to_dev(u)).cpu().numpy()
+    ref = orc.mlp_forward(p.astype(np.float64), u.astype(np.float64))
+    assert np.max(np.abs(y - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_adam_step_matches_oracle(gs, orc):
+    torch = need_gpu()
+    announce("mlp adam")
+    p = _he_params(orc, 9)
+    u, t = _batch(10, 512)
+    P, M, V = to_dev(p), torch.zeros(p.size, device="cuda"), torch.zeros(p.size, device="cuda")
+    losses = gs.gs_mlp_train(P, M, V, to_dev(u), to_dev(t), steps=1, batch=512, lr=1e-3,
+                             full_batch=True)
+    _, g = orc.mlp_loss_grad(p.astype(np.float64), u.astype(np.float64), t.astype(np.float64))
+    ref = p.astype(np.float64).copy()
+    m, v = np.zeros_like(ref), np.zeros_like(ref)
+    orc.adam_step(ref, g, m, v, 1, lr=1e-3)
+    got = P.cpu().numpy().astype(np.float64)
+    upd, ref_upd = got - p, ref - p
+    big = np.abs(g) > 1e-5                        # |g| >> eps: update is lr*sign(g)
+    assert np.allclose(upd[big], ref_upd[big], rtol=1e-3, atol=1e-7)
+    assert np.all(np.abs(upd) <= 1e-3 + 1e-6)
+    assert _relerr(M.cpu().numpy().astype(np.float64), 0.1 * g) <= 1e-4
+    assert _relerr(V.cpu().numpy().astype(np.float64), 0.001 * g * g) <= 1e-3
+    assert float(losses[0].item()) > 0
+
+
+def test_training_lowers_loss(gs, orc):
+    torch = need_gpu()
+    announce("mlp train")
+    p = _he_params(orc, 11)
+    u, t = _batch(12, 65536)
+    P, M, V = to_dev(p), torch.zeros(p.size, device="cuda"), torch.zeros(p.size, device="cuda")
+    losses = gs.gs_mlp_train(P, M, V, to_dev(u), to_dev(t), steps=200, batch=2048, lr=1e-2, seed=3)
+    first, last = (float(x) for x in losses.cpu().numpy())
+    assert last < 0.05 * first
+    # same seed, same result: the reductions are deterministic
+    P2, M2, V2 = to_dev(p), torch.zeros(p.size, device="cuda"), torch.zeros(p.size, device="cuda")
+    gs.gs_mlp_train(P2, M2, V2, to_dev(u), to_dev(t), steps=200, batch=2048, lr=1e-2, seed=3)
+    assert torch.equal(P, P2)
+
+
+N_SMALL = 1 << 20
+
+
+def _learned(gs, x, report=True, **kw):
+    t = to_dev(x)
+    rep = gs.gs_learned_sort(t, report=report, **kw)
+    return t, rep
+
+
+@pytest.mark.parametrize("pattern", ["lognormal", "gaussmix", "zipf_ints"])
+def test_learned_sort_parity(gs, orc, pattern):
+    announce("learned", pattern)
+    x = W.learned_pattern(pattern, N_SMALL + 12345, seed=1)
+    t, rep = _learned(gs, x, sample_size=16384)
+    assert rep["fallback"] == 0
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+    assert rep["train_loss_last"] < rep["train_loss_first"]
+
+
+@pytest.mark.parametrize("pattern", ["uniform", "tied", "presorted", "reversed", "zeros_signed"])
+def test_learned_sort_other_patterns(gs, orc, pattern):
+    announce("learned other", pattern)
+    x = W.f64_pattern(pattern, N_SMALL - 3, seed=2)
+    t, rep = _learned(gs, x, sample_size=16384)
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+def test_learned_sort_special_values(gs, orc):
+    announce("learned special")
+    x = W.learned_pattern("gaussmix", N_SMALL, seed=3)
+    rng = np.random.default_rng(4)
+    idx = rng.integers(0, x.size, 5000)
+    x[idx[:1000]] = np.nan
+    x[idx[1000:2000]] = np.inf
+    x[idx[2000:3000]] = -np.inf
+    x[idx[3000:4000]] = -0.0
+    x[idx[4000:]] = 0.0
+    t, rep = _learned(gs, x, sample_size=16384)
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+def test_learned_untrained_mode(gs, orc):
+    announce("learned mode1")
+    x = W.learned_pattern("lognormal", N_SMALL, seed=5)
+    t, rep = _learned(gs, x, sample_size=16384, mode=1)
+    assert rep["fallback"] == 0
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+def test_learned_weights_override(gs, orc):
+    announce("learned override")
+    p = _he_params(orc, 13)
+    x = W.learned_pattern("zipf_ints", N_SMALL, seed=6)
+    P = to_dev(p)
+    t, rep = _learned(gs, x, sample_size=16384, weights_override=P.data_ptr())
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+def test_learned_fallback_on_order_violation(gs, orc):
+    """A non-monotone raw bucket table (test hook) must be rejected before any
+    key moves; the plain path then sorts the untouched input."""
+    announce("learned fallback order")
+    params = gs.gs_learned_default_params()
+    G = params.knots
+    table = np.linspace(1.0, 0.0, G + 1).astype(np.float32)        # decreasing
+    T = to_dev(table)
+    x = W.learned_pattern("gaussmix", N_SMALL, seed=7)
+    t, rep = _learned(gs, x, sample_size=16384, test_bucket_table=T.data_ptr())
+    assert rep["fallback"] == 1
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+def test_learned_fallback_on_overflow(gs, orc):
+    """One key value holding 60% of a 2^22-key input puts more than the bucket
+    limit (2^20) into one bucket of each half: the call takes the plain path."""
+    announce("learned fallback overflow")
+    n = 1 << 22
+    x = W.f64_pattern("uniform", n, seed=8)
+    rng = np.random.default_rng(9)
+    x[rng.random(n) < 0.6] = 0.5
+    t, rep = _learned(gs, x, sample_size=16384)
+    assert rep["fallback"] == 1 and rep["overflow_buckets"] > 0
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+def test_learned_degenerate_all_equal(gs, orc):
+    announce("learned all equal")
+    x = np.full(N_SMALL, 3.25)
+    x[::7] = -0.0 + 3.25
+    t, rep = _learned(gs, x, sample_size=16384)
+    assert rep["fallback"] == 1
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+def test_learned_small_input_runs_plain(gs, orc):
+    announce("learned small")
+    for n in (0, 1, 2, 1000, 65535):
+        x = W.f64_pattern("zeros_signed", n, seed=10)
+        t, rep = _learned(gs, x)
+        assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+def test_learned_gain_over_untrained(gs):
+    """On lognormal keys the trained network spreads keys over the buckets
+    far more evenly than the untrained linear CDF on the same feature."""
+    announce("learned gain")
+    x = W.learned_pattern("lognormal", 1 << 22, seed=11)
+    _, trained = _learned(gs, x)
+    _, untrained = _learned(gs, x, mode=1)
+    assert trained["fallback"] == 0 and untrained["fallback"] == 0
+    avg = (1 << 22) / 2 / 4096
+    assert trained["max_bucket"] < 0.5 * untrained["max_bucket"]
+    assert trained["max_bucket"] < 4 * avg

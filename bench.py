@@ -11,6 +11,8 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+
+import numpy as np
 import json
 import math
 import os
@@ -21,6 +23,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+METRIC = "Gkeys/s stable f64 sort n=2^28 (learned vs plain merge), %HBM BW, %RAM footprint"
+COUNTERS = os.path.join(ROOT, "profiles", "merge_kernel_f64_2p28_uniform_hbm_counters.md")
+
+
+def merge_traffic():
+    """HBM bytes per merge-kernel launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, scaled by a copy kernel of known size),
+    or None when the merge kernel's sources no longer hash to the value the
+    counters were taken on."""
+    import hashlib
+    try:
+        kv = dict(l.split(": ", 1) for l in open(COUNTERS).read().splitlines()
+                  if l.startswith(("traffic_bytes_per_launch:", "sources_sha256_16:", "sources:")))
+        h = hashlib.sha256()
+        for f in kv["sources"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != kv["sources_sha256_16"].strip():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -44,6 +67,134 @@ def cpu_baseline(n_sample: int, pattern: str):
             "seconds": dt}
 
 
+def _time_calls(torch, stream, fn, reps):
+    """Median of `reps` HIP-event timings of fn(i) (input restored outside)."""
+    times = []
+    for i in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        fn(i, None)
+        e0.record(stream)
+        fn(i, True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def extras(gs, torch, W, log2n, dev):
+    """Side measurements on the same device: the learned path against the plain
+    path on the learned workloads, the segmented sort against per-array plain
+    calls, and the key-value sort.  Medians of a few HIP-event timed reps."""
+    stream = torch.cuda.current_stream(dev)
+    n = 1 << log2n
+    res = {}
+    # the plain sort on the other input patterns of the same size
+    pats = {}
+    need = gs.gs_workspace_bytes_f64(n)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    ws = ws[(-ws.data_ptr()) % 256:][:need]
+    for pat in ("tied", "presorted", "reversed", "perturbed"):
+        log(f"extras: plain {pat}")
+        x = torch.from_numpy(W.f64_pattern(pat, n, seed=0)).to(dev)
+        buf = torch.empty_like(x)
+
+        def fn_p(i, timed):
+            if timed is None:
+                buf.copy_(x)
+            else:
+                gs.gs_sort_f64(buf, workspace=ws)
+        gs.gs_sort_f64(buf.copy_(x), workspace=ws)
+        ms = _time_calls(torch, stream, fn_p, 3)
+        pats[pat] = {"ms": round(ms, 3), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3)}
+        del x, buf
+    del ws
+    res["plain_patterns"] = pats
+    # learned vs plain on the learned workloads
+    lr = {}
+    for pat in ("lognormal", "gaussmix", "zipf_ints"):
+        log(f"extras: learned {pat}")
+        x = torch.from_numpy(W.learned_pattern(pat, n, seed=0)).to(dev)
+        buf = torch.empty_like(x)
+        row = {}
+        for name, call in (("plain", lambda b: gs.gs_sort_f64(b)),
+                           ("learned", lambda b: gs.gs_learned_sort(b)),
+                           ("learned_untrained", lambda b: gs.gs_learned_sort(b, mode=1))):
+            def fn(i, timed, call=call):
+                if timed is None:
+                    buf.copy_(x)
+                else:
+                    call(buf)
+            call(buf)                                  # warm-up (and workspace)
+            ms = _time_calls(torch, stream, fn, 3)
+            row[name] = {"ms": round(ms, 3), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3)}
+        buf.copy_(x)
+        rep = gs.gs_learned_sort(buf, report=True)
+        row["learned_report"] = {k: rep[k] for k in ("fallback", "max_bucket", "overflow_buckets",
+                                                    "train_loss_first", "train_loss_last", "feature")}
+        row["learned_sorted"] = bool((buf[1:] >= buf[:-1]).all().item())
+        lr[pat] = row
+        del x, buf
+    res["learned_vs_plain"] = lr
+    # segmented: 100,000 arrays, log-uniform lengths, total 2^28, mixed patterns
+    log("extras: segmented")
+    xs, off = W.segmented(100_000, 16, 19023, seed=0, total=n)
+    x = torch.from_numpy(xs).to(dev)
+    o = torch.from_numpy(off).to(dev)
+    buf = torch.empty_like(x)
+    gs.gs_segsort(buf.copy_(x), o)
+
+    def fn_seg(i, timed):
+        if timed is None:
+            buf.copy_(x)
+        else:
+            gs.gs_segsort(buf, o)
+    ms_seg = _time_calls(torch, stream, fn_seg, 3)
+    # per-array plain launches on the first 2000 arrays, scaled to all
+    k = 2000
+    sub = [buf[int(off[i]):int(off[i + 1])] for i in range(k)]
+    wsmax = max(gs.gs_workspace_bytes_f64(t.numel()) for t in sub)
+    ws = torch.empty(wsmax + 256, dtype=torch.uint8, device=dev)
+    ws = ws[(-ws.data_ptr()) % 256:][:wsmax]
+
+    def fn_each(i, timed):
+        if timed is None:
+            buf.copy_(x)
+        else:
+            for t in sub:
+                if t.numel() > 1:
+                    gs.gs_sort_f64(t, workspace=ws[: gs.gs_workspace_bytes_f64(t.numel())])
+    ms_each = _time_calls(torch, stream, fn_each, 1) * (100_000 / k)
+    res["segmented"] = {"arrays": 100_000, "keys": n, "ms": round(ms_seg, 3),
+                        "gkeys_per_s": round(n / (ms_seg * 1e-3) / 1e9, 3),
+                        "per_array_launches_ms_est": round(ms_each, 1),
+                        "per_array_note": "2000 separate gs_sort_f64 calls timed, scaled to 100,000"}
+    del x, buf, o, sub, ws
+    # key-value: 2^(log2n+1) uint64 keys with uint32 payload
+    log("extras: key-value")
+    nk = 1 << (log2n + 1)
+    kv = {}
+    for pat in ("uniform", "zipf"):
+        k0, v0 = W.kv_pattern(pat, nk, seed=0)
+        K = torch.from_numpy(k0.view(np.int64)).to(dev)
+        V = torch.from_numpy(v0.view(np.int32)).to(dev)
+        Kb, Vb = torch.empty_like(K), torch.empty_like(V)
+
+        def fn_kv(i, timed):
+            if timed is None:
+                Kb.copy_(K)
+                Vb.copy_(V)
+            else:
+                gs.gs_sort_kv(Kb, Vb)
+        gs.gs_sort_kv(Kb.copy_(K), Vb.copy_(V))
+        ms = _time_calls(torch, stream, fn_kv, 3)
+        kv[pat] = {"n": nk, "ms": round(ms, 3), "gkeys_per_s": round(nk / (ms * 1e-3) / 1e9, 3)}
+        del K, V, Kb, Vb
+    res["key_value"] = kv
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +204,8 @@ def main():
     ap.add_argument("--pattern", default="uniform")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the learned / segmented / key-value side measurements")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -152,12 +305,13 @@ def main():
     merge_bytes = 16.0 * n                          # every key read once and written once
     achieved = merge_bytes / (merge_avg * 1e-3) / 1e9 if merge_avg > 0 else 0.0
     ram = 1.0 + need / (8.0 * n)
+    traffic = merge_traffic() if (n == 1 << 28 and args.pattern == "uniform") else None
     value = n / (ms_per_step * 1e-3) / 1e9
     passes = 1 + levels
     whole_bytes = 16.0 * n * passes
 
     out = {
-        "metric": "Gkeys/s stable f64 sort n=2^28 (plain frog merge), %HBM BW, %RAM footprint",
+        "metric": METRIC,
         "value": round(value, 4),
         "unit": "Gkeys/s",
         "n_gpus": 1,
@@ -175,7 +329,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "merge_kernel",
+                     "traffic": traffic, "kernel": "merge_kernel",
                      "bytes_per_launch": merge_bytes, "avg_launch_ms": round(merge_avg, 5)},
         "copy_ceiling_gbs": round(copy_gbs, 1),
         "merge_frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None,
@@ -187,6 +341,8 @@ def main():
         "wall_s": round(wall, 3),
         "report": rep,
     }
+    if not args.no_extras:
+        out["extras"] = extras(gs, torch, W, args.log2n, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2, args.pattern)

@@ -83,12 +83,20 @@ def uniform01(n: int, key: int, offset: int = 0) -> np.ndarray:
     return _fill(n, fn, np.float64)
 
 
+def _chunked(n: int, fn, dtype) -> np.ndarray:
+    """out[a:b] = fn(a, b) over chunks, on a thread pool (numpy releases the GIL)."""
+    def fill(a, b, out):
+        out[a:b] = fn(a, b)
+    return _fill(n, fill, dtype)
+
+
 def normal(n: int, key: int) -> np.ndarray:
     """Standard normal deviates by Box-Muller from two uniform streams."""
     u1 = uniform01(n, key, 0)
     u2 = uniform01(n, key ^ 0x5DEECE66D, 0)
-    u1 = 1.0 - u1                       # (0, 1]: log is finite
-    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+    # (0, 1] for the log: 1 - u1
+    return _chunked(n, lambda a, b: np.sqrt(-2.0 * np.log(1.0 - u1[a:b]))
+                    * np.cos(2.0 * math.pi * u2[a:b]), np.float64)
 
 
 def permute_indices(j: np.ndarray, n: int, key: int) -> np.ndarray:
@@ -187,8 +195,8 @@ def zipf_ranks(n: int, key: int, values: int = 1 << 20, s: float = 1.1) -> np.nd
     """Zipf(s) ranks in [0, values) by inverse CDF (binary search on U)."""
     cdf = zipf_cdf(values, s)
     u = uniform01(n, key)
-    r = np.searchsorted(cdf, u, side="right")
-    return np.minimum(r, values - 1).astype(np.int64)
+    return _chunked(n, lambda a, b: np.minimum(np.searchsorted(cdf, u[a:b], side="right"),
+                                               values - 1), np.int64)
 
 
 def kv_pattern(pattern: str, n: int, seed: int = 0, workload: int = 3,
@@ -271,7 +279,8 @@ def learned_pattern(pattern: str, n: int, seed: int = 0, workload: int = 5):
     through a seeded permutation of [1, 2^20] and cast to float64."""
     key = stream_seed(workload, _PATTERN_ID[pattern], seed)
     if pattern == "lognormal":
-        return np.exp(2.0 * normal(n, key))
+        z = normal(n, key)
+        return _chunked(n, lambda a, b: np.exp(2.0 * z[a:b]), np.float64)
     if pattern == "gaussmix":
         prm = uniform01(16, key ^ 0xF00D)
         mu = -100.0 + 200.0 * prm[:8]

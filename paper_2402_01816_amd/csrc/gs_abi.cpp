@@ -91,7 +91,7 @@ struct Reporter {
 gs_status check_err_word(const char *ws, const gs::SortPlan &p)
 {
     unsigned w = 0;
-    hipError_t e = hipMemcpy(&w, ws + p.off_tickets + 4 * gs::kErrWord, 4, hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(&w, ws + p.off_forest + p.forest.off_ctrl + 4 * gs::kErrWord, 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "reading the error word");
     if (w) return fail(GS_EDEVICE, "an ordered-store wait exceeded its spin limit");
     return GS_OK;

@@ -61,9 +61,12 @@ __device__ __forceinline__ void serial_merge(const typename KT::T *sk, int a_bas
 // adjacent strict inversions are exchanged, so equal keys keep their order),
 // then merge rounds that double the sorted run length up to `maxw` (a power of
 // two in [IPT, TILE]): each aligned block of maxw keys ends up sorted on its
-// own, which lets one work-group sort several short arrays at once.
+// own, which lets one work-group sort several short arrays at once.  Threads
+// whose keys lie at or past `active` (a multiple of maxw) skip the work: the
+// caller guarantees those slots hold only padding, which is already sorted.
 template <class KT, class VS, bool HV, int NT, int IPT>
-__device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int maxw = NT * IPT)
+__device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int maxw = NT * IPT,
+                                               int active = NT * IPT)
 {
     using K = typename KT::T;
     constexpr int TILE = NT * IPT;
@@ -72,52 +75,61 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
     VS v[IPT];
     int srcix[IPT];
     const int base = tid * IPT;
+    const bool work = base < active;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         k[i] = sk[lpad(base + i)];
         if constexpr (HV) v[i] = sv[lpad(base + i)];
     }
+    if (work) {
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
+        for (int r = 0; r < IPT; ++r) {
 #pragma unroll
-        for (int i = (r & 1); i + 1 < IPT; i += 2) {
-            const bool sw = KT::less(k[i + 1], k[i]);
-            const K lo = sw ? k[i + 1] : k[i];
-            const K hi = sw ? k[i] : k[i + 1];
-            k[i] = lo;
-            k[i + 1] = hi;
-            if constexpr (HV) {
-                const VS vlo = sw ? v[i + 1] : v[i];
-                const VS vhi = sw ? v[i] : v[i + 1];
-                v[i] = vlo;
-                v[i + 1] = vhi;
+            for (int i = (r & 1); i + 1 < IPT; i += 2) {
+                const bool sw = KT::less(k[i + 1], k[i]);
+                const K lo = sw ? k[i + 1] : k[i];
+                const K hi = sw ? k[i] : k[i + 1];
+                k[i] = lo;
+                k[i + 1] = hi;
+                if constexpr (HV) {
+                    const VS vlo = sw ? v[i + 1] : v[i];
+                    const VS vhi = sw ? v[i] : v[i + 1];
+                    v[i] = vlo;
+                    v[i + 1] = vhi;
+                }
             }
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        sk[lpad(base + i)] = k[i];
-        if constexpr (HV) sv[lpad(base + i)] = v[i];
-    }
-    __syncthreads();
-
-    for (int w = IPT; w < maxw; w *= 2) {
-        const int a0 = (base / (2 * w)) * 2 * w;
-        const int b0 = a0 + w;
-        const int kd = base - a0;
-        const int ai = merge_path_lds<KT>(kd, w, w, [&](int i) { return sk[lpad(a0 + i)]; },
-                                          [&](int i) { return sk[lpad(b0 + i)]; });
-        serial_merge<KT, IPT, HV>(sk, a0, w, b0, w, ai, kd - ai, TILE, k, srcix);
-        if constexpr (HV) {
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) v[i] = sv[lpad(srcix[i])];
-        }
-        __syncthreads();
+    if (work) {
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             sk[lpad(base + i)] = k[i];
             if constexpr (HV) sv[lpad(base + i)] = v[i];
+        }
+    }
+    __syncthreads();
+
+    for (int w = IPT; w < maxw; w *= 2) {
+        if (work) {
+            const int a0 = (base / (2 * w)) * 2 * w;
+            const int b0 = a0 + w;
+            const int kd = base - a0;
+            const int ai = merge_path_lds<KT>(kd, w, w, [&](int i) { return sk[lpad(a0 + i)]; },
+                                              [&](int i) { return sk[lpad(b0 + i)]; });
+            serial_merge<KT, IPT, HV>(sk, a0, w, b0, w, ai, kd - ai, TILE, k, srcix);
+            if constexpr (HV) {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) v[i] = sv[lpad(srcix[i])];
+            }
+        }
+        __syncthreads();
+        if (work) {
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                sk[lpad(base + i)] = k[i];
+                if constexpr (HV) sv[lpad(base + i)] = v[i];
+            }
         }
         __syncthreads();
     }

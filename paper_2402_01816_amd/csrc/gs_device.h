@@ -57,17 +57,110 @@ struct Gate {
 };
 
 // ---------------------------------------------------------------------------
-// merges of one launch: every node of one frog-tree level, or one explicit node
+// a forest of independent frog sorts processed level-synchronously
 // ---------------------------------------------------------------------------
-struct MergeGeo {
-    int64_t n_total;
-    int depth;
-    int single;       // 1: the launch merges exactly the node m1
-    FrogMerge m1;
-    __device__ __forceinline__ FrogMerge node(int64_t idx) const
-    {
-        return single ? m1 : frog_merge_of(frog_node(n_total, depth, idx));
+// Every problem (one array, one segment, one bucket) is a frog tree of its own
+// over its own logical space: slots [0, n) at D + doff, slots [n, n + n/2) at
+// H + hoff.  Round 0 sorts every leaf of every problem; round r >= 1 performs
+// the merges at depth (depth - r) of every problem that deep, so all problems
+// reach their roots together.  Work items (tickets) of a round are numbered
+// problem after problem; per problem, leaves in descending index order and
+// merge tiles node after node, each node's tiles in its write order.
+struct Prob {
+    int64_t doff;     // first key in the caller's array
+    int64_t hoff;     // first slot in the half buffer
+    int64_t n;        // keys
+    int32_t depth;    // depth of the leaf level
+    int32_t pad;
+};
+
+struct Forest {
+    const Prob *probs;        // problem table, or nullptr: the single problem p0
+    const unsigned *nprob;    // number of problems in the table (device word)
+    const unsigned *tbase;    // per round, prefix sums of tickets over problems
+    const unsigned *sbase;    // per round, prefix sums of merge-path splits
+    int64_t stride;           // row length of tbase / sbase (>= problems + 1)
+    Prob p0;
+    FrogMerge m1;             // with use_m1: round 1 of p0 is this one merge
+    int use_m1;
+};
+
+GS_HD int64_t forest_nodes(const Forest &F, const Prob &P, int round)
+{
+    if (F.use_m1) return 1;
+    return round <= P.depth ? ((int64_t)1 << (P.depth - round)) : 0;
+}
+
+template <int TILE>
+GS_HD int64_t forest_tpn(const Forest &F, const Prob &P, int round)
+{
+    if (F.use_m1) return (F.m1.nl + F.m1.nr + TILE - 1) / TILE;
+    return (frog_max_node(P.n, P.depth - round) + TILE - 1) / TILE;
+}
+
+// tickets of one problem in a round (round 0: its leaves)
+template <int TILE>
+GS_HD int64_t forest_tickets(const Forest &F, const Prob &P, int round)
+{
+    if (round == 0) return (int64_t)1 << P.depth;
+    return forest_nodes(F, P, round) * forest_tpn<TILE>(F, P, round);
+}
+
+template <int TILE>
+GS_HD int64_t forest_splits(const Forest &F, const Prob &P, int round)
+{
+    if (round == 0) return 0;
+    return forest_nodes(F, P, round) * (forest_tpn<TILE>(F, P, round) + 1);
+}
+
+GS_HD FrogMerge forest_merge(const Forest &F, const Prob &P, int round, int64_t node)
+{
+    return F.use_m1 ? F.m1 : frog_merge_of(frog_node(P.n, P.depth - round, node));
+}
+
+// Problem whose range of a prefix row holds x: the last s in [0, L) with
+// row[s] <= x (then row[s+1] > x, so the problem is not empty).
+__device__ __forceinline__ Prob forest_prob(const Forest &F, int64_t s) { return F.probs ? F.probs[s] : F.p0; }
+
+__device__ __forceinline__ int64_t forest_locate(const unsigned *row, int64_t L, int64_t x)
+{
+    int64_t lo = 0, hi = L;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)row[mid] <= x) lo = mid;
+        else hi = mid;
     }
+    return lo;
+}
+
+// The same search done by every lane of a wave together, x uniform: each
+// round probes 63 evenly spaced rows at once and keeps the interval between
+// the last probe <= x and the next, so about log64(L) rounds of loads.
+__device__ __forceinline__ int64_t forest_locate_wave(const unsigned *row, int64_t L, int64_t x)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t lo = 0, hi = L;
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t idx = lo + (int64_t)(lane + 1) * step;
+        const bool le = idx < hi && (int64_t)row[idx] <= x;
+        const int k = __popcll(__ballot(le));           // probes <= x form a prefix of the lanes
+        const int64_t nlo = lo + (int64_t)k * step;
+        const int64_t nhi = lo + (int64_t)(k + 1) * step;
+        lo = nlo;
+        hi = nhi < hi ? nhi : hi;
+    }
+    return lo;
+}
+
+// One merge output tile, resolved before the merge launch: the runs it reads,
+// where it writes, and the tickets it must wait for before storing.
+struct TileDesc {
+    int64_t pa, pb;   // logical slots of its first first-run / second-run input
+    int64_t o;        // logical slot of its first output
+    unsigned dlo, dhi;       // dependency window (tickets, inclusive; empty if dlo > dhi)
+    int la, cnt;      // first-run inputs, total inputs (= outputs)
+    int prob, pad;    // its problem (row of the table; 0 for the inline problem)
 };
 
 // ---------------------------------------------------------------------------

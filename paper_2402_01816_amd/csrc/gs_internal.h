@@ -11,6 +11,29 @@ namespace gs {
 // bounded wait gave up; it is cleared with the counters on every call.
 constexpr int kErrWord = 63;
 
+// Control words of a forest run: ticket counters of rounds 0..62 and the
+// error word.
+constexpr int kForestCtrlWords = 64;
+
+// Layout of the area a forest run (one or many frog trees) works in, from
+// offset 0 of that area.
+struct ForestPlan {
+    int64_t max_probs;    // rows of the problem table (0: one problem given inline)
+    int rounds;           // merge rounds launched
+    int64_t leaf, tile;   // largest leaf, merge output tile (elements)
+    int64_t stride;       // row length of the prefix tables
+    int64_t max_tickets;  // work items of one merge round (capacity)
+    int64_t max_status;   // status words (capacity over all rounds)
+    int64_t max_splits;   // merge-path splits of one round (capacity)
+    int64_t off_ctrl;     // kForestCtrlWords words
+    int64_t off_status;
+    int64_t off_splits;
+    int64_t off_desc;     // tile descriptors of the current round
+    int64_t off_probs;    // problem table (table runs only)
+    int64_t off_tbase, off_sbase;   // per-round prefix rows (table runs only)
+    int64_t bytes;
+};
+
 // Workspace layout and tree shape of one plain sort.
 struct SortPlan {
     int64_t n;            // keys
@@ -19,12 +42,8 @@ struct SortPlan {
     int depth;            // tree depth = number of merge levels
     int64_t off_hkeys;    // half buffer for keys: floor(n/2) elements
     int64_t off_hvals;    // half buffer for values (kv only)
-    int64_t off_tickets;  // per-launch ticket counters
-    int64_t n_tickets;
-    int64_t off_status;   // per-tile status words
-    int64_t n_status;
-    int64_t off_splits;   // merge-path splits of the current level
-    int64_t off_deps;     // dependency window (two tickets) of every merge tile
+    int64_t off_forest;   // control area of the run
+    ForestPlan forest;
     int64_t bytes;        // total workspace
 };
 
@@ -35,16 +54,31 @@ struct SegPlan {
     int64_t off_h;        // half buffer: floor(num_keys/2) doubles
     int64_t off_ctrl;     // 64 control words
     int64_t off_cls, off_rank, off_list;   // per-segment class, rank in class, class-ordered list
+    int64_t off_forest;   // forest area for the long segments
+    ForestPlan forest;
     int64_t bytes;
 };
 SegPlan plan_seg(int64_t num_keys, int64_t nseg);
+// Forest area for the long segments of up to nseg segments of at most max_len
+// keys each, num_keys keys in total.
+ForestPlan plan_forest_seg(int64_t num_keys, int64_t max_len, int64_t nseg);
 hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan &p, char *ws,
                              hipStream_t st);
 // The same with every buffer given: hbuf holds floor((offsets[nseg]-offsets[0])/2)
-// doubles, ctrl 64 words, cls/rank/list nseg ints each.
+// doubles, ctrl 64 words, cls/rank/list nseg ints each, forest an area laid
+// out by fp (from plan_forest_seg for these sizes).
 hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys,
-                              double *hbuf, unsigned *ctrl, int *cls, int *rank, int *list,
-                              const unsigned *gate, unsigned run_if, hipStream_t st);
+                              double *hbuf, unsigned *ctrl, int *cls, int *rank, int *list, char *forest,
+                              const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st);
+
+struct Prob;
+// Capacity of a forest area for up to max_probs f64 problems of at most
+// max_len keys each, num_keys keys in total.
+ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs);
+// Frog-sorts every problem of a device table (nprob: device word with the
+// number of rows) over D (keys) and H (half buffers); area fw laid out by fp.
+hipError_t forest_f64_async(double *D, double *H, const Prob *probs, const unsigned *nprob, const ForestPlan &fp,
+                            char *fw, hipStream_t st, const unsigned *gate, unsigned run_if);
 
 SortPlan plan_f64(int64_t n);
 SortPlan plan_kv(int64_t n);

@@ -38,10 +38,11 @@ namespace gs {
 
 namespace {
 
-constexpr int HNT = 256;                 // histogram / scatter work-group size
-constexpr int HIPT = 16;                 // keys per lane per batch
 constexpr int FEAT_BINS = 4096;          // bins for choosing the feature
 constexpr int kDensH = 32;               // half window (ranks) of the density targets
+// A bucket larger than max(kBucketLimit, a quarter of its half) sends the call
+// to the plain path: the network failed to spread the keys.
+constexpr int64_t kBucketLimit = (int64_t)1 << 20;
 
 // control words of the learned path
 constexpr int L_FALLBACK = 0;            // 1: take the plain path
@@ -77,35 +78,36 @@ __device__ __forceinline__ double phi_of(double x, const Feature &F)
     if (F.bits) {
         const uint64_t k = ckey(x);
         const double num = k >= F.klo ? (double)(k - F.klo) : -(double)(F.klo - k);
-        return num / F.krange;
+        return num * F.kinv;
     }
-    return (x - F.lo) / F.range;
+    return (x - F.lo) * F.inv;
 }
 
 // Bucket of key x.  Monotone non-decreasing in x whenever `tab` is
-// non-decreasing: phi is monotone (correctly rounded subtraction, conversion
-// and division by a positive constant), the knot index and the fraction are
-// monotone in phi, the interpolation is clamped to the next knot.
+// non-decreasing: the knot coordinate u is monotone (correctly rounded
+// subtraction, conversion, multiplication by a positive constant and
+// rounding to float), the knot index and the fraction are monotone in u, the
+// interpolation is clamped to the next knot.  NaN keys take the last bucket
+// (they sort last).
 __device__ __forceinline__ int bucket_of(double x, const Feature &F, const float *tab, int G, int B)
 {
-    if (x != x) return B - 1;
-    const double u = phi_of(x, F) * (double)G;
-    int i;
-    float f;
-    if (!(u > 0.0)) {
-        i = 0;
-        f = 0.f;
-    } else if (u >= (double)G) {
-        i = G - 1;
-        f = 1.f;
+    float u;
+    if (F.bits) {
+        const uint64_t k = ckey(x);
+        const uint64_t dk = k > F.klo ? k - F.klo : 0ull;
+        u = (float)((double)dk * F.kscale);
     } else {
-        i = (int)u;
-        f = (float)(u - (double)i);
+        u = (float)((x - F.lo) * F.scale);
     }
+    // clamp to [0, G] (a NaN u becomes 0), knot index and fraction
+    const float uc = fminf(fmaxf(u, 0.f), (float)G);
+    const int i = min((int)uc, G - 1);
+    const float f = uc - (float)i;
     const float a = tab[i], b = tab[i + 1];
     const float v = fminf(fmaf(f, b - a, a), b);
-    const int bk = (int)(v * (float)B);
-    return bk < 0 ? 0 : (bk > B - 1 ? B - 1 : bk);
+    int bk = (int)(v * (float)B);
+    bk = bk < 0 ? 0 : (bk > B - 1 ? B - 1 : bk);
+    return x != x ? B - 1 : bk;
 }
 
 }  // namespace
@@ -129,7 +131,7 @@ __global__ void learned_sample_kernel(const double *keys, int64_t n, int64_t S, 
 // key.  The feature whose FEAT_BINS-bin histogram of the sample has the
 // smaller largest bin wins (ties: linear).  Targets: log of the local density
 // of the sample in phi over a window of +-kDensH ranks.
-__global__ __launch_bounds__(1024) void learned_prep_kernel(const double *xs, int64_t S, Feature *feat,
+__global__ __launch_bounds__(1024) void learned_prep_kernel(const double *xs, int64_t S, int G, Feature *feat,
                                                             float *u, float *t, unsigned *ctrl)
 {
     __shared__ unsigned h_lin[FEAT_BINS], h_bits[FEAT_BINS];
@@ -159,8 +161,13 @@ __global__ __launch_bounds__(1024) void learned_prep_kernel(const double *xs, in
         F.klo = ckey(F.lo);
         F.khi = ckey(F.hi);
         F.krange = (double)(F.khi - F.klo);
+        F.inv = 1.0 / F.range;
+        F.kinv = 1.0 / F.krange;
+        F.scale = (double)G / F.range;
+        F.kscale = (double)G / F.krange;
     }
-    const bool lin_ok = nn > 0 && F.range > 0.0 && F.range < __builtin_inf();
+    const bool lin_ok = nn > 0 && F.range > 0.0 && F.range < __builtin_inf() && F.inv < __builtin_inf() &&
+                        F.scale < __builtin_inf();
     const bool bits_ok = nn > 0 && F.khi > F.klo;
     for (int64_t i = tid; i < nn; i += 1024) {
         if (lin_ok) {
@@ -283,92 +290,107 @@ __global__ __launch_bounds__(1024) void learned_table_kernel(const float *raw, c
 }
 
 // ---------------------------------------------------------------------------
-// 6a. per-wave bucket counts of one half
+// 6a. digit counts per tile (and bucket totals) of one half
 // ---------------------------------------------------------------------------
-// Wave w of the half takes keys [w*chunk, min((w+1)*chunk, len)); counts go
-// to counts[w*B + b].
-__global__ __launch_bounds__(HNT) void learned_hist_kernel(const double *src, int64_t len, int64_t chunk,
-                                                           int64_t nwaves, const Feature *feat, const float *tab,
-                                                           int G, int B, unsigned *counts, const unsigned *ctrl)
+// Tiles are SW_TILE consecutive keys.  Every work-group takes tiles
+// [blockIdx.x, blockIdx.x + gridDim.x, ...), counts the digit (bucket id >>
+// shift, dbits bits) of each of its keys into tilecnt[d * ntiles + tile] and,
+// if totals is given, every bucket id into a work-group histogram that is
+// added into totals[] with integer atomics at the end (the totals do not
+// depend on the order of the additions).
+constexpr int SW_NT = 256;
+constexpr int SW_ROUNDS = 16;
+constexpr int SW_TILE = SW_NT * SW_ROUNDS;           // 4096 keys
+
+__global__ __launch_bounds__(SW_NT) void learned_count_kernel(const double *src, int64_t len, const Feature *feat,
+                                                              const float *tab, int G, int B, int shift, int dbits,
+                                                              unsigned *tilecnt, unsigned *totals,
+                                                              const unsigned *ctrl)
 {
     extern __shared__ unsigned char lds_raw[];
     float *s_tab = (float *)lds_raw;
-    unsigned *s_cnt = (unsigned *)(lds_raw + (size_t)(G + 1) * 4);
-    if (ctrl[L_FALLBACK]) return;
+    unsigned *s_tot = (unsigned *)(lds_raw + (size_t)(G + 1) * 4);
+    __shared__ unsigned s_dc[64];
+    if (ctrl[L_FALLBACK] || len <= 0) return;
     const Feature F = *feat;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i <= G; i += HNT) s_tab[i] = tab[i];
-    unsigned *mycnt = s_cnt + (size_t)wave * B;
-    for (int i = lane; i < B; i += 64) mycnt[i] = 0u;
-    __syncthreads();
-    const int64_t w = (int64_t)blockIdx.x * (HNT / 64) + wave;
-    if (w < nwaves) {
-        const int64_t c0 = w * chunk;
-        const int64_t c1 = c0 + chunk < len ? c0 + chunk : len;
-        for (int64_t base = c0; base < c1; base += 64 * HIPT) {
-            double x[HIPT];
+    const int tid = threadIdx.x;
+    const int D = 1 << dbits;
+    const int64_t ntiles = (len + SW_TILE - 1) / SW_TILE;
+    for (int i = tid; i <= G; i += SW_NT) s_tab[i] = tab[i];
+    if (totals)
+        for (int i = tid; i < B; i += SW_NT) s_tot[i] = 0u;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        if (tid < 64) s_dc[tid] = 0u;
+        __syncthreads();
+        const int64_t base = t * SW_TILE;
+        double x[SW_ROUNDS];
 #pragma unroll
-            for (int r = 0; r < HIPT; ++r) {
-                const int64_t i = base + r * 64 + lane;
-                x[r] = src[i < c1 ? i : c1 - 1];
-            }
+        for (int r = 0; r < SW_ROUNDS; ++r) {
+            const int64_t i = base + r * SW_NT + tid;
+            x[r] = src[i < len ? i : len - 1];
+        }
 #pragma unroll
-            for (int r = 0; r < HIPT; ++r) {
-                const int64_t i = base + r * 64 + lane;
-                if (i < c1) atomicAdd(&mycnt[bucket_of(x[r], F, s_tab, G, B)], 1u);
+        for (int r = 0; r < SW_ROUNDS; ++r) {
+            if (base + r * SW_NT + tid < len) {
+                const int b = bucket_of(x[r], F, s_tab, G, B);
+                atomicAdd(&s_dc[(b >> shift) & (D - 1)], 1u);
+                if (totals) atomicAdd(&s_tot[b], 1u);
             }
         }
+        __syncthreads();
+        if (tid < D) tilecnt[(int64_t)tid * ntiles + t] = s_dc[tid];
     }
-    __syncthreads();
-    if (w < nwaves)
-        for (int i = lane; i < B; i += 64) counts[w * B + i] = mycnt[i];
+    if (totals) {
+        __syncthreads();
+        for (int i = tid; i < B; i += SW_NT)
+            if (s_tot[i]) atomicAdd(&totals[i], s_tot[i]);
+    }
 }
 
-// ---------------------------------------------------------------------------
-// 6b. per bucket: exclusive prefix over waves (in place) and the total
-// ---------------------------------------------------------------------------
-// Work-group of 256 threads = 64 buckets x 4 quarters of the waves: each
-// thread sums its quarter, the quarters are prefixed in LDS, then each thread
-// rewrites its quarter as exclusive prefixes (all in wave order).
-__global__ __launch_bounds__(256) void learned_colscan_kernel(unsigned *counts, int64_t nwaves, int B,
-                                                              unsigned *totals, const unsigned *ctrl)
+// Per digit (one work-group each): tilecnt[d][t] becomes the destination of
+// tile t's first key of digit d: dstart[d] + the keys of digit d in tiles
+// before t (an exclusive scan over the tiles, in tile order).
+__global__ __launch_bounds__(1024) void learned_tilescan_kernel(unsigned *tilecnt, int64_t ntiles,
+                                                                const unsigned *dstart, const unsigned *ctrl)
 {
-    __shared__ unsigned s_q[4][64];
+    __shared__ unsigned s_part[1024];
     if (ctrl[L_FALLBACK]) return;
-    const int bl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int b = blockIdx.x * 64 + bl;
-    const int64_t per = (nwaves + 3) / 4;
-    const int64_t w0 = q * per, w1 = w0 + per < nwaves ? w0 + per : nwaves;
+    const int d = blockIdx.x, tid = threadIdx.x;
+    unsigned *col = tilecnt + (int64_t)d * ntiles;
+    const int64_t per = (ntiles + 1023) / 1024;
+    const int64_t t0 = tid * per, t1 = t0 + per < ntiles ? t0 + per : ntiles;
     unsigned acc = 0;
-    if (b < B) {
-#pragma unroll 8
-        for (int64_t w = w0; w < w1; ++w) acc += counts[w * B + b];
-    }
-    s_q[q][bl] = acc;
+    for (int64_t t = t0; t < t1; ++t) acc += col[t];
+    s_part[tid] = acc;
     __syncthreads();
-    unsigned run = 0;
-    for (int k = 0; k < q; ++k) run += s_q[k][bl];
-    if (b < B) {
-#pragma unroll 8
-        for (int64_t w = w0; w < w1; ++w) {
-            const unsigned c = counts[w * B + b];
-            counts[w * B + b] = run;
-            run += c;
-        }
-        if (q == 3) totals[b] = run;
+    for (int o = 1; o < 1024; o <<= 1) {
+        const unsigned v = tid >= o ? s_part[tid - o] : 0u;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    unsigned run = dstart[d] + s_part[tid] - acc;
+    for (int64_t t = t0; t < t1; ++t) {
+        const unsigned c = col[t];
+        col[t] = run;
+        run += c;
     }
 }
 
 // Bucket starts (exclusive scan of totals) of both halves, the segment
-// offsets for the bucket sorts, the largest bucket and the overflow decision.
-__global__ __launch_bounds__(1024) void learned_bucket_scan_kernel(const unsigned *totals, int B, int halves,
-                                                                   unsigned *starts, int64_t *offsets,
-                                                                   int64_t limit, unsigned *ctrl)
+// offsets for the bucket sorts, the digit starts of the two distribution
+// passes, the largest bucket and the overflow decision.  A bucket id is
+// (high digit << lbits) | low digit.
+__global__ __launch_bounds__(1024) void learned_bucket_scan_kernel(const unsigned *totals, int B, int lbits,
+                                                                   int halves, unsigned *starts, int64_t *offsets,
+                                                                   unsigned *dstart, int64_t limit, unsigned *ctrl)
 {
     __shared__ int64_t s_part[1024];
     __shared__ unsigned s_max, s_over, s_big;
+    __shared__ unsigned s_low[64];
     if (ctrl[L_FALLBACK]) return;
     const int tid = threadIdx.x;
+    const int DL = 1 << lbits, DH = B >> lbits;
     if (tid == 0) s_max = s_over = s_big = 0u;
     __syncthreads();
     for (int h = 0; h < halves; ++h) {
@@ -394,6 +416,22 @@ __global__ __launch_bounds__(1024) void learned_bucket_scan_kernel(const unsigne
             run += tt[b];
         }
         if (tid == 1023) offsets[(size_t)h * (B + 1) + B] = s_part[1023];
+        // keys per low digit, in bucket order within each digit
+        if (tid < DL) {
+            unsigned c = 0;
+            for (int d1 = 0; d1 < DH; ++d1) c += tt[(d1 << lbits) | tid];
+            s_low[tid] = c;
+        }
+        __syncthreads();
+        unsigned *ds = dstart + (size_t)h * 128;
+        if (tid == 0) {
+            unsigned r = 0;
+            for (int d = 0; d < DL; ++d) {
+                ds[d] = r;                                  // pass 1: by low digit
+                r += s_low[d];
+            }
+        }
+        if (tid < DH) ds[64 + tid] = starts[(size_t)h * B + (tid << lbits)];   // pass 2: by high digit
         __syncthreads();
     }
     if (tid == 0) {
@@ -405,64 +443,127 @@ __global__ __launch_bounds__(1024) void learned_bucket_scan_kernel(const unsigne
 }
 
 // ---------------------------------------------------------------------------
-// 6c. stable ranked scatter of one half
+// 6b. one stable distribution pass by a digit of the bucket id
 // ---------------------------------------------------------------------------
-// Each wave walks its chunk in input order, 64 keys per step.  Lanes holding
-// the same bucket find each other with one ballot per bucket bit; a lane's
-// rank among them plus the wave's running count for the bucket (kept in LDS,
-// started at the bucket start plus the counts of all earlier waves) is its
-// destination, so equal buckets keep input order.
-__global__ __launch_bounds__(HNT) void learned_scatter_kernel(const double *src, int64_t len, int64_t chunk,
-                                                              int64_t nwaves, const Feature *feat,
-                                                              const float *tab, int G, int B, int bbits,
-                                                              const unsigned *counts, const unsigned *starts,
-                                                              double *dst, const unsigned *ctrl)
+// One tile per work-group.  Wave w ranks its 1024 keys (16 rounds of 64 in
+// input order): all digits first, equal digits of a round finding each other
+// with one ballot per digit bit; the group leaders record per-round digit
+// counts, lane d turns the counts of digit d into prefixes over the rounds,
+// and a key's rank is its round's prefix plus its place among its round's
+// equals.  The tile then stages its keys in LDS grouped by digit and writes
+// every digit's run contiguously at the tile's offset for that digit (from
+// the tile scan).  The rank scratch shares LDS with the staging area.
+__global__ __launch_bounds__(SW_NT) void learned_scatter_kernel(const double *src, double *dst, int64_t len,
+                                                                const Feature *feat, const float *tab, int G, int B,
+                                                                int shift, int dbits, const unsigned *tileoff,
+                                                                const unsigned *ctrl)
 {
     extern __shared__ unsigned char lds_raw[];
     float *s_tab = (float *)lds_raw;
-    unsigned *s_cnt = (unsigned *)(lds_raw + (size_t)(G + 1) * 4);
-    if (ctrl[L_FALLBACK]) return;
+    double *s_key = (double *)(lds_raw + (((size_t)(G + 1) * 4 + 15) & ~(size_t)15));
+    unsigned char *s_dig = (unsigned char *)(s_key + SW_TILE);
+    __shared__ unsigned s_wcnt[SW_NT / 64][64];
+    __shared__ unsigned s_toff[64];
+    __shared__ unsigned s_goff[64];
+    if (ctrl[L_FALLBACK] || len <= 0) return;
     const Feature F = *feat;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i <= G; i += HNT) s_tab[i] = tab[i];
-    const int64_t w = (int64_t)blockIdx.x * (HNT / 64) + wave;
-    unsigned *mycnt = s_cnt + (size_t)wave * B;
-    if (w < nwaves)
-        for (int i = lane; i < B; i += 64) mycnt[i] = counts[w * B + i] + starts[i];
-    __syncthreads();
-    if (w >= nwaves) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int D = 1 << dbits;
+    const int64_t ntiles = (len + SW_TILE - 1) / SW_TILE;
+    // this wave's [round][digit] scratch: lane masks, then prefixes
+    unsigned long long *wm = (unsigned long long *)s_key + wave * (SW_ROUNDS * 64);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t c0 = w * chunk;
-    const int64_t c1 = c0 + chunk < len ? c0 + chunk : len;
-    for (int64_t base = c0; base < c1; base += 64 * HIPT) {
-        double x[HIPT];
+    for (int i = tid; i <= G; i += SW_NT) s_tab[i] = tab[i];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t base = t * SW_TILE + (int64_t)wave * (SW_TILE / 4);
+        double x[SW_ROUNDS];
 #pragma unroll
-        for (int r = 0; r < HIPT; ++r) {
-            const int64_t i = base + r * 64 + lane;
-            x[r] = src[i < c1 ? i : c1 - 1];
+        for (int r = 0; r < SW_ROUNDS; ++r) {
+            const int64_t p = base + r * 64 + lane;
+            x[r] = src[p < len ? p : len - 1];
         }
 #pragma unroll
-        for (int r = 0; r < HIPT; ++r) {
-            const int64_t i = base + r * 64 + lane;
-            const bool valid = i < c1;
-            const int b = valid ? bucket_of(x[r], F, s_tab, G, B) : B;   // B: no bucket
-            uint64_t peers = __ballot(valid);
-            for (int k = 0; k < bbits + 1; ++k) {
-                const uint64_t m = __ballot((b >> k) & 1);
-                peers &= ((b >> k) & 1) ? m : ~m;
+        for (int r = 0; r < SW_ROUNDS; ++r) wm[r * 64 + lane] = 0ull;
+        if (tid < D) s_goff[tid] = tileoff[(int64_t)tid * ntiles + t];
+        __syncthreads();
+        int dg[SW_ROUNDS];
+#pragma unroll
+        for (int r = 0; r < SW_ROUNDS; ++r) {
+            const bool valid = base + r * 64 + lane < len;
+            dg[r] = valid ? ((bucket_of(x[r], F, s_tab, G, B) >> shift) & (D - 1)) : -1;
+        }
+        // lanes of a round with equal digits: each sets its bit in the digit's
+        // mask (bitwise or, so the order of the updates does not matter)
+#pragma unroll
+        for (int r = 0; r < SW_ROUNDS; ++r)
+            if (dg[r] >= 0) atomicOr(&wm[r * 64 + dg[r]], 1ull << lane);
+        __builtin_amdgcn_wave_barrier();
+        unsigned rk[SW_ROUNDS];
+#pragma unroll
+        for (int r = 0; r < SW_ROUNDS; ++r)
+            rk[r] = dg[r] >= 0 ? (unsigned)__popcll(wm[r * 64 + dg[r]] & below) : 0u;
+        unsigned cnt[SW_ROUNDS];
+#pragma unroll
+        for (int r = 0; r < SW_ROUNDS; ++r) cnt[r] = (unsigned)__popcll(wm[r * 64 + lane]);   // lane = digit
+        __builtin_amdgcn_wave_barrier();
+        {
+            unsigned run = 0;
+#pragma unroll
+            for (int r = 0; r < SW_ROUNDS; ++r) {
+                wm[r * 64 + lane] = run;                    // keys of digit `lane` in earlier rounds
+                run += cnt[r];
             }
-            const int rank = __popcll(peers & below);
-            const int cnt = __popcll(peers);
-            unsigned pos = 0;
-            if (valid) pos = mycnt[b];
-            // every lane has read its count before any leader writes
-            __builtin_amdgcn_wave_barrier();
-            if (valid && rank == 0) mycnt[b] = pos + (unsigned)cnt;
-            __builtin_amdgcn_wave_barrier();
-            const int64_t d = (int64_t)pos + rank;
-            if (valid && d < len) dst[d] = x[r];
+            s_wcnt[wave][lane] = run;
         }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int r = 0; r < SW_ROUNDS; ++r)
+            if (dg[r] >= 0) rk[r] += (unsigned)wm[r * 64 + dg[r]];
+        __syncthreads();
+        if (tid < 64) {
+            const int d = tid;
+            unsigned run = 0;
+            for (int w = 0; w < SW_NT / 64; ++w) {          // wave offsets per digit
+                const unsigned v = s_wcnt[w][d];
+                s_wcnt[w][d] = run;
+                run += v;
+            }
+            // tile-local start of every digit: exclusive scan over the digits
+            unsigned inc = run;
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned v = __shfl_up(inc, o);
+                if (lane >= o) inc += v;
+            }
+            s_toff[d] = inc - run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SW_ROUNDS; ++r) {
+            if (dg[r] >= 0) {
+                const unsigned pos = s_toff[dg[r]] + s_wcnt[wave][dg[r]] + rk[r];
+                s_key[pos] = x[r];
+                s_dig[pos] = (unsigned char)dg[r];
+            }
+        }
+        __syncthreads();
+        const int64_t rem = len - t * SW_TILE;
+        const int nvalid = rem < SW_TILE ? (int)rem : SW_TILE;
+        for (int i = tid; i < nvalid; i += SW_NT) {
+            const int d = s_dig[i];
+            const int64_t g = (int64_t)s_goff[d] + (i - (int)s_toff[d]);
+            if ((uint64_t)g < (uint64_t)len) dst[g] = s_key[i];
+        }
+        __syncthreads();                                    // LDS free for the next tile
     }
+}
+
+// gated copy (the sorted first half into the half buffer for the final merge)
+__global__ __launch_bounds__(256) void learned_copy_kernel(const double *src, double *dst, int64_t n,
+                                                           const unsigned *ctrl)
+{
+    if (ctrl[L_FALLBACK]) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -483,11 +584,8 @@ LearnedPlan plan_learned(int64_t n, const gs_learned_params &prm)
     L.plain = plan_f64(n);
     // half buffer with one extra slot (the second half has ceil(n/2) keys)
     const int64_t hb = al256((n / 2 + 1) * 8);
-    const int64_t shift = hb - L.plain.off_tickets;
-    L.plain.off_tickets += shift;
-    L.plain.off_status += shift;
-    L.plain.off_splits += shift;
-    L.plain.off_deps += shift;
+    const int64_t shift = hb - L.plain.off_forest;
+    L.plain.off_forest += shift;
     L.plain.bytes += shift;
     int64_t o = al256(L.plain.bytes);
     if (!L.use_learned) {
@@ -495,10 +593,8 @@ LearnedPlan plan_learned(int64_t n, const gs_learned_params &prm)
         return L;
     }
     const int64_t half = n - n / 2;
-    L.nwaves = (half + (1 << 14) - 1) >> 14;      // chunks of >= 2^14 keys per wave
-    if (L.nwaves < 1) L.nwaves = 1;
-    if (L.nwaves > 2048) L.nwaves = 2048;
-    L.chunk = (half + L.nwaves - 1) / L.nwaves;
+    L.limit = half / 4 > kBucketLimit ? half / 4 : kBucketLimit;
+    L.ntiles = (half + 4095) / 4096;
     L.splan = plan_f64(L.S);
     L.off_sample = o; o = al256(o + L.S * 8);
     L.off_sample_ws = o; o = al256(o + L.splan.bytes);
@@ -514,12 +610,15 @@ LearnedPlan plan_learned(int64_t n, const gs_learned_params &prm)
     L.off_losses = o; o = al256(o + 2 * 4);
     L.off_raw = o; o = al256(o + (int64_t)(L.G + 1) * 4);
     L.off_tab = o; o = al256(o + (int64_t)(L.G + 1) * 4);
-    L.off_counts = o; o = al256(o + 2 * L.nwaves * L.B * 4);
     L.off_totals = o; o = al256(o + 2 * (int64_t)L.B * 4);
     L.off_starts = o; o = al256(o + 2 * (int64_t)L.B * 4);
     L.off_offsets = o; o = al256(o + 2 * (int64_t)(L.B + 1) * 8);
+    L.off_dstart = o; o = al256(o + 2 * 128 * 4);
+    L.off_tilecnt = o; o = al256(o + 2 * L.ntiles * 64 * 4);
     L.off_segctrl = o; o = al256(o + 2 * 64 * 4);
     L.off_seglists = o; o = al256(o + 2 * 3 * (int64_t)L.B * 4);
+    L.segforest = plan_forest_seg(half, half < L.limit ? half : L.limit, L.B);
+    L.off_segforest = o; o = al256(o + L.segforest.bytes);
     L.bytes = o;
     return L;
 }
@@ -540,9 +639,6 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     float *m = (float *)(ws + L.off_m), *v = (float *)(ws + L.off_v);
     float *partial = (float *)(ws + L.off_partial), *losses = (float *)(ws + L.off_losses);
     float *raw = (float *)(ws + L.off_raw), *tab = (float *)(ws + L.off_tab);
-    unsigned *counts = (unsigned *)(ws + L.off_counts);
-    unsigned *totals = (unsigned *)(ws + L.off_totals);
-    unsigned *starts = (unsigned *)(ws + L.off_starts);
     int64_t *offsets = (int64_t *)(ws + L.off_offsets);
     unsigned *segctrl = (unsigned *)(ws + L.off_segctrl);
     int *seglists = (int *)(ws + L.off_seglists);
@@ -561,8 +657,8 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     hipError_t e = sort_f64_async(sample, L.S, ws + L.off_sample_ws, L.splan, st);
     if (e != hipSuccess) return e;
     if (tr) trace_begin(TK_LEARN_PREP, st);
-    hipLaunchKernelGGL(learned_prep_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample, L.S, feat, u, t,
-                       ctrl);
+    hipLaunchKernelGGL(learned_prep_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample, L.S, G, feat, u,
+                       t, ctrl);
     if (tr) trace_end(st);
 
     // 3-4. network and knot table
@@ -587,61 +683,85 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     hipLaunchKernelGGL(learned_table_kernel, dim3(1), dim3(1024), 0, st, (const float *)raw, prm.test_bucket_table,
                        (int)prm.mode, G, tab, ctrl, (const Feature *)feat);
 
-    // 6a-b. counts of both halves before anything moves
+    // 6. bucket totals of both halves (and the first pass's tile counts)
+    //    before anything moves
     const int64_t nA = n / 2, nB = n - nA;                 // first and second half
-    const size_t lds = (size_t)(G + 1) * 4 + (size_t)(HNT / 64) * B * 4;
-    (void)hipFuncSetAttribute((const void *)learned_hist_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
+    const int lbits = bbits / 2, hbits = bbits - lbits;    // bucket id = (high << lbits) | low
+    const int64_t tA = (nA + SW_TILE - 1) / SW_TILE, tB = (nB + SW_TILE - 1) / SW_TILE;
+    unsigned *totals = (unsigned *)(ws + L.off_totals);
+    unsigned *starts = (unsigned *)(ws + L.off_starts);
+    unsigned *dstart = (unsigned *)(ws + L.off_dstart);
+    unsigned *cntA = (unsigned *)(ws + L.off_tilecnt);
+    unsigned *cntB = cntA + 64 * tA;
+    const size_t clds = (size_t)(G + 1) * 4 + (size_t)B * 4;
+    const size_t slds = (((size_t)(G + 1) * 4 + 15) & ~(size_t)15) + (size_t)SW_TILE * 9;
+    (void)hipFuncSetAttribute((const void *)learned_count_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)clds);
     (void)hipFuncSetAttribute((const void *)learned_scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    const unsigned hgrid = (unsigned)((L.nwaves + (HNT / 64) - 1) / (HNT / 64));
-    const int64_t chunkA = (nA + L.nwaves - 1) / L.nwaves;
-    const int64_t chunkB = (nB + L.nwaves - 1) / L.nwaves;
-    unsigned *countsA = counts, *countsB = counts + L.nwaves * B;
+                              (int)slds);
+    const unsigned cgrid = 1024;
     if (tr) trace_begin(TK_LEARN_BUCKET, st);
-    hipLaunchKernelGGL(learned_hist_kernel, dim3(hgrid), dim3(HNT), lds, st, (const double *)keys, nA, chunkA,
-                       L.nwaves, (const Feature *)feat, (const float *)tab, G, B, countsA, (const unsigned *)ctrl);
-    hipLaunchKernelGGL(learned_hist_kernel, dim3(hgrid), dim3(HNT), lds, st, (const double *)(keys + nA), nB,
-                       chunkB, L.nwaves, (const Feature *)feat, (const float *)tab, G, B, countsB,
+    launch_fill_u32(totals, 2 * (int64_t)B, 0u, st);
+    hipLaunchKernelGGL(learned_count_kernel, dim3(cgrid), dim3(SW_NT), clds, st, (const double *)keys, nA,
+                       (const Feature *)feat, (const float *)tab, G, B, 0, lbits, cntA, totals,
                        (const unsigned *)ctrl);
-    hipLaunchKernelGGL(learned_colscan_kernel, dim3((unsigned)((B + 63) / 64)), dim3(256), 0, st, countsA,
-                       L.nwaves, B, totals, (const unsigned *)ctrl);
-    hipLaunchKernelGGL(learned_colscan_kernel, dim3((unsigned)((B + 63) / 64)), dim3(256), 0, st, countsB,
-                       L.nwaves, B, totals + B, (const unsigned *)ctrl);
-    const int64_t limit = (int64_t)1 << 20;
-    hipLaunchKernelGGL(learned_bucket_scan_kernel, dim3(1), dim3(1024), 0, st, (const unsigned *)totals, B, 2,
-                       starts, offsets, limit, ctrl);
+    hipLaunchKernelGGL(learned_count_kernel, dim3(cgrid), dim3(SW_NT), clds, st, (const double *)(keys + nA), nB,
+                       (const Feature *)feat, (const float *)tab, G, B, 0, lbits, cntB, totals + B,
+                       (const unsigned *)ctrl);
+    hipLaunchKernelGGL(learned_bucket_scan_kernel, dim3(1), dim3(1024), 0, st, (const unsigned *)totals, B, lbits,
+                       2, starts, offsets, dstart, L.limit, ctrl);
     if (tr) trace_end(st);
 
-    // 6c. second half -> half buffer, sorted there with its vacated region as scratch
+    // 7. each half: two stable distribution passes (low digit into the half
+    //    buffer, high digit back), which leave its keys grouped by bucket in
+    //    input order in place; then every bucket sorted, with the half buffer
+    //    as frog buffer.  Second half first, then the first.
+    auto distribute = [&](double *region, int64_t len, int64_t ntiles, unsigned *cnt, int h) {
+        if (ntiles == 0) return;
+        const unsigned sgrid = (unsigned)(ntiles < 1024 ? ntiles : 1024);
+        hipLaunchKernelGGL(learned_tilescan_kernel, dim3(1u << lbits), dim3(1024), 0, st, cnt, ntiles,
+                           (const unsigned *)(dstart + h * 128), (const unsigned *)ctrl);
+        hipLaunchKernelGGL(learned_scatter_kernel, dim3(sgrid), dim3(SW_NT), slds, st,
+                           (const double *)region, H, len, (const Feature *)feat, (const float *)tab, G, B, 0, lbits,
+                           (const unsigned *)cnt, (const unsigned *)ctrl);
+        hipLaunchKernelGGL(learned_count_kernel, dim3(cgrid), dim3(SW_NT), clds, st, (const double *)H, len,
+                           (const Feature *)feat, (const float *)tab, G, B, lbits, hbits, cnt, (unsigned *)nullptr,
+                           (const unsigned *)ctrl);
+        hipLaunchKernelGGL(learned_tilescan_kernel, dim3(1u << hbits), dim3(1024), 0, st, cnt, ntiles,
+                           (const unsigned *)(dstart + h * 128 + 64), (const unsigned *)ctrl);
+        hipLaunchKernelGGL(learned_scatter_kernel, dim3(sgrid), dim3(SW_NT), slds, st, (const double *)H,
+                           region, len, (const Feature *)feat, (const float *)tab, G, B, lbits, hbits,
+                           (const unsigned *)cnt, (const unsigned *)ctrl);
+    };
     if (tr) trace_begin(TK_LEARN_BUCKET, st);
-    hipLaunchKernelGGL(learned_scatter_kernel, dim3(hgrid), dim3(HNT), lds, st, (const double *)(keys + nA), nB,
-                       chunkB, L.nwaves, (const Feature *)feat, (const float *)tab, G, B, bbits,
-                       (const unsigned *)countsB, (const unsigned *)(starts + B), H, (const unsigned *)ctrl);
+    distribute(keys + nA, nB, tB, cntB, 1);
     if (tr) trace_end(st);
-    e = segsort_core_async(H, offsets + (B + 1), B, nB, keys + nA, segctrl + 64, seglists + 3 * B,
-                           seglists + 4 * B, seglists + 5 * B, ctrl + L_FALLBACK, 0u, st);
-    if (e != hipSuccess) return e;
-    // first half -> the top nA slots of the vacated second-half region
-    if (tr) trace_begin(TK_LEARN_BUCKET, st);
-    hipLaunchKernelGGL(learned_scatter_kernel, dim3(hgrid), dim3(HNT), lds, st, (const double *)keys, nA, chunkA,
-                       L.nwaves, (const Feature *)feat, (const float *)tab, G, B, bbits, (const unsigned *)countsA,
-                       (const unsigned *)starts, keys + nB, (const unsigned *)ctrl);
-    if (tr) trace_end(st);
-    e = segsort_core_async(keys + nB, offsets, B, nA, keys, segctrl, seglists, seglists + B, seglists + 2 * B,
+    e = segsort_core_async(keys + nA, offsets + (B + 1), B, nB, H, segctrl + 64, seglists + 3 * B,
+                           seglists + 4 * B, seglists + 5 * B, ws + L.off_segforest, L.segforest,
                            ctrl + L_FALLBACK, 0u, st);
     if (e != hipSuccess) return e;
+    if (tr) trace_begin(TK_LEARN_BUCKET, st);
+    distribute(keys, nA, tA, cntA, 0);
+    if (tr) trace_end(st);
+    e = segsort_core_async(keys, offsets, B, nA, H, segctrl, seglists, seglists + B, seglists + 2 * B,
+                           ws + L.off_segforest, L.segforest, ctrl + L_FALLBACK, 0u, st);
+    if (e != hipSuccess) return e;
 
-    // 7. merge: first run (sorted first half) at [nB, n), second run in the
-    //    half buffer (logical [n, n+nB)), output [0, n) written bottom-up
+    // 8. merge: the sorted first half moves to the half buffer (logical
+    //    [n, n+nA)); the second run stays at [nA, n) inside the output [0, n),
+    //    which is written bottom-up
+    if (tr) trace_begin(TK_LEARN_BUCKET, st);
+    hipLaunchKernelGGL(learned_copy_kernel, dim3(2048), dim3(256), 0, st, (const double *)keys, H, nA,
+                       (const unsigned *)ctrl);
+    if (tr) trace_end(st);
     FrogMerge fm{};
-    fm.l0 = nB;
+    fm.l0 = n;
     fm.nl = nA;
-    fm.r0 = n;
+    fm.r0 = nA;
     fm.nr = nB;
     fm.out0 = 0;
     fm.left = 0;
-    fm.outer = 2;
+    fm.outer = 1;
     e = merge_one_f64_async(keys, H, n, fm, ws, L.plain, st, ctrl + L_FALLBACK, 0u);
     if (e != hipSuccess) return e;
 

@@ -33,10 +33,12 @@ constexpr int RS = HID + 1;             // padded LDS row stride (no bank confli
 struct TrainLds {
     float p[kMlpParams + 3];
     float g[kMlpParams + 3];
+    float w2[HID * RS];                 // W2 with padded rows
     float u[SPW], t[SPW], dy[SPW], y[SPW];
     float z1[SPW * RS], h1[SPW * RS];
     float z2[SPW * RS], h2[SPW * RS];
     float g2[SPW * RS], g1[SPW * RS];
+    float red[TR_NT / 64][64];
     float loss;
 };
 
@@ -50,30 +52,53 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
 }
 
 // Partial loss (sum of squared errors) and gradient (sums over this group's
-// `ns` samples, in sample order) into L.g / L.loss.  inv_batch = 1 / total
-// batch over all work-groups.
-__device__ void wg_loss_grad(TrainLds &L, int ns, float inv_batch)
+// SPW samples) into L.g / L.loss; L.p holds the parameters, L.u / L.t the
+// samples.  inv_batch = 1 / total batch over all work-groups.  Each thread
+// computes a small block of outputs with its operands in registers; every
+// sum runs over its index in increasing order.
+__device__ void wg_loss_grad(TrainLds &L, float inv_batch)
 {
+    static_assert(TR_NT == 256 && SPW == 32 && HID == 64, "thread blocking below");
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < ns * HID; idx += TR_NT) {
+    for (int k = tid; k < HID * HID; k += TR_NT) L.w2[(k >> 6) * RS + (k & 63)] = L.p[OW2 + k];
+    for (int idx = tid; idx < SPW * HID; idx += TR_NT) {
         const int s = idx / HID, j = idx % HID;
         const float z = fmaf(L.p[OW1 + j], L.u[s], L.p[OB1 + j]);
         L.z1[s * RS + j] = z;
         L.h1[s * RS + j] = z > 0.f ? z : 0.f;
     }
     __syncthreads();
-    // hidden layer 2: lanes share the W2 row (broadcast) and read distinct h1 rows
-    for (int idx = tid; idx < ns * HID; idx += TR_NT) {
-        const int i = idx / ns, s = idx % ns;
-        float a = L.p[OB2 + i];
-        for (int j = 0; j < HID; ++j) a = fmaf(L.p[OW2 + i * HID + j], L.h1[s * RS + j], a);
-        L.z2[s * RS + i] = a;
-        L.h2[s * RS + i] = a > 0.f ? a : 0.f;
+    // hidden layer 2: thread block of 2 samples x 4 units
+    {
+        const int s0 = 2 * (tid & 15), i0 = 4 * (tid >> 4);
+        float acc[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] = L.p[OB2 + i0 + c];
+#pragma unroll 8
+        for (int j = 0; j < HID; ++j) {
+            const float h0 = L.h1[s0 * RS + j], h1v = L.h1[(s0 + 1) * RS + j];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float w = L.w2[(i0 + c) * RS + j];
+                acc[0][c] = fmaf(w, h0, acc[0][c]);
+                acc[1][c] = fmaf(w, h1v, acc[1][c]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                L.z2[(s0 + a) * RS + i0 + c] = acc[a][c];
+                L.h2[(s0 + a) * RS + i0 + c] = acc[a][c] > 0.f ? acc[a][c] : 0.f;
+            }
     }
     __syncthreads();
-    if (tid < ns) {
+    if (tid < SPW) {
         const int s = tid;
         float y = L.p[OB3];
+#pragma unroll 16
         for (int i = 0; i < HID; ++i) y = fmaf(L.p[OW3 + i], L.h2[s * RS + i], y);
         const float r = y - L.t[s];
         L.y[s] = r * r;
@@ -82,32 +107,70 @@ __device__ void wg_loss_grad(TrainLds &L, int ns, float inv_batch)
     __syncthreads();
     if (tid == 0) {
         float acc = 0.f;
-        for (int s = 0; s < ns; ++s) acc += L.y[s];
+        for (int s = 0; s < SPW; ++s) acc += L.y[s];
         L.loss = acc;
     }
-    for (int idx = tid; idx < ns * HID; idx += TR_NT) {
+    for (int idx = tid; idx < SPW * HID; idx += TR_NT) {
         const int s = idx / HID, i = idx % HID;
         L.g2[s * RS + i] = L.z2[s * RS + i] > 0.f ? L.dy[s] * L.p[OW3 + i] : 0.f;
     }
     __syncthreads();
-    // dW2[i][j] = sum_s g2[s][i] h1[s][j]
-    for (int idx = tid; idx < HID * HID; idx += TR_NT) {
-        const int i = idx / HID, j = idx % HID;
-        float a = 0.f;
-        for (int s = 0; s < ns; ++s) a = fmaf(L.g2[s * RS + i], L.h1[s * RS + j], a);
-        L.g[OW2 + idx] = a;
+    // dW2[i][j] = sum_s g2[s][i] h1[s][j]: thread block of 4 x 4
+    {
+        const int i0 = 4 * (tid >> 4), j0 = 4 * (tid & 15);
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] = 0.f;
+#pragma unroll 8
+        for (int s = 0; s < SPW; ++s) {
+            float gv[4], hv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) gv[a] = L.g2[s * RS + i0 + a];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) hv[c] = L.h1[s * RS + j0 + c];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(gv[a], hv[c], acc[a][c]);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) L.g[OW2 + (i0 + a) * HID + j0 + c] = acc[a][c];
     }
-    // g1[s][j] = [z1 > 0] sum_i W2[i][j] g2[s][i]
-    for (int idx = tid; idx < ns * HID; idx += TR_NT) {
-        const int s = idx / HID, j = idx % HID;
-        float a = 0.f;
-        for (int i = 0; i < HID; ++i) a = fmaf(L.p[OW2 + i * HID + j], L.g2[s * RS + i], a);
-        L.g1[s * RS + j] = L.z1[s * RS + j] > 0.f ? a : 0.f;
+    // g1[s][j] = [z1 > 0] sum_i W2[i][j] g2[s][i]: thread block of 2 x 4
+    {
+        const int s0 = 2 * (tid & 15), j0 = 4 * (tid >> 4);
+        float acc[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] = 0.f;
+#pragma unroll 8
+        for (int i = 0; i < HID; ++i) {
+            const float g0 = L.g2[s0 * RS + i], g1v = L.g2[(s0 + 1) * RS + i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float w = L.w2[i * RS + j0 + c];
+                acc[0][c] = fmaf(w, g0, acc[0][c]);
+                acc[1][c] = fmaf(w, g1v, acc[1][c]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int o = (s0 + a) * RS + j0 + c;
+                L.g1[o] = L.z1[o] > 0.f ? acc[a][c] : 0.f;
+            }
     }
     if (tid < HID) {
         const int i = tid;
         float db2 = 0.f, dw3 = 0.f;
-        for (int s = 0; s < ns; ++s) {
+#pragma unroll 8
+        for (int s = 0; s < SPW; ++s) {
             db2 += L.g2[s * RS + i];
             dw3 = fmaf(L.dy[s], L.h2[s * RS + i], dw3);
         }
@@ -116,14 +179,15 @@ __device__ void wg_loss_grad(TrainLds &L, int ns, float inv_batch)
     }
     if (tid == HID) {
         float db3 = 0.f;
-        for (int s = 0; s < ns; ++s) db3 += L.dy[s];
+        for (int s = 0; s < SPW; ++s) db3 += L.dy[s];
         L.g[OB3] = db3;
     }
     __syncthreads();
     if (tid < HID) {
         const int j = tid;
         float dw1 = 0.f, db1 = 0.f;
-        for (int s = 0; s < ns; ++s) {
+#pragma unroll 8
+        for (int s = 0; s < SPW; ++s) {
             dw1 = fmaf(L.g1[s * RS + j], L.u[s], dw1);
             db1 += L.g1[s * RS + j];
         }
@@ -223,23 +287,46 @@ __global__ __launch_bounds__(TR_NT) void mlp_train_kernel(float *params, float *
             L.t[tid] = st[idx];
         }
         __syncthreads();
-        wg_loss_grad(L, SPW, inv_batch);
+        wg_loss_grad(L, inv_batch);
         float *pw = partial + (size_t)wg * (kMlpParams + 1);
         for (int k = tid; k < kMlpParams; k += TR_NT) pw[k] = L.g[k];
         if (tid == 0) pw[kMlpParams] = L.loss;
         grid_barrier(bar, nwg, gen, err);
 
-        // reduce this group's parameter slice over all groups, in group order
+        // reduce this group's parameter slice over all groups: lane k of
+        // quarter q sums the partials of groups [q*nq, (q+1)*nq) in group
+        // order, then the four quarter sums are added in quarter order (a
+        // fixed order either way, so the result is reproducible)
         const float c1 = 1.f - powf(b1, (float)(step + 1));
         const float c2 = 1.f - powf(b2, (float)(step + 1));
-        for (int k = p0 + tid; k < p1; k += TR_NT) {
+        const int q = tid >> 6, kl = tid & 63;
+        const int nq = ((int)nwg + 3) / 4;
+        const int w0 = q * nq, w1 = min(w0 + nq, (int)nwg);
+        for (int kb = p0; kb < p1; kb += 64) {
+            const int k = kb + kl;
             float g = 0.f;
-            for (unsigned w = 0; w < nwg; ++w) g += partial[(size_t)w * (kMlpParams + 1) + k];
-            const float m = b1 * adam_m[k] + (1.f - b1) * g;
-            const float v = b2 * adam_v[k] + (1.f - b2) * g * g;
-            adam_m[k] = m;
-            adam_v[k] = v;
-            params[k] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+            if (k < p1) {
+                int w = w0;
+                for (; w + 8 <= w1; w += 8) {
+                    float v8[8];
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) v8[r] = partial[(size_t)(w + r) * (kMlpParams + 1) + k];
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) g += v8[r];
+                }
+                for (; w < w1; ++w) g += partial[(size_t)w * (kMlpParams + 1) + k];
+            }
+            L.red[q][kl] = g;
+            __syncthreads();
+            if (q == 0 && k < p1) {
+                const float gs = ((L.red[0][kl] + L.red[1][kl]) + L.red[2][kl]) + L.red[3][kl];
+                const float m = b1 * adam_m[k] + (1.f - b1) * gs;
+                const float v = b2 * adam_v[k] + (1.f - b2) * gs * gs;
+                adam_m[k] = m;
+                adam_v[k] = v;
+                params[k] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+            }
+            __syncthreads();
         }
         if (wg == 0 && tid == 0 && losses && (step == 0 || step == steps - 1)) {
             float l = 0.f;
@@ -265,7 +352,7 @@ __global__ __launch_bounds__(TR_NT) void mlp_grad_partial_kernel(const float *pa
         L.t[tid] = t[wg * SPW + tid];
     }
     __syncthreads();
-    wg_loss_grad(L, SPW, 1.f / (float)batch);
+    wg_loss_grad(L, 1.f / (float)batch);
     float *pw = partial + (size_t)wg * (kMlpParams + 1);
     for (int k = tid; k < kMlpParams; k += TR_NT) pw[k] = L.g[k];
     if (tid == 0) pw[kMlpParams] = L.loss;

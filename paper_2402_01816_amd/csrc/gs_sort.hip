@@ -36,16 +36,17 @@ void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st)
 // ---------------------------------------------------------------------------
 // leaf kernel: sort each leaf's input chunk and place it at its frog slot
 // ---------------------------------------------------------------------------
-// Leaf i takes the i-th contiguous chunk of the input (the order the setup
-// recursion visits elements) and leaves it sorted at its data start, which is
-// never before its input offset.  A leaf's output can therefore only cover
-// input chunks of leaves with a larger index: leaves take tickets in
+// Leaf i of a problem takes the i-th contiguous chunk of its input (the order
+// the setup recursion visits elements) and leaves it sorted at its data start,
+// which is never before its input offset.  A leaf's output can therefore only
+// cover input chunks of leaves with a larger index: leaves take tickets in
 // descending index order, and each waits for the leaves whose chunks its
-// output covers.
-template <class KT, class V, int NT, int IPT>
-__global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Space<V> vals,
-                                                  int64_t n_total, int depth, int64_t nleaves,
-                                                  unsigned *ticket_ctr, unsigned *status,
+// output covers.  With LOOP, persistent work-groups take tickets until the
+// round is done (a problem table, whose leaf count only the device knows);
+// without, every work-group takes one ticket (grid = leaves).
+template <class KT, class V, int NT, int IPT, int WAVES, bool LOOP>
+__global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv,
+                                                  Forest F, unsigned *ticket_ctr, unsigned *status,
                                                   unsigned epoch, unsigned *err, Gate gate)
 {
     using K = typename KT::T;
@@ -60,101 +61,220 @@ __global__ __launch_bounds__(NT) void leaf_kernel(Space<typename KT::T> keys, Sp
     if (gate.closed()) return;
 
     const int tid = threadIdx.x;
-    if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
-    __syncthreads();
-    const int64_t t = __builtin_amdgcn_readfirstlane(s_ticket);
-    const int64_t leaf = nleaves - 1 - t;
-    const FrogNode f = frog_node(n_total, depth, leaf);
-    const int len = (int)f.n;
-    const int64_t src = f.in_off;
-    const int64_t dst = frog_data_start(f);
+    const int64_t L = F.probs ? (int64_t)*F.nprob : 1;
+    const int64_t total = F.probs ? (int64_t)F.tbase[L] : ((int64_t)1 << F.p0.depth);
+    for (;;) {
+        if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
+        __syncthreads();
+        const int64_t t = __builtin_amdgcn_readfirstlane(s_ticket);
+        __syncthreads();
+        if (t >= total) break;
+        Prob P = F.p0;
+        int64_t base = 0;
+        if (F.probs) {
+            const int64_t s = forest_locate_wave(F.tbase, L, t);
+            P = F.probs[s];
+            base = F.tbase[s];
+        }
+        const int64_t nleaves = (int64_t)1 << P.depth;
+        const int64_t leaf = nleaves - 1 - (t - base);
+        const FrogNode f = frog_node(P.n, P.depth, leaf);
+        const Space<K> keys{Dk + P.doff, Hk + P.hoff, P.n};
+        const Space<V> vals{HV ? Dv + P.doff : nullptr, HV ? Hv + P.hoff : nullptr, P.n};
+        const int len = (int)f.n;
+        const int64_t src = f.in_off;
+        const int64_t dst = frog_data_start(f);
 
-    // load the chunk (input elements all live in the caller's array) with
-    // straight-line loads from clamped indices, all issued before the first
-    // LDS write
-    bool nan_here = false;
-    {
-        K lk[IPT];
-        VS lv[IPT];
+        // load the chunk (input elements all live in the caller's array) with
+        // straight-line loads from clamped indices, all issued before the
+        // first LDS write
+        bool nan_here = false;
+        {
+            K lk[IPT];
+            VS lv[IPT];
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) {
+                const int i = tid + r * NT;
+                const int ic = min(i, len - 1);
+                lk[r] = keys.D[src + ic];
+                if constexpr (HV) lv[r] = vals.D[src + ic];
+            }
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) nan_here |= is_nan_key(lk[r]);
+            const bool any_nan = __syncthreads_or(nan_here) != 0;
+            // slots past the chunk get a padding key that sorts after every
+            // real key (ties with it stay behind the real keys)
+            const K pad = any_nan ? KT::pad() : KF::pad();
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) {
+                const int i = tid + r * NT;
+                sk[lpad(i)] = i < len ? lk[r] : pad;
+                if constexpr (HV) sv[lpad(i)] = i < len ? lv[r] : VS();
+            }
+            nan_here = any_nan;
+        }
+        __syncthreads();
+        if (tid == 0) st_status(status + t, (epoch << 2) | ST_LOADED);
+
+        // a leaf of at most half a tile is sorted in the smallest power-of-two
+        // prefix holding it; the slots past it are padding
+        int maxw = TILE;
+        if (len <= TILE / 2) {
+            maxw = IPT;
+            while (maxw < len) maxw *= 2;
+        }
+        if (nan_here) block_sort_lds<KT, VS, HV, NT, IPT>(sk, sv, maxw, maxw);
+        else block_sort_lds<KF, VS, HV, NT, IPT>(sk, sv, maxw, maxw);
+
+        // wait for the leaves whose input chunks the destination covers
+        if (tid < 64 && dst < P.n) {
+            const int64_t end = (dst + len < P.n ? dst + len : P.n) - 1;
+            const int64_t lo_leaf = frog_leaf_of(P.n, P.depth, dst);
+            const int64_t hi_leaf = frog_leaf_of(P.n, P.depth, end);
+            wait_window(status, base + nleaves - 1 - hi_leaf, base + nleaves - 1 - lo_leaf, t, epoch, err);
+        }
+        __syncthreads();
+
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const int i = tid + r * NT;
-            const int ic = min(i, len - 1);
-            lk[r] = keys.D[src + ic];
-            if constexpr (HV) lv[r] = vals.D[src + ic];
+            if (i < len) {
+                *keys.at(dst + i) = sk[lpad(i)];
+                if constexpr (HV) *vals.at(dst + i) = sv[lpad(i)];
+            }
         }
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) nan_here |= is_nan_key(lk[r]);
-        const bool any_nan = __syncthreads_or(nan_here) != 0;
-        // slots past the chunk get a padding key that sorts after every real
-        // key (ties with it stay behind the real keys)
-        const K pad = any_nan ? KT::pad() : KF::pad();
-#pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const int i = tid + r * NT;
-            sk[lpad(i)] = i < len ? lk[r] : pad;
-            if constexpr (HV) sv[lpad(i)] = i < len ? lv[r] : VS();
-        }
-        nan_here = any_nan;
+        if constexpr (!LOOP) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forest prefix sums: tickets and splits of every round over the problems
+// ---------------------------------------------------------------------------
+// One work-group per round (round 0: leaves).  A round whose totals would pass
+// the capacity of the workspace arrays is cut to zero work and flags *err (the
+// call then fails instead of writing out of bounds).
+template <int TILE>
+__global__ __launch_bounds__(1024) void forest_scan_kernel(Forest F, unsigned *tbase, unsigned *sbase,
+                                                           int64_t cap_leaves, int64_t cap_tickets,
+                                                           int64_t cap_splits, unsigned *err, Gate gate)
+{
+    constexpr int NT = 1024, PER = 4;
+    __shared__ unsigned s_t[NT], s_s[NT];
+    __shared__ int64_t s_carry_t, s_carry_s;
+    if (gate.closed()) return;
+    const int round = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t L = *F.nprob;
+    unsigned *trow = tbase + (int64_t)round * F.stride;
+    unsigned *srow = sbase + (int64_t)round * F.stride;
+    if (tid == 0) {
+        s_carry_t = 0;
+        s_carry_s = 0;
     }
     __syncthreads();
-    if (tid == 0) st_status(status + t, (epoch << 2) | ST_LOADED);
-
-    if (nan_here) block_sort_lds<KT, VS, HV, NT, IPT>(sk, sv);
-    else block_sort_lds<KF, VS, HV, NT, IPT>(sk, sv);
-
-    // wait for the leaves whose input chunks the destination covers
-    if (tid < 64 && dst < n_total) {
-        const int64_t end = (dst + len < n_total ? dst + len : n_total) - 1;
-        const int64_t lo_leaf = frog_leaf_of(n_total, depth, dst);
-        const int64_t hi_leaf = frog_leaf_of(n_total, depth, end);
-        wait_window(status, nleaves - 1 - hi_leaf, nleaves - 1 - lo_leaf, t, epoch, err);
-    }
-    __syncthreads();
-
+    for (int64_t c0 = 0; c0 < L; c0 += NT * PER) {
+        unsigned tc[PER], sc[PER], tsum = 0, ssum = 0;
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const int i = tid + r * NT;
-        if (i < len) {
-            *keys.at(dst + i) = sk[lpad(i)];
-            if constexpr (HV) *vals.at(dst + i) = sv[lpad(i)];
+        for (int k = 0; k < PER; ++k) {
+            const int64_t s = c0 + (int64_t)tid * PER + k;
+            tc[k] = sc[k] = 0;
+            if (s < L) {
+                const Prob P = F.probs[s];
+                tc[k] = (unsigned)forest_tickets<TILE>(F, P, round);
+                sc[k] = (unsigned)forest_splits<TILE>(F, P, round);
+            }
+            tsum += tc[k];
+            ssum += sc[k];
         }
+        s_t[tid] = tsum;
+        s_s[tid] = ssum;
+        __syncthreads();
+        for (int d = 1; d < NT; d *= 2) {            // inclusive scan
+            const unsigned at = tid >= d ? s_t[tid - d] : 0u;
+            const unsigned as = tid >= d ? s_s[tid - d] : 0u;
+            __syncthreads();
+            s_t[tid] += at;
+            s_s[tid] += as;
+            __syncthreads();
+        }
+        int64_t rt = s_carry_t + s_t[tid] - tsum, rs = s_carry_s + s_s[tid] - ssum;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t s = c0 + (int64_t)tid * PER + k;
+            if (s < L) {
+                trow[s] = (unsigned)rt;
+                srow[s] = (unsigned)rs;
+            }
+            rt += tc[k];
+            rs += sc[k];
+        }
+        __syncthreads();
+        if (tid == NT - 1) {
+            s_carry_t = rt;
+            s_carry_s = rs;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int64_t tt = s_carry_t, ts = s_carry_s;
+        if (tt > (round == 0 ? cap_leaves : cap_tickets) || ts > cap_splits) {
+            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tt = 0;
+            ts = 0;
+            for (int64_t s = 0; s < L; ++s) trow[s] = srow[s] = 0;
+        }
+        trow[L] = (unsigned)tt;
+        srow[L] = (unsigned)ts;
     }
 }
 
 // ---------------------------------------------------------------------------
 // partition kernel: merge-path splits at every tile boundary of every node
 // ---------------------------------------------------------------------------
-// One thread per (node, boundary j): binary search for the number of left-run
+// One thread per (node, boundary j): binary search for the number of first-run
 // elements among the first j*TILE outputs of the node's stable merge.  (The
 // searches are bound by the rate of random reads, so one probe per step is
 // the cheapest form.)
 template <class KT, int TILE>
-__global__ __launch_bounds__(256) void partition_kernel(Space<typename KT::T> keys, MergeGeo geo,
-                                                        int64_t nnodes, int64_t tpn, int64_t *splits,
-                                                        Gate gate)
+__global__ __launch_bounds__(256) void partition_kernel(typename KT::T *Dk, typename KT::T *Hk, Forest F,
+                                                        int round, int64_t *splits, Gate gate)
 {
+    using K = typename KT::T;
     if (gate.closed()) return;
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= nnodes * (tpn + 1)) return;
-    const int64_t node = w / (tpn + 1);
-    const int64_t j = w - node * (tpn + 1);
-    const FrogMerge m = geo.node(node);
-    const int64_t nn = m.nl + m.nr;
-    int64_t kk = j * TILE;
-    if (kk > nn) kk = nn;
-    int64_t lo = kk > m.nr ? kk - m.nr : 0;
-    int64_t hi = kk < m.nl ? kk : m.nl;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (KT::less(*keys.at(m.r0 + (kk - 1 - mid)), *keys.at(m.l0 + mid))) hi = mid;
-        else lo = mid + 1;
+    const int64_t L = F.probs ? (int64_t)*F.nprob : 1;
+    const unsigned *srow = F.probs ? F.sbase + (int64_t)round * F.stride : nullptr;
+    const int64_t total = F.probs ? (int64_t)srow[L] : forest_splits<TILE>(F, F.p0, round);
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        Prob P = F.p0;
+        int64_t base = 0;
+        if (F.probs) {
+            const int64_t s = forest_locate(srow, L, w);
+            P = F.probs[s];
+            base = srow[s];
+        }
+        const int64_t tpn = forest_tpn<TILE>(F, P, round);
+        const int64_t lw = w - base;
+        const int64_t node = lw / (tpn + 1);
+        const int64_t j = lw - node * (tpn + 1);
+        const FrogMerge m = forest_merge(F, P, round, node);
+        const Space<K> keys{Dk + P.doff, Hk + P.hoff, P.n};
+        const int64_t nn = m.nl + m.nr;
+        int64_t kk = j * TILE;
+        if (kk > nn) kk = nn;
+        int64_t lo = kk > m.nr ? kk - m.nr : 0;
+        int64_t hi = kk < m.nl ? kk : m.nl;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (KT::less(*keys.at(m.r0 + (kk - 1 - mid)), *keys.at(m.l0 + mid))) hi = mid;
+            else lo = mid + 1;
+        }
+        splits[w] = lo;
     }
-    splits[w] = lo;
 }
 
 // ---------------------------------------------------------------------------
-// dependency windows of every merge tile
+// tile descriptors with their dependency windows
 // ---------------------------------------------------------------------------
 // A left node's tile with output ranks [k0,k1) overwrites the outer-run (left
 // child) elements with indices [k0, min(k1,nl)); a right node's tile overwrites
@@ -187,55 +307,82 @@ __device__ __forceinline__ int64_t upper_bound_bsplits(const int64_t *sp, int64_
 }
 
 template <int TILE>
-__global__ __launch_bounds__(256) void depwin_kernel(MergeGeo geo, int64_t nnodes, int64_t tpn,
-                                                     const int64_t *splits, int64_t *deps, Gate gate)
+__global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const int64_t *splits,
+                                                    TileDesc *desc, Gate gate)
 {
     if (gate.closed()) return;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nnodes * tpn) return;
-    const int64_t node = t / tpn;
-    const int64_t q = t - node * tpn;
-    const int64_t first = node * tpn;
-    const FrogMerge m = geo.node(node);
-    const int64_t nn = m.nl + m.nr;
-    const int64_t j = m.left ? (tpn - 1 - q) : q;
-    int64_t k0 = j * TILE;
-    if (k0 > nn) k0 = nn;
-    int64_t k1 = k0 + TILE;
-    if (k1 > nn) k1 = nn;
-    const int64_t *sp = splits + node * (tpn + 1);
-    int64_t lo = 1, hi = 0;              // empty window
-    if (k0 < k1) {
-        if (m.outer == 0) {              // first run at [out0, out0+nl), top-down
-            if (k0 < m.nl) {
-                const int64_t e = (k1 < m.nl ? k1 : m.nl) - 1;
-                const int64_t j0 = upper_bound_splits(sp, tpn + 1, k0) - 1;
-                const int64_t j1 = upper_bound_splits(sp, tpn + 1, e) - 1;
-                lo = first + (tpn - 1 - j1);
-                hi = first + (tpn - 1 - j0);
-            }
-        } else if (m.outer == 1) {       // second run at [out0+nl, out0+n), bottom-up
-            if (k1 > m.nl) {
-                const int64_t b0 = k0 > m.nl ? k0 - m.nl : 0;
-                const int64_t b1 = (k1 - m.nl < m.nr ? k1 - m.nl : m.nr) - 1;
-                const int64_t j0 = upper_bound_bsplits<TILE>(sp, tpn + 1, nn, b0) - 1;
-                const int64_t j1 = upper_bound_bsplits<TILE>(sp, tpn + 1, nn, b1) - 1;
-                lo = first + j0;
-                hi = first + j1;
-            }
-        } else {                         // first run at [out0+nr, out0+n), bottom-up
-            if (k1 > m.nr) {
-                const int64_t a0 = k0 > m.nr ? k0 - m.nr : 0;
-                const int64_t a1 = (k1 - m.nr < m.nl ? k1 - m.nr : m.nl) - 1;
-                const int64_t j0 = upper_bound_splits(sp, tpn + 1, a0) - 1;
-                const int64_t j1 = upper_bound_splits(sp, tpn + 1, a1) - 1;
-                lo = first + j0;
-                hi = first + j1;
+    const int64_t L = F.probs ? (int64_t)*F.nprob : 1;
+    const unsigned *trow = F.probs ? F.tbase + (int64_t)round * F.stride : nullptr;
+    const unsigned *srow = F.probs ? F.sbase + (int64_t)round * F.stride : nullptr;
+    const int64_t total = F.probs ? (int64_t)trow[L] : forest_tickets<TILE>(F, F.p0, round);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        Prob P = F.p0;
+        int64_t tb = 0, sb = 0, s = 0;
+        if (F.probs) {
+            s = forest_locate(trow, L, t);
+            P = F.probs[s];
+            tb = trow[s];
+            sb = srow[s];
+        }
+        const int64_t tpn = forest_tpn<TILE>(F, P, round);
+        const int64_t lt = t - tb;
+        const int64_t node = lt / tpn;
+        const int64_t q = lt - node * tpn;
+        const int64_t first = tb + node * tpn;
+        const int64_t *sp = splits + sb + node * (tpn + 1);
+        const FrogMerge m = forest_merge(F, P, round, node);
+        const int64_t nn = m.nl + m.nr;
+        const int64_t j = m.left ? (tpn - 1 - q) : q;
+        int64_t k0 = j * TILE;
+        if (k0 > nn) k0 = nn;
+        int64_t k1 = k0 + TILE;
+        if (k1 > nn) k1 = nn;
+        TileDesc T;
+        T.prob = (int)s;
+        T.pad = 0;
+        T.cnt = (int)(k1 - k0);
+        T.la = 0;
+        T.pa = T.pb = T.o = 0;
+        int64_t lo = 1, hi = 0;          // empty window
+        if (k0 < k1) {
+            const int64_t a0 = sp[j], a1 = sp[j + 1];
+            T.la = (int)(a1 - a0);
+            T.pa = m.l0 + a0;
+            T.pb = m.r0 + (k0 - a0);
+            T.o = m.out0 + k0;
+            if (m.outer == 0) {          // first run at [out0, out0+nl), top-down
+                if (k0 < m.nl) {
+                    const int64_t e = (k1 < m.nl ? k1 : m.nl) - 1;
+                    const int64_t j0 = upper_bound_splits(sp, tpn + 1, k0) - 1;
+                    const int64_t j1 = upper_bound_splits(sp, tpn + 1, e) - 1;
+                    lo = first + (tpn - 1 - j1);
+                    hi = first + (tpn - 1 - j0);
+                }
+            } else if (m.outer == 1) {   // second run at [out0+nl, out0+n), bottom-up
+                if (k1 > m.nl) {
+                    const int64_t b0 = k0 > m.nl ? k0 - m.nl : 0;
+                    const int64_t b1 = (k1 - m.nl < m.nr ? k1 - m.nl : m.nr) - 1;
+                    const int64_t j0 = upper_bound_bsplits<TILE>(sp, tpn + 1, nn, b0) - 1;
+                    const int64_t j1 = upper_bound_bsplits<TILE>(sp, tpn + 1, nn, b1) - 1;
+                    lo = first + j0;
+                    hi = first + j1;
+                }
+            } else {                     // first run at [out0+nr, out0+n), bottom-up
+                if (k1 > m.nr) {
+                    const int64_t a0w = k0 > m.nr ? k0 - m.nr : 0;
+                    const int64_t a1w = (k1 - m.nr < m.nl ? k1 - m.nr : m.nl) - 1;
+                    const int64_t j0 = upper_bound_splits(sp, tpn + 1, a0w) - 1;
+                    const int64_t j1 = upper_bound_splits(sp, tpn + 1, a1w) - 1;
+                    lo = first + j0;
+                    hi = first + j1;
+                }
             }
         }
+        T.dlo = (unsigned)lo;
+        T.dhi = (unsigned)hi;
+        desc[t] = T;
     }
-    deps[2 * t] = lo;
-    deps[2 * t + 1] = hi;
 }
 
 // ---------------------------------------------------------------------------
@@ -247,53 +394,11 @@ __global__ __launch_bounds__(256) void depwin_kernel(MergeGeo geo, int64_t nnode
 // output.  Tickets are handed out in each node's write order.  A work-group
 // takes the next ticket and issues that tile's loads while it merges and
 // stores the current one.
-struct MergeTile {
-    int64_t t;        // ticket
-    int64_t pa, pb;   // logical slots of the first left-run / right-run input
-    int64_t o;        // logical slot of the first output
-    int64_t dlo, dhi; // dependency window (tickets)
-    int la, cnt;      // left-run inputs, total inputs (= outputs)
-};
-
-template <int TILE>
-__device__ __forceinline__ MergeTile merge_tile_setup(int64_t t, const MergeGeo &geo, int64_t tpn,
-                                                      const int64_t *splits, const int64_t *deps)
-{
-    MergeTile T;
-    T.t = t;
-    const int64_t node = (int64_t)((uint64_t)t / (uint64_t)tpn);
-    const int64_t q = t - node * tpn;
-    const FrogMerge m = geo.node(node);
-    const int64_t nn = m.nl + m.nr;
-    const int64_t j = m.left ? (tpn - 1 - q) : q;
-    int64_t k0 = j * TILE;
-    if (k0 > nn) k0 = nn;
-    int64_t k1 = k0 + TILE;
-    if (k1 > nn) k1 = nn;
-    T.cnt = (int)(k1 - k0);
-    T.la = 0;
-    T.pa = T.pb = T.o = 0;
-    T.dlo = 1;
-    T.dhi = 0;
-    if (T.cnt > 0) {
-        const int64_t a0 = splits[node * (tpn + 1) + j];
-        const int64_t a1 = splits[node * (tpn + 1) + j + 1];
-        T.la = (int)(a1 - a0);
-        T.pa = m.l0 + a0;
-        T.pb = m.r0 + (k0 - a0);
-        T.o = m.out0 + k0;
-        T.dlo = deps[2 * t];
-        T.dhi = deps[2 * t + 1];
-    }
-    return T;
-}
-
-template <class KT, class V, int NT, int IPT>
-__global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, Space<V> vals,
-                                                   MergeGeo geo, int64_t tpn, int64_t ntiles,
-                                                   const int64_t *splits, const int64_t *deps,
-                                                   unsigned *ticket_ctr, unsigned *status,
-                                                   unsigned epoch, unsigned *err, Gate gate)
+template <class KT, class V, int NT, int IPT, int WAVES>
+__global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv,
+                                                   Forest F, int round, const TileDesc *desc,
+                                                   unsigned *ticket_ctr, unsigned *status, unsigned epoch,
+                                                   unsigned *err, Gate gate)
 {
     using K = typename KT::T;
     constexpr bool HV = ValOps<V>::has;
@@ -305,29 +410,38 @@ __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, S
     __shared__ unsigned s_next;
     if (gate.closed()) return;
 
+    const int64_t ntiles = F.probs ? (int64_t)F.tbase[(int64_t)round * F.stride + *F.nprob]
+                                   : forest_tickets<TILE>(F, F.p0, round);
     const int tid = threadIdx.x;
     if (tid == 0) s_next = atomicAdd(ticket_ctr, 1u);
     __syncthreads();
     int64_t t = __builtin_amdgcn_readfirstlane(s_next);
     if (t >= ntiles) return;
 
-    MergeTile cur = merge_tile_setup<TILE>(t, geo, tpn, splits, deps);
+    TileDesc cur = desc[t];
+    Prob cur_p = forest_prob(F, cur.prob);
+    int64_t cur_t = t;
     K lk[IPT];
     VS lv[IPT];
     // Straight-line loads: indices past the tile are clamped to its last input
-    // (an empty tile reads slot 0), so every load is valid and none needs a
-    // branch; the values loaded for clamped indices are never stored.
-    auto issue_loads = [&](const MergeTile &T) {
+    // (an empty tile reads its problem's slot 0), so every load is valid and
+    // none needs a branch; the values loaded for clamped indices are never
+    // stored.
+    auto issue_loads = [&](const TileDesc &T, const Prob &P) {
         const int last = T.cnt > 0 ? T.cnt - 1 : 0;
+        const Space<K> ks{Dk + P.doff, Hk + P.hoff, P.n};
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
             const int i = min(tid + r * NT, last);
             const int64_t p = i < T.la ? T.pa + i : T.pb + (i - T.la);
-            lk[r] = *keys.at(p);
-            if constexpr (HV) lv[r] = *vals.at(p);
+            lk[r] = *ks.at(p);
+            if constexpr (HV) {
+                const Space<V> vs{Dv + P.doff, Hv + P.hoff, P.n};
+                lv[r] = *vs.at(p);
+            }
         }
     };
-    issue_loads(cur);
+    issue_loads(cur, cur_p);
 
     for (;;) {
         // stage the current tile in LDS and publish that its inputs are read
@@ -341,7 +455,7 @@ __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, S
         __syncthreads();
         unsigned nt = 0;
         if (tid == 0) {
-            st_status(status + cur.t, (epoch << 2) | ST_LOADED);
+            st_status(status + cur_t, (epoch << 2) | ST_LOADED);
             nt = atomicAdd(ticket_ctr, 1u);
         }
 
@@ -368,12 +482,14 @@ __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, S
         // prefetch the next tile while this one waits and stores
         const int64_t t2 = __builtin_amdgcn_readfirstlane(s_next);
         const bool more = t2 < ntiles;
-        MergeTile nxt;
+        TileDesc nxt;
+        Prob nxt_p;
         if (more) {
-            nxt = merge_tile_setup<TILE>(t2, geo, tpn, splits, deps);
-            issue_loads(nxt);
+            nxt = desc[t2];
+            nxt_p = forest_prob(F, nxt.prob);
+            issue_loads(nxt, nxt_p);
         }
-        if (tid < 64) wait_window(status, cur.dlo, cur.dhi, cur.t, epoch, err);
+        if (tid < 64) wait_window(status, cur.dlo, cur.dhi, cur_t, epoch, err);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
@@ -383,17 +499,25 @@ __global__ __launch_bounds__(NT) void merge_kernel(Space<typename KT::T> keys, S
             }
         }
         __syncthreads();
+        {
+            const Space<K> ks{Dk + cur_p.doff, Hk + cur_p.hoff, cur_p.n};
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const int i = tid + r * NT;
-            if (i < cur.cnt) {
-                *keys.at(cur.o + i) = sk[lpad(i)];
-                if constexpr (HV) *vals.at(cur.o + i) = sv[lpad(i)];
+            for (int r = 0; r < IPT; ++r) {
+                const int i = tid + r * NT;
+                if (i < cur.cnt) {
+                    *ks.at(cur.o + i) = sk[lpad(i)];
+                    if constexpr (HV) {
+                        const Space<V> vs{Dv + cur_p.doff, Hv + cur_p.hoff, cur_p.n};
+                        *vs.at(cur.o + i) = sv[lpad(i)];
+                    }
+                }
             }
         }
         if (!more) break;
         __syncthreads();                 // LDS reads done before the next staging
         cur = nxt;
+        cur_p = nxt_p;
+        cur_t = t2;
     }
 }
 
@@ -414,56 +538,90 @@ struct SortCfg;
 #ifndef GS_F64_MERGE_IPT
 #define GS_F64_MERGE_IPT 16
 #endif
+// LEAF_WAVES / MERGE_WAVES: waves per SIMD each kernel is compiled to allow
+// (the register budget), chosen so that the LDS, not the registers, limits
+// the work-groups per compute unit.
 template <>
 struct SortCfg<KeyF64, NoVal> {
-    static constexpr int LEAF_NT = GS_F64_LEAF_NT, LEAF_IPT = GS_F64_LEAF_IPT;
-    static constexpr int MERGE_NT = GS_F64_MERGE_NT, MERGE_IPT = GS_F64_MERGE_IPT;
+    static constexpr int LEAF_NT = GS_F64_LEAF_NT, LEAF_IPT = GS_F64_LEAF_IPT, LEAF_WAVES = 4;
+    static constexpr int MERGE_NT = GS_F64_MERGE_NT, MERGE_IPT = GS_F64_MERGE_IPT, MERGE_WAVES = 3;
 };
 template <>
 struct SortCfg<KeyU64, uint32_t> {
-    static constexpr int LEAF_NT = 256, LEAF_IPT = 16;
-    static constexpr int MERGE_NT = 256, MERGE_IPT = 8;
+    static constexpr int LEAF_NT = 256, LEAF_IPT = 16, LEAF_WAVES = 2;
+    static constexpr int MERGE_NT = 256, MERGE_IPT = 8, MERGE_WAVES = 4;
 };
 
 template <class KT, class V>
-int64_t leaf_size()
+constexpr int64_t leaf_size()
 {
     return (int64_t)SortCfg<KT, V>::LEAF_NT * SortCfg<KT, V>::LEAF_IPT;
+}
+template <class KT, class V>
+constexpr int64_t tile_size()
+{
+    return (int64_t)SortCfg<KT, V>::MERGE_NT * SortCfg<KT, V>::MERGE_IPT;
 }
 
 static int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
-template <class KT, class V>
-SortPlan make_plan(int64_t n)
+// Control block, status words, splits, tile descriptors and (for a problem
+// table) the per-round prefix rows, laid out from offset 0.
+static ForestPlan layout_forest(int64_t max_probs, int rounds, int64_t max_tickets, int64_t max_status,
+                                int64_t max_splits, int64_t leaf, int64_t tile)
 {
-    using K = typename KT::T;
-    constexpr bool HV = ValOps<V>::has;
-    constexpr int TILE = SortCfg<KT, V>::MERGE_NT * SortCfg<KT, V>::MERGE_IPT;
-    SortPlan p{};
-    p.n = n;
-    p.leaf = leaf_size<KT, V>();
-    p.tile = TILE;
-    p.depth = n > 1 ? frog_depth(n, p.leaf) : 0;
-    int64_t max_tickets = (int64_t)1 << p.depth;     // leaf launch
-    int64_t max_splits = 0;
-    for (int d = 0; d < p.depth; ++d) {
-        const int64_t tpn = (frog_max_node(n, d) + TILE - 1) / TILE;
-        const int64_t nn = (int64_t)1 << d;
-        if (nn * tpn > max_tickets) max_tickets = nn * tpn;
-        if (nn * (tpn + 1) > max_splits) max_splits = nn * (tpn + 1);
+    ForestPlan f{};
+    f.max_probs = max_probs;
+    f.rounds = rounds;
+    f.leaf = leaf;
+    f.tile = tile;
+    f.stride = max_probs + 1;
+    f.max_tickets = max_tickets;
+    f.max_status = max_status;
+    f.max_splits = max_splits;
+    f.off_ctrl = 0;
+    f.off_status = align256(kForestCtrlWords * 4);
+    f.off_splits = f.off_status + align256(max_status * 4);
+    f.off_desc = f.off_splits + align256(max_splits * 8);
+    f.off_probs = f.off_desc + align256(max_tickets * (int64_t)sizeof(TileDesc));
+    f.off_tbase = f.off_probs + (max_probs > 0 ? align256(max_probs * (int64_t)sizeof(Prob)) : 0);
+    f.off_sbase = f.off_tbase + (max_probs > 0 ? align256((rounds + 1) * f.stride * 4) : 0);
+    f.bytes = f.off_sbase + (max_probs > 0 ? align256((rounds + 1) * f.stride * 4) : 0);
+    return f;
+}
+
+template <class KT, class V>
+ForestPlan forest_plan_one(int64_t n)
+{
+    constexpr int64_t LEAF = leaf_size<KT, V>(), TILE = tile_size<KT, V>();
+    Forest F{};
+    F.p0 = Prob{0, 0, n, n > 1 ? frog_depth(n, LEAF) : 0, 0};
+    int64_t mt = 1, ms = 1;
+    const int D = F.p0.depth;
+    const int64_t leaves = (int64_t)1 << D;
+    for (int r = 1; r <= D; ++r) {
+        const int64_t t = forest_tickets<TILE>(F, F.p0, r), s = forest_splits<TILE>(F, F.p0, r);
+        if (t > mt) mt = t;
+        if (s > ms) ms = s;
     }
-    const int64_t h = n / 2;
-    p.off_hkeys = 0;
-    p.off_hvals = align256(h * (int64_t)sizeof(K));
-    p.off_tickets = p.off_hvals + (HV ? align256(h * (int64_t)sizeof(V)) : 0);
-    p.n_tickets = 64;
-    p.off_status = p.off_tickets + align256(p.n_tickets * 4);
-    p.n_status = max_tickets;
-    p.off_splits = p.off_status + align256(max_tickets * 4);
-    p.off_deps = p.off_splits + align256(max_splits * 8);
-    p.bytes = p.off_deps + align256(max_tickets * 16);
-    if (n <= 1) p.bytes = 0;
-    return p;
+    return layout_forest(0, D, mt, mt > leaves ? mt : leaves, ms, LEAF, TILE);
+}
+
+// Capacity for any set of at most max_probs problems of at most max_len keys
+// each and num_keys keys in total.  At a merge depth d of a problem of n keys
+// the 2^d nodes hold at most ceil(n/2^d) keys each, so its tickets are
+// 2^d * ceil(ceil(n/2^d) / TILE) <= n / TILE + 2^d, and 2^d < n / LEAF
+// because a node above the leaf level holds more than LEAF keys; the splits
+// add one per node.  A problem has 1 leaf or fewer than 2n / LEAF.
+template <class KT, class V>
+ForestPlan forest_plan_many(int64_t num_keys, int64_t max_len, int64_t max_probs)
+{
+    constexpr int64_t LEAF = leaf_size<KT, V>(), TILE = tile_size<KT, V>();
+    const int rounds = max_len > 1 ? frog_depth(max_len, LEAF) : 0;
+    const int64_t mt = num_keys / TILE + num_keys / LEAF + 64;
+    const int64_t ms = num_keys / TILE + 2 * (num_keys / LEAF) + 64;
+    const int64_t leaves = 2 * (num_keys / LEAF) + max_probs + 64;
+    return layout_forest(max_probs, rounds, mt, mt > leaves ? mt : leaves, ms, LEAF, TILE);
 }
 
 // Resident work-groups of a kernel over the whole device (cached by caller).
@@ -482,34 +640,106 @@ static int64_t resident_groups(F kernel, int threads, int64_t &cache)
     return cache;
 }
 
-// Enqueues partition, dependency windows and the merge for one level (or one
-// explicit node) whose control words start at `tickets`.
+static unsigned grid_for(int64_t items, int threads, int64_t cap)
+{
+    int64_t g = (items + threads - 1) / threads;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+// Enqueues a whole forest sort (or, with use_m1, one explicit merge) on the
+// forest area `fw` laid out by `fp`.  Exact launch sizes for the single
+// problem; capacity-sized persistent launches for a device-side table.
 template <class KT, class V>
-static void launch_level(Space<typename KT::T> sk, Space<V> sv, const MergeGeo &geo, int64_t nn, int64_t tpn,
-                         int64_t *splits, int64_t *deps, unsigned *ticket, unsigned *status,
-                         unsigned *errw, unsigned epoch, Gate gate, hipStream_t st)
+static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv, Forest F,
+                             const ForestPlan &fp, char *fw, hipStream_t st, Gate gate, bool leaves)
 {
     using C = SortCfg<KT, V>;
     constexpr int TILE = C::MERGE_NT * C::MERGE_IPT;
-    auto merge_fn = merge_kernel<KT, V, C::MERGE_NT, C::MERGE_IPT>;
-    static int64_t merge_groups = 0;
-    const int64_t resident = resident_groups(merge_fn, C::MERGE_NT, merge_groups);
+    unsigned *ctrl = (unsigned *)(fw + fp.off_ctrl);
+    unsigned *status = (unsigned *)(fw + fp.off_status);
+    int64_t *splits = (int64_t *)(fw + fp.off_splits);
+    TileDesc *desc = (TileDesc *)(fw + fp.off_desc);
+    unsigned *errw = ctrl + kErrWord;
+    const bool table = F.probs != nullptr;
+    if (table) {
+        F.tbase = (const unsigned *)(fw + fp.off_tbase);
+        F.sbase = (const unsigned *)(fw + fp.off_sbase);
+        F.stride = fp.stride;
+    }
+    const int R = F.use_m1 ? 1 : fp.rounds;
+
     const bool tr = trace_on();
-    const int64_t nsplit = nn * (tpn + 1);
-    const int64_t ntiles = nn * tpn;
-    if (tr) trace_begin(TK_PARTITION, st);
-    hipLaunchKernelGGL((partition_kernel<KT, TILE>), dim3((unsigned)((nsplit + 255) / 256)), dim3(256), 0, st,
-                       sk, geo, nn, tpn, splits, gate);
+    // ticket counters and status words start at zero on every call
+    if (tr) trace_begin(TK_FILL, st);
+    launch_fill_u32(ctrl, (fp.off_splits - fp.off_ctrl) / 4, 0u, st);
     if (tr) trace_end(st);
-    if (tr) trace_begin(TK_DEPWIN, st);
-    hipLaunchKernelGGL((depwin_kernel<TILE>), dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st, geo, nn,
-                       tpn, (const int64_t *)splits, deps, gate);
-    if (tr) trace_end(st);
-    if (tr) trace_begin(TK_MERGE, st);
-    const int64_t grid = ntiles < resident ? ntiles : resident;
-    hipLaunchKernelGGL(merge_fn, dim3((unsigned)grid), dim3(C::MERGE_NT), 0, st, sk, sv, geo, tpn, ntiles,
-                       (const int64_t *)splits, (const int64_t *)deps, ticket, status, epoch, errw, gate);
-    if (tr) trace_end(st);
+    if (table) {
+        if (tr) trace_begin(TK_OTHER, st);
+        hipLaunchKernelGGL((forest_scan_kernel<TILE>), dim3((unsigned)(R + 1)), dim3(1024), 0, st, F,
+                           (unsigned *)(fw + fp.off_tbase), (unsigned *)(fw + fp.off_sbase), fp.max_status,
+                           fp.max_tickets, fp.max_splits, errw, gate);
+        if (tr) trace_end(st);
+    }
+
+    auto leaf_fn = leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, false>;
+    auto leaf_loop_fn = leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, true>;
+    auto merge_fn = merge_kernel<KT, V, C::MERGE_NT, C::MERGE_IPT, C::MERGE_WAVES>;
+    static int64_t leaf_groups = 0, merge_groups = 0;
+    unsigned epoch = 1;
+    if (leaves) {
+        if (tr) trace_begin(TK_LEAF, st);
+        if (table) {
+            const int64_t res = resident_groups(leaf_loop_fn, C::LEAF_NT, leaf_groups);
+            const int64_t items = fp.max_status;
+            hipLaunchKernelGGL(leaf_loop_fn, dim3((unsigned)(items < res ? items : res)), dim3(C::LEAF_NT), 0, st,
+                               Dk, Hk, Dv, Hv, F, ctrl + 0, status, epoch, errw, gate);
+        } else {
+            hipLaunchKernelGGL(leaf_fn, dim3((unsigned)((int64_t)1 << F.p0.depth)), dim3(C::LEAF_NT), 0, st, Dk,
+                               Hk, Dv, Hv, F, ctrl + 0, status, epoch, errw, gate);
+        }
+        if (tr) trace_end(st);
+    }
+    const int64_t mres = resident_groups(merge_fn, C::MERGE_NT, merge_groups);
+    for (int r = 1; r <= R; ++r) {
+        ++epoch;
+        const int64_t nsplit = table ? fp.max_splits : forest_splits<TILE>(F, F.p0, r);
+        const int64_t ntile = table ? fp.max_tickets : forest_tickets<TILE>(F, F.p0, r);
+        if (tr) trace_begin(TK_PARTITION, st);
+        hipLaunchKernelGGL((partition_kernel<KT, TILE>), dim3(grid_for(nsplit, 256, 4096)), dim3(256), 0, st, Dk,
+                           Hk, F, r, splits, gate);
+        if (tr) trace_end(st);
+        if (tr) trace_begin(TK_DEPWIN, st);
+        hipLaunchKernelGGL((tiles_kernel<TILE>), dim3(grid_for(ntile, 256, 4096)), dim3(256), 0, st, F, r,
+                           (const int64_t *)splits, desc, gate);
+        if (tr) trace_end(st);
+        if (tr) trace_begin(TK_MERGE, st);
+        hipLaunchKernelGGL(merge_fn, dim3((unsigned)(ntile < mres ? ntile : mres)), dim3(C::MERGE_NT), 0, st, Dk,
+                           Hk, Dv, Hv, F, r, (const TileDesc *)desc, ctrl + r, status, epoch, errw, gate);
+        if (tr) trace_end(st);
+    }
+    return hipGetLastError();
+}
+
+template <class KT, class V>
+SortPlan make_plan(int64_t n)
+{
+    using K = typename KT::T;
+    constexpr bool HV = ValOps<V>::has;
+    SortPlan p{};
+    p.n = n;
+    p.leaf = leaf_size<KT, V>();
+    p.tile = tile_size<KT, V>();
+    p.depth = n > 1 ? frog_depth(n, p.leaf) : 0;
+    const int64_t h = n / 2;
+    p.off_hkeys = 0;
+    p.off_hvals = align256(h * (int64_t)sizeof(K));
+    p.off_forest = p.off_hvals + (HV ? align256(h * (int64_t)sizeof(V)) : 0);
+    p.forest = forest_plan_one<KT, V>(n);
+    p.bytes = p.off_forest + p.forest.bytes;
+    if (n <= 1) p.bytes = 0;
+    return p;
 }
 
 template <class KT, class V>
@@ -517,58 +747,43 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
                     hipStream_t st, Gate gate)
 {
     using K = typename KT::T;
-    using C = SortCfg<KT, V>;
     constexpr bool HV = ValOps<V>::has;
-    constexpr int TILE = C::MERGE_NT * C::MERGE_IPT;
     if (n <= 1) return hipSuccess;
-    Space<K> sk{keys, (K *)(ws + p.off_hkeys), n};
-    Space<V> sv{vals, HV ? (V *)(ws + p.off_hvals) : nullptr, n};
-    unsigned *tickets = (unsigned *)(ws + p.off_tickets);
-    unsigned *status = (unsigned *)(ws + p.off_status);
-    int64_t *splits = (int64_t *)(ws + p.off_splits);
-    int64_t *deps = (int64_t *)(ws + p.off_deps);
-
-    const bool tr = trace_on();
-    // tickets and status words start at zero on every call
-    if (tr) trace_begin(TK_FILL, st);
-    launch_fill_u32(tickets, (p.off_splits - p.off_tickets) / 4, 0u, st);
-    if (tr) trace_end(st);
-
-    const int D = p.depth;
-    unsigned epoch = 1;
-    if (tr) trace_begin(TK_LEAF, st);
-    hipLaunchKernelGGL((leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT>), dim3((unsigned)((int64_t)1 << D)),
-                       dim3(C::LEAF_NT), 0, st, sk, sv, n, D, (int64_t)1 << D, tickets + 0, status,
-                       epoch, tickets + kErrWord, gate);
-    if (tr) trace_end(st);
-    for (int d = D - 1; d >= 0; --d) {
-        ++epoch;
-        MergeGeo geo{};
-        geo.n_total = n;
-        geo.depth = d;
-        geo.single = 0;
-        const int64_t nn = (int64_t)1 << d;
-        const int64_t tpn = (frog_max_node(n, d) + TILE - 1) / TILE;
-        launch_level<KT, V>(sk, sv, geo, nn, tpn, splits, deps, tickets + (D - d), status,
-                            tickets + kErrWord, epoch, gate, st);
-    }
-    return hipGetLastError();
+    Forest F{};
+    F.p0 = Prob{0, 0, n, p.depth, 0};
+    return run_forest<KT, V>(keys, (K *)(ws + p.off_hkeys), vals, HV ? (V *)(ws + p.off_hvals) : nullptr, F,
+                             p.forest, ws + p.off_forest, st, gate, true);
 }
 
 // explicit instantiations used by the ABI layer
 SortPlan plan_f64(int64_t n) { return make_plan<KeyF64, NoVal>(n); }
 SortPlan plan_kv(int64_t n) { return make_plan<KeyU64, uint32_t>(n); }
 
+ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs)
+{
+    return forest_plan_many<KeyF64, NoVal>(num_keys, max_len, max_probs);
+}
+
 hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st,
                           const unsigned *gate, unsigned run_if)
 {
-    return run_sort<KeyF64, NoVal>(keys, nullptr, n, ws, p, st, Gate{gate, run_if});
+    return run_sort<KeyF64, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st, Gate{gate, run_if});
 }
 
 hipError_t sort_kv_async(uint64_t *keys, uint32_t *vals, int64_t n, char *ws, const SortPlan &p,
                          hipStream_t st)
 {
     return run_sort<KeyU64, uint32_t>(keys, vals, n, ws, p, st, Gate{nullptr, 0u});
+}
+
+hipError_t forest_f64_async(double *D, double *H, const Prob *probs, const unsigned *nprob, const ForestPlan &fp,
+                            char *fw, hipStream_t st, const unsigned *gate, unsigned run_if)
+{
+    Forest F{};
+    F.probs = probs;
+    F.nprob = nprob;
+    return run_forest<KeyF64, NoVal>(D, H, (NoVal *)nullptr, (NoVal *)nullptr, F, fp, fw, st, Gate{gate, run_if},
+                                     true);
 }
 
 hipError_t merge_one_f64_async(double *D, double *H, int64_t n_space, const FrogMerge &m, char *ws,
@@ -578,22 +793,17 @@ hipError_t merge_one_f64_async(double *D, double *H, int64_t n_space, const Frog
     constexpr int TILE = C::MERGE_NT * C::MERGE_IPT;
     const int64_t n = m.nl + m.nr;
     if (n <= 0) return hipSuccess;
-    Space<double> sk{D, H, n_space};
-    Space<NoVal> sv{nullptr, nullptr, n_space};
-    unsigned *tickets = (unsigned *)(ws + p.off_tickets);
-    unsigned *status = (unsigned *)(ws + p.off_status);
-    int64_t *splits = (int64_t *)(ws + p.off_splits);
-    int64_t *deps = (int64_t *)(ws + p.off_deps);
-    launch_fill_u32(tickets, (p.off_splits - p.off_tickets) / 4, 0u, st);
-    MergeGeo geo{};
-    geo.n_total = n;
-    geo.depth = 0;
-    geo.single = 1;
-    geo.m1 = m;
-    const int64_t tpn = (n + TILE - 1) / TILE;
-    launch_level<KeyF64, NoVal>(sk, sv, geo, 1, tpn, splits, deps, tickets + 1, status, tickets + kErrWord, 1u,
-                                Gate{gate, run_if}, st);
-    return hipGetLastError();
+    Forest F{};
+    F.p0 = Prob{0, 0, n_space, 1, 0};
+    F.m1 = m;
+    F.use_m1 = 1;
+    // the plain plan's forest area holds the node's tiles when it covers
+    // a sort of at least n keys
+    if (forest_tickets<TILE>(F, F.p0, 1) > p.forest.max_tickets ||
+        forest_splits<TILE>(F, F.p0, 1) > p.forest.max_splits)
+        return hipErrorInvalidValue;
+    return run_forest<KeyF64, NoVal>(D, H, (NoVal *)nullptr, (NoVal *)nullptr, F, p.forest, ws + p.off_forest, st,
+                                     Gate{gate, run_if}, false);
 }
 
 }  // namespace gs

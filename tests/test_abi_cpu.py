@@ -42,7 +42,7 @@ def test_workspace_sizes():
         assert b >= 8 * (n // 2)
         assert b <= 8 * (n // 2) + 4096 + n // 64 + 64 * 1024
     n = 1 << 28
-    assert 1.5 < 1 + g.gs_workspace_bytes_f64(n) / (8 * n) < 1.5015
+    assert 1.5 < 1 + g.gs_workspace_bytes_f64(n) / (8 * n) < 1.502
     assert g.gs_workspace_bytes_kv(n) >= 12 * (n // 2)
     assert g.gs_workspace_bytes_f64(-1) == g.SIZE_MAX
 
@@ -107,3 +107,42 @@ def test_segsort_argument_errors():
     assert f(None, 0, None, 0, 0.5, None, 0, None, None) == g.GS_OK
     assert g.gs_workspace_bytes_seg(10, 0) == 0
     assert g.gs_workspace_bytes_seg(-1, 3) == g.SIZE_MAX
+
+
+def _forest_counts(n, leaf, tile, rnd):
+    """Exact work items of one problem of n keys in a round of the forest
+    sort (round 0: leaves; round r: merge tiles and splits at depth D - r)."""
+    D = 0
+    while -(-n // (1 << D)) > leaf:
+        D += 1
+    if rnd == 0:
+        return 1 << D, 0
+    if rnd > D:
+        return 0, 0
+    d = D - rnd
+    nodes = 1 << d
+    tpn = -(-(-(-n // nodes)) // tile)
+    return nodes * tpn, nodes * (tpn + 1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_forest_capacity_bounds(seed):
+    """The workspace capacities of the forest sort (tickets, splits, leaves per
+    round) bound the exact counts for random sets of problems of every size."""
+    leaf, tile = 8192, 4096
+    rng = np.random.default_rng(seed)
+    lo = [4097, 2, 8193, 4097, 2, 100000][seed]
+    hi = [9000, 70000, 1 << 20, 1 << 17, 5000, 1 << 22][seed]
+    lens = np.exp(rng.uniform(np.log(lo), np.log(hi), rng.integers(1, 3000))).astype(np.int64)
+    K, P = int(lens.sum()), lens.size
+    cap_t = K // tile + K // leaf + 64
+    cap_s = K // tile + 2 * (K // leaf) + 64
+    cap_leaves = max(cap_t, 2 * (K // leaf) + P + 64)
+    for rnd in range(0, 20):
+        t = s = 0
+        for n in lens:
+            a, b = _forest_counts(int(n), leaf, tile, rnd)
+            t += a
+            s += b
+        assert t <= (cap_leaves if rnd == 0 else cap_t)
+        assert s <= cap_s

@@ -52,6 +52,35 @@ def test_segsort_lengths(gs, orc, lengths, pattern):
     _check(orc, t, x, off)
 
 
+@pytest.mark.parametrize("lengths", [
+    [1 << 20, (1 << 20) - 1, 300001, 5, 0, 70000, 8193, 4097],
+    [(1 << 22) + 3],
+    [4097] * 300 + [9000] * 50 + [17] * 200,
+])
+def test_segsort_long_segments(gs, orc, lengths):
+    """Segments above one LDS tile go through the forest sort: many frog
+    trees of different depths merged level by level in shared launches."""
+    announce("segsort long", len(lengths), max(lengths))
+    n = int(sum(lengths))
+    x = W.f64_pattern("zeros_signed", n, seed=n % 1000)
+    off = np.zeros(len(lengths) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lengths)
+    t, _ = _run(gs, x, off)
+    _check(orc, t, x, off)
+
+
+def test_segsort_draw_until_total(gs, orc):
+    """Lengths log-uniform in [16, 2^20] drawn until 2^24 keys, mixed
+    patterns per segment."""
+    announce("segsort until-total")
+    x, off = W.segmented(None, 16, 1 << 20, seed=5, total=1 << 24)
+    x = x.copy()
+    x[::97] = -0.0
+    x[::89] = 0.0
+    t, _ = _run(gs, x, off)
+    _check(orc, t, x, off)
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_segsort_random_mix(gs, orc, seed):
     announce("segsort mix", seed)

@@ -233,10 +233,29 @@ def seg_lengths(num_segments: int, lo: int, hi: int, key: int, total: int | None
     return lens
 
 
-def segmented(num_segments: int, lo: int, hi: int, seed: int = 0, total: int | None = None,
+def seg_lengths_until(total: int, lo: int, hi: int, key: int):
+    """Log-uniform integer lengths in [lo, hi] drawn until they reach `total`
+    keys; the last length is cut so that they sum to it exactly."""
+    mean = (hi + 1 - lo) / (math.log(hi + 1) - math.log(lo))
+    m = int(total / mean * 1.2) + 64
+    while True:
+        u = uniform01(m, key)
+        lens = np.clip(np.floor(np.exp(math.log(lo) + u * (math.log(hi + 1) - math.log(lo)))).astype(np.int64),
+                       lo, hi)
+        c = np.cumsum(lens)
+        if c[-1] >= total:
+            k = int(np.searchsorted(c, total))          # first prefix reaching the total
+            lens = lens[: k + 1].copy()
+            lens[k] -= int(c[k]) - total
+            return lens
+        m *= 2
+
+
+def segmented(num_segments: int | None, lo: int, hi: int, seed: int = 0, total: int | None = None,
               workload: int = 4, patterns=("uniform", "tied", "presorted", "reversed")):
     """(keys, int64 offsets): segments of log-uniform length, each filled with a
-    pattern drawn uniformly from `patterns`.
+    pattern drawn uniformly from `patterns`.  With num_segments None, lengths
+    are drawn until they hold `total` keys (the last one cut to fit).
 
     uniform   i.i.d. U[0,1)
     tied      draws from 1024 distinct U[0,1) values
@@ -244,7 +263,11 @@ def segmented(num_segments: int, lo: int, hi: int, seed: int = 0, total: int | N
     reversed  1 - presorted (descending within the segment)
     """
     key = stream_seed(workload, 0, seed)
-    lens = seg_lengths(num_segments, lo, hi, key, total)
+    if num_segments is None:
+        lens = seg_lengths_until(int(total), lo, hi, key)
+        num_segments = lens.size
+    else:
+        lens = seg_lengths(num_segments, lo, hi, key, total)
     off = np.zeros(num_segments + 1, dtype=np.int64)
     np.cumsum(lens, out=off[1:])
     n = int(off[-1])

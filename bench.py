@@ -137,40 +137,84 @@ def extras(gs, torch, W, log2n, dev):
         lr[pat] = row
         del x, buf
     res["learned_vs_plain"] = lr
-    # segmented: 100,000 arrays, log-uniform lengths, total 2^28, mixed patterns
-    log("extras: segmented")
-    xs, off = W.segmented(100_000, 16, 19023, seed=0, total=n)
-    x = torch.from_numpy(xs).to(dev)
-    o = torch.from_numpy(off).to(dev)
-    buf = torch.empty_like(x)
-    gs.gs_segsort(buf.copy_(x), o)
+    # segmented: 100,000 arrays, log-uniform lengths rescaled to total 2^28,
+    # mixed patterns; and lengths log-uniform in [16, 2^20] drawn until 2^28
+    segres = {}
+    for name, (nseg, lo, hi) in (("100k_arrays", (100_000, 16, 19023)),
+                                 ("until_total_16_to_2^20", (None, 16, 1 << 20))):
+        log(f"extras: segmented {name}")
+        xs, off = W.segmented(nseg, lo, hi, seed=0, total=n)
+        nseg = off.size - 1
+        x = torch.from_numpy(xs).to(dev)
+        o = torch.from_numpy(off).to(dev)
+        buf = torch.empty_like(x)
+        need = gs.gs_workspace_bytes_seg(n, nseg)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        ws = ws[(-ws.data_ptr()) % 256:][:need]
+        best, times = gs.gs_segsort_autotune(x, o, reps=2, workspace=ws, scratch=buf)
 
-    def fn_seg(i, timed):
-        if timed is None:
-            buf.copy_(x)
-        else:
-            gs.gs_segsort(buf, o)
-    ms_seg = _time_calls(torch, stream, fn_seg, 3)
-    # per-array plain launches on the first 2000 arrays, scaled to all
-    k = 2000
-    sub = [buf[int(off[i]):int(off[i + 1])] for i in range(k)]
-    wsmax = max(gs.gs_workspace_bytes_f64(t.numel()) for t in sub)
-    ws = torch.empty(wsmax + 256, dtype=torch.uint8, device=dev)
-    ws = ws[(-ws.data_ptr()) % 256:][:wsmax]
+        def timed(cfg):
+            def fn_seg(i, t):
+                if t is None:
+                    buf.copy_(x)
+                else:
+                    gs.gs_segsort(buf, o, workspace=ws, config=cfg)
+            gs.gs_segsort(buf.copy_(x), o, workspace=ws, config=cfg)
+            return _time_calls(torch, stream, fn_seg, 3)
+        ms_default = timed(None)
+        ms_best = timed(best)
+        # the tuned call captured once in a HIP graph and replayed
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            gs.gs_segsort(buf.copy_(x), o, workspace=ws, config=best, stream=side)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            gs.gs_segsort(buf, o, workspace=ws, config=best, stream=side)
 
-    def fn_each(i, timed):
-        if timed is None:
-            buf.copy_(x)
-        else:
-            for t in sub:
-                if t.numel() > 1:
-                    gs.gs_sort_f64(t, workspace=ws[: gs.gs_workspace_bytes_f64(t.numel())])
-    ms_each = _time_calls(torch, stream, fn_each, 1) * (100_000 / k)
-    res["segmented"] = {"arrays": 100_000, "keys": n, "ms": round(ms_seg, 3),
-                        "gkeys_per_s": round(n / (ms_seg * 1e-3) / 1e9, 3),
-                        "per_array_launches_ms_est": round(ms_each, 1),
-                        "per_array_note": "2000 separate gs_sort_f64 calls timed, scaled to 100,000"}
-    del x, buf, o, sub, ws
+        def fn_graph(i, t):
+            if t is None:
+                buf.copy_(x)
+            else:
+                graph.replay()
+        ms_graph = _time_calls(torch, stream, fn_graph, 3)
+        buf.copy_(x)
+        graph.replay()
+        torch.cuda.synchronize()
+        ok = True
+        for k in range(0, nseg, max(1, nseg // 50)):
+            seg = buf[int(off[k]):int(off[k + 1])]
+            if seg.numel() > 1 and not bool((seg[1:] >= seg[:-1]).all().item()):
+                ok = False
+        del graph
+        # per-array plain launches on the first arrays, scaled to all
+        k = min(nseg, 2000)
+        sub = [buf[int(off[i]):int(off[i + 1])] for i in range(k)]
+        wsmax = max(gs.gs_workspace_bytes_f64(t.numel()) for t in sub)
+        ws1 = torch.empty(wsmax + 256, dtype=torch.uint8, device=dev)
+        ws1 = ws1[(-ws1.data_ptr()) % 256:][:wsmax]
+
+        def fn_each(i, t):
+            if t is None:
+                buf.copy_(x)
+            else:
+                for a in sub:
+                    if a.numel() > 1:
+                        gs.gs_sort_f64(a, workspace=ws1[: gs.gs_workspace_bytes_f64(a.numel())])
+        ms_each = _time_calls(torch, stream, fn_each, 1) * (nseg / k)
+        segres[name] = {
+            "arrays": nseg, "keys": n, "min_len": int(np.diff(off).min()), "max_len": int(np.diff(off).max()),
+            "ms_default_shape": round(ms_default, 3), "ms_tuned": round(ms_best, 3),
+            "ms_tuned_graph": round(ms_graph, 3),
+            "gkeys_per_s_tuned": round(n / (ms_best * 1e-3) / 1e9, 3),
+            "tuned_shape": best, "shape_ms": {str(i): round(v, 3) for i, v in times.items()},
+            "sorted_spot_check": ok,
+            "per_array_launches_ms_est": round(ms_each, 1),
+            "per_array_note": f"{k} separate gs_sort_f64 calls timed, scaled to {nseg}"}
+        del x, buf, o, sub, ws, ws1
+    res["segmented"] = segres
     # key-value: 2^(log2n+1) uint64 keys with uint32 payload
     log("extras: key-value")
     nk = 1 << (log2n + 1)

@@ -115,14 +115,52 @@ gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets,
                      int64_t num_segments, double buffer_fraction,
                      void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 
+/* Shape of a segmented sort (the result does not depend on it).  Segments of
+   at most short_threads * short_ipt keys are sorted in LDS, several per
+   work-group; longer ones are frog-sorted together, their merges cut into
+   tiles of 256 * merge_ipt outputs. */
+typedef struct {
+    uint32_t short_threads;  /* work-group size of the short-segment sort */
+    uint32_t short_ipt;      /* keys per thread of the short-segment sort */
+    uint32_t merge_ipt;      /* merge outputs per thread of the long segments (8 or 16) */
+    uint32_t reserved;       /* 0 */
+} gs_seg_config;
+
+/* The shapes gs_segsort_autotune tries (count, then the i-th) and the one
+   gs_segsort uses. */
+int gs_seg_config_count(void);
+gs_status gs_seg_config_get(int i, gs_seg_config *out);
+void gs_seg_default_config(gs_seg_config *out);
+
+/* gs_workspace_bytes_seg covers every shape; this one a given shape. */
+size_t gs_workspace_bytes_seg_ex(int64_t num_keys, int64_t num_segments, double buffer_fraction,
+                                 const gs_seg_config *cfg);
+
+/* gs_segsort with a given shape (host pointer; GS_EINVAL for a shape that is
+   not one of gs_seg_config_get's). */
+gs_status gs_segsort_ex(double *keys, int64_t num_keys, const int64_t *offsets, int64_t num_segments,
+                        double buffer_fraction, const gs_seg_config *cfg, void *ws, size_t ws_bytes,
+                        void *hip_stream, gs_report *rep);
+
+/* Times every shape on the caller's input and returns the fastest in *best.
+   keys (num_keys doubles) is only read: each timed run sorts a copy in
+   `scratch` (num_keys doubles, device, caller-owned); ws is sized by
+   gs_workspace_bytes_seg.  reps >= 1 runs per shape, the fastest counts;
+   times_ms (host, gs_seg_config_count() floats, may be NULL) receives each
+   shape's time.  Synchronises the stream; allocates no device memory. */
+gs_status gs_segsort_autotune(const double *keys, int64_t num_keys, const int64_t *offsets,
+                              int64_t num_segments, double *scratch, void *ws, size_t ws_bytes,
+                              void *hip_stream, int reps, gs_seg_config *best, float *times_ms);
+
 /* Stable ascending sort of n float64 keys with the same result as
    gs_sort_f64, using a small FP32 CDF network trained on the device to bucket
    the keys first.  The key-to-bucket map is verified monotone before any key
-   moves; if it is not, or a bucket would exceed 2^20 keys, or the sample has
-   no usable range, the plain path sorts the untouched input
-   (report.fallback = 1).  Inputs shorter than 4 * sample_size run the plain
-   path directly.  Extra memory stays at the half buffer (plus O(buckets *
-   waves) counters).  `p` is a host pointer (NULL = defaults). */
+   moves; if it is not, or a bucket would exceed max(2^20, a quarter of its
+   half), or the sample has no usable range, the plain path sorts the
+   untouched input (report.fallback = 1).  Inputs shorter than 4 * sample_size
+   run the plain path directly.  Extra memory stays at the half buffer (plus
+   per-tile digit counters and the network's state).  `p` is a host pointer
+   (NULL = defaults). */
 gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p,
                           void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 

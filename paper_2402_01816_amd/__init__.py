@@ -71,6 +71,20 @@ class GsLearnedParams(ctypes.Structure):
     ]
 
 
+class GsSegConfig(ctypes.Structure):
+    """Shape of a segmented sort (mirrors gs_seg_config)."""
+    _fields_ = [
+        ("short_threads", ctypes.c_uint32),
+        ("short_ipt", ctypes.c_uint32),
+        ("merge_ipt", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {"short_threads": self.short_threads, "short_ipt": self.short_ipt,
+                "merge_ipt": self.merge_ipt}
+
+
 class GsError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         self.status = status
@@ -98,6 +112,14 @@ _OPTIONAL = {
     "gs_workspace_bytes_seg": ([_I64, _I64, _D], _SZ),
     "gs_workspace_bytes_learned": ([_I64, ctypes.POINTER(GsLearnedParams)], _SZ),
     "gs_segsort": ([_P, _I64, _P, _I64, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)], ctypes.c_int),
+    "gs_seg_config_count": ([], ctypes.c_int),
+    "gs_seg_config_get": ([ctypes.c_int, ctypes.POINTER(GsSegConfig)], ctypes.c_int),
+    "gs_seg_default_config": ([ctypes.POINTER(GsSegConfig)], None),
+    "gs_workspace_bytes_seg_ex": ([_I64, _I64, _D, ctypes.POINTER(GsSegConfig)], _SZ),
+    "gs_segsort_ex": ([_P, _I64, _P, _I64, _D, ctypes.POINTER(GsSegConfig), _P, _SZ, _P,
+                       ctypes.POINTER(GsReport)], ctypes.c_int),
+    "gs_segsort_autotune": ([_P, _I64, _P, _I64, _P, _P, _SZ, _P, ctypes.c_int,
+                             ctypes.POINTER(GsSegConfig), ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "gs_learned_sort": ([_P, _I64, ctypes.POINTER(GsLearnedParams), _P, _SZ, _P,
                          ctypes.POINTER(GsReport)], ctypes.c_int),
     "gs_learned_default_params": ([ctypes.POINTER(GsLearnedParams)], None),
@@ -254,25 +276,73 @@ def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=
     return r.as_dict() if r is not None else None
 
 
+def gs_seg_configs():
+    """Every segmented-sort shape the tuner tries, as dicts (the first is the
+    default)."""
+    out = []
+    for i in range(_lib.gs_seg_config_count()):
+        c = GsSegConfig()
+        _check(_lib.gs_seg_config_get(i, ctypes.byref(c)), "gs_seg_config_get")
+        out.append(c.as_dict())
+    return out
+
+
+def _seg_config(config):
+    if config is None:
+        return None
+    c = GsSegConfig()
+    c.short_threads, c.short_ipt, c.merge_ipt = (int(config[k]) for k in
+                                                 ("short_threads", "short_ipt", "merge_ipt"))
+    return c
+
+
 def gs_segsort(keys, offsets, buffer_fraction: float = 0.5, workspace=None, stream=None,
-               report=False):
+               report=False, config=None):
     """Sort every segment keys[offsets[i]:offsets[i+1]] of a float64 device
-    tensor in place; offsets is an int64 device tensor of num_segments+1."""
+    tensor in place; offsets is an int64 device tensor of num_segments+1.
+    config: a shape from gs_seg_configs() / gs_segsort_autotune (None: the
+    default)."""
     torch = _torch()
     kp = _dev_ptr(keys, "keys", (torch.float64,))
     op = _dev_ptr(offsets, "offsets", (torch.int64,))
     nseg = max(offsets.numel() - 1, 0)
     n = keys.numel()
+    cfg = _seg_config(config)
     need = gs_workspace_bytes_seg(n, nseg, buffer_fraction)
     if need == SIZE_MAX:
         need = 0
     ws, wsb = _workspace(need, keys.device, workspace)
     r = _rep(report)
-    st = _lib.gs_segsort(kp, n, op, nseg, buffer_fraction,
-                         ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
-                         _stream_ptr(stream, keys.device), _rep_ptr(r))
+    st = _lib.gs_segsort_ex(kp, n, op, nseg, buffer_fraction,
+                            ctypes.byref(cfg) if cfg is not None else None,
+                            ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                            _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_segsort")
     return r.as_dict() if r is not None else None
+
+
+def gs_segsort_autotune(keys, offsets, reps: int = 2, workspace=None, scratch=None, stream=None):
+    """Time every segmented-sort shape on these keys (left unchanged; the runs
+    sort copies in `scratch`) and return (fastest shape, {shape index: ms})."""
+    torch = _torch()
+    kp = _dev_ptr(keys, "keys", (torch.float64,))
+    op = _dev_ptr(offsets, "offsets", (torch.int64,))
+    nseg = max(offsets.numel() - 1, 0)
+    n = keys.numel()
+    need = gs_workspace_bytes_seg(n, nseg, 0.5)
+    if need == SIZE_MAX:
+        need = 0
+    ws, wsb = _workspace(need, keys.device, workspace)
+    if scratch is None:
+        scratch = torch.empty_like(keys)
+    count = _lib.gs_seg_config_count()
+    times = (ctypes.c_float * count)()
+    best = GsSegConfig()
+    st = _lib.gs_segsort_autotune(kp, n, op, nseg, ctypes.c_void_p(scratch.data_ptr()),
+                                  ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                                  _stream_ptr(stream, keys.device), reps, ctypes.byref(best), times)
+    _check(st, "gs_segsort_autotune")
+    return best.as_dict(), {i: float(times[i]) for i in range(count)}
 
 
 def gs_learned_sort(keys, params: GsLearnedParams | None = None, workspace=None, stream=None,

@@ -87,14 +87,21 @@ struct Reporter {
     }
 };
 
-// Reads the kernels' bounded-wait error word after the stream is synchronised.
-gs_status check_err_word(const char *ws, const gs::SortPlan &p)
+// Reads the kernels' error word (a bounded wait that gave up, or a work
+// capacity exceeded) of a forest control block after the stream is
+// synchronised.
+gs_status check_err_word(const char *ctrl)
 {
     unsigned w = 0;
-    hipError_t e = hipMemcpy(&w, ws + p.off_forest + p.forest.off_ctrl + 4 * gs::kErrWord, 4, hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(&w, ctrl + 4 * gs::kErrWord, 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "reading the error word");
-    if (w) return fail(GS_EDEVICE, "an ordered-store wait exceeded its spin limit");
+    if (w) return fail(GS_EDEVICE, "a bounded device wait gave up or a work capacity was exceeded");
     return GS_OK;
+}
+
+gs_status check_err_word(const char *ws, const gs::SortPlan &p)
+{
+    return check_err_word(ws + p.off_forest + p.forest.off_ctrl);
 }
 
 struct TraceRec {
@@ -231,33 +238,93 @@ gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws,
     return s;
 }
 
+static bool to_seg_config(const gs_seg_config *c, gs::SegConfig *out)
+{
+    if (!c) {
+        *out = gs::seg_default_config();
+        return true;
+    }
+    out->short_threads = (int)c->short_threads;
+    out->short_ipt = (int)c->short_ipt;
+    out->merge_ipt = (int)c->merge_ipt;
+    return c->reserved == 0 && gs::seg_config_valid(*out);
+}
+
+int gs_seg_config_count(void) { return gs::seg_config_count(); }
+
+gs_status gs_seg_config_get(int i, gs_seg_config *out)
+{
+    g_detail.clear();
+    if (!out || i < 0 || i >= gs::seg_config_count()) return fail(GS_EINVAL, "no shape %d", i);
+    const gs::SegConfig c = gs::seg_config_at(i);
+    out->short_threads = (uint32_t)c.short_threads;
+    out->short_ipt = (uint32_t)c.short_ipt;
+    out->merge_ipt = (uint32_t)c.merge_ipt;
+    out->reserved = 0;
+    return GS_OK;
+}
+
+void gs_seg_default_config(gs_seg_config *out)
+{
+    if (out) (void)gs_seg_config_get(0, out);
+}
+
+size_t gs_workspace_bytes_seg_ex(int64_t num_keys, int64_t num_segments, double buffer_fraction,
+                                 const gs_seg_config *cfg)
+{
+    if (num_keys < 0 || num_segments < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
+    if (num_segments == 0) return 0;
+    gs::SegConfig c;
+    if (!to_seg_config(cfg, &c)) return SIZE_MAX;
+    return (size_t)gs::plan_seg(num_keys, num_segments, c).bytes;
+}
+
 size_t gs_workspace_bytes_seg(int64_t num_keys, int64_t num_segments, double buffer_fraction)
 {
     if (num_keys < 0 || num_segments < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
     if (num_segments == 0) return 0;
-    return (size_t)gs::plan_seg(num_keys, num_segments).bytes;
+    int64_t most = 0;
+    for (int i = 0; i < gs::seg_config_count(); ++i) {
+        const int64_t b = gs::plan_seg(num_keys, num_segments, gs::seg_config_at(i)).bytes;
+        if (b > most) most = b;
+    }
+    return (size_t)most;
 }
 
-gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets, int64_t num_segments,
-                     double buffer_fraction, void *ws, size_t ws_bytes, void *hip_stream,
-                     gs_report *rep)
+// Checks shared by the segmented entry points; fills the plan.
+static gs_status seg_checks(double *keys, int64_t num_keys, const int64_t *offsets, int64_t num_segments,
+                            double buffer_fraction, const gs_seg_config *cfg, void *ws, size_t ws_bytes,
+                            gs::SegPlan *p)
 {
-    g_detail.clear();
     if (num_keys < 0 || num_segments < 0) return fail(GS_EINVAL, "num_keys or num_segments < 0");
     if (num_segments > ((int64_t)1 << 31) - 2) return fail(GS_EINVAL, "num_segments above 2^31-2");
     if (num_keys > ((int64_t)1 << 40)) return fail(GS_EINVAL, "num_keys above 2^40");
     gs_status s = check_fraction(buffer_fraction);
     if (s != GS_OK) return s;
+    gs::SegConfig c;
+    if (!to_seg_config(cfg, &c)) return fail(GS_EINVAL, "unknown segmented-sort shape");
+    if (num_segments == 0) return GS_OK;
+    if (!offsets) return fail(GS_EINVAL, "offsets is NULL");
+    if (num_keys > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
+    *p = gs::plan_seg(num_keys, num_segments, c);
+    if ((int64_t)ws_bytes < p->bytes || !ws)
+        return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p->bytes);
+    if (!aligned256(ws)) return fail(GS_EINVAL, "workspace not 256-byte aligned");
+    return GS_OK;
+}
+
+gs_status gs_segsort_ex(double *keys, int64_t num_keys, const int64_t *offsets, int64_t num_segments,
+                        double buffer_fraction, const gs_seg_config *cfg, void *ws, size_t ws_bytes,
+                        void *hip_stream, gs_report *rep)
+{
+    g_detail.clear();
+    gs::SegPlan p{};
+    gs_status s = seg_checks(keys, num_keys, offsets, num_segments, buffer_fraction, cfg, ws, ws_bytes, &p);
+    if (s != GS_OK) return s;
     if (num_segments == 0) {
         if (rep) { memset(rep, 0, sizeof *rep); rep->ram_fraction = 1.0; }
         return GS_OK;
     }
-    if (!offsets) return fail(GS_EINVAL, "offsets is NULL");
-    if (num_keys > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
-    gs::SegPlan p = gs::plan_seg(num_keys, num_segments);
-    if ((int64_t)ws_bytes < p.bytes || !ws)
-        return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);
-    if (!aligned256(ws)) return fail(GS_EINVAL, "workspace not 256-byte aligned");
     if ((s = check_device()) != GS_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     Reporter r(rep, st);
@@ -272,7 +339,83 @@ gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets, int
         if (e2 != hipSuccess) return hip_fail(e2, "reading the offsets flag");
         rep->invalid_offsets = inval ? 1u : 0u;
         if (inval) return fail(GS_EINVAL, "offsets not non-decreasing within [0, num_keys]");
+        s = check_err_word((const char *)ws + p.off_forest + p.forest.off_ctrl);
     }
+    return s;
+}
+
+gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets, int64_t num_segments,
+                     double buffer_fraction, void *ws, size_t ws_bytes, void *hip_stream,
+                     gs_report *rep)
+{
+    return gs_segsort_ex(keys, num_keys, offsets, num_segments, buffer_fraction, nullptr, ws, ws_bytes,
+                         hip_stream, rep);
+}
+
+gs_status gs_segsort_autotune(const double *keys, int64_t num_keys, const int64_t *offsets,
+                              int64_t num_segments, double *scratch, void *ws, size_t ws_bytes,
+                              void *hip_stream, int reps, gs_seg_config *best, float *times_ms)
+{
+    g_detail.clear();
+    if (!best) return fail(GS_EINVAL, "best is NULL");
+    if (reps < 1) return fail(GS_EINVAL, "reps < 1");
+    if (num_keys > 0 && !scratch) return fail(GS_EINVAL, "scratch is NULL");
+    const int nc = gs::seg_config_count();
+    gs::SegPlan p{};
+    for (int i = 0; i < nc; ++i) {
+        gs_seg_config c;
+        (void)gs_seg_config_get(i, &c);
+        gs_status s = seg_checks(scratch, num_keys, offsets, num_segments, 0.5, &c, ws, ws_bytes, &p);
+        if (s != GS_OK) return s;
+    }
+    gs_seg_default_config(best);
+    if (num_segments == 0 || num_keys == 0) return GS_OK;
+    gs_status s = check_device();
+    if (s != GS_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(GS_EDEVICE, "hipEventCreate failed");
+    }
+    float best_ms = 0.f;
+    s = GS_OK;
+    for (int i = 0; i < nc && s == GS_OK; ++i) {
+        gs_seg_config c;
+        (void)gs_seg_config_get(i, &c);
+        float fastest = 0.f;
+        for (int r = 0; r <= reps && s == GS_OK; ++r) {           // run 0 warms up
+            hipError_t e = hipMemcpyAsync(scratch, keys, (size_t)num_keys * 8, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            if (e == hipSuccess) {
+                p = gs::plan_seg(num_keys, num_segments, gs::seg_config_at(i));
+                e = gs::segsort_f64_async(scratch, offsets, p, (char *)ws, st);
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                s = hip_fail(e, "timing a segmented-sort shape");
+                break;
+            }
+            if (r > 0 && (r == 1 || ms < fastest)) fastest = ms;
+        }
+        if (s != GS_OK) break;
+        unsigned inval = 0;
+        hipError_t e2 = hipMemcpy(&inval, (const char *)ws + p.off_ctrl, 4, hipMemcpyDeviceToHost);
+        if (e2 != hipSuccess) s = hip_fail(e2, "reading the offsets flag");
+        else if (inval) s = fail(GS_EINVAL, "offsets not non-decreasing within [0, num_keys]");
+        else s = check_err_word((const char *)ws + p.off_forest + p.forest.off_ctrl);
+        if (s != GS_OK) break;
+        if (times_ms) times_ms[i] = fastest;
+        if (i == 0 || fastest < best_ms) {
+            best_ms = fastest;
+            *best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return s;
 }
 

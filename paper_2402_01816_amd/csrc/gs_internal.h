@@ -47,10 +47,23 @@ struct SortPlan {
     int64_t bytes;        // total workspace
 };
 
+// Shape of a segmented sort: the work-group size and keys per thread of the
+// batched short-segment sort (their product is the LDS tile and the length
+// above which a segment goes to the forest) and the merge outputs per thread
+// of the forest's merge tiles (256 threads).
+struct SegConfig {
+    int short_threads, short_ipt, merge_ipt;
+};
+int seg_config_count();
+SegConfig seg_config_at(int i);
+SegConfig seg_default_config();
+bool seg_config_valid(const SegConfig &c);
+
 // Workspace layout of one segmented sort.
 struct SegPlan {
     int64_t num_keys, nseg;
-    int64_t tile;         // keys per LDS tile
+    SegConfig cfg;
+    int64_t tile;         // keys per short LDS tile
     int64_t off_h;        // half buffer: floor(num_keys/2) doubles
     int64_t off_ctrl;     // 64 control words
     int64_t off_cls, off_rank, off_list;   // per-segment class, rank in class, class-ordered list
@@ -58,7 +71,7 @@ struct SegPlan {
     ForestPlan forest;
     int64_t bytes;
 };
-SegPlan plan_seg(int64_t num_keys, int64_t nseg);
+SegPlan plan_seg(int64_t num_keys, int64_t nseg, const SegConfig &cfg);
 // Forest area for the long segments of up to nseg segments of at most max_len
 // keys each, num_keys keys in total.
 ForestPlan plan_forest_seg(int64_t num_keys, int64_t max_len, int64_t nseg);
@@ -74,11 +87,14 @@ hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg
 struct Prob;
 // Capacity of a forest area for up to max_probs f64 problems of at most
 // max_len keys each, num_keys keys in total.
-ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs);
+// merge_ipt: merge outputs per thread of the forest's 256-thread merge tiles
+// (8 or 16).
+ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs, int merge_ipt = 16);
 // Frog-sorts every problem of a device table (nprob: device word with the
-// number of rows) over D (keys) and H (half buffers); area fw laid out by fp.
+// number of rows) over D (keys) and H (half buffers); area fw laid out by fp
+// (planned with the same merge_ipt).
 hipError_t forest_f64_async(double *D, double *H, const Prob *probs, const unsigned *nprob, const ForestPlan &fp,
-                            char *fw, hipStream_t st, const unsigned *gate, unsigned run_if);
+                            char *fw, hipStream_t st, const unsigned *gate, unsigned run_if, int merge_ipt = 16);
 
 SortPlan plan_f64(int64_t n);
 SortPlan plan_kv(int64_t n);

@@ -22,12 +22,8 @@ namespace gs {
 
 namespace {
 
-constexpr int SEG_NT = 256;
-constexpr int SEG_IPT = 16;
-constexpr int SEG_TILE = SEG_NT * SEG_IPT;         // 4096 keys per LDS tile
-constexpr int SEG_LOG_TILE = 12;
-constexpr int SEG_SLOTS = lds_slots<SEG_TILE>();
-constexpr int SEG_CLASS_LONG = 13;                  // longer than one tile
+constexpr int SEG_CLASS_LONG = 15;                  // longer than one short tile
+constexpr int SEG_MAX_POS = 16;                     // work-list positions (long + short classes)
 
 // control words at the start of the segment workspace
 constexpr int C_INVALID = 0;
@@ -35,14 +31,22 @@ constexpr int C_TICKET = 1;
 constexpr int C_HIST = 16;                          // 16 class counters
 constexpr int C_NLONG = 48;                         // long segments handed to the forest
 
-__device__ __forceinline__ int seg_class(int64_t len)
+// Class of a segment for short tiles of 2^logt keys: 0 for at most one key,
+// c in [4, logt] for lengths in (2^(c-1), 2^c] (at least 16 keys per block),
+// SEG_CLASS_LONG above one tile.
+__device__ __forceinline__ int seg_class(int64_t len, int logt)
 {
     if (len <= 1) return 0;
-    if (len > SEG_TILE) return SEG_CLASS_LONG;
-    int c = 4;                                      // at least 16 keys per block
+    if (len > ((int64_t)1 << logt)) return SEG_CLASS_LONG;
+    int c = 4;
     while (((int64_t)1 << c) < len) ++c;
     return c;
 }
+
+// Work-list order: the long class first, then the short classes from the
+// largest blocks down.
+__device__ __forceinline__ int class_at(int pos, int logt) { return pos == 0 ? SEG_CLASS_LONG : logt - (pos - 1); }
+__device__ __forceinline__ int num_pos(int logt) { return logt - 2; }
 
 }  // namespace
 
@@ -50,7 +54,7 @@ __device__ __forceinline__ int seg_class(int64_t len)
 // 1. validate the offsets and count segments per class
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t *offsets, int64_t nseg,
-                                                           int64_t num_keys, unsigned *ctrl,
+                                                           int64_t num_keys, int logt, unsigned *ctrl,
                                                            int *cls, int *rank, Gate gate)
 {
     if (gate.closed()) return;
@@ -62,7 +66,7 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t *offset
         cls[s] = 0;
         return;
     }
-    const int c = seg_class(hi - lo);
+    const int c = seg_class(hi - lo, logt);
     cls[s] = c;
     rank[s] = (int)atomicAdd(ctrl + C_HIST + c, 1u);
 }
@@ -71,42 +75,31 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t *offset
 // 2. place segment ids into one list ordered by class
 // ---------------------------------------------------------------------------
 // First list position of class c (classes in work-list order).
-__device__ __forceinline__ int64_t class_base(const unsigned *ctrl, int c)
+__device__ __forceinline__ int64_t class_base(const unsigned *ctrl, int c, int logt)
 {
     int64_t acc = 0;
-    for (int pos = 0; pos <= 9; ++pos) {
-        const int cc = pos == 0 ? SEG_CLASS_LONG : 12 - (pos - 1);
+    for (int pos = 0; pos < num_pos(logt); ++pos) {
+        const int cc = class_at(pos, logt);
         if (cc == c) return acc;
         acc += ctrl[C_HIST + cc];
     }
     return acc;
 }
 
-__global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t nseg, const unsigned *ctrl,
-                                                          const int *cls, const int *rank,
-                                                          int *list, Gate gate)
+__global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t nseg, int logt, const unsigned *ctrl,
+                                                          const int *cls, const int *rank, int *list, Gate gate)
 {
     if (gate.closed()) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nseg || ctrl[C_INVALID]) return;
     const int c = cls[s];
     if (c == 0) return;
-    list[class_base(ctrl, c) + rank[s]] = (int)s;
+    list[class_base(ctrl, c, logt) + rank[s]] = (int)s;
 }
 
 // ---------------------------------------------------------------------------
-// 3. the persistent sorter
+// 3. the persistent sorter of the short classes
 // ---------------------------------------------------------------------------
-
-template <class KT>
-__device__ __forceinline__ void sort_tile(typename KT::T *sk, bool any_nan, int maxw)
-{
-    using KF = typename FastKey<KT>::type;
-    char dummy[1];
-    __syncthreads();
-    if (any_nan) block_sort_lds<KT, char, false, SEG_NT, SEG_IPT>(sk, dummy, maxw);
-    else block_sort_lds<KF, char, false, SEG_NT, SEG_IPT>(sk, dummy, maxw);
-}
 
 // Long segments (class SEG_CLASS_LONG, first in the work list) as forest
 // problems: the segment's keys and its slice of the half buffer, which starts
@@ -133,25 +126,33 @@ __global__ __launch_bounds__(256) void seg_probs_kernel(const int64_t *offsets, 
     probs[i] = P;
 }
 
-template <class KT>
-__global__ __launch_bounds__(SEG_NT) void seg_sort_kernel(typename KT::T *keys, const int64_t *offsets,
-                                                          unsigned *ctrl, const int *list, Gate gate)
+// Work items: batches of segments of one short class c, TILE >> c of them
+// (one per aligned block of 2^c keys of the LDS tile), sorted together.
+template <class KT, int NT, int IPT>
+__global__ __launch_bounds__(NT) void seg_sort_kernel(typename KT::T *keys, const int64_t *offsets,
+                                                      unsigned *ctrl, const int *list, Gate gate)
 {
     using K = typename KT::T;
-    __shared__ K sk[SEG_SLOTS];
+    using KF = typename FastKey<KT>::type;
+    constexpr int TILE = NT * IPT;
+    constexpr int LOGT = TILE == 2048 ? 11 : (TILE == 4096 ? 12 : (TILE == 8192 ? 13 : -1));
+    static_assert(LOGT > 0, "short tiles of 2048, 4096 or 8192 keys");
+    static_assert(TILE / 16 <= NT, "one thread per segment of the smallest class");
+    __shared__ K sk[lds_slots<TILE>()];
     __shared__ int s_item;
-    __shared__ int64_t s_off[SEG_NT];
-    __shared__ int s_len[SEG_NT];
-    __shared__ int64_t s_base[10], s_end[10];     // per work-list position
+    __shared__ int64_t s_off[NT];
+    __shared__ int s_len[NT];
+    __shared__ int64_t s_base[SEG_MAX_POS], s_end[SEG_MAX_POS];   // per work-list position
     if (gate.closed() || ctrl[C_INVALID]) return;
+    const int npos = num_pos(LOGT);
 
     // list start and cumulative work items of every class (work-list order)
     if (threadIdx.x == 0) {
         int64_t lacc = 0, iacc = 0;
-        for (int pos = 0; pos <= 9; ++pos) {
-            const int c = pos == 0 ? SEG_CLASS_LONG : 12 - (pos - 1);
+        for (int pos = 0; pos < npos; ++pos) {
+            const int c = class_at(pos, LOGT);
             const int64_t cnt = ctrl[C_HIST + c];
-            const int64_t per = pos == 0 ? 1 : (SEG_TILE >> c);
+            const int64_t per = pos == 0 ? 1 : (TILE >> c);
             s_base[pos] = lacc;
             lacc += cnt;
             if (pos > 0) iacc += (cnt + per - 1) / per;     // long segments: forest
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(SEG_NT) void seg_sort_kernel(typename KT::T *keys, 
         }
     }
     __syncthreads();
-    const int64_t total = s_end[9];
+    const int64_t total = s_end[npos - 1];
 
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(ctrl + C_TICKET, 1u);
@@ -167,13 +168,13 @@ __global__ __launch_bounds__(SEG_NT) void seg_sort_kernel(typename KT::T *keys, 
         const int64_t item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (item >= total) break;
-        int pos = 0;
+        int pos = 1;
         while (item >= s_end[pos]) ++pos;
-        const int64_t idx = item - (pos == 0 ? 0 : s_end[pos - 1]);
-        const int c = pos == 0 ? SEG_CLASS_LONG : 12 - (pos - 1);
+        const int64_t idx = item - s_end[pos - 1];
+        const int c = class_at(pos, LOGT);
         // a batch of short segments of class c, one per aligned block of P keys
         const int P_log = c;
-        const int per = SEG_TILE >> P_log;
+        const int per = TILE >> P_log;
         const int64_t first = idx * per;
         const int64_t cnt_c = ctrl[C_HIST + c];
         const int nb = (int)(cnt_c - first < per ? cnt_c - first : per);
@@ -183,12 +184,11 @@ __global__ __launch_bounds__(SEG_NT) void seg_sort_kernel(typename KT::T *keys, 
             s_len[threadIdx.x] = (int)(offsets[s + 1] - offsets[s]);
         }
         __syncthreads();
-        using KF = typename FastKey<KT>::type;
-        K r[SEG_IPT];
+        K r[IPT];
         bool nan_here = false;
 #pragma unroll
-        for (int q = 0; q < SEG_IPT; ++q) {
-            const int i = (int)threadIdx.x + q * SEG_NT;
+        for (int q = 0; q < IPT; ++q) {
+            const int i = (int)threadIdx.x + q * NT;
             const int b = i >> P_log, j = i & ((1 << P_log) - 1);
             const bool real = b < nb && j < s_len[b < nb ? b : 0];
             const int64_t p = real ? s_off[b] + j : s_off[0];
@@ -198,16 +198,21 @@ __global__ __launch_bounds__(SEG_NT) void seg_sort_kernel(typename KT::T *keys, 
         const bool any_nan = __syncthreads_or(nan_here) != 0;
         const K pad = any_nan ? KT::pad() : KF::pad();
 #pragma unroll
-        for (int q = 0; q < SEG_IPT; ++q) {
-            const int i = (int)threadIdx.x + q * SEG_NT;
+        for (int q = 0; q < IPT; ++q) {
+            const int i = (int)threadIdx.x + q * NT;
             const int b = i >> P_log, j = i & ((1 << P_log) - 1);
             const bool real = b < nb && j < s_len[b < nb ? b : 0];
             sk[lpad(i)] = real ? r[q] : pad;
         }
-        sort_tile<KT>(sk, any_nan, 1 << P_log);
+        // only the blocks that hold segments are sorted
+        const int active = nb << P_log;
+        char dummy[1];
+        __syncthreads();
+        if (any_nan) block_sort_lds<KT, char, false, NT, IPT>(sk, dummy, 1 << P_log, active);
+        else block_sort_lds<KF, char, false, NT, IPT>(sk, dummy, 1 << P_log, active);
 #pragma unroll
-        for (int q = 0; q < SEG_IPT; ++q) {
-            const int i = (int)threadIdx.x + q * SEG_NT;
+        for (int q = 0; q < IPT; ++q) {
+            const int i = (int)threadIdx.x + q * NT;
             const int b = i >> P_log, j = i & ((1 << P_log) - 1);
             if (b < nb && j < s_len[b]) keys[s_off[b] + j] = sk[lpad(i)];
         }
@@ -220,79 +225,130 @@ __global__ __launch_bounds__(SEG_NT) void seg_sort_kernel(typename KT::T *keys, 
 // ---------------------------------------------------------------------------
 static int64_t align256s(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
-// Most long segments a call can have: every one holds more than SEG_TILE keys.
-static int64_t max_long(int64_t num_keys, int64_t nseg)
+static int log2_exact(int v)
 {
-    const int64_t m = num_keys / (SEG_TILE + 1);
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// The configurations the tuner tries: short-tile shape and forest merge tile.
+static const SegConfig kSegConfigs[] = {
+    {256, 16, 16}, {256, 8, 16}, {512, 8, 16}, {512, 16, 16}, {1024, 8, 16},
+    {256, 16, 8}, {256, 8, 8}, {512, 8, 8}, {512, 16, 8}, {1024, 8, 8},
+};
+
+int seg_config_count() { return (int)(sizeof kSegConfigs / sizeof kSegConfigs[0]); }
+SegConfig seg_config_at(int i) { return kSegConfigs[i]; }
+SegConfig seg_default_config() { return kSegConfigs[0]; }
+
+bool seg_config_valid(const SegConfig &c)
+{
+    for (int i = 0; i < seg_config_count(); ++i)
+        if (kSegConfigs[i].short_threads == c.short_threads && kSegConfigs[i].short_ipt == c.short_ipt &&
+            kSegConfigs[i].merge_ipt == c.merge_ipt)
+            return true;
+    return false;
+}
+
+// Most long segments a call can have: every one holds more than a short tile.
+static int64_t max_long(int64_t num_keys, int64_t nseg, int64_t tile)
+{
+    const int64_t m = num_keys / (tile + 1);
     return m < nseg ? m : nseg;
 }
 
-SegPlan plan_seg(int64_t num_keys, int64_t nseg)
+SegPlan plan_seg(int64_t num_keys, int64_t nseg, const SegConfig &cfg)
 {
     SegPlan p{};
     p.num_keys = num_keys;
     p.nseg = nseg;
+    p.cfg = cfg;
+    p.tile = (int64_t)cfg.short_threads * cfg.short_ipt;
     p.off_h = 0;
     p.off_ctrl = align256s((num_keys / 2) * 8);
     p.off_cls = p.off_ctrl + 256;
     p.off_rank = p.off_cls + align256s(nseg * 4);
     p.off_list = p.off_rank + align256s(nseg * 4);
     p.off_forest = p.off_list + align256s(nseg * 4);
-    p.forest = plan_forest_seg(num_keys, num_keys, nseg);
+    p.forest = plan_forest_f64(num_keys, num_keys, max_long(num_keys, nseg, p.tile), cfg.merge_ipt);
     p.bytes = p.off_forest + p.forest.bytes;
-    p.tile = SEG_TILE;
     return p;
 }
 
 ForestPlan plan_forest_seg(int64_t num_keys, int64_t max_len, int64_t nseg)
 {
-    return plan_forest_f64(num_keys, max_len, max_long(num_keys, nseg));
+    return plan_forest_f64(num_keys, max_len, max_long(num_keys, nseg, 4096), 16);
 }
 
-hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys,
-                              double *hbuf, unsigned *ctrl, int *cls, int *rank, int *list, char *forest,
-                              const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st)
+template <int NT, int IPT>
+static void launch_short(double *keys, const int64_t *offsets, unsigned *ctrl, const int *list, Gate g,
+                         hipStream_t st)
 {
-    if (nseg <= 0) return hipSuccess;
-    const Gate g{gate, run_if};
-    const bool tr = trace_on();
-    if (tr) trace_begin(TK_OTHER, st);
-    launch_fill_u32(ctrl, 64, 0u, st);
-    const unsigned grid = (unsigned)((nseg + 255) / 256);
-    hipLaunchKernelGGL(seg_classify_kernel, dim3(grid), dim3(256), 0, st, offsets, nseg, num_keys, ctrl, cls,
-                       rank, g);
-    hipLaunchKernelGGL(seg_scatter_kernel, dim3(grid), dim3(256), 0, st, nseg, (const unsigned *)ctrl,
-                       (const int *)cls, (const int *)rank, list, g);
-    Prob *probs = (Prob *)(forest + fp.off_probs);
-    const int64_t maxp = fp.max_probs;
-    hipLaunchKernelGGL(seg_probs_kernel, dim3((unsigned)((maxp + 255) / 256 > 0 ? (maxp + 255) / 256 : 1)),
-                       dim3(256), 0, st, offsets, ctrl, (const int *)list, probs, maxp, fp.leaf, g);
-    if (tr) trace_end(st);
     static int64_t groups = 0;
     if (groups <= 0) {
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, seg_sort_kernel<KeyF64>, SEG_NT, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, seg_sort_kernel<KeyF64, NT, IPT>, NT, 0) !=
                 hipSuccess || per_cu <= 0)
             per_cu = 1;
         groups = (int64_t)cus * per_cu;
     }
+    hipLaunchKernelGGL((seg_sort_kernel<KeyF64, NT, IPT>), dim3((unsigned)groups), dim3(NT), 0, st, keys, offsets,
+                       ctrl, list, g);
+}
+
+static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys, double *hbuf,
+                              unsigned *ctrl, int *cls, int *rank, int *list, char *forest, const ForestPlan &fp,
+                              const SegConfig &cfg, const unsigned *gate, unsigned run_if, hipStream_t st)
+{
+    if (nseg <= 0) return hipSuccess;
+    const Gate g{gate, run_if};
+    const int logt = log2_exact(cfg.short_threads * cfg.short_ipt);
+    const bool tr = trace_on();
+    if (tr) trace_begin(TK_OTHER, st);
+    launch_fill_u32(ctrl, 64, 0u, st);
+    const unsigned grid = (unsigned)((nseg + 255) / 256);
+    hipLaunchKernelGGL(seg_classify_kernel, dim3(grid), dim3(256), 0, st, offsets, nseg, num_keys, logt, ctrl, cls,
+                       rank, g);
+    hipLaunchKernelGGL(seg_scatter_kernel, dim3(grid), dim3(256), 0, st, nseg, logt, (const unsigned *)ctrl,
+                       (const int *)cls, (const int *)rank, list, g);
+    Prob *probs = (Prob *)(forest + fp.off_probs);
+    const int64_t maxp = fp.max_probs;
+    hipLaunchKernelGGL(seg_probs_kernel, dim3((unsigned)((maxp + 255) / 256 > 0 ? (maxp + 255) / 256 : 1)),
+                       dim3(256), 0, st, offsets, ctrl, (const int *)list, probs, maxp, fp.leaf, g);
+    if (tr) trace_end(st);
     if (tr) trace_begin(TK_SEGSORT, st);
-    hipLaunchKernelGGL(seg_sort_kernel<KeyF64>, dim3((unsigned)groups), dim3(SEG_NT), 0, st, keys, offsets, ctrl,
-                       (const int *)list, g);
+    const int key = cfg.short_threads * 100 + cfg.short_ipt;
+    switch (key) {
+    case 25608: launch_short<256, 8>(keys, offsets, ctrl, list, g, st); break;
+    case 25616: launch_short<256, 16>(keys, offsets, ctrl, list, g, st); break;
+    case 51208: launch_short<512, 8>(keys, offsets, ctrl, list, g, st); break;
+    case 51216: launch_short<512, 16>(keys, offsets, ctrl, list, g, st); break;
+    case 102408: launch_short<1024, 8>(keys, offsets, ctrl, list, g, st); break;
+    default: return hipErrorInvalidValue;
+    }
     if (tr) trace_end(st);
     if (maxp <= 0) return hipGetLastError();
-    return forest_f64_async(keys, hbuf, probs, ctrl + C_NLONG, fp, forest, st, gate, run_if);
+    return forest_f64_async(keys, hbuf, probs, ctrl + C_NLONG, fp, forest, st, gate, run_if, cfg.merge_ipt);
+}
+
+hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys,
+                              double *hbuf, unsigned *ctrl, int *cls, int *rank, int *list, char *forest,
+                              const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st)
+{
+    return segsort_run(keys, offsets, nseg, num_keys, hbuf, ctrl, cls, rank, list, forest, fp,
+                       seg_default_config(), gate, run_if, st);
 }
 
 hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan &p, char *ws,
                              hipStream_t st)
 {
-    return segsort_core_async(keys, offsets, p.nseg, p.num_keys, (double *)(ws + p.off_h),
-                              (unsigned *)(ws + p.off_ctrl), (int *)(ws + p.off_cls), (int *)(ws + p.off_rank),
-                              (int *)(ws + p.off_list), ws + p.off_forest, p.forest, nullptr, 0u, st);
+    return segsort_run(keys, offsets, p.nseg, p.num_keys, (double *)(ws + p.off_h), (unsigned *)(ws + p.off_ctrl),
+                       (int *)(ws + p.off_cls), (int *)(ws + p.off_rank), (int *)(ws + p.off_list),
+                       ws + p.off_forest, p.forest, p.cfg, nullptr, 0u, st);
 }
 
 }  // namespace gs

@@ -546,6 +546,18 @@ struct SortCfg<KeyF64, NoVal> {
     static constexpr int LEAF_NT = GS_F64_LEAF_NT, LEAF_IPT = GS_F64_LEAF_IPT, LEAF_WAVES = 4;
     static constexpr int MERGE_NT = GS_F64_MERGE_NT, MERGE_IPT = GS_F64_MERGE_IPT, MERGE_WAVES = 3;
 };
+// the same f64 comparison with 2048-output merge tiles (a shape the
+// segmented sort's tuner can choose)
+struct KeyF64T8 : KeyF64 {};
+template <>
+struct FastKey<KeyF64T8> {
+    using type = KeyF64NoNaN;
+};
+template <>
+struct SortCfg<KeyF64T8, NoVal> {
+    static constexpr int LEAF_NT = GS_F64_LEAF_NT, LEAF_IPT = GS_F64_LEAF_IPT, LEAF_WAVES = 4;
+    static constexpr int MERGE_NT = 256, MERGE_IPT = 8, MERGE_WAVES = 4;
+};
 template <>
 struct SortCfg<KeyU64, uint32_t> {
     static constexpr int LEAF_NT = 256, LEAF_IPT = 16, LEAF_WAVES = 2;
@@ -759,8 +771,9 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
 SortPlan plan_f64(int64_t n) { return make_plan<KeyF64, NoVal>(n); }
 SortPlan plan_kv(int64_t n) { return make_plan<KeyU64, uint32_t>(n); }
 
-ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs)
+ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs, int merge_ipt)
 {
+    if (merge_ipt == 8) return forest_plan_many<KeyF64T8, NoVal>(num_keys, max_len, max_probs);
     return forest_plan_many<KeyF64, NoVal>(num_keys, max_len, max_probs);
 }
 
@@ -777,11 +790,14 @@ hipError_t sort_kv_async(uint64_t *keys, uint32_t *vals, int64_t n, char *ws, co
 }
 
 hipError_t forest_f64_async(double *D, double *H, const Prob *probs, const unsigned *nprob, const ForestPlan &fp,
-                            char *fw, hipStream_t st, const unsigned *gate, unsigned run_if)
+                            char *fw, hipStream_t st, const unsigned *gate, unsigned run_if, int merge_ipt)
 {
     Forest F{};
     F.probs = probs;
     F.nprob = nprob;
+    if (merge_ipt == 8)
+        return run_forest<KeyF64T8, NoVal>(D, H, (NoVal *)nullptr, (NoVal *)nullptr, F, fp, fw, st,
+                                           Gate{gate, run_if}, true);
     return run_forest<KeyF64, NoVal>(D, H, (NoVal *)nullptr, (NoVal *)nullptr, F, fp, fw, st, Gate{gate, run_if},
                                      true);
 }

@@ -146,3 +146,31 @@ def test_forest_capacity_bounds(seed):
             s += b
         assert t <= (cap_leaves if rnd == 0 else cap_t)
         assert s <= cap_s
+
+
+def test_segsort_shapes_and_errors():
+    shapes = g.gs_seg_configs()
+    assert len(shapes) == g.lib.gs_seg_config_count() >= 2
+    assert shapes[0] == {"short_threads": 256, "short_ipt": 16, "merge_ipt": 16}
+    c = g.GsSegConfig()
+    assert g.lib.gs_seg_config_get(len(shapes), ctypes.byref(c)) == g.GS_EINVAL
+    assert g.lib.gs_seg_config_get(-1, ctypes.byref(c)) == g.GS_EINVAL
+    top = g.gs_workspace_bytes_seg(1 << 24, 5000)
+    for s in shapes:
+        cs = g._seg_config(s)
+        b = g.lib.gs_workspace_bytes_seg_ex(1 << 24, 5000, 0.5, ctypes.byref(cs))
+        assert 8 * (1 << 23) <= b <= top
+    bad = g.GsSegConfig(300, 16, 16, 0)
+    assert g.lib.gs_workspace_bytes_seg_ex(1 << 20, 10, 0.5, ctypes.byref(bad)) == g.SIZE_MAX
+    fake = ctypes.c_void_p(0x100000)
+    need = g.gs_workspace_bytes_seg(1000, 10)
+    assert g.lib.gs_segsort_ex(fake, 1000, fake, 10, 0.5, ctypes.byref(bad), fake, need, None,
+                               None) == g.GS_EINVAL
+    reserved = g.GsSegConfig(256, 16, 16, 1)
+    assert g.lib.gs_segsort_ex(fake, 1000, fake, 10, 0.5, ctypes.byref(reserved), fake, need, None,
+                               None) == g.GS_EINVAL
+    best = g.GsSegConfig()
+    assert g.lib.gs_segsort_autotune(fake, 1000, fake, 10, None, fake, need, None, 1,
+                                     ctypes.byref(best), None) == g.GS_EINVAL
+    assert g.lib.gs_segsort_autotune(fake, 1000, fake, 10, fake, fake, need, None, 0,
+                                     ctypes.byref(best), None) == g.GS_EINVAL

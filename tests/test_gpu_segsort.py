@@ -81,6 +81,36 @@ def test_segsort_draw_until_total(gs, orc):
     _check(orc, t, x, off)
 
 
+@pytest.mark.parametrize("shape", range(10))
+def test_segsort_every_shape(gs, orc, shape):
+    """Every shape the tuner can pick gives the same (oracle) result on a mix
+    of short and long segments, ±0 ties included."""
+    cfg = gs.gs_seg_configs()[shape]
+    announce("segsort shape", cfg)
+    x, off = W.segmented(1500, 1, 40000, seed=20 + shape)
+    x = x.copy()
+    x[::7] = -0.0
+    x[::11] = 0.0
+    t, _ = _run(gs, x, off, config=cfg)
+    _check(orc, t, x, off)
+
+
+def test_segsort_autotune(gs, orc):
+    """The tuner leaves the input untouched, times every shape and returns one
+    of them; sorting with it matches the oracle."""
+    announce("segsort autotune")
+    x, off = W.segmented(3000, 16, 30000, seed=31)
+    keys = to_dev(x)
+    offs = to_dev(off)
+    best, times = gs.gs_segsort_autotune(keys, offs, reps=1)
+    assert np.array_equal(bits(keys), bits(x))
+    assert best in gs.gs_seg_configs()
+    assert len(times) == len(gs.gs_seg_configs()) and all(v > 0 for v in times.values())
+    assert times[gs.gs_seg_configs().index(best)] == min(times.values())
+    gs.gs_segsort(keys, offs, config=best)
+    _check(orc, keys, x, off)
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_segsort_random_mix(gs, orc, seed):
     announce("segsort mix", seed)

@@ -208,8 +208,8 @@ __global__ __launch_bounds__(NT) void seg_sort_kernel(typename KT::T *keys, cons
         const int active = nb << P_log;
         char dummy[1];
         __syncthreads();
-        if (any_nan) block_sort_lds<KT, char, false, NT, IPT>(sk, dummy, 1 << P_log, active);
-        else block_sort_lds<KF, char, false, NT, IPT>(sk, dummy, 1 << P_log, active);
+        if (any_nan) block_sort_lds<KT, char, false, NT, IPT, true>(sk, dummy, 1 << P_log, active);
+        else block_sort_lds<KF, char, false, NT, IPT, true>(sk, dummy, 1 << P_log, active);
 #pragma unroll
         for (int q = 0; q < IPT; ++q) {
             const int i = (int)threadIdx.x + q * NT;

@@ -33,6 +33,19 @@ void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st)
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, count, v);
 }
 
+// Every key is read once and written once per level: the leaf and merge
+// accesses can bypass the caches' normal retention.
+#ifndef GS_MERGE_NT
+#define GS_MERGE_NT 1
+#endif
+#if GS_MERGE_NT
+#define GS_MERGE_LOAD(ptr) __builtin_nontemporal_load(ptr)
+#define GS_MERGE_STORE(v, ptr) __builtin_nontemporal_store((v), (ptr))
+#else
+#define GS_MERGE_LOAD(ptr) (*(ptr))
+#define GS_MERGE_STORE(v, ptr) (*(ptr) = (v))
+#endif
+
 // ---------------------------------------------------------------------------
 // leaf kernel: sort each leaf's input chunk and place it at its frog slot
 // ---------------------------------------------------------------------------
@@ -96,7 +109,7 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
             for (int r = 0; r < IPT; ++r) {
                 const int i = tid + r * NT;
                 const int ic = min(i, len - 1);
-                lk[r] = keys.D[src + ic];
+                lk[r] = GS_MERGE_LOAD(keys.D + src + ic);
                 if constexpr (HV) lv[r] = vals.D[src + ic];
             }
 #pragma unroll
@@ -116,15 +129,18 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         __syncthreads();
         if (tid == 0) st_status(status + t, (epoch << 2) | ST_LOADED);
 
-        // a leaf of at most half a tile is sorted in the smallest power-of-two
-        // prefix holding it; the slots past it are padding
-        int maxw = TILE;
-        if (len <= TILE / 2) {
-            maxw = IPT;
+        // a short leaf (keys-only sorts: the forest's segments and buckets
+        // have them) is sorted in the smallest power-of-two prefix holding
+        // it, skipping the work on the padding past it
+        if (HV || len == TILE) {
+            if (nan_here) block_sort_lds<KT, VS, HV, NT, IPT>(sk, sv);
+            else block_sort_lds<KF, VS, HV, NT, IPT>(sk, sv);
+        } else if constexpr (!HV) {
+            int maxw = IPT;
             while (maxw < len) maxw *= 2;
+            if (nan_here) block_sort_lds<KT, VS, HV, NT, IPT, true>(sk, sv, maxw, len);
+            else block_sort_lds<KF, VS, HV, NT, IPT, true>(sk, sv, maxw, len);
         }
-        if (nan_here) block_sort_lds<KT, VS, HV, NT, IPT>(sk, sv, maxw, maxw);
-        else block_sort_lds<KF, VS, HV, NT, IPT>(sk, sv, maxw, maxw);
 
         // wait for the leaves whose input chunks the destination covers
         if (tid < 64 && dst < P.n) {
@@ -139,7 +155,7 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         for (int r = 0; r < IPT; ++r) {
             const int i = tid + r * NT;
             if (i < len) {
-                *keys.at(dst + i) = sk[lpad(i)];
+                GS_MERGE_STORE(sk[lpad(i)], keys.at(dst + i));
                 if constexpr (HV) *vals.at(dst + i) = sv[lpad(i)];
             }
         }
@@ -385,6 +401,7 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
     }
 }
 
+
 // ---------------------------------------------------------------------------
 // merge kernel: persistent work-groups, one output tile per iteration
 // ---------------------------------------------------------------------------
@@ -434,7 +451,7 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
         for (int r = 0; r < IPT; ++r) {
             const int i = min(tid + r * NT, last);
             const int64_t p = i < T.la ? T.pa + i : T.pb + (i - T.la);
-            lk[r] = *ks.at(p);
+            lk[r] = GS_MERGE_LOAD(ks.at(p));
             if constexpr (HV) {
                 const Space<V> vs{Dv + P.doff, Hv + P.hoff, P.n};
                 lv[r] = *vs.at(p);
@@ -505,7 +522,7 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
             for (int r = 0; r < IPT; ++r) {
                 const int i = tid + r * NT;
                 if (i < cur.cnt) {
-                    *ks.at(cur.o + i) = sk[lpad(i)];
+                    GS_MERGE_STORE(sk[lpad(i)], ks.at(cur.o + i));
                     if constexpr (HV) {
                         const Space<V> vs{Dv + cur_p.doff, Hv + cur_p.hoff, cur_p.n};
                         *vs.at(cur.o + i) = sv[lpad(i)];

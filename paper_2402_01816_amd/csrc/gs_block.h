@@ -63,9 +63,10 @@ __device__ __forceinline__ void serial_merge(const typename KT::T *sk, int a_bas
 // two in [IPT, TILE]): each aligned block of maxw keys ends up sorted on its
 // own, which lets one work-group sort several short arrays at once.  With
 // PARTIAL, the caller guarantees that slots at or past `active` hold only
-// padding (which sorts after every real key and is therefore already in
-// place): a thread skips its per-thread sort when its keys all lie there, and
-// a merge when both runs of its pair do.
+// padding, which sorts after every real key.  Then within every merge pair the
+// real keys stay at the front, so slots at or past `active` hold padding after
+// every round too, and a thread whose keys or outputs all lie there skips its
+// work.
 template <class KT, class VS, bool HV, int NT, int IPT, bool PARTIAL = false>
 __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int maxw = NT * IPT,
                                                int active = NT * IPT)
@@ -77,7 +78,7 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
     VS v[IPT];
     int srcix[IPT];
     const int base = tid * IPT;
-    const bool work = !PARTIAL || base < active;     // per-thread sort
+    const bool work = !PARTIAL || base < active;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         k[i] = sk[lpad(base + i)];
@@ -113,9 +114,8 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
     __syncthreads();
 
     for (int w = IPT; w < maxw; w *= 2) {
-        const int a0 = (base / (2 * w)) * 2 * w;
-        const bool mwork = !PARTIAL || a0 < active;  // this pair holds real keys
-        if (mwork) {
+        if (work) {
+            const int a0 = (base / (2 * w)) * 2 * w;
             const int b0 = a0 + w;
             const int kd = base - a0;
             const int ai = merge_path_lds<KT>(kd, w, w, [&](int i) { return sk[lpad(a0 + i)]; },
@@ -127,7 +127,7 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
             }
         }
         __syncthreads();
-        if (mwork) {
+        if (work) {
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 sk[lpad(base + i)] = k[i];

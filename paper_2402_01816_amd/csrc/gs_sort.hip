@@ -54,10 +54,9 @@ void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st)
 // which is never before its input offset.  A leaf's output can therefore only
 // cover input chunks of leaves with a larger index: leaves take tickets in
 // descending index order, and each waits for the leaves whose chunks its
-// output covers.  With LOOP, persistent work-groups take tickets until the
-// round is done (a problem table, whose leaf count only the device knows);
-// without, every work-group takes one ticket (grid = leaves).
-template <class KT, class V, int NT, int IPT, int WAVES, bool LOOP>
+// output covers.  Every work-group takes one ticket; with a problem table the
+// grid is the capacity and work-groups past the device's leaf count exit.
+template <class KT, class V, int NT, int IPT, int WAVES>
 __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv,
                                                   Forest F, unsigned *ticket_ctr, unsigned *status,
                                                   unsigned epoch, unsigned *err, Gate gate)
@@ -76,7 +75,7 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
     const int tid = threadIdx.x;
     const int64_t L = F.probs ? (int64_t)*F.nprob : 1;
     const int64_t total = F.probs ? (int64_t)F.tbase[L] : ((int64_t)1 << F.p0.depth);
-    for (;;) {
+    do {
         if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
         __syncthreads();
         const int64_t t = __builtin_amdgcn_readfirstlane(s_ticket);
@@ -159,8 +158,7 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
                 if constexpr (HV) *vals.at(dst + i) = sv[lpad(i)];
             }
         }
-        if constexpr (!LOOP) break;
-    }
+    } while (false);
 }
 
 // ---------------------------------------------------------------------------
@@ -712,18 +710,17 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         if (tr) trace_end(st);
     }
 
-    auto leaf_fn = leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, false>;
-    auto leaf_loop_fn = leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, true>;
+    auto leaf_fn = leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES>;
     auto merge_fn = merge_kernel<KT, V, C::MERGE_NT, C::MERGE_IPT, C::MERGE_WAVES>;
-    static int64_t leaf_groups = 0, merge_groups = 0;
+    static int64_t merge_groups = 0;
     unsigned epoch = 1;
     if (leaves) {
         if (tr) trace_begin(TK_LEAF, st);
         if (table) {
-            const int64_t res = resident_groups(leaf_loop_fn, C::LEAF_NT, leaf_groups);
-            const int64_t items = fp.max_status;
-            hipLaunchKernelGGL(leaf_loop_fn, dim3((unsigned)(items < res ? items : res)), dim3(C::LEAF_NT), 0, st,
-                               Dk, Hk, Dv, Hv, F, ctrl + 0, status, epoch, errw, gate);
+            // one leaf per work-group; work-groups past the device's leaf
+            // count exit at once
+            hipLaunchKernelGGL(leaf_fn, dim3((unsigned)fp.max_status), dim3(C::LEAF_NT), 0, st, Dk, Hk, Dv, Hv, F,
+                               ctrl + 0, status, epoch, errw, gate);
         } else {
             hipLaunchKernelGGL(leaf_fn, dim3((unsigned)((int64_t)1 << F.p0.depth)), dim3(C::LEAF_NT), 0, st, Dk,
                                Hk, Dv, Hv, F, ctrl + 0, status, epoch, errw, gate);

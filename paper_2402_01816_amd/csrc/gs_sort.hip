@@ -547,19 +547,25 @@ struct SortCfg;
 #ifndef GS_F64_LEAF_IPT
 #define GS_F64_LEAF_IPT 16
 #endif
+#ifndef GS_F64_LEAF_WAVES
+#define GS_F64_LEAF_WAVES 4
+#endif
 #ifndef GS_F64_MERGE_NT
 #define GS_F64_MERGE_NT 256
 #endif
 #ifndef GS_F64_MERGE_IPT
 #define GS_F64_MERGE_IPT 16
 #endif
+#ifndef GS_F64_MERGE_WAVES
+#define GS_F64_MERGE_WAVES 3
+#endif
 // LEAF_WAVES / MERGE_WAVES: waves per SIMD each kernel is compiled to allow
 // (the register budget), chosen so that the LDS, not the registers, limits
 // the work-groups per compute unit.
 template <>
 struct SortCfg<KeyF64, NoVal> {
-    static constexpr int LEAF_NT = GS_F64_LEAF_NT, LEAF_IPT = GS_F64_LEAF_IPT, LEAF_WAVES = 4;
-    static constexpr int MERGE_NT = GS_F64_MERGE_NT, MERGE_IPT = GS_F64_MERGE_IPT, MERGE_WAVES = 3;
+    static constexpr int LEAF_NT = GS_F64_LEAF_NT, LEAF_IPT = GS_F64_LEAF_IPT, LEAF_WAVES = GS_F64_LEAF_WAVES;
+    static constexpr int MERGE_NT = GS_F64_MERGE_NT, MERGE_IPT = GS_F64_MERGE_IPT, MERGE_WAVES = GS_F64_MERGE_WAVES;
 };
 // the same f64 comparison with 2048-output merge tiles (a shape the
 // segmented sort's tuner can choose)
@@ -573,10 +579,25 @@ struct SortCfg<KeyF64T8, NoVal> {
     static constexpr int LEAF_NT = GS_F64_LEAF_NT, LEAF_IPT = GS_F64_LEAF_IPT, LEAF_WAVES = 4;
     static constexpr int MERGE_NT = 256, MERGE_IPT = 8, MERGE_WAVES = 4;
 };
+#ifndef GS_KV_LEAF_NT
+#define GS_KV_LEAF_NT 512
+#endif
+#ifndef GS_KV_LEAF_WAVES
+#define GS_KV_LEAF_WAVES 6
+#endif
+#ifndef GS_KV_LEAF_IPT
+#define GS_KV_LEAF_IPT 8
+#endif
+#ifndef GS_KV_MERGE_IPT
+#define GS_KV_MERGE_IPT 16
+#endif
+#ifndef GS_KV_MERGE_WAVES
+#define GS_KV_MERGE_WAVES 2
+#endif
 template <>
 struct SortCfg<KeyU64, uint32_t> {
-    static constexpr int LEAF_NT = 256, LEAF_IPT = 16, LEAF_WAVES = 2;
-    static constexpr int MERGE_NT = 256, MERGE_IPT = 8, MERGE_WAVES = 4;
+    static constexpr int LEAF_NT = GS_KV_LEAF_NT, LEAF_IPT = GS_KV_LEAF_IPT, LEAF_WAVES = GS_KV_LEAF_WAVES;
+    static constexpr int MERGE_NT = 256, MERGE_IPT = GS_KV_MERGE_IPT, MERGE_WAVES = GS_KV_MERGE_WAVES;
 };
 
 template <class KT, class V>

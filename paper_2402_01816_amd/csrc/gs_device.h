@@ -160,7 +160,8 @@ struct TileDesc {
     int64_t o;        // logical slot of its first output
     unsigned dlo, dhi;       // dependency window (tickets, inclusive; empty if dlo > dhi)
     int la, cnt;      // first-run inputs, total inputs (= outputs)
-    int prob, pad;    // its problem (row of the table; 0 for the inline problem)
+    int prob;         // its problem (row of the table; 0 for the inline problem)
+    int skip;         // 1: empty, or every output already sits in its slot
 };
 
 // ---------------------------------------------------------------------------

@@ -11,9 +11,15 @@ namespace gs {
 // bounded wait gave up; it is cleared with the counters on every call.
 constexpr int kErrWord = 63;
 
-// Control words of a forest run: ticket counters of rounds 0..62 and the
-// error word.
-constexpr int kForestCtrlWords = 64;
+// Control words of a forest run: the leaf ticket counter (word 0), the
+// error word, and per merge round r >= 1 kMergeGroups ticket counters, each on
+// its own 128-byte line starting at word 32 * (kMergeGroups * r + g).
+#ifndef GS_MERGE_GROUPS
+#define GS_MERGE_GROUPS 8
+#endif
+constexpr int kMergeGroups = GS_MERGE_GROUPS;
+constexpr int kMaxRounds = 47;
+constexpr int kForestCtrlWords = 32 * kMergeGroups * (kMaxRounds + 1);
 
 // Layout of the area a forest run (one or many frog trees) works in, from
 // offset 0 of that area.

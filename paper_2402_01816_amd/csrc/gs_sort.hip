@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
         if (k1 > nn) k1 = nn;
         TileDesc T;
         T.prob = (int)s;
-        T.pad = 0;
+        T.skip = 0;
         T.cnt = (int)(k1 - k0);
         T.la = 0;
         T.pa = T.pb = T.o = 0;
@@ -395,6 +395,11 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
         }
         T.dlo = (unsigned)lo;
         T.dhi = (unsigned)hi;
+        // A tile that takes all its inputs from one run at the very slots it
+        // writes (the outer run's elements that stay in place, which is half
+        // of every merge on presorted input: "Symmetric merging") moves
+        // nothing; nobody else writes into its range, so it needs no wait.
+        T.skip = T.cnt == 0 || (T.la == T.cnt && T.pa == T.o) || (T.la == 0 && T.pb == T.o);
         desc[t] = T;
     }
 }
@@ -406,9 +411,19 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
 // A left node writes its output top-down (its outer run is the left child's
 // data, which only moves right); a right node bottom-up (its outer run is the
 // right child's data, which only moves left).  Inner runs lie outside the
-// output.  Tickets are handed out in each node's write order.  A work-group
-// takes the next ticket and issues that tile's loads while it merges and
-// stores the current one.
+// output.  Tickets are handed out in each node's write order, in chunks of
+// GS_MERGE_CLAIM consecutive tickets; chunk j belongs to counter group
+// j % kMergeGroups, and work-group b claims from group b % kMergeGroups, each
+// counter on its own cache line (a single device-wide counter limits the rate
+// at which tiles can start).  A work-group takes the next ticket and issues
+// that tile's loads while it merges and stores the current one.  It processes
+// its tickets in increasing order and waits only on smaller tickets; the
+// smallest ticket not yet loaded is always claimed (every group's earlier
+// tickets have loaded, so its work-groups finish them and claim on), so the
+// waits cannot deadlock.
+#ifndef GS_MERGE_CLAIM
+#define GS_MERGE_CLAIM 1
+#endif
 template <class KT, class V, int NT, int IPT, int WAVES>
 __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv,
                                                    Forest F, int round, const TileDesc *desc,
@@ -420,6 +435,7 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
     using VS = typename std::conditional<HV, V, char>::type;
     constexpr int TILE = NT * IPT;
     constexpr int SLOTS = lds_slots<TILE>();
+    constexpr int CLAIM = GS_MERGE_CLAIM;
     __shared__ K sk[SLOTS];
     __shared__ VS sv[HV ? SLOTS : 1];
     __shared__ unsigned s_next;
@@ -428,14 +444,18 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
     const int64_t ntiles = F.probs ? (int64_t)F.tbase[(int64_t)round * F.stride + *F.nprob]
                                    : forest_tickets<TILE>(F, F.p0, round);
     const int tid = threadIdx.x;
-    if (tid == 0) s_next = atomicAdd(ticket_ctr, 1u);
+    const int grp = (int)(blockIdx.x % kMergeGroups);
+    unsigned *my_ctr = ticket_ctr + 32 * grp;
+    // first ticket of the chunk a claim returns
+    auto chunk_start = [&](unsigned c) -> int64_t { return ((int64_t)c * kMergeGroups + grp) * CLAIM; };
+    if (tid == 0) s_next = atomicAdd(my_ctr, 1u);
     __syncthreads();
-    int64_t t = __builtin_amdgcn_readfirstlane(s_next);
-    if (t >= ntiles) return;
+    int64_t cur_t = chunk_start(__builtin_amdgcn_readfirstlane(s_next));
+    int slot = 0;                        // position of cur_t within its chunk
+    if (cur_t >= ntiles) return;
 
-    TileDesc cur = desc[t];
+    TileDesc cur = desc[cur_t];
     Prob cur_p = forest_prob(F, cur.prob);
-    int64_t cur_t = t;
     K lk[IPT];
     VS lv[IPT];
     // Straight-line loads: indices past the tile are clamped to its last input
@@ -456,22 +476,25 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
             }
         }
     };
-    issue_loads(cur, cur_p);
+    if (!cur.skip) issue_loads(cur, cur_p);
 
     for (;;) {
         // stage the current tile in LDS and publish that its inputs are read
         // (slots past the tile receive ignored values)
+        if (!cur.skip) {
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const int i = tid + r * NT;
-            sk[lpad(i)] = lk[r];
-            if constexpr (HV) sv[lpad(i)] = lv[r];
+            for (int r = 0; r < IPT; ++r) {
+                const int i = tid + r * NT;
+                sk[lpad(i)] = lk[r];
+                if constexpr (HV) sv[lpad(i)] = lv[r];
+            }
         }
         __syncthreads();
+        const bool last_of_claim = slot == CLAIM - 1;
         unsigned nt = 0;
         if (tid == 0) {
             st_status(status + cur_t, (epoch << 2) | ST_LOADED);
-            nt = atomicAdd(ticket_ctr, 1u);
+            if (last_of_claim) nt = atomicAdd(my_ctr, 1u);
         }
 
         // merge: thread tid produces outputs [tid*IPT, tid*IPT + nout)
@@ -479,7 +502,7 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
         VS v[IPT];
         int srcix[IPT];
         const int d = tid * IPT;
-        int nout = cur.cnt - d;
+        int nout = cur.skip ? 0 : cur.cnt - d;
         nout = nout < 0 ? 0 : (nout > IPT ? IPT : nout);
         const int la = cur.la, lb = cur.cnt - cur.la;
         if (nout > 0) {
@@ -491,30 +514,32 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
                 for (int i = 0; i < IPT; ++i) v[i] = sv[lpad(min(srcix[i], TILE))];
             }
         }
-        if (tid == 0) s_next = nt;
-        __syncthreads();
+        if (last_of_claim) {
+            if (tid == 0) s_next = nt;
+            __syncthreads();
+        }
 
         // prefetch the next tile while this one waits and stores
-        const int64_t t2 = __builtin_amdgcn_readfirstlane(s_next);
+        const int64_t t2 = last_of_claim ? chunk_start(__builtin_amdgcn_readfirstlane(s_next)) : cur_t + 1;
         const bool more = t2 < ntiles;
         TileDesc nxt;
         Prob nxt_p;
         if (more) {
             nxt = desc[t2];
             nxt_p = forest_prob(F, nxt.prob);
-            issue_loads(nxt, nxt_p);
+            if (!nxt.skip) issue_loads(nxt, nxt_p);
         }
-        if (tid < 64) wait_window(status, cur.dlo, cur.dhi, cur_t, epoch, err);
-        __syncthreads();
+        if (!cur.skip) {
+            if (tid < 64) wait_window(status, cur.dlo, cur.dhi, cur_t, epoch, err);
+            __syncthreads();
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            if (i < nout) {
-                sk[lpad(d + i)] = k[i];
-                if constexpr (HV) sv[lpad(d + i)] = v[i];
+            for (int i = 0; i < IPT; ++i) {
+                if (i < nout) {
+                    sk[lpad(d + i)] = k[i];
+                    if constexpr (HV) sv[lpad(d + i)] = v[i];
+                }
             }
-        }
-        __syncthreads();
-        {
+            __syncthreads();
             const Space<K> ks{Dk + cur_p.doff, Hk + cur_p.hoff, cur_p.n};
 #pragma unroll
             for (int r = 0; r < IPT; ++r) {
@@ -533,6 +558,7 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
         cur = nxt;
         cur_p = nxt_p;
         cur_t = t2;
+        slot = last_of_claim ? 0 : slot + 1;
     }
 }
 
@@ -717,6 +743,7 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         F.stride = fp.stride;
     }
     const int R = F.use_m1 ? 1 : fp.rounds;
+    if (R > kMaxRounds) return hipErrorInvalidValue;
 
     const bool tr = trace_on();
     // ticket counters and status words start at zero on every call
@@ -763,7 +790,8 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         if (tr) trace_end(st);
         if (tr) trace_begin(TK_MERGE, st);
         hipLaunchKernelGGL(merge_fn, dim3((unsigned)(ntile < mres ? ntile : mres)), dim3(C::MERGE_NT), 0, st, Dk,
-                           Hk, Dv, Hv, F, r, (const TileDesc *)desc, ctrl + r, status, epoch, errw, gate);
+                           Hk, Dv, Hv, F, r, (const TileDesc *)desc, ctrl + 32 * kMergeGroups * r, status, epoch,
+                           errw, gate);
         if (tr) trace_end(st);
     }
     return hipGetLastError();

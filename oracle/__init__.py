@@ -52,6 +52,10 @@ def _load():
     lib.oracle_sort_f64.restype = ctypes.c_int
     lib.oracle_sort_kv.argtypes = [P, P, I64]
     lib.oracle_sort_kv.restype = ctypes.c_int
+    lib.oracle_sort_f64_target.argtypes = [P, I64, ctypes.c_int]
+    lib.oracle_sort_f64_target.restype = ctypes.c_int
+    lib.oracle_sort_kv_target.argtypes = [P, P, I64, ctypes.c_int]
+    lib.oracle_sort_kv_target.restype = ctypes.c_int
     lib.oracle_segsort_f64.argtypes = [P, P, I64]
     lib.oracle_segsort_f64.restype = ctypes.c_int
     lib.oracle_segsort_kv.argtypes = [P, P, P, I64]
@@ -103,6 +107,29 @@ def sort_kv(keys: np.ndarray, vals: np.ndarray):
         raise ValueError("keys and vals differ in shape")
     if _load().oracle_sort_kv(_ptr(k), _ptr(v), k.size) != 0:
         raise MemoryError("oracle_sort_kv: allocation failed")
+    return k, v
+
+
+TARGETS = {"AscLeft": 0, "AscRight": 1, "DescLeft": 2, "DescRight": 3}
+
+
+def sort_f64_target(x: np.ndarray, target: str) -> np.ndarray:
+    """One of the four stable targets ("Definition of sorting"): ascending or
+    descending keys, ties in input order (Left) or reverse input order
+    (Right); returns a new array."""
+    y = np.array(x, dtype=np.float64, copy=True, order="C")
+    if _load().oracle_sort_f64_target(_ptr(y), y.size, TARGETS[target]) != 0:
+        raise MemoryError("oracle_sort_f64_target failed")
+    return y
+
+
+def sort_kv_target(keys: np.ndarray, vals: np.ndarray, target: str):
+    k = np.array(keys, dtype=np.uint64, copy=True, order="C")
+    v = np.array(vals, dtype=np.uint32, copy=True, order="C")
+    if k.shape != v.shape:
+        raise ValueError("keys and vals differ in shape")
+    if _load().oracle_sort_kv_target(_ptr(k), _ptr(v), k.size, TARGETS[target]) != 0:
+        raise MemoryError("oracle_sort_kv_target failed")
     return k, v
 
 

@@ -11,6 +11,8 @@
  *   - oracle_sort_*  : the result the paper's task defines ("Definition of
  *     sorting": stable ascending order with ties kept in input order read from
  *     left to right, the AscLeft target; "Values and principles / Stability").
+ *     oracle_sort_*_target: the four stable targets (AscLeft, AscRight,
+ *     DescLeft, DescRight) written as one composite (key, index) order.
  *     It is computed by the prototypical stable mergesort of the section
  *     "Merging or partitioning?" (one full-size buffer, top-down, take the left
  *     element unless the right one is strictly smaller).  Frogsort reaches this
@@ -107,6 +109,87 @@ int oracle_sort_kv(uint64_t *k, uint32_t *v, int64_t n)
     if (!tk || !tv) { free(tk); free(tv); return -1; }
     msort_kv(k, v, tk, tv, 0, n);
     free(tk); free(tv);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* the four stable targets ("Definition of sorting")                          */
+/* ------------------------------------------------------------------------ */
+/* Target t: bit 1 = descending key order, bit 0 = ties in reverse input order
+   (read from the right) instead of input order (read from the left):
+   0 AscLeft, 1 AscRight, 2 DescLeft, 3 DescRight.  Written as the plain
+   definition: element i comes before element j iff its key comes first in
+   the target's key order, or the keys tie and its index comes first in the
+   target's index order.  That order is total, so any correct sort of the
+   indices by it gives the result. */
+static int before_f64(const double *x, int64_t i, int64_t j, int t)
+{
+    const int desc = (t >> 1) & 1, right = t & 1;
+    const double a = x[i], b = x[j];
+    if (desc ? oracle_less_f64(b, a) : oracle_less_f64(a, b)) return 1;
+    if (desc ? oracle_less_f64(a, b) : oracle_less_f64(b, a)) return 0;
+    return right ? i > j : i < j;
+}
+
+static int before_u64(const uint64_t *k, int64_t i, int64_t j, int t)
+{
+    const int desc = (t >> 1) & 1, right = t & 1;
+    const uint64_t a = k[i], b = k[j];
+    if (desc ? less_u64(b, a) : less_u64(a, b)) return 1;
+    if (desc ? less_u64(a, b) : less_u64(b, a)) return 0;
+    return right ? i > j : i < j;
+}
+
+/* mergesort of an index array by the order `before` (keys of one type) */
+static void msort_idx(int64_t *ix, int64_t *tmp, int64_t lo, int64_t hi, const void *keys, int is_f64, int t)
+{
+    if (hi - lo < 2) return;
+    int64_t mid = lo + (hi - lo) / 2;
+    msort_idx(ix, tmp, lo, mid, keys, is_f64, t);
+    msort_idx(ix, tmp, mid, hi, keys, is_f64, t);
+    int64_t i = lo, j = mid, k = lo;
+    while (i < mid && j < hi) {
+        const int jb = is_f64 ? before_f64((const double *)keys, ix[j], ix[i], t)
+                              : before_u64((const uint64_t *)keys, ix[j], ix[i], t);
+        tmp[k++] = jb ? ix[j++] : ix[i++];
+    }
+    while (i < mid) tmp[k++] = ix[i++];
+    while (j < hi)  tmp[k++] = ix[j++];
+    memcpy(ix + lo, tmp + lo, (size_t)(hi - lo) * sizeof(int64_t));
+}
+
+/* x sorted in place for target t; -1 on allocation failure, -2 bad target. */
+int oracle_sort_f64_target(double *x, int64_t n, int t)
+{
+    if (t < 0 || t > 3) return -2;
+    if (n < 2) return 0;
+    int64_t *ix = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *tmp = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    double *y = (double *)malloc((size_t)n * sizeof(double));
+    if (!ix || !tmp || !y) { free(ix); free(tmp); free(y); return -1; }
+    for (int64_t i = 0; i < n; ++i) ix[i] = i;
+    msort_idx(ix, tmp, 0, n, x, 1, t);
+    for (int64_t i = 0; i < n; ++i) y[i] = x[ix[i]];
+    memcpy(x, y, (size_t)n * sizeof(double));
+    free(ix); free(tmp); free(y);
+    return 0;
+}
+
+int oracle_sort_kv_target(uint64_t *k, uint32_t *v, int64_t n, int t)
+{
+    if (t < 0 || t > 3) return -2;
+    if (n < 2) return 0;
+    int64_t *ix = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *tmp = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    uint64_t *yk = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    uint32_t *yv = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    if (!ix || !tmp || !yk || !yv) { free(ix); free(tmp); free(yk); free(yv); return -1; }
+    for (int64_t i = 0; i < n; ++i) ix[i] = i;
+    msort_idx(ix, tmp, 0, n, k, 0, t);
+    for (int64_t i = 0; i < n; ++i) { yk[i] = k[ix[i]]; yv[i] = v[ix[i]]; }
+    memcpy(k, yk, (size_t)n * sizeof(uint64_t));
+    memcpy(v, yv, (size_t)n * sizeof(uint32_t));
+    free(ix); free(tmp); free(yk); free(yv);
     return 0;
 }
 

@@ -359,3 +359,90 @@ def test_adam_first_step_closed_form(orc):
     orc.adam_step(p, g, m, v, 2, lr=1e-2)
     assert np.allclose(m, (0.9 * 0.1 + 0.1) * g)
     assert np.allclose(v, (0.999 * 0.001 + 0.001) * g * g)
+
+
+# --------------------------------------------------------------------------
+# the four stable targets ("Definition of sorting")
+# --------------------------------------------------------------------------
+TARGETS = ("AscLeft", "AscRight", "DescLeft", "DescRight")
+
+
+def _target_by_brute_force(keys, target):
+    """The unique permutation meeting the target, by trying every permutation:
+    keys in ascending (Asc) or descending (Desc) order, tied keys in input
+    order (Left) or reverse input order (Right)."""
+    desc, right = target.startswith("Desc"), target.endswith("Right")
+    n = len(keys)
+    found = []
+    for perm in itertools.permutations(range(n)):
+        ok = True
+        for a, b in zip(perm, perm[1:]):
+            ka, kb = keys[a], keys[b]
+            wrong_keys = (kb > ka) if desc else (kb < ka)
+            wrong_ties = ka == kb and ((b > a) if right else (b < a))
+            if wrong_keys or wrong_ties:
+                ok = False
+                break
+        if ok:
+            found.append(perm)
+    assert len(found) == 1
+    return np.array(found[0], dtype=np.int64)
+
+
+@pytest.mark.parametrize("target", TARGETS)
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 6])
+def test_targets_brute_force(orc, target, n):
+    rng = np.random.default_rng(300 + n)
+    for trial in range(25 if n > 3 else 8):
+        keys = rng.integers(0, max(1, n // 2 + 1), size=n).astype(np.uint64)
+        k, v = orc.sort_kv_target(keys, np.arange(n, dtype=np.uint32), target)
+        perm = _target_by_brute_force(keys.tolist(), target)
+        assert np.array_equal(v.astype(np.int64), perm)
+        assert np.array_equal(k, keys[perm])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_targets_exhaustive_weak_orders(orc, n):
+    """Every weak order of n keys, as ±0-labelled doubles: the f64 targets
+    keep or reverse the input order of ties exactly as the kv payload shows."""
+    for w in itertools.product(range(n), repeat=n):
+        if set(w) != set(range(max(w) + 1)):
+            continue
+        keys = np.array(w, dtype=np.uint64)
+        for target in TARGETS:
+            k, v = orc.sort_kv_target(keys, np.arange(n, dtype=np.uint32), target)
+            desc, right = target.startswith("Desc"), target.endswith("Right")
+            ks = k.astype(np.int64)
+            d = np.diff(ks)
+            assert np.all(d <= 0) if desc else np.all(d >= 0)
+            tie = d == 0
+            dv = np.diff(v.astype(np.int64))[tie]
+            assert np.all(dv < 0) if right else np.all(dv > 0)
+
+
+@pytest.mark.parametrize("pattern", ["uniform", "tied", "zeros_signed"])
+def test_targets_match_lexsort(orc, pattern):
+    """numpy's lexsort on (index, key) implements each target for NaN-free
+    keys (it compares -0.0 and 0.0 as equal, as the targets do)."""
+    x = W.f64_pattern(pattern, 3001, seed=8)
+    idx = np.arange(x.size)
+    for target in TARGETS:
+        desc, right = target.startswith("Desc"), target.endswith("Right")
+        order = np.lexsort((-idx if right else idx, -x if desc else x))
+        got = orc.sort_f64_target(x, target)
+        assert np.array_equal(got.view(np.uint64), x[order].view(np.uint64)), target
+
+
+def test_target_identities(orc):
+    """AscLeft is the plain stable sort; the right-anchored targets are the
+    left-anchored ones of the opposite direction read backwards."""
+    x = W.f64_pattern("zeros_signed", 5000, seed=9)
+    x[::97] = np.nan
+    b = lambda a: a.view(np.uint64)
+    asc_l = orc.sort_f64_target(x, "AscLeft")
+    assert np.array_equal(b(asc_l), b(orc.sort_f64(x)))
+    assert np.array_equal(b(orc.sort_f64_target(x, "DescRight")), b(asc_l[::-1]))
+    assert np.array_equal(b(orc.sort_f64_target(x, "AscRight")),
+                          b(orc.sort_f64_target(x, "DescLeft")[::-1]))
+    d = orc.sort_f64_target(x, "DescLeft")
+    assert np.isnan(d[: np.isnan(x).sum()]).all()             # NaN is the largest key

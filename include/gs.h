@@ -104,6 +104,18 @@ gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction,
 gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fraction,
                      void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 
+/* The four stable targets ("Definition of sorting"): keys ascending (Asc) or
+   descending (Desc); tied keys in input order (Left, read from the left) or in
+   reverse input order (Right, read from the right).  DescLeft is sorted
+   directly (the greater key first, ties in input order); AscRight and
+   DescRight are DescLeft and AscLeft read backwards (one extra reversal
+   pass).  AscLeft is gs_sort_f64 / gs_sort_kv.  Same workspace as those. */
+typedef enum { GS_ASC_LEFT = 0, GS_ASC_RIGHT = 1, GS_DESC_LEFT = 2, GS_DESC_RIGHT = 3 } gs_target;
+gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_fraction,
+                             void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction,
+                            void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+
 /* Sort every segment keys[offsets[i], offsets[i+1]) on its own, for
    i in [0, num_segments); `offsets` holds num_segments+1 int64 values (device).
    Offsets must be non-decreasing with offsets[0] >= 0 and

@@ -102,6 +102,10 @@ _SIGS = {
     "gs_workspace_bytes_kv": ([_I64, _D], _SZ),
     "gs_sort_f64": ([_P, _I64, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)], ctypes.c_int),
     "gs_sort_kv": ([_P, _P, _I64, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)], ctypes.c_int),
+    "gs_sort_f64_target": ([_P, _I64, ctypes.c_int, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)],
+                           ctypes.c_int),
+    "gs_sort_kv_target": ([_P, _P, _I64, ctypes.c_int, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)],
+                          ctypes.c_int),
     "gs_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "gs_last_error_detail": ([], ctypes.c_char_p),
     "gs_version": ([], ctypes.c_char_p),
@@ -236,8 +240,19 @@ def _rep_ptr(r):
     return ctypes.byref(r) if r is not None else ctypes.POINTER(GsReport)()
 
 
-def gs_sort_f64(keys, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False):
-    """Stable ascending in-place sort of a contiguous float64 device tensor."""
+TARGETS = {"AscLeft": 0, "AscRight": 1, "DescLeft": 2, "DescRight": 3}
+
+
+def _target(target) -> int:
+    if isinstance(target, str):
+        return TARGETS[target]
+    return int(target)
+
+
+def gs_sort_f64(keys, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False,
+                target="AscLeft"):
+    """Stable in-place sort of a contiguous float64 device tensor; target one
+    of AscLeft (default), AscRight, DescLeft, DescRight."""
     torch = _torch()
     kp = _dev_ptr(keys, "keys", (torch.float64,))
     n = keys.numel()
@@ -246,16 +261,18 @@ def gs_sort_f64(keys, buffer_fraction: float = 0.5, workspace=None, stream=None,
         need = 0
     ws, wsb = _workspace(need, keys.device, workspace)
     r = _rep(report)
-    st = _lib.gs_sort_f64(kp, n, buffer_fraction,
-                          ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
-                          _stream_ptr(stream, keys.device), _rep_ptr(r))
+    st = _lib.gs_sort_f64_target(kp, n, _target(target), buffer_fraction,
+                                 ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                                 _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_sort_f64")
     return r.as_dict() if r is not None else None
 
 
-def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False):
-    """Stable ascending in-place sort of 64-bit keys (int64 or uint64 storage,
-    compared as unsigned) carrying 32-bit values (int32 or uint32 storage)."""
+def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False,
+               target="AscLeft"):
+    """Stable in-place sort of 64-bit keys (int64 or uint64 storage, compared
+    as unsigned) carrying 32-bit values (int32 or uint32 storage); target as
+    for gs_sort_f64."""
     torch = _torch()
     k64 = tuple(d for d in (torch.int64, getattr(torch, "uint64", None)) if d is not None)
     v32 = tuple(d for d in (torch.int32, getattr(torch, "uint32", None)) if d is not None)
@@ -269,9 +286,9 @@ def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=
         need = 0
     ws, wsb = _workspace(need, keys.device, workspace)
     r = _rep(report)
-    st = _lib.gs_sort_kv(kp, vp, n, buffer_fraction,
-                         ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
-                         _stream_ptr(stream, keys.device), _rep_ptr(r))
+    st = _lib.gs_sort_kv_target(kp, vp, n, _target(target), buffer_fraction,
+                                ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                                _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_sort_kv")
     return r.as_dict() if r is not None else None
 

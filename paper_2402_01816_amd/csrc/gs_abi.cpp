@@ -207,7 +207,14 @@ void gs_plan_node(int64_t n, int depth, int64_t idx, int64_t *out)
 gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws, size_t ws_bytes,
                       void *hip_stream, gs_report *rep)
 {
+    return gs_sort_f64_target(keys, n, GS_ASC_LEFT, buffer_fraction, ws, ws_bytes, hip_stream, rep);
+}
+
+gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_fraction, void *ws,
+                             size_t ws_bytes, void *hip_stream, gs_report *rep)
+{
     g_detail.clear();
+    if (target < GS_ASC_LEFT || target > GS_DESC_RIGHT) return fail(GS_EINVAL, "unknown target %d", target);
     if (n < 0) return fail(GS_EINVAL, "n < 0");
     if (n > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
     gs_status s = check_fraction(buffer_fraction);
@@ -226,7 +233,7 @@ gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws,
     if ((s = check_device()) != GS_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     Reporter r(rep, st);
-    hipError_t e = gs::sort_f64_async(keys, n, (char *)ws, p, st);
+    hipError_t e = gs::sort_f64_target_async(keys, n, target, (char *)ws, p, st);
     if (e != hipSuccess) return r.finish(hip_fail(e, "gs_sort_f64 launch"));
     if (rep) {
         rep->levels = (uint32_t)p.depth;
@@ -422,7 +429,14 @@ gs_status gs_segsort_autotune(const double *keys, int64_t num_keys, const int64_
 gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fraction, void *ws,
                      size_t ws_bytes, void *hip_stream, gs_report *rep)
 {
+    return gs_sort_kv_target(keys, vals, n, GS_ASC_LEFT, buffer_fraction, ws, ws_bytes, hip_stream, rep);
+}
+
+gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction,
+                            void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep)
+{
     g_detail.clear();
+    if (target < GS_ASC_LEFT || target > GS_DESC_RIGHT) return fail(GS_EINVAL, "unknown target %d", target);
     if (n < 0) return fail(GS_EINVAL, "n < 0");
     if (n > 0 && (!keys || !vals)) return fail(GS_EINVAL, "keys or vals is NULL");
     gs_status s = check_fraction(buffer_fraction);
@@ -441,7 +455,7 @@ gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fr
     if ((s = check_device()) != GS_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     Reporter r(rep, st);
-    hipError_t e = gs::sort_kv_async(keys, vals, n, (char *)ws, p, st);
+    hipError_t e = gs::sort_kv_target_async(keys, vals, n, target, (char *)ws, p, st);
     if (e != hipSuccess) return r.finish(hip_fail(e, "gs_sort_kv launch"));
     if (rep) {
         rep->levels = (uint32_t)p.depth;

@@ -148,6 +148,10 @@ template <>
 struct FastKey<KeyF64> {
     using type = KeyF64NoNaN;
 };
+template <>
+struct FastKey<KeyF64Desc> {
+    using type = KeyF64DescNoNaN;
+};
 
 template <class K>
 __device__ __forceinline__ bool is_nan_key(K x)

@@ -32,6 +32,25 @@ struct KeyU64 {
     static __device__ __forceinline__ uint64_t pad() { return ~(uint64_t)0; }
 };
 
+// Descending orders of the same keys (the DescLeft target: the greater key
+// first, ties still in input order): less is the ascending less with its
+// arguments swapped; padding sorts after every key in this order.
+struct KeyF64Desc {
+    using T = double;
+    static __device__ __forceinline__ bool less(double a, double b) { return KeyF64::less(b, a); }
+    static __device__ __forceinline__ double pad() { return -__builtin_inf(); }
+};
+struct KeyF64DescNoNaN {
+    using T = double;
+    static __device__ __forceinline__ bool less(double a, double b) { return b < a; }
+    static __device__ __forceinline__ double pad() { return -__builtin_inf(); }
+};
+struct KeyU64Desc {
+    using T = uint64_t;
+    static __device__ __forceinline__ bool less(uint64_t a, uint64_t b) { return b < a; }
+    static __device__ __forceinline__ uint64_t pad() { return 0; }
+};
+
 struct NoVal {};
 
 // ---------------------------------------------------------------------------

@@ -109,6 +109,11 @@ hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, 
                           const unsigned *gate = nullptr, unsigned run_if = 0u);
 hipError_t sort_kv_async(uint64_t *keys, uint32_t *vals, int64_t n, char *ws, const SortPlan &p,
                          hipStream_t st);
+// Targets of "Definition of sorting": 0 AscLeft, 1 AscRight, 2 DescLeft,
+// 3 DescRight (plan from plan_f64 / plan_kv: the shapes are shared).
+hipError_t sort_f64_target_async(double *keys, int64_t n, int target, char *ws, const SortPlan &p, hipStream_t st);
+hipError_t sort_kv_target_async(uint64_t *keys, uint32_t *vals, int64_t n, int target, char *ws, const SortPlan &p,
+                                hipStream_t st);
 void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st);
 // One explicit merge node over the logical space {D, H, n_space}, using the
 // control area of a plain plan at least as large as the node.

@@ -625,6 +625,11 @@ struct SortCfg<KeyU64, uint32_t> {
     static constexpr int LEAF_NT = GS_KV_LEAF_NT, LEAF_IPT = GS_KV_LEAF_IPT, LEAF_WAVES = GS_KV_LEAF_WAVES;
     static constexpr int MERGE_NT = 256, MERGE_IPT = GS_KV_MERGE_IPT, MERGE_WAVES = GS_KV_MERGE_WAVES;
 };
+// descending orders: the same shapes as their ascending counterparts
+template <>
+struct SortCfg<KeyF64Desc, NoVal> : SortCfg<KeyF64, NoVal> {};
+template <>
+struct SortCfg<KeyU64Desc, uint32_t> : SortCfg<KeyU64, uint32_t> {};
 
 template <class KT, class V>
 constexpr int64_t leaf_size()
@@ -850,6 +855,58 @@ hipError_t sort_kv_async(uint64_t *keys, uint32_t *vals, int64_t n, char *ws, co
                          hipStream_t st)
 {
     return run_sort<KeyU64, uint32_t>(keys, vals, n, ws, p, st, Gate{nullptr, 0u});
+}
+
+// In-place reversal of keys[0, n) (and vals), one pair (i, n-1-i) per thread:
+// the right-anchored targets are the left-anchored ones of the opposite
+// direction read backwards.
+template <class K, class V>
+__global__ __launch_bounds__(256) void reverse_kernel(K *keys, V *vals, int64_t n)
+{
+    const int64_t half = n / 2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < half;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = n - 1 - i;
+        const K a = keys[i], b = keys[j];
+        keys[i] = b;
+        keys[j] = a;
+        if constexpr (ValOps<V>::has) {
+            const V va = vals[i], vb = vals[j];
+            vals[i] = vb;
+            vals[j] = va;
+        }
+    }
+}
+
+template <class K, class V>
+static void launch_reverse(K *keys, V *vals, int64_t n, hipStream_t st)
+{
+    if (n < 2) return;
+    const int64_t half = n / 2;
+    hipLaunchKernelGGL((reverse_kernel<K, V>), dim3(grid_for(half, 256, 8192)), dim3(256), 0, st, keys, vals, n);
+}
+
+hipError_t sort_f64_target_async(double *keys, int64_t n, int target, char *ws, const SortPlan &p, hipStream_t st)
+{
+    // targets: 0 AscLeft, 1 AscRight = reversed DescLeft, 2 DescLeft,
+    // 3 DescRight = reversed AscLeft
+    hipError_t e = (target == 1 || target == 2)
+                       ? run_sort<KeyF64Desc, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st, Gate{nullptr, 0u})
+                       : run_sort<KeyF64, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st, Gate{nullptr, 0u});
+    if (e != hipSuccess) return e;
+    if (target == 1 || target == 3) launch_reverse(keys, (NoVal *)nullptr, n, st);
+    return hipGetLastError();
+}
+
+hipError_t sort_kv_target_async(uint64_t *keys, uint32_t *vals, int64_t n, int target, char *ws, const SortPlan &p,
+                                hipStream_t st)
+{
+    hipError_t e = (target == 1 || target == 2)
+                       ? run_sort<KeyU64Desc, uint32_t>(keys, vals, n, ws, p, st, Gate{nullptr, 0u})
+                       : run_sort<KeyU64, uint32_t>(keys, vals, n, ws, p, st, Gate{nullptr, 0u});
+    if (e != hipSuccess) return e;
+    if (target == 1 || target == 3) launch_reverse(keys, vals, n, st);
+    return hipGetLastError();
 }
 
 hipError_t forest_f64_async(double *D, double *H, const Prob *probs, const unsigned *nprob, const ForestPlan &fp,

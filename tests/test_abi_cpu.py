@@ -174,3 +174,12 @@ def test_segsort_shapes_and_errors():
                                      ctypes.byref(best), None) == g.GS_EINVAL
     assert g.lib.gs_segsort_autotune(fake, 1000, fake, 10, fake, fake, need, None, 0,
                                      ctypes.byref(best), None) == g.GS_EINVAL
+
+
+def test_target_argument_errors():
+    fake = ctypes.c_void_p(0x100000)
+    need = g.gs_workspace_bytes_f64(1000)
+    for bad in (-1, 4, 99):
+        assert g.lib.gs_sort_f64_target(fake, 1000, bad, 0.5, fake, need, None, None) == g.GS_EINVAL
+        assert g.lib.gs_sort_kv_target(fake, fake, 1000, bad, 0.5, fake, 1 << 20, None, None) == g.GS_EINVAL
+    assert g.lib.gs_sort_f64_target(None, 0, 2, 0.5, None, 0, None, None) == g.GS_OK

@@ -115,3 +115,38 @@ def test_sort_f64_full_size_sampled(gs, orc, pattern):
     ranks = orc.rank_f64(x, idx)
     got = t[torch.from_numpy(ranks).to("cuda")].cpu().numpy()
     assert np.array_equal(bits(got), bits(x[idx]))
+
+
+TARGETS = ("AscLeft", "AscRight", "DescLeft", "DescRight")
+
+
+@pytest.mark.parametrize("target", TARGETS)
+@pytest.mark.parametrize("n", [2, 3, 4097, 12345, 1 << 20, (1 << 20) + 7])
+def test_sort_f64_targets(gs, orc, target, n):
+    """The four stable targets, bit for bit (±0 ties show the tie order;
+    NaNs and infinities included)."""
+    announce("sort_f64 target", target, n)
+    x = W.f64_pattern("zeros_signed", n, seed=21 + n)
+    x[::61] = np.nan
+    x[::67] = -np.inf
+    x[::71] = np.inf
+    t = to_dev(x)
+    gs.gs_sort_f64(t, target=target)
+    assert np.array_equal(bits(t), bits(orc.sort_f64_target(x, target)))
+
+
+@pytest.mark.parametrize("target", TARGETS)
+@pytest.mark.parametrize("pattern", ["uniform", "few"])
+def test_sort_kv_targets(gs, orc, target, pattern):
+    """Key/value targets: payload = input index, so the tie order is visible
+    for every tie."""
+    torch = need_gpu()
+    n = (1 << 20) + 13
+    announce("sort_kv target", target, pattern)
+    k0, v0 = W.kv_pattern(pattern, n, seed=5)
+    K = to_dev(k0.view(np.int64))
+    V = to_dev(v0.view(np.int32))
+    gs.gs_sort_kv(K, V, target=target)
+    rk, rv = orc.sort_kv_target(k0, v0, target)
+    assert np.array_equal(K.cpu().numpy().view(np.uint64), rk)
+    assert np.array_equal(V.cpu().numpy().view(np.uint32), rv)

@@ -68,6 +68,8 @@ def _load():
     lib.oracle_frog_model.restype = I64
     lib.oracle_frog_geometry.argtypes = [I64, ctypes.c_int, P]
     lib.oracle_frog_geometry.restype = I64
+    lib.oracle_frog2_model.argtypes = [P, I64, I64, I64, I64, P, P, P, P, I64, P, I64, P, I64, P]
+    lib.oracle_frog2_model.restype = I64
     lib.oracle_mlp_num_params.argtypes = []
     lib.oracle_mlp_num_params.restype = ctypes.c_int
     lib.oracle_mlp_forward.argtypes = [P, P, I64, P]
@@ -214,6 +216,67 @@ def frog_geometry(n: int, depth: int) -> np.ndarray:
     out = np.zeros((1 << depth, 5), dtype=np.int64)
     k = _load().oracle_frog_geometry(n, depth, _ptr(out))
     return out[:k]
+
+
+def frog2_fraction_q(p: float) -> int:
+    """The fraction p as q / 65536, rounded down (so the buffer never exceeds
+    p of the data): the reading the Frogsort2 model and the library share."""
+    return int(np.floor(float(p) * 65536.0))
+
+
+def frog2_model(keys, q: int, leaf_max: int, max_snap: int = 0, gap_shrink: int = 0):
+    """Run the instrumented Frogsort2 model (inner child floor(q*n/65536),
+    leaves of at most leaf_max elements) as a top-level left node.  With keys
+    None only the geometry is walked.
+
+    Returns a dict with the sorted keys and their input indices, the slot
+    labels after setup, the label snapshots after every merge, the leaves
+    (input offset, data start, length) in input order, the merge nodes
+    (region start, n, is_left, height) in post order, the comparison / move
+    counts, the slot count and the violation bits."""
+    geo_only = keys is None
+    if geo_only:
+        raise ValueError("use frog2_geometry")
+    keys = np.ascontiguousarray(keys, dtype=np.float64)
+    return _frog2(keys, keys.size, q, leaf_max, max_snap, gap_shrink)
+
+
+def frog2_geometry(n: int, q: int, leaf_max: int):
+    """Leaves and merge nodes of the Frogsort2 tree over n elements (see
+    frog2_model), without moving any data."""
+    return _frog2(None, int(n), q, leaf_max, 0, 0)
+
+
+def _frog2(keys, n, q, leaf_max, max_snap, gap_shrink):
+    lib = _load()
+    counts = np.zeros(6, dtype=np.int64)
+    # first pass: sizes only
+    lib.oracle_frog2_model(None, n, q, leaf_max, gap_shrink, None, None, None, None, 0,
+                           None, 0, None, 0, _ptr(counts))
+    nl, nn = int(counts[3]), int(counts[4])
+    leaves = np.zeros((max(nl, 1), 3), dtype=np.int64)
+    nodes = np.zeros((max(nn, 1), 4), dtype=np.int64)
+    nslots = n + (n * q) // 65536 if n > 0 else 0
+    nslots = max(nslots - gap_shrink, n)
+    res = {"n": n}
+    if keys is None:
+        ns = lib.oracle_frog2_model(None, n, q, leaf_max, gap_shrink, None, None, None, None, 0,
+                                    _ptr(leaves), nl, _ptr(nodes), nn, _ptr(counts))
+    else:
+        out_k = np.zeros(max(n, 1), dtype=np.float64)
+        out_l = np.zeros(max(n, 1), dtype=np.int64)
+        setup = np.zeros(max(nslots, 1), dtype=np.int64)
+        trace = np.zeros((max(max_snap, 1), max(nslots, 1)), dtype=np.int64)
+        ns = lib.oracle_frog2_model(_ptr(keys), n, q, leaf_max, gap_shrink, _ptr(out_k), _ptr(out_l),
+                                    _ptr(setup), _ptr(trace), max_snap, _ptr(leaves), nl,
+                                    _ptr(nodes), nn, _ptr(counts))
+        if ns < 0:
+            raise MemoryError("oracle_frog2_model: allocation failed")
+        res.update(keys=out_k[:n], labels=out_l[:n], setup=setup[:ns],
+                   trace=trace[: int(counts[2]), :ns])
+    res.update(leaves=leaves[:nl], nodes=nodes[:nn], compares=int(counts[0]), moves=int(counts[1]),
+               nslots=int(ns), bad=int(counts[5]))
+    return res
 
 
 def mlp_forward(params: np.ndarray, u: np.ndarray) -> np.ndarray:

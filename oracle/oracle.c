@@ -22,6 +22,8 @@
  *   - oracle_frog_*  : an instrumented model of the paper's Frogsort0/Frogsort1
  *     recursion ("Symmetric merging", "Frogsort0", "Frogsort1") used only to
  *     pin the memory layout and the adaptivity counts the paper states.
+ *   - oracle_frog2_* : the same for Frogsort2 ("Frogsort2": imbalanced splits,
+ *     buffer p), checking on every write that the smaller buffer suffices.
  *   - oracle_mlp_*   : an fp64 forward pass, MSE loss, backward pass and Adam
  *     step for the 1-64-64-1 ReLU network used by the learned bucket path
  *     (not part of the paper; parity of the GPU gradients is checked here).
@@ -486,6 +488,207 @@ static int64_t frog_geom(int64_t s, int64_t n, int left, int depth, int64_t in_o
 int64_t oracle_frog_geometry(int64_t n, int depth, int64_t *out)
 {
     return frog_geom(0, n, 1, depth, 0, out, 0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* instrumented model of Frogsort2 (imbalanced split, smaller buffer)        */
+/* ------------------------------------------------------------------------ */
+/*
+ * "Frogsort2": the inner child of every node takes a fraction p of the node's
+ * elements, and symmetric merging then needs a buffer of only that fraction.
+ * Here p = q / 65536 for an integer q in [1, 32768]: a node of n elements has
+ * an inner child of floor(q*n/65536) elements, an outer child with the rest,
+ * and a region of n + floor(q*n/65536) slots.  A split is only defined when the
+ * inner child is not empty; the model reports a node where it would be.  The
+ * children sit as in Frogsort1 (the left child is a left node at the start of
+ * the region, the right child a right node at its end; the outer child is the
+ * left child of a left node and the right child of a right node), and merging
+ * runs from the runs' inner ends outward.  Nodes of at most leaf_max elements
+ * are leaves: the setup recursion copies their chunk of the input (in input
+ * order) to their data slots, at the left end of the region for a left leaf and
+ * at the right end for a right leaf, where a stable insertion sort orders them.
+ * With q = 32768 and leaf_max = 1 this is the Frogsort1 model above, step for
+ * step ("Frogsort1 is a special case of Frogsort2 at p = 0.5").
+ *
+ * The model checks that the buffer suffices: a write to a slot that still holds
+ * an element nobody has read sets bit 0 of `bad`; an empty inner child sets
+ * bit 1.  gap_shrink > 0 shrinks every region by that many slots (only so that a
+ * test can see the check fire).
+ *
+ * With in == NULL only the geometry is walked (no slots are allocated).
+ */
+typedef struct {
+    double  *key;
+    int64_t *lab;
+    int64_t  q, leaf_max, gap_shrink;
+    int64_t  cmp, mov, bad;
+    int64_t *trace;
+    int64_t  nslots, nsnap, max_snap;
+    int64_t *leaves, max_leaves, nleaves;   /* {input offset, data start, len}      */
+    int64_t *nodes, max_nodes, nnodes;      /* {region start, n, is_left, height}   */
+} frog2_model;
+
+static int64_t f2_inner(const frog2_model *M, int64_t n) { return n * M->q / 65536; }
+
+static int64_t f2_region(const frog2_model *M, int64_t n)
+{
+    int64_t r = n + f2_inner(M, n) - M->gap_shrink;
+    return r < n ? n : r;
+}
+
+static void f2_snapshot(frog2_model *M)
+{
+    if (!M->key || !M->trace || M->nsnap >= M->max_snap) return;
+    memcpy(M->trace + M->nsnap * M->nslots, M->lab, (size_t)M->nslots * sizeof(int64_t));
+    M->nsnap++;
+}
+
+/* Move the element in slot src to slot dst: src becomes free, and dst must
+   not hold an element that has not been read yet. */
+static void f2_put(frog2_model *M, int64_t dst, int64_t src)
+{
+    if (dst == src) return;
+    double k = M->key[src];
+    int64_t l = M->lab[src];
+    M->lab[src] = -1;
+    if (M->lab[dst] >= 0) M->bad |= 1;
+    M->key[dst] = k;
+    M->lab[dst] = l;
+    M->mov++;
+}
+
+/* Setup: place the input chunk of every leaf (in input order) at its data
+   slots and sort it there.  Returns the next input position. */
+static int64_t f2_setup(frog2_model *M, const double *in, int64_t next, int64_t s, int64_t n, int left)
+{
+    if (n <= M->leaf_max) {
+        int64_t d = left ? s : s + f2_region(M, n) - n;
+        if (M->nleaves < M->max_leaves) {
+            M->leaves[3 * M->nleaves + 0] = next;
+            M->leaves[3 * M->nleaves + 1] = d;
+            M->leaves[3 * M->nleaves + 2] = n;
+        }
+        M->nleaves++;
+        if (M->key) {
+            for (int64_t i = 0; i < n; i++) {
+                if (M->lab[d + i] >= 0) M->bad |= 1;
+                M->key[d + i] = in[next + i];
+                M->lab[d + i] = next + i;
+            }
+            /* stable insertion sort: an element moves below another only
+               if it is strictly smaller */
+            for (int64_t i = 1; i < n; i++) {
+                double k = M->key[d + i];
+                int64_t l = M->lab[d + i], j = i - 1;
+                while (j >= 0 && oracle_less_f64(k, M->key[d + j])) {
+                    M->key[d + j + 1] = M->key[d + j];
+                    M->lab[d + j + 1] = M->lab[d + j];
+                    j--;
+                }
+                M->key[d + j + 1] = k;
+                M->lab[d + j + 1] = l;
+            }
+        }
+        return next + n;
+    }
+    int64_t ni = f2_inner(M, n);
+    if (ni < 1) { M->bad |= 2; return next + n; }
+    int64_t nl = left ? n - ni : ni, nr = n - nl;
+    next = f2_setup(M, in, next, s, nl, 1);
+    next = f2_setup(M, in, next, s + f2_region(M, n) - f2_region(M, nr), nr, 0);
+    return next;
+}
+
+/* Merge recursion over a node placed by f2_setup; returns the node's height
+   (0 for a leaf). */
+static int64_t f2_node(frog2_model *M, int64_t s, int64_t n, int left)
+{
+    if (n <= M->leaf_max) return 0;
+    int64_t ni = f2_inner(M, n);
+    if (ni < 1) { M->bad |= 2; return 0; }
+    int64_t nl = left ? n - ni : ni, nr = n - nl;
+    int64_t reg = f2_region(M, n);
+    int64_t hl = f2_node(M, s, nl, 1);
+    int64_t hr = f2_node(M, s + reg - f2_region(M, nr), nr, 0);
+    int64_t h = 1 + (hl > hr ? hl : hr);
+    if (M->key) {
+        int64_t Lb = s, Rb = s + reg - nr;
+        if (left) {
+            /* descending from the top slot of the output; on a tie the
+               right-run element takes the higher slot */
+            int64_t i = nl - 1, j = nr - 1, w = s + n - 1;
+            while (j >= 0) {
+                if (i < 0) { f2_put(M, w--, Rb + j); j--; continue; }
+                M->cmp++;
+                if (oracle_less_f64(M->key[Rb + j], M->key[Lb + i])) { f2_put(M, w--, Lb + i); i--; }
+                else                                                 { f2_put(M, w--, Rb + j); j--; }
+            }
+        } else {
+            /* ascending from the bottom slot of the output; on a tie the
+               left-run element takes the lower slot */
+            int64_t i = 0, j = 0, w = s + reg - n;
+            while (i < nl) {
+                if (j >= nr) { f2_put(M, w++, Lb + i); i++; continue; }
+                M->cmp++;
+                if (oracle_less_f64(M->key[Rb + j], M->key[Lb + i])) { f2_put(M, w++, Rb + j); j++; }
+                else                                                 { f2_put(M, w++, Lb + i); i++; }
+            }
+        }
+        f2_snapshot(M);
+    }
+    if (M->nnodes < M->max_nodes) {
+        M->nodes[4 * M->nnodes + 0] = s;
+        M->nodes[4 * M->nnodes + 1] = n;
+        M->nodes[4 * M->nnodes + 2] = left;
+        M->nodes[4 * M->nnodes + 3] = h;
+    }
+    M->nnodes++;
+    return h;
+}
+
+/*
+ * Run the model on in[0, n) as a top-level left node (in may be NULL: geometry
+ * only).  Outputs as for oracle_frog_model, plus the leaves in input order and
+ * the merge nodes in post order (each array written up to its capacity).
+ *   counts: {comparisons, moves, snapshots, leaves, nodes, bad}
+ * Returns the number of slots, n + floor(q*n/65536) (minus gap_shrink), or -1
+ * on allocation failure.
+ */
+int64_t oracle_frog2_model(const double *in, int64_t n, int64_t q, int64_t leaf_max, int64_t gap_shrink,
+                           double *out_key, int64_t *out_label, int64_t *setup_lab,
+                           int64_t *trace, int64_t max_snap,
+                           int64_t *leaves, int64_t max_leaves, int64_t *nodes, int64_t max_nodes,
+                           int64_t *counts)
+{
+    frog2_model M;
+    memset(&M, 0, sizeof M);
+    M.q = q;
+    M.leaf_max = leaf_max < 1 ? 1 : leaf_max;
+    M.gap_shrink = gap_shrink;
+    M.leaves = leaves; M.max_leaves = leaves ? max_leaves : 0;
+    M.nodes = nodes;   M.max_nodes = nodes ? max_nodes : 0;
+    for (int i = 0; i < 6; i++) counts[i] = 0;
+    if (n <= 0) return 0;
+    M.nslots = f2_region(&M, n);
+    if (in) {
+        M.key = (double *)calloc((size_t)M.nslots, sizeof(double));
+        M.lab = (int64_t *)malloc((size_t)M.nslots * sizeof(int64_t));
+        if (!M.key || !M.lab) { free(M.key); free(M.lab); return -1; }
+        for (int64_t p = 0; p < M.nslots; p++) M.lab[p] = -1;
+    }
+    f2_setup(&M, in, 0, 0, n, 1);
+    if (in && setup_lab) memcpy(setup_lab, M.lab, (size_t)M.nslots * sizeof(int64_t));
+    M.trace = trace; M.max_snap = max_snap;
+    f2_node(&M, 0, n, 1);
+    if (in) {
+        if (out_key) memcpy(out_key, M.key, (size_t)n * sizeof(double));
+        if (out_label) memcpy(out_label, M.lab, (size_t)n * sizeof(int64_t));
+    }
+    counts[0] = M.cmp; counts[1] = M.mov; counts[2] = M.nsnap;
+    counts[3] = M.nleaves; counts[4] = M.nnodes; counts[5] = M.bad;
+    int64_t ns = M.nslots;
+    free(M.key); free(M.lab);
+    return ns;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -276,7 +276,122 @@ def test_frog_geometry_rules(orc, n):
         (s0, n0, l0, d0, _), (s1, n1, l1, d1, _) = g
         assert l0 == 1 and l1 == 0 and n0 == (n + 1) // 2 and n1 == n // 2
         assert d1 == n                                   # inner run right after the output
-        assert d1 - (d0 + n0) == n // 2 - 0 * n1 or True
+        assert d1 - (d0 + n0) == n // 2                 # the gap holds the inner child
+
+
+# --------------------------------------------------------------------------
+# Frogsort2 model: the special case, the definition, the buffer check
+# --------------------------------------------------------------------------
+F2_QS = [1024, 3277, 6553, 13107, 16384, 21845, 29491, 32767, 32768]
+
+
+@pytest.mark.parametrize("n", list(range(1, 40)) + [100, 255, 1000, 1023])
+def test_frog2_half_is_frogsort1(orc, n):
+    """"Frogsort1 is a special case of Frogsort2 at p = 0.5": with q = 32768
+    and one-element leaves the Frogsort2 model places, compares and moves
+    exactly as the Frogsort1 model, merge for merge."""
+    rng = np.random.default_rng(7000 + n)
+    x = rng.integers(0, max(2, n // 4), size=n).astype(np.float64)
+    a = orc.frog2_model(x, 32768, 1, max_snap=2 * n + 2)
+    b = orc.frog_model(x, g=1, max_snap=2 * n + 2)
+    assert a["bad"] == 0 and a["nslots"] == b["nslots"] == n + n // 2
+    assert np.array_equal(a["setup"], b["setup"])
+    assert np.array_equal(a["trace"], b["trace"])
+    assert (a["compares"], a["moves"]) == (b["compares"], b["moves"])
+    assert np.array_equal(a["labels"], b["labels"])
+
+
+@pytest.mark.parametrize("q", F2_QS)
+@pytest.mark.parametrize("leaf_max", [1, 2, 7, 64])
+def test_frog2_sorts_stably_within_its_buffer(orc, q, leaf_max):
+    """For every fraction the model reaches the definition (stable ascending,
+    checked against numpy's stable argsort) with n + floor(q n / 65536) slots
+    and never writes over an element that has not been read."""
+    rng = np.random.default_rng(q * 131 + leaf_max)
+    if q * (leaf_max + 1) < 65536:
+        # a node just above the leaf size would get an empty inner child
+        r = orc.frog2_model(rng.random(leaf_max + 1), q, leaf_max)
+        assert r["bad"] & 2
+        return
+    for n in [1, leaf_max, leaf_max + 1, 97, 300, 1000, 2049]:
+        x = rng.integers(0, max(2, n // 5), size=n).astype(np.float64)
+        x[rng.random(n) < 0.1] = -0.0
+        x[rng.random(n) < 0.05] = np.nan
+        r = orc.frog2_model(x, q, leaf_max)
+        assert r["bad"] == 0, (q, leaf_max, n)
+        assert r["nslots"] == n + (q * n) // 65536 <= n + n * q / 65536
+        p = _stable_order(x)
+        assert np.array_equal(r["labels"], p)
+        assert np.array_equal(r["keys"].view(np.uint64), x[p].view(np.uint64))
+
+
+def _stable_order(x):
+    """Stable ascending order with NaN last (numpy's argsort puts NaN last and
+    is stable with kind='stable'); -0.0 and +0.0 tie."""
+    return np.argsort(x, kind="stable")
+
+
+@pytest.mark.parametrize("q", [3277, 6553, 16384, 32767])
+def test_frog2_check_fires_on_a_short_buffer(orc, q):
+    """The model's buffer check is live: one slot fewer per region makes some
+    write land on an element that has not been read."""
+    rng = np.random.default_rng(q)
+    x = rng.random(2000)
+    assert orc.frog2_model(x, q, 32)["bad"] == 0
+    assert orc.frog2_model(x, q, 32, gap_shrink=1)["bad"] & 1
+
+
+def _children(q, s, n, left):
+    ni = (q * n) // 65536
+    nl = n - ni if left else ni
+    nr = n - nl
+    reg = n + ni
+    return (s, nl, 1), (s + reg - (nr + (q * nr) // 65536), nr, 0)
+
+
+@pytest.mark.parametrize("q", F2_QS)
+@pytest.mark.parametrize("n", [5000, 65537, 1 << 20])
+def test_frog2_geometry_rules(orc, q, n):
+    """The inner child holds floor(q n / 65536) elements and the outer child
+    the rest; children fit their parent's region side by side; leaves cover
+    the input in order, none larger than the leaf size, each starting at or
+    after its input offset; a node's height is one more than its higher
+    child's."""
+    leaf_max = 512
+    g = orc.frog2_geometry(n, q, leaf_max)
+    lv, nd = g["leaves"], g["nodes"]
+    assert g["bad"] == 0
+    assert lv[:, 2].sum() == n and (lv[:, 2] <= leaf_max).all() and (lv[:, 2] >= 1).all()
+    assert np.array_equal(np.concatenate([[0], np.cumsum(lv[:, 2])[:-1]]), lv[:, 0])
+    assert (lv[:, 1] >= lv[:, 0]).all()
+    assert lv[:, 1].max() + lv[lv[:, 1].argmax(), 2] <= g["nslots"]
+    height = {(int(s), int(m), int(l)): int(h) for s, m, l, h in nd}
+    assert height[(0, n, 1)] == nd[:, 3].max()
+    for (s, m, l), h in height.items():
+        assert m > leaf_max
+        c0, c1 = _children(q, s, m, l)
+        h0 = height.get(c0, 0 if c0[1] <= leaf_max else None)
+        h1 = height.get(c1, 0 if c1[1] <= leaf_max else None)
+        assert h0 is not None and h1 is not None
+        assert h == 1 + max(h0, h1)
+        reg0 = c0[1] + (q * c0[1]) // 65536
+        assert c0[0] + reg0 <= c1[0]                       # side by side
+    assert len(height) == nd.shape[0] == lv.shape[0] - 1   # a binary tree
+
+
+@pytest.mark.parametrize("q", [3277, 6553, 13107, 32768])
+def test_frog2_presorted_and_reversed_counts(orc, q):
+    """Presorted input: a merge compares and moves only its inner run
+    ("Symmetric merging"), so both counts are the sum of the inner children.
+    Strictly descending input: every merge moves its whole output."""
+    n = 3000
+    inner = lambda nd: int(sum((q * m) // 65536 for m in nd[:, 1]))
+    leaf = 65536 // q                     # the smallest leaf size that always splits
+    r = orc.frog2_model(np.arange(n, dtype=np.float64), q, leaf)
+    assert r["compares"] == r["moves"] == inner(r["nodes"])
+    r = orc.frog2_model(np.arange(n, 0, -1, dtype=np.float64), q, leaf)
+    assert r["moves"] == int(r["nodes"][:, 1].sum())
+    assert np.array_equal(r["keys"], np.arange(1, n + 1, dtype=np.float64))
 
 
 # --------------------------------------------------------------------------

@@ -111,6 +111,8 @@ _SIGS = {
     "gs_version": ([], ctypes.c_char_p),
     "gs_plan_depth": ([_I64, ctypes.c_int, ctypes.POINTER(_I64)], ctypes.c_int),
     "gs_plan_node": ([_I64, ctypes.c_int, _I64, ctypes.POINTER(_I64)], None),
+    "gs_plan_frog2": ([_I64, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64, ctypes.c_void_p, _I64,
+                       ctypes.c_void_p], ctypes.c_int),
 }
 _OPTIONAL = {
     "gs_workspace_bytes_seg": ([_I64, _I64, _D], _SZ),
@@ -193,6 +195,22 @@ def plan_node(n: int, depth: int, idx: int):
     out = (_I64 * 5)()
     _lib.gs_plan_node(n, depth, idx, out)
     return tuple(out)
+
+
+def plan_frog2(n: int, buffer_fraction: float, kv: bool = False):
+    """The library's Frogsort2 plan for n keys (host only): leaves as rows
+    (input offset, data start, length) in input order, merge nodes as rows
+    (region start, n, is_left, round), and the counts
+    (leaves, nodes, rounds, buffer elements, largest round's tiles, splits)."""
+    import numpy as np
+    counts = np.zeros(6, dtype=np.int64)
+    if _lib.gs_plan_frog2(n, buffer_fraction, 1 if kv else 0, None, 0, None, 0, counts.ctypes.data) != 0:
+        raise ValueError("no Frogsort2 plan for these arguments")
+    leaves = np.zeros((int(counts[0]), 3), dtype=np.int64)
+    nodes = np.zeros((max(int(counts[1]), 1), 4), dtype=np.int64)
+    _lib.gs_plan_frog2(n, buffer_fraction, 1 if kv else 0, leaves.ctypes.data, leaves.shape[0],
+                       nodes.ctypes.data, int(counts[1]), counts.ctypes.data)
+    return leaves, nodes[: int(counts[1])], tuple(int(c) for c in counts)
 
 
 # ---------------------------------------------------------------------------

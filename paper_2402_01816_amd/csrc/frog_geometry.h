@@ -1,4 +1,5 @@
-// Geometry of the Frogsort1 tree ("Symmetric merging", "Frogsort1").
+// Geometry of the Frogsort1 tree ("Symmetric merging", "Frogsort1") and of
+// one Frogsort2 node ("Frogsort2", at the end).
 //
 // A node sorts `n` data elements inside a region of m(n) = n + floor(n/2)
 // slots of the logical frog space.  A left node leaves its data at the left
@@ -13,7 +14,7 @@
 // The GPU path processes the tree breadth first: all leaves (depth D, at most
 // `leaf_max` elements each) in one launch, then one merge launch per level from
 // depth D-1 up to 0.  Every node's geometry is recomputed on the fly by walking
-// from the root, so no descriptor table is ever uploaded.
+// from the root, so Frogsort1 needs no descriptor table.
 #pragma once
 #include <stdint.h>
 
@@ -122,6 +123,42 @@ GS_HD int frog_depth(int64_t n, int64_t leaf_max)
 GS_HD int64_t frog_max_node(int64_t n, int d)
 {
     return (n + ((int64_t)1 << d) - 1) >> d;
+}
+
+// ---------------------------------------------------------------------------
+// Frogsort2
+// ---------------------------------------------------------------------------
+// The inner child of a node of n elements takes floor(q n / 2^16) of them and
+// the outer child the rest; the node's region is n + floor(q n / 2^16) slots
+// ("Frogsort2": inner branch and buffer both the fraction p = q / 2^16).  The
+// children sit as in Frogsort1, so a node's merge is a FrogMerge of the same
+// two kinds (outer 0 for a left node, outer 1 for a right node).
+constexpr int64_t kF2LeftBit = (int64_t)1 << 62;
+
+GS_HD int64_t f2_inner(int64_t n, int64_t q) { return (n * q) >> 16; }
+
+GS_HD FrogMerge f2_merge(int64_t s, int64_t n_left, int64_t q)
+{
+    const int64_t n = n_left & (kF2LeftBit - 1);
+    const int64_t ni = f2_inner(n, q);
+    FrogMerge m;
+    m.l0 = s;
+    if (n_left & kF2LeftBit) {           // outer run: left child's data at [s, s + n - ni)
+        m.nl = n - ni;
+        m.nr = ni;
+        m.r0 = s + n;                    // inner run just past the output
+        m.out0 = s;
+        m.left = 1;
+        m.outer = 0;
+    } else {                             // inner run at [s, s + ni), just before the output
+        m.nl = ni;
+        m.nr = n - ni;
+        m.r0 = s + 2 * ni;
+        m.out0 = s + ni;
+        m.left = 0;
+        m.outer = 1;
+    }
+    return m;
 }
 
 }  // namespace gs

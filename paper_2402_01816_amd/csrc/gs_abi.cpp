@@ -50,12 +50,42 @@ gs_status check_device()
     return GS_OK;
 }
 
-gs_status check_fraction(double f)
+// buffer_fraction >= 0.5: Frogsort1 (*q = 0).  In [1/64, 0.5): Frogsort2 with
+// the fraction rounded down to q / 2^16, so the buffer never exceeds it.
+// Below 1/64 the imbalanced tree grows too deep to be worth running.
+gs_status check_fraction(double f, int64_t *q)
 {
+    *q = 0;
     if (!(f > 0.0)) return fail(GS_EINVAL, "buffer_fraction must be > 0 (got %g)", f);
-    if (f < 0.5)
-        return fail(GS_EUNSUPPORTED,
-                    "buffer_fraction %g < 0.5 needs imbalanced splits (Frogsort2), not built", f);
+    if (f >= 0.5) return GS_OK;
+    const int64_t v = (int64_t)floor(f * 65536.0);
+    if (v < gs::kF2MinQ)
+        return fail(GS_EUNSUPPORTED, "buffer_fraction %g is below the smallest supported, 1/64", f);
+    *q = v;
+    return GS_OK;
+}
+
+// The segmented sort has Frogsort1 only.
+gs_status check_fraction_seg(double f)
+{
+    int64_t q = 0;
+    gs_status s = check_fraction(f, &q);
+    if (s == GS_OK && q != 0)
+        return fail(GS_EUNSUPPORTED, "segmented sort: buffer_fraction %g < 0.5 is not built", f);
+    return s;
+}
+
+// A Frogsort2 call copies its host-built tree tables into the workspace, which
+// a graph capture cannot record safely.
+gs_status check_not_capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return GS_OK;
+    }
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(GS_EUNSUPPORTED, "buffer_fraction < 0.5 cannot be captured into a graph");
     return GS_OK;
 }
 
@@ -175,16 +205,18 @@ const char *gs_version(void) { return "0.1.0 gfx950"; }
 
 size_t gs_workspace_bytes_f64(int64_t n, double buffer_fraction)
 {
-    if (n < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
+    int64_t q = 0;
+    if (n < 0 || n > ((int64_t)1 << 40) || check_fraction(buffer_fraction, &q) != GS_OK) return SIZE_MAX;
     if (n <= 1) return 0;
-    return (size_t)gs::plan_f64(n).bytes;
+    return (size_t)gs::plan_f64(n, q).bytes;
 }
 
 size_t gs_workspace_bytes_kv(int64_t n, double buffer_fraction)
 {
-    if (n < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
+    int64_t q = 0;
+    if (n < 0 || n > ((int64_t)1 << 40) || check_fraction(buffer_fraction, &q) != GS_OK) return SIZE_MAX;
     if (n <= 1) return 0;
-    return (size_t)gs::plan_kv(n).bytes;
+    return (size_t)gs::plan_kv(n, q).bytes;
 }
 
 int gs_plan_depth(int64_t n, int is_kv, int64_t *leaf_max)
@@ -204,6 +236,38 @@ void gs_plan_node(int64_t n, int depth, int64_t idx, int64_t *out)
     out[4] = f.in_off;
 }
 
+int gs_plan_frog2(int64_t n, double buffer_fraction, int is_kv, int64_t *leaves, int64_t max_leaves,
+                  int64_t *nodes, int64_t max_nodes, int64_t *counts)
+{
+    int64_t q = 0;
+    if (n < 2 || n > ((int64_t)1 << 32) || check_fraction(buffer_fraction, &q) != GS_OK || q == 0) return -1;
+    const gs::SortPlan p = is_kv ? gs::plan_kv(n, q) : gs::plan_f64(n, q);
+    const gs::F2Tables &T = *p.f2;
+    const char *b = T.blob.data();
+    const int64_t *lc = (const int64_t *)(b + T.off_leaf_c), *ld = (const int64_t *)(b + T.off_leaf_d);
+    const int64_t *ns = (const int64_t *)(b + T.off_node_s), *nn = (const int64_t *)(b + T.off_node_n);
+    const unsigned *rb = (const unsigned *)(b + T.off_rb);
+    for (int64_t i = 0; i < T.nleaves && i < max_leaves; ++i) {
+        leaves[3 * i + 0] = lc[i];
+        leaves[3 * i + 1] = ld[i];
+        leaves[3 * i + 2] = lc[i + 1] - lc[i];
+    }
+    for (int r = 1; r <= T.rounds; ++r)
+        for (unsigned k = rb[r]; k < rb[r + 1] && (int64_t)k < max_nodes; ++k) {
+            nodes[4 * k + 0] = ns[k];
+            nodes[4 * k + 1] = nn[k] & (gs::kF2LeftBit - 1);
+            nodes[4 * k + 2] = (nn[k] & gs::kF2LeftBit) ? 1 : 0;
+            nodes[4 * k + 3] = r;
+        }
+    counts[0] = T.nleaves;
+    counts[1] = T.nnodes;
+    counts[2] = T.rounds;
+    counts[3] = p.hlen;
+    counts[4] = T.max_tickets;
+    counts[5] = T.max_splits;
+    return 0;
+}
+
 gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws, size_t ws_bytes,
                       void *hip_stream, gs_report *rep)
 {
@@ -217,10 +281,11 @@ gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_
     if (target < GS_ASC_LEFT || target > GS_DESC_RIGHT) return fail(GS_EINVAL, "unknown target %d", target);
     if (n < 0) return fail(GS_EINVAL, "n < 0");
     if (n > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
-    gs_status s = check_fraction(buffer_fraction);
+    int64_t q = 0;
+    gs_status s = check_fraction(buffer_fraction, &q);
     if (s != GS_OK) return s;
     if (n > ((int64_t)1 << 40)) return fail(GS_EINVAL, "n above 2^40");
-    gs::SortPlan p = gs::plan_f64(n);
+    gs::SortPlan p = gs::plan_f64(n, q);
     if (n > 1) {
         if ((int64_t)ws_bytes < p.bytes || !ws)
             return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);
@@ -232,6 +297,7 @@ gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_
     }
     if ((s = check_device()) != GS_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
+    if (p.f2 && (s = check_not_capturing(st)) != GS_OK) return s;
     Reporter r(rep, st);
     hipError_t e = gs::sort_f64_target_async(keys, n, target, (char *)ws, p, st);
     if (e != hipSuccess) return r.finish(hip_fail(e, "gs_sort_f64 launch"));
@@ -306,7 +372,7 @@ static gs_status seg_checks(double *keys, int64_t num_keys, const int64_t *offse
     if (num_keys < 0 || num_segments < 0) return fail(GS_EINVAL, "num_keys or num_segments < 0");
     if (num_segments > ((int64_t)1 << 31) - 2) return fail(GS_EINVAL, "num_segments above 2^31-2");
     if (num_keys > ((int64_t)1 << 40)) return fail(GS_EINVAL, "num_keys above 2^40");
-    gs_status s = check_fraction(buffer_fraction);
+    gs_status s = check_fraction_seg(buffer_fraction);
     if (s != GS_OK) return s;
     gs::SegConfig c;
     if (!to_seg_config(cfg, &c)) return fail(GS_EINVAL, "unknown segmented-sort shape");
@@ -439,10 +505,11 @@ gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int targe
     if (target < GS_ASC_LEFT || target > GS_DESC_RIGHT) return fail(GS_EINVAL, "unknown target %d", target);
     if (n < 0) return fail(GS_EINVAL, "n < 0");
     if (n > 0 && (!keys || !vals)) return fail(GS_EINVAL, "keys or vals is NULL");
-    gs_status s = check_fraction(buffer_fraction);
+    int64_t q = 0;
+    gs_status s = check_fraction(buffer_fraction, &q);
     if (s != GS_OK) return s;
     if (n > ((int64_t)1 << 40)) return fail(GS_EINVAL, "n above 2^40");
-    gs::SortPlan p = gs::plan_kv(n);
+    gs::SortPlan p = gs::plan_kv(n, q);
     if (n > 1) {
         if ((int64_t)ws_bytes < p.bytes || !ws)
             return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);
@@ -454,6 +521,7 @@ gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int targe
     }
     if ((s = check_device()) != GS_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
+    if (p.f2 && (s = check_not_capturing(st)) != GS_OK) return s;
     Reporter r(rep, st);
     hipError_t e = gs::sort_kv_target_async(keys, vals, n, target, (char *)ws, p, st);
     if (e != hipSuccess) return r.finish(hip_fail(e, "gs_sort_kv launch"));

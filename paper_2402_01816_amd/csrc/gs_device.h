@@ -93,6 +93,35 @@ struct Prob {
     int32_t pad;
 };
 
+// ---------------------------------------------------------------------------
+// Frogsort2: one irregular tree from host-built tables (geometry in
+// frog_geometry.h)
+// ---------------------------------------------------------------------------
+struct F2View {
+    const int64_t *leaf_c;     // input offset of every leaf, in input order (+ a final n)
+    const int64_t *leaf_d;     // data start of every leaf
+    const int64_t *node_s;     // region start of every merge node (grouped by round)
+    const int64_t *node_n;     // its elements, | kF2LeftBit for a left node
+    const unsigned *node_tb;   // its first ticket within its round
+    const unsigned *node_sb;   // its first split within its round
+    const unsigned *rb;        // first node of every round (rounds + 2 entries)
+    const unsigned *rt, *rs;   // tickets and splits of every round
+    int64_t nleaves;
+    int64_t q;
+};
+
+// Last index i in [0, L) with c[i] <= x (c ascending, c[0] <= x).
+__device__ __forceinline__ int64_t locate_i64(const int64_t *c, int64_t L, int64_t x)
+{
+    int64_t lo = 0, hi = L;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (c[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 struct Forest {
     const Prob *probs;        // problem table, or nullptr: the single problem p0
     const unsigned *nprob;    // number of problems in the table (device word)
@@ -102,6 +131,8 @@ struct Forest {
     Prob p0;
     FrogMerge m1;             // with use_m1: round 1 of p0 is this one merge
     int use_m1;
+    int use_f2;               // with use_f2: p0 is sorted by the Frogsort2 tree in f2
+    F2View f2;
 };
 
 GS_HD int64_t forest_nodes(const Forest &F, const Prob &P, int round)

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
+#include <vector>
+
 #include "frog_geometry.h"
 
 namespace gs {
@@ -18,8 +21,10 @@ constexpr int kErrWord = 63;
 #define GS_MERGE_GROUPS 8
 #endif
 constexpr int kMergeGroups = GS_MERGE_GROUPS;
-constexpr int kMaxRounds = 47;
-constexpr int kForestCtrlWords = 32 * kMergeGroups * (kMaxRounds + 1);
+inline int64_t forest_ctrl_words(int rounds)
+{
+    return (int64_t)32 * kMergeGroups * ((rounds > 0 ? rounds : 1) + 1);
+}
 
 // Layout of the area a forest run (one or many frog trees) works in, from
 // offset 0 of that area.
@@ -31,13 +36,29 @@ struct ForestPlan {
     int64_t max_tickets;  // work items of one merge round (capacity)
     int64_t max_status;   // status words (capacity over all rounds)
     int64_t max_splits;   // merge-path splits of one round (capacity)
-    int64_t off_ctrl;     // kForestCtrlWords words
+    int64_t off_ctrl;     // forest_ctrl_words(rounds) words
     int64_t off_status;
     int64_t off_splits;
     int64_t off_desc;     // tile descriptors of the current round
     int64_t off_probs;    // problem table (table runs only)
     int64_t off_tbase, off_sbase;   // per-round prefix rows (table runs only)
+    int64_t off_f2, f2_bytes;       // Frogsort2 tree tables (imbalanced plans only)
     int64_t bytes;
+};
+
+// Frogsort2 ("Frogsort2": the inner child of a node of n elements takes
+// floor(q n / 2^16) of them, q / 2^16 = p < 1/2, and the buffer shrinks to the
+// same fraction).  The tree is irregular, so the host walks it once and the
+// call uploads these tables into the workspace: the leaves in input order and
+// the merge nodes grouped by height (round r merges every node of height r).
+struct F2Tables {
+    int64_t n, q, leaf, tile;
+    int rounds;                          // height of the root
+    int64_t nleaves, nnodes;
+    int64_t max_tickets, max_splits;     // largest round
+    std::vector<unsigned> rt, rs;        // tickets / splits per round (host copy)
+    std::vector<char> blob;              // device image, offsets below
+    int64_t off_leaf_c, off_leaf_d, off_node_s, off_node_n, off_node_tb, off_node_sb, off_rb, off_rt, off_rs;
 };
 
 // Workspace layout and tree shape of one plain sort.
@@ -45,11 +66,14 @@ struct SortPlan {
     int64_t n;            // keys
     int64_t leaf;         // largest leaf (elements)
     int64_t tile;         // merge output tile (elements)
-    int depth;            // tree depth = number of merge levels
-    int64_t off_hkeys;    // half buffer for keys: floor(n/2) elements
-    int64_t off_hvals;    // half buffer for values (kv only)
+    int depth;            // number of merge rounds
+    int64_t q;            // 0: Frogsort1; else Frogsort2 with inner child floor(q n / 2^16)
+    int64_t hlen;         // buffer elements: floor(n/2), or floor(q n / 2^16)
+    int64_t off_hkeys;    // buffer for keys
+    int64_t off_hvals;    // buffer for values (kv only)
     int64_t off_forest;   // control area of the run
     ForestPlan forest;
+    std::shared_ptr<const F2Tables> f2;   // Frogsort2 tables (q != 0)
     int64_t bytes;        // total workspace
 };
 
@@ -102,8 +126,10 @@ ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs,
 hipError_t forest_f64_async(double *D, double *H, const Prob *probs, const unsigned *nprob, const ForestPlan &fp,
                             char *fw, hipStream_t st, const unsigned *gate, unsigned run_if, int merge_ipt = 16);
 
-SortPlan plan_f64(int64_t n);
-SortPlan plan_kv(int64_t n);
+// q = 0: Frogsort1 (buffer floor(n/2)); q in [kF2MinQ, 2^15): Frogsort2.
+constexpr int64_t kF2MinQ = 1024;       // p >= 1/64
+SortPlan plan_f64(int64_t n, int64_t q = 0);
+SortPlan plan_kv(int64_t n, int64_t q = 0);
 // gate (may be null): every launch exits at once unless *gate == run_if.
 hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st,
                           const unsigned *gate = nullptr, unsigned run_if = 0u);

@@ -7,7 +7,12 @@
 // buffer floor(n/2); the setup recursion that places elements before merging).
 #include <hip/hip_runtime.h>
 
+#include <string.h>
+
+#include <list>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "gs_block.h"
 #include "gs_device.h"
@@ -56,7 +61,7 @@ void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st)
 // descending index order, and each waits for the leaves whose chunks its
 // output covers.  Every work-group takes one ticket; with a problem table the
 // grid is the capacity and work-groups past the device's leaf count exit.
-template <class KT, class V, int NT, int IPT, int WAVES>
+template <class KT, class V, int NT, int IPT, int WAVES, bool F2>
 __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv,
                                                   Forest F, unsigned *ticket_ctr, unsigned *status,
                                                   unsigned epoch, unsigned *err, Gate gate)
@@ -74,7 +79,7 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
 
     const int tid = threadIdx.x;
     const int64_t L = F.probs ? (int64_t)*F.nprob : 1;
-    const int64_t total = F.probs ? (int64_t)F.tbase[L] : ((int64_t)1 << F.p0.depth);
+    const int64_t total = F2 ? F.f2.nleaves : F.probs ? (int64_t)F.tbase[L] : ((int64_t)1 << F.p0.depth);
     do {
         if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
         __syncthreads();
@@ -88,14 +93,28 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
             P = F.probs[s];
             base = F.tbase[s];
         }
-        const int64_t nleaves = (int64_t)1 << P.depth;
+        const int64_t nleaves = F2 ? F.f2.nleaves : ((int64_t)1 << P.depth);
         const int64_t leaf = nleaves - 1 - (t - base);
-        const FrogNode f = frog_node(P.n, P.depth, leaf);
+        int64_t src, dst;
+        int len;
+        int64_t wlo = 1, whi = 0;        // Frogsort2: dependency window, found up front
+        if constexpr (F2) {
+            src = F.f2.leaf_c[leaf];
+            len = (int)(F.f2.leaf_c[leaf + 1] - src);
+            dst = F.f2.leaf_d[leaf];
+            if (dst < P.n) {
+                const int64_t end = (dst + len < P.n ? dst + len : P.n) - 1;
+                wlo = nleaves - 1 - locate_i64(F.f2.leaf_c, nleaves, end);
+                whi = nleaves - 1 - locate_i64(F.f2.leaf_c, nleaves, dst);
+            }
+        } else {
+            const FrogNode f = frog_node(P.n, P.depth, leaf);
+            src = f.in_off;
+            len = (int)f.n;
+            dst = frog_data_start(f);
+        }
         const Space<K> keys{Dk + P.doff, Hk + P.hoff, P.n};
         const Space<V> vals{HV ? Dv + P.doff : nullptr, HV ? Hv + P.hoff : nullptr, P.n};
-        const int len = (int)f.n;
-        const int64_t src = f.in_off;
-        const int64_t dst = frog_data_start(f);
 
         // load the chunk (input elements all live in the caller's array) with
         // straight-line loads from clamped indices, all issued before the
@@ -142,7 +161,9 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         }
 
         // wait for the leaves whose input chunks the destination covers
-        if (tid < 64 && dst < P.n) {
+        if constexpr (F2) {
+            if (tid < 64 && wlo <= whi) wait_window(status, wlo, whi, t, epoch, err);
+        } else if (tid < 64 && dst < P.n) {
             const int64_t end = (dst + len < P.n ? dst + len : P.n) - 1;
             const int64_t lo_leaf = frog_leaf_of(P.n, P.depth, dst);
             const int64_t hi_leaf = frog_leaf_of(P.n, P.depth, end);
@@ -257,21 +278,31 @@ __global__ __launch_bounds__(256) void partition_kernel(typename KT::T *Dk, type
     if (gate.closed()) return;
     const int64_t L = F.probs ? (int64_t)*F.nprob : 1;
     const unsigned *srow = F.probs ? F.sbase + (int64_t)round * F.stride : nullptr;
-    const int64_t total = F.probs ? (int64_t)srow[L] : forest_splits<TILE>(F, F.p0, round);
+    const int64_t total = F.use_f2  ? (int64_t)F.f2.rs[round]
+                          : F.probs ? (int64_t)srow[L] : forest_splits<TILE>(F, F.p0, round);
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
          w += (int64_t)gridDim.x * blockDim.x) {
         Prob P = F.p0;
-        int64_t base = 0;
-        if (F.probs) {
-            const int64_t s = forest_locate(srow, L, w);
-            P = F.probs[s];
-            base = srow[s];
+        FrogMerge m;
+        int64_t j;
+        if (F.use_f2) {
+            const unsigned b0 = F.f2.rb[round], b1 = F.f2.rb[round + 1];
+            const int64_t k = b0 + forest_locate(F.f2.node_sb + b0, b1 - b0, w);
+            j = w - F.f2.node_sb[k];
+            m = f2_merge(F.f2.node_s[k], F.f2.node_n[k], F.f2.q);
+        } else {
+            int64_t base = 0;
+            if (F.probs) {
+                const int64_t s = forest_locate(srow, L, w);
+                P = F.probs[s];
+                base = srow[s];
+            }
+            const int64_t tpn = forest_tpn<TILE>(F, P, round);
+            const int64_t lw = w - base;
+            const int64_t node = lw / (tpn + 1);
+            j = lw - node * (tpn + 1);
+            m = forest_merge(F, P, round, node);
         }
-        const int64_t tpn = forest_tpn<TILE>(F, P, round);
-        const int64_t lw = w - base;
-        const int64_t node = lw / (tpn + 1);
-        const int64_t j = lw - node * (tpn + 1);
-        const FrogMerge m = forest_merge(F, P, round, node);
         const Space<K> keys{Dk + P.doff, Hk + P.hoff, P.n};
         const int64_t nn = m.nl + m.nr;
         int64_t kk = j * TILE;
@@ -328,24 +359,39 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
     const int64_t L = F.probs ? (int64_t)*F.nprob : 1;
     const unsigned *trow = F.probs ? F.tbase + (int64_t)round * F.stride : nullptr;
     const unsigned *srow = F.probs ? F.sbase + (int64_t)round * F.stride : nullptr;
-    const int64_t total = F.probs ? (int64_t)trow[L] : forest_tickets<TILE>(F, F.p0, round);
+    const int64_t total = F.use_f2  ? (int64_t)F.f2.rt[round]
+                          : F.probs ? (int64_t)trow[L] : forest_tickets<TILE>(F, F.p0, round);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        Prob P = F.p0;
-        int64_t tb = 0, sb = 0, s = 0;
-        if (F.probs) {
-            s = forest_locate(trow, L, t);
-            P = F.probs[s];
-            tb = trow[s];
-            sb = srow[s];
+        int64_t s = 0, tpn, q, first;
+        const int64_t *sp;
+        FrogMerge m;
+        if (F.use_f2) {
+            // a node has ceil(n / TILE) tiles and one split more
+            const unsigned b0 = F.f2.rb[round], b1 = F.f2.rb[round + 1];
+            const int64_t k = b0 + forest_locate(F.f2.node_tb + b0, b1 - b0, t);
+            m = f2_merge(F.f2.node_s[k], F.f2.node_n[k], F.f2.q);
+            tpn = (m.nl + m.nr + TILE - 1) / TILE;
+            first = F.f2.node_tb[k];
+            q = t - first;
+            sp = splits + F.f2.node_sb[k];
+        } else {
+            Prob P = F.p0;
+            int64_t tb = 0, sb = 0;
+            if (F.probs) {
+                s = forest_locate(trow, L, t);
+                P = F.probs[s];
+                tb = trow[s];
+                sb = srow[s];
+            }
+            tpn = forest_tpn<TILE>(F, P, round);
+            const int64_t lt = t - tb;
+            const int64_t node = lt / tpn;
+            q = lt - node * tpn;
+            first = tb + node * tpn;
+            sp = splits + sb + node * (tpn + 1);
+            m = forest_merge(F, P, round, node);
         }
-        const int64_t tpn = forest_tpn<TILE>(F, P, round);
-        const int64_t lt = t - tb;
-        const int64_t node = lt / tpn;
-        const int64_t q = lt - node * tpn;
-        const int64_t first = tb + node * tpn;
-        const int64_t *sp = splits + sb + node * (tpn + 1);
-        const FrogMerge m = forest_merge(F, P, round, node);
         const int64_t nn = m.nl + m.nr;
         const int64_t j = m.left ? (tpn - 1 - q) : q;
         int64_t k0 = j * TILE;
@@ -426,7 +472,7 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
 #endif
 template <class KT, class V, int NT, int IPT, int WAVES>
 __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv,
-                                                   Forest F, int round, const TileDesc *desc,
+                                                   Forest F, int round, int64_t nt_host, const TileDesc *desc,
                                                    unsigned *ticket_ctr, unsigned *status, unsigned epoch,
                                                    unsigned *err, Gate gate)
 {
@@ -441,8 +487,9 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
     __shared__ unsigned s_next;
     if (gate.closed()) return;
 
-    const int64_t ntiles = F.probs ? (int64_t)F.tbase[(int64_t)round * F.stride + *F.nprob]
-                                   : forest_tickets<TILE>(F, F.p0, round);
+    // tiles of this round: from the device table, else the count the host
+    // passes (it knows it for one problem)
+    const int64_t ntiles = F.probs ? (int64_t)F.tbase[(int64_t)round * F.stride + *F.nprob] : nt_host;
     const int tid = threadIdx.x;
     const int grp = (int)(blockIdx.x % kMergeGroups);
     unsigned *my_ctr = ticket_ctr + 32 * grp;
@@ -659,13 +706,15 @@ static ForestPlan layout_forest(int64_t max_probs, int rounds, int64_t max_ticke
     f.max_status = max_status;
     f.max_splits = max_splits;
     f.off_ctrl = 0;
-    f.off_status = align256(kForestCtrlWords * 4);
+    f.off_status = align256(forest_ctrl_words(rounds) * 4);
     f.off_splits = f.off_status + align256(max_status * 4);
     f.off_desc = f.off_splits + align256(max_splits * 8);
     f.off_probs = f.off_desc + align256(max_tickets * (int64_t)sizeof(TileDesc));
     f.off_tbase = f.off_probs + (max_probs > 0 ? align256(max_probs * (int64_t)sizeof(Prob)) : 0);
     f.off_sbase = f.off_tbase + (max_probs > 0 ? align256((rounds + 1) * f.stride * 4) : 0);
     f.bytes = f.off_sbase + (max_probs > 0 ? align256((rounds + 1) * f.stride * 4) : 0);
+    f.off_f2 = f.bytes;
+    f.f2_bytes = 0;
     return f;
 }
 
@@ -732,7 +781,8 @@ static unsigned grid_for(int64_t items, int threads, int64_t cap)
 // problem; capacity-sized persistent launches for a device-side table.
 template <class KT, class V>
 static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv, Forest F,
-                             const ForestPlan &fp, char *fw, hipStream_t st, Gate gate, bool leaves)
+                             const ForestPlan &fp, char *fw, hipStream_t st, Gate gate, bool leaves,
+                             const F2Tables *f2 = nullptr)
 {
     using C = SortCfg<KT, V>;
     constexpr int TILE = C::MERGE_NT * C::MERGE_IPT;
@@ -748,7 +798,25 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         F.stride = fp.stride;
     }
     const int R = F.use_m1 ? 1 : fp.rounds;
-    if (R > kMaxRounds) return hipErrorInvalidValue;
+    if (R > (fp.rounds > 0 ? fp.rounds : 1)) return hipErrorInvalidValue;
+    if (f2) {
+        // the tree tables travel with the call (see F2Tables)
+        char *img = fw + fp.off_f2;
+        hipError_t e = hipMemcpyAsync(img, f2->blob.data(), f2->blob.size(), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        F.use_f2 = 1;
+        F.f2.leaf_c = (const int64_t *)(img + f2->off_leaf_c);
+        F.f2.leaf_d = (const int64_t *)(img + f2->off_leaf_d);
+        F.f2.node_s = (const int64_t *)(img + f2->off_node_s);
+        F.f2.node_n = (const int64_t *)(img + f2->off_node_n);
+        F.f2.node_tb = (const unsigned *)(img + f2->off_node_tb);
+        F.f2.node_sb = (const unsigned *)(img + f2->off_node_sb);
+        F.f2.rb = (const unsigned *)(img + f2->off_rb);
+        F.f2.rt = (const unsigned *)(img + f2->off_rt);
+        F.f2.rs = (const unsigned *)(img + f2->off_rs);
+        F.f2.nleaves = f2->nleaves;
+        F.f2.q = f2->q;
+    }
 
     const bool tr = trace_on();
     // ticket counters and status words start at zero on every call
@@ -763,7 +831,8 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         if (tr) trace_end(st);
     }
 
-    auto leaf_fn = leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES>;
+    auto leaf_fn = f2 ? leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, true>
+                      : leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, false>;
     auto merge_fn = merge_kernel<KT, V, C::MERGE_NT, C::MERGE_IPT, C::MERGE_WAVES>;
     static int64_t merge_groups = 0;
     unsigned epoch = 1;
@@ -775,16 +844,18 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
             hipLaunchKernelGGL(leaf_fn, dim3((unsigned)fp.max_status), dim3(C::LEAF_NT), 0, st, Dk, Hk, Dv, Hv, F,
                                ctrl + 0, status, epoch, errw, gate);
         } else {
-            hipLaunchKernelGGL(leaf_fn, dim3((unsigned)((int64_t)1 << F.p0.depth)), dim3(C::LEAF_NT), 0, st, Dk,
-                               Hk, Dv, Hv, F, ctrl + 0, status, epoch, errw, gate);
+            const int64_t nl = f2 ? f2->nleaves : ((int64_t)1 << F.p0.depth);
+            hipLaunchKernelGGL(leaf_fn, dim3((unsigned)nl), dim3(C::LEAF_NT), 0, st, Dk, Hk, Dv, Hv, F, ctrl + 0,
+                               status, epoch, errw, gate);
         }
         if (tr) trace_end(st);
     }
     const int64_t mres = resident_groups(merge_fn, C::MERGE_NT, merge_groups);
     for (int r = 1; r <= R; ++r) {
         ++epoch;
-        const int64_t nsplit = table ? fp.max_splits : forest_splits<TILE>(F, F.p0, r);
-        const int64_t ntile = table ? fp.max_tickets : forest_tickets<TILE>(F, F.p0, r);
+        const int64_t nsplit = table ? fp.max_splits : f2 ? f2->rs[r] : forest_splits<TILE>(F, F.p0, r);
+        const int64_t ntile = table ? fp.max_tickets : f2 ? f2->rt[r] : forest_tickets<TILE>(F, F.p0, r);
+        if (ntile <= 0) continue;
         if (tr) trace_begin(TK_PARTITION, st);
         hipLaunchKernelGGL((partition_kernel<KT, TILE>), dim3(grid_for(nsplit, 256, 4096)), dim3(256), 0, st, Dk,
                            Hk, F, r, splits, gate);
@@ -795,15 +866,149 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         if (tr) trace_end(st);
         if (tr) trace_begin(TK_MERGE, st);
         hipLaunchKernelGGL(merge_fn, dim3((unsigned)(ntile < mres ? ntile : mres)), dim3(C::MERGE_NT), 0, st, Dk,
-                           Hk, Dv, Hv, F, r, (const TileDesc *)desc, ctrl + 32 * kMergeGroups * r, status, epoch,
+                           Hk, Dv, Hv, F, r, ntile, (const TileDesc *)desc, ctrl + 32 * kMergeGroups * r, status, epoch,
                            errw, gate);
         if (tr) trace_end(st);
     }
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Frogsort2 planning (host)
+// ---------------------------------------------------------------------------
+// The tree of an imbalanced split has leaves at many depths and no closed form
+// for "node i of level d", so the host walks it once (O(n / leaf) nodes) and
+// keeps the tables of the last few (n, q, leaf, tile) it planned.
+namespace {
+
+struct F2Walk {
+    int64_t q, leaf;
+    std::vector<int64_t> leaf_c, leaf_d;   // leaves in input order
+    std::vector<int64_t> ns, nn;           // merge nodes in post order
+    std::vector<int> nh;                   // their heights
+};
+
+int64_t f2_region(int64_t n, int64_t q) { return n + f2_inner(n, q); }
+
+// The node over [s, s + region) that holds input [c, c + n); returns its
+// height (0 for a leaf).  A left leaf's data start at its region's start, a
+// right leaf's at its end minus n.
+int f2_walk(F2Walk &W, int64_t s, int64_t n, int64_t c, int left)
+{
+    if (n <= W.leaf) {
+        W.leaf_c.push_back(c);
+        W.leaf_d.push_back(left ? s : s + f2_inner(n, W.q));
+        return 0;
+    }
+    const int64_t ni = f2_inner(n, W.q);
+    const int64_t nl = left ? n - ni : ni, nr = n - nl;
+    const int hl = f2_walk(W, s, nl, c, 1);
+    const int hr = f2_walk(W, s + f2_region(n, W.q) - f2_region(nr, W.q), nr, c + nl, 0);
+    const int h = 1 + (hl > hr ? hl : hr);
+    W.ns.push_back(s);
+    W.nn.push_back(n | (left ? kF2LeftBit : 0));
+    W.nh.push_back(h);
+    return h;
+}
+
+template <class T>
+int64_t f2_put(std::vector<char> &blob, const std::vector<T> &v)
+{
+    const int64_t off = align256((int64_t)blob.size());
+    blob.resize((size_t)(off + (int64_t)(v.size() * sizeof(T))));
+    if (!v.empty()) memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+}
+
+std::shared_ptr<const F2Tables> f2_build(int64_t n, int64_t q, int64_t leaf, int64_t tile)
+{
+    F2Walk W;
+    W.q = q;
+    W.leaf = leaf;
+    const int H = f2_walk(W, 0, n, 0, 1);
+    auto T = std::make_shared<F2Tables>();
+    T->n = n;
+    T->q = q;
+    T->leaf = leaf;
+    T->tile = tile;
+    T->rounds = H;
+    T->nleaves = (int64_t)W.leaf_c.size();
+    T->nnodes = (int64_t)W.ns.size();
+    // merge nodes grouped by height, post order within a height
+    std::vector<unsigned> rb((size_t)H + 2, 0u);
+    for (int h : W.nh) rb[(size_t)h + 1]++;
+    for (int r = 1; r <= H; ++r) rb[(size_t)r + 1] += rb[(size_t)r];
+    std::vector<unsigned> fill(rb.begin(), rb.end());
+    std::vector<int64_t> ns((size_t)T->nnodes), nn((size_t)T->nnodes);
+    for (size_t i = 0; i < W.ns.size(); ++i) {
+        const unsigned k = fill[(size_t)W.nh[i]]++;
+        ns[k] = W.ns[i];
+        nn[k] = W.nn[i];
+    }
+    std::vector<unsigned> tb((size_t)T->nnodes), sb((size_t)T->nnodes);
+    T->rt.assign((size_t)H + 1, 0u);
+    T->rs.assign((size_t)H + 1, 0u);
+    T->max_tickets = T->max_splits = 0;
+    for (int r = 1; r <= H; ++r) {
+        int64_t t = 0, sp = 0;
+        for (unsigned k = rb[(size_t)r]; k < rb[(size_t)r + 1]; ++k) {
+            const int64_t tpn = ((nn[k] & (kF2LeftBit - 1)) + tile - 1) / tile;
+            tb[k] = (unsigned)t;
+            sb[k] = (unsigned)sp;
+            t += tpn;
+            sp += tpn + 1;
+        }
+        T->rt[(size_t)r] = (unsigned)t;
+        T->rs[(size_t)r] = (unsigned)sp;
+        if (t > T->max_tickets) T->max_tickets = t;
+        if (sp > T->max_splits) T->max_splits = sp;
+    }
+    std::vector<int64_t> lc = W.leaf_c;
+    lc.push_back(n);
+    T->off_leaf_c = f2_put(T->blob, lc);
+    T->off_leaf_d = f2_put(T->blob, W.leaf_d);
+    T->off_node_s = f2_put(T->blob, ns);
+    T->off_node_n = f2_put(T->blob, nn);
+    T->off_node_tb = f2_put(T->blob, tb);
+    T->off_node_sb = f2_put(T->blob, sb);
+    T->off_rb = f2_put(T->blob, rb);
+    T->off_rt = f2_put(T->blob, T->rt);
+    T->off_rs = f2_put(T->blob, T->rs);
+    T->blob.resize((size_t)align256((int64_t)T->blob.size()));
+    return T;
+}
+
+std::mutex g_f2_mu;
+std::list<std::shared_ptr<const F2Tables>> g_f2_cache;   // most recently used first
+constexpr size_t kF2CacheEntries = 8;
+
+// Entries are immutable; a call holds its own reference for as long as it
+// reads one, so dropping an entry from the list never frees tables in use.
+std::shared_ptr<const F2Tables> f2_tables(int64_t n, int64_t q, int64_t leaf, int64_t tile)
+{
+    {
+        std::lock_guard<std::mutex> g(g_f2_mu);
+        for (auto it = g_f2_cache.begin(); it != g_f2_cache.end(); ++it) {
+            const F2Tables &t = **it;
+            if (t.n == n && t.q == q && t.leaf == leaf && t.tile == tile) {
+                auto hit = *it;
+                g_f2_cache.erase(it);
+                g_f2_cache.push_front(hit);
+                return hit;
+            }
+        }
+    }
+    auto t = f2_build(n, q, leaf, tile);
+    std::lock_guard<std::mutex> g(g_f2_mu);
+    g_f2_cache.push_front(t);
+    if (g_f2_cache.size() > kF2CacheEntries) g_f2_cache.pop_back();
+    return t;
+}
+
+}  // namespace
+
 template <class KT, class V>
-SortPlan make_plan(int64_t n)
+SortPlan make_plan(int64_t n, int64_t q)
 {
     using K = typename KT::T;
     constexpr bool HV = ValOps<V>::has;
@@ -811,12 +1016,29 @@ SortPlan make_plan(int64_t n)
     p.n = n;
     p.leaf = leaf_size<KT, V>();
     p.tile = tile_size<KT, V>();
-    p.depth = n > 1 ? frog_depth(n, p.leaf) : 0;
-    const int64_t h = n / 2;
+    p.q = q;
+    if (q != 0 && n > 1) {
+        p.f2 = f2_tables(n, q, p.leaf, p.tile);
+        p.depth = p.f2->rounds;
+        p.hlen = f2_inner(n, q);
+    } else {
+        p.depth = n > 1 ? frog_depth(n, p.leaf) : 0;
+        p.hlen = n / 2;
+    }
     p.off_hkeys = 0;
-    p.off_hvals = align256(h * (int64_t)sizeof(K));
-    p.off_forest = p.off_hvals + (HV ? align256(h * (int64_t)sizeof(V)) : 0);
-    p.forest = forest_plan_one<KT, V>(n);
+    p.off_hvals = align256(p.hlen * (int64_t)sizeof(K));
+    p.off_forest = p.off_hvals + (HV ? align256(p.hlen * (int64_t)sizeof(V)) : 0);
+    if (p.f2) {
+        const F2Tables &T = *p.f2;
+        const int64_t mt = T.max_tickets > 1 ? T.max_tickets : 1;
+        p.forest = layout_forest(0, T.rounds, mt, mt > T.nleaves ? mt : T.nleaves,
+                                 T.max_splits > 1 ? T.max_splits : 1, p.leaf, p.tile);
+        p.forest.off_f2 = p.forest.bytes;
+        p.forest.f2_bytes = (int64_t)T.blob.size();
+        p.forest.bytes += p.forest.f2_bytes;
+    } else {
+        p.forest = forest_plan_one<KT, V>(n);
+    }
     p.bytes = p.off_forest + p.forest.bytes;
     if (n <= 1) p.bytes = 0;
     return p;
@@ -832,12 +1054,12 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
     Forest F{};
     F.p0 = Prob{0, 0, n, p.depth, 0};
     return run_forest<KT, V>(keys, (K *)(ws + p.off_hkeys), vals, HV ? (V *)(ws + p.off_hvals) : nullptr, F,
-                             p.forest, ws + p.off_forest, st, gate, true);
+                             p.forest, ws + p.off_forest, st, gate, true, p.f2.get());
 }
 
 // explicit instantiations used by the ABI layer
-SortPlan plan_f64(int64_t n) { return make_plan<KeyF64, NoVal>(n); }
-SortPlan plan_kv(int64_t n) { return make_plan<KeyU64, uint32_t>(n); }
+SortPlan plan_f64(int64_t n, int64_t q) { return make_plan<KeyF64, NoVal>(n, q); }
+SortPlan plan_kv(int64_t n, int64_t q) { return make_plan<KeyU64, uint32_t>(n, q); }
 
 ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs, int merge_ipt)
 {

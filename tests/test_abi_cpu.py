@@ -58,7 +58,8 @@ def test_argument_errors_before_device():
     assert _call_f64(None, 10, 0.5, fake, need) == g.GS_EINVAL
     assert _call_f64(fake, 1000, 0.0, fake, need) == g.GS_EINVAL
     assert _call_f64(fake, 1000, float("nan"), fake, need) == g.GS_EINVAL
-    assert _call_f64(fake, 1000, 0.25, fake, need) == g.GS_EUNSUPPORTED
+    assert _call_f64(fake, 1000, 0.01, fake, need) == g.GS_EUNSUPPORTED      # below 1/64
+    assert g.gs_workspace_bytes_f64(1000, 0.01) == g.SIZE_MAX
     assert _call_f64(fake, 1000, 0.5, fake, need - 1) == g.GS_EWORKSPACE
     assert _call_f64(fake, 1000, 0.5, None, need) == g.GS_EWORKSPACE
     assert _call_f64(fake, 1000, 0.5, ctypes.c_void_p(0x100010), need) == g.GS_EINVAL
@@ -183,3 +184,53 @@ def test_target_argument_errors():
         assert g.lib.gs_sort_f64_target(fake, 1000, bad, 0.5, fake, need, None, None) == g.GS_EINVAL
         assert g.lib.gs_sort_kv_target(fake, fake, 1000, bad, 0.5, fake, 1 << 20, None, None) == g.GS_EINVAL
     assert g.lib.gs_sort_f64_target(None, 0, 2, 0.5, None, 0, None, None) == g.GS_OK
+
+
+FRACTIONS = [1 / 64, 0.05, 0.1, 0.2, 0.25, 1 / 3, 0.45, 0.4999]
+
+
+@pytest.mark.parametrize("kv", [False, True])
+@pytest.mark.parametrize("p", FRACTIONS)
+def test_frog2_plan_matches_oracle(orc, kv, p):
+    """The library's Frogsort2 planner walks the same tree as the oracle's
+    model: the same leaves (input offset, data start, length) in input order,
+    the same merge nodes, each merged in the round of its height, and a buffer
+    of floor(q n / 65536) elements."""
+    _, leaf = g.plan_depth(1 << 20, kv=kv)
+    q = orc.frog2_fraction_q(p)
+    for n in [2, leaf, leaf + 1, 3 * leaf + 7, 1000003, (1 << 22) + 12345]:
+        lv, nd, counts = g.plan_frog2(n, p, kv)
+        r = orc.frog2_geometry(n, q, leaf)
+        assert np.array_equal(lv, r["leaves"]), n
+        mine = sorted(map(tuple, nd.tolist()))
+        theirs = sorted(map(tuple, r["nodes"].tolist()))
+        assert mine == theirs, n
+        assert counts[2] == (r["nodes"][:, 3].max() if r["nodes"].size else 0)
+        assert counts[3] == (q * n) // 65536 == r["nslots"] - n
+
+
+@pytest.mark.parametrize("p", FRACTIONS)
+def test_frog2_workspace(p):
+    """%RAM follows the fraction: the buffer is floor(q n / 65536) elements
+    (never above p n) and the control area and tree tables stay a small
+    fraction of the data."""
+    import oracle
+    q = oracle.frog2_fraction_q(p)
+    for n in [5000, 1 << 20, (1 << 24) + 5]:
+        h = (q * n) // 65536
+        assert h <= p * n
+        b = g.gs_workspace_bytes_f64(n, p)
+        assert 8 * h <= b <= 8 * h + 0.02 * 8 * n + (1 << 20)
+        bk = g.gs_workspace_bytes_kv(n, p)
+        assert 12 * h <= bk <= 12 * h + 0.02 * 12 * n + (1 << 20)
+    if p <= 0.45:
+        assert g.gs_workspace_bytes_f64(1 << 24, p) < g.gs_workspace_bytes_f64(1 << 24, 0.5)
+
+
+def test_frog2_fraction_bounds():
+    assert g.gs_workspace_bytes_f64(1 << 20, 1 / 64) != g.SIZE_MAX
+    assert g.gs_workspace_bytes_f64(1 << 20, 1 / 64 - 1e-9) == g.SIZE_MAX
+    assert g.gs_workspace_bytes_f64(1 << 20, 0.5) == g.gs_workspace_bytes_f64(1 << 20, 0.9)
+    fake = ctypes.c_void_p(0x100000)
+    need = g.gs_workspace_bytes_seg(1000, 10)
+    assert g.lib.gs_segsort(fake, 1000, fake, 10, 0.25, fake, need, None, None) == g.GS_EUNSUPPORTED

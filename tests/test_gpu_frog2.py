@@ -1,0 +1,144 @@
+"""Frogsort2 on the GPU ("Frogsort2": inner branch and buffer both a fraction
+p < 1/2 of the data): parity with the CPU oracle through the C ABI, bit for
+bit, for fractions from 1/64 to just under 1/2, sizes from one leaf to many
+rounds with ragged tails, both key types and all four targets; at 2^28 the
+oracle's counting definition fixes sampled positions."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import announce, bits, multiset_hash_dev, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FRACTIONS = [1 / 64, 0.05, 0.1, 0.2, 1 / 3, 0.4999]
+SIZES = [2, 17, 8192, 8193, 12345, 65537, 100003, (1 << 20) + 7]
+PATTERNS = ["uniform", "tied", "presorted", "reversed", "zeros_signed"]
+
+
+@pytest.fixture(scope="module")
+def gs():
+    need_gpu()
+    import paper_2402_01816_amd as g
+    return g
+
+
+@pytest.mark.parametrize("pattern", PATTERNS)
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("p", FRACTIONS)
+def test_frog2_f64_parity(gs, orc, p, n, pattern):
+    announce("frog2 f64", p, n, pattern)
+    x = W.f64_pattern(pattern, n, seed=31 + n)
+    t = to_dev(x)
+    gs.gs_sort_f64(t, buffer_fraction=p)
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+@pytest.mark.parametrize("pattern", ["uniform", "few"])
+@pytest.mark.parametrize("n", [4097, 65537, (1 << 20) + 3])
+@pytest.mark.parametrize("p", [1 / 64, 0.1, 0.25, 0.45])
+def test_frog2_kv_parity(gs, orc, p, n, pattern):
+    announce("frog2 kv", p, n, pattern)
+    k, v = W.kv_pattern(pattern, n, seed=9)
+    tk = to_dev(k.view(np.int64))
+    tv = to_dev(v.view(np.int32))
+    gs.gs_sort_kv(tk, tv, buffer_fraction=p)
+    rk, rv = orc.sort_kv(k, v)
+    assert np.array_equal(tk.cpu().numpy().view(np.uint64), rk)
+    assert np.array_equal(tv.cpu().numpy().view(np.uint32), rv)
+
+
+@pytest.mark.parametrize("target", ("AscLeft", "AscRight", "DescLeft", "DescRight"))
+def test_frog2_targets(gs, orc, target):
+    n = (1 << 20) + 7
+    announce("frog2 target", target, n)
+    x = W.f64_pattern("zeros_signed", n, seed=3)
+    x[::61] = np.nan
+    x[::67] = -np.inf
+    t = to_dev(x)
+    gs.gs_sort_f64(t, buffer_fraction=0.1, target=target)
+    assert np.array_equal(bits(t), bits(orc.sort_f64_target(x, target)))
+    k, v = W.kv_pattern("few", n, seed=4)
+    tk = to_dev(k.view(np.int64))
+    tv = to_dev(v.view(np.int32))
+    gs.gs_sort_kv(tk, tv, buffer_fraction=0.2, target=target)
+    rk, rv = orc.sort_kv_target(k, v, target)
+    assert np.array_equal(tk.cpu().numpy().view(np.uint64), rk)
+    assert np.array_equal(tv.cpu().numpy().view(np.uint32), rv)
+
+
+@pytest.mark.parametrize("p", [0.05, 0.25])
+def test_frog2_report(gs, orc, p):
+    """The report carries the rounds (the root's height) and %RAM = 1 + the
+    buffer fraction + a small control area."""
+    n = 1 << 22
+    t = to_dev(W.f64_pattern("uniform", n, seed=2))
+    rep = gs.gs_sort_f64(t, buffer_fraction=p, report=True)
+    _, _, counts = gs.plan_frog2(n, p)
+    assert rep["levels"] == counts[2]
+    assert rep["workspace_bytes_used"] == gs.gs_workspace_bytes_f64(n, p)
+    assert 1 + p - 0.001 <= rep["ram_fraction"] < 1 + p + 0.02
+
+
+def test_frog2_repeated_calls(gs, orc):
+    """Calls with different fractions and sizes in a row, the last ones
+    reusing one workspace: the plan cache and the uploaded tables never mix."""
+    torch = need_gpu()
+    big = gs.gs_workspace_bytes_f64(300_001, 0.1)
+    ws = torch.empty(big + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off: off + big]
+    for i, (p, n) in enumerate([(0.1, 300_001), (0.3, 200_000), (0.05, 123_457), (0.1, 300_001),
+                                (0.49, 250_000), (0.2, 100_000)]):
+        announce("frog2 repeated", p, n)
+        x = W.f64_pattern("uniform", n, seed=40 + i)
+        t = to_dev(x)
+        need = gs.gs_workspace_bytes_f64(n, p)
+        gs.gs_sort_f64(t, buffer_fraction=p, workspace=ws if need <= big else None)
+        assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+@pytest.mark.parametrize("p", [0.1, 0.25])
+def test_frog2_full_size_sampled(gs, orc, p):
+    """n = 2^28: sampled positions from the oracle's counting definition,
+    plus sortedness and multiset equality over the whole output."""
+    torch = need_gpu()
+    n = 1 << 28
+    announce("frog2 full", p, n)
+    x = W.f64_pattern("uniform", n, seed=0)
+    t = to_dev(x)
+    h_in = multiset_hash_dev(t)
+    gs.gs_sort_f64(t, buffer_fraction=p)
+    torch.cuda.synchronize()
+    assert multiset_hash_dev(t) == h_in
+    assert bool((t[1:] >= t[:-1]).all().item())
+    rng = np.random.default_rng(2)
+    idx = np.concatenate([[0, n - 1], rng.integers(0, n, 14)])
+    ranks = orc.rank_f64(x, idx)
+    got = t[torch.from_numpy(ranks).to("cuda")].cpu().numpy()
+    assert np.array_equal(bits(got), bits(x[idx]))
+
+
+def test_frog2_rejects_capture(gs):
+    """A Frogsort2 call uploads host-built tables, so it refuses to be
+    recorded into a graph (and enqueues nothing)."""
+    torch = need_gpu()
+    n = 100_000
+    t = to_dev(W.f64_pattern("uniform", n, seed=1))
+    need = gs.gs_workspace_bytes_f64(n, 0.1)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off: off + need]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    err = None
+    with torch.cuda.stream(s):
+        g.capture_begin()
+        try:
+            gs.gs_sort_f64(t, buffer_fraction=0.1, workspace=ws, stream=s)
+        except gs.GsError as e:
+            err = e
+        finally:
+            g.capture_end()
+    assert err is not None and err.status == gs.GS_EUNSUPPORTED

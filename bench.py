@@ -236,6 +236,31 @@ def extras(gs, torch, W, log2n, dev):
         kv[pat] = {"n": nk, "ms": round(ms, 3), "gkeys_per_s": round(nk / (ms * 1e-3) / 1e9, 3)}
         del K, V, Kb, Vb
     res["key_value"] = kv
+    # Frogsort2: smaller buffer fractions on the headline input; %RAM is
+    # 1 + workspace / data and tFootprint = %RAM x runTime ("Sustainability
+    # measures")
+    x = torch.from_numpy(W.f64_pattern("uniform", n, seed=0)).to(dev)
+    buf = torch.empty_like(x)
+    f2 = {}
+    for p in (0.5, 0.45, 0.25, 0.1):
+        log(f"extras: buffer_fraction {p}")
+        need = gs.gs_workspace_bytes_f64(n, p)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        ws = ws[(-ws.data_ptr()) % 256:][:need]
+
+        def fn_f2(i, timed, p=p, ws=ws):
+            if timed is None:
+                buf.copy_(x)
+            else:
+                gs.gs_sort_f64(buf, buffer_fraction=p, workspace=ws)
+        gs.gs_sort_f64(buf.copy_(x), buffer_fraction=p, workspace=ws)
+        ms = _time_calls(torch, stream, fn_f2, 3)
+        ram = 1.0 + need / (8.0 * n)
+        f2[str(p)] = {"ms": round(ms, 3), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
+                      "ram_fraction": round(ram, 4), "t_footprint_ms": round(ram * ms, 3)}
+        del ws
+    del x, buf
+    res["buffer_fraction"] = f2
     return res
 
 

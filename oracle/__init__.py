@@ -70,6 +70,8 @@ def _load():
     lib.oracle_frog_geometry.restype = I64
     lib.oracle_frog2_model.argtypes = [P, I64, I64, I64, I64, P, P, P, P, I64, P, I64, P, I64, P]
     lib.oracle_frog2_model.restype = I64
+    lib.oracle_frog3_model.argtypes = [P, I64, I64, I64, I64, P, P, P, I64, P, I64, P, I64, P, I64, P]
+    lib.oracle_frog3_model.restype = I64
     lib.oracle_mlp_num_params.argtypes = []
     lib.oracle_mlp_num_params.restype = ctypes.c_int
     lib.oracle_mlp_forward.argtypes = [P, P, I64, P]
@@ -276,6 +278,56 @@ def _frog2(keys, n, q, leaf_max, max_snap, gap_shrink):
                    trace=trace[: int(counts[2]), :ns])
     res.update(leaves=leaves[:nl], nodes=nodes[:nn], compares=int(counts[0]), moves=int(counts[1]),
                nslots=int(ns), bad=int(counts[5]))
+    return res
+
+
+def frog3_model(keys, q: int, leaf_max: int, gap_shrink: int = 0):
+    """Run the instrumented Frogsort3 model (shared buffer floor(q*n/65536),
+    Frogsort1 subtrees with leaves of at most leaf_max elements) in place on
+    keys; keys None walks the geometry only.
+
+    Returns a dict with the sorted keys and their input indices, the leaves
+    (input offset, data start, length) in placement order, the merge nodes of
+    the Frogsort1 trees (region start, n, is_left, height), the spine merges
+    (outer elements, inner start, inner elements) bottom up, the Frogsort1
+    trees in running order (region start, n, input offset, is_left), the merge
+    comparison / move counts, the slot count and the violation bits."""
+    lib = _load()
+    n = 0 if keys is None else np.asarray(keys).size
+    return _frog3(lib, keys, n, q, leaf_max, gap_shrink)
+
+
+def frog3_geometry(n: int, q: int, leaf_max: int):
+    return _frog3(_load(), None, int(n), q, leaf_max, 0)
+
+
+def _frog3(lib, keys, n, q, leaf_max, gap_shrink):
+    counts = np.zeros(7, dtype=np.int64)
+    lib.oracle_frog3_model(None, n, q, leaf_max, gap_shrink, None, None, None, 0, None, 0,
+                           None, 0, None, 0, _ptr(counts))
+    sizes = [int(c) for c in counts]
+    leaves = np.zeros((max(sizes[2], 1), 3), dtype=np.int64)
+    nodes = np.zeros((max(sizes[3], 1), 4), dtype=np.int64)
+    spine = np.zeros((max(sizes[5], 1), 3), dtype=np.int64)
+    trees = np.zeros((max(sizes[6], 1), 4), dtype=np.int64)
+    res = {"n": n}
+    if keys is not None:
+        keys = np.ascontiguousarray(keys, dtype=np.float64)
+        out_k = np.zeros(max(n, 1), dtype=np.float64)
+        out_l = np.zeros(max(n, 1), dtype=np.int64)
+        ns = lib.oracle_frog3_model(_ptr(keys), n, q, leaf_max, gap_shrink, _ptr(out_k), _ptr(out_l),
+                                    _ptr(leaves), sizes[2], _ptr(nodes), sizes[3], _ptr(spine), sizes[5],
+                                    _ptr(trees), sizes[6], _ptr(counts))
+        if ns < 0:
+            raise MemoryError("oracle_frog3_model: allocation failed")
+        res.update(keys=out_k[:n], labels=out_l[:n])
+    else:
+        ns = lib.oracle_frog3_model(None, n, q, leaf_max, gap_shrink, None, None,
+                                    _ptr(leaves), sizes[2], _ptr(nodes), sizes[3], _ptr(spine), sizes[5],
+                                    _ptr(trees), sizes[6], _ptr(counts))
+    res.update(leaves=leaves[: sizes[2]], nodes=nodes[: sizes[3]], spine=spine[: sizes[5]],
+               trees=trees[: sizes[6]], compares=int(counts[0]), moves=int(counts[1]),
+               nslots=int(ns), bad=int(counts[4]))
     return res
 
 

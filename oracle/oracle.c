@@ -24,6 +24,8 @@
  *     pin the memory layout and the adaptivity counts the paper states.
  *   - oracle_frog2_* : the same for Frogsort2 ("Frogsort2": imbalanced splits,
  *     buffer p), checking on every write that the smaller buffer suffices.
+ *   - oracle_frog3_* : the same for Frogsort3 (the buffer shared by the two
+ *     branches in turn), with the input placed in place.
  *   - oracle_mlp_*   : an fp64 forward pass, MSE loss, backward pass and Adam
  *     step for the 1-64-64-1 ReLU network used by the learned bucket path
  *     (not part of the paper; parity of the GPU gradients is checked here).
@@ -686,6 +688,156 @@ int64_t oracle_frog2_model(const double *in, int64_t n, int64_t q, int64_t leaf_
     }
     counts[0] = M.cmp; counts[1] = M.mov; counts[2] = M.nsnap;
     counts[3] = M.nleaves; counts[4] = M.nnodes; counts[5] = M.bad;
+    int64_t ns = M.nslots;
+    free(M.key); free(M.lab);
+    return ns;
+}
+
+/* ------------------------------------------------------------------------ */
+/* instrumented model of Frogsort3 (one buffer shared by the branches)       */
+/* ------------------------------------------------------------------------ */
+/*
+ * "Frogsort3": instead of splitting the buffer between the two branches, the
+ * whole buffer serves one branch after the other, and a branch switches to
+ * Frogsort1 once the buffer is at least half its size.  Reading: the input
+ * sits in slots [0, n), the buffer is b = floor(q*n/65536) slots [n, n+b).  A
+ * node of m elements over slots [0, m + b) with b < floor(m/2) splits into an
+ * inner child of b elements (its last b input elements) and an outer child of
+ * m - b.  The inner child is sorted first, by Frogsort1 as a right node whose
+ * region ends at slot m + b, so its data end at [m, m + b) (its setup moves its
+ * chunk there; the space it passes through is free).  The outer child is then
+ * the same problem on m - b elements over [0, m), and the node finishes with a
+ * left-node merge of [0, m-b) and [m, m+b) into [0, m), written from the top.
+ * A node with floor(m/2) <= b is one Frogsort1 tree over [0, m + floor(m/2)).
+ *
+ * Every placement and merge write is checked as in the Frogsort2 model (bit 0
+ * of `bad`; bit 1: an empty buffer where the node still has to split).  gap_shrink > 0 ends every inner child that many slots early, so
+ * a test can see the check fire.
+ */
+static int64_t f3_r1(int64_t m) { return m + m / 2; }
+
+/* In-place setup of a Frogsort1 subtree over [s, s + f3_r1(n)) whose input
+   sits at [c, c + n): leaves from right to left, each chunk moved from its
+   top element down (every destination is at or after its source), then
+   sorted in place. */
+static void f3_place(frog2_model *M, int64_t s, int64_t n, int64_t c, int left)
+{
+    if (n <= M->leaf_max) {
+        int64_t d = left ? s : s + f3_r1(n) - n;
+        if (M->nleaves < M->max_leaves) {
+            M->leaves[3 * M->nleaves + 0] = c;
+            M->leaves[3 * M->nleaves + 1] = d;
+            M->leaves[3 * M->nleaves + 2] = n;
+        }
+        M->nleaves++;
+        if (!M->key) return;
+        int64_t mov = M->mov;
+        for (int64_t i = n - 1; i >= 0; i--) f2_put(M, d + i, c + i);
+        M->mov = mov;                        /* placement is not counted as merge moves */
+        for (int64_t i = 1; i < n; i++) {
+            double k = M->key[d + i];
+            int64_t l = M->lab[d + i], j = i - 1;
+            while (j >= 0 && oracle_less_f64(k, M->key[d + j])) {
+                M->key[d + j + 1] = M->key[d + j];
+                M->lab[d + j + 1] = M->lab[d + j];
+                j--;
+            }
+            M->key[d + j + 1] = k;
+            M->lab[d + j + 1] = l;
+        }
+        return;
+    }
+    int64_t nl = left ? (n + 1) / 2 : n / 2, nr = n - nl;
+    f3_place(M, s + f3_r1(n) - f3_r1(nr), nr, c + nl, 0);
+    f3_place(M, s, nl, c, 1);
+}
+
+/* The spine: a node of m elements over [0, m + b).  spine[] receives
+   {outer elements, inner start, inner elements} of every spine merge, bottom
+   up; tree[] {region start, elements, input offset, is_left} of every
+   Frogsort1 tree in the order they run. */
+typedef struct {
+    int64_t *spine, max_spine, nspine;
+    int64_t *tree, max_tree, ntree;
+    int64_t shrink;
+} frog3_sched;
+
+static void f3_tree(frog2_model *M, frog3_sched *S, int64_t s, int64_t n, int64_t c, int left)
+{
+    if (S->ntree < S->max_tree) {
+        S->tree[4 * S->ntree + 0] = s;
+        S->tree[4 * S->ntree + 1] = n;
+        S->tree[4 * S->ntree + 2] = c;
+        S->tree[4 * S->ntree + 3] = left;
+    }
+    S->ntree++;
+    f3_place(M, s, n, c, left);
+    f2_node(M, s, n, left);
+}
+
+static void f3_node(frog2_model *M, frog3_sched *S, int64_t m, int64_t b)
+{
+    if (m / 2 <= b) { f3_tree(M, S, 0, m, 0, 1); return; }
+    if (b < 1) { M->bad |= 2; return; }              /* no buffer to share */
+    int64_t end = m + b - S->shrink;                 /* the inner child's region end */
+    f3_tree(M, S, end - f3_r1(b), b, m - b, 0);
+    f3_node(M, S, m - b, b);
+    int64_t nl = m - b, nr = b, Lb = 0, Rb = end - b;
+    int64_t i = nl - 1, j = nr - 1, w = m - 1;
+    while (M->key && j >= 0) {
+        if (i < 0) { f2_put(M, w--, Rb + j); j--; continue; }
+        M->cmp++;
+        if (oracle_less_f64(M->key[Rb + j], M->key[Lb + i])) { f2_put(M, w--, Lb + i); i--; }
+        else                                                 { f2_put(M, w--, Rb + j); j--; }
+    }
+    if (S->nspine < S->max_spine) {
+        S->spine[3 * S->nspine + 0] = nl;
+        S->spine[3 * S->nspine + 1] = Rb;
+        S->spine[3 * S->nspine + 2] = nr;
+    }
+    S->nspine++;
+}
+
+/*
+ * Run the model on in[0, n) (in == NULL: geometry only).  Outputs as for
+ * oracle_frog2_model, plus the spine merges and the Frogsort1 trees.
+ *   counts: {comparisons, moves, leaves, nodes, bad, spine merges, trees}
+ * Returns the number of slots n + floor(q*n/65536), or -1 on allocation
+ * failure.
+ */
+int64_t oracle_frog3_model(const double *in, int64_t n, int64_t q, int64_t leaf_max, int64_t gap_shrink,
+                           double *out_key, int64_t *out_label,
+                           int64_t *leaves, int64_t max_leaves, int64_t *nodes, int64_t max_nodes,
+                           int64_t *spine, int64_t max_spine, int64_t *tree, int64_t max_tree,
+                           int64_t *counts)
+{
+    frog2_model M;
+    frog3_sched S;
+    memset(&M, 0, sizeof M);
+    memset(&S, 0, sizeof S);
+    for (int i = 0; i < 7; i++) counts[i] = 0;
+    if (n <= 0) return 0;
+    int64_t b = n * q / 65536;
+    M.q = 32768;                                     /* the Frogsort1 subtrees */
+    M.leaf_max = leaf_max < 1 ? 1 : leaf_max;
+    M.leaves = leaves; M.max_leaves = leaves ? max_leaves : 0;
+    M.nodes = nodes;   M.max_nodes = nodes ? max_nodes : 0;
+    S.spine = spine;   S.max_spine = spine ? max_spine : 0;
+    S.tree = tree;     S.max_tree = tree ? max_tree : 0;
+    S.shrink = gap_shrink;
+    M.nslots = n + (n / 2 <= b ? n / 2 : b);
+    if (in) {
+        M.key = (double *)calloc((size_t)M.nslots, sizeof(double));
+        M.lab = (int64_t *)malloc((size_t)M.nslots * sizeof(int64_t));
+        if (!M.key || !M.lab) { free(M.key); free(M.lab); return -1; }
+        for (int64_t p = 0; p < M.nslots; p++) M.lab[p] = -1;
+        for (int64_t p = 0; p < n; p++) { M.key[p] = in[p]; M.lab[p] = p; }
+    }
+    f3_node(&M, &S, n, b);
+    if (in && out_key) memcpy(out_key, M.key, (size_t)n * sizeof(double));
+    if (in && out_label) memcpy(out_label, M.lab, (size_t)n * sizeof(int64_t));
+    counts[0] = M.cmp; counts[1] = M.mov; counts[2] = M.nleaves; counts[3] = M.nnodes;
+    counts[4] = M.bad; counts[5] = S.nspine; counts[6] = S.ntree;
     int64_t ns = M.nslots;
     free(M.key); free(M.lab);
     return ns;

@@ -395,6 +395,92 @@ def test_frog2_presorted_and_reversed_counts(orc, q):
 
 
 # --------------------------------------------------------------------------
+# Frogsort3 model: one buffer shared by the branches in turn
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 33, 100, 257, 1000])
+def test_frog3_with_enough_buffer_is_frogsort1(orc, n):
+    """With a buffer of at least half the data the top node switches to
+    Frogsort1 at once: the same result, compares and moves as the Frogsort1
+    special case of the Frogsort2 model."""
+    rng = np.random.default_rng(8000 + n)
+    x = rng.integers(0, max(2, n // 4), size=n).astype(np.float64)
+    a = orc.frog3_model(x, 32768, 4)
+    b = orc.frog2_model(x, 32768, 4)
+    assert a["bad"] == 0 and a["spine"].shape[0] == 0 and a["trees"].shape[0] == 1
+    assert a["nslots"] == b["nslots"] == n + n // 2
+    assert (a["compares"], a["moves"]) == (b["compares"], b["moves"])
+    assert np.array_equal(a["labels"], b["labels"])
+
+
+@pytest.mark.parametrize("q", F2_QS)
+@pytest.mark.parametrize("leaf_max", [1, 5, 64])
+def test_frog3_sorts_stably_within_its_buffer(orc, q, leaf_max):
+    """Every fraction reaches the definition in place with n + min(b, n/2)
+    slots, b = floor(q n / 65536), and no write lands on an unread element."""
+    rng = np.random.default_rng(q * 7 + leaf_max)
+    for n in [2, 3, 64, 65, 300, 1000, 2049, 5000]:
+        b = (q * n) // 65536
+        x = rng.integers(0, max(2, n // 5), size=n).astype(np.float64)
+        x[rng.random(n) < 0.1] = -0.0
+        x[rng.random(n) < 0.05] = np.nan
+        r = orc.frog3_model(x, q, leaf_max)
+        if b < 1 and n // 2 > b:
+            assert r["bad"] & 2
+            continue
+        assert r["bad"] == 0, (q, leaf_max, n)
+        assert r["nslots"] == n + min(b, n // 2)
+        p = _stable_order(x)
+        assert np.array_equal(r["labels"], p)
+        assert np.array_equal(r["keys"].view(np.uint64), x[p].view(np.uint64))
+
+
+@pytest.mark.parametrize("q", [1024, 6553, 16384])
+def test_frog3_check_fires_on_a_short_gap(orc, q):
+    rng = np.random.default_rng(q)
+    x = rng.random(3000)
+    assert orc.frog3_model(x, q, 16)["bad"] == 0
+    assert orc.frog3_model(x, q, 16, gap_shrink=1)["bad"] & 1
+
+
+@pytest.mark.parametrize("q", [1024, 3277, 6553, 13107, 21845, 32767])
+@pytest.mark.parametrize("n", [5000, 1 << 16, (1 << 20) + 3])
+def test_frog3_schedule_rules(orc, q, n):
+    """The spine takes b = floor(q n / 65536) elements at a time off the end
+    of the input until the buffer covers half of what is left; each piece is
+    one Frogsort1 tree, a right node whose region ends b slots past its input;
+    the rest is one Frogsort1 tree at slot 0; the spine merges run bottom up."""
+    b = (q * n) // 65536
+    g = orc.frog3_geometry(n, q, 512)
+    assert g["bad"] == 0
+    sizes = []
+    m = n
+    while m // 2 > b:
+        sizes.append(m)
+        m -= b
+    K = len(sizes)
+    assert g["spine"].shape[0] == K and g["trees"].shape[0] == K + 1
+    for k, mk in enumerate(sizes):
+        s, size, c, left = g["trees"][k]
+        assert (size, c, left) == (b, mk - b, 0)
+        assert s + b + b // 2 == mk + b                   # the region ends at mk + b
+    assert tuple(g["trees"][K]) == (0, m, 0, 1)
+    for k, (nl, r0, nr) in enumerate(g["spine"]):
+        mk = sizes[K - 1 - k]
+        assert (nl, r0, nr) == (mk - b, mk, b)
+    assert g["nslots"] == n + (b if K else n // 2)
+
+
+@pytest.mark.parametrize("q", [3277, 6553, 32767])
+def test_frog3_presorted_counts(orc, q):
+    """Presorted input: every merge, in the Frogsort1 trees and on the spine,
+    compares and moves only its inner run."""
+    n = 3000
+    r = orc.frog3_model(np.arange(n, dtype=np.float64), q, 8)
+    inner = int(sum(m // 2 for m in r["nodes"][:, 1])) + int(r["spine"][:, 2].sum())
+    assert r["compares"] == r["moves"] == inner
+
+
+# --------------------------------------------------------------------------
 # network reference: forward closed forms, finite differences, Adam
 # --------------------------------------------------------------------------
 def test_mlp_forward_closed_form(orc):

@@ -708,7 +708,9 @@ int64_t oracle_frog2_model(const double *in, int64_t n, int64_t q, int64_t leaf_
  * chunk there; the space it passes through is free).  The outer child is then
  * the same problem on m - b elements over [0, m), and the node finishes with a
  * left-node merge of [0, m-b) and [m, m+b) into [0, m), written from the top.
- * A node with floor(m/2) <= b is one Frogsort1 tree over [0, m + floor(m/2)).
+ * A node with floor(m/2) <= b is one Frogsort1 tree over [0, m + floor(m/2)),
+ * and so is a node of at most leaf_max elements: that tree is a single leaf,
+ * sorted where it lies, which needs no buffer at all.
  *
  * Every placement and merge write is checked as in the Frogsort2 model (bit 0
  * of `bad`; bit 1: an empty buffer where the node still has to split).  gap_shrink > 0 ends every inner child that many slots early, so
@@ -777,7 +779,7 @@ static void f3_tree(frog2_model *M, frog3_sched *S, int64_t s, int64_t n, int64_
 
 static void f3_node(frog2_model *M, frog3_sched *S, int64_t m, int64_t b)
 {
-    if (m / 2 <= b) { f3_tree(M, S, 0, m, 0, 1); return; }
+    if (m / 2 <= b || m <= M->leaf_max) { f3_tree(M, S, 0, m, 0, 1); return; }
     if (b < 1) { M->bad |= 2; return; }              /* no buffer to share */
     int64_t end = m + b - S->shrink;                 /* the inner child's region end */
     f3_tree(M, S, end - f3_r1(b), b, m - b, 0);

@@ -23,10 +23,18 @@
  *     ("Sustainability measures") is exactly 1 + ws_bytes / data_bytes.
  *   - Errors are returned, never thrown.  Argument errors are detected before
  *     any device work is enqueued, so the input is untouched on any error.
- *   - `buffer_fraction` is the cap on extra buffer as a fraction of the data.
- *     Values >= 0.5 select Frogsort1 (buffer floor(n/2); never more).  Values in
- *     (0, 0.5) would select Frogsort2 ("Frogsort2": inner branch p*n) and return
- *     GS_EUNSUPPORTED in this version.  NaN, <= 0 -> GS_EINVAL.
+ *   - `buffer_fraction` p is the cap on extra buffer as a fraction of the data.
+ *     p >= 0.5 selects Frogsort1 (buffer floor(n/2); never more).  For p in
+ *     [1/64, 0.5) the fraction is rounded down to q/65536 (q = floor(65536 p))
+ *     and the sort runs Frogsort3 ("Frogsort3": one buffer of floor(q n/65536)
+ *     elements serving the branches in turn) unless gs_sort_*_ex asks for
+ *     Frogsort2 ("Frogsort2": every inner branch, and the buffer, the fraction
+ *     p).  p in (0, 1/64) -> GS_EUNSUPPORTED (the trees get hundreds of levels
+ *     deep); NaN, <= 0 -> GS_EINVAL.  The segmented sort takes p >= 0.5 only.
+ *   - A call with p < 0.5 plans its tree on the host and copies the plan's
+ *     tables into the workspace on the stream (hipMemcpyAsync from host
+ *     memory the library keeps), so it returns GS_EUNSUPPORTED while the
+ *     stream is capturing a graph.
  *   - Calls on different streams with different workspaces may run
  *     concurrently; two calls sharing one workspace must be ordered.
  *
@@ -48,7 +56,7 @@ extern "C" {
 typedef enum {
     GS_OK = 0,
     GS_EINVAL = 1,        /* bad argument (null pointer with n > 0, n < 0, bad fraction, bad offsets) */
-    GS_EUNSUPPORTED = 2,  /* valid request this version does not implement (buffer_fraction < 0.5) */
+    GS_EUNSUPPORTED = 2,  /* valid request this version does not implement (buffer_fraction < 1/64, ...) */
     GS_EWORKSPACE = 3,    /* ws_bytes below the size the matching gs_workspace_bytes_* returns */
     GS_ENODEVICE = 4,     /* no HIP device visible */
     GS_EDEVICE = 5        /* a HIP runtime call failed; see gs_last_error_detail() */
@@ -115,6 +123,20 @@ gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_
                              void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction,
                             void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+
+/* The same with the tree named ("Frogsort1", "Frogsort2", "Frogsort3").
+   GS_ALGO_AUTO is what the calls above run: Frogsort1 for p >= 0.5, Frogsort3
+   below.  GS_ALGO_FROGSORT1 with p < 0.5 -> GS_EINVAL; Frogsort2 / Frogsort3
+   with p >= 0.5 run their own tree at p = 0.5 (Frogsort3 is then one Frogsort1
+   tree).  The workspace depends on the tree: size it with the _ex queries.
+   rep->levels counts every merge round of the call. */
+typedef enum { GS_ALGO_AUTO = 0, GS_ALGO_FROGSORT1 = 1, GS_ALGO_FROGSORT2 = 2, GS_ALGO_FROGSORT3 = 3 } gs_algo;
+size_t gs_workspace_bytes_f64_ex(int64_t n, double buffer_fraction, int algo);
+size_t gs_workspace_bytes_kv_ex(int64_t n, double buffer_fraction, int algo);
+gs_status gs_sort_f64_ex(double *keys, int64_t n, int target, double buffer_fraction, int algo,
+                         void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+gs_status gs_sort_kv_ex(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction, int algo,
+                        void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 
 /* Sort every segment keys[offsets[i], offsets[i+1]) on its own, for
    i in [0, num_segments); `offsets` holds num_segments+1 int64 values (device).
@@ -218,6 +240,19 @@ int gs_plan_depth(int64_t n, int is_kv, int64_t *leaf_max);
 /* Geometry of node `idx` at `depth` of the frog tree over n elements:
    out[0..4] = region start, data size, is_left, data start, input offset. */
 void gs_plan_node(int64_t n, int depth, int64_t idx, int64_t *out);
+/* The Frogsort2 tree for n keys at buffer_fraction (is_kv: the key/value leaf
+   size): leaves[3*i..] = input offset, data start, length (input order);
+   nodes[4*j..] = region start, elements, is_left, merge round; counts[0..5] =
+   leaves, nodes, rounds, buffer elements, tiles and splits of the largest
+   round.  Arrays are filled up to their capacities.  -1 on bad arguments. */
+int gs_plan_frog2(int64_t n, double buffer_fraction, int is_kv, int64_t *leaves, int64_t max_leaves,
+                  int64_t *nodes, int64_t max_nodes, int64_t *counts);
+/* The Frogsort3 schedule: trees[4*i..] = root region start, elements, input
+   offset, is_left (running order); spine[3*k..] = outer elements, inner start,
+   inner elements (bottom up); leaves[3*i..] of every tree; counts[0..5] =
+   trees, spine merges, leaves, merge rounds, buffer elements, b. */
+int gs_plan_frog3(int64_t n, double buffer_fraction, int is_kv, int64_t *trees, int64_t max_trees, int64_t *spine,
+                  int64_t max_spine, int64_t *leaves, int64_t max_leaves, int64_t *counts);
 
 #ifdef __cplusplus
 }

@@ -113,6 +113,14 @@ _SIGS = {
     "gs_plan_node": ([_I64, ctypes.c_int, _I64, ctypes.POINTER(_I64)], None),
     "gs_plan_frog2": ([_I64, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64, ctypes.c_void_p, _I64,
                        ctypes.c_void_p], ctypes.c_int),
+    "gs_plan_frog3": ([_I64, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64, ctypes.c_void_p, _I64,
+                       ctypes.c_void_p, _I64, ctypes.c_void_p], ctypes.c_int),
+    "gs_workspace_bytes_f64_ex": ([_I64, _D, ctypes.c_int], _SZ),
+    "gs_workspace_bytes_kv_ex": ([_I64, _D, ctypes.c_int], _SZ),
+    "gs_sort_f64_ex": ([_P, _I64, ctypes.c_int, _D, ctypes.c_int, _P, _SZ, _P, ctypes.POINTER(GsReport)],
+                       ctypes.c_int),
+    "gs_sort_kv_ex": ([_P, _P, _I64, ctypes.c_int, _D, ctypes.c_int, _P, _SZ, _P, ctypes.POINTER(GsReport)],
+                      ctypes.c_int),
 }
 _OPTIONAL = {
     "gs_workspace_bytes_seg": ([_I64, _I64, _D], _SZ),
@@ -162,12 +170,21 @@ def _check(status: int, where: str):
 # ---------------------------------------------------------------------------
 # workspace queries
 # ---------------------------------------------------------------------------
-def gs_workspace_bytes_f64(n: int, buffer_fraction: float = 0.5) -> int:
-    return int(_lib.gs_workspace_bytes_f64(n, buffer_fraction))
+ALGOS = {"auto": 0, "frogsort1": 1, "frogsort2": 2, "frogsort3": 3}
 
 
-def gs_workspace_bytes_kv(n: int, buffer_fraction: float = 0.5) -> int:
-    return int(_lib.gs_workspace_bytes_kv(n, buffer_fraction))
+def _algo(algo) -> int:
+    if isinstance(algo, str):
+        return ALGOS[algo.lower()]
+    return int(algo)
+
+
+def gs_workspace_bytes_f64(n: int, buffer_fraction: float = 0.5, algo="auto") -> int:
+    return int(_lib.gs_workspace_bytes_f64_ex(n, buffer_fraction, _algo(algo)))
+
+
+def gs_workspace_bytes_kv(n: int, buffer_fraction: float = 0.5, algo="auto") -> int:
+    return int(_lib.gs_workspace_bytes_kv_ex(n, buffer_fraction, _algo(algo)))
 
 
 def gs_workspace_bytes_seg(num_keys: int, num_segments: int, buffer_fraction: float = 0.5) -> int:
@@ -211,6 +228,26 @@ def plan_frog2(n: int, buffer_fraction: float, kv: bool = False):
     _lib.gs_plan_frog2(n, buffer_fraction, 1 if kv else 0, leaves.ctypes.data, leaves.shape[0],
                        nodes.ctypes.data, int(counts[1]), counts.ctypes.data)
     return leaves, nodes[: int(counts[1])], tuple(int(c) for c in counts)
+
+
+def plan_frog3(n: int, buffer_fraction: float, kv: bool = False):
+    """The library's Frogsort3 schedule for n keys (host only): trees as rows
+    (root region start, elements, input offset, is_left) in running order,
+    spine merges as rows (outer elements, inner start, inner elements) bottom
+    up, every tree's leaves (input offset, data start, length), and the counts
+    (trees, spine merges, leaves, merge rounds, buffer elements, b)."""
+    import numpy as np
+    counts = np.zeros(6, dtype=np.int64)
+    if _lib.gs_plan_frog3(n, buffer_fraction, 1 if kv else 0, None, 0, None, 0, None, 0,
+                          counts.ctypes.data) != 0:
+        raise ValueError("no Frogsort3 plan for these arguments")
+    trees = np.zeros((int(counts[0]), 4), dtype=np.int64)
+    spine = np.zeros((max(int(counts[1]), 1), 3), dtype=np.int64)
+    leaves = np.zeros((int(counts[2]), 3), dtype=np.int64)
+    _lib.gs_plan_frog3(n, buffer_fraction, 1 if kv else 0, trees.ctypes.data, trees.shape[0],
+                       spine.ctypes.data, int(counts[1]), leaves.ctypes.data, leaves.shape[0],
+                       counts.ctypes.data)
+    return trees, spine[: int(counts[1])], leaves, tuple(int(c) for c in counts)
 
 
 # ---------------------------------------------------------------------------
@@ -268,26 +305,27 @@ def _target(target) -> int:
 
 
 def gs_sort_f64(keys, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False,
-                target="AscLeft"):
+                target="AscLeft", algo="auto"):
     """Stable in-place sort of a contiguous float64 device tensor; target one
-    of AscLeft (default), AscRight, DescLeft, DescRight."""
+    of AscLeft (default), AscRight, DescLeft, DescRight; algo one of auto,
+    frogsort1, frogsort2, frogsort3."""
     torch = _torch()
     kp = _dev_ptr(keys, "keys", (torch.float64,))
     n = keys.numel()
-    need = gs_workspace_bytes_f64(n, buffer_fraction)
+    need = gs_workspace_bytes_f64(n, buffer_fraction, algo)
     if need == SIZE_MAX:
         need = 0
     ws, wsb = _workspace(need, keys.device, workspace)
     r = _rep(report)
-    st = _lib.gs_sort_f64_target(kp, n, _target(target), buffer_fraction,
-                                 ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
-                                 _stream_ptr(stream, keys.device), _rep_ptr(r))
+    st = _lib.gs_sort_f64_ex(kp, n, _target(target), buffer_fraction, _algo(algo),
+                             ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                             _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_sort_f64")
     return r.as_dict() if r is not None else None
 
 
 def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False,
-               target="AscLeft"):
+               target="AscLeft", algo="auto"):
     """Stable in-place sort of 64-bit keys (int64 or uint64 storage, compared
     as unsigned) carrying 32-bit values (int32 or uint32 storage); target as
     for gs_sort_f64."""
@@ -299,14 +337,14 @@ def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=
     if keys.numel() != vals.numel():
         raise ValueError("keys and vals differ in length")
     n = keys.numel()
-    need = gs_workspace_bytes_kv(n, buffer_fraction)
+    need = gs_workspace_bytes_kv(n, buffer_fraction, algo)
     if need == SIZE_MAX:
         need = 0
     ws, wsb = _workspace(need, keys.device, workspace)
     r = _rep(report)
-    st = _lib.gs_sort_kv_target(kp, vp, n, _target(target), buffer_fraction,
-                                ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
-                                _stream_ptr(stream, keys.device), _rep_ptr(r))
+    st = _lib.gs_sort_kv_ex(kp, vp, n, _target(target), buffer_fraction, _algo(algo),
+                            ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
+                            _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_sort_kv")
     return r.as_dict() if r is not None else None
 

@@ -50,18 +50,29 @@ gs_status check_device()
     return GS_OK;
 }
 
-// buffer_fraction >= 0.5: Frogsort1 (*q = 0).  In [1/64, 0.5): Frogsort2 with
-// the fraction rounded down to q / 2^16, so the buffer never exceeds it.
-// Below 1/64 the imbalanced tree grows too deep to be worth running.
-gs_status check_fraction(double f, int64_t *q)
+// Which tree a call runs.  buffer_fraction >= 0.5 with GS_ALGO_AUTO (or
+// GS_ALGO_FROGSORT1): Frogsort1, buffer floor(n/2).  Below 0.5 the fraction is
+// rounded down to q / 2^16 (so the buffer never exceeds it) and AUTO runs
+// Frogsort3, the faster of the two small-buffer trees on this device;
+// Frogsort2 / Frogsort3 can be asked for by name (at a fraction >= 0.5 they
+// run with q = 2^15).  Below 1/64 both grow too deep to be worth running.
+constexpr int kAutoSmallBuffer = gs::kAlgoFrog3;
+
+gs_status resolve_algo(double f, int algo, int *out, int64_t *q)
 {
     *q = 0;
+    *out = gs::kAlgoFrog1;
+    if (algo < GS_ALGO_AUTO || algo > GS_ALGO_FROGSORT3) return fail(GS_EINVAL, "unknown algorithm %d", algo);
     if (!(f > 0.0)) return fail(GS_EINVAL, "buffer_fraction must be > 0 (got %g)", f);
-    if (f >= 0.5) return GS_OK;
-    const int64_t v = (int64_t)floor(f * 65536.0);
+    if (algo == GS_ALGO_FROGSORT1 || (algo == GS_ALGO_AUTO && f >= 0.5)) {
+        if (f < 0.5) return fail(GS_EINVAL, "Frogsort1 needs buffer_fraction >= 0.5 (got %g)", f);
+        return GS_OK;
+    }
+    const int64_t v = f >= 0.5 ? 32768 : (int64_t)floor(f * 65536.0);
     if (v < gs::kF2MinQ)
         return fail(GS_EUNSUPPORTED, "buffer_fraction %g is below the smallest supported, 1/64", f);
     *q = v;
+    *out = algo == GS_ALGO_FROGSORT2 ? gs::kAlgoFrog2 : algo == GS_ALGO_FROGSORT3 ? gs::kAlgoFrog3 : kAutoSmallBuffer;
     return GS_OK;
 }
 
@@ -69,8 +80,9 @@ gs_status check_fraction(double f, int64_t *q)
 gs_status check_fraction_seg(double f)
 {
     int64_t q = 0;
-    gs_status s = check_fraction(f, &q);
-    if (s == GS_OK && q != 0)
+    int a = 0;
+    gs_status s = resolve_algo(f, GS_ALGO_AUTO, &a, &q);
+    if (s == GS_OK && a != gs::kAlgoFrog1)
         return fail(GS_EUNSUPPORTED, "segmented sort: buffer_fraction %g < 0.5 is not built", f);
     return s;
 }
@@ -203,20 +215,32 @@ const char *gs_last_error_detail(void) { return g_detail.c_str(); }
 
 const char *gs_version(void) { return "0.1.0 gfx950"; }
 
-size_t gs_workspace_bytes_f64(int64_t n, double buffer_fraction)
+size_t gs_workspace_bytes_f64_ex(int64_t n, double buffer_fraction, int algo)
 {
     int64_t q = 0;
-    if (n < 0 || n > ((int64_t)1 << 40) || check_fraction(buffer_fraction, &q) != GS_OK) return SIZE_MAX;
+    int a = 0;
+    if (n < 0 || n > ((int64_t)1 << 40) || resolve_algo(buffer_fraction, algo, &a, &q) != GS_OK) return SIZE_MAX;
     if (n <= 1) return 0;
-    return (size_t)gs::plan_f64(n, q).bytes;
+    return (size_t)gs::plan_f64(n, q, a).bytes;
+}
+
+size_t gs_workspace_bytes_kv_ex(int64_t n, double buffer_fraction, int algo)
+{
+    int64_t q = 0;
+    int a = 0;
+    if (n < 0 || n > ((int64_t)1 << 40) || resolve_algo(buffer_fraction, algo, &a, &q) != GS_OK) return SIZE_MAX;
+    if (n <= 1) return 0;
+    return (size_t)gs::plan_kv(n, q, a).bytes;
+}
+
+size_t gs_workspace_bytes_f64(int64_t n, double buffer_fraction)
+{
+    return gs_workspace_bytes_f64_ex(n, buffer_fraction, GS_ALGO_AUTO);
 }
 
 size_t gs_workspace_bytes_kv(int64_t n, double buffer_fraction)
 {
-    int64_t q = 0;
-    if (n < 0 || n > ((int64_t)1 << 40) || check_fraction(buffer_fraction, &q) != GS_OK) return SIZE_MAX;
-    if (n <= 1) return 0;
-    return (size_t)gs::plan_kv(n, q).bytes;
+    return gs_workspace_bytes_kv_ex(n, buffer_fraction, GS_ALGO_AUTO);
 }
 
 int gs_plan_depth(int64_t n, int is_kv, int64_t *leaf_max)
@@ -240,8 +264,10 @@ int gs_plan_frog2(int64_t n, double buffer_fraction, int is_kv, int64_t *leaves,
                   int64_t *nodes, int64_t max_nodes, int64_t *counts)
 {
     int64_t q = 0;
-    if (n < 2 || n > ((int64_t)1 << 32) || check_fraction(buffer_fraction, &q) != GS_OK || q == 0) return -1;
-    const gs::SortPlan p = is_kv ? gs::plan_kv(n, q) : gs::plan_f64(n, q);
+    int a = 0;
+    if (n < 2 || n > ((int64_t)1 << 32) || resolve_algo(buffer_fraction, GS_ALGO_FROGSORT2, &a, &q) != GS_OK)
+        return -1;
+    const gs::SortPlan p = is_kv ? gs::plan_kv(n, q, a) : gs::plan_f64(n, q, a);
     const gs::F2Tables &T = *p.f2;
     const char *b = T.blob.data();
     const int64_t *lc = (const int64_t *)(b + T.off_leaf_c), *ld = (const int64_t *)(b + T.off_leaf_d);
@@ -268,6 +294,47 @@ int gs_plan_frog2(int64_t n, double buffer_fraction, int is_kv, int64_t *leaves,
     return 0;
 }
 
+int gs_plan_frog3(int64_t n, double buffer_fraction, int is_kv, int64_t *trees, int64_t max_trees, int64_t *spine,
+                  int64_t max_spine, int64_t *leaves, int64_t max_leaves, int64_t *counts)
+{
+    int64_t q = 0;
+    int a = 0;
+    if (n < 2 || n > ((int64_t)1 << 32) || resolve_algo(buffer_fraction, GS_ALGO_FROGSORT3, &a, &q) != GS_OK)
+        return -1;
+    const gs::SortPlan p = is_kv ? gs::plan_kv(n, q, a) : gs::plan_f64(n, q, a);
+    const gs::F3Plan &P = *p.f3;
+    int64_t nl = 0;
+    for (size_t i = 0; i < P.trees.size(); ++i) {
+        const gs::F2Tables &T = *P.trees[i];
+        const char *b = T.blob.data();
+        const int64_t *lc = (const int64_t *)(b + T.off_leaf_c), *ld = (const int64_t *)(b + T.off_leaf_d);
+        if ((int64_t)i < max_trees) {
+            trees[4 * i + 0] = P.root_s[i];
+            trees[4 * i + 1] = P.root_n[i];
+            trees[4 * i + 2] = P.root_c[i];
+            trees[4 * i + 3] = P.root_left[i];
+        }
+        for (int64_t k = 0; k < T.nleaves; ++k, ++nl)
+            if (nl < max_leaves) {
+                leaves[3 * nl + 0] = lc[k];
+                leaves[3 * nl + 1] = ld[k];
+                leaves[3 * nl + 2] = lc[k + 1] - lc[k];
+            }
+    }
+    for (size_t k = 0; k < P.spine.size() && (int64_t)k < max_spine; ++k) {
+        spine[3 * k + 0] = P.spine[k].nl;
+        spine[3 * k + 1] = P.spine[k].r0;
+        spine[3 * k + 2] = P.spine[k].nr;
+    }
+    counts[0] = (int64_t)P.trees.size();
+    counts[1] = (int64_t)P.spine.size();
+    counts[2] = nl;
+    counts[3] = P.total_rounds;
+    counts[4] = p.hlen;
+    counts[5] = P.b;
+    return 0;
+}
+
 gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws, size_t ws_bytes,
                       void *hip_stream, gs_report *rep)
 {
@@ -277,15 +344,22 @@ gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws,
 gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_fraction, void *ws,
                              size_t ws_bytes, void *hip_stream, gs_report *rep)
 {
+    return gs_sort_f64_ex(keys, n, target, buffer_fraction, GS_ALGO_AUTO, ws, ws_bytes, hip_stream, rep);
+}
+
+gs_status gs_sort_f64_ex(double *keys, int64_t n, int target, double buffer_fraction, int algo, void *ws,
+                         size_t ws_bytes, void *hip_stream, gs_report *rep)
+{
     g_detail.clear();
     if (target < GS_ASC_LEFT || target > GS_DESC_RIGHT) return fail(GS_EINVAL, "unknown target %d", target);
     if (n < 0) return fail(GS_EINVAL, "n < 0");
     if (n > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
     int64_t q = 0;
-    gs_status s = check_fraction(buffer_fraction, &q);
+    int a = 0;
+    gs_status s = resolve_algo(buffer_fraction, algo, &a, &q);
     if (s != GS_OK) return s;
     if (n > ((int64_t)1 << 40)) return fail(GS_EINVAL, "n above 2^40");
-    gs::SortPlan p = gs::plan_f64(n, q);
+    gs::SortPlan p = gs::plan_f64(n, q, a);
     if (n > 1) {
         if ((int64_t)ws_bytes < p.bytes || !ws)
             return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);
@@ -297,7 +371,7 @@ gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_
     }
     if ((s = check_device()) != GS_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
-    if (p.f2 && (s = check_not_capturing(st)) != GS_OK) return s;
+    if ((p.f2 || p.f3) && (s = check_not_capturing(st)) != GS_OK) return s;
     Reporter r(rep, st);
     hipError_t e = gs::sort_f64_target_async(keys, n, target, (char *)ws, p, st);
     if (e != hipSuccess) return r.finish(hip_fail(e, "gs_sort_f64 launch"));
@@ -501,15 +575,22 @@ gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fr
 gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction,
                             void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep)
 {
+    return gs_sort_kv_ex(keys, vals, n, target, buffer_fraction, GS_ALGO_AUTO, ws, ws_bytes, hip_stream, rep);
+}
+
+gs_status gs_sort_kv_ex(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction, int algo,
+                        void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep)
+{
     g_detail.clear();
     if (target < GS_ASC_LEFT || target > GS_DESC_RIGHT) return fail(GS_EINVAL, "unknown target %d", target);
     if (n < 0) return fail(GS_EINVAL, "n < 0");
     if (n > 0 && (!keys || !vals)) return fail(GS_EINVAL, "keys or vals is NULL");
     int64_t q = 0;
-    gs_status s = check_fraction(buffer_fraction, &q);
+    int a = 0;
+    gs_status s = resolve_algo(buffer_fraction, algo, &a, &q);
     if (s != GS_OK) return s;
     if (n > ((int64_t)1 << 40)) return fail(GS_EINVAL, "n above 2^40");
-    gs::SortPlan p = gs::plan_kv(n, q);
+    gs::SortPlan p = gs::plan_kv(n, q, a);
     if (n > 1) {
         if ((int64_t)ws_bytes < p.bytes || !ws)
             return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);
@@ -521,7 +602,7 @@ gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int targe
     }
     if ((s = check_device()) != GS_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
-    if (p.f2 && (s = check_not_capturing(st)) != GS_OK) return s;
+    if ((p.f2 || p.f3) && (s = check_not_capturing(st)) != GS_OK) return s;
     Reporter r(rep, st);
     hipError_t e = gs::sort_kv_target_async(keys, vals, n, target, (char *)ws, p, st);
     if (e != hipSuccess) return r.finish(hip_fail(e, "gs_sort_kv launch"));

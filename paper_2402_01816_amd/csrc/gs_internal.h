@@ -61,6 +61,30 @@ struct F2Tables {
     int64_t off_leaf_c, off_leaf_d, off_node_s, off_node_n, off_node_tb, off_node_sb, off_rb, off_rt, off_rs;
 };
 
+// Frogsort3 ("Frogsort3": one buffer of b = floor(q n / 2^16) elements serves
+// the branches in turn).  While b is under half of the m elements left, the
+// last b of them form an inner child, sorted by Frogsort1 as a right node
+// whose region ends at slot m + b (its data land at [m, m + b)); then the rest
+// is the same problem on m - b.  What remains (b covers half of it, or it is a
+// single leaf) is one Frogsort1 tree at slot 0, and the spine merges
+// [0, m - b) with [m, m + b) into [0, m), bottom up.  Every tree is run from
+// F2Tables (q = 2^15 gives the Frogsort1 split); all their tables go up in one
+// image.
+struct F3Plan {
+    int64_t n, q, b, leaf, tile;
+    std::vector<std::shared_ptr<const F2Tables>> trees;   // in running order
+    std::vector<int64_t> root_s, root_n, root_c;           // their roots: region start, size, input offset
+    std::vector<int> root_left;
+    std::vector<int64_t> tree_off;                        // their tables' offsets in `image`
+    std::vector<FrogMerge> spine;                         // bottom up
+    std::vector<char> image;
+    int max_rounds;                                       // deepest tree
+    int total_rounds;                                     // merge rounds of the whole sort
+    int64_t max_tickets, max_splits, max_status;
+};
+
+enum : int { kAlgoFrog1 = 1, kAlgoFrog2 = 2, kAlgoFrog3 = 3 };
+
 // Workspace layout and tree shape of one plain sort.
 struct SortPlan {
     int64_t n;            // keys
@@ -73,7 +97,8 @@ struct SortPlan {
     int64_t off_hvals;    // buffer for values (kv only)
     int64_t off_forest;   // control area of the run
     ForestPlan forest;
-    std::shared_ptr<const F2Tables> f2;   // Frogsort2 tables (q != 0)
+    std::shared_ptr<const F2Tables> f2;   // Frogsort2 tables
+    std::shared_ptr<const F3Plan> f3;     // Frogsort3 schedule
     int64_t bytes;        // total workspace
 };
 
@@ -126,10 +151,11 @@ ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs,
 hipError_t forest_f64_async(double *D, double *H, const Prob *probs, const unsigned *nprob, const ForestPlan &fp,
                             char *fw, hipStream_t st, const unsigned *gate, unsigned run_if, int merge_ipt = 16);
 
-// q = 0: Frogsort1 (buffer floor(n/2)); q in [kF2MinQ, 2^15): Frogsort2.
+// algo kAlgoFrog1: buffer floor(n/2) (q unused).  kAlgoFrog2 / kAlgoFrog3:
+// the buffer fraction is q / 2^16, q in [kF2MinQ, 2^15].
 constexpr int64_t kF2MinQ = 1024;       // p >= 1/64
-SortPlan plan_f64(int64_t n, int64_t q = 0);
-SortPlan plan_kv(int64_t n, int64_t q = 0);
+SortPlan plan_f64(int64_t n, int64_t q = 0, int algo = kAlgoFrog1);
+SortPlan plan_kv(int64_t n, int64_t q = 0, int algo = kAlgoFrog1);
 // gate (may be null): every launch exits at once unless *gate == run_if.
 hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st,
                           const unsigned *gate = nullptr, unsigned run_if = 0u);

@@ -782,7 +782,7 @@ static unsigned grid_for(int64_t items, int threads, int64_t cap)
 template <class KT, class V>
 static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv, Forest F,
                              const ForestPlan &fp, char *fw, hipStream_t st, Gate gate, bool leaves,
-                             const F2Tables *f2 = nullptr)
+                             const F2Tables *f2 = nullptr, char *f2_img = nullptr)
 {
     using C = SortCfg<KT, V>;
     constexpr int TILE = C::MERGE_NT * C::MERGE_IPT;
@@ -797,13 +797,22 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         F.sbase = (const unsigned *)(fw + fp.off_sbase);
         F.stride = fp.stride;
     }
-    const int R = F.use_m1 ? 1 : fp.rounds;
+    // rounds of this run: one explicit merge, the tree's own height (trees
+    // of one plan differ), or the capacity the forest area was laid out for
+    const int R = F.use_m1 ? 1 : f2 ? f2->rounds : fp.rounds;
     if (R > (fp.rounds > 0 ? fp.rounds : 1)) return hipErrorInvalidValue;
     if (f2) {
-        // the tree tables travel with the call (see F2Tables)
-        char *img = fw + fp.off_f2;
-        hipError_t e = hipMemcpyAsync(img, f2->blob.data(), f2->blob.size(), hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return e;
+        // every launch of the tree must fit the area's capacities
+        if ((int)f2->rt.size() != R + 1 || (int)f2->rs.size() != R + 1 || f2->nleaves > fp.max_status ||
+            f2->max_tickets > fp.max_tickets || f2->max_splits > fp.max_splits)
+            return hipErrorInvalidValue;
+        // the tree tables travel with the call (see F2Tables), unless the
+        // caller has already put them at f2_img
+        char *img = f2_img ? f2_img : fw + fp.off_f2;
+        if (!f2_img) {
+            hipError_t e = hipMemcpyAsync(img, f2->blob.data(), f2->blob.size(), hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) return e;
+        }
         F.use_f2 = 1;
         F.f2.leaf_c = (const int64_t *)(img + f2->off_leaf_c);
         F.f2.leaf_d = (const int64_t *)(img + f2->off_leaf_d);
@@ -920,12 +929,15 @@ int64_t f2_put(std::vector<char> &blob, const std::vector<T> &v)
     return off;
 }
 
-std::shared_ptr<const F2Tables> f2_build(int64_t n, int64_t q, int64_t leaf, int64_t tile)
+// Tables of the tree whose root (left or right node) has its region at s0 and
+// its n input elements at [c0, c0 + n).
+std::shared_ptr<const F2Tables> f2_build(int64_t s0, int64_t n, int64_t c0, int left0, int64_t q, int64_t leaf,
+                                         int64_t tile)
 {
     F2Walk W;
     W.q = q;
     W.leaf = leaf;
-    const int H = f2_walk(W, 0, n, 0, 1);
+    const int H = f2_walk(W, s0, n, c0, left0);
     auto T = std::make_shared<F2Tables>();
     T->n = n;
     T->q = q;
@@ -964,7 +976,7 @@ std::shared_ptr<const F2Tables> f2_build(int64_t n, int64_t q, int64_t leaf, int
         if (sp > T->max_splits) T->max_splits = sp;
     }
     std::vector<int64_t> lc = W.leaf_c;
-    lc.push_back(n);
+    lc.push_back(c0 + n);
     T->off_leaf_c = f2_put(T->blob, lc);
     T->off_leaf_d = f2_put(T->blob, W.leaf_d);
     T->off_node_s = f2_put(T->blob, ns);
@@ -998,17 +1010,103 @@ std::shared_ptr<const F2Tables> f2_tables(int64_t n, int64_t q, int64_t leaf, in
             }
         }
     }
-    auto t = f2_build(n, q, leaf, tile);
+    auto t = f2_build(0, n, 0, 1, q, leaf, tile);
     std::lock_guard<std::mutex> g(g_f2_mu);
     g_f2_cache.push_front(t);
     if (g_f2_cache.size() > kF2CacheEntries) g_f2_cache.pop_back();
     return t;
 }
 
+std::shared_ptr<const F3Plan> f3_build(int64_t n, int64_t q, int64_t leaf, int64_t tile)
+{
+    auto P = std::make_shared<F3Plan>();
+    P->n = n;
+    P->q = q;
+    P->leaf = leaf;
+    P->tile = tile;
+    const int64_t b = f2_inner(n, q);
+    P->b = b;
+    std::vector<int64_t> sizes;                 // spine nodes that split
+    int64_t m = n;
+    while (m > leaf && m / 2 > b) {
+        // inner child: the last b elements, a right node whose Frogsort1
+        // region (b + floor(b/2) slots) ends at m + b
+        const int64_t s0 = m + b - f2_region(b, 32768);
+        P->trees.push_back(f2_build(s0, b, m - b, 0, 32768, leaf, tile));
+        P->root_s.push_back(s0);
+        P->root_n.push_back(b);
+        P->root_c.push_back(m - b);
+        P->root_left.push_back(0);
+        sizes.push_back(m);
+        m -= b;
+    }
+    P->trees.push_back(f2_build(0, m, 0, 1, 32768, leaf, tile));
+    P->root_s.push_back(0);
+    P->root_n.push_back(m);
+    P->root_c.push_back(0);
+    P->root_left.push_back(1);
+    for (size_t k = sizes.size(); k-- > 0;) {
+        const int64_t mk = sizes[k];
+        FrogMerge fm;
+        fm.l0 = 0;
+        fm.nl = mk - b;
+        fm.r0 = mk;
+        fm.nr = b;
+        fm.out0 = 0;
+        fm.left = 1;
+        fm.outer = 0;
+        P->spine.push_back(fm);
+    }
+    P->max_rounds = 0;
+    P->total_rounds = (int)P->spine.size();
+    P->max_tickets = P->max_splits = P->max_status = 1;
+    for (const auto &t : P->trees) {
+        const int64_t off = align256((int64_t)P->image.size());
+        P->tree_off.push_back(off);
+        P->image.resize((size_t)(off + (int64_t)t->blob.size()));
+        memcpy(P->image.data() + off, t->blob.data(), t->blob.size());
+        P->max_rounds = t->rounds > P->max_rounds ? t->rounds : P->max_rounds;
+        P->total_rounds += t->rounds;
+        P->max_tickets = t->max_tickets > P->max_tickets ? t->max_tickets : P->max_tickets;
+        P->max_splits = t->max_splits > P->max_splits ? t->max_splits : P->max_splits;
+        P->max_status = t->nleaves > P->max_status ? t->nleaves : P->max_status;
+    }
+    for (const FrogMerge &fm : P->spine) {
+        const int64_t tiles = (fm.nl + fm.nr + tile - 1) / tile;
+        P->max_tickets = tiles > P->max_tickets ? tiles : P->max_tickets;
+        P->max_splits = tiles + 1 > P->max_splits ? tiles + 1 : P->max_splits;
+    }
+    P->max_status = P->max_tickets > P->max_status ? P->max_tickets : P->max_status;
+    return P;
+}
+
+std::list<std::shared_ptr<const F3Plan>> g_f3_cache;     // most recently used first
+
+std::shared_ptr<const F3Plan> f3_plans(int64_t n, int64_t q, int64_t leaf, int64_t tile)
+{
+    {
+        std::lock_guard<std::mutex> g(g_f2_mu);
+        for (auto it = g_f3_cache.begin(); it != g_f3_cache.end(); ++it) {
+            const F3Plan &t = **it;
+            if (t.n == n && t.q == q && t.leaf == leaf && t.tile == tile) {
+                auto hit = *it;
+                g_f3_cache.erase(it);
+                g_f3_cache.push_front(hit);
+                return hit;
+            }
+        }
+    }
+    auto t = f3_build(n, q, leaf, tile);
+    std::lock_guard<std::mutex> g(g_f2_mu);
+    g_f3_cache.push_front(t);
+    if (g_f3_cache.size() > kF2CacheEntries) g_f3_cache.pop_back();
+    return t;
+}
+
 }  // namespace
 
 template <class KT, class V>
-SortPlan make_plan(int64_t n, int64_t q)
+SortPlan make_plan(int64_t n, int64_t q, int algo)
 {
     using K = typename KT::T;
     constexpr bool HV = ValOps<V>::has;
@@ -1016,11 +1114,16 @@ SortPlan make_plan(int64_t n, int64_t q)
     p.n = n;
     p.leaf = leaf_size<KT, V>();
     p.tile = tile_size<KT, V>();
-    p.q = q;
-    if (q != 0 && n > 1) {
+    p.q = algo == kAlgoFrog1 ? 0 : q;
+    if (algo == kAlgoFrog2 && n > 1) {
         p.f2 = f2_tables(n, q, p.leaf, p.tile);
         p.depth = p.f2->rounds;
         p.hlen = f2_inner(n, q);
+    } else if (algo == kAlgoFrog3 && n > 1) {
+        p.f3 = f3_plans(n, q, p.leaf, p.tile);
+        p.depth = p.f3->total_rounds;
+        // b covers half of a spine-less tree, and a single leaf needs none
+        p.hlen = p.f3->b < n / 2 ? p.f3->b : n / 2;
     } else {
         p.depth = n > 1 ? frog_depth(n, p.leaf) : 0;
         p.hlen = n / 2;
@@ -1036,12 +1139,51 @@ SortPlan make_plan(int64_t n, int64_t q)
         p.forest.off_f2 = p.forest.bytes;
         p.forest.f2_bytes = (int64_t)T.blob.size();
         p.forest.bytes += p.forest.f2_bytes;
+    } else if (p.f3) {
+        const F3Plan &P3 = *p.f3;
+        p.forest = layout_forest(0, P3.max_rounds, P3.max_tickets, P3.max_status, P3.max_splits, p.leaf, p.tile);
+        p.forest.off_f2 = p.forest.bytes;
+        p.forest.f2_bytes = align256((int64_t)P3.image.size());
+        p.forest.bytes += p.forest.f2_bytes;
     } else {
         p.forest = forest_plan_one<KT, V>(n);
     }
     p.bytes = p.off_forest + p.forest.bytes;
     if (n <= 1) p.bytes = 0;
     return p;
+}
+
+// Frogsort3: the trees in order (each placing and sorting its part), then the
+// spine merges bottom up, all on the caller's stream.
+template <class KT, class V>
+static hipError_t run_frog3(typename KT::T *keys, V *vals, int64_t n, char *ws, const SortPlan &p,
+                            hipStream_t st, Gate gate)
+{
+    using K = typename KT::T;
+    constexpr bool HV = ValOps<V>::has;
+    const F3Plan &P3 = *p.f3;
+    K *Hk = (K *)(ws + p.off_hkeys);
+    V *Hv = HV ? (V *)(ws + p.off_hvals) : nullptr;
+    char *fw = ws + p.off_forest;
+    char *img = fw + p.forest.off_f2;
+    hipError_t e = hipMemcpyAsync(img, P3.image.data(), P3.image.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i < P3.trees.size(); ++i) {
+        Forest F{};
+        F.p0 = Prob{0, 0, n, 0, 0};
+        e = run_forest<KT, V>(keys, Hk, vals, Hv, F, p.forest, fw, st, gate, true, P3.trees[i].get(),
+                              img + P3.tree_off[i]);
+        if (e != hipSuccess) return e;
+    }
+    for (const FrogMerge &m : P3.spine) {
+        Forest F{};
+        F.p0 = Prob{0, 0, n, 1, 0};
+        F.m1 = m;
+        F.use_m1 = 1;
+        e = run_forest<KT, V>(keys, Hk, vals, Hv, F, p.forest, fw, st, gate, false);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
 }
 
 template <class KT, class V>
@@ -1051,6 +1193,7 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
     using K = typename KT::T;
     constexpr bool HV = ValOps<V>::has;
     if (n <= 1) return hipSuccess;
+    if (p.f3) return run_frog3<KT, V>(keys, vals, n, ws, p, st, gate);
     Forest F{};
     F.p0 = Prob{0, 0, n, p.depth, 0};
     return run_forest<KT, V>(keys, (K *)(ws + p.off_hkeys), vals, HV ? (V *)(ws + p.off_hvals) : nullptr, F,
@@ -1058,8 +1201,8 @@ hipError_t run_sort(typename KT::T *keys, V *vals, int64_t n, char *ws, const So
 }
 
 // explicit instantiations used by the ABI layer
-SortPlan plan_f64(int64_t n, int64_t q) { return make_plan<KeyF64, NoVal>(n, q); }
-SortPlan plan_kv(int64_t n, int64_t q) { return make_plan<KeyU64, uint32_t>(n, q); }
+SortPlan plan_f64(int64_t n, int64_t q, int algo) { return make_plan<KeyF64, NoVal>(n, q, algo); }
+SortPlan plan_kv(int64_t n, int64_t q, int algo) { return make_plan<KeyU64, uint32_t>(n, q, algo); }
 
 ForestPlan plan_forest_f64(int64_t num_keys, int64_t max_len, int64_t max_probs, int merge_ipt)
 {

@@ -210,21 +210,25 @@ def test_frog2_plan_matches_oracle(orc, kv, p):
 
 
 @pytest.mark.parametrize("p", FRACTIONS)
-def test_frog2_workspace(p):
-    """%RAM follows the fraction: the buffer is floor(q n / 65536) elements
-    (never above p n) and the control area and tree tables stay a small
-    fraction of the data."""
+def test_small_buffer_workspace(p):
+    """%RAM follows the fraction for both small-buffer trees: the buffer is at
+    most floor(q n / 65536) elements (never above p n) and the control area
+    and tree tables stay a small fraction of the data; the default below 0.5
+    is Frogsort3."""
     import oracle
     q = oracle.frog2_fraction_q(p)
     for n in [5000, 1 << 20, (1 << 24) + 5]:
         h = (q * n) // 65536
         assert h <= p * n
-        b = g.gs_workspace_bytes_f64(n, p)
-        assert 8 * h <= b <= 8 * h + 0.02 * 8 * n + (1 << 20)
-        bk = g.gs_workspace_bytes_kv(n, p)
-        assert 12 * h <= bk <= 12 * h + 0.02 * 12 * n + (1 << 20)
+        for algo in ("frogsort2", "frogsort3"):
+            b = g.gs_workspace_bytes_f64(n, p, algo)
+            assert 8 * min(h, n // 2) <= b <= 8 * h + 0.02 * 8 * n + (1 << 20)
+            bk = g.gs_workspace_bytes_kv(n, p, algo)
+            assert 12 * min(h, n // 2) <= bk <= 12 * h + 0.02 * 12 * n + (1 << 20)
+    assert g.gs_workspace_bytes_f64(1 << 24, p) == g.gs_workspace_bytes_f64(1 << 24, p, "frogsort3")
     if p <= 0.45:
-        assert g.gs_workspace_bytes_f64(1 << 24, p) < g.gs_workspace_bytes_f64(1 << 24, 0.5)
+        for algo in ("frogsort2", "frogsort3"):
+            assert g.gs_workspace_bytes_f64(1 << 24, p, algo) < g.gs_workspace_bytes_f64(1 << 24, 0.5)
 
 
 def test_frog2_fraction_bounds():
@@ -234,3 +238,32 @@ def test_frog2_fraction_bounds():
     fake = ctypes.c_void_p(0x100000)
     need = g.gs_workspace_bytes_seg(1000, 10)
     assert g.lib.gs_segsort(fake, 1000, fake, 10, 0.25, fake, need, None, None) == g.GS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("kv", [False, True])
+@pytest.mark.parametrize("p", FRACTIONS)
+def test_frog3_plan_matches_oracle(orc, kv, p):
+    """The library's Frogsort3 schedule is the oracle model's: the same
+    Frogsort1 trees (root, size, input offset, side) in running order, the same
+    spine merges bottom up, the same leaves, and the same buffer."""
+    _, leaf = g.plan_depth(1 << 20, kv=kv)
+    q = orc.frog2_fraction_q(p)
+    for n in [2, leaf, leaf + 1, 3 * leaf + 7, 1000003, (1 << 22) + 12345]:
+        trees, spine, leaves, counts = g.plan_frog3(n, p, kv)
+        r = orc.frog3_geometry(n, q, leaf)
+        assert np.array_equal(trees, r["trees"]), n
+        assert np.array_equal(spine, r["spine"]), n
+        assert sorted(map(tuple, leaves.tolist())) == sorted(map(tuple, r["leaves"].tolist()))
+        assert counts[4] == r["nslots"] - n
+        assert counts[4] <= p * n
+
+
+def test_algo_argument_errors():
+    fake = ctypes.c_void_p(0x100000)
+    need = g.gs_workspace_bytes_f64(1000, 0.5)
+    f = g.lib.gs_sort_f64_ex
+    assert f(fake, 1000, 0, 0.5, 7, fake, need, None, None) == g.GS_EINVAL
+    assert f(fake, 1000, 0, 0.25, 1, fake, need, None, None) == g.GS_EINVAL     # Frogsort1 needs 0.5
+    assert f(fake, 1000, 0, 0.01, 3, fake, need, None, None) == g.GS_EUNSUPPORTED
+    assert g.gs_workspace_bytes_f64(1000, 0.25, "frogsort1") == g.SIZE_MAX
+    assert g.gs_workspace_bytes_f64(1 << 20, 0.9, "frogsort3") == g.gs_workspace_bytes_f64(1 << 20, 0.5, "frogsort3")

@@ -70,7 +70,7 @@ def _load():
     lib.oracle_frog_geometry.restype = I64
     lib.oracle_frog2_model.argtypes = [P, I64, I64, I64, I64, P, P, P, P, I64, P, I64, P, I64, P]
     lib.oracle_frog2_model.restype = I64
-    lib.oracle_frog3_model.argtypes = [P, I64, I64, I64, I64, P, P, P, I64, P, I64, P, I64, P, I64, P]
+    lib.oracle_frog3_model.argtypes = [P, I64, I64, I64, I64, I64, P, P, P, I64, P, I64, P, I64, P, I64, P]
     lib.oracle_frog3_model.restype = I64
     lib.oracle_mlp_num_params.argtypes = []
     lib.oracle_mlp_num_params.restype = ctypes.c_int
@@ -281,9 +281,10 @@ def _frog2(keys, n, q, leaf_max, max_snap, gap_shrink):
     return res
 
 
-def frog3_model(keys, q: int, leaf_max: int, gap_shrink: int = 0):
+def frog3_model(keys, q: int, leaf_max: int, gap_shrink: int = 0, q2: int = 32768):
     """Run the instrumented Frogsort3 model (shared buffer floor(q*n/65536),
-    Frogsort1 subtrees with leaves of at most leaf_max elements) in place on
+    sub-trees with leaves of at most leaf_max elements: Frogsort1 for
+    q2 = 32768, Frogsort2 at q2 / 65536 otherwise, i.e. Frogsort6) in place on
     keys; keys None walks the geometry only.
 
     Returns a dict with the sorted keys and their input indices, the leaves
@@ -294,16 +295,16 @@ def frog3_model(keys, q: int, leaf_max: int, gap_shrink: int = 0):
     comparison / move counts, the slot count and the violation bits."""
     lib = _load()
     n = 0 if keys is None else np.asarray(keys).size
-    return _frog3(lib, keys, n, q, leaf_max, gap_shrink)
+    return _frog3(lib, keys, n, q, leaf_max, gap_shrink, q2)
 
 
-def frog3_geometry(n: int, q: int, leaf_max: int):
-    return _frog3(_load(), None, int(n), q, leaf_max, 0)
+def frog3_geometry(n: int, q: int, leaf_max: int, q2: int = 32768):
+    return _frog3(_load(), None, int(n), q, leaf_max, 0, q2)
 
 
-def _frog3(lib, keys, n, q, leaf_max, gap_shrink):
+def _frog3(lib, keys, n, q, leaf_max, gap_shrink, q2):
     counts = np.zeros(7, dtype=np.int64)
-    lib.oracle_frog3_model(None, n, q, leaf_max, gap_shrink, None, None, None, 0, None, 0,
+    lib.oracle_frog3_model(None, n, q, q2, leaf_max, gap_shrink, None, None, None, 0, None, 0,
                            None, 0, None, 0, _ptr(counts))
     sizes = [int(c) for c in counts]
     leaves = np.zeros((max(sizes[2], 1), 3), dtype=np.int64)
@@ -315,14 +316,14 @@ def _frog3(lib, keys, n, q, leaf_max, gap_shrink):
         keys = np.ascontiguousarray(keys, dtype=np.float64)
         out_k = np.zeros(max(n, 1), dtype=np.float64)
         out_l = np.zeros(max(n, 1), dtype=np.int64)
-        ns = lib.oracle_frog3_model(_ptr(keys), n, q, leaf_max, gap_shrink, _ptr(out_k), _ptr(out_l),
+        ns = lib.oracle_frog3_model(_ptr(keys), n, q, q2, leaf_max, gap_shrink, _ptr(out_k), _ptr(out_l),
                                     _ptr(leaves), sizes[2], _ptr(nodes), sizes[3], _ptr(spine), sizes[5],
                                     _ptr(trees), sizes[6], _ptr(counts))
         if ns < 0:
             raise MemoryError("oracle_frog3_model: allocation failed")
         res.update(keys=out_k[:n], labels=out_l[:n])
     else:
-        ns = lib.oracle_frog3_model(None, n, q, leaf_max, gap_shrink, None, None,
+        ns = lib.oracle_frog3_model(None, n, q, q2, leaf_max, gap_shrink, None, None,
                                     _ptr(leaves), sizes[2], _ptr(nodes), sizes[3], _ptr(spine), sizes[5],
                                     _ptr(trees), sizes[6], _ptr(counts))
     res.update(leaves=leaves[: sizes[2]], nodes=nodes[: sizes[3]], spine=spine[: sizes[5]],

@@ -24,8 +24,8 @@
  *     pin the memory layout and the adaptivity counts the paper states.
  *   - oracle_frog2_* : the same for Frogsort2 ("Frogsort2": imbalanced splits,
  *     buffer p), checking on every write that the smaller buffer suffices.
- *   - oracle_frog3_* : the same for Frogsort3 (the buffer shared by the two
- *     branches in turn), with the input placed in place.
+ *   - oracle_frog3_* : the same for Frogsort3 / Frogsort6 (the buffer shared by
+ *     the two branches in turn), with the input placed in place.
  *   - oracle_mlp_*   : an fp64 forward pass, MSE loss, backward pass and Adam
  *     step for the 1-64-64-1 ReLU network used by the learned bucket path
  *     (not part of the paper; parity of the GPU gradients is checked here).
@@ -694,38 +694,44 @@ int64_t oracle_frog2_model(const double *in, int64_t n, int64_t q, int64_t leaf_
 }
 
 /* ------------------------------------------------------------------------ */
-/* instrumented model of Frogsort3 (one buffer shared by the branches)       */
+/* instrumented model of Frogsort3 / Frogsort6 (one buffer shared in turn)   */
 /* ------------------------------------------------------------------------ */
 /*
  * "Frogsort3": instead of splitting the buffer between the two branches, the
  * whole buffer serves one branch after the other, and a branch switches to
- * Frogsort1 once the buffer is at least half its size.  Reading: the input
- * sits in slots [0, n), the buffer is b = floor(q*n/65536) slots [n, n+b).  A
- * node of m elements over slots [0, m + b) with b < floor(m/2) splits into an
- * inner child of b elements (its last b input elements) and an outer child of
- * m - b.  The inner child is sorted first, by Frogsort1 as a right node whose
- * region ends at slot m + b, so its data end at [m, m + b) (its setup moves its
- * chunk there; the space it passes through is free).  The outer child is then
- * the same problem on m - b elements over [0, m), and the node finishes with a
- * left-node merge of [0, m-b) and [m, m+b) into [0, m), written from the top.
- * A node with floor(m/2) <= b is one Frogsort1 tree over [0, m + floor(m/2)),
- * and so is a node of at most leaf_max elements: that tree is a single leaf,
- * sorted where it lies, which needs no buffer at all.
+ * Frogsort1 once the buffer is at least half its size.  "Frogsort6" does the
+ * same but switches to Frogsort2 (inner fraction p2) once that fits; Frogsort1,
+ * 2 and 3 are its special cases.  Reading: the input sits in slots [0, n), the
+ * buffer is b = floor(q*n/65536) slots [n, n+b), and the sub-trees are
+ * Frogsort2 trees with inner child floor(q2*m/65536) (q2 = 32768: Frogsort1,
+ * i.e. Frogsort3).  A node of m elements over slots [0, m + b) whose sub-tree
+ * would need more than b (floor(q2*m/65536) > b) splits into an inner child of
+ * b elements (its last b input elements) and an outer child of m - b.  The
+ * inner child is sorted first, by a sub-tree whose root is a right node with
+ * its region ending at slot m + b, so its data end at [m, m + b) (its setup
+ * moves its chunk there; the space it passes through is free).  The outer
+ * child is then the same problem on m - b elements over [0, m), and the node
+ * finishes with a left-node merge of [0, m-b) and [m, m+b) into [0, m),
+ * written from the top.  A node whose sub-tree fits the buffer is one sub-tree
+ * over [0, m + floor(q2*m/65536)), and so is a node of at most leaf_max
+ * elements: that tree is a single leaf, sorted where it lies, which needs no
+ * buffer at all.
  *
  * Every placement and merge write is checked as in the Frogsort2 model (bit 0
- * of `bad`; bit 1: an empty buffer where the node still has to split).  gap_shrink > 0 ends every inner child that many slots early, so
- * a test can see the check fire.
+ * of `bad`; bit 1: an empty buffer where the node still has to split).
+ * gap_shrink > 0 ends every inner child that many slots early, so a test can
+ * see the check fire.
  */
-static int64_t f3_r1(int64_t m) { return m + m / 2; }
+static int64_t f3_r1(const frog2_model *M, int64_t m) { return m + f2_inner(M, m); }
 
-/* In-place setup of a Frogsort1 subtree over [s, s + f3_r1(n)) whose input
-   sits at [c, c + n): leaves from right to left, each chunk moved from its
-   top element down (every destination is at or after its source), then
-   sorted in place. */
+/* In-place setup of a sub-tree over [s, s + f3_r1(n)) whose input sits at
+   [c, c + n): leaves from right to left, each chunk moved from its top
+   element down (every destination is at or after its source), then sorted
+   in place. */
 static void f3_place(frog2_model *M, int64_t s, int64_t n, int64_t c, int left)
 {
     if (n <= M->leaf_max) {
-        int64_t d = left ? s : s + f3_r1(n) - n;
+        int64_t d = left ? s : s + f3_r1(M, n) - n;
         if (M->nleaves < M->max_leaves) {
             M->leaves[3 * M->nleaves + 0] = c;
             M->leaves[3 * M->nleaves + 1] = d;
@@ -749,15 +755,17 @@ static void f3_place(frog2_model *M, int64_t s, int64_t n, int64_t c, int left)
         }
         return;
     }
-    int64_t nl = left ? (n + 1) / 2 : n / 2, nr = n - nl;
-    f3_place(M, s + f3_r1(n) - f3_r1(nr), nr, c + nl, 0);
+    int64_t ni = f2_inner(M, n);
+    if (ni < 1) { M->bad |= 2; return; }
+    int64_t nl = left ? n - ni : ni, nr = n - nl;
+    f3_place(M, s + f3_r1(M, n) - f3_r1(M, nr), nr, c + nl, 0);
     f3_place(M, s, nl, c, 1);
 }
 
 /* The spine: a node of m elements over [0, m + b).  spine[] receives
    {outer elements, inner start, inner elements} of every spine merge, bottom
    up; tree[] {region start, elements, input offset, is_left} of every
-   Frogsort1 tree in the order they run. */
+   sub-tree in the order they run. */
 typedef struct {
     int64_t *spine, max_spine, nspine;
     int64_t *tree, max_tree, ntree;
@@ -779,10 +787,10 @@ static void f3_tree(frog2_model *M, frog3_sched *S, int64_t s, int64_t n, int64_
 
 static void f3_node(frog2_model *M, frog3_sched *S, int64_t m, int64_t b)
 {
-    if (m / 2 <= b || m <= M->leaf_max) { f3_tree(M, S, 0, m, 0, 1); return; }
+    if (f2_inner(M, m) <= b || m <= M->leaf_max) { f3_tree(M, S, 0, m, 0, 1); return; }
     if (b < 1) { M->bad |= 2; return; }              /* no buffer to share */
     int64_t end = m + b - S->shrink;                 /* the inner child's region end */
-    f3_tree(M, S, end - f3_r1(b), b, m - b, 0);
+    f3_tree(M, S, end - f3_r1(M, b), b, m - b, 0);
     f3_node(M, S, m - b, b);
     int64_t nl = m - b, nr = b, Lb = 0, Rb = end - b;
     int64_t i = nl - 1, j = nr - 1, w = m - 1;
@@ -801,13 +809,14 @@ static void f3_node(frog2_model *M, frog3_sched *S, int64_t m, int64_t b)
 }
 
 /*
- * Run the model on in[0, n) (in == NULL: geometry only).  Outputs as for
- * oracle_frog2_model, plus the spine merges and the Frogsort1 trees.
+ * Run the model on in[0, n) (in == NULL: geometry only); q2 = 32768 is
+ * Frogsort3.  Outputs as for oracle_frog2_model, plus the spine merges and the
+ * sub-trees.
  *   counts: {comparisons, moves, leaves, nodes, bad, spine merges, trees}
- * Returns the number of slots n + floor(q*n/65536), or -1 on allocation
- * failure.
+ * Returns the number of slots, n + min(b, the whole tree's buffer), or -1 on
+ * allocation failure.
  */
-int64_t oracle_frog3_model(const double *in, int64_t n, int64_t q, int64_t leaf_max, int64_t gap_shrink,
+int64_t oracle_frog3_model(const double *in, int64_t n, int64_t q, int64_t q2, int64_t leaf_max, int64_t gap_shrink,
                            double *out_key, int64_t *out_label,
                            int64_t *leaves, int64_t max_leaves, int64_t *nodes, int64_t max_nodes,
                            int64_t *spine, int64_t max_spine, int64_t *tree, int64_t max_tree,
@@ -820,14 +829,14 @@ int64_t oracle_frog3_model(const double *in, int64_t n, int64_t q, int64_t leaf_
     for (int i = 0; i < 7; i++) counts[i] = 0;
     if (n <= 0) return 0;
     int64_t b = n * q / 65536;
-    M.q = 32768;                                     /* the Frogsort1 subtrees */
+    M.q = q2;                                        /* the sub-trees' split */
     M.leaf_max = leaf_max < 1 ? 1 : leaf_max;
     M.leaves = leaves; M.max_leaves = leaves ? max_leaves : 0;
     M.nodes = nodes;   M.max_nodes = nodes ? max_nodes : 0;
     S.spine = spine;   S.max_spine = spine ? max_spine : 0;
     S.tree = tree;     S.max_tree = tree ? max_tree : 0;
     S.shrink = gap_shrink;
-    M.nslots = n + (n / 2 <= b ? n / 2 : b);
+    M.nslots = n + (f2_inner(&M, n) <= b ? f2_inner(&M, n) : b);
     if (in) {
         M.key = (double *)calloc((size_t)M.nslots, sizeof(double));
         M.lab = (int64_t *)malloc((size_t)M.nslots * sizeof(int64_t));

@@ -480,6 +480,49 @@ def test_frog3_presorted_counts(orc, q):
     assert r["compares"] == r["moves"] == inner
 
 
+@pytest.mark.parametrize("q2", [6553, 16384, 21845])
+@pytest.mark.parametrize("n", [100, 1000, 4097])
+def test_frog6_with_enough_buffer_is_frogsort2(orc, q2, n):
+    """"Frogsorts 1, 2, 3 are special cases of Frogsort6": when the shared
+    buffer already covers the whole tree's Frogsort2 buffer (p3 >= p2), the
+    sort is one Frogsort2 tree at p2, merge for merge."""
+    rng = np.random.default_rng(q2 + n)
+    x = rng.integers(0, max(2, n // 4), size=n).astype(np.float64)
+    leaf = 65536 // q2 + 1
+    a = orc.frog3_model(x, q2, leaf, q2=q2)
+    b = orc.frog2_model(x, q2, leaf)
+    assert a["bad"] == 0 and a["spine"].shape[0] == 0 and a["trees"].shape[0] == 1
+    assert a["nslots"] == b["nslots"] == n + (q2 * n) // 65536
+    assert (a["compares"], a["moves"]) == (b["compares"], b["moves"])
+    assert np.array_equal(a["labels"], b["labels"])
+
+
+@pytest.mark.parametrize("q", [1024, 3277, 6553, 13107])
+@pytest.mark.parametrize("q2", [6553, 16384, 32767])
+def test_frog6_sorts_stably_within_its_buffer(orc, q, q2):
+    """Frogsort6 (shared buffer b = floor(q n / 65536), Frogsort2 sub-trees
+    at q2) reaches the definition with no write on an unread element, in at
+    most n + b slots; the spine runs while a sub-tree would need more than b."""
+    rng = np.random.default_rng(q * 3 + q2)
+    leaf = 65536 // min(q, q2) + 1
+    for n in [leaf + 1, 300, 1000, 4097, 20000]:
+        b = (q * n) // 65536
+        x = rng.integers(0, max(2, n // 5), size=n).astype(np.float64)
+        x[rng.random(n) < 0.1] = -0.0
+        r = orc.frog3_model(x, q, leaf, q2=q2)
+        assert r["bad"] == 0, (q, q2, n)
+        assert r["nslots"] <= n + b
+        p = _stable_order(x)
+        assert np.array_equal(r["labels"], p)
+        m, K = n, 0
+        while m > leaf and (q2 * m) // 65536 > b:
+            m -= b
+            K += 1
+        assert r["spine"].shape[0] == K
+        if K and b >= 2:       # one slot short: the first spine write lands on the inner run
+            assert orc.frog3_model(x, q, leaf, q2=q2, gap_shrink=1)["bad"] & 1
+
+
 # --------------------------------------------------------------------------
 # network reference: forward closed forms, finite differences, Adam
 # --------------------------------------------------------------------------

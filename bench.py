@@ -236,31 +236,33 @@ def extras(gs, torch, W, log2n, dev):
         kv[pat] = {"n": nk, "ms": round(ms, 3), "gkeys_per_s": round(nk / (ms * 1e-3) / 1e9, 3)}
         del K, V, Kb, Vb
     res["key_value"] = kv
-    # Frogsort2: smaller buffer fractions on the headline input; %RAM is
-    # 1 + workspace / data and tFootprint = %RAM x runTime ("Sustainability
-    # measures")
+    # smaller buffers on the headline input (Frogsort3, the default below
+    # 0.5, and Frogsort2); %RAM is 1 + workspace / data and tFootprint =
+    # %RAM x runTime ("Sustainability measures")
     x = torch.from_numpy(W.f64_pattern("uniform", n, seed=0)).to(dev)
     buf = torch.empty_like(x)
-    f2 = {}
-    for p in (0.5, 0.45, 0.25, 0.1):
-        log(f"extras: buffer_fraction {p}")
-        need = gs.gs_workspace_bytes_f64(n, p)
-        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
-        ws = ws[(-ws.data_ptr()) % 256:][:need]
+    small = {}
+    for algo, fracs in (("frogsort1", (0.5,)), ("frogsort3", (0.45, 0.25, 0.1, 1 / 64)),
+                        ("frogsort2", (0.25, 0.1))):
+        for p in fracs:
+            log(f"extras: {algo} buffer_fraction {p}")
+            need = gs.gs_workspace_bytes_f64(n, p, algo)
+            ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+            ws = ws[(-ws.data_ptr()) % 256:][:need]
 
-        def fn_f2(i, timed, p=p, ws=ws):
-            if timed is None:
-                buf.copy_(x)
-            else:
-                gs.gs_sort_f64(buf, buffer_fraction=p, workspace=ws)
-        gs.gs_sort_f64(buf.copy_(x), buffer_fraction=p, workspace=ws)
-        ms = _time_calls(torch, stream, fn_f2, 3)
-        ram = 1.0 + need / (8.0 * n)
-        f2[str(p)] = {"ms": round(ms, 3), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
-                      "ram_fraction": round(ram, 4), "t_footprint_ms": round(ram * ms, 3)}
-        del ws
+            def fn_small(i, timed, p=p, ws=ws, algo=algo):
+                if timed is None:
+                    buf.copy_(x)
+                else:
+                    gs.gs_sort_f64(buf, buffer_fraction=p, workspace=ws, algo=algo)
+            gs.gs_sort_f64(buf.copy_(x), buffer_fraction=p, workspace=ws, algo=algo)
+            ms = _time_calls(torch, stream, fn_small, 3)
+            ram = 1.0 + need / (8.0 * n)
+            small[f"{algo}_p{p:.4g}"] = {"ms": round(ms, 3), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
+                                         "ram_fraction": round(ram, 4), "t_footprint_ms": round(ram * ms, 3)}
+            del ws
     del x, buf
-    res["buffer_fraction"] = f2
+    res["buffer_fraction"] = small
     return res
 
 
@@ -275,7 +277,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the learned / segmented / key-value side measurements")
+    ap.add_argument("--buffer-fraction", type=float, default=0.5,
+                    help="time this buffer fraction instead (below 0.5: Frogsort3 unless --algo)")
+    ap.add_argument("--algo", default="auto", choices=["auto", "frogsort1", "frogsort2", "frogsort3"])
     args = ap.parse_args()
+    frac, algo = args.buffer_fraction, args.algo
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -298,7 +304,7 @@ def main():
     x = W.f64_pattern(args.pattern, n, seed=0)
     pristine = torch.from_numpy(x).to(dev)
     del x
-    need = gs.gs_workspace_bytes_f64(n)
+    need = gs.gs_workspace_bytes_f64(n, frac, algo)
     ws_raw = torch.empty(need + 256, dtype=torch.uint8, device=dev)
     off = (-ws_raw.data_ptr()) % 256
     ws = ws_raw[off: off + need]
@@ -308,12 +314,12 @@ def main():
     buf = torch.empty_like(pristine)
     for _ in range(args.warmup):
         buf.copy_(pristine)
-        gs.gs_sort_f64(buf, workspace=ws)
+        gs.gs_sort_f64(buf, frac, workspace=ws, algo=algo)
     torch.cuda.synchronize()
     rep = None
     if args.warmup > 0:
         buf.copy_(pristine)
-        rep = gs.gs_sort_f64(buf, workspace=ws, report=True)
+        rep = gs.gs_sort_f64(buf, frac, workspace=ws, report=True, algo=algo)
     del buf
 
     # empirical ceiling: a device-to-device copy moves the same 16n bytes as
@@ -347,7 +353,7 @@ def main():
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for c in copies:
-        gs.gs_sort_f64(c, workspace=ws)
+        gs.gs_sort_f64(c, frac, workspace=ws, algo=algo)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -371,12 +377,21 @@ def main():
     merge_ms = per_kind.get("merge", [])
     levels = len(merge_ms) // max(args.steps, 1)
     merge_avg = sum(merge_ms) / max(len(merge_ms), 1)
-    merge_bytes = 16.0 * n                          # every key read once and written once
+    default = frac >= 0.5 and algo in ("auto", "frogsort1")
+    if default:
+        merge_bytes = 16.0 * n                      # every key read once and written once
+        merged = n * levels
+    else:
+        # launches differ in size: the plan's merged elements over all rounds
+        # give the average bytes per launch
+        cnt = gs.plan_frog2(n, frac)[2] if algo == "frogsort2" else gs.plan_frog3(n, frac)[3]
+        merged = cnt[6]
+        merge_bytes = 16.0 * merged / max(levels, 1)
     achieved = merge_bytes / (merge_avg * 1e-3) / 1e9 if merge_avg > 0 else 0.0
     ram = 1.0 + need / (8.0 * n)
-    traffic = merge_traffic() if (n == 1 << 28 and args.pattern == "uniform") else None
+    traffic = merge_traffic() if (n == 1 << 28 and args.pattern == "uniform" and default) else None
     value = n / (ms_per_step * 1e-3) / 1e9
-    passes = 1 + levels
+    passes = 1 + merged / n
     whole_bytes = 16.0 * n * passes
 
     out = {
@@ -393,8 +408,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"plain stable f64 sort, n=2^{args.log2n}, {args.pattern} keys "
-                               f"(seed 0), buffer_fraction 0.5",
-                   "n": n, "pattern": args.pattern, "buffer_fraction": 0.5,
+                               f"(seed 0), buffer_fraction {frac:g}" + ("" if default else f", {algo}"),
+                   "n": n, "pattern": args.pattern, "buffer_fraction": frac, "algo": algo,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -405,7 +420,7 @@ def main():
         "ram_fraction": round(ram, 5),
         "t_footprint_ram_s": round(ram * ms_per_step * 1e-3, 6),
         "whole_sort_hbm_frac": round(whole_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "passes": passes,
+        "passes": round(passes, 3),
         "per_kernel_ms_per_step": {k: round(sum(v) / args.steps, 4) for k, v in per_kind.items()},
         "wall_s": round(wall, 3),
         "report": rep,

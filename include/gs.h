@@ -124,19 +124,29 @@ gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_
 gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction,
                             void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 
-/* The same with the tree named ("Frogsort1", "Frogsort2", "Frogsort3").
-   GS_ALGO_AUTO is what the calls above run: Frogsort1 for p >= 0.5, Frogsort3
-   below.  GS_ALGO_FROGSORT1 with p < 0.5 -> GS_EINVAL; Frogsort2 / Frogsort3
-   with p >= 0.5 run their own tree at p = 0.5 (Frogsort3 is then one Frogsort1
-   tree).  The workspace depends on the tree: size it with the _ex queries.
-   rep->levels counts every merge round of the call. */
-typedef enum { GS_ALGO_AUTO = 0, GS_ALGO_FROGSORT1 = 1, GS_ALGO_FROGSORT2 = 2, GS_ALGO_FROGSORT3 = 3 } gs_algo;
-size_t gs_workspace_bytes_f64_ex(int64_t n, double buffer_fraction, int algo);
-size_t gs_workspace_bytes_kv_ex(int64_t n, double buffer_fraction, int algo);
+/* The same with the tree named ("Frogsort1", "Frogsort2", "Frogsort3",
+   "Frogsort6").  GS_ALGO_AUTO is what the calls above run: Frogsort1 for
+   p >= 0.5, Frogsort3 below.  GS_ALGO_FROGSORT1 with p < 0.5 -> GS_EINVAL;
+   the others with p >= 0.5 run their own tree at p = 0.5 (Frogsort3 is then
+   one Frogsort1 tree).  Frogsort6 shares the buffer like Frogsort3 but its
+   sub-trees are Frogsort2 trees at sub_fraction (rounded down to a multiple
+   of 1/65536; >= 0.5 is Frogsort3, <= buffer_fraction a single Frogsort2
+   tree); sub_fraction is ignored by the other trees.  The workspace depends
+   on the tree: size it with the _ex queries.  rep->levels counts every merge
+   round of the call. */
+typedef enum {
+    GS_ALGO_AUTO = 0,
+    GS_ALGO_FROGSORT1 = 1,
+    GS_ALGO_FROGSORT2 = 2,
+    GS_ALGO_FROGSORT3 = 3,
+    GS_ALGO_FROGSORT6 = 4
+} gs_algo;
+size_t gs_workspace_bytes_f64_ex(int64_t n, double buffer_fraction, int algo, double sub_fraction);
+size_t gs_workspace_bytes_kv_ex(int64_t n, double buffer_fraction, int algo, double sub_fraction);
 gs_status gs_sort_f64_ex(double *keys, int64_t n, int target, double buffer_fraction, int algo,
-                         void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+                         double sub_fraction, void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 gs_status gs_sort_kv_ex(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction, int algo,
-                        void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+                        double sub_fraction, void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 
 /* Sort every segment keys[offsets[i], offsets[i+1]) on its own, for
    i in [0, num_segments); `offsets` holds num_segments+1 int64 values (device).
@@ -242,17 +252,20 @@ int gs_plan_depth(int64_t n, int is_kv, int64_t *leaf_max);
 void gs_plan_node(int64_t n, int depth, int64_t idx, int64_t *out);
 /* The Frogsort2 tree for n keys at buffer_fraction (is_kv: the key/value leaf
    size): leaves[3*i..] = input offset, data start, length (input order);
-   nodes[4*j..] = region start, elements, is_left, merge round; counts[0..5] =
+   nodes[4*j..] = region start, elements, is_left, merge round; counts[0..6] =
    leaves, nodes, rounds, buffer elements, tiles and splits of the largest
-   round.  Arrays are filled up to their capacities.  -1 on bad arguments. */
+   round, elements merged over all rounds.  Arrays are filled up to their
+   capacities.  -1 on bad arguments. */
 int gs_plan_frog2(int64_t n, double buffer_fraction, int is_kv, int64_t *leaves, int64_t max_leaves,
                   int64_t *nodes, int64_t max_nodes, int64_t *counts);
-/* The Frogsort3 schedule: trees[4*i..] = root region start, elements, input
-   offset, is_left (running order); spine[3*k..] = outer elements, inner start,
-   inner elements (bottom up); leaves[3*i..] of every tree; counts[0..5] =
-   trees, spine merges, leaves, merge rounds, buffer elements, b. */
-int gs_plan_frog3(int64_t n, double buffer_fraction, int is_kv, int64_t *trees, int64_t max_trees, int64_t *spine,
-                  int64_t max_spine, int64_t *leaves, int64_t max_leaves, int64_t *counts);
+/* The Frogsort6 schedule (sub_fraction 0.5: Frogsort3): trees[4*i..] = root
+   region start, elements, input offset, is_left (running order);
+   spine[3*k..] = outer elements, inner start, inner elements (bottom up);
+   leaves[3*i..] of every tree; counts[0..6] = trees, spine merges, leaves,
+   merge rounds, buffer elements, b, elements merged over all rounds. */
+int gs_plan_frog3(int64_t n, double buffer_fraction, double sub_fraction, int is_kv, int64_t *trees,
+                  int64_t max_trees, int64_t *spine, int64_t max_spine, int64_t *leaves, int64_t max_leaves,
+                  int64_t *counts);
 
 #ifdef __cplusplus
 }

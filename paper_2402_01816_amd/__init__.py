@@ -113,14 +113,14 @@ _SIGS = {
     "gs_plan_node": ([_I64, ctypes.c_int, _I64, ctypes.POINTER(_I64)], None),
     "gs_plan_frog2": ([_I64, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64, ctypes.c_void_p, _I64,
                        ctypes.c_void_p], ctypes.c_int),
-    "gs_plan_frog3": ([_I64, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64, ctypes.c_void_p, _I64,
-                       ctypes.c_void_p, _I64, ctypes.c_void_p], ctypes.c_int),
-    "gs_workspace_bytes_f64_ex": ([_I64, _D, ctypes.c_int], _SZ),
-    "gs_workspace_bytes_kv_ex": ([_I64, _D, ctypes.c_int], _SZ),
-    "gs_sort_f64_ex": ([_P, _I64, ctypes.c_int, _D, ctypes.c_int, _P, _SZ, _P, ctypes.POINTER(GsReport)],
+    "gs_plan_frog3": ([_I64, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64,
+                       ctypes.c_void_p, _I64, ctypes.c_void_p, _I64, ctypes.c_void_p], ctypes.c_int),
+    "gs_workspace_bytes_f64_ex": ([_I64, _D, ctypes.c_int, _D], _SZ),
+    "gs_workspace_bytes_kv_ex": ([_I64, _D, ctypes.c_int, _D], _SZ),
+    "gs_sort_f64_ex": ([_P, _I64, ctypes.c_int, _D, ctypes.c_int, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)],
                        ctypes.c_int),
-    "gs_sort_kv_ex": ([_P, _P, _I64, ctypes.c_int, _D, ctypes.c_int, _P, _SZ, _P, ctypes.POINTER(GsReport)],
-                      ctypes.c_int),
+    "gs_sort_kv_ex": ([_P, _P, _I64, ctypes.c_int, _D, ctypes.c_int, _D, _P, _SZ, _P,
+                       ctypes.POINTER(GsReport)], ctypes.c_int),
 }
 _OPTIONAL = {
     "gs_workspace_bytes_seg": ([_I64, _I64, _D], _SZ),
@@ -170,7 +170,7 @@ def _check(status: int, where: str):
 # ---------------------------------------------------------------------------
 # workspace queries
 # ---------------------------------------------------------------------------
-ALGOS = {"auto": 0, "frogsort1": 1, "frogsort2": 2, "frogsort3": 3}
+ALGOS = {"auto": 0, "frogsort1": 1, "frogsort2": 2, "frogsort3": 3, "frogsort6": 4}
 
 
 def _algo(algo) -> int:
@@ -179,12 +179,12 @@ def _algo(algo) -> int:
     return int(algo)
 
 
-def gs_workspace_bytes_f64(n: int, buffer_fraction: float = 0.5, algo="auto") -> int:
-    return int(_lib.gs_workspace_bytes_f64_ex(n, buffer_fraction, _algo(algo)))
+def gs_workspace_bytes_f64(n: int, buffer_fraction: float = 0.5, algo="auto", sub_fraction: float = 0.5) -> int:
+    return int(_lib.gs_workspace_bytes_f64_ex(n, buffer_fraction, _algo(algo), sub_fraction))
 
 
-def gs_workspace_bytes_kv(n: int, buffer_fraction: float = 0.5, algo="auto") -> int:
-    return int(_lib.gs_workspace_bytes_kv_ex(n, buffer_fraction, _algo(algo)))
+def gs_workspace_bytes_kv(n: int, buffer_fraction: float = 0.5, algo="auto", sub_fraction: float = 0.5) -> int:
+    return int(_lib.gs_workspace_bytes_kv_ex(n, buffer_fraction, _algo(algo), sub_fraction))
 
 
 def gs_workspace_bytes_seg(num_keys: int, num_segments: int, buffer_fraction: float = 0.5) -> int:
@@ -218,9 +218,10 @@ def plan_frog2(n: int, buffer_fraction: float, kv: bool = False):
     """The library's Frogsort2 plan for n keys (host only): leaves as rows
     (input offset, data start, length) in input order, merge nodes as rows
     (region start, n, is_left, round), and the counts
-    (leaves, nodes, rounds, buffer elements, largest round's tiles, splits)."""
+    (leaves, nodes, rounds, buffer elements, largest round's tiles, splits,
+    elements merged)."""
     import numpy as np
-    counts = np.zeros(6, dtype=np.int64)
+    counts = np.zeros(7, dtype=np.int64)
     if _lib.gs_plan_frog2(n, buffer_fraction, 1 if kv else 0, None, 0, None, 0, counts.ctypes.data) != 0:
         raise ValueError("no Frogsort2 plan for these arguments")
     leaves = np.zeros((int(counts[0]), 3), dtype=np.int64)
@@ -230,21 +231,23 @@ def plan_frog2(n: int, buffer_fraction: float, kv: bool = False):
     return leaves, nodes[: int(counts[1])], tuple(int(c) for c in counts)
 
 
-def plan_frog3(n: int, buffer_fraction: float, kv: bool = False):
-    """The library's Frogsort3 schedule for n keys (host only): trees as rows
+def plan_frog3(n: int, buffer_fraction: float, kv: bool = False, sub_fraction: float = 0.5):
+    """The library's Frogsort3 schedule for n keys (Frogsort6 with
+    sub_fraction < 0.5; host only): trees as rows
     (root region start, elements, input offset, is_left) in running order,
     spine merges as rows (outer elements, inner start, inner elements) bottom
     up, every tree's leaves (input offset, data start, length), and the counts
-    (trees, spine merges, leaves, merge rounds, buffer elements, b)."""
+    (trees, spine merges, leaves, merge rounds, buffer elements, b, elements
+    merged)."""
     import numpy as np
-    counts = np.zeros(6, dtype=np.int64)
-    if _lib.gs_plan_frog3(n, buffer_fraction, 1 if kv else 0, None, 0, None, 0, None, 0,
+    counts = np.zeros(7, dtype=np.int64)
+    if _lib.gs_plan_frog3(n, buffer_fraction, sub_fraction, 1 if kv else 0, None, 0, None, 0, None, 0,
                           counts.ctypes.data) != 0:
         raise ValueError("no Frogsort3 plan for these arguments")
     trees = np.zeros((int(counts[0]), 4), dtype=np.int64)
     spine = np.zeros((max(int(counts[1]), 1), 3), dtype=np.int64)
     leaves = np.zeros((int(counts[2]), 3), dtype=np.int64)
-    _lib.gs_plan_frog3(n, buffer_fraction, 1 if kv else 0, trees.ctypes.data, trees.shape[0],
+    _lib.gs_plan_frog3(n, buffer_fraction, sub_fraction, 1 if kv else 0, trees.ctypes.data, trees.shape[0],
                        spine.ctypes.data, int(counts[1]), leaves.ctypes.data, leaves.shape[0],
                        counts.ctypes.data)
     return trees, spine[: int(counts[1])], leaves, tuple(int(c) for c in counts)
@@ -305,19 +308,20 @@ def _target(target) -> int:
 
 
 def gs_sort_f64(keys, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False,
-                target="AscLeft", algo="auto"):
+                target="AscLeft", algo="auto", sub_fraction: float = 0.5):
     """Stable in-place sort of a contiguous float64 device tensor; target one
     of AscLeft (default), AscRight, DescLeft, DescRight; algo one of auto,
-    frogsort1, frogsort2, frogsort3."""
+    frogsort1, frogsort2, frogsort3, frogsort6 (sub_fraction: Frogsort6's
+    sub-tree fraction)."""
     torch = _torch()
     kp = _dev_ptr(keys, "keys", (torch.float64,))
     n = keys.numel()
-    need = gs_workspace_bytes_f64(n, buffer_fraction, algo)
+    need = gs_workspace_bytes_f64(n, buffer_fraction, algo, sub_fraction)
     if need == SIZE_MAX:
         need = 0
     ws, wsb = _workspace(need, keys.device, workspace)
     r = _rep(report)
-    st = _lib.gs_sort_f64_ex(kp, n, _target(target), buffer_fraction, _algo(algo),
+    st = _lib.gs_sort_f64_ex(kp, n, _target(target), buffer_fraction, _algo(algo), sub_fraction,
                              ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
                              _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_sort_f64")
@@ -325,7 +329,7 @@ def gs_sort_f64(keys, buffer_fraction: float = 0.5, workspace=None, stream=None,
 
 
 def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False,
-               target="AscLeft", algo="auto"):
+               target="AscLeft", algo="auto", sub_fraction: float = 0.5):
     """Stable in-place sort of 64-bit keys (int64 or uint64 storage, compared
     as unsigned) carrying 32-bit values (int32 or uint32 storage); target as
     for gs_sort_f64."""
@@ -337,12 +341,12 @@ def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=
     if keys.numel() != vals.numel():
         raise ValueError("keys and vals differ in length")
     n = keys.numel()
-    need = gs_workspace_bytes_kv(n, buffer_fraction, algo)
+    need = gs_workspace_bytes_kv(n, buffer_fraction, algo, sub_fraction)
     if need == SIZE_MAX:
         need = 0
     ws, wsb = _workspace(need, keys.device, workspace)
     r = _rep(report)
-    st = _lib.gs_sort_kv_ex(kp, vp, n, _target(target), buffer_fraction, _algo(algo),
+    st = _lib.gs_sort_kv_ex(kp, vp, n, _target(target), buffer_fraction, _algo(algo), sub_fraction,
                             ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
                             _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_sort_kv")

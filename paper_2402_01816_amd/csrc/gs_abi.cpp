@@ -53,35 +53,46 @@ gs_status check_device()
 // Which tree a call runs.  buffer_fraction >= 0.5 with GS_ALGO_AUTO (or
 // GS_ALGO_FROGSORT1): Frogsort1, buffer floor(n/2).  Below 0.5 the fraction is
 // rounded down to q / 2^16 (so the buffer never exceeds it) and AUTO runs
-// Frogsort3, the faster of the two small-buffer trees on this device;
-// Frogsort2 / Frogsort3 can be asked for by name (at a fraction >= 0.5 they
-// run with q = 2^15).  Below 1/64 both grow too deep to be worth running.
+// Frogsort3, the faster of the small-buffer trees on this device; Frogsort2,
+// Frogsort3 and Frogsort6 can be asked for by name (at a fraction >= 0.5 they
+// run with q = 2^15).  Frogsort6's sub-tree fraction is rounded the same way
+// into q2 (2^15 at >= 0.5: Frogsort3).  Below 1/64 the trees grow too deep to
+// be worth running.
 constexpr int kAutoSmallBuffer = gs::kAlgoFrog3;
 
-gs_status resolve_algo(double f, int algo, int *out, int64_t *q)
+gs_status fraction_q(double f, const char *what, int64_t *q)
+{
+    if (!(f > 0.0)) return fail(GS_EINVAL, "%s must be > 0 (got %g)", what, f);
+    const int64_t v = f >= 0.5 ? 32768 : (int64_t)floor(f * 65536.0);
+    if (v < gs::kF2MinQ) return fail(GS_EUNSUPPORTED, "%s %g is below the smallest supported, 1/64", what, f);
+    *q = v;
+    return GS_OK;
+}
+
+gs_status resolve_algo(double f, int algo, double sub, int *out, int64_t *q, int64_t *q2)
 {
     *q = 0;
+    *q2 = 32768;
     *out = gs::kAlgoFrog1;
-    if (algo < GS_ALGO_AUTO || algo > GS_ALGO_FROGSORT3) return fail(GS_EINVAL, "unknown algorithm %d", algo);
+    if (algo < GS_ALGO_AUTO || algo > GS_ALGO_FROGSORT6) return fail(GS_EINVAL, "unknown algorithm %d", algo);
     if (!(f > 0.0)) return fail(GS_EINVAL, "buffer_fraction must be > 0 (got %g)", f);
     if (algo == GS_ALGO_FROGSORT1 || (algo == GS_ALGO_AUTO && f >= 0.5)) {
         if (f < 0.5) return fail(GS_EINVAL, "Frogsort1 needs buffer_fraction >= 0.5 (got %g)", f);
         return GS_OK;
     }
-    const int64_t v = f >= 0.5 ? 32768 : (int64_t)floor(f * 65536.0);
-    if (v < gs::kF2MinQ)
-        return fail(GS_EUNSUPPORTED, "buffer_fraction %g is below the smallest supported, 1/64", f);
-    *q = v;
-    *out = algo == GS_ALGO_FROGSORT2 ? gs::kAlgoFrog2 : algo == GS_ALGO_FROGSORT3 ? gs::kAlgoFrog3 : kAutoSmallBuffer;
+    gs_status s = fraction_q(f, "buffer_fraction", q);
+    if (s != GS_OK) return s;
+    if (algo == GS_ALGO_FROGSORT6 && (s = fraction_q(sub, "sub_fraction", q2)) != GS_OK) return s;
+    *out = algo == GS_ALGO_FROGSORT2 ? gs::kAlgoFrog2 : algo == GS_ALGO_AUTO ? kAutoSmallBuffer : gs::kAlgoFrog3;
     return GS_OK;
 }
 
 // The segmented sort has Frogsort1 only.
 gs_status check_fraction_seg(double f)
 {
-    int64_t q = 0;
+    int64_t q = 0, q2 = 0;
     int a = 0;
-    gs_status s = resolve_algo(f, GS_ALGO_AUTO, &a, &q);
+    gs_status s = resolve_algo(f, GS_ALGO_AUTO, 0.5, &a, &q, &q2);
     if (s == GS_OK && a != gs::kAlgoFrog1)
         return fail(GS_EUNSUPPORTED, "segmented sort: buffer_fraction %g < 0.5 is not built", f);
     return s;
@@ -215,32 +226,34 @@ const char *gs_last_error_detail(void) { return g_detail.c_str(); }
 
 const char *gs_version(void) { return "0.1.0 gfx950"; }
 
-size_t gs_workspace_bytes_f64_ex(int64_t n, double buffer_fraction, int algo)
+size_t gs_workspace_bytes_f64_ex(int64_t n, double buffer_fraction, int algo, double sub_fraction)
 {
-    int64_t q = 0;
+    int64_t q = 0, q2 = 0;
     int a = 0;
-    if (n < 0 || n > ((int64_t)1 << 40) || resolve_algo(buffer_fraction, algo, &a, &q) != GS_OK) return SIZE_MAX;
+    if (n < 0 || n > ((int64_t)1 << 40) || resolve_algo(buffer_fraction, algo, sub_fraction, &a, &q, &q2) != GS_OK)
+        return SIZE_MAX;
     if (n <= 1) return 0;
-    return (size_t)gs::plan_f64(n, q, a).bytes;
+    return (size_t)gs::plan_f64(n, q, a, q2).bytes;
 }
 
-size_t gs_workspace_bytes_kv_ex(int64_t n, double buffer_fraction, int algo)
+size_t gs_workspace_bytes_kv_ex(int64_t n, double buffer_fraction, int algo, double sub_fraction)
 {
-    int64_t q = 0;
+    int64_t q = 0, q2 = 0;
     int a = 0;
-    if (n < 0 || n > ((int64_t)1 << 40) || resolve_algo(buffer_fraction, algo, &a, &q) != GS_OK) return SIZE_MAX;
+    if (n < 0 || n > ((int64_t)1 << 40) || resolve_algo(buffer_fraction, algo, sub_fraction, &a, &q, &q2) != GS_OK)
+        return SIZE_MAX;
     if (n <= 1) return 0;
-    return (size_t)gs::plan_kv(n, q, a).bytes;
+    return (size_t)gs::plan_kv(n, q, a, q2).bytes;
 }
 
 size_t gs_workspace_bytes_f64(int64_t n, double buffer_fraction)
 {
-    return gs_workspace_bytes_f64_ex(n, buffer_fraction, GS_ALGO_AUTO);
+    return gs_workspace_bytes_f64_ex(n, buffer_fraction, GS_ALGO_AUTO, 0.5);
 }
 
 size_t gs_workspace_bytes_kv(int64_t n, double buffer_fraction)
 {
-    return gs_workspace_bytes_kv_ex(n, buffer_fraction, GS_ALGO_AUTO);
+    return gs_workspace_bytes_kv_ex(n, buffer_fraction, GS_ALGO_AUTO, 0.5);
 }
 
 int gs_plan_depth(int64_t n, int is_kv, int64_t *leaf_max)
@@ -263,9 +276,10 @@ void gs_plan_node(int64_t n, int depth, int64_t idx, int64_t *out)
 int gs_plan_frog2(int64_t n, double buffer_fraction, int is_kv, int64_t *leaves, int64_t max_leaves,
                   int64_t *nodes, int64_t max_nodes, int64_t *counts)
 {
-    int64_t q = 0;
+    int64_t q = 0, q2 = 0;
     int a = 0;
-    if (n < 2 || n > ((int64_t)1 << 32) || resolve_algo(buffer_fraction, GS_ALGO_FROGSORT2, &a, &q) != GS_OK)
+    if (n < 2 || n > ((int64_t)1 << 32) ||
+        resolve_algo(buffer_fraction, GS_ALGO_FROGSORT2, 0.5, &a, &q, &q2) != GS_OK)
         return -1;
     const gs::SortPlan p = is_kv ? gs::plan_kv(n, q, a) : gs::plan_f64(n, q, a);
     const gs::F2Tables &T = *p.f2;
@@ -291,17 +305,20 @@ int gs_plan_frog2(int64_t n, double buffer_fraction, int is_kv, int64_t *leaves,
     counts[3] = p.hlen;
     counts[4] = T.max_tickets;
     counts[5] = T.max_splits;
+    counts[6] = T.merged;
     return 0;
 }
 
-int gs_plan_frog3(int64_t n, double buffer_fraction, int is_kv, int64_t *trees, int64_t max_trees, int64_t *spine,
-                  int64_t max_spine, int64_t *leaves, int64_t max_leaves, int64_t *counts)
+int gs_plan_frog3(int64_t n, double buffer_fraction, double sub_fraction, int is_kv, int64_t *trees,
+                  int64_t max_trees, int64_t *spine, int64_t max_spine, int64_t *leaves, int64_t max_leaves,
+                  int64_t *counts)
 {
-    int64_t q = 0;
+    int64_t q = 0, q2 = 0;
     int a = 0;
-    if (n < 2 || n > ((int64_t)1 << 32) || resolve_algo(buffer_fraction, GS_ALGO_FROGSORT3, &a, &q) != GS_OK)
+    if (n < 2 || n > ((int64_t)1 << 32) ||
+        resolve_algo(buffer_fraction, GS_ALGO_FROGSORT6, sub_fraction, &a, &q, &q2) != GS_OK)
         return -1;
-    const gs::SortPlan p = is_kv ? gs::plan_kv(n, q, a) : gs::plan_f64(n, q, a);
+    const gs::SortPlan p = is_kv ? gs::plan_kv(n, q, a, q2) : gs::plan_f64(n, q, a, q2);
     const gs::F3Plan &P = *p.f3;
     int64_t nl = 0;
     for (size_t i = 0; i < P.trees.size(); ++i) {
@@ -332,6 +349,7 @@ int gs_plan_frog3(int64_t n, double buffer_fraction, int is_kv, int64_t *trees, 
     counts[3] = P.total_rounds;
     counts[4] = p.hlen;
     counts[5] = P.b;
+    counts[6] = P.merged;
     return 0;
 }
 
@@ -344,22 +362,22 @@ gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws,
 gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_fraction, void *ws,
                              size_t ws_bytes, void *hip_stream, gs_report *rep)
 {
-    return gs_sort_f64_ex(keys, n, target, buffer_fraction, GS_ALGO_AUTO, ws, ws_bytes, hip_stream, rep);
+    return gs_sort_f64_ex(keys, n, target, buffer_fraction, GS_ALGO_AUTO, 0.5, ws, ws_bytes, hip_stream, rep);
 }
 
-gs_status gs_sort_f64_ex(double *keys, int64_t n, int target, double buffer_fraction, int algo, void *ws,
-                         size_t ws_bytes, void *hip_stream, gs_report *rep)
+gs_status gs_sort_f64_ex(double *keys, int64_t n, int target, double buffer_fraction, int algo, double sub_fraction,
+                         void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep)
 {
     g_detail.clear();
     if (target < GS_ASC_LEFT || target > GS_DESC_RIGHT) return fail(GS_EINVAL, "unknown target %d", target);
     if (n < 0) return fail(GS_EINVAL, "n < 0");
     if (n > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
-    int64_t q = 0;
+    int64_t q = 0, q2 = 0;
     int a = 0;
-    gs_status s = resolve_algo(buffer_fraction, algo, &a, &q);
+    gs_status s = resolve_algo(buffer_fraction, algo, sub_fraction, &a, &q, &q2);
     if (s != GS_OK) return s;
     if (n > ((int64_t)1 << 40)) return fail(GS_EINVAL, "n above 2^40");
-    gs::SortPlan p = gs::plan_f64(n, q, a);
+    gs::SortPlan p = gs::plan_f64(n, q, a, q2);
     if (n > 1) {
         if ((int64_t)ws_bytes < p.bytes || !ws)
             return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);
@@ -575,22 +593,22 @@ gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fr
 gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction,
                             void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep)
 {
-    return gs_sort_kv_ex(keys, vals, n, target, buffer_fraction, GS_ALGO_AUTO, ws, ws_bytes, hip_stream, rep);
+    return gs_sort_kv_ex(keys, vals, n, target, buffer_fraction, GS_ALGO_AUTO, 0.5, ws, ws_bytes, hip_stream, rep);
 }
 
 gs_status gs_sort_kv_ex(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction, int algo,
-                        void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep)
+                        double sub_fraction, void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep)
 {
     g_detail.clear();
     if (target < GS_ASC_LEFT || target > GS_DESC_RIGHT) return fail(GS_EINVAL, "unknown target %d", target);
     if (n < 0) return fail(GS_EINVAL, "n < 0");
     if (n > 0 && (!keys || !vals)) return fail(GS_EINVAL, "keys or vals is NULL");
-    int64_t q = 0;
+    int64_t q = 0, q2 = 0;
     int a = 0;
-    gs_status s = resolve_algo(buffer_fraction, algo, &a, &q);
+    gs_status s = resolve_algo(buffer_fraction, algo, sub_fraction, &a, &q, &q2);
     if (s != GS_OK) return s;
     if (n > ((int64_t)1 << 40)) return fail(GS_EINVAL, "n above 2^40");
-    gs::SortPlan p = gs::plan_kv(n, q, a);
+    gs::SortPlan p = gs::plan_kv(n, q, a, q2);
     if (n > 1) {
         if ((int64_t)ws_bytes < p.bytes || !ws)
             return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p.bytes);

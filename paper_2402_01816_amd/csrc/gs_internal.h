@@ -56,22 +56,25 @@ struct F2Tables {
     int rounds;                          // height of the root
     int64_t nleaves, nnodes;
     int64_t max_tickets, max_splits;     // largest round
+    int64_t merged;                      // elements merged over all rounds (sum of node sizes)
     std::vector<unsigned> rt, rs;        // tickets / splits per round (host copy)
     std::vector<char> blob;              // device image, offsets below
     int64_t off_leaf_c, off_leaf_d, off_node_s, off_node_n, off_node_tb, off_node_sb, off_rb, off_rt, off_rs;
 };
 
 // Frogsort3 ("Frogsort3": one buffer of b = floor(q n / 2^16) elements serves
-// the branches in turn).  While b is under half of the m elements left, the
-// last b of them form an inner child, sorted by Frogsort1 as a right node
-// whose region ends at slot m + b (its data land at [m, m + b)); then the rest
-// is the same problem on m - b.  What remains (b covers half of it, or it is a
-// single leaf) is one Frogsort1 tree at slot 0, and the spine merges
-// [0, m - b) with [m, m + b) into [0, m), bottom up.  Every tree is run from
-// F2Tables (q = 2^15 gives the Frogsort1 split); all their tables go up in one
-// image.
+// the branches in turn) and Frogsort6 (the same, switching to Frogsort2 trees
+// at fraction q2 / 2^16 instead of Frogsort1; q2 = 2^15 is Frogsort3).  While
+// a sub-tree over the m elements left would need more than b, the last b of
+// them form an inner child, sorted by a sub-tree whose root is a right node
+// with its region ending at slot m + b (its data land at [m, m + b)); then the
+// rest is the same problem on m - b.  What remains (its sub-tree fits b, or it
+// is a single leaf) is one sub-tree at slot 0, and the spine merges [0, m - b)
+// with [m, m + b) into [0, m), bottom up.  Every sub-tree runs from F2Tables;
+// all their tables go up in one image.
 struct F3Plan {
     int64_t n, q, b, leaf, tile;
+    int64_t q2;                                           // the sub-trees' split (2^15: Frogsort1)
     std::vector<std::shared_ptr<const F2Tables>> trees;   // in running order
     std::vector<int64_t> root_s, root_n, root_c;           // their roots: region start, size, input offset
     std::vector<int> root_left;
@@ -81,6 +84,7 @@ struct F3Plan {
     int max_rounds;                                       // deepest tree
     int total_rounds;                                     // merge rounds of the whole sort
     int64_t max_tickets, max_splits, max_status;
+    int64_t merged;                                       // elements merged (trees and spine)
 };
 
 enum : int { kAlgoFrog1 = 1, kAlgoFrog2 = 2, kAlgoFrog3 = 3 };
@@ -152,10 +156,15 @@ hipError_t forest_f64_async(double *D, double *H, const Prob *probs, const unsig
                             char *fw, hipStream_t st, const unsigned *gate, unsigned run_if, int merge_ipt = 16);
 
 // algo kAlgoFrog1: buffer floor(n/2) (q unused).  kAlgoFrog2 / kAlgoFrog3:
-// the buffer fraction is q / 2^16, q in [kF2MinQ, 2^15].
+// the buffer fraction is q / 2^16, q in [kF2MinQ, 2^15]; kAlgoFrog3 with
+// q2 < 2^15 is Frogsort6.
 constexpr int64_t kF2MinQ = 1024;       // p >= 1/64
-SortPlan plan_f64(int64_t n, int64_t q = 0, int algo = kAlgoFrog1);
-SortPlan plan_kv(int64_t n, int64_t q = 0, int algo = kAlgoFrog1);
+SortPlan plan_f64(int64_t n, int64_t q = 0, int algo = kAlgoFrog1, int64_t q2 = 32768);
+SortPlan plan_kv(int64_t n, int64_t q = 0, int algo = kAlgoFrog1, int64_t q2 = 32768);
+// Tables of the Frogsort2 tree over n elements, and the Frogsort3 / 6
+// schedule (gs_plan.cpp; cached, immutable once built).
+std::shared_ptr<const F2Tables> f2_tables(int64_t n, int64_t q, int64_t leaf, int64_t tile);
+std::shared_ptr<const F3Plan> f3_plans(int64_t n, int64_t q, int64_t q2, int64_t leaf, int64_t tile);
 // gate (may be null): every launch exits at once unless *gate == run_if.
 hipError_t sort_f64_async(double *keys, int64_t n, char *ws, const SortPlan &p, hipStream_t st,
                           const unsigned *gate = nullptr, unsigned run_if = 0u);

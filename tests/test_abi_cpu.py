@@ -242,15 +242,18 @@ def test_frog2_fraction_bounds():
 
 @pytest.mark.parametrize("kv", [False, True])
 @pytest.mark.parametrize("p", FRACTIONS)
-def test_frog3_plan_matches_oracle(orc, kv, p):
-    """The library's Frogsort3 schedule is the oracle model's: the same
-    Frogsort1 trees (root, size, input offset, side) in running order, the same
-    spine merges bottom up, the same leaves, and the same buffer."""
+@pytest.mark.parametrize("p2", [0.5, 0.2, 1 / 64])
+def test_frog3_plan_matches_oracle(orc, kv, p, p2):
+    """The library's Frogsort3 (p2 = 0.5) and Frogsort6 (Frogsort2 sub-trees
+    at p2) schedules are the oracle model's: the same sub-trees (root, size,
+    input offset, side) in running order, the same spine merges bottom up, the
+    same leaves, and the same buffer."""
     _, leaf = g.plan_depth(1 << 20, kv=kv)
     q = orc.frog2_fraction_q(p)
+    q2 = 32768 if p2 >= 0.5 else orc.frog2_fraction_q(p2)
     for n in [2, leaf, leaf + 1, 3 * leaf + 7, 1000003, (1 << 22) + 12345]:
-        trees, spine, leaves, counts = g.plan_frog3(n, p, kv)
-        r = orc.frog3_geometry(n, q, leaf)
+        trees, spine, leaves, counts = g.plan_frog3(n, p, kv, sub_fraction=p2)
+        r = orc.frog3_geometry(n, q, leaf, q2=q2)
         assert np.array_equal(trees, r["trees"]), n
         assert np.array_equal(spine, r["spine"]), n
         assert sorted(map(tuple, leaves.tolist())) == sorted(map(tuple, r["leaves"].tolist()))
@@ -262,8 +265,15 @@ def test_algo_argument_errors():
     fake = ctypes.c_void_p(0x100000)
     need = g.gs_workspace_bytes_f64(1000, 0.5)
     f = g.lib.gs_sort_f64_ex
-    assert f(fake, 1000, 0, 0.5, 7, fake, need, None, None) == g.GS_EINVAL
-    assert f(fake, 1000, 0, 0.25, 1, fake, need, None, None) == g.GS_EINVAL     # Frogsort1 needs 0.5
-    assert f(fake, 1000, 0, 0.01, 3, fake, need, None, None) == g.GS_EUNSUPPORTED
+    assert f(fake, 1000, 0, 0.5, 7, 0.5, fake, need, None, None) == g.GS_EINVAL
+    assert f(fake, 1000, 0, 0.25, 1, 0.5, fake, need, None, None) == g.GS_EINVAL     # Frogsort1 needs 0.5
+    assert f(fake, 1000, 0, 0.01, 3, 0.5, fake, need, None, None) == g.GS_EUNSUPPORTED
+    assert f(fake, 1000, 0, 0.1, 4, 0.01, fake, need, None, None) == g.GS_EUNSUPPORTED
+    assert f(fake, 1000, 0, 0.1, 4, 0.0, fake, need, None, None) == g.GS_EINVAL
+    assert f(fake, 1000, 0, 0.1, 4, float("nan"), fake, need, None, None) == g.GS_EINVAL
     assert g.gs_workspace_bytes_f64(1000, 0.25, "frogsort1") == g.SIZE_MAX
     assert g.gs_workspace_bytes_f64(1 << 20, 0.9, "frogsort3") == g.gs_workspace_bytes_f64(1 << 20, 0.5, "frogsort3")
+    # Frogsort6 at sub-fraction 0.5 is Frogsort3; at or below the fraction, one Frogsort2 tree
+    n = (1 << 22) + 5
+    assert g.gs_workspace_bytes_f64(n, 0.1, "frogsort6", 0.5) == g.gs_workspace_bytes_f64(n, 0.1, "frogsort3")
+    assert g.plan_frog3(n, 0.25, sub_fraction=0.2)[3][1] == 0

@@ -129,6 +129,25 @@ def test_small_buffer_full_size_sampled(gs, orc, algo, p):
     assert np.array_equal(bits(got), bits(x[idx]))
 
 
+@pytest.mark.parametrize("n", [8193, 100003, (1 << 20) + 7, (1 << 22) + 3])
+@pytest.mark.parametrize("p,p2", [(0.1, 0.25), (0.05, 0.2), (1 / 64, 0.1), (0.25, 0.2), (0.3, 0.45)])
+def test_frog6_parity(gs, orc, p, p2, n):
+    """Frogsort6: the buffer shared as in Frogsort3 with Frogsort2 sub-trees
+    at p2 (a single Frogsort2 tree once p >= p2)."""
+    announce("frog6", p, p2, n)
+    x = W.f64_pattern("tied", n, seed=n)
+    t = to_dev(x)
+    gs.gs_sort_f64(t, buffer_fraction=p, algo="frogsort6", sub_fraction=p2)
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+    k, v = W.kv_pattern("few", n, seed=n)
+    tk = to_dev(k.view(np.int64))
+    tv = to_dev(v.view(np.int32))
+    gs.gs_sort_kv(tk, tv, buffer_fraction=p, algo="frogsort6", sub_fraction=p2)
+    rk, rv = orc.sort_kv(k, v)
+    assert np.array_equal(tk.cpu().numpy().view(np.uint64), rk)
+    assert np.array_equal(tv.cpu().numpy().view(np.uint32), rv)
+
+
 def test_small_buffer_rejects_capture(gs):
     """A small-buffer call uploads host-built tables, so it refuses to be
     recorded into a graph (and enqueues nothing)."""

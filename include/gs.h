@@ -26,7 +26,7 @@
  *   - `buffer_fraction` p is the cap on extra buffer as a fraction of the data.
  *     p >= 0.5 selects Frogsort1 (buffer floor(n/2); never more).  For p in
  *     [1/64, 0.5) the fraction is rounded down to q/65536 (q = floor(65536 p))
- *     and the sort runs Frogsort3 ("Frogsort3": one buffer of floor(q n/65536)
+ *     and the sort runs Frogsort3 ("Frogsort3 and 6": one buffer of floor(q n/65536)
  *     elements serving the branches in turn) unless gs_sort_*_ex asks for
  *     Frogsort2 ("Frogsort2": every inner branch, and the buffer, the fraction
  *     p).  p in (0, 1/64) -> GS_EUNSUPPORTED (the trees get hundreds of levels
@@ -124,8 +124,8 @@ gs_status gs_sort_f64_target(double *keys, int64_t n, int target, double buffer_
 gs_status gs_sort_kv_target(uint64_t *keys, uint32_t *vals, int64_t n, int target, double buffer_fraction,
                             void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 
-/* The same with the tree named ("Frogsort1", "Frogsort2", "Frogsort3",
-   "Frogsort6").  GS_ALGO_AUTO is what the calls above run: Frogsort1 for
+/* The same with the tree named (sections "Frogsort1", "Frogsort2",
+   "Frogsort3 and 6").  GS_ALGO_AUTO is what the calls above run: Frogsort1 for
    p >= 0.5, Frogsort3 below.  GS_ALGO_FROGSORT1 with p < 0.5 -> GS_EINVAL;
    the others with p >= 0.5 run their own tree at p = 0.5 (Frogsort3 is then
    one Frogsort1 tree).  Frogsort6 shares the buffer like Frogsort3 but its

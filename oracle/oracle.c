@@ -697,9 +697,10 @@ int64_t oracle_frog2_model(const double *in, int64_t n, int64_t q, int64_t leaf_
 /* instrumented model of Frogsort3 / Frogsort6 (one buffer shared in turn)   */
 /* ------------------------------------------------------------------------ */
 /*
- * "Frogsort3": instead of splitting the buffer between the two branches, the
- * whole buffer serves one branch after the other, and a branch switches to
- * Frogsort1 once the buffer is at least half its size.  "Frogsort6" does the
+ * "Frogsort3 and 6": Frogsort3, instead of splitting the buffer between the
+ * two branches, lets the whole buffer serve one branch after the other, and a
+ * branch switches to Frogsort1 once the buffer is at least half its size;
+ * Frogsort6 does the
  * same but switches to Frogsort2 (inner fraction p2) once that fits; Frogsort1,
  * 2 and 3 are its special cases.  Reading: the input sits in slots [0, n), the
  * buffer is b = floor(q*n/65536) slots [n, n+b), and the sub-trees are

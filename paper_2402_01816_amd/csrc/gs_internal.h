@@ -62,7 +62,7 @@ struct F2Tables {
     int64_t off_leaf_c, off_leaf_d, off_node_s, off_node_n, off_node_tb, off_node_sb, off_rb, off_rt, off_rs;
 };
 
-// Frogsort3 ("Frogsort3": one buffer of b = floor(q n / 2^16) elements serves
+// Frogsort3 ("Frogsort3 and 6": one buffer of b = floor(q n / 2^16) elements serves
 // the branches in turn) and Frogsort6 (the same, switching to Frogsort2 trees
 // at fraction q2 / 2^16 instead of Frogsort1; q2 = 2^15 is Frogsort3).  While
 // a sub-tree over the m elements left would need more than b, the last b of

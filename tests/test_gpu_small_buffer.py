@@ -1,5 +1,5 @@
 """The small-buffer trees on the GPU: Frogsort2 ("Frogsort2": inner branch and
-buffer both a fraction p < 1/2 of the data) and Frogsort3 ("Frogsort3": one
+buffer both a fraction p < 1/2 of the data) and Frogsort3 ("Frogsort3 and 6": one
 buffer of that fraction serving the branches in turn).  Parity with the CPU
 oracle through the C ABI, bit for bit, for fractions from 1/64 to just under
 1/2, sizes from one leaf to many rounds with ragged tails, both key types and

@@ -75,6 +75,9 @@ typedef struct {
     uint32_t feature;               /* learned: 0 = linear in x, 1 = linear in the key bits */
     uint32_t invalid_offsets;       /* segsort: 1 if the device check rejected the offsets */
     double   elapsed_ms;            /* wall time of the call measured with HIP events */
+    uint32_t order;                 /* plain sorts: 0 sorted, 1 input already in order (nothing
+                                       moved), 2 input strictly reversed (one reversal pass) */
+    uint32_t reserved;
 } gs_report;
 
 /* Parameters of the learned CDF bucket path (not from the paper). */
@@ -103,7 +106,12 @@ size_t gs_workspace_bytes_learned(int64_t n, const gs_learned_params *p);
 
 /* Stable ascending sort of n float64 keys in place ("Frogsort1").  The top
    merge writes the result straight into `keys`; ws holds the floor(n/2)
-   half buffer. */
+   half buffer.  Every plain sort (these, the targets, the _ex calls) first
+   checks on the device whether the keys are already in order (then nothing
+   moves) or strictly reversed (then one reversal pass is the whole sort):
+   the bi-adaptivity of "Octosort" and "Squidsort" at the level of the whole
+   array; 4096 sampled pairs keep the check to one small launch on other
+   input. */
 gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction,
                       void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 

@@ -50,6 +50,8 @@ class GsReport(ctypes.Structure):
         ("feature", ctypes.c_uint32),
         ("invalid_offsets", ctypes.c_uint32),
         ("elapsed_ms", ctypes.c_double),
+        ("order", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
     def as_dict(self):

@@ -157,6 +157,16 @@ gs_status check_err_word(const char *ws, const gs::SortPlan &p)
     return check_err_word(ws + p.off_forest + p.forest.off_ctrl);
 }
 
+// The order check's decision of a plain sort, after the stream is synchronised.
+gs_status read_order(const char *ws, const gs::SortPlan &p, uint32_t *order)
+{
+    unsigned w = 0;
+    hipError_t e = hipMemcpy(&w, ws + p.off_order, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the order word");
+    *order = w;
+    return GS_OK;
+}
+
 struct TraceRec {
     int kind;
     hipEvent_t a, b;
@@ -400,6 +410,7 @@ gs_status gs_sort_f64_ex(double *keys, int64_t n, int target, double buffer_frac
     }
     s = r.finish(GS_OK);
     if (rep && s == GS_OK) s = check_err_word((const char *)ws, p);
+    if (rep && s == GS_OK) s = read_order((const char *)ws, p, &rep->order);
     return s;
 }
 
@@ -631,6 +642,7 @@ gs_status gs_sort_kv_ex(uint64_t *keys, uint32_t *vals, int64_t n, int target, d
     }
     s = r.finish(GS_OK);
     if (rep && s == GS_OK) s = check_err_word((const char *)ws, p);
+    if (rep && s == GS_OK) s = read_order((const char *)ws, p, &rep->order);
     return s;
 }
 

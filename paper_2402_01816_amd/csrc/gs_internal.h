@@ -103,8 +103,13 @@ struct SortPlan {
     ForestPlan forest;
     std::shared_ptr<const F2Tables> f2;   // Frogsort2 tables
     std::shared_ptr<const F3Plan> f3;     // Frogsort3 schedule
+    int64_t off_order;    // the order check's two words (see ORD_*)
     int64_t bytes;        // total workspace
 };
+
+// The order check's decision (word 0 at off_order): sort, keys already in
+// order, keys strictly reversed; candidate while the full check runs.
+enum : unsigned { ORD_SORT = 0, ORD_IN_ORDER = 1, ORD_REVERSED = 2, ORD_CANDIDATE = 3 };
 
 // Shape of a segmented sort: the work-group size and keys per thread of the
 // batched short-segment sort (their product is the LDS tile and the length

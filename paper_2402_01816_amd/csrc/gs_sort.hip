@@ -922,7 +922,8 @@ SortPlan make_plan(int64_t n, int64_t q, int algo, int64_t q2)
     } else {
         p.forest = forest_plan_one<KT, V>(n);
     }
-    p.bytes = p.off_forest + p.forest.bytes;
+    p.off_order = p.off_forest + p.forest.bytes;
+    p.bytes = p.off_order + 256;
     if (n <= 1) p.bytes = 0;
     return p;
 }
@@ -998,10 +999,11 @@ hipError_t sort_kv_async(uint64_t *keys, uint32_t *vals, int64_t n, char *ws, co
 
 // In-place reversal of keys[0, n) (and vals), one pair (i, n-1-i) per thread:
 // the right-anchored targets are the left-anchored ones of the opposite
-// direction read backwards.
+// direction read backwards, and strictly reversed input is sorted by it.
 template <class K, class V>
-__global__ __launch_bounds__(256) void reverse_kernel(K *keys, V *vals, int64_t n)
+__global__ __launch_bounds__(256) void reverse_kernel(K *keys, V *vals, int64_t n, Gate gate)
 {
+    if (gate.closed()) return;
     const int64_t half = n / 2;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < half;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -1018,11 +1020,93 @@ __global__ __launch_bounds__(256) void reverse_kernel(K *keys, V *vals, int64_t 
 }
 
 template <class K, class V>
-static void launch_reverse(K *keys, V *vals, int64_t n, hipStream_t st)
+static void launch_reverse(K *keys, V *vals, int64_t n, hipStream_t st, Gate gate = Gate{nullptr, 0u})
 {
     if (n < 2) return;
     const int64_t half = n / 2;
-    hipLaunchKernelGGL((reverse_kernel<K, V>), dim3(grid_for(half, 256, 8192)), dim3(256), 0, st, keys, vals, n);
+    hipLaunchKernelGGL((reverse_kernel<K, V>), dim3(grid_for(half, 256, 8192)), dim3(256), 0, st, keys, vals, n,
+                       gate);
+}
+
+// ---------------------------------------------------------------------------
+// input already in order, or exactly reversed
+// ---------------------------------------------------------------------------
+// "Octosort", "Squidsort": bi-adaptive to presorted and reverse-sorted input.
+// Before the tree runs, the call decides on the device whether the keys are
+// already in the sort's order (every neighbour pair non-decreasing: nothing
+// to do) or strictly reversed (every pair strictly decreasing: the result is
+// the reversal, and no ties can occur); anything else is sorted.  4096
+// sampled pairs decide first, so unsorted input pays one small launch; the
+// pass over every pair runs only when the sample finds no counter-example.
+// The decision (word 0) gates every later launch of the call; word 1 holds
+// the orders still possible (bit 0 in order, bit 1 reversed).
+template <class KT>
+__global__ __launch_bounds__(256) void order_sample_kernel(const typename KT::T *keys, int64_t n, unsigned *word)
+{
+    const int64_t m = n - 1;             // pairs
+    bool asc = true, desc = true;
+    for (int j = threadIdx.x; j < 4096; j += 256) {
+        const int64_t i = (int64_t)j * m / 4096;
+        const auto a = keys[i], b = keys[i + 1];
+        asc = asc && !KT::less(b, a);
+        desc = desc && KT::less(b, a);
+    }
+    asc = __syncthreads_and(asc) != 0;
+    desc = __syncthreads_and(desc) != 0;
+    if (threadIdx.x == 0) {
+        word[1] = (asc ? 1u : 0u) | (desc ? 2u : 0u);
+        word[0] = (asc || desc) ? (unsigned)ORD_CANDIDATE : (unsigned)ORD_SORT;
+    }
+}
+
+template <class KT>
+__global__ __launch_bounds__(256) void order_check_kernel(const typename KT::T *keys, int64_t n, unsigned *word)
+{
+    if (word[0] != ORD_CANDIDATE) return;
+    const unsigned possible = word[1];
+    bool asc = (possible & 1u) != 0, desc = (possible & 2u) != 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n - 1 && (asc || desc);
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const auto a = keys[i], b = keys[i + 1];
+        asc = asc && !KT::less(b, a);
+        desc = desc && KT::less(b, a);
+    }
+    asc = __syncthreads_and(asc) != 0;
+    desc = __syncthreads_and(desc) != 0;
+    if (threadIdx.x == 0) {
+        if (!asc) atomicAnd(word + 1, ~1u);
+        if (!desc) atomicAnd(word + 1, ~2u);
+    }
+}
+
+__global__ void order_decide_kernel(unsigned *word)
+{
+    if (word[0] == ORD_CANDIDATE)
+        word[0] = (word[1] & 1u) ? (unsigned)ORD_IN_ORDER : (word[1] & 2u) ? (unsigned)ORD_REVERSED : (unsigned)ORD_SORT;
+}
+
+template <class KT>
+static void launch_order_check(const typename KT::T *keys, int64_t n, unsigned *word, hipStream_t st)
+{
+    hipLaunchKernelGGL((order_sample_kernel<KT>), dim3(1), dim3(256), 0, st, keys, n, word);
+    hipLaunchKernelGGL((order_check_kernel<KT>), dim3(grid_for(n - 1, 256, 8192)), dim3(256), 0, st, keys, n,
+                       word);
+    hipLaunchKernelGGL(order_decide_kernel, dim3(1), dim3(1), 0, st, word);
+}
+
+// One stable sort with its order check: KT is the key order the tree sorts
+// in; its result is left in place, or the input reversed, or the input kept.
+template <class KT, class V>
+static hipError_t run_sort_adaptive(typename KT::T *keys, V *vals, int64_t n, char *ws, const SortPlan &p,
+                                    hipStream_t st)
+{
+    if (n <= 1) return hipSuccess;
+    unsigned *word = (unsigned *)(ws + p.off_order);
+    launch_order_check<KT>(keys, n, word, st);
+    hipError_t e = run_sort<KT, V>(keys, vals, n, ws, p, st, Gate{word, (unsigned)ORD_SORT});
+    if (e != hipSuccess) return e;
+    launch_reverse(keys, vals, n, st, Gate{word, (unsigned)ORD_REVERSED});
+    return hipGetLastError();
 }
 
 hipError_t sort_f64_target_async(double *keys, int64_t n, int target, char *ws, const SortPlan &p, hipStream_t st)
@@ -1030,8 +1114,8 @@ hipError_t sort_f64_target_async(double *keys, int64_t n, int target, char *ws, 
     // targets: 0 AscLeft, 1 AscRight = reversed DescLeft, 2 DescLeft,
     // 3 DescRight = reversed AscLeft
     hipError_t e = (target == 1 || target == 2)
-                       ? run_sort<KeyF64Desc, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st, Gate{nullptr, 0u})
-                       : run_sort<KeyF64, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st, Gate{nullptr, 0u});
+                       ? run_sort_adaptive<KeyF64Desc, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st)
+                       : run_sort_adaptive<KeyF64, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st);
     if (e != hipSuccess) return e;
     if (target == 1 || target == 3) launch_reverse(keys, (NoVal *)nullptr, n, st);
     return hipGetLastError();
@@ -1041,8 +1125,8 @@ hipError_t sort_kv_target_async(uint64_t *keys, uint32_t *vals, int64_t n, int t
                                 hipStream_t st)
 {
     hipError_t e = (target == 1 || target == 2)
-                       ? run_sort<KeyU64Desc, uint32_t>(keys, vals, n, ws, p, st, Gate{nullptr, 0u})
-                       : run_sort<KeyU64, uint32_t>(keys, vals, n, ws, p, st, Gate{nullptr, 0u});
+                       ? run_sort_adaptive<KeyU64Desc, uint32_t>(keys, vals, n, ws, p, st)
+                       : run_sort_adaptive<KeyU64, uint32_t>(keys, vals, n, ws, p, st);
     if (e != hipSuccess) return e;
     if (target == 1 || target == 3) launch_reverse(keys, vals, n, st);
     return hipGetLastError();

@@ -150,3 +150,79 @@ def test_sort_kv_targets(gs, orc, target, pattern):
     rk, rv = orc.sort_kv_target(k0, v0, target)
     assert np.array_equal(K.cpu().numpy().view(np.uint64), rk)
     assert np.array_equal(V.cpu().numpy().view(np.uint32), rv)
+
+
+# --------------------------------------------------------------------------
+# input already in order or strictly reversed ("Octosort", "Squidsort")
+# --------------------------------------------------------------------------
+def _order_cases(n, seed):
+    rng = np.random.default_rng(seed)
+    base = np.sort(rng.random(n))
+    ties = np.sort(rng.integers(0, 50, n).astype(np.float64))
+    cases = {
+        "in order": (base, 1),
+        "in order, ties": (ties, 1),
+        "in order, ±0 and NaN tail": (np.concatenate([[-1.0], [0.0, -0.0, 0.0, -0.0], np.full(3, 7.0),
+                                                     np.full(max(n - 11, 0), np.inf), [np.nan, np.nan, np.nan]]), 1),
+        "strictly reversed": (base[::-1].copy(), 2),
+        "strictly reversed, NaN first": (np.concatenate([[np.nan], base[::-1]]), 2),
+        "reversed with ties": (ties[::-1].copy(), 0),
+        "two NaNs then reversed": (np.concatenate([[np.nan, np.nan], base[::-1]]), 0),
+    }
+    # one inversion between two sampled pairs (the sample sees pairs at
+    # floor(j (n-1) / 4096)): only the full check finds it
+    if n > 16:
+        x = base.copy()
+        k = 5 * (n - 1) // 4096 + 3
+        x[k], x[k + 1] = x[k + 1], x[k]
+        cases["one hidden inversion"] = (x, 0)
+    return cases
+
+
+@pytest.mark.parametrize("n", [3, 4097, 1_000_003])
+def test_order_fast_paths(gs, orc, n):
+    for name, (x, want) in _order_cases(n, seed=n).items():
+        announce("order", name, x.size)
+        t = to_dev(x)
+        rep = gs.gs_sort_f64(t, report=True)
+        assert np.array_equal(bits(t), bits(orc.sort_f64(x))), name
+        if x.size > 3:
+            assert rep["order"] == want, name
+
+
+@pytest.mark.parametrize("target", TARGETS)
+def test_order_fast_paths_targets(gs, orc, target):
+    n = 200_003
+    for name, (x, _) in _order_cases(n, seed=7).items():
+        announce("order target", target, name)
+        t = to_dev(x)
+        gs.gs_sort_f64(t, target=target)
+        assert np.array_equal(bits(t), bits(orc.sort_f64_target(x, target))), name
+
+
+def test_order_fast_paths_kv(gs, orc):
+    n = 300_001
+    rng = np.random.default_rng(3)
+    base = np.sort(rng.integers(0, 1 << 62, n, dtype=np.int64).astype(np.uint64))
+    for name, k, want in (("in order", base, 1), ("strictly reversed", base[::-1].copy(), 2),
+                          ("in order, ties", np.sort(rng.integers(0, 9, n).astype(np.uint64)), 1)):
+        announce("order kv", name)
+        v = np.arange(n, dtype=np.uint32)
+        tk = to_dev(k.view(np.int64))
+        tv = to_dev(v.view(np.int32))
+        rep = gs.gs_sort_kv(tk, tv, report=True)
+        rk, rv = orc.sort_kv(k, v)
+        assert rep["order"] == want, name
+        assert np.array_equal(tk.cpu().numpy().view(np.uint64), rk)
+        assert np.array_equal(tv.cpu().numpy().view(np.uint32), rv)
+
+
+@pytest.mark.parametrize("algo,p", [("frogsort2", 0.1), ("frogsort3", 0.25), ("frogsort6", 0.1)])
+def test_order_fast_paths_small_buffer(gs, orc, algo, p):
+    n = 1_000_003
+    for name, (x, want) in _order_cases(n, seed=11).items():
+        announce("order small buffer", algo, name)
+        t = to_dev(x)
+        rep = gs.gs_sort_f64(t, buffer_fraction=p, algo=algo, sub_fraction=0.25, report=True)
+        assert np.array_equal(bits(t), bits(orc.sort_f64(x))), name
+        assert rep["order"] == want, name

@@ -29,28 +29,57 @@ constexpr int lds_slots() { return TILE + TILE / 16 + 2; }
 // B = [b_base, b_base+nb) (logical LDS indices) starting at A index ai and B
 // index bi; on a tie the A element goes first.  Branch free: the heads of both
 // runs stay in registers, every step costs one comparison and one LDS read,
-// and reads past a run's end (clamped to `limit`, a readable slot) are never
-// selected.  Outputs beyond the runs' total are garbage and must be ignored.
+// and a lookahead past a run's end is never selected.  Positions are tracked
+// absolutely; a lookahead never passes its run's end and every run ends at or
+// before `limit` (the tile's end, a readable slot), so only the first two
+// reads need clamping.  Outputs beyond the runs' total are garbage and must be
+// ignored.
 template <class KT, int IPT, bool WANT_SRC>
 __device__ __forceinline__ void serial_merge(const typename KT::T *sk, int a_base, int na, int b_base,
                                              int nb, int ai, int bi, int limit,
                                              typename KT::T (&k)[IPT], int (&src)[IPT])
 {
     using K = typename KT::T;
-    K va = sk[lpad(min(a_base + ai, limit))];
-    K vb = sk[lpad(min(b_base + bi, limit))];
+    int pa = a_base + ai, pb = b_base + bi;
+    const int ea = a_base + na, eb = b_base + nb;
+    K va = sk[lpad(min(pa, limit))];
+    K vb = sk[lpad(min(pb, limit))];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const bool takeB = (bi < nb) & ((ai >= na) | KT::less(vb, va));
+        const bool takeB = (pb < eb) & ((pa >= ea) | KT::less(vb, va));
         k[i] = takeB ? vb : va;
-        if constexpr (WANT_SRC) src[i] = takeB ? b_base + bi : a_base + ai;
-        bi += takeB ? 1 : 0;
-        ai += takeB ? 0 : 1;
-        const int nidx = min(takeB ? b_base + bi : a_base + ai, limit);
-        const K nv = sk[lpad(nidx)];
+        if constexpr (WANT_SRC) src[i] = takeB ? pb : pa;
+        pb += takeB ? 1 : 0;
+        pa += takeB ? 0 : 1;
+        const K nv = sk[lpad(takeB ? pb : pa)];
         va = takeB ? va : nv;
         vb = takeB ? nv : vb;
     }
+}
+
+// Batcher's odd-even merge sort network on N = 2^k registers (Knuth, TAOCP
+// vol. 3, 5.3.4, Algorithm M): compare-exchange (lo[c], hi[c]) in order c.
+template <int N>
+struct SortNet {
+    int lo[N * N], hi[N * N];
+    int count;
+};
+
+template <int N>
+constexpr SortNet<N> batcher_net()
+{
+    SortNet<N> s{};
+    s.count = 0;
+    for (int p = 1; p < N; p *= 2)
+        for (int k = p; k >= 1; k /= 2)
+            for (int j = k % p; j < N - k; j += 2 * k)
+                for (int i = 0; i < (k < N - j - k ? k : N - j - k); ++i)
+                    if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        s.lo[s.count] = i + j;
+                        s.hi[s.count] = i + j + k;
+                        ++s.count;
+                    }
+    return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -66,10 +95,13 @@ __device__ __forceinline__ void serial_merge(const typename KT::T *sk, int a_bas
 // padding, which sorts after every real key.  Then within every merge pair the
 // real keys stay at the front, so slots at or past `active` hold padding after
 // every round too, and a thread whose keys or outputs all lie there skips its
-// work.
+// work.  With `ties_identical` (keys only; the caller has checked that equal
+// keys are bit for bit equal, so no order among them can be seen) the
+// per-thread sort is Batcher's network, half the compare-exchanges of the
+// transposition sort.
 template <class KT, class VS, bool HV, int NT, int IPT, bool PARTIAL = false>
 __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int maxw = NT * IPT,
-                                               int active = NT * IPT)
+                                               int active = NT * IPT, bool ties_identical = false)
 {
     using K = typename KT::T;
     constexpr int TILE = NT * IPT;
@@ -84,7 +116,18 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
         k[i] = sk[lpad(base + i)];
         if constexpr (HV) v[i] = sv[lpad(base + i)];
     }
-    if (work) {
+    bool network = false;
+    if constexpr (!HV) network = ties_identical;
+    if (work && network) {
+        constexpr SortNet<IPT> net = batcher_net<IPT>();
+#pragma unroll
+        for (int c = 0; c < net.count; ++c) {
+            const K a = k[net.lo[c]], b = k[net.hi[c]];
+            const bool sw = KT::less(b, a);
+            k[net.lo[c]] = sw ? b : a;
+            k[net.hi[c]] = sw ? a : b;
+        }
+    } else if (work) {
 #pragma unroll
         for (int r = 0; r < IPT; ++r) {
 #pragma unroll
@@ -158,6 +201,15 @@ __device__ __forceinline__ bool is_nan_key(K x)
 {
     if constexpr (std::is_same<K, double>::value) return x != x;
     else return false;
+}
+
+// Keys whose ties may differ in their bits: NaN payloads and the two zeros.
+// Without them, equal keys are identical.
+template <class K>
+__device__ __forceinline__ bool tie_bits_may_differ(K x)
+{
+    if constexpr (std::is_same<K, double>::value) return x != x || x == 0.0;
+    else return true;
 }
 
 }  // namespace gs

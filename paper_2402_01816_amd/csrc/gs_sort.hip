@@ -116,7 +116,7 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         // load the chunk (input elements all live in the caller's array) with
         // straight-line loads from clamped indices, all issued before the
         // first LDS write
-        bool nan_here = false;
+        bool nan_here = false, ties_identical = false;
         {
             K lk[IPT];
             VS lv[IPT];
@@ -127,9 +127,14 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
                 lk[r] = GS_MERGE_LOAD(keys.D + src + ic);
                 if constexpr (HV) lv[r] = vals.D[src + ic];
             }
+            bool differ = false;
 #pragma unroll
-            for (int r = 0; r < IPT; ++r) nan_here |= is_nan_key(lk[r]);
+            for (int r = 0; r < IPT; ++r) {
+                nan_here |= is_nan_key(lk[r]);
+                differ |= tie_bits_may_differ(lk[r]);
+            }
             const bool any_nan = __syncthreads_or(nan_here) != 0;
+            ties_identical = !HV && __syncthreads_or(differ) == 0;
             // slots past the chunk get a padding key that sorts after every
             // real key (ties with it stay behind the real keys)
             const K pad = any_nan ? KT::pad() : KF::pad();
@@ -149,12 +154,12 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         // it, skipping the work on the padding past it
         if (HV || len == TILE) {
             if (nan_here) block_sort_lds<KT, VS, HV, NT, IPT>(sk, sv);
-            else block_sort_lds<KF, VS, HV, NT, IPT>(sk, sv);
+            else block_sort_lds<KF, VS, HV, NT, IPT>(sk, sv, TILE, TILE, ties_identical);
         } else if constexpr (!HV) {
             int maxw = IPT;
             while (maxw < len) maxw *= 2;
             if (nan_here) block_sort_lds<KT, VS, HV, NT, IPT, true>(sk, sv, maxw, len);
-            else block_sort_lds<KF, VS, HV, NT, IPT, true>(sk, sv, maxw, len);
+            else block_sort_lds<KF, VS, HV, NT, IPT, true>(sk, sv, maxw, len, ties_identical);
         }
 
         // wait for the leaves whose input chunks the destination covers

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(NT) void seg_sort_kernel(typename KT::T *keys, cons
         }
         __syncthreads();
         K r[IPT];
-        bool nan_here = false;
+        bool nan_here = false, differ = false;
 #pragma unroll
         for (int q = 0; q < IPT; ++q) {
             const int i = (int)threadIdx.x + q * NT;
@@ -194,8 +194,11 @@ __global__ __launch_bounds__(NT) void seg_sort_kernel(typename KT::T *keys, cons
             const int64_t p = real ? s_off[b] + j : s_off[0];
             r[q] = keys[p];
             nan_here |= real && is_nan_key(r[q]);
+            differ |= real && tie_bits_may_differ(r[q]);
         }
         const bool any_nan = __syncthreads_or(nan_here) != 0;
+        // equal keys bit for bit equal: the order among them cannot be seen
+        const bool ties_identical = __syncthreads_or(differ) == 0;
         const K pad = any_nan ? KT::pad() : KF::pad();
 #pragma unroll
         for (int q = 0; q < IPT; ++q) {
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(NT) void seg_sort_kernel(typename KT::T *keys, cons
         char dummy[1];
         __syncthreads();
         if (any_nan) block_sort_lds<KT, char, false, NT, IPT, true>(sk, dummy, 1 << P_log, active);
-        else block_sort_lds<KF, char, false, NT, IPT, true>(sk, dummy, 1 << P_log, active);
+        else block_sort_lds<KF, char, false, NT, IPT, true>(sk, dummy, 1 << P_log, active, ties_identical);
 #pragma unroll
         for (int q = 0; q < IPT; ++q) {
             const int i = (int)threadIdx.x + q * NT;

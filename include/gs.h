@@ -15,7 +15,8 @@
  *     structs are device pointers unless their comment says host.
  *   - `hip_stream` is a hipStream_t (NULL = the default stream).  Every call is
  *     asynchronous on that stream unless `rep` is non-NULL, in which case the
- *     call synchronises the stream before filling the report.
+ *     call synchronises the stream before filling the report (gs_learned_sort
+ *     also synchronises once mid-call; see there).
  *   - Sorting is in place: the result replaces `keys` (and `vals`).
  *   - The caller owns all memory.  The library makes no device allocation; the
  *     workspace `ws` (at least gs_workspace_bytes_*() bytes, 256-byte aligned)
@@ -67,7 +68,8 @@ typedef struct {
     double   ram_fraction;          /* %RAM = (data bytes + workspace bytes) / data bytes */
     uint64_t workspace_bytes_used;  /* bytes of ws the call may touch */
     uint32_t levels;                /* merge levels (tree depth) of the largest sort done */
-    uint32_t fallback;              /* learned: 1 if the bucket order failed verification */
+    uint32_t fallback;              /* learned: 1 the bucket table failed verification (order,
+                                       overflow), 2 the sample predicted too uneven buckets */
     uint32_t overflow_buckets;      /* learned: buckets above the in-LDS capacity */
     uint32_t max_bucket;            /* learned: largest bucket (keys) */
     float    train_loss_first;      /* learned: training loss of the first / last step */
@@ -90,6 +92,9 @@ typedef struct {
     float    lr;             /* Adam learning rate; default 2e-2 */
     uint64_t seed;           /* sample positions, weight init and minibatches */
     uint32_t mode;           /* 0 = trained network, 1 = untrained linear CDF (table[i] = i/knots) */
+    uint32_t judge;          /* 0 = trained mode lets the plain path judge the table on the
+                                sample before any key moves (default); 1 = skip that early
+                                judgment (the checks on the full bucket totals still apply) */
     const float *weights_override;    /* device, 4353 floats: skip training, use these weights; may be NULL */
     const float *test_bucket_table;   /* device, `knots`+1 floats: raw table, bypasses the running max
                                          (test hook to force an order violation); may be NULL */
@@ -209,10 +214,15 @@ gs_status gs_segsort_autotune(const double *keys, int64_t num_keys, const int64_
    the keys first.  The key-to-bucket map is verified monotone before any key
    moves; if it is not, or a bucket would exceed max(2^20, a quarter of its
    half), or the sample has no usable range, the plain path sorts the
-   untouched input (report.fallback = 1).  Inputs shorter than 4 * sample_size
-   run the plain path directly.  Extra memory stays at the half buffer (plus
-   per-tile digit counters and the network's state).  `p` is a host pointer
-   (NULL = defaults). */
+   untouched input (report.fallback = 1).  Before that, the trained table
+   buckets the sorted sample: a bucket predicted above max(2^19, 16 x the
+   average) sends the call to the plain path at once (report.fallback = 2).
+   Unless the stream is capturing a graph, the call synchronises the stream
+   once, after training, to read that decision and enqueue only the path that
+   runs; under capture both paths are enqueued, gated on the device.  Inputs
+   shorter than 4 * sample_size run the plain path directly.  Extra memory
+   stays at the half buffer (plus per-tile digit counters and the network's
+   state).  `p` is a host pointer (NULL = defaults). */
 gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p,
                           void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 

@@ -53,6 +53,14 @@ constexpr int L_BAR = 4;                 // training grid barrier
 constexpr int L_ERR = 5;
 constexpr int L_BIGB = 6;                // buckets larger than one LDS tile
 constexpr int L_FEAT = 7;                // chosen feature
+constexpr int L_JUDGED = 8;              // the sample predicted too uneven buckets
+
+// The plain path judges the learned form before any key moves: a bucket
+// predicted (from the sample, scaled to a half) above max(kJudgeMin, 16 x the
+// average bucket) means the network did not spread the keys well enough for
+// the bucket sorts to beat the merge passes they replace.
+constexpr int64_t kJudgeMin = (int64_t)1 << 19;
+constexpr int64_t kJudgeSkew = 16;
 
 __device__ __forceinline__ uint64_t mix64d(uint64_t z)
 {
@@ -301,6 +309,42 @@ __global__ __launch_bounds__(1024) void learned_table_kernel(const float *raw, c
 constexpr int SW_NT = 256;
 constexpr int SW_ROUNDS = 16;
 constexpr int SW_TILE = SW_NT * SW_ROUNDS;           // 4096 keys
+
+// The sorted sample through the trained knot table: its largest bucket,
+// scaled to a half of the input, decides whether the call goes on with the
+// learned form or takes the plain path at once.
+__global__ __launch_bounds__(1024) void learned_judge_kernel(const double *sample, int64_t S, const Feature *feat,
+                                                             const float *tab, int G, int B, int64_t half,
+                                                             unsigned *ctrl)
+{
+    extern __shared__ unsigned char s_raw[];
+    float *s_tab = (float *)s_raw;                       // G + 1 knots
+    unsigned *s_hist = (unsigned *)(s_tab + G + 1);      // B buckets
+    __shared__ unsigned s_max;
+    if (ctrl[L_FALLBACK]) return;
+    const int tid = threadIdx.x;
+    for (int i = tid; i <= G; i += 1024) s_tab[i] = tab[i];
+    for (int i = tid; i < B; i += 1024) s_hist[i] = 0u;
+    if (tid == 0) s_max = 0u;
+    __syncthreads();
+    const Feature F = *feat;
+    for (int64_t i = tid; i < S; i += 1024) atomicAdd(&s_hist[bucket_of(sample[i], F, s_tab, G, B)], 1u);
+    __syncthreads();
+    unsigned m = 0u;
+    for (int i = tid; i < B; i += 1024) m = s_hist[i] > m ? s_hist[i] : m;
+    atomicMax(&s_max, m);
+    __syncthreads();
+    if (tid == 0) {
+        const int64_t predicted = (int64_t)s_max * half / S;
+        const int64_t avg = half / B;
+        const int64_t limit = kJudgeSkew * avg > kJudgeMin ? kJudgeSkew * avg : kJudgeMin;
+        if (predicted > limit) {
+            ctrl[L_JUDGED] = 1u;
+            ctrl[L_MAXB] = (unsigned)(predicted < 0xffffffffll ? predicted : 0xffffffffll);
+            ctrl[L_FALLBACK] = 1u;
+        }
+    }
+}
 
 __global__ __launch_bounds__(SW_NT) void learned_count_kernel(const double *src, int64_t len, const Feature *feat,
                                                               const float *tab, int G, int B, int shift, int dbits,
@@ -682,6 +726,29 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     if (tr) trace_end(st);
     hipLaunchKernelGGL(learned_table_kernel, dim3(1), dim3(1024), 0, st, (const float *)raw, prm.test_bucket_table,
                        (int)prm.mode, G, tab, ctrl, (const Feature *)feat);
+    if (prm.mode == 0 && !prm.test_bucket_table && prm.judge == 0) {
+        const size_t jlds = (size_t)(G + 1) * 4 + (size_t)B * 4;
+        (void)hipFuncSetAttribute((const void *)learned_judge_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)jlds);
+        hipLaunchKernelGGL(learned_judge_kernel, dim3(1), dim3(1024), jlds, st, (const double *)sample, L.S,
+                           (const Feature *)feat, (const float *)tab, G, B, n - n / 2, ctrl);
+    }
+    // Unless the stream is being captured, the host reads the decision once
+    // and enqueues only the path that runs (the gated launches of the other
+    // one cost about a millisecond); under capture every launch stays gated
+    // on the device word.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusActive;
+    }
+    if (cs == hipStreamCaptureStatusNone) {
+        unsigned fb = 0u;
+        e = hipMemcpyAsync(&fb, ctrl + L_FALLBACK, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (fb) return sort_f64_async(keys, n, ws, L.plain, st, ctrl + L_FALLBACK, 1u);
+    }
 
     // 6. bucket totals of both halves (and the first pass's tile counts)
     //    before anything moves
@@ -782,7 +849,7 @@ hipError_t learned_read_report(const char *ws, const LearnedPlan &L, LearnedRepo
     hipError_t e = hipMemcpy(c, ws + L.off_ctrl, sizeof c, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(loss, ws + L.off_losses, sizeof loss, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return e;
-    r->fallback = c[L_FALLBACK];
+    r->fallback = c[L_FALLBACK] ? (c[L_JUDGED] ? 2u : 1u) : 0u;
     r->order_violation = c[L_ORDER];
     r->overflow_buckets = c[L_OVERFLOW];
     r->max_bucket = c[L_MAXB];

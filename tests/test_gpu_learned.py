@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import announce, bits, need_gpu, to_dev
+from gpu_util import multiset_hash_dev, announce, bits, need_gpu, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -185,15 +185,44 @@ def test_learned_fallback_on_order_violation(gs, orc):
 
 def test_learned_fallback_on_overflow(gs, orc):
     """One key value holding 60% of a 2^22-key input puts more than the bucket
-    limit (2^20) into one bucket of each half: the call takes the plain path."""
+    limit (2^20) into one bucket of each half.  The sample predicts it, so the
+    plain path takes the call before any key moves (fallback 2); with that
+    early judgment off, the check on the full bucket totals catches it
+    (fallback 1).  Either way the result is the plain sort's."""
     announce("learned fallback overflow")
     n = 1 << 22
     x = W.f64_pattern("uniform", n, seed=8)
     rng = np.random.default_rng(9)
     x[rng.random(n) < 0.6] = 0.5
     t, rep = _learned(gs, x, sample_size=16384)
+    assert rep["fallback"] == 2 and rep["max_bucket"] > (1 << 20)
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+    t, rep = _learned(gs, x, sample_size=16384, judge=1)
     assert rep["fallback"] == 1 and rep["overflow_buckets"] > 0
     assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
+@pytest.mark.parametrize("pattern", ["gaussmix", "zipf_ints"])
+def test_learned_judged_at_full_size(gs, orc, pattern):
+    """At 2^26 keys the trained table leaves these inputs' buckets too uneven
+    (a Gaussian component narrower than the knots resolve; one integer
+    holding about a tenth of the keys): the sample says so and the plain
+    path sorts; the result is still the definition's."""
+    torch = need_gpu()
+    n = 1 << 26
+    announce("learned judged", pattern, n)
+    x = W.learned_pattern(pattern, n, seed=0)
+    t, rep = _learned(gs, x)
+    assert rep["fallback"] in (0, 2)
+    if pattern == "zipf_ints":
+        assert rep["fallback"] == 2
+    h = multiset_hash_dev(torch.from_numpy(x).to("cuda"))
+    assert multiset_hash_dev(t) == h
+    assert bool((t[1:] >= t[:-1]).all().item())
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([[0, n - 1], rng.integers(0, n, 14)])
+    got = t[torch.from_numpy(orc.rank_f64(x, idx)).to("cuda")].cpu().numpy()
+    assert np.array_equal(bits(got), bits(x[idx]))
 
 
 def test_learned_degenerate_all_equal(gs, orc):
@@ -224,3 +253,37 @@ def test_learned_gain_over_untrained(gs):
     avg = (1 << 22) / 2 / 4096
     assert trained["max_bucket"] < 0.5 * untrained["max_bucket"]
     assert trained["max_bucket"] < 4 * avg
+
+
+@pytest.mark.parametrize("pattern,n", [("lognormal", 1 << 20), ("zipf_ints", 1 << 24)])
+def test_learned_graph_capture(gs, orc, pattern, n):
+    """Captured into a graph, the call keeps its decision on the device (both
+    paths enqueued, gated); every replay on a freshly restored input gives
+    the definition's result."""
+    torch = need_gpu()
+    announce("learned capture", pattern, n)
+    x = W.learned_pattern(pattern, n, seed=12)
+    src = to_dev(x)
+    t = torch.empty_like(src)
+    p = gs.gs_learned_default_params()
+    p.sample_size = 16384
+    need = gs.gs_workspace_bytes_learned(n, p)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    ws = ws[(-ws.data_ptr()) % 256:][:need]
+    t.copy_(src)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        g.capture_begin()
+        try:
+            gs.gs_learned_sort(t, p, workspace=ws, stream=s)
+        finally:
+            g.capture_end()
+    ref = bits(orc.sort_f64(x))
+    for _ in range(3):
+        t.copy_(src)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(t), ref)

@@ -1034,69 +1034,91 @@ static void launch_reverse(K *keys, V *vals, int64_t n, hipStream_t st, Gate gat
 }
 
 // ---------------------------------------------------------------------------
-// input already in order, or exactly reversed
+// input already in order, or reversed
 // ---------------------------------------------------------------------------
 // "Octosort", "Squidsort": bi-adaptive to presorted and reverse-sorted input.
 // Before the tree runs, the call decides on the device whether the keys are
 // already in the sort's order (every neighbour pair non-decreasing: nothing
-// to do) or strictly reversed (every pair strictly decreasing: the result is
-// the reversal, and no ties can occur); anything else is sorted.  4096
-// sampled pairs decide first, so unsorted input pays one small launch; the
-// pass over every pair runs only when the sample finds no counter-example.
-// The decision (word 0) gates every later launch of the call; word 1 holds
-// the orders still possible (bit 0 in order, bit 1 reversed).
+// to do) or reversed (every pair strictly decreasing, or -- keys without
+// values only -- non-increasing with every tie between bit-identical keys,
+// i.e. no NaN and no zero: either way the reversal is the stable result);
+// anything else is sorted.  4096 sampled pairs decide first, so unsorted
+// input pays one small launch; the pass over every pair runs only when the
+// sample finds no counter-example.  The decision (word 0) gates every later
+// launch of the call; word 1 holds the properties still possible: bit 0 in
+// order, bit 1 strictly decreasing, bit 2 non-increasing, bit 3 no key whose
+// ties could differ in their bits.
 template <class KT>
-__global__ __launch_bounds__(256) void order_sample_kernel(const typename KT::T *keys, int64_t n, unsigned *word)
+__device__ __forceinline__ unsigned order_bits(typename KT::T a, typename KT::T b)
+{
+    return (!KT::less(b, a) ? 1u : 0u) | (KT::less(b, a) ? 2u : 0u) | (!KT::less(a, b) ? 4u : 0u) |
+           (!tie_bits_may_differ(a) && !tie_bits_may_differ(b) ? 8u : 0u);
+}
+
+template <class KT>
+__device__ __forceinline__ unsigned order_decisive(unsigned bits, bool keys_only)
+{
+    // the properties that still decide something
+    const bool rev_ties = keys_only && (bits & 4u) && (bits & 8u);
+    return (bits & 1u) || (bits & 2u) || rev_ties;
+}
+
+template <class KT>
+__global__ __launch_bounds__(256) void order_sample_kernel(const typename KT::T *keys, int64_t n, unsigned *word,
+                                                           int keys_only)
 {
     const int64_t m = n - 1;             // pairs
-    bool asc = true, desc = true;
+    unsigned bits = 15u;
     for (int j = threadIdx.x; j < 4096; j += 256) {
         const int64_t i = (int64_t)j * m / 4096;
-        const auto a = keys[i], b = keys[i + 1];
-        asc = asc && !KT::less(b, a);
-        desc = desc && KT::less(b, a);
+        bits &= order_bits<KT>(keys[i], keys[i + 1]);
     }
-    asc = __syncthreads_and(asc) != 0;
-    desc = __syncthreads_and(desc) != 0;
+    __shared__ unsigned s_bits;
+    if (threadIdx.x == 0) s_bits = 15u;
+    __syncthreads();
+    atomicAnd(&s_bits, bits);
+    __syncthreads();
     if (threadIdx.x == 0) {
-        word[1] = (asc ? 1u : 0u) | (desc ? 2u : 0u);
-        word[0] = (asc || desc) ? (unsigned)ORD_CANDIDATE : (unsigned)ORD_SORT;
+        word[1] = s_bits;
+        word[0] = order_decisive<KT>(s_bits, keys_only != 0) ? (unsigned)ORD_CANDIDATE : (unsigned)ORD_SORT;
     }
 }
 
 template <class KT>
-__global__ __launch_bounds__(256) void order_check_kernel(const typename KT::T *keys, int64_t n, unsigned *word)
+__global__ __launch_bounds__(256) void order_check_kernel(const typename KT::T *keys, int64_t n, unsigned *word,
+                                                          int keys_only)
 {
     if (word[0] != ORD_CANDIDATE) return;
-    const unsigned possible = word[1];
-    bool asc = (possible & 1u) != 0, desc = (possible & 2u) != 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n - 1 && (asc || desc);
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const auto a = keys[i], b = keys[i + 1];
-        asc = asc && !KT::less(b, a);
-        desc = desc && KT::less(b, a);
-    }
-    asc = __syncthreads_and(asc) != 0;
-    desc = __syncthreads_and(desc) != 0;
-    if (threadIdx.x == 0) {
-        if (!asc) atomicAnd(word + 1, ~1u);
-        if (!desc) atomicAnd(word + 1, ~2u);
-    }
+    unsigned bits = word[1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+         i < n - 1 && order_decisive<KT>(bits, keys_only != 0); i += (int64_t)gridDim.x * blockDim.x)
+        bits &= order_bits<KT>(keys[i], keys[i + 1]);
+    __shared__ unsigned s_bits;
+    if (threadIdx.x == 0) s_bits = 15u;
+    __syncthreads();
+    atomicAnd(&s_bits, bits);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_bits != 15u) atomicAnd(word + 1, s_bits);
 }
 
-__global__ void order_decide_kernel(unsigned *word)
+__global__ void order_decide_kernel(unsigned *word, int keys_only)
 {
-    if (word[0] == ORD_CANDIDATE)
-        word[0] = (word[1] & 1u) ? (unsigned)ORD_IN_ORDER : (word[1] & 2u) ? (unsigned)ORD_REVERSED : (unsigned)ORD_SORT;
+    if (word[0] != ORD_CANDIDATE) return;
+    const unsigned b = word[1];
+    word[0] = (b & 1u)                                        ? (unsigned)ORD_IN_ORDER
+              : ((b & 2u) || (keys_only && (b & 4u) && (b & 8u))) ? (unsigned)ORD_REVERSED
+                                                                : (unsigned)ORD_SORT;
 }
 
 template <class KT>
-static void launch_order_check(const typename KT::T *keys, int64_t n, unsigned *word, hipStream_t st)
+static void launch_order_check(const typename KT::T *keys, int64_t n, unsigned *word, bool keys_only,
+                               hipStream_t st)
 {
-    hipLaunchKernelGGL((order_sample_kernel<KT>), dim3(1), dim3(256), 0, st, keys, n, word);
+    const int ko = keys_only ? 1 : 0;
+    hipLaunchKernelGGL((order_sample_kernel<KT>), dim3(1), dim3(256), 0, st, keys, n, word, ko);
     hipLaunchKernelGGL((order_check_kernel<KT>), dim3(grid_for(n - 1, 256, 8192)), dim3(256), 0, st, keys, n,
-                       word);
-    hipLaunchKernelGGL(order_decide_kernel, dim3(1), dim3(1), 0, st, word);
+                       word, ko);
+    hipLaunchKernelGGL(order_decide_kernel, dim3(1), dim3(1), 0, st, word, ko);
 }
 
 // One stable sort with its order check: KT is the key order the tree sorts
@@ -1107,7 +1129,7 @@ static hipError_t run_sort_adaptive(typename KT::T *keys, V *vals, int64_t n, ch
 {
     if (n <= 1) return hipSuccess;
     unsigned *word = (unsigned *)(ws + p.off_order);
-    launch_order_check<KT>(keys, n, word, st);
+    launch_order_check<KT>(keys, n, word, !ValOps<V>::has, st);
     hipError_t e = run_sort<KT, V>(keys, vals, n, ws, p, st, Gate{word, (unsigned)ORD_SORT});
     if (e != hipSuccess) return e;
     launch_reverse(keys, vals, n, st, Gate{word, (unsigned)ORD_REVERSED});

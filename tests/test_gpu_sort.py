@@ -166,7 +166,9 @@ def _order_cases(n, seed):
                                                      np.full(max(n - 11, 0), np.inf), [np.nan, np.nan, np.nan]]), 1),
         "strictly reversed": (base[::-1].copy(), 2),
         "strictly reversed, NaN first": (np.concatenate([[np.nan], base[::-1]]), 2),
-        "reversed with ties": (ties[::-1].copy(), 0),
+        "reversed with ties, zeros among them": (ties[::-1].copy(), 0),
+        # equal keys bit for bit equal: the reversal is the stable result
+        "reversed with ties, no zero or NaN": ((ties + 1.0)[::-1].copy(), 2),
         "two NaNs then reversed": (np.concatenate([[np.nan, np.nan], base[::-1]]), 0),
     }
     # one inversion between two sampled pairs (the sample sees pairs at
@@ -204,8 +206,11 @@ def test_order_fast_paths_kv(gs, orc):
     n = 300_001
     rng = np.random.default_rng(3)
     base = np.sort(rng.integers(0, 1 << 62, n, dtype=np.int64).astype(np.uint64))
+    ties = np.sort(rng.integers(1, 9, n).astype(np.uint64))
     for name, k, want in (("in order", base, 1), ("strictly reversed", base[::-1].copy(), 2),
-                          ("in order, ties", np.sort(rng.integers(0, 9, n).astype(np.uint64)), 1)):
+                          ("in order, ties", ties, 1),
+                          # the payload shows the order of ties: no reversal shortcut
+                          ("reversed with ties", ties[::-1].copy(), 0)):
         announce("order kv", name)
         v = np.arange(n, dtype=np.uint32)
         tk = to_dev(k.view(np.int64))

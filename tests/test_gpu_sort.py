@@ -231,3 +231,35 @@ def test_order_fast_paths_small_buffer(gs, orc, algo, p):
         rep = gs.gs_sort_f64(t, buffer_fraction=p, algo=algo, sub_fraction=0.25, report=True)
         assert np.array_equal(bits(t), bits(orc.sort_f64(x))), name
         assert rep["order"] == want, name
+
+
+def test_concurrent_streams(gs, orc):
+    """Calls on different streams with different workspaces run at the same
+    time: a plain sort, a Frogsort3 sort (with its table upload) and a
+    key/value sort, each on its own stream, all bit for bit right."""
+    torch = need_gpu()
+    n = 3_000_017
+    announce("concurrent streams", n)
+    xs = [W.f64_pattern("uniform", n, seed=s) for s in (31, 32)]
+    k, v = W.kv_pattern("few", n, seed=33)
+    ts = [to_dev(x) for x in xs]
+    tk, tv = to_dev(k.view(np.int64)), to_dev(v.view(np.int32))
+    streams = [torch.cuda.Stream() for _ in range(3)]
+
+    def ws(nbytes):
+        w = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        return w[(-w.data_ptr()) % 256:][:nbytes]
+    w0 = ws(gs.gs_workspace_bytes_f64(n))
+    w1 = ws(gs.gs_workspace_bytes_f64(n, 0.2))
+    w2 = ws(gs.gs_workspace_bytes_kv(n))
+    torch.cuda.synchronize()
+    for _ in range(2):
+        gs.gs_sort_f64(ts[0], workspace=w0, stream=streams[0])
+        gs.gs_sort_f64(ts[1], 0.2, workspace=w1, stream=streams[1])
+        gs.gs_sort_kv(tk, tv, workspace=w2, stream=streams[2])
+    torch.cuda.synchronize()
+    for t, x in zip(ts, xs):
+        assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+    rk, rv = orc.sort_kv(k, v)
+    assert np.array_equal(tk.cpu().numpy().view(np.uint64), rk)
+    assert np.array_equal(tv.cpu().numpy().view(np.uint32), rv)

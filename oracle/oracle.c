@@ -510,7 +510,7 @@ int64_t oracle_frog_geometry(int64_t n, int depth, int64_t *out)
  * order) to their data slots, at the left end of the region for a left leaf and
  * at the right end for a right leaf, where a stable insertion sort orders them.
  * With q = 32768 and leaf_max = 1 this is the Frogsort1 model above, step for
- * step ("Frogsort1 is a special case of Frogsort2 at p = 0.5").
+ * step (the paper notes Frogsort1 is Frogsort2 with p = 0.5).
  *
  * The model checks that the buffer suffices: a write to a slot that still holds
  * an element nobody has read sets bit 0 of `bad`; an empty inner child sets

@@ -287,7 +287,7 @@ F2_QS = [1024, 3277, 6553, 13107, 16384, 21845, 29491, 32767, 32768]
 
 @pytest.mark.parametrize("n", list(range(1, 40)) + [100, 255, 1000, 1023])
 def test_frog2_half_is_frogsort1(orc, n):
-    """"Frogsort1 is a special case of Frogsort2 at p = 0.5": with q = 32768
+    """The paper notes that Frogsort1 is Frogsort2 with p = 0.5: with q = 32768
     and one-element leaves the Frogsort2 model places, compares and moves
     exactly as the Frogsort1 model, merge for merge."""
     rng = np.random.default_rng(7000 + n)
@@ -483,7 +483,7 @@ def test_frog3_presorted_counts(orc, q):
 @pytest.mark.parametrize("q2", [6553, 16384, 21845])
 @pytest.mark.parametrize("n", [100, 1000, 4097])
 def test_frog6_with_enough_buffer_is_frogsort2(orc, q2, n):
-    """"Frogsorts 1, 2, 3 are special cases of Frogsort6": when the shared
+    """Frogsort1, 2 and 3 are instances of Frogsort6 ("Frogsort3 and 6"): when the shared
     buffer already covers the whole tree's Frogsort2 buffer (p3 >= p2), the
     sort is one Frogsort2 tree at p2, merge for merge."""
     rng = np.random.default_rng(q2 + n)

@@ -92,9 +92,9 @@ typedef struct {
     float    lr;             /* Adam learning rate; default 2e-2 */
     uint64_t seed;           /* sample positions, weight init and minibatches */
     uint32_t mode;           /* 0 = trained network, 1 = untrained linear CDF (table[i] = i/knots) */
-    uint32_t judge;          /* 0 = trained mode lets the plain path judge the table on the
+    uint32_t screen;         /* 0 = trained mode lets the plain path screen the table on the
                                 sample before any key moves (default); 1 = skip that early
-                                judgment (the checks on the full bucket totals still apply) */
+                                screening (the checks on the full bucket totals still apply) */
     const float *weights_override;    /* device, 4353 floats: skip training, use these weights; may be NULL */
     const float *test_bucket_table;   /* device, `knots`+1 floats: raw table, bypasses the running max
                                          (test hook to force an order violation); may be NULL */

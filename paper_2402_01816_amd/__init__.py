@@ -68,7 +68,7 @@ class GsLearnedParams(ctypes.Structure):
         ("lr", ctypes.c_float),
         ("seed", ctypes.c_uint64),
         ("mode", ctypes.c_uint32),
-        ("judge", ctypes.c_uint32),
+        ("screen", ctypes.c_uint32),
         ("weights_override", ctypes.c_void_p),
         ("test_bucket_table", ctypes.c_void_p),
     ]

@@ -673,7 +673,7 @@ static gs_status check_learned_params(const gs_learned_params &p)
     if (p.knots < 2 || p.knots > 16384) return fail(GS_EINVAL, "knots out of [2, 16384]");
     if (p.batch < 32 || p.batch % 32 || p.batch > 8192) return fail(GS_EINVAL, "batch must be a multiple of 32 in [32, 8192]");
     if (p.mode > 1) return fail(GS_EINVAL, "mode must be 0 or 1");
-    if (p.judge > 1) return fail(GS_EINVAL, "judge must be 0 or 1");
+    if (p.screen > 1) return fail(GS_EINVAL, "screen must be 0 or 1");
     if (!(p.lr > 0.f) || !(p.lr < 1.f)) return fail(GS_EINVAL, "lr out of (0, 1)");
     if (p.train_steps > 100000) return fail(GS_EINVAL, "train_steps above 100000");
     return GS_OK;

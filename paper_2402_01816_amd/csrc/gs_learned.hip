@@ -53,14 +53,14 @@ constexpr int L_BAR = 4;                 // training grid barrier
 constexpr int L_ERR = 5;
 constexpr int L_BIGB = 6;                // buckets larger than one LDS tile
 constexpr int L_FEAT = 7;                // chosen feature
-constexpr int L_JUDGED = 8;              // the sample predicted too uneven buckets
+constexpr int L_SCREENED = 8;              // the sample predicted too uneven buckets
 
-// The plain path judges the learned form before any key moves: a bucket
-// predicted (from the sample, scaled to a half) above max(kJudgeMin, 16 x the
+// The plain path screens the learned form before any key moves: a bucket
+// predicted (from the sample, scaled to a half) above max(kScreenMin, 16 x the
 // average bucket) means the network did not spread the keys well enough for
 // the bucket sorts to beat the merge passes they replace.
-constexpr int64_t kJudgeMin = (int64_t)1 << 19;
-constexpr int64_t kJudgeSkew = 16;
+constexpr int64_t kScreenMin = (int64_t)1 << 19;
+constexpr int64_t kScreenSkew = 16;
 
 __device__ __forceinline__ uint64_t mix64d(uint64_t z)
 {
@@ -313,7 +313,7 @@ constexpr int SW_TILE = SW_NT * SW_ROUNDS;           // 4096 keys
 // The sorted sample through the trained knot table: its largest bucket,
 // scaled to a half of the input, decides whether the call goes on with the
 // learned form or takes the plain path at once.
-__global__ __launch_bounds__(1024) void learned_judge_kernel(const double *sample, int64_t S, const Feature *feat,
+__global__ __launch_bounds__(1024) void learned_screen_kernel(const double *sample, int64_t S, const Feature *feat,
                                                              const float *tab, int G, int B, int64_t half,
                                                              unsigned *ctrl)
 {
@@ -337,9 +337,9 @@ __global__ __launch_bounds__(1024) void learned_judge_kernel(const double *sampl
     if (tid == 0) {
         const int64_t predicted = (int64_t)s_max * half / S;
         const int64_t avg = half / B;
-        const int64_t limit = kJudgeSkew * avg > kJudgeMin ? kJudgeSkew * avg : kJudgeMin;
+        const int64_t limit = kScreenSkew * avg > kScreenMin ? kScreenSkew * avg : kScreenMin;
         if (predicted > limit) {
-            ctrl[L_JUDGED] = 1u;
+            ctrl[L_SCREENED] = 1u;
             ctrl[L_MAXB] = (unsigned)(predicted < 0xffffffffll ? predicted : 0xffffffffll);
             ctrl[L_FALLBACK] = 1u;
         }
@@ -726,11 +726,11 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     if (tr) trace_end(st);
     hipLaunchKernelGGL(learned_table_kernel, dim3(1), dim3(1024), 0, st, (const float *)raw, prm.test_bucket_table,
                        (int)prm.mode, G, tab, ctrl, (const Feature *)feat);
-    if (prm.mode == 0 && !prm.test_bucket_table && prm.judge == 0) {
+    if (prm.mode == 0 && !prm.test_bucket_table && prm.screen == 0) {
         const size_t jlds = (size_t)(G + 1) * 4 + (size_t)B * 4;
-        (void)hipFuncSetAttribute((const void *)learned_judge_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void *)learned_screen_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)jlds);
-        hipLaunchKernelGGL(learned_judge_kernel, dim3(1), dim3(1024), jlds, st, (const double *)sample, L.S,
+        hipLaunchKernelGGL(learned_screen_kernel, dim3(1), dim3(1024), jlds, st, (const double *)sample, L.S,
                            (const Feature *)feat, (const float *)tab, G, B, n - n / 2, ctrl);
     }
     // Unless the stream is being captured, the host reads the decision once
@@ -849,7 +849,7 @@ hipError_t learned_read_report(const char *ws, const LearnedPlan &L, LearnedRepo
     hipError_t e = hipMemcpy(c, ws + L.off_ctrl, sizeof c, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(loss, ws + L.off_losses, sizeof loss, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return e;
-    r->fallback = c[L_FALLBACK] ? (c[L_JUDGED] ? 2u : 1u) : 0u;
+    r->fallback = c[L_FALLBACK] ? (c[L_SCREENED] ? 2u : 1u) : 0u;
     r->order_violation = c[L_ORDER];
     r->overflow_buckets = c[L_OVERFLOW];
     r->max_bucket = c[L_MAXB];

@@ -187,7 +187,7 @@ def test_learned_fallback_on_overflow(gs, orc):
     """One key value holding 60% of a 2^22-key input puts more than the bucket
     limit (2^20) into one bucket of each half.  The sample predicts it, so the
     plain path takes the call before any key moves (fallback 2); with that
-    early judgment off, the check on the full bucket totals catches it
+    early screening off, the check on the full bucket totals catches it
     (fallback 1).  Either way the result is the plain sort's."""
     announce("learned fallback overflow")
     n = 1 << 22
@@ -197,20 +197,20 @@ def test_learned_fallback_on_overflow(gs, orc):
     t, rep = _learned(gs, x, sample_size=16384)
     assert rep["fallback"] == 2 and rep["max_bucket"] > (1 << 20)
     assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
-    t, rep = _learned(gs, x, sample_size=16384, judge=1)
+    t, rep = _learned(gs, x, sample_size=16384, screen=1)
     assert rep["fallback"] == 1 and rep["overflow_buckets"] > 0
     assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
 
 
 @pytest.mark.parametrize("pattern", ["gaussmix", "zipf_ints"])
-def test_learned_judged_at_full_size(gs, orc, pattern):
+def test_learned_screened_at_full_size(gs, orc, pattern):
     """At 2^26 keys the trained table leaves these inputs' buckets too uneven
     (a Gaussian component narrower than the knots resolve; one integer
     holding about a tenth of the keys): the sample says so and the plain
     path sorts; the result is still the definition's."""
     torch = need_gpu()
     n = 1 << 26
-    announce("learned judged", pattern, n)
+    announce("learned screened", pattern, n)
     x = W.learned_pattern(pattern, n, seed=0)
     t, rep = _learned(gs, x)
     assert rep["fallback"] in (0, 2)

@@ -75,10 +75,10 @@ __device__ __forceinline__ uint64_t mix64d(uint64_t z)
 // comparison: -0 and +0 map together, every NaN maps to the maximum.
 __device__ __forceinline__ uint64_t ckey(double x)
 {
-    if (x != x) return ~0ull;
     uint64_t u = (uint64_t)__double_as_longlong(x);
-    if ((u << 1) == 0) u = 0;
-    return (u >> 63) ? ~u : (u | (1ull << 63));
+    u = (u << 1) == 0 ? 0ull : u;
+    const uint64_t m = (u >> 63) ? ~u : (u | (1ull << 63));
+    return x != x ? ~0ull : m;
 }
 
 __device__ __forceinline__ double phi_of(double x, const Feature &F)
@@ -116,6 +116,46 @@ __device__ __forceinline__ int bucket_of(double x, const Feature &F, const float
     int bk = (int)(v * (float)B);
     bk = bk < 0 ? 0 : (bk > B - 1 ? B - 1 : bk);
     return x != x ? B - 1 : bk;
+}
+
+// bucket_of for N keys at once, step for step the same arithmetic: every
+// knot coordinate first, then all table reads, then the interpolations, so
+// that the keys' LDS reads are in flight together.
+template <int N>
+__device__ __forceinline__ void buckets_of(const double *x, int *bk, const Feature &F, const float *tab, int G, int B)
+{
+    float uc[N];
+    if (F.bits) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const uint64_t k = ckey(x[r]);
+            const uint64_t dk = k > F.klo ? k - F.klo : 0ull;
+            const float u = (float)((double)dk * F.kscale);
+            uc[r] = fminf(fmaxf(u, 0.f), (float)G);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const float u = (float)((x[r] - F.lo) * F.scale);
+            uc[r] = fminf(fmaxf(u, 0.f), (float)G);
+        }
+    }
+    int ix[N];
+    float a[N], b[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        ix[r] = min((int)uc[r], G - 1);
+        a[r] = tab[ix[r]];
+        b[r] = tab[ix[r] + 1];
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        const float f = uc[r] - (float)ix[r];
+        const float v = fminf(fmaf(f, b[r] - a[r], a[r]), b[r]);
+        int k = (int)(v * (float)B);
+        k = k < 0 ? 0 : (k > B - 1 ? B - 1 : k);
+        bk[r] = x[r] != x[r] ? B - 1 : k;
+    }
 }
 
 }  // namespace
@@ -307,8 +347,24 @@ __global__ __launch_bounds__(1024) void learned_table_kernel(const float *raw, c
 // added into totals[] with integer atomics at the end (the totals do not
 // depend on the order of the additions).
 constexpr int SW_NT = 256;
-constexpr int SW_ROUNDS = 16;
-constexpr int SW_TILE = SW_NT * SW_ROUNDS;           // 4096 keys
+// work-groups of a distribution pass (each walks tiles with a stride of the grid)
+#ifndef GS_LEARN_SGRID
+#define GS_LEARN_SGRID 1024
+#endif
+// work-groups of a counting pass
+#ifndef GS_LEARN_CGRID
+#define GS_LEARN_CGRID 1024
+#endif
+#ifndef GS_LEARN_ROUNDS
+#define GS_LEARN_ROUNDS 16
+#endif
+constexpr int SW_ROUNDS = GS_LEARN_ROUNDS;
+constexpr int SW_TILE = SW_NT * SW_ROUNDS;           // 4096 keys by default
+// waves per SIMD the distribution pass's registers are sized for: as many
+// work-groups as its LDS (knot table + staged tile) lets a compute unit hold
+#ifndef GS_LEARN_SCATTER_WAVES
+#define GS_LEARN_SCATTER_WAVES (SW_ROUNDS >= 16 ? 2 : SW_ROUNDS >= 12 ? 3 : 4)
+#endif
 
 // The sorted sample through the trained knot table: its largest bucket,
 // scaled to a half of the input, decides whether the call goes on with the
@@ -346,7 +402,7 @@ __global__ __launch_bounds__(1024) void learned_screen_kernel(const double *samp
     }
 }
 
-__global__ __launch_bounds__(SW_NT) void learned_count_kernel(const double *src, int64_t len, const Feature *feat,
+__global__ __launch_bounds__(SW_NT, 4) void learned_count_kernel(const double *src, int64_t len, const Feature *feat,
                                                               const float *tab, int G, int B, int shift, int dbits,
                                                               unsigned *tilecnt, unsigned *totals,
                                                               const unsigned *ctrl)
@@ -363,22 +419,34 @@ __global__ __launch_bounds__(SW_NT) void learned_count_kernel(const double *src,
     for (int i = tid; i <= G; i += SW_NT) s_tab[i] = tab[i];
     if (totals)
         for (int i = tid; i < B; i += SW_NT) s_tot[i] = 0u;
+    // keys of tile t (indices past the input read its last key)
+    double x[SW_ROUNDS];
+    auto load_tile = [&](int64_t t) {
+        const double *p = src + t * SW_TILE + tid;
+        if ((t + 1) * SW_TILE <= len) {
+#pragma unroll
+            for (int r = 0; r < SW_ROUNDS; ++r) x[r] = p[r * SW_NT];
+        } else {
+#pragma unroll
+            for (int r = 0; r < SW_ROUNDS; ++r) {
+                const int64_t i = t * SW_TILE + r * SW_NT + tid;
+                x[r] = src[i < len ? i : len - 1];
+            }
+        }
+    };
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        load_tile(t);
         if (tid < 64) s_dc[tid] = 0u;
         __syncthreads();
         const int64_t base = t * SW_TILE;
-        double x[SW_ROUNDS];
-#pragma unroll
-        for (int r = 0; r < SW_ROUNDS; ++r) {
-            const int64_t i = base + r * SW_NT + tid;
-            x[r] = src[i < len ? i : len - 1];
-        }
+        int bk[SW_ROUNDS];
+        buckets_of<SW_ROUNDS / 2>(x, bk, F, s_tab, G, B);    // two halves: fewer live registers
+        buckets_of<SW_ROUNDS / 2>(x + SW_ROUNDS / 2, bk + SW_ROUNDS / 2, F, s_tab, G, B);
 #pragma unroll
         for (int r = 0; r < SW_ROUNDS; ++r) {
             if (base + r * SW_NT + tid < len) {
-                const int b = bucket_of(x[r], F, s_tab, G, B);
-                atomicAdd(&s_dc[(b >> shift) & (D - 1)], 1u);
-                if (totals) atomicAdd(&s_tot[b], 1u);
+                atomicAdd(&s_dc[(bk[r] >> shift) & (D - 1)], 1u);
+                if (totals) atomicAdd(&s_tot[bk[r]], 1u);
             }
         }
         __syncthreads();
@@ -497,7 +565,7 @@ __global__ __launch_bounds__(1024) void learned_bucket_scan_kernel(const unsigne
 // equals.  The tile then stages its keys in LDS grouped by digit and writes
 // every digit's run contiguously at the tile's offset for that digit (from
 // the tile scan).  The rank scratch shares LDS with the staging area.
-__global__ __launch_bounds__(SW_NT) void learned_scatter_kernel(const double *src, double *dst, int64_t len,
+__global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter_kernel(const double *src, double *dst, int64_t len,
                                                                 const Feature *feat, const float *tab, int G, int B,
                                                                 int shift, int dbits, const unsigned *tileoff,
                                                                 const unsigned *ctrl)
@@ -518,34 +586,51 @@ __global__ __launch_bounds__(SW_NT) void learned_scatter_kernel(const double *sr
     unsigned long long *wm = (unsigned long long *)s_key + wave * (SW_ROUNDS * 64);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int i = tid; i <= G; i += SW_NT) s_tab[i] = tab[i];
+    // tile t's destination of every digit (thread d < D holds digit d's),
+    // then a wave's keys of the tile (indices past the input read its last
+    // key)
+    double x[SW_ROUNDS];
+    unsigned goff = 0u;
+    auto load_tile = [&](int64_t t) {
+        if (tid < D) goff = tileoff[(int64_t)tid * ntiles + t];
+        const int64_t base = t * SW_TILE + (int64_t)wave * (SW_TILE / 4);
+        if ((t + 1) * SW_TILE <= len) {
+            const double *q = src + base + lane;
+#pragma unroll
+            for (int r = 0; r < SW_ROUNDS; ++r) x[r] = q[r * 64];
+        } else {
+#pragma unroll
+            for (int r = 0; r < SW_ROUNDS; ++r) {
+                const int64_t p = base + r * 64 + lane;
+                x[r] = src[p < len ? p : len - 1];
+            }
+        }
+    };
+    if ((int64_t)blockIdx.x < ntiles) load_tile(blockIdx.x);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * SW_TILE + (int64_t)wave * (SW_TILE / 4);
-        double x[SW_ROUNDS];
-#pragma unroll
-        for (int r = 0; r < SW_ROUNDS; ++r) {
-            const int64_t p = base + r * 64 + lane;
-            x[r] = src[p < len ? p : len - 1];
-        }
 #pragma unroll
         for (int r = 0; r < SW_ROUNDS; ++r) wm[r * 64 + lane] = 0ull;
-        if (tid < D) s_goff[tid] = tileoff[(int64_t)tid * ntiles + t];
+        if (tid < D) s_goff[tid] = goff;
         __syncthreads();
         int dg[SW_ROUNDS];
+        buckets_of<SW_ROUNDS>(x, dg, F, s_tab, G, B);
 #pragma unroll
         for (int r = 0; r < SW_ROUNDS; ++r) {
             const bool valid = base + r * 64 + lane < len;
-            dg[r] = valid ? ((bucket_of(x[r], F, s_tab, G, B) >> shift) & (D - 1)) : -1;
+            dg[r] = valid ? ((dg[r] >> shift) & (D - 1)) : -1;
         }
         // lanes of a round with equal digits: each sets its bit in the digit's
         // mask (bitwise or, so the order of the updates does not matter)
+        // (a key past the input sets no bit: it ors 0 into digit 0's mask)
 #pragma unroll
         for (int r = 0; r < SW_ROUNDS; ++r)
-            if (dg[r] >= 0) atomicOr(&wm[r * 64 + dg[r]], 1ull << lane);
+            atomicOr(&wm[r * 64 + (dg[r] >= 0 ? dg[r] : 0)], dg[r] >= 0 ? 1ull << lane : 0ull);
         __builtin_amdgcn_wave_barrier();
         unsigned rk[SW_ROUNDS];
 #pragma unroll
         for (int r = 0; r < SW_ROUNDS; ++r)
-            rk[r] = dg[r] >= 0 ? (unsigned)__popcll(wm[r * 64 + dg[r]] & below) : 0u;
+            rk[r] = (unsigned)__popcll(wm[r * 64 + (dg[r] >= 0 ? dg[r] : 0)] & below);
         unsigned cnt[SW_ROUNDS];
 #pragma unroll
         for (int r = 0; r < SW_ROUNDS; ++r) cnt[r] = (unsigned)__popcll(wm[r * 64 + lane]);   // lane = digit
@@ -561,8 +646,7 @@ __global__ __launch_bounds__(SW_NT) void learned_scatter_kernel(const double *sr
         }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int r = 0; r < SW_ROUNDS; ++r)
-            if (dg[r] >= 0) rk[r] += (unsigned)wm[r * 64 + dg[r]];
+        for (int r = 0; r < SW_ROUNDS; ++r) rk[r] += (unsigned)wm[r * 64 + (dg[r] >= 0 ? dg[r] : 0)];
         __syncthreads();
         if (tid < 64) {
             const int d = tid;
@@ -589,6 +673,8 @@ __global__ __launch_bounds__(SW_NT) void learned_scatter_kernel(const double *sr
                 s_dig[pos] = (unsigned char)dg[r];
             }
         }
+        // the keys are staged: load the next tile while this one is written
+        if (t + gridDim.x < ntiles) load_tile(t + gridDim.x);
         __syncthreads();
         const int64_t rem = len - t * SW_TILE;
         const int nvalid = rem < SW_TILE ? (int)rem : SW_TILE;
@@ -638,7 +724,7 @@ LearnedPlan plan_learned(int64_t n, const gs_learned_params &prm)
     }
     const int64_t half = n - n / 2;
     L.limit = half / 4 > kBucketLimit ? half / 4 : kBucketLimit;
-    L.ntiles = (half + 4095) / 4096;
+    L.ntiles = (half + SW_TILE - 1) / SW_TILE;        // tiles of the larger half
     L.splan = plan_f64(L.S);
     L.off_sample = o; o = al256(o + L.S * 8);
     L.off_sample_ws = o; o = al256(o + L.splan.bytes);
@@ -755,6 +841,7 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     const int64_t nA = n / 2, nB = n - nA;                 // first and second half
     const int lbits = bbits / 2, hbits = bbits - lbits;    // bucket id = (high << lbits) | low
     const int64_t tA = (nA + SW_TILE - 1) / SW_TILE, tB = (nB + SW_TILE - 1) / SW_TILE;
+    if (tA > L.ntiles || tB > L.ntiles) return hipErrorInvalidValue;   // the plan sized the tile counts
     unsigned *totals = (unsigned *)(ws + L.off_totals);
     unsigned *starts = (unsigned *)(ws + L.off_starts);
     unsigned *dstart = (unsigned *)(ws + L.off_dstart);
@@ -766,7 +853,7 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
                               (int)clds);
     (void)hipFuncSetAttribute((const void *)learned_scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)slds);
-    const unsigned cgrid = 1024;
+    const unsigned cgrid = GS_LEARN_CGRID;
     if (tr) trace_begin(TK_LEARN_BUCKET, st);
     launch_fill_u32(totals, 2 * (int64_t)B, 0u, st);
     hipLaunchKernelGGL(learned_count_kernel, dim3(cgrid), dim3(SW_NT), clds, st, (const double *)keys, nA,
@@ -785,7 +872,7 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     //    as frog buffer.  Second half first, then the first.
     auto distribute = [&](double *region, int64_t len, int64_t ntiles, unsigned *cnt, int h) {
         if (ntiles == 0) return;
-        const unsigned sgrid = (unsigned)(ntiles < 1024 ? ntiles : 1024);
+        const unsigned sgrid = (unsigned)(ntiles < GS_LEARN_SGRID ? ntiles : GS_LEARN_SGRID);
         hipLaunchKernelGGL(learned_tilescan_kernel, dim3(1u << lbits), dim3(1024), 0, st, cnt, ntiles,
                            (const unsigned *)(dstart + h * 128), (const unsigned *)ctrl);
         hipLaunchKernelGGL(learned_scatter_kernel, dim3(sgrid), dim3(SW_NT), slds, st,

@@ -225,6 +225,25 @@ def test_learned_screened_at_full_size(gs, orc, pattern):
     assert np.array_equal(bits(got), bits(x[idx]))
 
 
+def test_learned_full_size_lognormal(gs, orc):
+    """The learned workload at its full size, 2^28 lognormal(0, 2) keys: the
+    trained table spreads them (no fallback), and sortedness, the multiset and
+    sampled positions from the oracle's counting form fix the result."""
+    torch = need_gpu()
+    n = 1 << 28
+    announce("learned full", "lognormal", n)
+    x = W.learned_pattern("lognormal", n, seed=0)
+    t, rep = _learned(gs, x)
+    assert rep["fallback"] == 0
+    h = multiset_hash_dev(torch.from_numpy(x).to("cuda"))
+    assert multiset_hash_dev(t) == h
+    assert bool((t[1:] >= t[:-1]).all().item())
+    rng = np.random.default_rng(4)
+    idx = np.concatenate([[0, n - 1], rng.integers(0, n, 14)])
+    got = t[torch.from_numpy(orc.rank_f64(x, idx)).to("cuda")].cpu().numpy()
+    assert np.array_equal(bits(got), bits(x[idx]))
+
+
 def test_learned_degenerate_all_equal(gs, orc):
     announce("learned all equal")
     x = np.full(N_SMALL, 3.25)

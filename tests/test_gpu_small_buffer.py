@@ -148,6 +148,7 @@ def test_frog6_parity(gs, orc, p, p2, n):
     assert np.array_equal(tv.cpu().numpy().view(np.uint32), rv)
 
 
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")   # nothing may be recorded
 def test_small_buffer_rejects_capture(gs):
     """A small-buffer call uploads host-built tables, so it refuses to be
     recorded into a graph (and enqueues nothing)."""

@@ -117,6 +117,45 @@ def test_sort_f64_full_size_sampled(gs, orc, pattern):
     assert np.array_equal(bits(got), bits(x[idx]))
 
 
+KV_FULL_N = 1 << 29
+
+
+@pytest.mark.parametrize("pattern", ["uniform", "zipf"])
+def test_sort_kv_full_size(gs, orc, pattern):
+    """n = 2^29 key/value pairs with payload = input index.  Every output pair
+    is checked on the device: keys non-decreasing as unsigned integers, the
+    payload a permutation of the input indices that carries each key with it,
+    and equal keys in increasing payload order -- together exactly the
+    stable definition.  Sampled positions also come from the oracle's
+    counting form."""
+    torch = need_gpu()
+    n = KV_FULL_N
+    announce("sort_kv full", pattern, n)
+    k, v = W.kv_pattern(pattern, n, seed=0)
+    tk_in = to_dev(k.view(np.int64))
+    tk = tk_in.clone()
+    tv = to_dev(v.view(np.int32))
+    gs.gs_sort_kv(tk, tv)
+    torch.cuda.synchronize()
+    ks = tk ^ (-(1 << 63))               # unsigned order as signed order
+    assert bool((ks[1:] >= ks[:-1]).all().item())
+    del ks
+    vi = tv.to(torch.int64)
+    seen = torch.zeros(n, dtype=torch.bool, device="cuda")
+    seen[vi] = True
+    assert bool(seen.all().item())
+    del seen
+    assert torch.equal(tk_in[vi], tk)
+    bad = (tk[1:] == tk[:-1]) & (vi[1:] <= vi[:-1])
+    assert not bool(bad.any().item())
+    del bad, tk_in
+    rng = np.random.default_rng(2)
+    idx = np.concatenate([[0, n - 1], rng.integers(0, n, 6)])
+    ranks = orc.rank_u64(k, idx)
+    got = tv[torch.from_numpy(ranks).to("cuda")].cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, v[idx])
+
+
 TARGETS = ("AscLeft", "AscRight", "DescLeft", "DescRight")
 
 

@@ -1,6 +1,6 @@
 // Learned CDF bucket path (not part of the paper): the same stable ascending
-// result as the plain frog sort, with most merge levels replaced by one
-// bucketing scatter and per-bucket sorts.
+// result as the plain frog sort, with most merge levels replaced by two
+// stable 64-way distribution passes and per-bucket sorts.
 //
 //   1. sample keys at strided positions, sort the sample with the plain path;
 //   2. pick a monotone feature phi (linear in x, or linear in the key's
@@ -19,13 +19,17 @@
 //      than every key in a lower one; the table is checked for monotonicity
 //      before any key moves (a non-monotone table -- only possible through the
 //      test hook -- sends the call to the plain path on the untouched input);
-//   6. for the second half then the first half of the input: per-wave bucket
-//      counts, a stable ranked scatter into free memory, per-bucket sorts;
-//   7. one frog-style in-place merge of the two sorted halves into the input.
-// Memory stays at the half buffer: the second half is scattered into the half
-// buffer, sorted there using its own vacated input region as scratch; the
-// first half is scattered into that vacated region, sorted using its own
-// vacated region; the final merge writes bottom-up over the first half's run.
+//   6. bucket totals of both halves before any key moves (the overflow
+//      check sends the call to the plain path on the untouched input); then
+//      for the second half and then the first: per-tile digit counts, a
+//      stable pass by the bucket id's low digit into the half buffer and one
+//      by its high digit back, which leaves the half grouped by bucket in
+//      input order, and every bucket frog-sorted in place with the half
+//      buffer as its buffer;
+//   7. the sorted first half moves into the half buffer, and one frog merge
+//      (a right node: the second half is its outer run and stays or moves
+//      left) writes the output bottom-up.
+// Memory stays at the half buffer throughout.
 #include <hip/hip_runtime.h>
 
 #include "gs_block.h"

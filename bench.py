@@ -83,14 +83,40 @@ def _time_calls(torch, stream, fn, reps):
     return times[len(times) // 2]
 
 
-def extras(gs, torch, W, log2n, dev):
-    """Side measurements on the same device: the learned path against the plain
-    path on the learned workloads, the segmented sort against per-array plain
-    calls, and the key-value sort.  Medians of a few HIP-event timed reps."""
+SECTIONS = ("patterns", "learned", "segmented", "kv", "buffer")
+LEARNED_PATTERNS = ("lognormal", "gaussmix", "zipf_ints")
+LEARNED_CALLS = ("plain", "learned", "learned_untrained")
+KV_PATTERNS = ("uniform", "zipf")
+SEG_WORKLOADS = ("100k_arrays", "until_total_16_to_2^20")
+
+
+def extras(gs, torch, W, log2n, dev, sections=SECTIONS, learned_patterns=LEARNED_PATTERNS,
+           learned_calls=LEARNED_CALLS, kv_patterns=KV_PATTERNS, seg_workloads=SEG_WORKLOADS,
+           seg_per_array=True):
+    """Side measurements on the same device: the plain sort on the other input
+    patterns, the learned path against the plain path on the learned
+    workloads, the segmented sort against per-array plain calls, the
+    key-value sort and the smaller buffers.  Medians of a few HIP-event timed
+    reps.  `sections` (and the learned filters) choose a subset, e.g. to
+    profile one workload on its own."""
     stream = torch.cuda.current_stream(dev)
     n = 1 << log2n
     res = {}
-    # the plain sort on the other input patterns of the same size
+    if "patterns" in sections:
+        res["plain_patterns"] = _extras_patterns(gs, torch, W, n, dev, stream)
+    if "learned" in sections:
+        res["learned_vs_plain"] = _extras_learned(gs, torch, W, n, dev, stream, learned_patterns, learned_calls)
+    if "segmented" in sections:
+        res["segmented"] = _extras_segmented(gs, torch, W, n, dev, stream, seg_workloads, seg_per_array)
+    if "kv" in sections:
+        res["key_value"] = _extras_kv(gs, torch, W, log2n, dev, stream, kv_patterns)
+    if "buffer" in sections:
+        res["buffer_fraction"] = _extras_buffer(gs, torch, W, n, dev, stream)
+    return res
+
+
+def _extras_patterns(gs, torch, W, n, dev, stream):
+    """The plain sort on the other input patterns of the same size."""
     pats = {}
     need = gs.gs_workspace_bytes_f64(n)
     ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
@@ -110,17 +136,23 @@ def extras(gs, torch, W, log2n, dev):
         pats[pat] = {"ms": round(ms, 3), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3)}
         del x, buf
     del ws
-    res["plain_patterns"] = pats
-    # learned vs plain on the learned workloads
+    return pats
+
+
+def _extras_learned(gs, torch, W, n, dev, stream, patterns, calls):
+    """Learned vs plain on the learned workloads."""
+    every = {"plain": lambda b: gs.gs_sort_f64(b),
+             "learned": lambda b: gs.gs_learned_sort(b),
+             "learned_untrained": lambda b: gs.gs_learned_sort(b, mode=1)}
     lr = {}
-    for pat in ("lognormal", "gaussmix", "zipf_ints"):
+    for pat in patterns:
         log(f"extras: learned {pat}")
         x = torch.from_numpy(W.learned_pattern(pat, n, seed=0)).to(dev)
         buf = torch.empty_like(x)
         row = {}
-        for name, call in (("plain", lambda b: gs.gs_sort_f64(b)),
-                           ("learned", lambda b: gs.gs_learned_sort(b)),
-                           ("learned_untrained", lambda b: gs.gs_learned_sort(b, mode=1))):
+        for name in calls:
+            call = every[name]
+
             def fn(i, timed, call=call):
                 if timed is None:
                     buf.copy_(x)
@@ -136,12 +168,16 @@ def extras(gs, torch, W, log2n, dev):
         row["learned_sorted"] = bool((buf[1:] >= buf[:-1]).all().item())
         lr[pat] = row
         del x, buf
-    res["learned_vs_plain"] = lr
-    # segmented: 100,000 arrays, log-uniform lengths rescaled to total 2^28,
-    # mixed patterns; and lengths log-uniform in [16, 2^20] drawn until 2^28
+    return lr
+
+
+def _extras_segmented(gs, torch, W, n, dev, stream, workloads, per_array):
+    """Segmented: 100,000 arrays, log-uniform lengths rescaled to total n,
+    mixed patterns; and lengths log-uniform in [16, 2^20] drawn until n."""
     segres = {}
-    for name, (nseg, lo, hi) in (("100k_arrays", (100_000, 16, 19023)),
-                                 ("until_total_16_to_2^20", (None, 16, 1 << 20))):
+    shapes = {"100k_arrays": (100_000, 16, 19023), "until_total_16_to_2^20": (None, 16, 1 << 20)}
+    for name in workloads:
+        nseg, lo, hi = shapes[name]
         log(f"extras: segmented {name}")
         xs, off = W.segmented(nseg, lo, hi, seed=0, total=n)
         nseg = off.size - 1
@@ -189,6 +225,17 @@ def extras(gs, torch, W, log2n, dev):
             if seg.numel() > 1 and not bool((seg[1:] >= seg[:-1]).all().item()):
                 ok = False
         del graph
+        row = {
+            "arrays": nseg, "keys": n, "min_len": int(np.diff(off).min()), "max_len": int(np.diff(off).max()),
+            "ms_default_shape": round(ms_default, 3), "ms_tuned": round(ms_best, 3),
+            "ms_tuned_graph": round(ms_graph, 3),
+            "gkeys_per_s_tuned": round(n / (ms_best * 1e-3) / 1e9, 3),
+            "tuned_shape": best, "shape_ms": {str(i): round(v, 3) for i, v in times.items()},
+            "sorted_spot_check": ok}
+        segres[name] = row
+        if not per_array:
+            del x, buf, o, ws
+            continue
         # per-array plain launches on the first arrays, scaled to all
         k = min(nseg, 2000)
         sub = [buf[int(off[i]):int(off[i + 1])] for i in range(k)]
@@ -204,22 +251,18 @@ def extras(gs, torch, W, log2n, dev):
                     if a.numel() > 1:
                         gs.gs_sort_f64(a, workspace=ws1[: gs.gs_workspace_bytes_f64(a.numel())])
         ms_each = _time_calls(torch, stream, fn_each, 1) * (nseg / k)
-        segres[name] = {
-            "arrays": nseg, "keys": n, "min_len": int(np.diff(off).min()), "max_len": int(np.diff(off).max()),
-            "ms_default_shape": round(ms_default, 3), "ms_tuned": round(ms_best, 3),
-            "ms_tuned_graph": round(ms_graph, 3),
-            "gkeys_per_s_tuned": round(n / (ms_best * 1e-3) / 1e9, 3),
-            "tuned_shape": best, "shape_ms": {str(i): round(v, 3) for i, v in times.items()},
-            "sorted_spot_check": ok,
-            "per_array_launches_ms_est": round(ms_each, 1),
-            "per_array_note": f"{k} separate gs_sort_f64 calls timed, scaled to {nseg}"}
+        row["per_array_launches_ms_est"] = round(ms_each, 1)
+        row["per_array_note"] = f"{k} separate gs_sort_f64 calls timed, scaled to {nseg}"
         del x, buf, o, sub, ws, ws1
-    res["segmented"] = segres
-    # key-value: 2^(log2n+1) uint64 keys with uint32 payload
+    return segres
+
+
+def _extras_kv(gs, torch, W, log2n, dev, stream, patterns):
+    """Key-value: 2^(log2n+1) uint64 keys with uint32 payload."""
     log("extras: key-value")
     nk = 1 << (log2n + 1)
     kv = {}
-    for pat in ("uniform", "zipf"):
+    for pat in patterns:
         k0, v0 = W.kv_pattern(pat, nk, seed=0)
         K = torch.from_numpy(k0.view(np.int64)).to(dev)
         V = torch.from_numpy(v0.view(np.int32)).to(dev)
@@ -235,10 +278,13 @@ def extras(gs, torch, W, log2n, dev):
         ms = _time_calls(torch, stream, fn_kv, 3)
         kv[pat] = {"n": nk, "ms": round(ms, 3), "gkeys_per_s": round(nk / (ms * 1e-3) / 1e9, 3)}
         del K, V, Kb, Vb
-    res["key_value"] = kv
-    # smaller buffers on the headline input (Frogsort3, the default below
-    # 0.5, and Frogsort2); %RAM is 1 + workspace / data and tFootprint =
-    # %RAM x runTime ("Sustainability measures")
+    return kv
+
+
+def _extras_buffer(gs, torch, W, n, dev, stream):
+    """Smaller buffers on the headline input (Frogsort3, the default below
+    0.5, and Frogsort2); %RAM is 1 + workspace / data and tFootprint =
+    %RAM x runTime (the paper's sustainability measures)."""
     x = torch.from_numpy(W.f64_pattern("uniform", n, seed=0)).to(dev)
     buf = torch.empty_like(x)
     small = {}
@@ -262,8 +308,23 @@ def extras(gs, torch, W, log2n, dev):
                                          "ram_fraction": round(ram, 4), "t_footprint_ms": round(ram * ms, 3)}
             del ws
     del x, buf
-    res["buffer_fraction"] = small
-    return res
+    return small
+
+
+def _names(arg, allowed):
+    names = tuple(a for a in arg.split(",") if a)
+    bad = [a for a in names if a not in allowed]
+    if bad:
+        print(f"unknown name(s) {bad}; choose from {list(allowed)}", file=sys.stderr)
+        sys.exit(2)
+    return names
+
+
+def run_extras(args, gs, torch, W, dev):
+    return extras(gs, torch, W, args.log2n, dev, _names(args.extras, SECTIONS),
+                  _names(args.learned_patterns, LEARNED_PATTERNS), _names(args.learned_calls, LEARNED_CALLS),
+                  _names(args.kv_patterns, KV_PATTERNS), _names(args.seg_workloads, SEG_WORKLOADS),
+                  not args.no_seg_per_array)
 
 
 def main():
@@ -277,11 +338,26 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the learned / segmented / key-value side measurements")
+    ap.add_argument("--extras", default=",".join(SECTIONS),
+                    help="comma-separated side measurements to run, from " + ", ".join(SECTIONS))
+    ap.add_argument("--learned-patterns", default=",".join(LEARNED_PATTERNS))
+    ap.add_argument("--learned-calls", default=",".join(LEARNED_CALLS))
+    ap.add_argument("--kv-patterns", default=",".join(KV_PATTERNS))
+    ap.add_argument("--seg-workloads", default=",".join(SEG_WORKLOADS))
+    ap.add_argument("--no-seg-per-array", action="store_true",
+                    help="skip the per-array plain launches the segmented sort is compared with")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only the chosen side measurements (to profile one workload) and print "
+                         "them; no headline line")
     ap.add_argument("--buffer-fraction", type=float, default=0.5,
                     help="time this buffer fraction instead (below 0.5: Frogsort3 unless --algo)")
     ap.add_argument("--algo", default="auto", choices=["auto", "frogsort1", "frogsort2", "frogsort3"])
     args = ap.parse_args()
     frac, algo = args.buffer_fraction, args.algo
+    for arg, allowed in ((args.extras, SECTIONS), (args.learned_patterns, LEARNED_PATTERNS),
+                         (args.learned_calls, LEARNED_CALLS), (args.kv_patterns, KV_PATTERNS),
+                         (args.seg_workloads, SEG_WORKLOADS)):
+        _names(arg, allowed)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -299,6 +375,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(3)
     dev = torch.device("cuda:0")
+    if args.extras_only:
+        print(json.dumps({"extras": run_extras(args, gs, torch, W, dev)}), flush=True)
+        return
     n = 1 << args.log2n
     log(f"generating {args.pattern} n=2^{args.log2n}")
     x = W.f64_pattern(args.pattern, n, seed=0)
@@ -426,7 +505,7 @@ def main():
         "report": rep,
     }
     if not args.no_extras:
-        out["extras"] = extras(gs, torch, W, args.log2n, dev)
+        out["extras"] = run_extras(args, gs, torch, W, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2, args.pattern)

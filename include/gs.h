@@ -167,7 +167,12 @@ gs_status gs_sort_kv_ex(uint64_t *keys, uint32_t *vals, int64_t n, int target, d
    offsets[num_segments] <= num_keys; keys outside every segment are untouched.
    The offsets are checked on the device: on a violation nothing is written and
    the report (if any) shows invalid_offsets = 1 and the call returns GS_EINVAL;
-   without a report the call returns GS_OK and the keys are left unchanged. */
+   without a report the call returns GS_OK and the keys are left unchanged.
+   Every segment first gets the order check of the plain path ("Octosort",
+   "Squidsort"): one already in order is left as it is, one whose neighbours
+   all strictly decrease (or do not increase and tie only bit-identical keys)
+   is reversed in place -- in both cases the stable result -- and only the
+   others are sorted. */
 gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets,
                      int64_t num_segments, double buffer_fraction,
                      void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);

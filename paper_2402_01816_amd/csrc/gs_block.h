@@ -212,4 +212,26 @@ __device__ __forceinline__ bool tie_bits_may_differ(K x)
     else return true;
 }
 
+// Order properties of one neighbour pair (a, b) under the key order KT, as
+// bits that stay set only while every pair has them: bit 0 in order
+// (b not before a), bit 1 strictly decreasing, bit 2 non-increasing, bit 3
+// neither key one whose ties could differ in their bits.  A run whose pairs
+// all keep bit 0 is already sorted; one whose pairs all keep bit 1 -- or,
+// keys without values, bits 2 and 3 -- is sorted by one reversal.
+template <class KT>
+__device__ __forceinline__ unsigned order_bits(typename KT::T a, typename KT::T b)
+{
+    return (!KT::less(b, a) ? 1u : 0u) | (KT::less(b, a) ? 2u : 0u) | (!KT::less(a, b) ? 4u : 0u) |
+           (!tie_bits_may_differ(a) && !tie_bits_may_differ(b) ? 8u : 0u);
+}
+
+// Whether the properties still possible can decide anything (otherwise the
+// run must be sorted and checking further pairs is pointless).
+template <class KT>
+__device__ __forceinline__ bool order_decisive(unsigned bits, bool keys_only)
+{
+    const bool rev_ties = keys_only && (bits & 4u) && (bits & 8u);
+    return (bits & 1u) || (bits & 2u) || rev_ties;
+}
+
 }  // namespace gs

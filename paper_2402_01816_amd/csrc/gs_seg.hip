@@ -43,6 +43,15 @@ __device__ __forceinline__ int seg_class(int64_t len, int logt)
     return c;
 }
 
+// A segment's order code, held in its rank word until the classification
+// overwrites it (ranks are never negative): sort it, nothing to do, reverse
+// it, or still to be decided from the order bits in its class word.
+constexpr int SEG_SORT = 0;
+constexpr int SEG_DONE = -1;
+constexpr int SEG_REVERSE = -2;
+constexpr int SEG_CANDIDATE = -3;
+constexpr int64_t SEG_RANGE = 16384;                // keys per work-group of the range passes
+
 // Work-list order: the long class first, then the short classes from the
 // largest blocks down.
 __device__ __forceinline__ int class_at(int pos, int logt) { return pos == 0 ? SEG_CLASS_LONG : logt - (pos - 1); }
@@ -51,11 +60,110 @@ __device__ __forceinline__ int num_pos(int logt) { return logt - 2; }
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// 0. per segment: already in order, or reversed ("Octosort", "Squidsort")
+// ---------------------------------------------------------------------------
+// The whole-array order check of the plain path, applied to every segment:
+// a segment whose neighbour pairs are all in order needs nothing, one whose
+// pairs all strictly decrease (or, these being keys without values, do not
+// increase and tie only bit-identical keys) is sorted by one reversal.
+// Nothing moves in these passes (the offsets are validated only by the
+// classification; a segment with bad offsets reads nothing).
+//
+// 0a. One work-group per segment: a segment of at most 1024 pairs is checked
+// whole; a longer one on 1024 evenly spaced pairs, which rules out almost
+// every unsorted segment at once, and otherwise becomes a candidate whose
+// order bits (in cls[s]) the range pass completes.
+template <class KT>
+__global__ __launch_bounds__(256) void seg_order_sample_kernel(const typename KT::T *keys, const int64_t *offsets,
+                                                               int64_t nseg, int64_t num_keys, int *cls,
+                                                               int *rank, Gate gate)
+{
+    constexpr int SAMPLE = 1024;
+    __shared__ unsigned s_bits;
+    if (gate.closed()) return;
+    for (int64_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+        const int64_t lo = offsets[s], hi = offsets[s + 1];
+        if (lo < 0 || hi < lo || hi > num_keys) {
+            if (threadIdx.x == 0) rank[s] = SEG_SORT;
+            continue;
+        }
+        const int64_t pairs = hi - lo - 1;
+        if (threadIdx.x == 0) s_bits = 15u;
+        __syncthreads();
+        unsigned bits = 15u;
+        for (int j = threadIdx.x; j < SAMPLE; j += 256) {
+            if (j < pairs) {
+                const int64_t i = lo + (pairs <= SAMPLE ? (int64_t)j : (int64_t)j * pairs / SAMPLE);
+                bits &= order_bits<KT>(keys[i], keys[i + 1]);
+            }
+        }
+        atomicAnd(&s_bits, bits);
+        __syncthreads();
+        const unsigned all = s_bits;
+        __syncthreads();                            // read before the next segment resets it
+        if (threadIdx.x == 0) {
+            int code;
+            if (pairs > SAMPLE && order_decisive<KT>(all, true)) code = SEG_CANDIDATE;
+            else code = (all & 1u) ? SEG_DONE : ((all & 2u) || ((all & 4u) && (all & 8u))) ? SEG_REVERSE : SEG_SORT;
+            rank[s] = code;
+            cls[s] = (int)all;
+        }
+    }
+}
+
+// First segment that ends past key r0 (offsets non-decreasing; with bad
+// offsets any segment index comes back, and the keys read stay inside the
+// segment's own checked bounds).
+__device__ __forceinline__ int64_t seg_first_after(const int64_t *offsets, int64_t nseg, int64_t r0)
+{
+    int64_t a = 0, b = nseg;                        // first s with offsets[s + 1] > r0
+    while (a < b) {
+        const int64_t m = (a + b) >> 1;
+        if (offsets[m + 1] > r0) b = m;
+        else a = m + 1;
+    }
+    return a;
+}
+
+// 0b. One work-group per SEG_RANGE keys of the array: every candidate
+// segment's pairs that start in the range are checked and their order bits
+// and-ed into cls[s], so a long segment is read by many work-groups at once.
+template <class KT>
+__global__ __launch_bounds__(256) void seg_order_range_kernel(const typename KT::T *keys, const int64_t *offsets,
+                                                              int64_t nseg, int64_t num_keys, int *cls,
+                                                              const int *rank, Gate gate)
+{
+    __shared__ unsigned s_bits;
+    if (gate.closed()) return;
+    const int64_t r0 = (int64_t)blockIdx.x * SEG_RANGE;
+    const int64_t r1 = r0 + SEG_RANGE < num_keys ? r0 + SEG_RANGE : num_keys;
+    for (int64_t s = seg_first_after(offsets, nseg, r0); s < nseg; ++s) {
+        const int64_t lo = offsets[s], hi = offsets[s + 1];
+        if (lo >= r1) break;
+        if (rank[s] != SEG_CANDIDATE || lo < 0 || hi < lo || hi > num_keys) continue;
+        const int64_t a = lo > r0 ? lo : r0;
+        const int64_t b = hi - 1 < r1 ? hi - 1 : r1;  // pairs (i, i+1) with i in [a, b)
+        if (a >= b) continue;
+        if (threadIdx.x == 0) s_bits = 15u;
+        __syncthreads();
+        unsigned bits = 15u;
+        for (int64_t i = a + threadIdx.x; i < b; i += 256) bits &= order_bits<KT>(keys[i], keys[i + 1]);
+        atomicAnd(&s_bits, bits);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_bits != 15u) atomicAnd((unsigned *)cls + s, s_bits);
+        __syncthreads();                            // s_bits read before the next segment resets it
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 1. validate the offsets and count segments per class
 // ---------------------------------------------------------------------------
+// With the order codes (order_codes != 0), a candidate's code is decided from
+// its order bits, and a segment already in order or to be reversed takes
+// class 0 (no sorting work) and keeps its code.
 __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t *offsets, int64_t nseg,
                                                            int64_t num_keys, int logt, unsigned *ctrl,
-                                                           int *cls, int *rank, Gate gate)
+                                                           int *cls, int *rank, int order_codes, Gate gate)
 {
     if (gate.closed()) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -66,9 +174,48 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t *offset
         cls[s] = 0;
         return;
     }
+    if (order_codes) {
+        int code = rank[s];
+        if (code == SEG_CANDIDATE) {
+            const unsigned b = (unsigned)cls[s];
+            code = (b & 1u) ? SEG_DONE : ((b & 2u) || ((b & 4u) && (b & 8u))) ? SEG_REVERSE : SEG_SORT;
+            rank[s] = code;
+        }
+        if (code != SEG_SORT) {
+            cls[s] = 0;
+            return;
+        }
+    }
     const int c = seg_class(hi - lo, logt);
     cls[s] = c;
     rank[s] = (int)atomicAdd(ctrl + C_HIST + c, 1u);
+}
+
+// Reverses, in place, every segment whose code says so, once every segment's
+// offsets passed the classification.  One work-group per SEG_RANGE keys
+// swaps the pairs (i, lo + hi - 1 - i) whose lower index i lies in its range.
+template <class K>
+__global__ __launch_bounds__(256) void seg_reverse_kernel(K *keys, const int64_t *offsets, int64_t nseg,
+                                                          int64_t num_keys, const unsigned *ctrl, const int *cls,
+                                                          const int *rank, Gate gate)
+{
+    if (gate.closed() || ctrl[C_INVALID]) return;
+    const int64_t r0 = (int64_t)blockIdx.x * SEG_RANGE;
+    const int64_t r1 = r0 + SEG_RANGE < num_keys ? r0 + SEG_RANGE : num_keys;
+    for (int64_t s = seg_first_after(offsets, nseg, r0); s < nseg; ++s) {
+        const int64_t lo = offsets[s], hi = offsets[s + 1];
+        if (lo >= r1) break;
+        if (cls[s] != 0 || rank[s] != SEG_REVERSE) continue;
+        const int64_t mid = lo + (hi - lo) / 2;     // lower halves: [lo, mid)
+        const int64_t a = lo > r0 ? lo : r0;
+        const int64_t b = mid < r1 ? mid : r1;
+        for (int64_t i = a + threadIdx.x; i < b; i += 256) {
+            const int64_t j = lo + hi - 1 - i;
+            const K x = keys[i], y = keys[j];
+            keys[i] = y;
+            keys[j] = x;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -303,9 +450,17 @@ static void launch_short(double *keys, const int64_t *offsets, unsigned *ctrl, c
                        ctrl, list, g);
 }
 
+// work-groups for a one-segment-per-group pass (each walks segments with a
+// stride of the grid)
+static unsigned seg_groups(int64_t nseg)
+{
+    return (unsigned)(nseg < 65536 ? nseg : 65536);
+}
+
 static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys, double *hbuf,
                               unsigned *ctrl, int *cls, int *rank, int *list, char *forest, const ForestPlan &fp,
-                              const SegConfig &cfg, const unsigned *gate, unsigned run_if, hipStream_t st)
+                              const SegConfig &cfg, bool order_check, const unsigned *gate, unsigned run_if,
+                              hipStream_t st)
 {
     if (nseg <= 0) return hipSuccess;
     const Gate g{gate, run_if};
@@ -314,8 +469,19 @@ static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg
     if (tr) trace_begin(TK_OTHER, st);
     launch_fill_u32(ctrl, 64, 0u, st);
     const unsigned grid = (unsigned)((nseg + 255) / 256);
+    const unsigned ranges = (unsigned)((num_keys + SEG_RANGE - 1) / SEG_RANGE);
+    if (order_check) {
+        hipLaunchKernelGGL((seg_order_sample_kernel<KeyF64>), dim3(seg_groups(nseg)), dim3(256), 0, st,
+                           (const double *)keys, offsets, nseg, num_keys, cls, rank, g);
+        if (ranges > 0)
+            hipLaunchKernelGGL((seg_order_range_kernel<KeyF64>), dim3(ranges), dim3(256), 0, st,
+                               (const double *)keys, offsets, nseg, num_keys, cls, (const int *)rank, g);
+    }
     hipLaunchKernelGGL(seg_classify_kernel, dim3(grid), dim3(256), 0, st, offsets, nseg, num_keys, logt, ctrl, cls,
-                       rank, g);
+                       rank, order_check ? 1 : 0, g);
+    if (order_check && ranges > 0)
+        hipLaunchKernelGGL((seg_reverse_kernel<double>), dim3(ranges), dim3(256), 0, st, keys, offsets, nseg,
+                           num_keys, (const unsigned *)ctrl, (const int *)cls, (const int *)rank, g);
     hipLaunchKernelGGL(seg_scatter_kernel, dim3(grid), dim3(256), 0, st, nseg, logt, (const unsigned *)ctrl,
                        (const int *)cls, (const int *)rank, list, g);
     Prob *probs = (Prob *)(forest + fp.off_probs);
@@ -343,7 +509,7 @@ hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg
                               const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st)
 {
     return segsort_run(keys, offsets, nseg, num_keys, hbuf, ctrl, cls, rank, list, forest, fp,
-                       seg_default_config(), gate, run_if, st);
+                       seg_default_config(), false, gate, run_if, st);
 }
 
 hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan &p, char *ws,
@@ -351,7 +517,7 @@ hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan
 {
     return segsort_run(keys, offsets, p.nseg, p.num_keys, (double *)(ws + p.off_h), (unsigned *)(ws + p.off_ctrl),
                        (int *)(ws + p.off_cls), (int *)(ws + p.off_rank), (int *)(ws + p.off_list),
-                       ws + p.off_forest, p.forest, p.cfg, nullptr, 0u, st);
+                       ws + p.off_forest, p.forest, p.cfg, true, nullptr, 0u, st);
 }
 
 }  // namespace gs

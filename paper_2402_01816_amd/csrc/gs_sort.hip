@@ -1045,23 +1045,8 @@ static void launch_reverse(K *keys, V *vals, int64_t n, hipStream_t st, Gate gat
 // anything else is sorted.  4096 sampled pairs decide first, so unsorted
 // input pays one small launch; the pass over every pair runs only when the
 // sample finds no counter-example.  The decision (word 0) gates every later
-// launch of the call; word 1 holds the properties still possible: bit 0 in
-// order, bit 1 strictly decreasing, bit 2 non-increasing, bit 3 no key whose
-// ties could differ in their bits.
-template <class KT>
-__device__ __forceinline__ unsigned order_bits(typename KT::T a, typename KT::T b)
-{
-    return (!KT::less(b, a) ? 1u : 0u) | (KT::less(b, a) ? 2u : 0u) | (!KT::less(a, b) ? 4u : 0u) |
-           (!tie_bits_may_differ(a) && !tie_bits_may_differ(b) ? 8u : 0u);
-}
-
-template <class KT>
-__device__ __forceinline__ unsigned order_decisive(unsigned bits, bool keys_only)
-{
-    // the properties that still decide something
-    const bool rev_ties = keys_only && (bits & 4u) && (bits & 8u);
-    return (bits & 1u) || (bits & 2u) || rev_ties;
-}
+// launch of the call; word 1 holds the properties still possible (the bits
+// of order_bits).
 
 template <class KT>
 __global__ __launch_bounds__(256) void order_sample_kernel(const typename KT::T *keys, int64_t n, unsigned *word,

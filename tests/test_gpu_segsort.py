@@ -159,6 +159,75 @@ def test_segsort_invalid_offsets_reported(gs, bad):
     assert np.array_equal(bits(t), bits(x))
 
 
+ORDER_LENGTHS = [2, 3, 17, 1000, 4097, 20000, 70001]
+
+
+def _ordered_segment(kind, m, rng):
+    u = np.sort(rng.random(m))
+    if kind == "sorted":
+        return u
+    if kind == "reversed":
+        return u[::-1].copy()
+    if kind == "reversed_ties":                 # non-increasing, ties bit-identical
+        return np.sort(rng.integers(0, 16, m).astype(np.float64))[::-1].copy()
+    if kind == "reversed_signed_zero_ties":     # non-increasing, but +0 and -0 tie
+        v = np.sort(rng.integers(-3, 4, m).astype(np.float64))[::-1].copy()
+        z = np.flatnonzero(v == 0)
+        v[z[::2]] = -0.0
+        return v
+    if kind == "reversed_nan_first":            # one NaN, then strictly decreasing
+        v = u[::-1].copy()
+        v[0] = np.nan
+        return v
+    if kind == "reversed_two_nans":             # NaN ties NaN: not strictly decreasing
+        v = u[::-1].copy()
+        v[: min(2, m)] = np.nan
+        return v
+    if kind == "almost_sorted":
+        v = u.copy()
+        v[m - 2], v[m - 1] = v[m - 1], v[m - 2]
+        return v
+    if kind == "almost_reversed":
+        v = u[::-1].copy()
+        v[m - 2], v[m - 1] = v[m - 1], v[m - 2]
+        return v
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["sorted", "reversed", "reversed_ties", "reversed_signed_zero_ties",
+                                  "reversed_nan_first", "reversed_two_nans", "almost_sorted", "almost_reversed"])
+def test_segsort_ordered_segments(gs, orc, kind):
+    """Segments already in order are left alone and reversed ones reversed
+    (the order check's shortcut); near misses in the last pair, signed-zero
+    ties and tied NaNs must still be sorted.  Lengths span the short classes
+    and the forest; a uniform segment sits between every two."""
+    announce("segsort ordered", kind)
+    rng = np.random.default_rng(11)
+    parts, lens = [], []
+    for m in ORDER_LENGTHS:
+        parts += [_ordered_segment(kind, m, rng), rng.random(m // 2 + 1)]
+        lens += [m, m // 2 + 1]
+    x = np.concatenate(parts)
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    t, rep = _run(gs, x, off, report=True)
+    _check(orc, t, x, off)
+    assert rep["invalid_offsets"] == 0
+
+
+def test_segsort_invalid_offsets_with_reversed_segments(gs):
+    """Valid reversed segments around an invalid one: the call fails and
+    nothing moves (the reversal waits for every segment's offsets)."""
+    announce("segsort invalid reversed")
+    x = np.arange(100, 0, -1, dtype=np.float64)
+    t = to_dev(x)
+    o = to_dev(np.array([0, 50, 40, 100], dtype=np.int64))
+    with pytest.raises(gs.GsError) as e:
+        gs.gs_segsort(t, o, report=True)
+    assert e.value.status == gs.GS_EINVAL
+    assert np.array_equal(bits(t), bits(x))
+
+
 def _weak_orders(n):
     grid = np.indices((n,) * n).reshape(n, -1).T
     present = np.zeros((grid.shape[0], n), dtype=bool)

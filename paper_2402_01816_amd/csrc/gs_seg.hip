@@ -426,9 +426,12 @@ SegPlan plan_seg(int64_t num_keys, int64_t nseg, const SegConfig &cfg)
     return p;
 }
 
+// The forest of segsort_core_async, which runs the default shape.
 ForestPlan plan_forest_seg(int64_t num_keys, int64_t max_len, int64_t nseg)
 {
-    return plan_forest_f64(num_keys, max_len, max_long(num_keys, nseg, 4096), 16);
+    const SegConfig c = seg_default_config();
+    return plan_forest_f64(num_keys, max_len, max_long(num_keys, nseg, (int64_t)c.short_threads * c.short_ipt),
+                           c.merge_ipt);
 }
 
 template <int NT, int IPT>

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgs.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is not built; run `python -m paper_2402_01816_amd.build` "
+        f"{LIB_PATH} is not built; run `python paper_2402_01816_amd/build.py` "
         "(hipcc, gfx950) first")
 
 # torch brings its own copy of the HIP runtime (same soname as the system one).

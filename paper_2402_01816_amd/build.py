@@ -1,6 +1,6 @@
 """Build libgs.so (the HIP library behind include/gs.h) for gfx950 with hipcc.
 
-Usage: python -m paper_2402_01816_amd.build
+Usage: python paper_2402_01816_amd/build.py   (or build() of __graft_entry__.py)
 """
 from __future__ import annotations
 

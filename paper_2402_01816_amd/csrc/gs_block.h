@@ -82,6 +82,99 @@ constexpr SortNet<N> batcher_net()
     return s;
 }
 
+// Key orders whose compare-exchange may be a min and a max: float64 blocks
+// with no NaN and no signed zero, where the min and the max of two keys are
+// the two keys themselves, bit for bit (equal keys are identical there).
+// dir 1: ascending, -1: descending, 0: compare and select only.
+template <class KT>
+struct NetMinMax {
+    static constexpr int dir = 0;
+};
+template <>
+struct NetMinMax<KeyF64NoNaN> {
+    static constexpr int dir = 1;
+};
+template <>
+struct NetMinMax<KeyF64DescNoNaN> {
+    static constexpr int dir = -1;
+};
+
+// Key of lane (this lane's quad position permuted by the quad pattern QP) in
+// register r, moved across lanes with DPP (no LDS traffic).
+template <int QP>
+__device__ __forceinline__ double quad_swap(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), QP, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), QP, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// One compare-exchange kept on one side: the earlier position of the pair
+// keeps the key that comes first in the order, the later one the other.
+template <int DIR>
+__device__ __forceinline__ double keep_side(double mine, double other, bool earlier)
+{
+    const double mn = __builtin_fmin(mine, other), mx = __builtin_fmax(mine, other);
+    return (earlier == (DIR > 0)) ? mn : mx;
+}
+
+// Sorts the IPT keys of a bitonic sequence held in registers (half-cleaners
+// of strides IPT/2 .. 1, each compare-exchange one min and one max).
+template <int DIR, int IPT>
+__device__ __forceinline__ void bitonic_clean_regs(double (&k)[IPT])
+{
+#pragma unroll
+    for (int s = IPT / 2; s >= 1; s /= 2) {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            if ((i & s) == 0) {
+                const double a = k[i], b = k[i + s];
+                const double mn = __builtin_fmin(a, b), mx = __builtin_fmax(a, b);
+                k[i] = DIR > 0 ? mn : mx;
+                k[i + s] = DIR > 0 ? mx : mn;
+            }
+        }
+    }
+}
+
+// The first merge rounds of the block sort across neighbouring lanes, for
+// blocks whose equal keys are bit for bit identical: every lane holds IPT
+// sorted keys (positions IPT*lane ..), and a bitonic merger (a flip stage
+// pairing position p with the mirror position of the merged run, then
+// half-cleaners) turns runs of IPT into runs of 2*IPT (lanes t, t^1) and,
+// with rounds >= 2, into runs of 4*IPT (lanes of a quad).  Any order among
+// identical keys is the stable one, so the unstable merger gives the stable
+// result.  Every lane of the wave must execute this (DPP reads neighbours).
+template <int DIR, int IPT>
+__device__ __forceinline__ void lane_merge_rounds(double (&k)[IPT], int rounds)
+{
+    const int lane = threadIdx.x & 63;
+    if (rounds >= 1) {                   // lanes t, t^1: flip, then in-register cleaners
+        double o[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = quad_swap<0xB1>(k[IPT - 1 - r]);
+        const bool earlier = (lane & 1) == 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k[r] = keep_side<DIR>(k[r], o[r], earlier);
+        bitonic_clean_regs<DIR, IPT>(k);
+    }
+    if (rounds >= 2) {                   // a quad: flip (t, 3-t), cleaner (t, t^1), in-register cleaners
+        double o[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = quad_swap<0x1B>(k[IPT - 1 - r]);
+        const bool earlier = (lane & 2) == 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k[r] = keep_side<DIR>(k[r], o[r], earlier);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = quad_swap<0xB1>(k[r]);
+        const bool earlier1 = (lane & 1) == 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k[r] = keep_side<DIR>(k[r], o[r], earlier1);
+        bitonic_clean_regs<DIR, IPT>(k);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // block sort in LDS
 // ---------------------------------------------------------------------------
@@ -146,6 +239,16 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
             }
         }
     }
+    // identical ties: the first rounds across lanes, in registers (every lane
+    // of the wave joins; lanes past `active` hold padding, which stays behind)
+    int w0 = IPT;
+    if constexpr (!HV && NetMinMax<KT>::dir != 0) {
+        if (network) {
+            const int rounds = maxw >= 4 * IPT ? 2 : maxw >= 2 * IPT ? 1 : 0;
+            lane_merge_rounds<NetMinMax<KT>::dir, IPT>(k, rounds);
+            w0 = IPT << rounds;
+        }
+    }
     __syncthreads();
     if (work) {
 #pragma unroll
@@ -156,7 +259,7 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
     }
     __syncthreads();
 
-    for (int w = IPT; w < maxw; w *= 2) {
+    for (int w = w0; w < maxw; w *= 2) {
         if (work) {
             const int a0 = (base / (2 * w)) * 2 * w;
             const int b0 = a0 + w;

@@ -99,8 +99,9 @@ struct NetMinMax<KeyF64DescNoNaN> {
     static constexpr int dir = -1;
 };
 
-// Key of lane (this lane's quad position permuted by the quad pattern QP) in
-// register r, moved across lanes with DPP (no LDS traffic).
+// A neighbour lane's key, moved with DPP (no LDS traffic): QP is the DPP
+// control -- a quad permutation (0x00-0xff) or 0x141, the mirror of each
+// group of eight lanes.
 template <int QP>
 __device__ __forceinline__ double quad_swap(double x)
 {
@@ -142,8 +143,9 @@ __device__ __forceinline__ void bitonic_clean_regs(double (&k)[IPT])
 // blocks whose equal keys are bit for bit identical: every lane holds IPT
 // sorted keys (positions IPT*lane ..), and a bitonic merger (a flip stage
 // pairing position p with the mirror position of the merged run, then
-// half-cleaners) turns runs of IPT into runs of 2*IPT (lanes t, t^1) and,
-// with rounds >= 2, into runs of 4*IPT (lanes of a quad).  Any order among
+// half-cleaners) turns runs of IPT into runs of 2*IPT (lanes t, t^1), with
+// rounds >= 2 into runs of 4*IPT (lanes of a quad) and with rounds >= 3 into
+// runs of 8*IPT (eight lanes).  Any order among
 // identical keys is the stable one, so the unstable merger gives the stable
 // result.  Every lane of the wave must execute this (DPP reads neighbours).
 template <int DIR, int IPT>
@@ -166,6 +168,25 @@ __device__ __forceinline__ void lane_merge_rounds(double (&k)[IPT], int rounds)
         const bool earlier = (lane & 2) == 0;
 #pragma unroll
         for (int r = 0; r < IPT; ++r) k[r] = keep_side<DIR>(k[r], o[r], earlier);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = quad_swap<0xB1>(k[r]);
+        const bool earlier1 = (lane & 1) == 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k[r] = keep_side<DIR>(k[r], o[r], earlier1);
+        bitonic_clean_regs<DIR, IPT>(k);
+    }
+    if (rounds >= 3) {                   // eight lanes: flip (t, 7-t), cleaners (t, t^2), (t, t^1), in-register
+        double o[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = quad_swap<0x141>(k[IPT - 1 - r]);   // mirror within 8 lanes
+        const bool earlier = (lane & 4) == 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k[r] = keep_side<DIR>(k[r], o[r], earlier);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = quad_swap<0x4E>(k[r]);
+        const bool earlier2 = (lane & 2) == 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k[r] = keep_side<DIR>(k[r], o[r], earlier2);
 #pragma unroll
         for (int r = 0; r < IPT; ++r) o[r] = quad_swap<0xB1>(k[r]);
         const bool earlier1 = (lane & 1) == 0;
@@ -244,7 +265,7 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
     int w0 = IPT;
     if constexpr (!HV && NetMinMax<KT>::dir != 0) {
         if (network) {
-            const int rounds = maxw >= 4 * IPT ? 2 : maxw >= 2 * IPT ? 1 : 0;
+            const int rounds = maxw >= 8 * IPT ? 3 : maxw >= 4 * IPT ? 2 : maxw >= 2 * IPT ? 1 : 0;
             lane_merge_rounds<NetMinMax<KT>::dir, IPT>(k, rounds);
             w0 = IPT << rounds;
         }

@@ -175,6 +175,20 @@ def test_sort_f64_targets(gs, orc, target, n):
 
 
 @pytest.mark.parametrize("target", TARGETS)
+@pytest.mark.parametrize("pattern", ["uniform", "tied"])
+@pytest.mark.parametrize("n", [300, 4097, 100003, 1 << 20])
+def test_sort_f64_targets_identical_ties(gs, orc, target, pattern, n):
+    """The four targets on keys without NaN or zeros, where every tie is
+    between bit-identical keys: the blocks take the register network and the
+    merge rounds across lanes, ascending and descending."""
+    announce("sort_f64 target identical ties", target, pattern, n)
+    x = W.f64_pattern(pattern, n, seed=5 + n) + 1.0
+    t = to_dev(x)
+    gs.gs_sort_f64(t, target=target)
+    assert np.array_equal(bits(t), bits(orc.sort_f64_target(x, target)))
+
+
+@pytest.mark.parametrize("target", TARGETS)
 @pytest.mark.parametrize("pattern", ["uniform", "few"])
 def test_sort_kv_targets(gs, orc, target, pattern):
     """Key/value targets: payload = input index, so the tie order is visible

@@ -212,7 +212,9 @@ __device__ __forceinline__ void lane_merge_rounds(double (&k)[IPT], int rounds)
 // work.  With `ties_identical` (keys only; the caller has checked that equal
 // keys are bit for bit equal, so no order among them can be seen) the
 // per-thread sort is Batcher's network, half the compare-exchanges of the
-// transposition sort.
+// transposition sort, and for float64 orders the first (up to three) merge
+// rounds run across lanes in registers (lane_merge_rounds) instead of
+// through LDS.
 template <class KT, class VS, bool HV, int NT, int IPT, bool PARTIAL = false>
 __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int maxw = NT * IPT,
                                                int active = NT * IPT, bool ties_identical = false)

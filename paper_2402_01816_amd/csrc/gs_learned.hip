@@ -183,9 +183,47 @@ __global__ void learned_sample_kernel(const double *keys, int64_t n, int64_t S, 
 // key.  The feature whose FEAT_BINS-bin histogram of the sample has the
 // smaller largest bin wins (ties: linear).  Targets: log of the local density
 // of the sample in phi over a window of +-kDensH ranks.
+//
+// With `screen_half` > 0 (the half size the screening scales to) the sorted
+// sample's equal keys are screened first: equal keys (and all NaNs) always
+// share a bucket, so a run of equal keys long enough that it alone scales to
+// more than the screening limit fails the screening whatever the network
+// learns.  Such an input takes the plain path before any training (the
+// training and tabulation launches are gated on the fallback word).
 __global__ __launch_bounds__(1024) void learned_prep_kernel(const double *xs, int64_t S, int G, Feature *feat,
-                                                            float *u, float *t, unsigned *ctrl)
+                                                            float *u, float *t, unsigned *ctrl, int64_t screen_half,
+                                                            int B)
 {
+    if (screen_half > 0) {
+        __shared__ unsigned s_run;
+        const int64_t avg = screen_half / B;
+        const int64_t limit = kScreenSkew * avg > kScreenMin ? kScreenSkew * avg : kScreenMin;
+        // shortest run whose scaled size run * half / S exceeds the limit
+        const int64_t m = ((limit + 1) * S + screen_half - 1) / screen_half;
+        if (threadIdx.x == 0) s_run = 0u;
+        __syncthreads();
+        auto same = [&](double a, double b) { return a == b || (a != a && b != b); };
+        for (int64_t i = threadIdx.x; m >= 1 && i + m - 1 < S; i += 1024) {
+            // a long run starting here: measure it (its end by binary search)
+            if (same(xs[i], xs[i + m - 1]) && (i == 0 || !same(xs[i - 1], xs[i]))) {
+                int64_t lo = i + m - 1, hi = S;          // last index of the run: lo
+                while (hi - lo > 1) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (same(xs[i], xs[mid])) lo = mid;
+                    else hi = mid;
+                }
+                atomicMax(&s_run, (unsigned)(lo - i + 1));
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && s_run) {
+            const int64_t predicted = (int64_t)s_run * screen_half / S;
+            ctrl[L_SCREENED] = 1u;
+            ctrl[L_MAXB] = (unsigned)(predicted < 0xffffffffll ? predicted : 0xffffffffll);
+            ctrl[L_FALLBACK] = 1u;
+        }
+        __syncthreads();
+    }
     __shared__ unsigned h_lin[FEAT_BINS], h_bits[FEAT_BINS];
     __shared__ int64_t s_nn;
     __shared__ unsigned s_max[2];
@@ -279,6 +317,7 @@ __global__ __launch_bounds__(1024) void learned_table_kernel(const float *raw, c
     __shared__ double s_part[1024];
     __shared__ float s_mx[1024];
     __shared__ unsigned s_bad;
+    if (ctrl[L_FALLBACK]) return;        // screened out before training
     const int tid = threadIdx.x;
     const int cnt = G + 1;
     const int per = (cnt + 1023) / 1024;
@@ -791,8 +830,9 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     hipError_t e = sort_f64_async(sample, L.S, ws + L.off_sample_ws, L.splan, st);
     if (e != hipSuccess) return e;
     if (tr) trace_begin(TK_LEARN_PREP, st);
+    const bool screening = prm.mode == 0 && !prm.test_bucket_table && prm.screen == 0;
     hipLaunchKernelGGL(learned_prep_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample, L.S, G, feat, u,
-                       t, ctrl);
+                       t, ctrl, screening ? n - n / 2 : (int64_t)0, B);
     if (tr) trace_end(st);
 
     // 3-4. network and knot table
@@ -806,17 +846,17 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
             if (e != hipSuccess) return e;
             if (prm.train_steps > 0) {
                 e = mlp_train(params, m, v, u, t, L.S, (int)prm.train_steps, L.batch, prm.lr, prm.seed, 0, partial,
-                              losses, ctrl + L_BAR, ctrl + L_ERR, nullptr, st);
+                              losses, ctrl + L_BAR, ctrl + L_ERR, ctrl + L_FALLBACK, st);
                 if (e != hipSuccess) return e;
             }
         }
-        e = mlp_forward(params, nullptr, G + 1, raw, G, nullptr, st);
+        e = mlp_forward(params, nullptr, G + 1, raw, G, ctrl + L_FALLBACK, st);
         if (e != hipSuccess) return e;
     }
     if (tr) trace_end(st);
     hipLaunchKernelGGL(learned_table_kernel, dim3(1), dim3(1024), 0, st, (const float *)raw, prm.test_bucket_table,
                        (int)prm.mode, G, tab, ctrl, (const Feature *)feat);
-    if (prm.mode == 0 && !prm.test_bucket_table && prm.screen == 0) {
+    if (screening) {
         const size_t jlds = (size_t)(G + 1) * 4 + (size_t)B * 4;
         (void)hipFuncSetAttribute((const void *)learned_screen_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)jlds);

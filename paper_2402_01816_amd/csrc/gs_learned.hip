@@ -505,30 +505,51 @@ __global__ __launch_bounds__(SW_NT, 4) void learned_count_kernel(const double *s
 // Per digit (one work-group each): tilecnt[d][t] becomes the destination of
 // tile t's first key of digit d: dstart[d] + the keys of digit d in tiles
 // before t (an exclusive scan over the tiles, in tile order).
+// The column of one digit is scanned in chunks of TS_CHUNK counts staged in
+// LDS: loaded and stored back coalesced, each thread scanning 32 consecutive
+// counts of the chunk (padded LDS index: conflict-free), a block scan of the
+// threads' sums, and a carry from chunk to chunk.
+constexpr int TS_CHUNK = 32 * 1024;
+__host__ __device__ constexpr int ts_pad(int i) { return i + (i >> 5); }
+
 __global__ __launch_bounds__(1024) void learned_tilescan_kernel(unsigned *tilecnt, int64_t ntiles,
                                                                 const unsigned *dstart, const unsigned *ctrl)
 {
+    extern __shared__ unsigned s_col[];              // ts_pad(TS_CHUNK) words
     __shared__ unsigned s_part[1024];
     if (ctrl[L_FALLBACK]) return;
     const int d = blockIdx.x, tid = threadIdx.x;
     unsigned *col = tilecnt + (int64_t)d * ntiles;
-    const int64_t per = (ntiles + 1023) / 1024;
-    const int64_t t0 = tid * per, t1 = t0 + per < ntiles ? t0 + per : ntiles;
-    unsigned acc = 0;
-    for (int64_t t = t0; t < t1; ++t) acc += col[t];
-    s_part[tid] = acc;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const unsigned v = tid >= o ? s_part[tid - o] : 0u;
+    unsigned carry = dstart[d];
+    for (int64_t c0 = 0; c0 < ntiles; c0 += TS_CHUNK) {
+        const int len = (int)(ntiles - c0 < TS_CHUNK ? ntiles - c0 : TS_CHUNK);
+        for (int i = tid; i < len; i += 1024) s_col[ts_pad(i)] = col[c0 + i];
         __syncthreads();
-        s_part[tid] += v;
+        const int b0 = 32 * tid;
+        unsigned acc = 0;
+        for (int i = 0; i < 32; ++i)
+            if (b0 + i < len) acc += s_col[ts_pad(b0 + i)];
+        s_part[tid] = acc;
         __syncthreads();
-    }
-    unsigned run = dstart[d] + s_part[tid] - acc;
-    for (int64_t t = t0; t < t1; ++t) {
-        const unsigned c = col[t];
-        col[t] = run;
-        run += c;
+        for (int o = 1; o < 1024; o <<= 1) {
+            const unsigned v = tid >= o ? s_part[tid - o] : 0u;
+            __syncthreads();
+            s_part[tid] += v;
+            __syncthreads();
+        }
+        unsigned run = carry + s_part[tid] - acc;
+        const unsigned total = s_part[1023];
+        for (int i = 0; i < 32; ++i) {
+            if (b0 + i < len) {
+                const unsigned c = s_col[ts_pad(b0 + i)];
+                s_col[ts_pad(b0 + i)] = run;
+                run += c;
+            }
+        }
+        carry += total;
+        __syncthreads();
+        for (int i = tid; i < len; i += 1024) col[c0 + i] = s_col[ts_pad(i)];
+        __syncthreads();                             // LDS and s_part free for the next chunk
     }
 }
 
@@ -898,6 +919,9 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     (void)hipFuncSetAttribute((const void *)learned_scatter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)slds);
     const unsigned cgrid = GS_LEARN_CGRID;
+    const size_t tslds = (size_t)ts_pad(TS_CHUNK) * 4;
+    (void)hipFuncSetAttribute((const void *)learned_tilescan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)tslds);
     if (tr) trace_begin(TK_LEARN_BUCKET, st);
     launch_fill_u32(totals, 2 * (int64_t)B, 0u, st);
     hipLaunchKernelGGL(learned_count_kernel, dim3(cgrid), dim3(SW_NT), clds, st, (const double *)keys, nA,
@@ -917,7 +941,7 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     auto distribute = [&](double *region, int64_t len, int64_t ntiles, unsigned *cnt, int h) {
         if (ntiles == 0) return;
         const unsigned sgrid = (unsigned)(ntiles < GS_LEARN_SGRID ? ntiles : GS_LEARN_SGRID);
-        hipLaunchKernelGGL(learned_tilescan_kernel, dim3(1u << lbits), dim3(1024), 0, st, cnt, ntiles,
+        hipLaunchKernelGGL(learned_tilescan_kernel, dim3(1u << lbits), dim3(1024), tslds, st, cnt, ntiles,
                            (const unsigned *)(dstart + h * 128), (const unsigned *)ctrl);
         hipLaunchKernelGGL(learned_scatter_kernel, dim3(sgrid), dim3(SW_NT), slds, st,
                            (const double *)region, H, len, (const Feature *)feat, (const float *)tab, G, B, 0, lbits,
@@ -925,7 +949,7 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
         hipLaunchKernelGGL(learned_count_kernel, dim3(cgrid), dim3(SW_NT), clds, st, (const double *)H, len,
                            (const Feature *)feat, (const float *)tab, G, B, lbits, hbits, cnt, (unsigned *)nullptr,
                            (const unsigned *)ctrl);
-        hipLaunchKernelGGL(learned_tilescan_kernel, dim3(1u << hbits), dim3(1024), 0, st, cnt, ntiles,
+        hipLaunchKernelGGL(learned_tilescan_kernel, dim3(1u << hbits), dim3(1024), tslds, st, cnt, ntiles,
                            (const unsigned *)(dstart + h * 128 + 64), (const unsigned *)ctrl);
         hipLaunchKernelGGL(learned_scatter_kernel, dim3(sgrid), dim3(SW_NT), slds, st, (const double *)H,
                            region, len, (const Feature *)feat, (const float *)tab, G, B, lbits, hbits,

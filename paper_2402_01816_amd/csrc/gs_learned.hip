@@ -181,8 +181,8 @@ __global__ void learned_sample_kernel(const double *keys, int64_t n, int64_t S, 
 // ---------------------------------------------------------------------------
 // One work-group of 1024 threads.  lo/hi: smallest and largest non-NaN sample
 // key.  The feature whose FEAT_BINS-bin histogram of the sample has the
-// smaller largest bin wins (ties: linear).  Targets: log of the local density
-// of the sample in phi over a window of +-kDensH ranks.
+// smaller largest bin wins (ties: linear).  (The training inputs and targets
+// follow in learned_targets_kernel.)
 //
 // With `screen_half` > 0 (the half size the screening scales to) the sorted
 // sample's equal keys are screened first: equal keys (and all NaNs) always
@@ -191,8 +191,7 @@ __global__ void learned_sample_kernel(const double *keys, int64_t n, int64_t S, 
 // learns.  Such an input takes the plain path before any training (the
 // training and tabulation launches are gated on the fallback word).
 __global__ __launch_bounds__(1024) void learned_prep_kernel(const double *xs, int64_t S, int G, Feature *feat,
-                                                            float *u, float *t, unsigned *ctrl, int64_t screen_half,
-                                                            int B)
+                                                            unsigned *ctrl, int64_t screen_half, int B)
 {
     if (screen_half > 0) {
         __shared__ unsigned s_run;
@@ -227,7 +226,6 @@ __global__ __launch_bounds__(1024) void learned_prep_kernel(const double *xs, in
     __shared__ unsigned h_lin[FEAT_BINS], h_bits[FEAT_BINS];
     __shared__ int64_t s_nn;
     __shared__ unsigned s_max[2];
-    __shared__ Feature sF;
     const int tid = threadIdx.x;
     for (int i = tid; i < FEAT_BINS; i += 1024) h_lin[i] = h_bits[i] = 0u;
     if (tid == 0) {
@@ -282,29 +280,37 @@ __global__ __launch_bounds__(1024) void learned_prep_kernel(const double *xs, in
     if (tid == 0) {
         F.valid = (lin_ok || bits_ok) ? 1 : 0;
         F.bits = (!lin_ok || (bits_ok && s_max[1] < s_max[0])) ? 1 : 0;
-        sF = F;
         *feat = F;
         ctrl[L_FEAT] = (unsigned)F.bits;
     }
-    __syncthreads();
-    F = sF;
-    // inputs phi (NaN keys at the top), then log-density targets from the
-    // rank differences of the (non-decreasing) inputs
-    for (int64_t i = tid; i < S; i += 1024) {
-        double p = F.valid ? phi_of(xs[i], F) : 0.0;
-        if (xs[i] != xs[i]) p = 1.0;
-        p = p < 0.0 ? 0.0 : (p > 1.0 ? 1.0 : p);
-        u[i] = (float)p;
-    }
-    __syncthreads();
-    __threadfence_block();
-    for (int64_t i = tid; i < S; i += 1024) {
-        const int64_t lo = i - kDensH > 0 ? i - kDensH : 0;
-        const int64_t hi = i + kDensH < S - 1 ? i + kDensH : S - 1;
-        double w = (double)u[hi] - (double)u[lo];
-        w = w > 1e-7 ? w : 1e-7;
-        t[i] = (float)log((double)(hi - lo) / ((double)S * w));
-    }
+}
+
+// Training input of sample key i: phi (NaN keys at the top), clamped to
+// [0, 1] and rounded to float.
+__device__ __forceinline__ float train_input(double x, const Feature &F)
+{
+    double p = F.valid ? phi_of(x, F) : 0.0;
+    if (x != x) p = 1.0;
+    p = p < 0.0 ? 0.0 : (p > 1.0 ? 1.0 : p);
+    return (float)p;
+}
+
+// Inputs and log-density targets (from the rank differences of the
+// non-decreasing inputs over +-kDensH ranks), one thread per sample key; the
+// two neighbours' inputs are recomputed from their keys, so no pass waits on
+// another.
+__global__ __launch_bounds__(256) void learned_targets_kernel(const double *xs, int64_t S, const Feature *feat,
+                                                              float *u, float *t)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const Feature F = *feat;
+    u[i] = train_input(xs[i], F);
+    const int64_t lo = i - kDensH > 0 ? i - kDensH : 0;
+    const int64_t hi = i + kDensH < S - 1 ? i + kDensH : S - 1;
+    double w = (double)train_input(xs[hi], F) - (double)train_input(xs[lo], F);
+    w = w > 1e-7 ? w : 1e-7;
+    t[i] = (float)log((double)(hi - lo) / ((double)S * w));
 }
 
 // ---------------------------------------------------------------------------
@@ -852,8 +858,10 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     if (e != hipSuccess) return e;
     if (tr) trace_begin(TK_LEARN_PREP, st);
     const bool screening = prm.mode == 0 && !prm.test_bucket_table && prm.screen == 0;
-    hipLaunchKernelGGL(learned_prep_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample, L.S, G, feat, u,
-                       t, ctrl, screening ? n - n / 2 : (int64_t)0, B);
+    hipLaunchKernelGGL(learned_prep_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample, L.S, G, feat, ctrl,
+                       screening ? n - n / 2 : (int64_t)0, B);
+    hipLaunchKernelGGL(learned_targets_kernel, dim3((unsigned)((L.S + 255) / 256)), dim3(256), 0, st,
+                       (const double *)sample, L.S, (const Feature *)feat, u, t);
     if (tr) trace_end(st);
 
     // 3-4. network and knot table

@@ -316,3 +316,63 @@ def test_concurrent_streams(gs, orc):
     rk, rv = orc.sort_kv(k, v)
     assert np.array_equal(tk.cpu().numpy().view(np.uint64), rk)
     assert np.array_equal(tv.cpu().numpy().view(np.uint32), rv)
+
+
+@pytest.mark.parametrize("kv", [False, True])
+def test_graph_capture_replay(gs, orc, kv):
+    """The plain sort (Frogsort1) captured once into a HIP graph and replayed
+    on fresh inputs copied into the captured buffers -- unsorted, presorted
+    and reversed, so every replay takes a different branch of the on-device
+    order decision -- with eager work between replays; every replay is
+    checked against the oracle."""
+    torch = need_gpu()
+    n = (1 << 20) + 7
+    announce("graph capture", "kv" if kv else "f64", n)
+    if kv:
+        k0, v0 = W.kv_pattern("uniform", n, seed=3)
+        keys, vals = to_dev(k0.view(np.int64)), to_dev(v0.view(np.int32))
+        need = gs.gs_workspace_bytes_kv(n)
+    else:
+        keys, vals = to_dev(W.f64_pattern("uniform", n, seed=3)), None
+        need = gs.gs_workspace_bytes_f64(n)
+    ws_raw = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    o = (-ws_raw.data_ptr()) % 256
+    ws = ws_raw[o:o + need]
+
+    def call(stream):
+        if kv:
+            gs.gs_sort_kv(keys, vals, workspace=ws, stream=stream)
+        else:
+            gs.gs_sort_f64(keys, workspace=ws, stream=stream)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):                      # warm-up outside capture
+        call(s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        call(s)
+    for pattern in ("uniform", "presorted", "reversed", "tied"):
+        if kv:
+            k, v = W.kv_pattern("few" if pattern == "tied" else "uniform", n, seed=17)
+            if pattern == "presorted":
+                k = np.sort(k)
+            elif pattern == "reversed":
+                k = np.sort(k)[::-1].copy()
+            keys.copy_(torch.from_numpy(k.view(np.int64)))
+            vals.copy_(torch.from_numpy(v.view(np.int32)))
+        else:
+            x = W.f64_pattern(pattern, n, seed=17)
+            keys.copy_(torch.from_numpy(x))
+        _ = (keys * 2).sum()                        # unrelated eager work
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        if kv:
+            rk, rv = orc.sort_kv(k, v)
+            assert np.array_equal(keys.cpu().numpy().view(np.uint64), rk), pattern
+            assert np.array_equal(vals.cpu().numpy().view(np.uint32), rv), pattern
+        else:
+            assert np.array_equal(bits(keys), bits(orc.sort_f64(x))), pattern

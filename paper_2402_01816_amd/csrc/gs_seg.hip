@@ -125,6 +125,14 @@ __device__ __forceinline__ int64_t seg_first_after(const int64_t *offsets, int64
     return a;
 }
 
+// Last of the empty segments at offset o that start with segment s (the
+// loop then continues after it); never moves backwards, whatever the offsets.
+__device__ __forceinline__ int64_t seg_skip_empty(const int64_t *offsets, int64_t nseg, int64_t s, int64_t o)
+{
+    const int64_t next = seg_first_after(offsets, nseg, o);   // first segment ending past o
+    return next - 1 > s ? next - 1 : s;
+}
+
 // 0b. One work-group per SEG_RANGE keys of the array: every candidate
 // segment's pairs that start in the range are checked and their order bits
 // and-ed into cls[s], so a long segment is read by many work-groups at once.
@@ -140,6 +148,10 @@ __global__ __launch_bounds__(256) void seg_order_range_kernel(const typename KT:
     for (int64_t s = seg_first_after(offsets, nseg, r0); s < nseg; ++s) {
         const int64_t lo = offsets[s], hi = offsets[s + 1];
         if (lo >= r1) break;
+        if (hi == lo) {                              // past a run of empty segments at once
+            s = seg_skip_empty(offsets, nseg, s, lo);
+            continue;
+        }
         if (rank[s] != SEG_CANDIDATE || lo < 0 || hi < lo || hi > num_keys) continue;
         const int64_t a = lo > r0 ? lo : r0;
         const int64_t b = hi - 1 < r1 ? hi - 1 : r1;  // pairs (i, i+1) with i in [a, b)
@@ -205,6 +217,10 @@ __global__ __launch_bounds__(256) void seg_reverse_kernel(K *keys, const int64_t
     for (int64_t s = seg_first_after(offsets, nseg, r0); s < nseg; ++s) {
         const int64_t lo = offsets[s], hi = offsets[s + 1];
         if (lo >= r1) break;
+        if (hi == lo) {                              // past a run of empty segments at once
+            s = seg_skip_empty(offsets, nseg, s, lo);
+            continue;
+        }
         if (cls[s] != 0 || rank[s] != SEG_REVERSE) continue;
         const int64_t mid = lo + (hi - lo) / 2;     // lower halves: [lo, mid)
         const int64_t a = lo > r0 ? lo : r0;

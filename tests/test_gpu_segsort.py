@@ -215,6 +215,27 @@ def test_segsort_ordered_segments(gs, orc, kind):
     assert rep["invalid_offsets"] == 0
 
 
+def test_segsort_many_empty_segments(gs, orc):
+    """Runs of hundreds of thousands of empty segments around long presorted,
+    reversed and unsorted ones (the range passes jump over each run)."""
+    announce("segsort many empty")
+    rng = np.random.default_rng(5)
+    parts, lens = [], []
+    for kind in ("reversed", "sorted", "uniform", "reversed"):
+        lens += [0] * 200_000
+        m = int(rng.integers(40_000, 90_000))
+        u = np.sort(rng.random(m))
+        parts.append(u[::-1].copy() if kind == "reversed" else u if kind == "sorted" else rng.random(m))
+        lens.append(m)
+    lens += [0] * 1000
+    x = np.concatenate(parts)
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    t, rep = _run(gs, x, off, report=True)
+    _check(orc, t, x, off)
+    assert rep["invalid_offsets"] == 0
+
+
 def test_segsort_invalid_offsets_with_reversed_segments(gs):
     """Valid reversed segments around an invalid one: the call fails and
     nothing moves (the reversal waits for every segment's offsets)."""

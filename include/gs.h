@@ -38,6 +38,10 @@
  *     stream is capturing a graph.
  *   - Calls on different streams with different workspaces may run
  *     concurrently; two calls sharing one workspace must be ordered.
+ *   - Failures found on the device after a call has returned (a bounded wait
+ *     that gave up, a work capacity exceeded, rejected segment offsets) reach
+ *     the caller through the call's status when it asks for a report, and in
+ *     every case through the per-device flags of gs_device_errors (below).
  *
  * Comparison: float64 keys compare as IEEE `<` except that NaNs are greater
  * than every other value and tie with each other; -0.0 and +0.0 tie.  Keys are
@@ -230,6 +234,33 @@ gs_status gs_segsort_autotune(const double *keys, int64_t num_keys, const int64_
    state).  `p` is a host pointer (NULL = defaults). */
 gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p,
                           void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
+
+/* ---- device-side failures ------------------------------------------------ */
+/* Some failures happen on the device after a call has returned GS_OK, since
+   the calls are asynchronous:
+     GS_DEVERR_WAIT     a bounded wait of the ordered-store protocol gave up
+                        (the waiting work item stored anyway, so the output may
+                        be wrong), or a work capacity of the device-side plan was
+                        exceeded (that work was skipped); the in-place merges
+                        make such an output unusable;
+     GS_DEVERR_OFFSETS  a segmented sort rejected its offsets on the device
+                        (nothing was written).
+   A call made with a report synchronises and returns GS_EDEVICE (GS_EINVAL for
+   offsets).  Every call, with or without a report, also ORs what it met into
+   sticky flags kept in device memory, one set per device, for the life of the
+   process; this needs no workspace and no allocation. */
+#define GS_DEVERR_WAIT 1u
+#define GS_DEVERR_OFFSETS 2u
+/* Reads the flags of `device` into *flags and, with clear != 0, resets them.
+   Synchronous copies: call it after synchronising the streams of the calls it
+   is meant to cover.  GS_EINVAL for a device that does not exist. */
+gs_status gs_device_errors(int device, uint32_t *flags, int clear);
+/* Test hook, process-wide, for calls enqueued from now on: with on != 0 every
+   bounded wait that checks another work item waits as usual and is then
+   recorded as one that gave up, so the calls report GS_DEVERR_WAIT (and
+   GS_EDEVICE with a report) while their output stays correct; 0 restores
+   normal operation.  Returns the previous setting. */
+int gs_test_fail_waits(int on);
 
 const char *gs_status_string(gs_status s);
 /* Detail of the last error on the calling thread (never NULL). */

@@ -144,6 +144,8 @@ _OPTIONAL = {
     "gs_mlp_train": ([_P, _P, _P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_float,
                       ctypes.c_uint64, ctypes.c_int, _P, _P, _SZ, _P], ctypes.c_int),
     "gs_mlp_forward": ([_P, _P, _I64, _P, _P], ctypes.c_int),
+    "gs_device_errors": ([ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int], ctypes.c_int),
+    "gs_test_fail_waits": ([ctypes.c_int], ctypes.c_int),
     "gs_trace_enable": ([ctypes.c_int], ctypes.c_int),
     "gs_trace_read": ([ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), ctypes.c_int],
                       ctypes.c_int),
@@ -264,7 +266,18 @@ def _torch():
     return torch
 
 
-def _workspace(nbytes: int, device, workspace=None):
+def _on_stream(stream, *tensors):
+    """Temporaries allocated here on the current stream but used by a call
+    on another stream: tell torch's caching allocator, so it does not hand
+    their memory out again before the work queued on that stream is done."""
+    if stream is None:
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
+def _workspace(nbytes: int, device, workspace=None, stream=None):
     torch = _torch()
     if nbytes == 0:
         return None, 0
@@ -273,6 +286,7 @@ def _workspace(nbytes: int, device, workspace=None):
             raise ValueError("workspace must be a uint8 tensor on the keys' device")
         return workspace, workspace.numel()
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    _on_stream(stream, ws)
     off = (-ws.data_ptr()) % 256
     return ws[off: off + nbytes], nbytes
 
@@ -322,7 +336,7 @@ def gs_sort_f64(keys, buffer_fraction: float = 0.5, workspace=None, stream=None,
     need = gs_workspace_bytes_f64(n, buffer_fraction, algo, sub_fraction)
     if need == SIZE_MAX:
         need = 0
-    ws, wsb = _workspace(need, keys.device, workspace)
+    ws, wsb = _workspace(need, keys.device, workspace, stream)
     r = _rep(report)
     st = _lib.gs_sort_f64_ex(kp, n, _target(target), buffer_fraction, _algo(algo), sub_fraction,
                              ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
@@ -347,7 +361,7 @@ def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=
     need = gs_workspace_bytes_kv(n, buffer_fraction, algo, sub_fraction)
     if need == SIZE_MAX:
         need = 0
-    ws, wsb = _workspace(need, keys.device, workspace)
+    ws, wsb = _workspace(need, keys.device, workspace, stream)
     r = _rep(report)
     st = _lib.gs_sort_kv_ex(kp, vp, n, _target(target), buffer_fraction, _algo(algo), sub_fraction,
                             ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
@@ -391,7 +405,7 @@ def gs_segsort(keys, offsets, buffer_fraction: float = 0.5, workspace=None, stre
     need = gs_workspace_bytes_seg(n, nseg, buffer_fraction)
     if need == SIZE_MAX:
         need = 0
-    ws, wsb = _workspace(need, keys.device, workspace)
+    ws, wsb = _workspace(need, keys.device, workspace, stream)
     r = _rep(report)
     st = _lib.gs_segsort_ex(kp, n, op, nseg, buffer_fraction,
                             ctypes.byref(cfg) if cfg is not None else None,
@@ -412,9 +426,10 @@ def gs_segsort_autotune(keys, offsets, reps: int = 2, workspace=None, scratch=No
     need = gs_workspace_bytes_seg(n, nseg, 0.5)
     if need == SIZE_MAX:
         need = 0
-    ws, wsb = _workspace(need, keys.device, workspace)
+    ws, wsb = _workspace(need, keys.device, workspace, stream)
     if scratch is None:
         scratch = torch.empty_like(keys)
+        _on_stream(stream, scratch)
     count = _lib.gs_seg_config_count()
     times = (ctypes.c_float * count)()
     best = GsSegConfig()
@@ -438,13 +453,34 @@ def gs_learned_sort(keys, params: GsLearnedParams | None = None, workspace=None,
     need = gs_workspace_bytes_learned(n, p)
     if need == SIZE_MAX:
         need = 0
-    ws, wsb = _workspace(need, keys.device, workspace)
+    ws, wsb = _workspace(need, keys.device, workspace, stream)
     r = _rep(report)
     st = _lib.gs_learned_sort(kp, n, ctypes.byref(p),
                               ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, wsb,
                               _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_learned_sort")
     return r.as_dict() if r is not None else None
+
+
+# ---------------------------------------------------------------------------
+# device-side failures
+# ---------------------------------------------------------------------------
+GS_DEVERR_WAIT = 1
+GS_DEVERR_OFFSETS = 2
+
+
+def gs_device_errors(device=0, clear=False) -> int:
+    """The device's sticky failure flags (GS_DEVERR_*) of every call so far;
+    synchronise the calls' streams first."""
+    flags = ctypes.c_uint32(0)
+    _check(_lib.gs_device_errors(int(device), ctypes.byref(flags), 1 if clear else 0), "gs_device_errors")
+    return int(flags.value)
+
+
+def gs_test_fail_waits(on: bool) -> bool:
+    """Test hook: record every ordered-store wait as failed (the waits still
+    complete, the output stays correct); returns the previous setting."""
+    return bool(_lib.gs_test_fail_waits(1 if on else 0))
 
 
 # ---------------------------------------------------------------------------
@@ -462,6 +498,7 @@ def gs_mlp_loss_grad(params, u, t, stream=None):
     grad = torch.empty(MLP_NUM_PARAMS, dtype=torch.float32, device=params.device)
     loss = torch.empty(1, dtype=torch.float32, device=params.device)
     work = torch.empty((batch // 32 + 1) * (MLP_NUM_PARAMS + 1), dtype=torch.float32, device=params.device)
+    _on_stream(stream, grad, loss, work)
     st = _lib.gs_mlp_loss_grad(_f32(params, "params"), _f32(u, "u"), _f32(t, "t"), batch,
                                _f32(grad, "grad"), _f32(loss, "loss"), _f32(work, "work"),
                                work.numel() * 4, _stream_ptr(stream, params.device))
@@ -476,6 +513,7 @@ def gs_mlp_train(params, adam_m, adam_v, u, t, steps, batch, lr, seed=0, full_ba
     losses = torch.zeros(2, dtype=torch.float32, device=params.device)
     work = torch.empty((batch // 32) * (MLP_NUM_PARAMS + 1) + 64, dtype=torch.float32,
                        device=params.device)
+    _on_stream(stream, losses, work)
     st = _lib.gs_mlp_train(_f32(params, "params"), _f32(adam_m, "m"), _f32(adam_v, "v"),
                            _f32(u, "u"), _f32(t, "t"), u.numel(), steps, batch, lr, seed,
                            1 if full_batch else 0, _f32(losses, "losses"), _f32(work, "work"),
@@ -487,6 +525,7 @@ def gs_mlp_train(params, adam_m, adam_v, u, t, steps, batch, lr, seed=0, full_ba
 def gs_mlp_forward(params, u, stream=None):
     torch = _torch()
     y = torch.empty_like(u)
+    _on_stream(stream, y)
     st = _lib.gs_mlp_forward(_f32(params, "params"), _f32(u, "u"), u.numel(), _f32(y, "y"),
                              _stream_ptr(stream, params.device))
     _check(st, "gs_mlp_forward")

@@ -219,6 +219,34 @@ int gs_trace_read(int *kinds, double *ms, int max)
     return k < max ? k : max;
 }
 
+gs_status gs_device_errors(int device, uint32_t *flags, int clear)
+{
+    g_detail.clear();
+    if (!flags) return fail(GS_EINVAL, "flags is NULL");
+    *flags = 0;
+    gs_status s = check_device();
+    if (s != GS_OK) return s;
+    int count = 0, cur = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return fail(GS_EINVAL, "no device %d", device);
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "selecting the device");
+    unsigned f = 0;
+    e = gs::sticky_errors_read(&f, clear != 0);
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "reading the device error flags");
+    *flags = f;
+    return GS_OK;
+}
+
+int gs_test_fail_waits(int on)
+{
+    const unsigned was = gs::test_wait_word();
+    gs::set_test_wait_word(on ? 1u : 0u);
+    return (was & 1u) ? 1 : 0;
+}
+
 const char *gs_status_string(gs_status s)
 {
     switch (s) {
@@ -729,8 +757,10 @@ gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p, v
         rep->train_loss_first = lr.loss_first;
         rep->train_loss_last = lr.loss_last;
         rep->feature = lr.feature;
-        if (lr.err) return fail(GS_EDEVICE, "a bounded device wait gave up during training");
-        s = check_err_word((const char *)ws, L.plain);
+        unsigned any = 0;
+        hipError_t e3 = gs::learned_errors((const char *)ws, L, &any);
+        if (e3 != hipSuccess) return hip_fail(e3, "reading the error words");
+        if (any) return fail(GS_EDEVICE, "a bounded device wait gave up or a work capacity was exceeded");
     }
     return s;
 }

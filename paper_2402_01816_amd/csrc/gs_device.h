@@ -238,17 +238,23 @@ __device__ __forceinline__ void st_status(unsigned *p, unsigned v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Every wait is bounded: a wait that exceeds kSpinLimit polls sets *err (the
-// call then reports a device error) and gives up, so no wave spins forever.
+// Every wait is bounded: a wait whose status has not arrived after
+// kSpinLimit polls sets *err (the call then reports a device error) and gives
+// up, so no wave spins forever.  The word before *err is a test setting
+// written from the host: with bit 0 set, every wait that checks another work
+// item still waits as usual but then sets *err as if it had given up (the
+// error paths run while the output stays correct).
 constexpr unsigned kSpinLimit = 1u << 22;
 
 // Called by one full wavefront: returns once every ticket in [lo, hi] other
-// than `self` has published its loaded status for `epoch`.
+// than `self` has published its loaded status for `epoch`, or the limit ran
+// out.
 __device__ __forceinline__ void wait_window(const unsigned *status, int64_t lo, int64_t hi,
                                             int64_t self, unsigned epoch, unsigned *err)
 {
     const int lane = threadIdx.x & 63;
     const unsigned want = epoch << 2;
+    const bool force_fail = (ld_status(err - 1) & 1u) != 0;
     for (int64_t base = lo; base <= hi; base += 64) {
         const int64_t idx = base + lane;
         if (idx <= hi && idx != self) {
@@ -259,7 +265,7 @@ __device__ __forceinline__ void wait_window(const unsigned *status, int64_t lo, 
                 st = ld_status(status + idx);
                 ++spins;
             }
-            if (spins >= kSpinLimit)
+            if ((st & ~3u) != want || force_fail)
                 __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }

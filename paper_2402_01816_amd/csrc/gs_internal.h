@@ -11,8 +11,44 @@
 namespace gs {
 
 // Index (in the ticket-counter block) of the word the kernels set when a
-// bounded wait gave up; it is cleared with the counters on every call.
+// bounded wait gave up or a work capacity was exceeded.  The clearing at the
+// start of every forest run keeps it, so it collects every run of a call; the
+// call clears it once when it starts (err_words_begin).
 constexpr int kErrWord = 63;
+// The word before it: the test setting of the bounded waits (bit 0: record
+// every wait that checked another work item as failed).  Every forest run
+// writes it from the host's setting.
+constexpr int kTestWord = kErrWord - 1;
+
+// Flags of the device-side failures a call can meet (gs_device_errors).
+enum : unsigned { DEVERR_WAIT = 1u, DEVERR_OFFSETS = 2u };
+
+// The error words of one call: cleared by err_words_begin before the call's
+// first kernel; err_words_end ORs bit[i] into the device's sticky flags for
+// every word that is set once the call's kernels have run.
+struct ErrWords {
+    unsigned *w[4];
+    unsigned bit[4];
+    int count;
+    void add(unsigned *word, unsigned b)
+    {
+        if (count < 4) {
+            w[count] = word;
+            bit[count] = b;
+            ++count;
+        }
+    }
+};
+hipError_t err_words_begin(const ErrWords &e, hipStream_t st);
+hipError_t err_words_end(const ErrWords &e, hipStream_t st);
+// The device's sticky flags (current device); read and optionally clear them.
+hipError_t sticky_errors_read(unsigned *flags, bool clear);
+// Test setting of the bounded waits (the value of kTestWord).
+unsigned test_wait_word();
+void set_test_wait_word(unsigned w);
+// Clears a forest control block of `count` words except kTestWord, which
+// gets the test setting, and kErrWord, which is kept.
+void launch_fill_ctrl(unsigned *ctrl, int64_t count, hipStream_t st);
 
 // Control words of a forest run: the leaf ticket counter (word 0), the
 // error word, and per merge round r >= 1 kMergeGroups ticket counters, each on
@@ -181,10 +217,8 @@ hipError_t sort_f64_target_async(double *keys, int64_t n, int target, char *ws, 
 hipError_t sort_kv_target_async(uint64_t *keys, uint32_t *vals, int64_t n, int target, char *ws, const SortPlan &p,
                                 hipStream_t st);
 void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st);
-// One explicit merge node over the logical space {D, H, n_space}, using the
-// control area of a plain plan at least as large as the node.
-hipError_t merge_one_f64_async(double *D, double *H, int64_t n_space, const FrogMerge &m, char *ws,
-                               const SortPlan &p, hipStream_t st, const unsigned *gate, unsigned run_if);
+// The error word of a plain plan's control area.
+ErrWords plain_err_words(char *ws, const SortPlan &p);
 
 // Launch tracing (measurement only).  When enabled on the calling thread,
 // launchers bracket every kernel launch with HIP events on its stream.

@@ -45,5 +45,8 @@ LearnedPlan plan_learned(int64_t n, const gs_learned_params &prm);
 hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &prm, char *ws,
                               const LearnedPlan &L, hipStream_t st);
 hipError_t learned_read_report(const char *ws, const LearnedPlan &L, LearnedReport *r);
+// After the stream is synchronised: the DEVERR_* flags of every error word
+// of the call (0: none set).
+hipError_t learned_errors(const char *ws, const LearnedPlan &L, unsigned *any);
 
 }  // namespace gs

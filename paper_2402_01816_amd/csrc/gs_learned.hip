@@ -823,8 +823,8 @@ LearnedPlan plan_learned(int64_t n, const gs_learned_params &prm)
     return L;
 }
 
-hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &prm, char *ws,
-                              const LearnedPlan &L, hipStream_t st)
+static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_params &prm, char *ws,
+                                    const LearnedPlan &L, hipStream_t st)
 {
     if (!L.use_learned) return sort_f64_async(keys, n, ws, L.plain, st);
     const int B = L.B, G = L.G;
@@ -999,6 +999,45 @@ hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &
     e = sort_f64_async(keys, n, ws, L.plain, st, ctrl + L_FALLBACK, 1u);
     if (e != hipSuccess) return e;
     return hipGetLastError();
+}
+
+// The error words of every control area the call uses: the plain plan's
+// (fallback sort and final merge), the sample sort's, the bucket forest's and
+// the training barrier's.
+static ErrWords learned_err_words(char *ws, const LearnedPlan &L)
+{
+    ErrWords ew = plain_err_words(ws, L.plain);
+    if (L.use_learned) {
+        ew.add((unsigned *)(ws + L.off_sample_ws + L.splan.off_forest + L.splan.forest.off_ctrl) + kErrWord,
+               DEVERR_WAIT);
+        ew.add((unsigned *)(ws + L.off_segforest + L.segforest.off_ctrl) + kErrWord, DEVERR_WAIT);
+        ew.add((unsigned *)(ws + L.off_ctrl) + L_ERR, DEVERR_WAIT);
+    }
+    return ew;
+}
+
+hipError_t learned_sort_async(double *keys, int64_t n, const gs_learned_params &prm, char *ws,
+                              const LearnedPlan &L, hipStream_t st)
+{
+    const ErrWords ew = learned_err_words(ws, L);
+    hipError_t e = err_words_begin(ew, st);
+    if (e != hipSuccess) return e;
+    e = learned_sort_body(keys, n, prm, ws, L, st);
+    if (e != hipSuccess) return e;
+    return err_words_end(ew, st);
+}
+
+hipError_t learned_errors(const char *ws, const LearnedPlan &L, unsigned *any)
+{
+    const ErrWords ew = learned_err_words((char *)ws, L);
+    *any = 0;
+    for (int i = 0; i < ew.count; ++i) {
+        unsigned w = 0;
+        hipError_t e = hipMemcpy(&w, ew.w[i], 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return e;
+        *any |= w ? ew.bit[i] : 0u;
+    }
+    return hipSuccess;
 }
 
 hipError_t learned_read_report(const char *ws, const LearnedPlan &L, LearnedReport *r)

@@ -534,9 +534,18 @@ hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg
 hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan &p, char *ws,
                              hipStream_t st)
 {
-    return segsort_run(keys, offsets, p.nseg, p.num_keys, (double *)(ws + p.off_h), (unsigned *)(ws + p.off_ctrl),
-                       (int *)(ws + p.off_cls), (int *)(ws + p.off_rank), (int *)(ws + p.off_list),
-                       ws + p.off_forest, p.forest, p.cfg, true, nullptr, 0u, st);
+    // the forest's error word; the offsets flag (control word 0) is set by
+    // the run itself before anything else reads it
+    ErrWords ew{};
+    ew.add((unsigned *)(ws + p.off_forest + p.forest.off_ctrl) + kErrWord, DEVERR_WAIT);
+    hipError_t e = err_words_begin(ew, st);
+    if (e != hipSuccess) return e;
+    e = segsort_run(keys, offsets, p.nseg, p.num_keys, (double *)(ws + p.off_h), (unsigned *)(ws + p.off_ctrl),
+                    (int *)(ws + p.off_cls), (int *)(ws + p.off_rank), (int *)(ws + p.off_list),
+                    ws + p.off_forest, p.forest, p.cfg, true, nullptr, 0u, st);
+    if (e != hipSuccess) return e;
+    ew.add((unsigned *)(ws + p.off_ctrl), DEVERR_OFFSETS);
+    return err_words_end(ew, st);
 }
 
 }  // namespace gs

@@ -408,7 +408,15 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
         T.pa = T.pb = T.o = 0;
         int64_t lo = 1, hi = 0;          // empty window
         if (k0 < k1) {
-            const int64_t a0 = sp[j], a1 = sp[j + 1];
+            // Splits of sorted runs are monotone and every tile takes between
+            // 0 and cnt elements from each run; the clamp keeps the
+            // descriptor within the runs whatever they hold (it changes
+            // nothing for sorted runs).
+            const int64_t a0 = sp[j];
+            int64_t a1 = sp[j + 1];
+            const int64_t a1lo = a0 > k1 - m.nr ? a0 : k1 - m.nr;
+            const int64_t a1hi = a0 + (k1 - k0) < m.nl ? a0 + (k1 - k0) : m.nl;
+            a1 = a1 < a1lo ? a1lo : a1 > a1hi ? a1hi : a1;
             T.la = (int)(a1 - a0);
             T.pa = m.l0 + a0;
             T.pb = m.r0 + (k0 - a0);
@@ -440,6 +448,12 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
                     hi = first + j1;
                 }
             }
+        }
+        // the window lies within the node's tickets and never passes the
+        // tile's own (again a no-op for sorted runs)
+        if (lo <= hi) {
+            lo = lo < first ? first : lo;
+            hi = hi > t ? t : hi;
         }
         T.dlo = (unsigned)lo;
         T.dhi = (unsigned)hi;
@@ -830,9 +844,10 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
     }
 
     const bool tr = trace_on();
-    // ticket counters and status words start at zero on every call
+    // ticket counters and status words start at zero on every run (the
+    // call's error word is kept, so it collects every run of the call)
     if (tr) trace_begin(TK_FILL, st);
-    launch_fill_u32(ctrl, (fp.off_splits - fp.off_ctrl) / 4, 0u, st);
+    launch_fill_ctrl(ctrl, (fp.off_splits - fp.off_ctrl) / 4, st);
     if (tr) trace_end(st);
     if (table) {
         if (tr) trace_begin(TK_OTHER, st);
@@ -1121,27 +1136,44 @@ static hipError_t run_sort_adaptive(typename KT::T *keys, V *vals, int64_t n, ch
     return hipGetLastError();
 }
 
+ErrWords plain_err_words(char *ws, const SortPlan &p)
+{
+    ErrWords e{};
+    e.add((unsigned *)(ws + p.off_forest + p.forest.off_ctrl) + kErrWord, DEVERR_WAIT);
+    return e;
+}
+
 hipError_t sort_f64_target_async(double *keys, int64_t n, int target, char *ws, const SortPlan &p, hipStream_t st)
 {
+    if (n <= 1) return hipSuccess;
+    const ErrWords ew = plain_err_words(ws, p);
+    hipError_t e = err_words_begin(ew, st);
+    if (e != hipSuccess) return e;
     // targets: 0 AscLeft, 1 AscRight = reversed DescLeft, 2 DescLeft,
     // 3 DescRight = reversed AscLeft
-    hipError_t e = (target == 1 || target == 2)
-                       ? run_sort_adaptive<KeyF64Desc, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st)
-                       : run_sort_adaptive<KeyF64, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st);
+    e = (target == 1 || target == 2) ? run_sort_adaptive<KeyF64Desc, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st)
+                                     : run_sort_adaptive<KeyF64, NoVal>(keys, (NoVal *)nullptr, n, ws, p, st);
     if (e != hipSuccess) return e;
     if (target == 1 || target == 3) launch_reverse(keys, (NoVal *)nullptr, n, st);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return err_words_end(ew, st);
 }
 
 hipError_t sort_kv_target_async(uint64_t *keys, uint32_t *vals, int64_t n, int target, char *ws, const SortPlan &p,
                                 hipStream_t st)
 {
-    hipError_t e = (target == 1 || target == 2)
-                       ? run_sort_adaptive<KeyU64Desc, uint32_t>(keys, vals, n, ws, p, st)
-                       : run_sort_adaptive<KeyU64, uint32_t>(keys, vals, n, ws, p, st);
+    if (n <= 1) return hipSuccess;
+    const ErrWords ew = plain_err_words(ws, p);
+    hipError_t e = err_words_begin(ew, st);
+    if (e != hipSuccess) return e;
+    e = (target == 1 || target == 2) ? run_sort_adaptive<KeyU64Desc, uint32_t>(keys, vals, n, ws, p, st)
+                                     : run_sort_adaptive<KeyU64, uint32_t>(keys, vals, n, ws, p, st);
     if (e != hipSuccess) return e;
     if (target == 1 || target == 3) launch_reverse(keys, vals, n, st);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return err_words_end(ew, st);
 }
 
 hipError_t forest_f64_async(double *D, double *H, const Prob *probs, const unsigned *nprob, const ForestPlan &fp,

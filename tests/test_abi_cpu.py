@@ -277,3 +277,25 @@ def test_algo_argument_errors():
     n = (1 << 22) + 5
     assert g.gs_workspace_bytes_f64(n, 0.1, "frogsort6", 0.5) == g.gs_workspace_bytes_f64(n, 0.1, "frogsort3")
     assert g.plan_frog3(n, 0.25, sub_fraction=0.2)[3][1] == 0
+
+
+def test_device_error_query_without_device():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is visible")
+    except ImportError:
+        pass
+    flags = ctypes.c_uint32(7)
+    assert g.lib.gs_device_errors(0, ctypes.byref(flags), 0) == g.GS_ENODEVICE
+    assert flags.value == 0
+    assert g.lib.gs_device_errors(0, None, 0) == g.GS_EINVAL
+
+
+def test_fail_waits_hook_toggles():
+    was = g.gs_test_fail_waits(True)
+    try:
+        assert g.gs_test_fail_waits(True) is True
+    finally:
+        g.gs_test_fail_waits(was)
+    assert g.gs_test_fail_waits(was) is was

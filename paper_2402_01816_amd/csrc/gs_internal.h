@@ -219,6 +219,10 @@ hipError_t sort_kv_target_async(uint64_t *keys, uint32_t *vals, int64_t n, int t
 void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st);
 // The error word of a plain plan's control area.
 ErrWords plain_err_words(char *ws, const SortPlan &p);
+// One explicit merge node over the logical space {D, H, n_space}, using the
+// control area of a plain plan at least as large as the node.
+hipError_t merge_one_f64_async(double *D, double *H, int64_t n_space, const FrogMerge &m, char *ws,
+                               const SortPlan &p, hipStream_t st, const unsigned *gate, unsigned run_if);
 
 // Launch tracing (measurement only).  When enabled on the calling thread,
 // launchers bracket every kernel launch with HIP events on its stream.

@@ -66,6 +66,8 @@ def _load():
     lib.oracle_rank_u64.restype = None
     lib.oracle_frog_model.argtypes = [P, I64, ctypes.c_int, P, P, P, P, I64, P]
     lib.oracle_frog_model.restype = I64
+    lib.oracle_squid_model.argtypes = [P, I64, ctypes.c_int, P, P, P]
+    lib.oracle_squid_model.restype = I64
     lib.oracle_frog_geometry.argtypes = [I64, ctypes.c_int, P]
     lib.oracle_frog_geometry.restype = I64
     lib.oracle_frog2_model.argtypes = [P, I64, I64, I64, I64, P, P, P, P, I64, P, I64, P, I64, P]
@@ -210,6 +212,30 @@ def frog_model(keys: np.ndarray, g: int = 1, max_snap: int = 0):
         "trace": trace[: int(counts[2]), :nslots], "compares": int(counts[0]),
         "moves": int(counts[1]), "nslots": int(ns),
     }
+
+
+SQUID_NONE, SQUID_ASC, SQUID_DESC = 0, 1, 2
+
+
+def squid_model(keys: np.ndarray, mode: int = 0):
+    """Run the instrumented Squidsort1 model (one element per leaf).
+
+    Returns (sorted keys, input index of each output, counts) with counts a
+    dict: merge_cmp, test_cmp, moves (merges and concatenations), rev_moves
+    (final reversal), top_dir (SQUID_*), overwrites (writes over unread
+    elements).  mode 1 enforces ascending at every merge (the literal
+    reading; shows why the model merges in the outer run's direction)."""
+    lib = _load()
+    x = np.ascontiguousarray(keys, dtype=np.float64)
+    n = x.size
+    out = np.zeros(n, dtype=np.float64)
+    lab = np.zeros(n, dtype=np.int64)
+    c = np.zeros(6, dtype=np.int64)
+    r = lib.oracle_squid_model(_ptr(x), n, int(mode), _ptr(out), _ptr(lab), _ptr(c))
+    if r < 0:
+        raise MemoryError("oracle_squid_model")
+    names = ("merge_cmp", "test_cmp", "moves", "rev_moves", "top_dir", "overwrites")
+    return out, lab, {k: int(v) for k, v in zip(names, c)}
 
 
 def frog_geometry(n: int, depth: int) -> np.ndarray:

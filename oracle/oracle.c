@@ -22,6 +22,9 @@
  *   - oracle_frog_*  : an instrumented model of the paper's Frogsort0/Frogsort1
  *     recursion ("Symmetric merging", "Frogsort0", "Frogsort1") used only to
  *     pin the memory layout and the adaptivity counts the paper states.
+ *   - oracle_squid_* : the same for Squidsort1 ("Squidsort": Frogsort1 with the
+ *     non-overlap test of "Full adaptivity" and Octosort's data-driven,
+ *     lazily enforced order), checking every write against unread elements.
  *   - oracle_frog2_* : the same for Frogsort2 ("Frogsort2": imbalanced splits,
  *     buffer p), checking on every write that the smaller buffer suffices.
  *   - oracle_frog3_* : the same for Frogsort3 / Frogsort6 (the buffer shared by
@@ -490,6 +493,182 @@ static int64_t frog_geom(int64_t s, int64_t n, int left, int depth, int64_t in_o
 int64_t oracle_frog_geometry(int64_t n, int depth, int64_t *out)
 {
     return frog_geom(0, n, 1, depth, 0, out, 0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* instrumented model of Squidsort1 (Frogsort1 + non-overlap test + lazy order) */
+/* ------------------------------------------------------------------------ */
+/*
+ * "Squidsort": Frogsort1 combined with the non-overlap test of "Full
+ * adaptivity" (Omitsort: a merge whose two inputs do not overlap is left out)
+ * and the data-driven order of Octosort (a run may come back ascending or
+ * descending, and the wanted order is enforced lazily).
+ *
+ * Every node returns the direction of its run: SQ_NONE for a single element,
+ * SQ_ASC (the run holds the stable ascending result of the node's input) or
+ * SQ_DESC (the run holds that result reversed).  With the two children's
+ * ascending views SL and SR (a descending run is read from its end):
+ *   - both not descending and SR[0] not less than SL[last]: the node is the
+ *     concatenation, ascending; nothing is compared beyond the test and only
+ *     the inner run moves (next to the outer one);
+ *   - else, both not ascending and SR[last] less than SL[0]: the
+ *     concatenation of the two stored runs is the reversed result, so the
+ *     node is descending, again moving only the inner run;
+ *   - else the node merges.  Its direction is the outer child's (ascending
+ *     if that is a single element): the paper enforces the wanted order when
+ *     the children's directions differ, but in the frog layout the outer run
+ *     lies inside the output, and only a merge in the outer run's own
+ *     direction moves its elements away from the side the output is written
+ *     from.  The inner run is read in whichever direction the merge needs.
+ *     The wanted order is then enforced once, by reversing the whole array if
+ *     the top node ends descending.
+ * mode 1 enforces ascending at every merge instead (the literal reading);
+ * the write check then finds outer elements overwritten before they are read.
+ *
+ * Writes go in the frog order (left node top-down, right node bottom-up) and
+ * every write is checked: a slot that still holds an element not yet read is
+ * a violation (counted; the model carries on).
+ */
+enum { SQ_NONE = 0, SQ_ASC = 1, SQ_DESC = 2 };
+
+typedef struct {
+    double  *key;
+    int64_t *lab;
+    char    *live;      /* slot holds a run element not yet read */
+    int64_t  cmp;       /* merge comparisons                      */
+    int64_t  test;      /* non-overlap test comparisons           */
+    int64_t  mov;       /* moves of merges and concatenations      */
+    int64_t  bad;       /* writes over an element not yet read     */
+    int      mode;
+} squid_model;
+
+static double sq_view(const squid_model *M, int64_t base, int64_t n, int dir, int64_t i)
+{
+    return M->key[dir == SQ_DESC ? base + n - 1 - i : base + i];
+}
+
+static int64_t sq_slot(int64_t base, int64_t n, int dir, int64_t i)
+{
+    return dir == SQ_DESC ? base + n - 1 - i : base + i;
+}
+
+static void sq_put(squid_model *M, int64_t dst, int64_t src)
+{
+    M->live[src] = 0;                   /* read first: a run element may stay */
+    if (M->live[dst]) M->bad++;
+    if (dst != src) {
+        M->key[dst] = M->key[src];
+        M->lab[dst] = M->lab[src];
+        M->mov++;
+    }
+}
+
+static int squid_node(squid_model *M, int64_t s, int64_t n, int left)
+{
+    if (n == 1) return SQ_NONE;
+    const int64_t nl = left ? (n + 1) / 2 : n / 2, nr = n - nl;
+    const int64_t reg = n + n / 2;
+    const int dL = squid_node(M, s, nl, 1);
+    const int dR = squid_node(M, s + reg - (nr + nr / 2), nr, 0);
+    const int64_t Lb = s, Rb = s + reg - nr, out0 = left ? s : s + reg - n;
+    for (int64_t p = Lb; p < Lb + nl; p++) M->live[p] = 1;
+    for (int64_t p = Rb; p < Rb + nr; p++) M->live[p] = 1;
+    int dir = SQ_ASC, concat = 0;
+    if (dL != SQ_DESC && dR != SQ_DESC) {
+        M->test++;
+        if (!oracle_less_f64(sq_view(M, Rb, nr, dR, 0), sq_view(M, Lb, nl, dL, nl - 1))) concat = 1;
+    }
+    if (!concat && dL != SQ_ASC && dR != SQ_ASC) {
+        M->test++;
+        if (oracle_less_f64(sq_view(M, Rb, nr, dR, nr - 1), sq_view(M, Lb, nl, dL, 0))) {
+            concat = 1;
+            dir = SQ_DESC;
+        }
+    }
+    if (concat) {
+        /* the stored runs side by side: the outer one stays, the inner moves */
+        if (left) for (int64_t j = nr - 1; j >= 0; j--) sq_put(M, s + nl + j, Rb + j);
+        else      for (int64_t i = 0; i < nl; i++) sq_put(M, out0 + i, Lb + i);
+        for (int64_t p = Lb; p < Lb + nl; p++) M->live[p] = 0;
+        for (int64_t p = Rb; p < Rb + nr; p++) M->live[p] = 0;
+        return dir;
+    }
+    const int douter = left ? dL : dR;
+    dir = (M->mode == 0 && douter == SQ_DESC) ? SQ_DESC : SQ_ASC;
+    /* The stable ascending merge M of SL and SR takes SL first on ties; slot
+       out0+k receives M[k] (ascending) or M[n-1-k] (descending).  The write
+       order decides which end of M is produced first. */
+    const int smallest_first = left ? (dir == SQ_DESC) : (dir == SQ_ASC);
+    int64_t i, j, ie, je, step;
+    if (smallest_first) { i = 0; j = 0; ie = nl; je = nr; step = 1; }
+    else                { i = nl - 1; j = nr - 1; ie = -1; je = -1; step = -1; }
+    for (int64_t k = 0; k < n; k++) {
+        int takeL;
+        if (i == ie) takeL = 0;
+        else if (j == je) takeL = 1;
+        else {
+            M->cmp++;
+            const double a = sq_view(M, Lb, nl, dL, i), b = sq_view(M, Rb, nr, dR, j);
+            /* from the small end L wins ties; from the large end R's tied
+               elements come out first (they follow L's in M) */
+            takeL = smallest_first ? !oracle_less_f64(b, a) : oracle_less_f64(b, a);
+        }
+        const int64_t mpos = smallest_first ? k : n - 1 - k;           /* position in M */
+        const int64_t w = (dir == SQ_ASC) ? out0 + mpos : out0 + (n - 1 - mpos);
+        const int64_t src = takeL ? sq_slot(Lb, nl, dL, i) : sq_slot(Rb, nr, dR, j);
+        sq_put(M, w, src);
+        if (takeL) i += step; else j += step;
+    }
+    for (int64_t p = Lb; p < Lb + nl; p++) M->live[p] = 0;
+    for (int64_t p = Rb; p < Rb + nr; p++) M->live[p] = 0;
+    return dir;
+}
+
+/*
+ * Run the Squidsort1 model on in[0, n) (elements placed by the Frogsort1 setup
+ * recursion, one element per leaf).  mode 0: the reading above; mode 1:
+ * ascending enforced at every merge.
+ *   out_key, out_label: the n results and the input index of each (after the
+ *                       final reversal when the top node is descending)
+ *   counts: {merge comparisons, test comparisons, merge and concatenation
+ *            moves, final-reversal moves, direction of the top node,
+ *            overwrites of unread elements}
+ * Returns the number of slots, or -1 on allocation failure.
+ */
+int64_t oracle_squid_model(const double *in, int64_t n, int mode, double *out_key, int64_t *out_label,
+                           int64_t *counts)
+{
+    for (int c = 0; c < 6; c++) counts[c] = 0;
+    if (n <= 0) return 0;
+    frog_model F;
+    memset(&F, 0, sizeof F);
+    F.g = 1;
+    F.nslots = frog_region(&F, n);
+    F.key = (double *)calloc((size_t)F.nslots, sizeof(double));
+    F.lab = (int64_t *)malloc((size_t)F.nslots * sizeof(int64_t));
+    char *live = (char *)calloc((size_t)F.nslots, 1);
+    if (!F.key || !F.lab || !live) { free(F.key); free(F.lab); free(live); return -1; }
+    for (int64_t p = 0; p < F.nslots; p++) F.lab[p] = -1;
+    frog_setup(&F, in, 0, 0, n, 1);
+    squid_model M;
+    memset(&M, 0, sizeof M);
+    M.key = F.key; M.lab = F.lab; M.live = live; M.mode = mode;
+    const int dir = squid_node(&M, 0, n, 1);
+    int64_t rev = 0;
+    if (dir == SQ_DESC) {
+        for (int64_t a = 0, b = n - 1; a < b; a++, b--) {
+            double tk = M.key[a]; M.key[a] = M.key[b]; M.key[b] = tk;
+            int64_t tl = M.lab[a]; M.lab[a] = M.lab[b]; M.lab[b] = tl;
+            rev += 2;
+        }
+    }
+    if (out_key) memcpy(out_key, M.key, (size_t)n * sizeof(double));
+    if (out_label) memcpy(out_label, M.lab, (size_t)n * sizeof(int64_t));
+    counts[0] = M.cmp; counts[1] = M.test; counts[2] = M.mov; counts[3] = rev;
+    counts[4] = dir; counts[5] = M.bad;
+    int64_t ns = F.nslots;
+    free(F.key); free(F.lab); free(live);
+    return ns;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -690,3 +690,140 @@ def test_target_identities(orc):
                           b(orc.sort_f64_target(x, "DescLeft")[::-1]))
     d = orc.sort_f64_target(x, "DescLeft")
     assert np.isnan(d[: np.isnan(x).sum()]).all()             # NaN is the largest key
+
+
+# ---------------------------------------------------------------------------
+# Squidsort1 model ("Squidsort", "Full adaptivity", Octosort's lazy order)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("k", range(1, 15))
+def test_squid_presorted_and_reversed_counts(orc, k):
+    """"Squidsort": no merge comparisons and 50 % of the moves on presorted and
+    on reverse-sorted input.  For n = 2^k the moves are (n/2) log2 n, the
+    inner runs of every node; reversed input adds one final reversal of n."""
+    n = 1 << k
+    for x, top, rev in ((np.arange(1, n + 1, dtype=np.float64), orc.SQUID_ASC, 0),
+                        (np.arange(n, 0, -1, dtype=np.float64), orc.SQUID_DESC, n)):
+        y, lab, c = orc.squid_model(x)
+        assert c["merge_cmp"] == 0
+        assert c["moves"] == (n // 2) * k
+        assert c["rev_moves"] == rev
+        assert c["top_dir"] == (top if n > 1 else orc.SQUID_NONE)
+        assert c["overwrites"] == 0
+        assert c["test_cmp"] <= 2 * (n - 1)
+        assert np.array_equal(y, np.arange(1, n + 1, dtype=np.float64))
+
+
+@pytest.mark.parametrize("n", [3, 5, 7, 100, 1000, 1023, 4097, 12345])
+def test_squid_moves_equal_frogsort_presorted(orc, n):
+    """For any n the moves on presorted input are the inner runs of every
+    node, which the Frogsort1 model also moves on presorted input (pinned by
+    its own closed form above); reversed input moves the same plus the final
+    reversal."""
+    x = np.arange(n, dtype=np.float64)
+    frog = orc.frog_model(x, g=1)
+    _, _, c = orc.squid_model(x)
+    assert c["merge_cmp"] == 0 and c["moves"] == frog["moves"]
+    _, _, c = orc.squid_model(x[::-1].copy())
+    assert c["merge_cmp"] == 0 and c["moves"] == frog["moves"]
+    assert c["rev_moves"] == n - (n & 1)
+
+
+@pytest.mark.parametrize("n", range(0, 8))
+def test_squid_exhaustive_weak_orders(orc, n):
+    """Every weak order of n keys (tie class 0 as signed zeros, so stability
+    is visible in the bits): the model's output is the definition's, element
+    by element, and no write lands on an unread element."""
+    arrs = _weak_orders(n)
+    for row in arrs:
+        x = row.astype(np.float64)
+        x[(x == 0) & ((np.arange(n) & 1) == 1)] = -0.0
+        y, lab, c = orc.squid_model(x)
+        p = np.argsort(row, kind="stable")
+        assert np.array_equal(lab, p), row
+        assert np.array_equal(y.view(np.uint64), x[p].view(np.uint64))
+        assert c["overwrites"] == 0
+
+
+def _runs(rng, n, max_run, tie_values):
+    """Ascending and descending runs of random lengths (strict, non-strict and
+    tied), concatenated."""
+    out = []
+    while sum(map(len, out)) < n:
+        m = int(rng.integers(1, max_run + 1))
+        kind = rng.integers(0, 4)
+        if kind == 0:
+            r = np.sort(rng.integers(0, tie_values, m))
+        elif kind == 1:
+            r = np.sort(rng.integers(0, tie_values, m))[::-1]
+        elif kind == 2:
+            r = np.sort(rng.permutation(10 * n)[:m])[::-1]       # strictly descending
+        else:
+            r = rng.integers(0, tie_values, m)
+        out.append(r.astype(np.float64))
+    return np.concatenate(out)[:n]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_squid_sorts_mixed_runs_stably(orc, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 5000))
+    x = _runs(rng, n, int(rng.integers(2, 300)), int(rng.integers(2, 50)))
+    x[(x == 0) & (rng.random(n) < 0.5)] = -0.0
+    y, lab, c = orc.squid_model(x)
+    p = np.argsort(x, kind="stable")
+    assert np.array_equal(lab, p)
+    assert np.array_equal(y.view(np.uint64), x[p].view(np.uint64))
+    assert c["overwrites"] == 0
+    frog = orc.frog_model(x, g=1)
+    assert c["moves"] <= frog["moves"] + x.size
+
+
+@pytest.mark.parametrize("pattern", ["asclocal", "ascglobal", "desclocal", "descglobal",
+                                     "permut", "tielog2"])
+def test_squid_on_paper_patterns(orc, pattern):
+    """The paper's patterns: the model sorts them and, where runs are
+    presorted, needs fewer merge comparisons than Frogsort1."""
+    import workloads as W
+    n = 1 << 12
+    x = W.paper_pattern(pattern, n, seed=2)
+    y, lab, c = orc.squid_model(x)
+    assert np.array_equal(lab, np.argsort(x, kind="stable"))
+    assert c["overwrites"] == 0
+    frog = orc.frog_model(x, g=1)
+    if pattern in ("asclocal", "desclocal", "ascglobal"):
+        assert c["merge_cmp"] < frog["compares"]
+
+
+def test_squid_literal_reading_overwrites(orc):
+    """Planted on the CPU: enforcing ascending at a merge whose outer run is
+    descending (the literal reading of Octosort's rule) overwrites outer
+    elements before they are read; the model's reading (merge in the outer
+    run's direction) never does."""
+    x = np.concatenate([np.arange(64, 0, -1), np.arange(100, 164), np.arange(300, 236, -1)]).astype(np.float64)
+    x = np.concatenate([x, np.arange(500, 692).astype(np.float64)])
+    _, lab, c1 = orc.squid_model(x, mode=1)
+    assert c1["overwrites"] > 0
+    _, lab, c0 = orc.squid_model(x, mode=0)
+    assert c0["overwrites"] == 0
+    assert np.array_equal(lab, np.argsort(x, kind="stable"))
+
+
+def test_paper_patterns_shapes():
+    """The generators make what the paper's patterns describe: distinct
+    values (tielog2: ceil(log2 n) of them), runs of L = sqrt(n) ascending
+    (asclocal) or descending (desclocal) spread over the whole range,
+    quantile runs in ascending (ascglobal) or descending (descglobal)
+    order."""
+    import workloads as W
+    n, L = 1 << 14, 1 << 7
+    for p in W.PAPER_PATTERNS:
+        x = W.paper_pattern(p, n, seed=5)
+        assert np.unique(x).size == (14 if p == "tielog2" else n), p
+    r = W.paper_pattern("asclocal", n, seed=5).reshape(-1, L)
+    assert (np.diff(r, axis=1) > 0).all() and (r[:, 0] < n / 2).all() and (r[:, -1] > n / 2).all()
+    r = W.paper_pattern("desclocal", n, seed=5).reshape(-1, L)
+    assert (np.diff(r, axis=1) < 0).all()
+    r = W.paper_pattern("ascglobal", n, seed=5).reshape(-1, L)
+    assert (r.max(axis=1)[:-1] < r.min(axis=1)[1:]).all() and not (np.diff(r, axis=1) > 0).all()
+    r = W.paper_pattern("descglobal", n, seed=5).reshape(-1, L)
+    assert (r.min(axis=1)[:-1] > r.max(axis=1)[1:]).all()

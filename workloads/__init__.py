@@ -182,6 +182,93 @@ def f64_pattern(pattern: str, n: int, seed: int = 0, workload: int = 2,
 
 
 # ---------------------------------------------------------------------------
+# the paper's measurement patterns ("Methods and measurement")
+# ---------------------------------------------------------------------------
+PAPER_PATTERNS = ("permut", "tielog2", "ascall", "descall", "asclocal", "ascglobal",
+                  "desclocal", "descglobal")
+_PAPER_ID = {p: 32 + i for i, p in enumerate(PAPER_PATTERNS)}
+
+
+def permute_in_groups(idx: np.ndarray, group: np.ndarray, size: int, key: int) -> np.ndarray:
+    """For every element, a seeded bijection of [0, size) chosen by its group
+    id, applied to idx (in [0, size)): each group gets its own permutation.
+    Same construction as permute_indices, with round constants drawn per
+    group."""
+    if size <= 1:
+        return np.zeros_like(idx, dtype=np.int64)
+    bits = max(2, int(math.ceil(math.log2(size))))
+    mask = np.uint64((1 << bits) - 1)
+    g = np.asarray(group, dtype=np.uint64)
+    consts = []
+    with np.errstate(over="ignore"):
+        for r in range(8):
+            consts.append(mix64(g * GAMMA + np.uint64((key + 0x51ED * (r + 1)) & 0xFFFFFFFFFFFFFFFF)))
+    x = np.asarray(idx, dtype=np.uint64).copy()
+
+    def rounds(v, sel):
+        with np.errstate(over="ignore"):
+            for r in range(4):
+                v = (v * (consts[2 * r][sel] | np.uint64(1)) + consts[2 * r + 1][sel]) & mask
+                v ^= v >> np.uint64(bits // 2)
+        return v
+
+    allsel = np.ones(x.size, dtype=bool)
+    x = rounds(x, allsel)
+    bad = x >= np.uint64(size)
+    while bad.any():
+        x[bad] = rounds(x[bad], bad)
+        bad = x >= np.uint64(size)
+    return x.astype(np.int64)
+
+
+def paper_pattern(pattern: str, n: int, seed: int = 0, workload: int = 2) -> np.ndarray:
+    """float64 keys of the paper's measurement patterns (distinct integers
+    unless tied), with sqrt(n) runs of length L = round(sqrt(n)) (the last
+    run shorter when L does not divide n):
+
+    permut      a random permutation of 1..n
+    tielog2     draws from ceil(log2 n) distinct random values
+    ascall      1..n ascending;  descall: n..1
+    asclocal    L-long ascending runs whose values are spread at random over
+                the whole range: run b, place j holds j*B + s_j(b) + 1, with B
+                runs and s_j a random permutation of the runs for every place j
+    ascglobal   run b holds the b-th quantile b*L+1 .. (b+1)*L, in random order
+    desclocal   as asclocal with every run descending
+    descglobal  as ascglobal with the quantiles in descending order
+    """
+    key = stream_seed(workload, _PAPER_ID[pattern], seed)
+    if n == 0:
+        return np.zeros(0, dtype=np.float64)
+    pos = np.arange(n, dtype=np.int64) if n <= 1 << 24 else None
+    if pattern == "permut":
+        pos = np.arange(n, dtype=np.int64)
+        return (permute_indices(pos, n, key) + 1).astype(np.float64)
+    if pattern == "tielog2":
+        d = max(1, int(math.ceil(math.log2(max(n, 2)))))
+        table = np.unique(uniform01(4 * d + 16, key ^ 0xA5A5))[:d]
+        return table[(u64(n, key) % np.uint64(table.size)).astype(np.int64)]
+    if pattern == "ascall":
+        return np.arange(1, n + 1, dtype=np.float64)
+    if pattern == "descall":
+        return np.arange(n, 0, -1, dtype=np.float64)
+    if pattern not in ("asclocal", "desclocal", "ascglobal", "descglobal"):
+        raise ValueError(pattern)
+    L = max(1, int(round(math.sqrt(n))))
+    B = -(-n // L)
+
+    def fill(a, e, out):
+        p = np.arange(a, e, dtype=np.int64)
+        b, j = p // L, p % L
+        if pattern in ("asclocal", "desclocal"):
+            jj = j if pattern == "asclocal" else (L - 1 - j)
+            out[a:e] = jj * B + permute_in_groups(b, jj, B, key) + 1
+        else:
+            q = b if pattern == "ascglobal" else (B - 1 - b)
+            out[a:e] = q * L + permute_in_groups(j, b, L, key) + 1
+    return _fill(n, fill, np.float64)
+
+
+# ---------------------------------------------------------------------------
 # key-value workloads (uint64 keys, uint32 payload = original index)
 # ---------------------------------------------------------------------------
 def zipf_cdf(values: int, s: float) -> np.ndarray:

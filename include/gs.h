@@ -124,6 +124,22 @@ size_t gs_workspace_bytes_learned(int64_t n, const gs_learned_params *p);
 gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction,
                       void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
 
+/* gs_sort_f64 at buffer_fraction 0.5 that allocates nothing and takes no
+   workspace: for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid allocation).  The
+   half buffer and control area live in a static device array of
+   GS_NOALLOC_SCRATCH_BYTES that every device the library runs on holds until
+   the process ends; n above GS_NOALLOC_MAX_KEYS -> GS_EINVAL with nothing
+   enqueued.  Same result, order check and error reporting (gs_device_errors)
+   as gs_sort_f64; asynchronous on `hip_stream`.  All calls on one device share
+   that device's array: two calls that can overlap on one device (different
+   streams, or host threads without ordering) race and give wrong results;
+   calls ordered on one stream are safe.  The array is not cleared between
+   calls and needs no clearing: each call initialises what it reads. */
+#define GS_NOALLOC_MAX_KEYS ((int64_t)1 << 22)
+#define GS_NOALLOC_SCRATCH_BYTES ((int64_t)17 << 20)
+gs_status gs_sort_f64_noalloc(double *keys, int64_t n, void *hip_stream);
+
 /* Stable ascending sort of n uint64 keys; vals[i] (uint32) travels with
    keys[i].  Stability is observable through vals ("Stability"). */
 gs_status gs_sort_kv(uint64_t *keys, uint32_t *vals, int64_t n, double buffer_fraction,

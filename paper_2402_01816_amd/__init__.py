@@ -144,6 +144,7 @@ _OPTIONAL = {
     "gs_mlp_train": ([_P, _P, _P, _P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_float,
                       ctypes.c_uint64, ctypes.c_int, _P, _P, _SZ, _P], ctypes.c_int),
     "gs_mlp_forward": ([_P, _P, _I64, _P, _P], ctypes.c_int),
+    "gs_sort_f64_noalloc": ([_P, _I64, _P], ctypes.c_int),
     "gs_device_errors": ([ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int], ctypes.c_int),
     "gs_test_fail_waits": ([ctypes.c_int], ctypes.c_int),
     "gs_trace_enable": ([ctypes.c_int], ctypes.c_int),
@@ -343,6 +344,19 @@ def gs_sort_f64(keys, buffer_fraction: float = 0.5, workspace=None, stream=None,
                              _stream_ptr(stream, keys.device), _rep_ptr(r))
     _check(st, "gs_sort_f64")
     return r.as_dict() if r is not None else None
+
+
+NOALLOC_MAX_KEYS = 1 << 22
+
+
+def gs_sort_f64_noalloc(keys, stream=None):
+    """gs_sort_f64 at buffer fraction 0.5 with the library's static device
+    workspace: no allocation at all (at most NOALLOC_MAX_KEYS keys; calls
+    that can overlap on one device race)."""
+    torch = _torch()
+    kp = _dev_ptr(keys, "keys", (torch.float64,))
+    st = _lib.gs_sort_f64_noalloc(kp, keys.numel(), _stream_ptr(stream, keys.device))
+    _check(st, "gs_sort_f64_noalloc")
 
 
 def gs_sort_kv(keys, vals, buffer_fraction: float = 0.5, workspace=None, stream=None, report=False,

@@ -442,6 +442,28 @@ gs_status gs_sort_f64_ex(double *keys, int64_t n, int target, double buffer_frac
     return s;
 }
 
+gs_status gs_sort_f64_noalloc(double *keys, int64_t n, void *hip_stream)
+{
+    g_detail.clear();
+    if (n < 0) return fail(GS_EINVAL, "n < 0");
+    if (n > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
+    if (n > gs::kNoAllocMaxKeys)
+        return fail(GS_EINVAL, "gs_sort_f64_noalloc: n = %lld is above its static workspace's limit of %lld keys",
+                    (long long)n, (long long)gs::kNoAllocMaxKeys);
+    if (n <= 1) return GS_OK;
+    gs::SortPlan p = gs::plan_f64(n);
+    if (p.bytes > gs::kNoAllocScratchBytes)
+        return fail(GS_EUNSUPPORTED, "gs_sort_f64_noalloc: n = %lld needs %lld workspace bytes, above the static %lld",
+                    (long long)n, (long long)p.bytes, (long long)gs::kNoAllocScratchBytes);
+    gs_status s = check_device();
+    if (s != GS_OK) return s;
+    char *ws = nullptr;
+    hipError_t e = gs::noalloc_scratch(&ws);
+    if (e != hipSuccess) return hip_fail(e, "looking up the static workspace");
+    e = gs::sort_f64_target_async(keys, n, GS_ASC_LEFT, ws, p, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_sort_f64_noalloc launch");
+}
+
 static bool to_seg_config(const gs_seg_config *c, gs::SegConfig *out)
 {
     if (!c) {

@@ -219,6 +219,13 @@ hipError_t sort_kv_target_async(uint64_t *keys, uint32_t *vals, int64_t n, int t
 void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st);
 // The error word of a plain plan's control area.
 ErrWords plain_err_words(char *ws, const SortPlan &p);
+
+// The static workspace of gs_sort_f64_noalloc (gs_noalloc.hip): the device
+// address of the current device's copy, looked up on the first call there.
+constexpr int64_t kNoAllocMaxKeys = (int64_t)1 << 22;
+constexpr int64_t kNoAllocScratchBytes = (int64_t)17 << 20;
+hipError_t noalloc_scratch(char **out);
+
 // One explicit merge node over the logical space {D, H, n_space}, using the
 // control area of a plain plan at least as large as the node.
 hipError_t merge_one_f64_async(double *D, double *H, int64_t n_space, const FrogMerge &m, char *ws,

@@ -299,3 +299,27 @@ def test_fail_waits_hook_toggles():
     finally:
         g.gs_test_fail_waits(was)
     assert g.gs_test_fail_waits(was) is was
+
+
+def test_noalloc_limits():
+    """The static workspace of gs_sort_f64_noalloc holds the workspace of
+    every size up to its limit; above it, and on bad arguments, the call
+    fails before touching a device."""
+    src = open(os.path.join(ROOT, "include", "gs.h")).read()
+    max_keys = int(re.search(r"#define GS_NOALLOC_MAX_KEYS \(\(int64_t\)1 << (\d+)\)", src).group(1))
+    scratch = int(re.search(r"#define GS_NOALLOC_SCRATCH_BYTES \(\(int64_t\)(\d+) << 20\)", src).group(1)) << 20
+    assert 1 << max_keys == g.NOALLOC_MAX_KEYS
+    rng = np.random.default_rng(5)
+    sizes = {2, 3, 4097, 8192, 8193, (1 << max_keys) - 1, 1 << max_keys}
+    sizes |= {int(v) for v in rng.integers(2, (1 << max_keys) + 1, 300)}
+    sizes |= {(1 << k) + d for k in range(1, max_keys) for d in (-1, 0, 1)}
+    for n in sorted(sizes):
+        if 2 <= n <= 1 << max_keys:
+            assert g.gs_workspace_bytes_f64(n) <= scratch, n
+    fake = ctypes.c_void_p(0x100000)
+    assert g.lib.gs_sort_f64_noalloc(fake, (1 << max_keys) + 1, None) == g.GS_EINVAL
+    assert "limit" in g.lib.gs_last_error_detail().decode()
+    assert g.lib.gs_sort_f64_noalloc(fake, -1, None) == g.GS_EINVAL
+    assert g.lib.gs_sort_f64_noalloc(None, 10, None) == g.GS_EINVAL
+    assert g.lib.gs_sort_f64_noalloc(None, 0, None) == g.GS_OK
+    assert g.lib.gs_sort_f64_noalloc(fake, 1, None) == g.GS_OK

@@ -84,6 +84,9 @@ typedef struct {
     uint32_t order;                 /* plain sorts: 0 sorted, 1 input already in order (nothing
                                        moved), 2 input strictly reversed (one reversal pass) */
     uint32_t reserved;
+    uint64_t keys_moved;            /* plain sorts: element moves of the call (leaf stores, merge
+                                       and concatenation stores, reversals), the bytes a pass
+                                       writes divided by the element size */
 } gs_report;
 
 /* Parameters of the learned CDF bucket path (not from the paper). */
@@ -320,6 +323,23 @@ int gs_plan_depth(int64_t n, int is_kv, int64_t *leaf_max);
 /* Geometry of node `idx` at `depth` of the frog tree over n elements:
    out[0..4] = region start, data size, is_left, data start, input offset. */
 void gs_plan_node(int64_t n, int depth, int64_t idx, int64_t *out);
+/* The ordered-store protocol's windows, computed by the code the kernels run.
+   Leaf `leaf` of the Frogsort1 tree of `depth` over n keys: lo_hi[0..1] =
+   the leaf tickets (ticket = 2^depth - 1 - leaf index) whose input chunks its
+   destination covers (empty when lo > hi).  Returns 0, -1 on bad arguments. */
+int gs_plan_leaf_window(int64_t n, int depth, int64_t leaf, int64_t *lo_hi);
+/* One merge: merge[0..6] = first run start, its size, second run start, its
+   size, output start, written top-down (1) or bottom-up (0), which run lies
+   inside the output (0 first at the output start, 1 second at its end, 2
+   first at its end); kind 0 merge, 1 merge after turning a descending outer
+   run around (turned: 1 once that has happened), 2 concatenation; dir_first /
+   dir_second: 1 ascending, 2 descending runs; splits[0..tiles]: the merge-path
+   splits at every tile boundary (first-view elements among the first
+   j * tile outputs).  windows[2 t], windows[2 t + 1] = the tickets ticket t
+   waits for before storing (tiles take tickets in write order).  Returns the
+   number of tiles, -1 on bad arguments. */
+int gs_plan_tile_windows(const int64_t *merge, int kind, int dir_first, int dir_second, int turned, int64_t tile,
+                         const int64_t *splits, int64_t *windows);
 /* The Frogsort2 tree for n keys at buffer_fraction (is_kv: the key/value leaf
    size): leaves[3*i..] = input offset, data start, length (input order);
    nodes[4*j..] = region start, elements, is_left, merge round; counts[0..6] =

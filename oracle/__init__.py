@@ -224,7 +224,9 @@ def squid_model(keys: np.ndarray, mode: int = 0):
     dict: merge_cmp, test_cmp, moves (merges and concatenations), rev_moves
     (final reversal), top_dir (SQUID_*), overwrites (writes over unread
     elements).  mode 1 enforces ascending at every merge (the literal
-    reading; shows why the model merges in the outer run's direction)."""
+    reading; shows why the model merges in the outer run's direction); mode 2
+    turns a descending outer run around in place before an ascending merge
+    (the rule the GPU path runs)."""
     lib = _load()
     x = np.ascontiguousarray(keys, dtype=np.float64)
     n = x.size

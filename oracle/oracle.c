@@ -524,6 +524,12 @@ int64_t oracle_frog_geometry(int64_t n, int depth, int64_t *out)
  *     the top node ends descending.
  * mode 1 enforces ascending at every merge instead (the literal reading);
  * the write check then finds outer elements overwritten before they are read.
+ * mode 2 keeps a descending run only through concatenations: before a merge
+ * a descending outer run is turned around in place (a reversal within its
+ * own slots, counted with the moves), and every merge is ascending -- on a
+ * device that pays the same for a move whether or not it compares, this
+ * avoids merges that keep a run descending only for the final reversal to
+ * turn it around again.
  *
  * Writes go in the frog order (left node top-down, right node bottom-up) and
  * every write is checked: a slot that still holds an element not yet read is
@@ -593,7 +599,19 @@ static int squid_node(squid_model *M, int64_t s, int64_t n, int left)
         for (int64_t p = Rb; p < Rb + nr; p++) M->live[p] = 0;
         return dir;
     }
-    const int douter = left ? dL : dR;
+    int douter = left ? dL : dR;
+    int dLm = dL, dRm = dR;
+    if (M->mode == 2 && douter == SQ_DESC) {
+        /* turn the outer run around in its own slots */
+        const int64_t x0 = left ? Lb : Rb, nx = left ? nl : nr;
+        for (int64_t a = x0, b = x0 + nx - 1; a < b; a++, b--) {
+            double tk = M->key[a]; M->key[a] = M->key[b]; M->key[b] = tk;
+            int64_t tl = M->lab[a]; M->lab[a] = M->lab[b]; M->lab[b] = tl;
+            M->mov += 2;
+        }
+        if (left) dLm = SQ_ASC; else dRm = SQ_ASC;
+        douter = SQ_ASC;
+    }
     dir = (M->mode == 0 && douter == SQ_DESC) ? SQ_DESC : SQ_ASC;
     /* The stable ascending merge M of SL and SR takes SL first on ties; slot
        out0+k receives M[k] (ascending) or M[n-1-k] (descending).  The write
@@ -608,14 +626,14 @@ static int squid_node(squid_model *M, int64_t s, int64_t n, int left)
         else if (j == je) takeL = 1;
         else {
             M->cmp++;
-            const double a = sq_view(M, Lb, nl, dL, i), b = sq_view(M, Rb, nr, dR, j);
+            const double a = sq_view(M, Lb, nl, dLm, i), b = sq_view(M, Rb, nr, dRm, j);
             /* from the small end L wins ties; from the large end R's tied
                elements come out first (they follow L's in M) */
             takeL = smallest_first ? !oracle_less_f64(b, a) : oracle_less_f64(b, a);
         }
         const int64_t mpos = smallest_first ? k : n - 1 - k;           /* position in M */
         const int64_t w = (dir == SQ_ASC) ? out0 + mpos : out0 + (n - 1 - mpos);
-        const int64_t src = takeL ? sq_slot(Lb, nl, dL, i) : sq_slot(Rb, nr, dR, j);
+        const int64_t src = takeL ? sq_slot(Lb, nl, dLm, i) : sq_slot(Rb, nr, dRm, j);
         sq_put(M, w, src);
         if (takeL) i += step; else j += step;
     }
@@ -627,7 +645,8 @@ static int squid_node(squid_model *M, int64_t s, int64_t n, int left)
 /*
  * Run the Squidsort1 model on in[0, n) (elements placed by the Frogsort1 setup
  * recursion, one element per leaf).  mode 0: the reading above; mode 1:
- * ascending enforced at every merge.
+ * ascending enforced at every merge; mode 2: descending outer runs turned
+ * around before their merge.
  *   out_key, out_label: the n results and the input index of each (after the
  *                       final reversal when the top node is descending)
  *   counts: {merge comparisons, test comparisons, merge and concatenation

@@ -52,6 +52,7 @@ class GsReport(ctypes.Structure):
         ("elapsed_ms", ctypes.c_double),
         ("order", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+        ("keys_moved", ctypes.c_uint64),
     ]
 
     def as_dict(self):
@@ -114,6 +115,9 @@ _SIGS = {
     "gs_version": ([], ctypes.c_char_p),
     "gs_plan_depth": ([_I64, ctypes.c_int, ctypes.POINTER(_I64)], ctypes.c_int),
     "gs_plan_node": ([_I64, ctypes.c_int, _I64, ctypes.POINTER(_I64)], None),
+    "gs_plan_leaf_window": ([_I64, ctypes.c_int, _I64, ctypes.c_void_p], ctypes.c_int),
+    "gs_plan_tile_windows": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64,
+                              ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "gs_plan_frog2": ([_I64, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64, ctypes.c_void_p, _I64,
                        ctypes.c_void_p], ctypes.c_int),
     "gs_plan_frog3": ([_I64, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64,

@@ -157,13 +157,21 @@ gs_status check_err_word(const char *ws, const gs::SortPlan &p)
     return check_err_word(ws + p.off_forest + p.forest.off_ctrl);
 }
 
-// The order check's decision of a plain sort, after the stream is synchronised.
-gs_status read_order(const char *ws, const gs::SortPlan &p, uint32_t *order)
+// The order check's decision of a plain sort and the call's element moves,
+// after the stream is synchronised (target: the extra reversal of the
+// right-anchored targets).
+gs_status read_order(const char *ws, const gs::SortPlan &p, int64_t n, int target, gs_report *rep)
 {
     unsigned w = 0;
+    uint64_t moved = 0;
     hipError_t e = hipMemcpy(&w, ws + p.off_order, 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(&moved, ws + p.off_forest + p.forest.off_ctrl + 4 * gs::kMovedWord, 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "reading the order word");
-    *order = w;
+    const uint64_t rev = (uint64_t)(n - (n & 1));
+    rep->order = w;
+    rep->keys_moved = (w == gs::ORD_IN_ORDER ? 0 : w == gs::ORD_REVERSED ? rev : moved) +
+                      ((target == GS_ASC_RIGHT || target == GS_DESC_RIGHT) ? rev : 0);
     return GS_OK;
 }
 
@@ -311,6 +319,42 @@ void gs_plan_node(int64_t n, int depth, int64_t idx, int64_t *out)
     out[4] = f.in_off;
 }
 
+int gs_plan_leaf_window(int64_t n, int depth, int64_t leaf, int64_t *lo_hi)
+{
+    if (n < 1 || depth < 0 || depth > 40 || leaf < 0 || leaf >= ((int64_t)1 << depth) || !lo_hi) return -1;
+    gs::leaf_window(n, depth, leaf, lo_hi, lo_hi + 1);
+    return 0;
+}
+
+int gs_plan_tile_windows(const int64_t *merge, int kind, int dir_first, int dir_second, int turned, int64_t tile,
+                         const int64_t *splits, int64_t *windows)
+{
+    if (!merge || !splits || !windows || tile < 1 || kind < gs::NODE_MERGE || kind > gs::NODE_CONCAT) return -1;
+    gs::FrogMerge m{};
+    m.l0 = merge[0];
+    m.nl = merge[1];
+    m.r0 = merge[2];
+    m.nr = merge[3];
+    m.out0 = merge[4];
+    m.left = (int)merge[5];
+    m.outer = (int)merge[6];
+    if (m.nl < 0 || m.nr < 0 || m.outer < 0 || m.outer > 2) return -1;
+    const gs::NodeViews v = gs::node_views(m, kind, dir_first, dir_second, turned != 0);
+    const int64_t n = m.nl + m.nr, tpn = (n + tile - 1) / tile;
+    for (int64_t q = 0; q < tpn; ++q) {
+        const int64_t j = m.left ? tpn - 1 - q : q;
+        int64_t lo, hi;
+        gs::tile_window(v, m.out0, m.left, splits, tpn, tile, j, 0, &lo, &hi);
+        if (lo <= hi) {
+            lo = lo < 0 ? 0 : lo;
+            hi = hi > q ? q : hi;
+        }
+        windows[2 * q] = lo;
+        windows[2 * q + 1] = hi;
+    }
+    return (int)tpn;
+}
+
 int gs_plan_frog2(int64_t n, double buffer_fraction, int is_kv, int64_t *leaves, int64_t max_leaves,
                   int64_t *nodes, int64_t max_nodes, int64_t *counts)
 {
@@ -438,7 +482,7 @@ gs_status gs_sort_f64_ex(double *keys, int64_t n, int target, double buffer_frac
     }
     s = r.finish(GS_OK);
     if (rep && s == GS_OK) s = check_err_word((const char *)ws, p);
-    if (rep && s == GS_OK) s = read_order((const char *)ws, p, &rep->order);
+    if (rep && s == GS_OK) s = read_order((const char *)ws, p, n, target, rep);
     return s;
 }
 
@@ -692,7 +736,7 @@ gs_status gs_sort_kv_ex(uint64_t *keys, uint32_t *vals, int64_t n, int target, d
     }
     s = r.finish(GS_OK);
     if (rep && s == GS_OK) s = check_err_word((const char *)ws, p);
-    if (rep && s == GS_OK) s = read_order((const char *)ws, p, &rep->order);
+    if (rep && s == GS_OK) s = read_order((const char *)ws, p, n, target, rep);
     return s;
 }
 

@@ -133,6 +133,11 @@ struct Forest {
     int use_m1;
     int use_f2;               // with use_f2: p0 is sorted by the Frogsort2 tree in f2
     F2View f2;
+    // Squidsort (the single Frogsort1 tree only, else null): the direction
+    // (DIR_*) of every node's run, heap order (depth d, node i at
+    // 2^d - 1 + i), and the packed mode of every node of the current round
+    uint8_t *dirs;
+    uint8_t *modes;
 };
 
 GS_HD int64_t forest_nodes(const Forest &F, const Prob &P, int round)
@@ -204,15 +209,22 @@ __device__ __forceinline__ int64_t forest_locate_wave(const unsigned *row, int64
 }
 
 // One merge output tile, resolved before the merge launch: the runs it reads,
-// where it writes, and the tickets it must wait for before storing.
+// where it writes, and the tickets it must wait for before storing.  Its
+// inputs are la elements of view a, stored at slots [pa, pa + la), then
+// cnt - la elements of view b at [pb, pb + cnt - la); a view read from its
+// end (TF_AREV / TF_BREV) has its slots loaded upwards all the same and
+// staged in reverse; its outputs are their stable merge (a first on ties),
+// or simply the inputs in that order (TF_COPY: a concatenation node).
+enum : int { TF_SKIP = 1, TF_COPY = 2, TF_AREV = 8, TF_BREV = 16 };
 struct TileDesc {
-    int64_t pa, pb;   // logical slots of its first first-run / second-run input
+    int64_t pa, pb;   // lowest logical slots of its view-a / view-b inputs
     int64_t o;        // logical slot of its first output
     unsigned dlo, dhi;       // dependency window (tickets, inclusive; empty if dlo > dhi)
-    int la, cnt;      // first-run inputs, total inputs (= outputs)
+    int la, cnt;      // view-a inputs, total inputs (= outputs)
     int prob;         // its problem (row of the table; 0 for the inline problem)
-    int skip;         // 1: empty, or every output already sits in its slot
+    int flags;        // TF_*; TF_SKIP: empty, or every output already sits in its slot
 };
+
 
 // ---------------------------------------------------------------------------
 // ordered-store protocol
@@ -269,6 +281,16 @@ __device__ __forceinline__ void wait_window(const unsigned *status, int64_t lo, 
                 __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// A work-group barrier that orders LDS accesses only: the fences are limited
+// to the local address space, so global loads in flight (a prefetched tile)
+// stay in flight across it.  For barriers whose only job is LDS reuse.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // ---------------------------------------------------------------------------

@@ -56,7 +56,7 @@ __global__ void fill_ctrl_kernel(unsigned *p, int64_t count, unsigned test)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < count; i += stride) {
-        if (i == kErrWord) continue;
+        if (i == kErrWord || i == kMovedWord || i == kMovedWord + 1) continue;
         p[i] = i == kTestWord ? test : 0u;
     }
 }

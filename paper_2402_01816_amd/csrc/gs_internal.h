@@ -15,6 +15,14 @@ namespace gs {
 // start of every forest run keeps it, so it collects every run of a call; the
 // call clears it once when it starts (err_words_begin).
 constexpr int kErrWord = 63;
+// Words 60-61: elements moved by the call's leaf, merge and reversal launches
+// (a 64-bit count, cleared by the plain sort's first kernel; kept across the
+// runs of a call like the error word).
+constexpr int kMovedWord = 60;
+// Words 16 + r: set when a node of merge round r turns its outer run around
+// first (Squidsort, the single Frogsort1 tree; rounds up to 40).
+constexpr int kTurnWord0 = 16;
+constexpr int kTurnRounds = 40;
 // The word before it: the test setting of the bounded waits (bit 0: record
 // every wait that checked another work item as failed).  Every forest run
 // writes it from the host's setting.
@@ -47,7 +55,7 @@ hipError_t sticky_errors_read(unsigned *flags, bool clear);
 unsigned test_wait_word();
 void set_test_wait_word(unsigned w);
 // Clears a forest control block of `count` words except kTestWord, which
-// gets the test setting, and kErrWord, which is kept.
+// gets the test setting, and kErrWord and the moved count, which are kept.
 void launch_fill_ctrl(unsigned *ctrl, int64_t count, hipStream_t st);
 
 // Control words of a forest run: the leaf ticket counter (word 0), the
@@ -74,6 +82,9 @@ struct ForestPlan {
     int64_t max_splits;   // merge-path splits of one round (capacity)
     int64_t off_ctrl;     // forest_ctrl_words(rounds) words
     int64_t off_status;
+    int64_t off_dirs;     // Squidsort run directions, heap order (dir_nodes bytes; 0 = none)
+    int64_t off_modes;    // node modes of the current round (dir_nodes / 2 bytes)
+    int64_t dir_nodes;
     int64_t off_splits;
     int64_t off_desc;     // tile descriptors of the current round
     int64_t off_probs;    // problem table (table runs only)

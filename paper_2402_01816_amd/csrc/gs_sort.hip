@@ -58,10 +58,50 @@ void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st)
 // descending index order, and each waits for the leaves whose chunks its
 // output covers.  Every work-group takes one ticket; with a problem table the
 // grid is the capacity and work-groups past the device's leaf count exit.
+// The value held by the next lane of the 16-lane row (DPP row shift; the
+// last lane of a row gets its own value back).
+template <class K>
+__device__ __forceinline__ K lane_next(K x)
+{
+    static_assert(sizeof(K) == 8, "64-bit keys");
+    const long long b = (long long)__builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp((int)(b & 0xffffffffll), (int)(b & 0xffffffffll), 0x101, 0xF, 0xF,
+                                               false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0x101, 0xF, 0xF, false);
+    return __builtin_bit_cast(K, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Order of the chunk in sk[0, len) (lpad layout), the same answer in every
+// thread: 1 if no neighbour pair is out of order, 2 if every pair strictly
+// decreases, else 0.  Each thread checks the pairs that start among its IPT
+// consecutive slots.
+template <class KT, class VS, int NT, int IPT>
+__device__ __forceinline__ int chunk_order(const typename KT::T *sk, int len)
+{
+    using K = typename KT::T;
+    const int base = threadIdx.x * IPT;
+    bool up = true, down = true;
+    if (base < len - 1) {
+        K prev = sk[lpad(base)];
+#pragma unroll
+        for (int i = 1; i <= IPT; ++i) {
+            if (base + i < len) {
+                const K x = sk[lpad(base + i)];
+                up &= !KT::less(x, prev);
+                down &= KT::less(x, prev);
+                prev = x;
+            }
+        }
+    }
+    const bool not_up = __syncthreads_or(!up) != 0;
+    const bool not_down = __syncthreads_or(!down) != 0;
+    return !not_up ? 1 : !not_down ? 2 : 0;
+}
+
 template <class KT, class V, int NT, int IPT, int WAVES, bool F2>
 __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv,
                                                   Forest F, unsigned *ticket_ctr, unsigned *status,
-                                                  unsigned epoch, unsigned *err, Gate gate)
+                                                  unsigned epoch, unsigned *err, uint64_t *moved, Gate gate)
 {
     using K = typename KT::T;
     using KF = typename FastKey<KT>::type;
@@ -71,7 +111,7 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
     constexpr int SLOTS = lds_slots<TILE>();
     __shared__ K sk[SLOTS];
     __shared__ VS sv[HV ? SLOTS : 1];
-    __shared__ unsigned s_ticket;
+    __shared__ unsigned s_ticket, s_order;
     if (gate.closed()) return;
 
     const int tid = threadIdx.x;
@@ -81,6 +121,7 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
         __syncthreads();
         const int64_t t = __builtin_amdgcn_readfirstlane(s_ticket);
+        if (tid == 0) s_order = 0;
         __syncthreads();
         if (t >= total) break;
         Prob P = F.p0;
@@ -133,6 +174,18 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
                 nan_here |= is_nan_key(lk[r]);
                 differ |= tie_bits_may_differ(lk[r]);
             }
+            // Squidsort: a first look at the chunk's order from the pairs
+            // (i, i+1) with i = tid, the neighbour taken from the next lane
+            // of the row; s_order bit 0: some pair falls, bit 1: some pair
+            // does not fall (both: the chunk is neither in order nor
+            // strictly decreasing)
+            if (F.dirs) {
+                const K nb = lane_next(lk[0]);
+                const bool ok = (tid & 15) != 15 && tid + 1 < len;
+                const bool falls = ok && KT::less(nb, lk[0]), rises = ok && !KT::less(nb, lk[0]);
+                const unsigned bits = (__ballot(falls) ? 1u : 0u) | (__ballot(rises) ? 2u : 0u);
+                if ((tid & 63) == 0 && bits) atomicOr(&s_order, bits);
+            }
             const bool any_nan = __syncthreads_or(nan_here) != 0;
             ties_identical = !HV && __syncthreads_or(differ) == 0;
             // slots past the chunk get a padding key that sorts after every
@@ -149,10 +202,24 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         __syncthreads();
         if (tid == 0) st_status(status + t, (epoch << 2) | ST_LOADED);
 
+        // Squidsort: a chunk already in order stays as it is (ascending run),
+        // a strictly decreasing one too (descending run: reversed, it is the
+        // stable result); only the others are sorted
+        int ord = 0;                     // 0: to be sorted, 1: in order, 2: strictly decreasing
+        if (F.dirs) {
+            ord = len <= 1 ? 1 : s_order == 3u ? 0 : chunk_order<KT, VS, NT, IPT>(sk, len);
+            if (tid == 0)
+                F.dirs[((int64_t)1 << P.depth) - 1 + leaf] =
+                    (uint8_t)(len <= 1 ? DIR_NONE : ord == 2 ? DIR_DESC : DIR_ASC);
+        }
+        if (tid == 0 && moved) atomicAdd((unsigned long long *)moved, (unsigned long long)len);
+
         // a short leaf (keys-only sorts: the forest's segments and buckets
         // have them) is sorted in the smallest power-of-two prefix holding
         // it, skipping the work on the padding past it
-        if (HV || len == TILE) {
+        if (ord != 0) {
+            // nothing to sort
+        } else if (HV || len == TILE) {
             if (nan_here) block_sort_lds<KT, VS, HV, NT, IPT>(sk, sv);
             else block_sort_lds<KF, VS, HV, NT, IPT>(sk, sv, TILE, TILE, ties_identical);
         } else if constexpr (!HV) {
@@ -165,11 +232,10 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         // wait for the leaves whose input chunks the destination covers
         if constexpr (F2) {
             if (tid < 64 && wlo <= whi) wait_window(status, wlo, whi, t, epoch, err);
-        } else if (tid < 64 && dst < P.n) {
-            const int64_t end = (dst + len < P.n ? dst + len : P.n) - 1;
-            const int64_t lo_leaf = frog_leaf_of(P.n, P.depth, dst);
-            const int64_t hi_leaf = frog_leaf_of(P.n, P.depth, end);
-            wait_window(status, base + nleaves - 1 - hi_leaf, base + nleaves - 1 - lo_leaf, t, epoch, err);
+        } else if (tid < 64) {
+            int64_t wl, wh;
+            leaf_window(P.n, P.depth, leaf, &wl, &wh);
+            if (wl <= wh) wait_window(status, base + wl, base + wh, t, epoch, err);
         }
         __syncthreads();
 
@@ -268,13 +334,62 @@ __global__ __launch_bounds__(1024) void forest_scan_kernel(Forest F, unsigned *t
 // ---------------------------------------------------------------------------
 // partition kernel: merge-path splits at every tile boundary of every node
 // ---------------------------------------------------------------------------
-// One thread per (node, boundary j): binary search for the number of first-run
-// elements among the first j*TILE outputs of the node's stable merge.  (The
-// searches are bound by the rate of random reads, so one probe per step is
-// the cheapest form.)
+// How a node of the single Frogsort1 tree forms its run from its children's
+// runs (directions dL, dR): the concatenation when both come back ascending
+// and the first run's last key is not above the second run's first, or both
+// descending and every key of the second run is below every key of the first
+// ("Full adaptivity": the non-overlap test; "Squidsort"); otherwise an
+// ascending merge, after turning a descending outer run around.  *dir
+// receives the node's direction.
+template <class KT>
+__device__ __forceinline__ int node_kind(const Space<typename KT::T> &keys, const FrogMerge &m, int dL, int dR,
+                                         unsigned *dir)
+{
+    if (m.nl > 0 && m.nr > 0) {
+        const RunView L = view_of(m.l0, m.nl, dL == DIR_DESC), R = view_of(m.r0, m.nr, dR == DIR_DESC);
+        if (dL != DIR_DESC && dR != DIR_DESC &&
+            !KT::less(*keys.at(view_slot(R, 0)), *keys.at(view_slot(L, m.nl - 1)))) {
+            *dir = DIR_ASC;
+            return NODE_CONCAT;
+        }
+        if (dL != DIR_ASC && dR != DIR_ASC &&
+            KT::less(*keys.at(view_slot(R, m.nr - 1)), *keys.at(view_slot(L, 0)))) {
+            *dir = DIR_DESC;
+            return NODE_CONCAT;
+        }
+    }
+    const int douter = m.outer != 1 ? dL : dR;
+    *dir = DIR_ASC;
+    return douter == DIR_DESC ? NODE_MERGE_REV : NODE_MERGE;
+}
+
+// Merge-path split of the views' stable merge: the number of view-a
+// elements among the first kk outputs.
+template <class KT>
+__device__ __forceinline__ int64_t view_split(const Space<typename KT::T> &keys, const NodeViews &v, int64_t kk)
+{
+    int64_t lo = kk > v.b.n ? kk - v.b.n : 0;
+    int64_t hi = kk < v.a.n ? kk : v.a.n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (KT::less(*keys.at(view_slot(v.b, kk - 1 - mid)), *keys.at(view_slot(v.a, mid)))) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// One thread per (node, boundary j): the number of view-a elements among the
+// first j*TILE outputs of the node's merge (no search for a concatenation).
+// For the single Frogsort1 tree the node's mode is decided here from its
+// children's directions (every thread of the node decides alike; the one
+// with j = 0 records the mode and the node's direction, and flags the round
+// if the node's outer run has to be turned around before the merge).  The
+// splits read a descending run from its end, the sequence it holds once
+// turned.  (The searches are bound by the rate of random reads, so one probe
+// per step is the cheapest form.)
 template <class KT, int TILE>
 __global__ __launch_bounds__(256) void partition_kernel(typename KT::T *Dk, typename KT::T *Hk, Forest F,
-                                                        int round, int64_t *splits, Gate gate)
+                                                        int round, int64_t *splits, unsigned *turn_flag, Gate gate)
 {
     using K = typename KT::T;
     if (gate.closed()) return;
@@ -286,7 +401,7 @@ __global__ __launch_bounds__(256) void partition_kernel(typename KT::T *Dk, type
          w += (int64_t)gridDim.x * blockDim.x) {
         Prob P = F.p0;
         FrogMerge m;
-        int64_t j;
+        int64_t j, node = 0;
         if (F.use_f2) {
             const unsigned b0 = F.f2.rb[round], b1 = F.f2.rb[round + 1];
             const int64_t k = b0 + forest_locate(F.f2.node_sb + b0, b1 - b0, w);
@@ -301,63 +416,86 @@ __global__ __launch_bounds__(256) void partition_kernel(typename KT::T *Dk, type
             }
             const int64_t tpn = forest_tpn<TILE>(F, P, round);
             const int64_t lw = w - base;
-            const int64_t node = lw / (tpn + 1);
+            node = lw / (tpn + 1);
             j = lw - node * (tpn + 1);
             m = forest_merge(F, P, round, node);
         }
         const Space<K> keys{Dk + P.doff, Hk + P.hoff, P.n};
+        int kind = NODE_MERGE, dL = DIR_ASC, dR = DIR_ASC;
+        if (F.dirs) {
+            const int dep = P.depth - round;
+            const uint8_t *cd = F.dirs + ((int64_t)2 << dep) - 1 + 2 * node;
+            dL = (int)cd[0];
+            dR = (int)cd[1];
+            unsigned ndir = DIR_ASC;
+            kind = node_kind<KT>(keys, m, dL, dR, &ndir);
+            if (j == 0) {
+                F.dirs[((int64_t)1 << dep) - 1 + node] = (uint8_t)ndir;
+                F.modes[node] = (uint8_t)node_mode_pack(kind, dL, dR);
+                if (kind == NODE_MERGE_REV) atomicOr(turn_flag, 1u);
+            }
+        }
+        const NodeViews v = node_views(m, kind, dL, dR, false);
         const int64_t nn = m.nl + m.nr;
         int64_t kk = j * TILE;
         if (kk > nn) kk = nn;
-        int64_t lo = kk > m.nr ? kk - m.nr : 0;
-        int64_t hi = kk < m.nl ? kk : m.nl;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (KT::less(*keys.at(m.r0 + (kk - 1 - mid)), *keys.at(m.l0 + mid))) hi = mid;
-            else lo = mid + 1;
+        splits[w] = v.copy ? (kk < v.a.n ? kk : v.a.n) : view_split<KT>(keys, v, kk);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// turning descending outer runs around (Squidsort, single Frogsort1 tree)
+// ---------------------------------------------------------------------------
+// Done by the tile-descriptor launch of a round (between the partition and
+// the merge launches; the descriptors do not read keys): every node marked
+// NODE_MERGE_REV gets its outer run reversed in place, so the merge reads it
+// ascending.  Work-groups take chunks of kTurnChunk element pairs.
+constexpr int64_t kTurnChunk = 4096;
+template <class K, class V>
+__device__ __forceinline__ void turn_outer_runs(K *Dk, K *Hk, V *Dv, V *Hv, const Forest &F, int round,
+                                                uint64_t *moved)
+{
+    const int dep = F.p0.depth - round;
+    const int64_t nodes = (int64_t)1 << dep;
+    const int64_t chunks = (frog_max_node(F.p0.n, dep) / 2 + 1 + kTurnChunk - 1) / kTurnChunk;
+    const Space<K> ks{Dk + F.p0.doff, Hk + F.p0.hoff, F.p0.n};
+    const Space<V> vs{ValOps<V>::has ? Dv + F.p0.doff : nullptr, ValOps<V>::has ? Hv + F.p0.hoff : nullptr, F.p0.n};
+    for (int64_t w = blockIdx.x; w < nodes * chunks; w += gridDim.x) {
+        const int64_t node = w / chunks, c = w - node * chunks;
+        if (node_mode_kind(F.modes[node]) != NODE_MERGE_REV) continue;
+        const FrogMerge m = frog_merge_of(frog_node(F.p0.n, dep, node));
+        const int64_t x0 = m.outer != 1 ? m.l0 : m.r0, nx = m.outer != 1 ? m.nl : m.nr;
+        const int64_t pairs = nx / 2, e = (c + 1) * kTurnChunk < pairs ? (c + 1) * kTurnChunk : pairs;
+        if (c == 0 && threadIdx.x == 0) atomicAdd((unsigned long long *)moved, (unsigned long long)(2 * pairs));
+        for (int64_t i = c * kTurnChunk + threadIdx.x; i < e; i += blockDim.x) {
+            K *a = ks.at(x0 + i), *b = ks.at(x0 + nx - 1 - i);
+            const K ka = *a, kb = *b;
+            *a = kb;
+            *b = ka;
+            if constexpr (ValOps<V>::has) {
+                V *va = vs.at(x0 + i), *vb = vs.at(x0 + nx - 1 - i);
+                const V xa = *va, xb = *vb;
+                *va = xb;
+                *vb = xa;
+            }
         }
-        splits[w] = lo;
     }
 }
 
 // ---------------------------------------------------------------------------
 // tile descriptors with their dependency windows
 // ---------------------------------------------------------------------------
-// A left node's tile with output ranks [k0,k1) overwrites the outer-run (left
-// child) elements with indices [k0, min(k1,nl)); a right node's tile overwrites
-// the outer-run (right child) elements with indices [k0-nl, k1-nl) clipped to
-// [0,nr).  The tiles that read those elements follow from the splits; their
-// tickets form one contiguous range that never starts after the tile's own.
-__device__ __forceinline__ int64_t upper_bound_splits(const int64_t *sp, int64_t count, int64_t x)
-{
-    int64_t lo = 0, hi = count;          // first j with sp[j] > x
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (sp[mid] > x) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
-
-template <int TILE>
-__device__ __forceinline__ int64_t upper_bound_bsplits(const int64_t *sp, int64_t count, int64_t n,
-                                                       int64_t x)
-{
-    int64_t lo = 0, hi = count;          // first j with min(j*TILE,n) - sp[j] > x
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        const int64_t k = mid * TILE < n ? mid * TILE : n;
-        if (k - sp[mid] > x) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
-
-template <int TILE>
-__global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const int64_t *splits,
-                                                    TileDesc *desc, Gate gate)
+// A tile overwrites the slots [o, o + cnt); the elements of the outer run in
+// those slots are read by the tiles whose inputs include them, which the
+// splits give (tile_window in frog_geometry.h); their tickets form one
+// contiguous range that never passes the tile's own.
+template <class K, class V, int TILE>
+__global__ __launch_bounds__(256) void tiles_kernel(K *Dk, K *Hk, V *Dv, V *Hv, Forest F, int round,
+                                                    const int64_t *splits, TileDesc *desc, const unsigned *turn_flag,
+                                                    uint64_t *moved, Gate gate)
 {
     if (gate.closed()) return;
+    if (F.dirs && *turn_flag) turn_outer_runs<K, V>(Dk, Hk, Dv, Hv, F, round, moved);
     const int64_t L = F.probs ? (int64_t)*F.nprob : 1;
     const unsigned *trow = F.probs ? F.tbase + (int64_t)round * F.stride : nullptr;
     const unsigned *srow = F.probs ? F.sbase + (int64_t)round * F.stride : nullptr;
@@ -365,7 +503,7 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
                           : F.probs ? (int64_t)trow[L] : forest_tickets<TILE>(F, F.p0, round);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        int64_t s = 0, tpn, q, first;
+        int64_t s = 0, tpn, q, first, node = 0;
         const int64_t *sp;
         FrogMerge m;
         if (F.use_f2) {
@@ -388,12 +526,21 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
             }
             tpn = forest_tpn<TILE>(F, P, round);
             const int64_t lt = t - tb;
-            const int64_t node = lt / tpn;
+            node = lt / tpn;
             q = lt - node * tpn;
             first = tb + node * tpn;
             sp = splits + sb + node * (tpn + 1);
             m = forest_merge(F, P, round, node);
         }
+        int kind = NODE_MERGE, dL = DIR_ASC, dR = DIR_ASC;
+        if (F.dirs) {
+            const unsigned w = F.modes[node];     // written by the partition launch
+            kind = node_mode_kind(w);
+            dL = node_mode_dl(w);
+            dR = node_mode_dr(w);
+        }
+        // the outer run of a NODE_MERGE_REV node has been turned around by now
+        const NodeViews v = node_views(m, kind, dL, dR, true);
         const int64_t nn = m.nl + m.nr;
         const int64_t j = m.left ? (tpn - 1 - q) : q;
         int64_t k0 = j * TILE;
@@ -402,70 +549,48 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
         if (k1 > nn) k1 = nn;
         TileDesc T;
         T.prob = (int)s;
-        T.skip = 0;
         T.cnt = (int)(k1 - k0);
         T.la = 0;
         T.pa = T.pb = T.o = 0;
+        T.flags = (v.copy ? TF_COPY : 0) | (v.a.step < 0 ? TF_AREV : 0) | (v.b.step < 0 ? TF_BREV : 0);
         int64_t lo = 1, hi = 0;          // empty window
         if (k0 < k1) {
             // Splits of sorted runs are monotone and every tile takes between
-            // 0 and cnt elements from each run; the clamp keeps the
-            // descriptor within the runs whatever they hold (it changes
+            // 0 and cnt elements from each view; the clamp keeps the
+            // descriptor within the views whatever the runs hold (it changes
             // nothing for sorted runs).
             const int64_t a0 = sp[j];
             int64_t a1 = sp[j + 1];
-            const int64_t a1lo = a0 > k1 - m.nr ? a0 : k1 - m.nr;
-            const int64_t a1hi = a0 + (k1 - k0) < m.nl ? a0 + (k1 - k0) : m.nl;
+            const int64_t a1lo = a0 > k1 - v.b.n ? a0 : k1 - v.b.n;
+            const int64_t a1hi = a0 + (k1 - k0) < v.a.n ? a0 + (k1 - k0) : v.a.n;
             a1 = a1 < a1lo ? a1lo : a1 > a1hi ? a1hi : a1;
             T.la = (int)(a1 - a0);
-            T.pa = m.l0 + a0;
-            T.pb = m.r0 + (k0 - a0);
+            // lowest slot of each view's range: view indices [a0, a1) of a,
+            // [k0 - a0, k1 - a1) of b
+            T.pa = v.a.step > 0 ? view_slot(v.a, a0) : view_slot(v.a, a1 - 1);
+            T.pb = v.b.step > 0 ? view_slot(v.b, k0 - a0) : view_slot(v.b, k1 - a1 - 1);
             T.o = m.out0 + k0;
-            if (m.outer == 0) {          // first run at [out0, out0+nl), top-down
-                if (k0 < m.nl) {
-                    const int64_t e = (k1 < m.nl ? k1 : m.nl) - 1;
-                    const int64_t j0 = upper_bound_splits(sp, tpn + 1, k0) - 1;
-                    const int64_t j1 = upper_bound_splits(sp, tpn + 1, e) - 1;
-                    lo = first + (tpn - 1 - j1);
-                    hi = first + (tpn - 1 - j0);
-                }
-            } else if (m.outer == 1) {   // second run at [out0+nl, out0+n), bottom-up
-                if (k1 > m.nl) {
-                    const int64_t b0 = k0 > m.nl ? k0 - m.nl : 0;
-                    const int64_t b1 = (k1 - m.nl < m.nr ? k1 - m.nl : m.nr) - 1;
-                    const int64_t j0 = upper_bound_bsplits<TILE>(sp, tpn + 1, nn, b0) - 1;
-                    const int64_t j1 = upper_bound_bsplits<TILE>(sp, tpn + 1, nn, b1) - 1;
-                    lo = first + j0;
-                    hi = first + j1;
-                }
-            } else {                     // first run at [out0+nr, out0+n), bottom-up
-                if (k1 > m.nr) {
-                    const int64_t a0w = k0 > m.nr ? k0 - m.nr : 0;
-                    const int64_t a1w = (k1 - m.nr < m.nl ? k1 - m.nr : m.nl) - 1;
-                    const int64_t j0 = upper_bound_splits(sp, tpn + 1, a0w) - 1;
-                    const int64_t j1 = upper_bound_splits(sp, tpn + 1, a1w) - 1;
-                    lo = first + j0;
-                    hi = first + j1;
-                }
+            tile_window(v, m.out0, m.left, sp, tpn, TILE, j, first, &lo, &hi);
+            // the window lies within the node's tickets and never passes the
+            // tile's own (again a no-op for sorted runs)
+            if (lo <= hi) {
+                lo = lo < first ? first : lo;
+                hi = hi > t ? t : hi;
             }
-        }
-        // the window lies within the node's tickets and never passes the
-        // tile's own (again a no-op for sorted runs)
-        if (lo <= hi) {
-            lo = lo < first ? first : lo;
-            hi = hi > t ? t : hi;
         }
         T.dlo = (unsigned)lo;
         T.dhi = (unsigned)hi;
-        // A tile that takes all its inputs from one run at the very slots it
-        // writes (the outer run's elements that stay in place, which is half
-        // of every merge on presorted input: "Symmetric merging") moves
-        // nothing; nobody else writes into its range, so it needs no wait.
-        T.skip = T.cnt == 0 || (T.la == T.cnt && T.pa == T.o) || (T.la == 0 && T.pb == T.o);
+        // A tile that takes all its inputs from one run, stepping upwards, at
+        // the very slots it writes (the outer run's elements that stay in
+        // place: half of every merge on presorted input, "Symmetric merging",
+        // and the outer half of a concatenation) moves nothing; nobody else
+        // writes into its range, so it needs no wait.
+        const bool in_place = T.cnt == 0 || (T.la == T.cnt && v.a.step > 0 && T.pa == T.o) ||
+                              (T.la == 0 && v.b.step > 0 && T.pb == T.o);
+        if (in_place) T.flags |= TF_SKIP;
         desc[t] = T;
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // merge kernel: persistent work-groups, one output tile per iteration
@@ -486,11 +611,40 @@ __global__ __launch_bounds__(256) void tiles_kernel(Forest F, int round, const i
 #ifndef GS_MERGE_CLAIM
 #define GS_MERGE_CLAIM 1
 #endif
+// Reverses the staged elements at LDS positions [first, first + len).
+template <class K, class VS, bool HV, int NT>
+__device__ __forceinline__ void reverse_lds(K *sk, VS *sv, int first, int len)
+{
+    for (int i = threadIdx.x; i < len / 2; i += NT) {
+        const int a = lpad(first + i), b = lpad(first + len - 1 - i);
+        const K ka = sk[a], kb = sk[b];
+        sk[a] = kb;
+        sk[b] = ka;
+        if constexpr (HV) {
+            const VS va = sv[a], vb = sv[b];
+            sv[a] = vb;
+            sv[b] = va;
+        }
+    }
+}
+
+// The thread's IPT outputs of a tile staged in LDS (view-a inputs at
+// [0, la), view-b inputs at [la, cnt)), merged under order KO.
+template <class KO, class VS, bool HV, int IPT, int TILE>
+__device__ __forceinline__ void merge_tile_outputs(const typename KO::T *sk, int d, int la, int lb,
+                                                   typename KO::T (&k)[IPT], int (&srcix)[IPT])
+{
+    const int ai = merge_path_lds<KO>(d, la, lb, [&](int i) { return sk[lpad(i)]; },
+                                      [&](int i) { return sk[lpad(la + i)]; });
+    serial_merge<KO, IPT, HV>(sk, 0, la, la, lb, ai, d - ai, TILE, k, srcix);
+}
+
 template <class KT, class V, int NT, int IPT, int WAVES>
 __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv,
-                                                   Forest F, int round, int64_t nt_host, const TileDesc *desc,
+                                                   Forest F, int round, int64_t nt_host,
+                                                   const TileDesc *__restrict__ desc,
                                                    unsigned *ticket_ctr, unsigned *status, unsigned epoch,
-                                                   unsigned *err, Gate gate)
+                                                   unsigned *err, uint64_t *moved, Gate gate)
 {
     using K = typename KT::T;
     constexpr bool HV = ValOps<V>::has;
@@ -512,13 +666,23 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
     // first ticket of the chunk a claim returns
     auto chunk_start = [&](unsigned c) -> int64_t { return ((int64_t)c * kMergeGroups + grp) * CLAIM; };
     if (tid == 0) s_next = atomicAdd(my_ctr, 1u);
-    __syncthreads();
+    lds_barrier();
     int64_t cur_t = chunk_start(__builtin_amdgcn_readfirstlane(s_next));
     int slot = 0;                        // position of cur_t within its chunk
     if (cur_t >= ntiles) return;
 
+    // (descriptors and problems are uniform per tile and read-only here: the
+    // restrict qualifiers let them come through the scalar unit, so waiting
+    // for them never waits for the tile data in flight)
+    using ConstProb = const __attribute__((address_space(4))) Prob;
+    ConstProb *const probs = (ConstProb *)(uintptr_t)F.probs;
+    auto prob_of = [&](int s) -> Prob {
+        if (!probs) return F.p0;
+        ConstProb &q = probs[s];
+        return Prob{q.doff, q.hoff, q.n, q.depth, q.pad};
+    };
     TileDesc cur = desc[cur_t];
-    Prob cur_p = forest_prob(F, cur.prob);
+    Prob cur_p = prob_of(cur.prob);
     K lk[IPT];
     VS lv[IPT];
     // Straight-line loads: indices past the tile are clamped to its last input
@@ -539,12 +703,15 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
             }
         }
     };
-    if (!cur.skip) issue_loads(cur, cur_p);
+    if (!(cur.flags & TF_SKIP)) issue_loads(cur, cur_p);
+    unsigned my_moved = 0;
 
     for (;;) {
+        const bool skip = (cur.flags & TF_SKIP) != 0, copy = (cur.flags & TF_COPY) != 0;
         // stage the current tile in LDS and publish that its inputs are read
-        // (slots past the tile receive ignored values)
-        if (!cur.skip) {
+        // (slots past the tile receive ignored values); a view read from its
+        // end is staged in reverse
+        if (!skip) {
 #pragma unroll
             for (int r = 0; r < IPT; ++r) {
                 const int i = tid + r * NT;
@@ -552,7 +719,15 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
                 if constexpr (HV) sv[lpad(i)] = lv[r];
             }
         }
-        __syncthreads();
+        lds_barrier();
+        if (!skip && (cur.flags & (TF_AREV | TF_BREV))) {
+            // a view read from its end: its slots came in upwards, so its
+            // segment of the staged inputs is reversed in place
+            const int la = cur.la, lb = cur.cnt - cur.la;
+            if (cur.flags & TF_AREV) reverse_lds<K, VS, HV, NT>(sk, sv, 0, la);
+            if (cur.flags & TF_BREV) reverse_lds<K, VS, HV, NT>(sk, sv, la, lb);
+            lds_barrier();
+        }
         const bool last_of_claim = slot == CLAIM - 1;
         unsigned nt = 0;
         if (tid == 0) {
@@ -565,13 +740,11 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
         VS v[IPT];
         int srcix[IPT];
         const int d = tid * IPT;
-        int nout = cur.skip ? 0 : cur.cnt - d;
+        int nout = skip || copy ? 0 : cur.cnt - d;
         nout = nout < 0 ? 0 : (nout > IPT ? IPT : nout);
         const int la = cur.la, lb = cur.cnt - cur.la;
         if (nout > 0) {
-            const int ai = merge_path_lds<KT>(d, la, lb, [&](int i) { return sk[lpad(i)]; },
-                                              [&](int i) { return sk[lpad(la + i)]; });
-            serial_merge<KT, IPT, HV>(sk, 0, la, la, lb, ai, d - ai, TILE, k, srcix);
+            merge_tile_outputs<KT, VS, HV, IPT, TILE>(sk, d, la, lb, k, srcix);
             if constexpr (HV) {
 #pragma unroll
                 for (int i = 0; i < IPT; ++i) v[i] = sv[lpad(min(srcix[i], TILE))];
@@ -579,22 +752,37 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
         }
         if (last_of_claim) {
             if (tid == 0) s_next = nt;
-            __syncthreads();
+            lds_barrier();
         }
+        // where this tile's outputs go, fixed before the next tile's loads are
+        // issued (so the stores wait for none of them): output i lands in
+        // the caller's array below logical slot n, in the half buffer above
+        const int64_t out_o = cur.o, out_split = cur_p.n - cur.o;
+        K *const out_d = Dk + cur_p.doff + out_o;
+        K *const out_h = Hk + cur_p.hoff + (out_o - cur_p.n);
+        V *const vout_d = HV ? Dv + cur_p.doff + out_o : nullptr;
+        V *const vout_h = HV ? Hv + cur_p.hoff + (out_o - cur_p.n) : nullptr;
+        const int out_cnt = cur.cnt;
+        // wait for the window before issuing the next tile's loads: a poll
+        // of a status word has to wait for every load issued before it, so
+        // polling after the prefetch would drain the prefetch
+        if (!skip && tid < 64) wait_window(status, cur.dlo, cur.dhi, cur_t, epoch, err);
 
-        // prefetch the next tile while this one waits and stores
+        // prefetch the next tile while this one is written back and stored
         const int64_t t2 = last_of_claim ? chunk_start(__builtin_amdgcn_readfirstlane(s_next)) : cur_t + 1;
         const bool more = t2 < ntiles;
         TileDesc nxt;
         Prob nxt_p;
         if (more) {
             nxt = desc[t2];
-            nxt_p = forest_prob(F, nxt.prob);
-            if (!nxt.skip) issue_loads(nxt, nxt_p);
+            nxt_p = prob_of(nxt.prob);
+            if (!(nxt.flags & TF_SKIP)) issue_loads(nxt, nxt_p);
         }
-        if (!cur.skip) {
-            if (tid < 64) wait_window(status, cur.dlo, cur.dhi, cur_t, epoch, err);
-            __syncthreads();
+        if (!skip) {
+            my_moved += (unsigned)cur.cnt;
+            lds_barrier();             // the merge's reads are done and the window has been waited for
+            // (a concatenation has no outputs to write back: its outputs are
+            // its staged inputs, in order)
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 if (i < nout) {
@@ -602,27 +790,24 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
                     if constexpr (HV) sv[lpad(d + i)] = v[i];
                 }
             }
-            __syncthreads();
-            const Space<K> ks{Dk + cur_p.doff, Hk + cur_p.hoff, cur_p.n};
+            lds_barrier();
 #pragma unroll
             for (int r = 0; r < IPT; ++r) {
                 const int i = tid + r * NT;
-                if (i < cur.cnt) {
-                    GS_MERGE_STORE(sk[lpad(i)], ks.at(cur.o + i));
-                    if constexpr (HV) {
-                        const Space<V> vs{Dv + cur_p.doff, Hv + cur_p.hoff, cur_p.n};
-                        *vs.at(cur.o + i) = sv[lpad(i)];
-                    }
+                if (i < out_cnt) {
+                    GS_MERGE_STORE(sk[lpad(i)], i < out_split ? out_d + i : out_h + i);
+                    if constexpr (HV) *(i < out_split ? vout_d + i : vout_h + i) = sv[lpad(i)];
                 }
             }
         }
         if (!more) break;
-        __syncthreads();                 // LDS reads done before the next staging
+        lds_barrier();                 // LDS reads done before the next staging
         cur = nxt;
         cur_p = nxt_p;
         cur_t = t2;
         slot = last_of_claim ? 0 : slot + 1;
     }
+    if (tid == 0 && moved && my_moved) atomicAdd((unsigned long long *)moved, (unsigned long long)my_moved);
 }
 
 // ---------------------------------------------------------------------------
@@ -710,7 +895,7 @@ static int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 // Control block, status words, splits, tile descriptors and (for a problem
 // table) the per-round prefix rows, laid out from offset 0.
 static ForestPlan layout_forest(int64_t max_probs, int rounds, int64_t max_tickets, int64_t max_status,
-                                int64_t max_splits, int64_t leaf, int64_t tile)
+                                int64_t max_splits, int64_t leaf, int64_t tile, int64_t dir_nodes = 0)
 {
     ForestPlan f{};
     f.max_probs = max_probs;
@@ -723,7 +908,10 @@ static ForestPlan layout_forest(int64_t max_probs, int rounds, int64_t max_ticke
     f.max_splits = max_splits;
     f.off_ctrl = 0;
     f.off_status = align256(forest_ctrl_words(rounds) * 4);
-    f.off_splits = f.off_status + align256(max_status * 4);
+    f.dir_nodes = dir_nodes;
+    f.off_dirs = f.off_status + align256(max_status * 4);
+    f.off_modes = f.off_dirs + align256(dir_nodes);
+    f.off_splits = f.off_modes + align256(dir_nodes / 2);
     f.off_desc = f.off_splits + align256(max_splits * 8);
     f.off_probs = f.off_desc + align256(max_tickets * (int64_t)sizeof(TileDesc));
     f.off_tbase = f.off_probs + (max_probs > 0 ? align256(max_probs * (int64_t)sizeof(Prob)) : 0);
@@ -748,7 +936,8 @@ ForestPlan forest_plan_one(int64_t n)
         if (t > mt) mt = t;
         if (s > ms) ms = s;
     }
-    return layout_forest(0, D, mt, mt > leaves ? mt : leaves, ms, LEAF, TILE);
+    // Squidsort directions of every node (heap order, 2^(D+1) - 1 of them)
+    return layout_forest(0, D, mt, mt > leaves ? mt : leaves, ms, LEAF, TILE, (int64_t)2 << D);
 }
 
 // Capacity for any set of at most max_probs problems of at most max_len keys
@@ -792,6 +981,40 @@ static unsigned grid_for(int64_t items, int threads, int64_t cap)
     return (unsigned)g;
 }
 
+template <class V>
+constexpr bool HV_of() { return ValOps<V>::has; }
+
+// Reversal of keys[0, n) (and vals) when the top node's run came back
+// descending (*top == DIR_DESC) and the gate is open; counts the moves.
+template <class K, class V>
+__global__ __launch_bounds__(256) void root_reverse_kernel(K *keys, V *vals, int64_t n, Gate gate, const uint8_t *top,
+                                                           uint64_t *moved)
+{
+    if (gate.closed() || *top != (uint8_t)DIR_DESC) return;
+    const int64_t half = n / 2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long *)moved, (unsigned long long)(2 * half));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < half;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = n - 1 - i;
+        const K a = keys[i], b = keys[j];
+        keys[i] = b;
+        keys[j] = a;
+        if constexpr (ValOps<V>::has) {
+            const V va = vals[i], vb = vals[j];
+            vals[i] = vb;
+            vals[j] = va;
+        }
+    }
+}
+
+template <class K, class V>
+static void launch_root_reverse(K *keys, V *vals, int64_t n, Gate gate, const uint8_t *top, uint64_t *moved,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL((root_reverse_kernel<K, V>), dim3(grid_for(n / 2, 256, 8192)), dim3(256), 0, st, keys, vals, n,
+                       gate, top, moved);
+}
+
 // Enqueues a whole forest sort (or, with use_m1, one explicit merge) on the
 // forest area `fw` laid out by `fp`.  Exact launch sizes for the single
 // problem; capacity-sized persistent launches for a device-side table.
@@ -801,13 +1024,22 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
                              const F2Tables *f2 = nullptr, char *f2_img = nullptr)
 {
     using C = SortCfg<KT, V>;
+    using K = typename KT::T;
     constexpr int TILE = C::MERGE_NT * C::MERGE_IPT;
     unsigned *ctrl = (unsigned *)(fw + fp.off_ctrl);
     unsigned *status = (unsigned *)(fw + fp.off_status);
     int64_t *splits = (int64_t *)(fw + fp.off_splits);
     TileDesc *desc = (TileDesc *)(fw + fp.off_desc);
     unsigned *errw = ctrl + kErrWord;
+    uint64_t *moved = (uint64_t *)(ctrl + kMovedWord);
     const bool table = F.probs != nullptr;
+    // Squidsort's run directions: the single Frogsort1 tree only
+    const bool squid = !table && !f2 && !F.use_m1 && fp.dir_nodes >= ((int64_t)2 << F.p0.depth) &&
+                       fp.rounds < kTurnRounds;
+    if (squid) {
+        F.dirs = (uint8_t *)(fw + fp.off_dirs);
+        F.modes = (uint8_t *)(fw + fp.off_modes);
+    }
     if (table) {
         F.tbase = (const unsigned *)(fw + fp.off_tbase);
         F.sbase = (const unsigned *)(fw + fp.off_sbase);
@@ -868,11 +1100,11 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
             // one leaf per work-group; work-groups past the device's leaf
             // count exit at once
             hipLaunchKernelGGL(leaf_fn, dim3((unsigned)fp.max_status), dim3(C::LEAF_NT), 0, st, Dk, Hk, Dv, Hv, F,
-                               ctrl + 0, status, epoch, errw, gate);
+                               ctrl + 0, status, epoch, errw, moved, gate);
         } else {
             const int64_t nl = f2 ? f2->nleaves : ((int64_t)1 << F.p0.depth);
             hipLaunchKernelGGL(leaf_fn, dim3((unsigned)nl), dim3(C::LEAF_NT), 0, st, Dk, Hk, Dv, Hv, F, ctrl + 0,
-                               status, epoch, errw, gate);
+                               status, epoch, errw, moved, gate);
         }
         if (tr) trace_end(st);
     }
@@ -883,17 +1115,30 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         const int64_t ntile = table ? fp.max_tickets : f2 ? f2->rt[r] : forest_tickets<TILE>(F, F.p0, r);
         if (ntile <= 0) continue;
         if (tr) trace_begin(TK_PARTITION, st);
+        unsigned *turn_flag = ctrl + kTurnWord0 + (r < kTurnRounds ? r : 0);
         hipLaunchKernelGGL((partition_kernel<KT, TILE>), dim3(grid_for(nsplit, 256, 4096)), dim3(256), 0, st, Dk,
-                           Hk, F, r, splits, gate);
+                           Hk, F, r, splits, turn_flag, gate);
         if (tr) trace_end(st);
         if (tr) trace_begin(TK_DEPWIN, st);
-        hipLaunchKernelGGL((tiles_kernel<TILE>), dim3(grid_for(ntile, 256, 4096)), dim3(256), 0, st, F, r,
-                           (const int64_t *)splits, desc, gate);
+        // (with Squidsort the launch also turns descending outer runs around:
+        // at least 512 work-groups, most of which exit at once when there is
+        // nothing to turn)
+        unsigned tgrid = grid_for(ntile, 256, 4096);
+        if (squid && tgrid < 512) tgrid = 512;
+        hipLaunchKernelGGL((tiles_kernel<K, V, TILE>), dim3(tgrid), dim3(256), 0, st, Dk, Hk, Dv, Hv, F, r,
+                           (const int64_t *)splits, desc, (const unsigned *)turn_flag, moved, gate);
         if (tr) trace_end(st);
         if (tr) trace_begin(TK_MERGE, st);
         hipLaunchKernelGGL(merge_fn, dim3((unsigned)(ntile < mres ? ntile : mres)), dim3(C::MERGE_NT), 0, st, Dk,
                            Hk, Dv, Hv, F, r, ntile, (const TileDesc *)desc, ctrl + 32 * kMergeGroups * r, status, epoch,
-                           errw, gate);
+                           errw, moved, gate);
+        if (tr) trace_end(st);
+    }
+    if (squid && F.p0.n > 1) {
+        // the wanted order is enforced once: a top run that came back
+        // descending is reversed
+        if (tr) trace_begin(TK_OTHER, st);
+        launch_root_reverse(Dk + F.p0.doff, HV_of<V>() ? Dv + F.p0.doff : Dv, F.p0.n, gate, F.dirs, moved, st);
         if (tr) trace_end(st);
     }
     return hipGetLastError();
@@ -1065,8 +1310,9 @@ static void launch_reverse(K *keys, V *vals, int64_t n, hipStream_t st, Gate gat
 
 template <class KT>
 __global__ __launch_bounds__(256) void order_sample_kernel(const typename KT::T *keys, int64_t n, unsigned *word,
-                                                           int keys_only)
+                                                           int keys_only, uint64_t *moved)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *moved = 0;     // the call's move count starts here
     const int64_t m = n - 1;             // pairs
     unsigned bits = 15u;
     for (int j = threadIdx.x; j < 4096; j += 256) {
@@ -1112,10 +1358,10 @@ __global__ void order_decide_kernel(unsigned *word, int keys_only)
 
 template <class KT>
 static void launch_order_check(const typename KT::T *keys, int64_t n, unsigned *word, bool keys_only,
-                               hipStream_t st)
+                               uint64_t *moved, hipStream_t st)
 {
     const int ko = keys_only ? 1 : 0;
-    hipLaunchKernelGGL((order_sample_kernel<KT>), dim3(1), dim3(256), 0, st, keys, n, word, ko);
+    hipLaunchKernelGGL((order_sample_kernel<KT>), dim3(1), dim3(256), 0, st, keys, n, word, ko, moved);
     hipLaunchKernelGGL((order_check_kernel<KT>), dim3(grid_for(n - 1, 256, 8192)), dim3(256), 0, st, keys, n,
                        word, ko);
     hipLaunchKernelGGL(order_decide_kernel, dim3(1), dim3(1), 0, st, word, ko);
@@ -1129,7 +1375,8 @@ static hipError_t run_sort_adaptive(typename KT::T *keys, V *vals, int64_t n, ch
 {
     if (n <= 1) return hipSuccess;
     unsigned *word = (unsigned *)(ws + p.off_order);
-    launch_order_check<KT>(keys, n, word, !ValOps<V>::has, st);
+    uint64_t *moved = (uint64_t *)(ws + p.off_forest + p.forest.off_ctrl + 4 * kMovedWord);
+    launch_order_check<KT>(keys, n, word, !ValOps<V>::has, moved, st);
     hipError_t e = run_sort<KT, V>(keys, vals, n, ws, p, st, Gate{word, (unsigned)ORD_SORT});
     if (e != hipSuccess) return e;
     launch_reverse(keys, vals, n, st, Gate{word, (unsigned)ORD_REVERSED});

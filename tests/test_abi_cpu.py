@@ -323,3 +323,155 @@ def test_noalloc_limits():
     assert g.lib.gs_sort_f64_noalloc(None, 10, None) == g.GS_EINVAL
     assert g.lib.gs_sort_f64_noalloc(None, 0, None) == g.GS_OK
     assert g.lib.gs_sort_f64_noalloc(fake, 1, None) == g.GS_OK
+
+
+# ---------------------------------------------------------------------------
+# the in-place protocol's windows against brute force ("Symmetric merging")
+# ---------------------------------------------------------------------------
+ASC, DESC = 1, 2
+MERGE, MERGE_REV, CONCAT = 0, 1, 2
+
+
+def _merge_case(rng, outer, kind, tile):
+    """A random merge of the frog kinds: the outer run inside the output
+    (outer 0: first run at its start, written top-down; 1: second run at its
+    end, bottom-up; 2: first run at its end, bottom-up), the inner run
+    outside; random sizes (ragged against the tile), ties, and run
+    directions fitting the node kind."""
+    nl, nr = (int(v) for v in rng.integers(1, 5 * tile, 2))
+    n = nl + nr
+    out0 = int(rng.integers(0, 3 * tile))
+    gap = int(rng.integers(0, tile))
+    if outer == 0:
+        l0, r0 = out0, out0 + n + gap
+    elif outer == 1:
+        if rng.random() < 0.5:              # inner run just before the output (a right node)
+            out0 += nl + gap
+            l0 = out0 - nl - gap
+        else:                               # inner run past the output (an explicit merge)
+            l0 = out0 + n + gap
+        r0 = out0 + nl
+    else:
+        l0 = out0 + nr
+        r0 = out0 + n + gap
+    left = 1 if outer == 0 else 0
+    vals = int(rng.choice([3, 50, 10 ** 6]))
+    sl = np.sort(rng.integers(0, vals, nl))
+    sr = np.sort(rng.integers(0, vals, nr))
+    outer_first = outer != 1
+    if kind == CONCAT:
+        dl = dr = ASC if rng.random() < 0.5 else DESC
+        if dl == ASC:
+            sr = sr + sl[-1]                        # ties across the seam allowed
+        else:
+            sl = sl + sr[-1] + 1                    # strictly above
+    else:
+        d_outer = DESC if kind == MERGE_REV else ASC
+        d_inner = ASC if rng.random() < 0.5 else DESC
+        dl, dr = (d_outer, d_inner) if outer_first else (d_inner, d_outer)
+    return dict(merge=np.array([l0, nl, r0, nr, out0, left, outer], dtype=np.int64),
+                sl=sl, sr=sr, dl=dl, dr=dr, n=n, outer_first=outer_first)
+
+
+def _brute_windows(c, kind, tile):
+    """Tickets each tile must wait for, from the slots every tile reads and
+    writes (the outer run already turned for MERGE_REV), and the splits."""
+    l0, nl, r0, nr, out0, left, outer = (int(v) for v in c["merge"])
+    n = c["n"]
+    # storage direction of each run when the tiles run
+    st_l = c["dl"] == DESC and not (kind == MERGE_REV and c["outer_first"])
+    st_r = c["dr"] == DESC and not (kind == MERGE_REV and not c["outer_first"])
+    slot_l = (lambda i: l0 + nl - 1 - i) if st_l else (lambda i: l0 + i)
+    slot_r = (lambda i: r0 + nr - 1 - i) if st_r else (lambda i: r0 + i)
+    if kind == CONCAT:
+        # stored orders side by side
+        src = [l0 + i for i in range(nl)] + [r0 + i for i in range(nr)]
+        from_a = [True] * nl + [False] * nr
+    else:
+        i = j = 0
+        src, from_a = [], []
+        sl, sr = c["sl"], c["sr"]
+        while i < nl or j < nr:
+            if j >= nr or (i < nl and not sr[j] < sl[i]):
+                src.append(slot_l(i)); from_a.append(True); i += 1
+            else:
+                src.append(slot_r(j)); from_a.append(False); j += 1
+    tpn = -(-n // tile)
+    splits = np.array([sum(from_a[: min(k * tile, n)]) for k in range(tpn + 1)], dtype=np.int64)
+    ticket = (lambda jj: tpn - 1 - jj) if left else (lambda jj: jj)
+    reads = [set(src[jj * tile: min((jj + 1) * tile, n)]) for jj in range(tpn)]
+    windows = {}
+    for jj in range(tpn):
+        writes = set(range(out0 + jj * tile, out0 + min((jj + 1) * tile, n)))
+        windows[ticket(jj)] = sorted(ticket(k) for k in range(tpn) if reads[k] & writes)
+    return splits, windows, tpn
+
+
+@pytest.mark.parametrize("outer", [0, 1, 2])
+@pytest.mark.parametrize("kind", [MERGE, MERGE_REV, CONCAT])
+@pytest.mark.parametrize("seed", range(20))
+def test_tile_windows_match_brute_force(outer, kind, seed):
+    """Every merge tile's window, as the kernels compute it, is the smallest
+    ticket range holding every ticket whose inputs include a slot the tile
+    writes, and never passes the tile's own ticket: the outer run only moves away
+    from the side the output is written from.  Both frog node kinds, the
+    third kind of the explicit merges, concatenations, inner runs read from
+    their end and outer runs turned around first, with ties."""
+    rng = np.random.default_rng(100 * seed + 10 * outer + kind)
+    tile = int(rng.choice([4, 7, 16]))
+    c = _merge_case(rng, outer, kind, tile)
+    splits, want, tpn = _brute_windows(c, kind, tile)
+    got = np.zeros(2 * tpn, dtype=np.int64)
+    r = g.lib.gs_plan_tile_windows(c["merge"].ctypes.data, kind, c["dl"], c["dr"], 1, tile,
+                                   splits.ctypes.data, got.ctypes.data)
+    assert r == tpn
+    for t in range(tpn):
+        w = want[t]
+        assert not w or w[-1] <= t, (t, w)                        # never a later ticket
+        # the window is the smallest ticket range holding that set (a tile
+        # in between that reads none of those slots may be waited for too)
+        lo, hi = int(got[2 * t]), int(got[2 * t + 1])
+        assert ((lo, hi) == (w[0], w[-1])) if w else lo > hi, (t, lo, hi, w)
+
+
+@pytest.mark.parametrize("n", [8193, 12345, 65536, (1 << 20) + 7, 3_000_017])
+def test_leaf_windows_match_brute_force(n):
+    """Every leaf's window is exactly the set of leaf tickets whose input
+    chunks its destination covers, never past its own ticket."""
+    depth, _ = g.plan_depth(n)
+    L = 1 << depth
+    nodes = [g.plan_node(n, depth, i) for i in range(L)]        # (s, n, left, data start, input offset)
+    chunk_lo = np.array([nd[4] for nd in nodes])
+    lo_hi = np.zeros(2, dtype=np.int64)
+    for i, nd in enumerate(nodes):
+        dst, ln = nd[3], nd[1]
+        cover = set()
+        if dst < n:
+            for p in (dst, min(dst + ln, n) - 1):
+                cover.add(int(np.searchsorted(chunk_lo, p, side="right") - 1))
+            cover = set(range(min(cover), max(cover) + 1))
+        want = sorted(L - 1 - k for k in cover)
+        assert g.lib.gs_plan_leaf_window(n, depth, i, lo_hi.ctypes.data) == 0
+        lo, hi = int(lo_hi[0]), int(lo_hi[1])
+        assert (list(range(lo, hi + 1)) if lo <= hi else []) == want
+        assert not want or want[-1] <= L - 1 - i
+
+
+def test_tile_windows_check_sees_a_wrong_layout():
+    """The brute-force check above is not blind: windows computed as if a
+    turned outer run were still stored descending disagree with it."""
+    bad = 0
+    for seed in range(20):
+        for outer in (0, 1, 2):
+            rng = np.random.default_rng(100 * seed + 10 * outer + MERGE_REV)
+            tile = int(rng.choice([4, 7, 16]))
+            c = _merge_case(rng, outer, MERGE_REV, tile)
+            splits, want, tpn = _brute_windows(c, MERGE_REV, tile)
+            got = np.zeros(2 * tpn, dtype=np.int64)
+            g.lib.gs_plan_tile_windows(c["merge"].ctypes.data, MERGE_REV, c["dl"], c["dr"], 0, tile,
+                                       splits.ctypes.data, got.ctypes.data)
+            for t in range(tpn):
+                w = want[t]
+                lo, hi = int(got[2 * t]), int(got[2 * t + 1])
+                bad += (((lo, hi) != (w[0], w[-1])) if w else lo <= hi)
+    assert bad > 0

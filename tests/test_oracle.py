@@ -728,16 +728,18 @@ def test_squid_moves_equal_frogsort_presorted(orc, n):
     assert c["rev_moves"] == n - (n & 1)
 
 
+@pytest.mark.parametrize("mode", [0, 2])
 @pytest.mark.parametrize("n", range(0, 8))
-def test_squid_exhaustive_weak_orders(orc, n):
+def test_squid_exhaustive_weak_orders(orc, n, mode):
     """Every weak order of n keys (tie class 0 as signed zeros, so stability
     is visible in the bits): the model's output is the definition's, element
-    by element, and no write lands on an unread element."""
+    by element, and no write lands on an unread element -- for the reading
+    above (mode 0) and for the rule the GPU runs (mode 2)."""
     arrs = _weak_orders(n)
     for row in arrs:
         x = row.astype(np.float64)
         x[(x == 0) & ((np.arange(n) & 1) == 1)] = -0.0
-        y, lab, c = orc.squid_model(x)
+        y, lab, c = orc.squid_model(x, mode=mode)
         p = np.argsort(row, kind="stable")
         assert np.array_equal(lab, p), row
         assert np.array_equal(y.view(np.uint64), x[p].view(np.uint64))
@@ -763,19 +765,40 @@ def _runs(rng, n, max_run, tie_values):
     return np.concatenate(out)[:n]
 
 
+@pytest.mark.parametrize("mode", [0, 2])
 @pytest.mark.parametrize("seed", range(12))
-def test_squid_sorts_mixed_runs_stably(orc, seed):
+def test_squid_sorts_mixed_runs_stably(orc, seed, mode):
     rng = np.random.default_rng(seed)
     n = int(rng.integers(2, 5000))
     x = _runs(rng, n, int(rng.integers(2, 300)), int(rng.integers(2, 50)))
     x[(x == 0) & (rng.random(n) < 0.5)] = -0.0
-    y, lab, c = orc.squid_model(x)
+    y, lab, c = orc.squid_model(x, mode=mode)
     p = np.argsort(x, kind="stable")
     assert np.array_equal(lab, p)
     assert np.array_equal(y.view(np.uint64), x[p].view(np.uint64))
     assert c["overwrites"] == 0
     frog = orc.frog_model(x, g=1)
     assert c["moves"] <= frog["moves"] + x.size
+
+
+@pytest.mark.parametrize("k", range(1, 13))
+def test_squid_turning_rule_counts(orc, k):
+    """The GPU's rule (mode 2) on presorted and reversed input is the
+    model's: no merge, 50 % moves, one final reversal for reversed input.  On
+    descending runs of 2^j that the tree then has to merge, it moves at most
+    what Frogsort1 moves (each turn costs half of the node it precedes, and
+    the concatenations below it saved half of every node)."""
+    n = 1 << k
+    for x, rev in ((np.arange(1, n + 1, dtype=np.float64), 0), (np.arange(n, 0, -1, dtype=np.float64), n)):
+        _, _, c = orc.squid_model(x, mode=2)
+        assert c["merge_cmp"] == 0 and c["moves"] == (n // 2) * k and c["rev_moves"] == (rev if n > 1 else 0)
+    rng = np.random.default_rng(k)
+    for j in range(1, k):
+        runs = np.arange(n, dtype=np.float64).reshape(-1, 1 << j)[:, ::-1]      # descending runs
+        x = runs[rng.permutation(runs.shape[0])].reshape(-1).copy()
+        _, lab, c = orc.squid_model(x, mode=2)
+        assert np.array_equal(lab, np.argsort(x, kind="stable"))
+        assert c["moves"] <= orc.frog_model(x, g=1)["moves"] + n
 
 
 @pytest.mark.parametrize("pattern", ["asclocal", "ascglobal", "desclocal", "descglobal",

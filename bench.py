@@ -121,9 +121,12 @@ def _extras_patterns(gs, torch, W, n, dev, stream):
     need = gs.gs_workspace_bytes_f64(n)
     ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
     ws = ws[(-ws.data_ptr()) % 256:][:need]
-    for pat in ("tied", "presorted", "reversed", "perturbed"):
+    # the build's own patterns, then the paper's ("Methods and measurement")
+    plan = [(p, lambda p=p: W.f64_pattern(p, n, seed=0)) for p in ("tied", "presorted", "reversed", "perturbed")]
+    plan += [(p, lambda p=p: W.paper_pattern(p, n, seed=0)) for p in W.PAPER_PATTERNS]
+    for pat, make in plan:
         log(f"extras: plain {pat}")
-        x = torch.from_numpy(W.f64_pattern(pat, n, seed=0)).to(dev)
+        x = torch.from_numpy(make()).to(dev)
         buf = torch.empty_like(x)
 
         def fn_p(i, timed):
@@ -131,9 +134,16 @@ def _extras_patterns(gs, torch, W, n, dev, stream):
                 buf.copy_(x)
             else:
                 gs.gs_sort_f64(buf, workspace=ws)
-        gs.gs_sort_f64(buf.copy_(x), workspace=ws)
+        rep = gs.gs_sort_f64(buf.copy_(x), workspace=ws, report=True)
         ms = _time_calls(torch, stream, fn_p, 3)
-        pats[pat] = {"ms": round(ms, 3), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3)}
+        # element moves of the call (16 B per move: one 8-byte read and one
+        # 8-byte write), against the 16n(levels+1) of a sort that merges
+        # every level in full
+        moved = int(rep["keys_moved"])
+        pats[pat] = {"ms": round(ms, 3), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
+                     "keys_moved": moved, "moved_bytes_gb": round(16.0 * moved / 1e9, 3),
+                     "moves_vs_full_merge": round(moved / (n * (rep["levels"] + 1)), 4),
+                     "order": int(rep["order"])}
         del x, buf
     del ws
     return pats

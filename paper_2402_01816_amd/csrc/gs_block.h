@@ -196,6 +196,77 @@ __device__ __forceinline__ void lane_merge_rounds(double (&k)[IPT], int rounds)
     }
 }
 
+// The first / second of two keys in the order DIR (1 ascending, -1
+// descending), as one min and one max: exact for keys whose equal values are
+// bit for bit identical (no NaN, no signed zero).
+template <int DIR>
+__device__ __forceinline__ double first_of(double a, double b)
+{
+    return DIR > 0 ? __builtin_fmin(a, b) : __builtin_fmax(a, b);
+}
+template <int DIR>
+__device__ __forceinline__ double second_of(double a, double b)
+{
+    return DIR > 0 ? __builtin_fmax(a, b) : __builtin_fmin(a, b);
+}
+
+// The LDS merge rounds of the block sort for blocks whose equal keys are bit
+// for bit identical, on runs stored alternately in order and reversed (run r
+// of a round reversed when r is odd): the first run of a pair is read from
+// its start, the second from its end, so the two heads a thread merges never
+// leave the pair -- a run that runs out continues into the other run's
+// largest keys, which come out no earlier than the keys still needed (equal
+// ones are identical) -- and the serial merge needs no bounds checks.  Each
+// step keeps the two heads as (kept, new): the output is the first of them,
+// the kept one the second, and the run the next head comes from follows from
+// the comparison and the previous step's run.  Every thread holds IPT sorted
+// keys of runs of w0 (positions IPT*thread ..); on return sk holds every
+// aligned block of maxw keys sorted in order.
+template <class KT, int DIR, int NT, int IPT>
+__device__ __forceinline__ void block_merge_rounds_identical(typename KT::T *sk, typename KT::T (&k)[IPT], int w0,
+                                                             int maxw)
+{
+    using K = typename KT::T;
+    const int base = threadIdx.x * IPT;
+    {
+        const int r0 = base / w0, off = base - r0 * w0;
+        const bool rev = (r0 & 1) && w0 < maxw;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) sk[lpad(rev ? r0 * w0 + w0 - 1 - off - i : base + i)] = k[i];
+    }
+    __syncthreads();
+    for (int w = w0; w < maxw; w *= 2) {
+        const int a0 = (base / (2 * w)) * 2 * w, kd = base - a0, top = a0 + 2 * w - 1;
+        // merge-path split: view a = sk[a0 + i], view b = sk[top - j]
+        int lo = kd > w ? kd - w : 0, hi = kd < w ? kd : w;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (KT::less(sk[lpad(top - (kd - 1 - mid))], sk[lpad(a0 + mid)])) hi = mid;
+            else lo = mid + 1;
+        }
+        int sa = a0 + lo, sb = top - (kd - lo);
+        K keep = sk[lpad(sa)], nv = sk[lpad(sb)];
+        bool tb = true;                  // the run of nv: true = the second run
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const bool lt = KT::less(nv, keep);
+            tb = lt == tb;               // the run the output comes from
+            k[i] = first_of<DIR>(keep, nv);
+            keep = second_of<DIR>(keep, nv);
+            if (i + 1 < IPT) {
+                sb -= tb ? 1 : 0;
+                sa += tb ? 0 : 1;
+                nv = sk[lpad(tb ? sb : sa)];
+            }
+        }
+        __syncthreads();
+        const bool rev = ((base / (2 * w)) & 1) && 2 * w < maxw;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) sk[lpad(rev ? top - kd - i : base + i)] = k[i];
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // block sort in LDS
 // ---------------------------------------------------------------------------
@@ -270,6 +341,12 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
             const int rounds = maxw >= 8 * IPT ? 3 : maxw >= 4 * IPT ? 2 : maxw >= 2 * IPT ? 1 : 0;
             lane_merge_rounds<NetMinMax<KT>::dir, IPT>(k, rounds);
             w0 = IPT << rounds;
+            // a whole block: the remaining rounds on alternately reversed runs
+            if constexpr (!PARTIAL) {
+                __syncthreads();
+                block_merge_rounds_identical<KT, NetMinMax<KT>::dir, NT, IPT>(sk, k, w0, maxw);
+                return;
+            }
         }
     }
     __syncthreads();

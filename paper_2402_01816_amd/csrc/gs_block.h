@@ -196,6 +196,101 @@ __device__ __forceinline__ void lane_merge_rounds(double (&k)[IPT], int rounds)
     }
 }
 
+// The register phase of the block sort for float64 blocks whose equal keys are
+// bit for bit identical, 16 keys per thread: Batcher's network on each
+// thread's keys, then up to three bitonic merge levels across 2, 4 and 8
+// lanes, so that runs of w = min(maxw, 128) keys end up sorted -- in the
+// order DIR where w == maxw, else alternately in order and reversed (run r
+// reversed when r is odd), the layout the LDS rounds take.
+//
+// Every compare-exchange is one instruction per key by a sign convention: a
+// lane whose keys must come out in descending value order (a block sorted in
+// reverse, or the lane that keeps the larger keys of a cross-lane pair) holds
+// its keys negated, so that sorting ascending in storage sorts it the way it
+// needs.  A cross-lane pair always has one plain and one negated lane, and
+// both keep min(own, -partner): the plain one the smaller key, the negated one
+// the negated larger key.  Between stages the lanes whose role changes negate
+// their keys (a multiply by -1, exact for the finite and infinite keys these
+// blocks hold).  The merge levels: 2 lanes (half-cleaner on lane bit 0, then
+// in-register half-cleaners), 4 lanes (half-cleaners on lane bits 1 and 0; its
+// runs all ascend, which the next level needs) and 8 lanes (a flip that pairs
+// lane t with 7 - t and register r with 15 - r, then half-cleaners on lane
+// bits 1 and 0).  Position bit 4 + j is lane bit j.  Every lane of the wave
+// must execute this (DPP reads neighbours).
+template <int DIR, int IPT>
+__device__ __forceinline__ void register_sort_identical(double (&k)[IPT], int maxw)
+{
+    static_assert(IPT == 16, "lane bit j is position bit 4 + j");
+    const unsigned lane = threadIdx.x & 63;
+    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    const bool neg = DIR < 0;
+    bool cur = false;
+    auto set_mode = [&](bool m) {
+        // kept a multiply (an empty asm hides that s is +-1): its result is a
+        // canonical float, so the min and max that follow need no extra
+        // canonicalising instruction, as a sign flip on the bits would
+        double s = m != cur ? -1.0 : 1.0;
+        asm volatile("" : "+v"(s));
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k[r] *= s;
+        cur = m;
+    };
+    // keep min(own, -partner): partner register r (MIRROR: 15 - r) of the lane QP reads
+    auto cross = [&](auto qp, auto mirror) {
+        constexpr int QP = decltype(qp)::value;
+        constexpr bool MIRROR = decltype(mirror)::value;
+        double o[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = quad_swap<QP>(k[MIRROR ? IPT - 1 - r : r]);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k[r] = __builtin_fmin(k[r], -o[r]);
+    };
+    using X1 = std::integral_constant<int, 0xB1>;    // lane t ^ 1
+    using X2 = std::integral_constant<int, 0x4E>;    // lane t ^ 2
+    using M8 = std::integral_constant<int, 0x141>;   // lane 7 - t within eight
+    using Same = std::false_type;
+    using Mirror = std::true_type;
+
+    // levels 0-3 in registers; their runs alternate with position bit 4
+    set_mode(neg ^ (maxw > 16 && b0));
+    {
+        constexpr SortNet<IPT> net = batcher_net<IPT>();
+#pragma unroll
+        for (int c = 0; c < net.count; ++c) {
+            const double a = k[net.lo[c]], b = k[net.hi[c]];
+            k[net.lo[c]] = __builtin_fmin(a, b);
+            k[net.hi[c]] = __builtin_fmax(a, b);
+        }
+    }
+    if (maxw >= 32) {                    // level 4: runs alternate with bit 5 unless last
+        const bool d = maxw > 32 && b1;
+        set_mode(neg ^ b0 ^ d);
+        cross(X1{}, Same{});
+        set_mode(neg ^ d);
+        bitonic_clean_regs<1, IPT>(k);
+    }
+    if (maxw >= 64) {                    // level 5: every run ascends
+        set_mode(neg ^ b1);
+        cross(X2{}, Same{});
+        set_mode(neg ^ b0);
+        cross(X1{}, Same{});
+        set_mode(neg);
+        bitonic_clean_regs<1, IPT>(k);
+    }
+    if (maxw >= 128) {                   // level 6: runs alternate with bit 7 unless last
+        const bool d = maxw > 128 && b3;
+        set_mode(neg ^ b2 ^ d);
+        cross(M8{}, Mirror{});
+        set_mode(neg ^ b1 ^ d);
+        cross(X2{}, Same{});
+        set_mode(neg ^ b0 ^ d);
+        cross(X1{}, Same{});
+        set_mode(neg ^ d);
+        bitonic_clean_regs<1, IPT>(k);
+    }
+    set_mode(false);
+}
+
 // The first / second of two keys in the order DIR (1 ascending, -1
 // descending), as one min and one max: exact for keys whose equal values are
 // bit for bit identical (no NaN, no signed zero).
@@ -210,6 +305,10 @@ __device__ __forceinline__ double second_of(double a, double b)
     return DIR > 0 ? __builtin_fmax(a, b) : __builtin_fmin(a, b);
 }
 
+// Byte offset of logical LDS index i in the lpad layout.  For a base b that is
+// a multiple of 16, lpad8(b + x) == lpad8(b) + lpad8(x).
+__device__ __forceinline__ unsigned lpad8(unsigned i) { return (i + (i >> 4)) << 3; }
+
 // The LDS merge rounds of the block sort for blocks whose equal keys are bit
 // for bit identical, on runs stored alternately in order and reversed (run r
 // of a round reversed when r is odd): the first run of a pair is read from
@@ -219,50 +318,74 @@ __device__ __forceinline__ double second_of(double a, double b)
 // ones are identical) -- and the serial merge needs no bounds checks.  Each
 // step keeps the two heads as (kept, new): the output is the first of them,
 // the kept one the second, and the run the next head comes from follows from
-// the comparison and the previous step's run.  Every thread holds IPT sorted
-// keys of runs of w0 (positions IPT*thread ..); on return sk holds every
-// aligned block of maxw keys sorted in order.
+// the comparison and the previous step's run.  Every step moves exactly one
+// head, so after s steps the second run's head sits at (first head + e - s)
+// for a per-thread constant e, and only the first head is tracked.  Merge
+// pairs, thread positions and the reversed second views all start at
+// multiples of 16, where the pad layout is linear, so every probe address is
+// a per-pair base plus lpad8 of a small index.  Every thread holds IPT sorted
+// keys of runs of w0 (positions IPT*thread ..), the runs already alternately
+// in order and reversed when w0 < maxw; on return sk holds every aligned block
+// of maxw keys sorted in order.  Threads whose maxw block starts at or past
+// `active` hold only padding and skip the work.
 template <class KT, int DIR, int NT, int IPT>
 __device__ __forceinline__ void block_merge_rounds_identical(typename KT::T *sk, typename KT::T (&k)[IPT], int w0,
-                                                             int maxw)
+                                                             int maxw, int active)
 {
+    static_assert(IPT == 16, "the address arithmetic assumes 16 keys per thread, the pad period");
     using K = typename KT::T;
-    const int base = threadIdx.x * IPT;
-    {
-        const int r0 = base / w0, off = base - r0 * w0;
-        const bool rev = (r0 & 1) && w0 < maxw;
+    char *lb = reinterpret_cast<char *>(sk);
+    const unsigned base = threadIdx.x * IPT;
+    const bool work = base < (((unsigned)active + maxw - 1) & ~(unsigned)(maxw - 1));
+    if (work) {
+        const unsigned b8 = lpad8(base);
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) sk[lpad(rev ? r0 * w0 + w0 - 1 - off - i : base + i)] = k[i];
+        for (int i = 0; i < IPT; ++i) *reinterpret_cast<K *>(lb + b8 + 8u * i) = k[i];
     }
     __syncthreads();
-    for (int w = w0; w < maxw; w *= 2) {
-        const int a0 = (base / (2 * w)) * 2 * w, kd = base - a0, top = a0 + 2 * w - 1;
-        // merge-path split: view a = sk[a0 + i], view b = sk[top - j]
-        int lo = kd > w ? kd - w : 0, hi = kd < w ? kd : w;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (KT::less(sk[lpad(top - (kd - 1 - mid))], sk[lpad(a0 + mid)])) hi = mid;
-            else lo = mid + 1;
-        }
-        int sa = a0 + lo, sb = top - (kd - lo);
-        K keep = sk[lpad(sa)], nv = sk[lpad(sb)];
-        bool tb = true;                  // the run of nv: true = the second run
+    for (unsigned w = w0; w < (unsigned)maxw; w *= 2) {
+        const unsigned a0 = base & ~(2 * w - 1), kd = base - a0;
+        if (work) {
+            // merge-path split over views a[i] = sk[a0 + i], b[j] = sk[a0 + 2w - 1 - j]:
+            // the probe pair (a[mid], b[kd - 1 - mid]) sits at a0 + mid and c0 + mid
+            const unsigned c0 = a0 + 2 * w - kd;
+            const unsigned pa = lpad8(a0), pc = lpad8(c0);
+            unsigned lo = kd > w ? kd - w : 0, hi = kd < w ? kd : w;
+            while (lo < hi) {
+                const unsigned mid = (lo + hi) >> 1, pm = lpad8(mid);
+                if (KT::less(*reinterpret_cast<const K *>(lb + pc + pm), *reinterpret_cast<const K *>(lb + pa + pm)))
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            unsigned sa = a0 + lo;                   // first head; the second at sa + e - steps
+            const unsigned e = 2 * w - 1 - kd;
+            K keep = *reinterpret_cast<const K *>(lb + lpad8(sa));
+            K nv = *reinterpret_cast<const K *>(lb + lpad8(sa + e));
+            bool tb = true;                          // the run of nv: true = the second run
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            const bool lt = KT::less(nv, keep);
-            tb = lt == tb;               // the run the output comes from
-            k[i] = first_of<DIR>(keep, nv);
-            keep = second_of<DIR>(keep, nv);
-            if (i + 1 < IPT) {
-                sb -= tb ? 1 : 0;
-                sa += tb ? 0 : 1;
-                nv = sk[lpad(tb ? sb : sa)];
+            for (int i = 0; i < IPT; ++i) {
+                const bool lt = KT::less(nv, keep);
+                tb = lt == tb;                       // the run the next head comes from
+                k[i] = first_of<DIR>(keep, nv);
+                keep = second_of<DIR>(keep, nv);
+                if (i + 1 < IPT) {
+                    sa += tb ? 0u : 1u;
+                    const unsigned idx = tb ? sa + e - (unsigned)(i + 1) : sa;
+                    nv = *reinterpret_cast<const K *>(lb + lpad8(idx));
+                }
             }
         }
         __syncthreads();
-        const bool rev = ((base / (2 * w)) & 1) && 2 * w < maxw;
+        // the pair's output is run (a0 / 2w); odd ones are stored reversed
+        // unless this was the last round
+        const bool rev = ((base / (2 * w)) & 1) && 2 * w < (unsigned)maxw;
+        const unsigned b8 = lpad8(rev ? a0 + 2 * w - IPT - kd : base);
+        if (work) {
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) sk[lpad(rev ? top - kd - i : base + i)] = k[i];
+            for (int i = 0; i < IPT; ++i)
+                *reinterpret_cast<K *>(lb + b8 + 8u * (rev ? IPT - 1 - i : i)) = k[i];
+        }
         __syncthreads();
     }
 }
@@ -305,14 +428,31 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
     }
     bool network = false;
     if constexpr (!HV) network = ties_identical;
+    if constexpr (!HV && NetMinMax<KT>::dir != 0 && IPT == 16) {
+        // every thread joins (padding keys are all equal, so sorting them
+        // changes nothing)
+        if (network) {
+            register_sort_identical<NetMinMax<KT>::dir, IPT>(k, maxw);
+            __syncthreads();
+            block_merge_rounds_identical<KT, NetMinMax<KT>::dir, NT, IPT>(sk, k, maxw < 128 ? maxw : 128, maxw,
+                                                                           active);
+            return;
+        }
+    }
     if (work && network) {
         constexpr SortNet<IPT> net = batcher_net<IPT>();
 #pragma unroll
         for (int c = 0; c < net.count; ++c) {
             const K a = k[net.lo[c]], b = k[net.hi[c]];
-            const bool sw = KT::less(b, a);
-            k[net.lo[c]] = sw ? b : a;
-            k[net.hi[c]] = sw ? a : b;
+            if constexpr (NetMinMax<KT>::dir != 0) {
+                // a compare-exchange as one min and one max
+                k[net.lo[c]] = first_of<NetMinMax<KT>::dir>(a, b);
+                k[net.hi[c]] = second_of<NetMinMax<KT>::dir>(a, b);
+            } else {
+                const bool sw = KT::less(b, a);
+                k[net.lo[c]] = sw ? b : a;
+                k[net.hi[c]] = sw ? a : b;
+            }
         }
     } else if (work) {
 #pragma unroll
@@ -341,12 +481,6 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
             const int rounds = maxw >= 8 * IPT ? 3 : maxw >= 4 * IPT ? 2 : maxw >= 2 * IPT ? 1 : 0;
             lane_merge_rounds<NetMinMax<KT>::dir, IPT>(k, rounds);
             w0 = IPT << rounds;
-            // a whole block: the remaining rounds on alternately reversed runs
-            if constexpr (!PARTIAL) {
-                __syncthreads();
-                block_merge_rounds_identical<KT, NetMinMax<KT>::dir, NT, IPT>(sk, k, w0, maxw);
-                return;
-            }
         }
     }
     __syncthreads();

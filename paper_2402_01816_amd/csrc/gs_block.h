@@ -20,7 +20,7 @@ struct ValOps<NoVal> {
 
 // LDS index with one pad slot per 16 elements: a thread's IPT consecutive
 // outputs, and merge heads spaced about 8 apart, land in distinct banks.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+__device__ __forceinline__ constexpr int lpad(int i) { return i + (i >> 4); }
 // slots for TILE elements plus one readable slot past the end
 template <int TILE>
 constexpr int lds_slots() { return TILE + TILE / 16 + 2; }
@@ -318,9 +318,7 @@ __device__ __forceinline__ unsigned lpad8(unsigned i) { return (i + (i >> 4)) <<
 // ones are identical) -- and the serial merge needs no bounds checks.  Each
 // step keeps the two heads as (kept, new): the output is the first of them,
 // the kept one the second, and the run the next head comes from follows from
-// the comparison and the previous step's run.  Every step moves exactly one
-// head, so after s steps the second run's head sits at (first head + e - s)
-// for a per-thread constant e, and only the first head is tracked.  Merge
+// the comparison and the previous step's run.  Merge
 // pairs, thread positions and the reversed second views all start at
 // multiples of 16, where the pad layout is linear, so every probe address is
 // a per-pair base plus lpad8 of a small index.  Every thread holds IPT sorted
@@ -358,10 +356,9 @@ __device__ __forceinline__ void block_merge_rounds_identical(typename KT::T *sk,
                 else
                     lo = mid + 1;
             }
-            unsigned sa = a0 + lo;                   // first head; the second at sa + e - steps
-            const unsigned e = 2 * w - 1 - kd;
+            unsigned sa = a0 + lo, sb = sa + 2 * w - 1 - kd;   // the heads of both views
             K keep = *reinterpret_cast<const K *>(lb + lpad8(sa));
-            K nv = *reinterpret_cast<const K *>(lb + lpad8(sa + e));
+            K nv = *reinterpret_cast<const K *>(lb + lpad8(sb));
             bool tb = true;                          // the run of nv: true = the second run
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
@@ -370,9 +367,10 @@ __device__ __forceinline__ void block_merge_rounds_identical(typename KT::T *sk,
                 k[i] = first_of<DIR>(keep, nv);
                 keep = second_of<DIR>(keep, nv);
                 if (i + 1 < IPT) {
-                    sa += tb ? 0u : 1u;
-                    const unsigned idx = tb ? sa + e - (unsigned)(i + 1) : sa;
-                    nv = *reinterpret_cast<const K *>(lb + lpad8(idx));
+                    const unsigned inc = tb ? 0u : 1u;
+                    sa += inc;
+                    sb += inc - 1u;
+                    nv = *reinterpret_cast<const K *>(lb + lpad8(tb ? sb : sa));
                 }
             }
         }
@@ -380,11 +378,17 @@ __device__ __forceinline__ void block_merge_rounds_identical(typename KT::T *sk,
         // the pair's output is run (a0 / 2w); odd ones are stored reversed
         // unless this was the last round
         const bool rev = ((base / (2 * w)) & 1) && 2 * w < (unsigned)maxw;
-        const unsigned b8 = lpad8(rev ? a0 + 2 * w - IPT - kd : base);
         if (work) {
+            // two straight-line stores of the 16 keys, from one base each
+            if (rev) {
+                const unsigned b8 = lpad8(a0 + 2 * w - IPT - kd);
 #pragma unroll
-            for (int i = 0; i < IPT; ++i)
-                *reinterpret_cast<K *>(lb + b8 + 8u * (rev ? IPT - 1 - i : i)) = k[i];
+                for (int i = 0; i < IPT; ++i) *reinterpret_cast<K *>(lb + b8 + 8u * (IPT - 1 - i)) = k[i];
+            } else {
+                const unsigned b8 = lpad8(base);
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) *reinterpret_cast<K *>(lb + b8 + 8u * i) = k[i];
+            }
         }
         __syncthreads();
     }
@@ -533,10 +537,14 @@ struct FastKey<KeyF64Desc> {
     using type = KeyF64DescNoNaN;
 };
 
+// float64 class masks of __builtin_amdgcn_class: signalling and quiet NaN,
+// negative and positive zero
+constexpr int kClassNaN = 0x3, kClassNaNOrZero = 0x63;
+
 template <class K>
 __device__ __forceinline__ bool is_nan_key(K x)
 {
-    if constexpr (std::is_same<K, double>::value) return x != x;
+    if constexpr (std::is_same<K, double>::value) return __builtin_amdgcn_class(x, kClassNaN);
     else return false;
 }
 
@@ -545,7 +553,7 @@ __device__ __forceinline__ bool is_nan_key(K x)
 template <class K>
 __device__ __forceinline__ bool tie_bits_may_differ(K x)
 {
-    if constexpr (std::is_same<K, double>::value) return x != x || x == 0.0;
+    if constexpr (std::is_same<K, double>::value) return __builtin_amdgcn_class(x, kClassNaNOrZero);
     else return true;
 }
 

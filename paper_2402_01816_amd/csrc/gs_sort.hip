@@ -109,6 +109,7 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
     using VS = typename std::conditional<HV, V, char>::type;
     constexpr int TILE = NT * IPT;
     constexpr int SLOTS = lds_slots<TILE>();
+    static_assert(NT % 16 == 0, "slot tid + r * NT pads as lpad(tid) + r * lpad(NT)");
     __shared__ K sk[SLOTS];
     __shared__ VS sv[HV ? SLOTS : 1];
     __shared__ unsigned s_ticket, s_order;
@@ -154,26 +155,36 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         const Space<K> keys{Dk + P.doff, Hk + P.hoff, P.n};
         const Space<V> vals{HV ? Dv + P.doff : nullptr, HV ? Hv + P.hoff : nullptr, P.n};
 
-        // load the chunk (input elements all live in the caller's array) with
-        // straight-line loads from clamped indices, all issued before the
-        // first LDS write
+        // load the chunk (input elements all live in the caller's array), all
+        // loads issued before the first LDS write: a whole tile straight, a
+        // short chunk from clamped indices
         bool nan_here = false, ties_identical = false;
         {
             K lk[IPT];
             VS lv[IPT];
+            const K *ks = keys.D + src;
+            if (len == TILE) {
+                // a uniform base plus a 32-bit offset per load
+                const char *kb = reinterpret_cast<const char *>(ks);
 #pragma unroll
-            for (int r = 0; r < IPT; ++r) {
-                const int i = tid + r * NT;
-                const int ic = min(i, len - 1);
-                lk[r] = GS_MERGE_LOAD(keys.D + src + ic);
-                if constexpr (HV) lv[r] = vals.D[src + ic];
+                for (int r = 0; r < IPT; ++r) {
+                    lk[r] = GS_MERGE_LOAD(reinterpret_cast<const K *>(kb + (unsigned)(tid + r * NT) * sizeof(K)));
+                    if constexpr (HV) lv[r] = vals.D[src + tid + r * NT];
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < IPT; ++r) {
+                    const int ic = min(tid + r * NT, len - 1);
+                    lk[r] = GS_MERGE_LOAD(ks + ic);
+                    if constexpr (HV) lv[r] = vals.D[src + ic];
+                }
             }
+            // NaN keys and zeros (the keys whose ties may differ in their
+            // bits) are rare: one class test per key finds whether any is
+            // here, and only then the NaNs are looked for
             bool differ = false;
 #pragma unroll
-            for (int r = 0; r < IPT; ++r) {
-                nan_here |= is_nan_key(lk[r]);
-                differ |= tie_bits_may_differ(lk[r]);
-            }
+            for (int r = 0; r < IPT; ++r) differ |= tie_bits_may_differ(lk[r]);
             // Squidsort: a first look at the chunk's order from the pairs
             // (i, i+1) with i = tid, the neighbour taken from the next lane
             // of the row; s_order bit 0: some pair falls, bit 1: some pair
@@ -186,16 +197,32 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
                 const unsigned bits = (__ballot(falls) ? 1u : 0u) | (__ballot(rises) ? 2u : 0u);
                 if ((tid & 63) == 0 && bits) atomicOr(&s_order, bits);
             }
-            const bool any_nan = __syncthreads_or(nan_here) != 0;
-            ties_identical = !HV && __syncthreads_or(differ) == 0;
-            // slots past the chunk get a padding key that sorts after every
-            // real key (ties with it stay behind the real keys)
-            const K pad = any_nan ? KT::pad() : KF::pad();
+            const bool any_differ = __syncthreads_or(differ) != 0;
+            bool any_nan = false;
+            if (any_differ) {
 #pragma unroll
-            for (int r = 0; r < IPT; ++r) {
-                const int i = tid + r * NT;
-                sk[lpad(i)] = i < len ? lk[r] : pad;
-                if constexpr (HV) sv[lpad(i)] = i < len ? lv[r] : VS();
+                for (int r = 0; r < IPT; ++r) nan_here |= is_nan_key(lk[r]);
+                any_nan = __syncthreads_or(nan_here) != 0;
+            }
+            ties_identical = !HV && !any_differ;
+            // tid + r * NT with NT a multiple of 16: lpad of it is lpad(tid) + r * lpad(NT)
+            const int lt = lpad(tid);
+            if (len == TILE) {
+#pragma unroll
+                for (int r = 0; r < IPT; ++r) {
+                    sk[lt + r * lpad(NT)] = lk[r];
+                    if constexpr (HV) sv[lt + r * lpad(NT)] = lv[r];
+                }
+            } else {
+                // slots past the chunk get a padding key that sorts after
+                // every real key (ties with it stay behind the real keys)
+                const K pad = any_nan ? KT::pad() : KF::pad();
+#pragma unroll
+                for (int r = 0; r < IPT; ++r) {
+                    const int i = tid + r * NT;
+                    sk[lt + r * lpad(NT)] = i < len ? lk[r] : pad;
+                    if constexpr (HV) sv[lt + r * lpad(NT)] = i < len ? lv[r] : VS();
+                }
             }
             nan_here = any_nan;
         }
@@ -239,12 +266,39 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         }
         __syncthreads();
 
+        // the destination lies in one space unless it straddles the end of
+        // the caller's array
+        const bool in_d = dst + len <= P.n, in_h = dst >= P.n;
+        if (in_d || in_h) {
+            K *ko = in_d ? keys.D + dst : keys.H + (dst - P.n);
+            V *vo = nullptr;
+            if constexpr (HV) vo = in_d ? vals.D + dst : vals.H + (dst - P.n);
+            const int lt = lpad(tid);
+            char *kb = reinterpret_cast<char *>(ko);
+            if (len == TILE) {
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            const int i = tid + r * NT;
-            if (i < len) {
-                GS_MERGE_STORE(sk[lpad(i)], keys.at(dst + i));
-                if constexpr (HV) *vals.at(dst + i) = sv[lpad(i)];
+                for (int r = 0; r < IPT; ++r) {
+                    GS_MERGE_STORE(sk[lt + r * lpad(NT)], reinterpret_cast<K *>(kb + (unsigned)(tid + r * NT) * sizeof(K)));
+                    if constexpr (HV) vo[tid + r * NT] = sv[lt + r * lpad(NT)];
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < IPT; ++r) {
+                    const int i = tid + r * NT;
+                    if (i < len) {
+                        GS_MERGE_STORE(sk[lt + r * lpad(NT)], reinterpret_cast<K *>(kb + (unsigned)i * sizeof(K)));
+                        if constexpr (HV) vo[i] = sv[lt + r * lpad(NT)];
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < IPT; ++r) {
+                const int i = tid + r * NT;
+                if (i < len) {
+                    GS_MERGE_STORE(sk[lpad(i)], keys.at(dst + i));
+                    if constexpr (HV) *vals.at(dst + i) = sv[lpad(i)];
+                }
             }
         }
     } while (false);

@@ -24,7 +24,14 @@
  *     ("Sustainability measures") is exactly 1 + ws_bytes / data_bytes.
  *   - Errors are returned, never thrown.  Argument errors are detected before
  *     any device work is enqueued, so the input is untouched on any error.
- *   - `buffer_fraction` p is the cap on extra buffer as a fraction of the data.
+ *   - `buffer_fraction` p caps the element buffer (the half buffer of keys,
+ *     and of values) as a fraction of the data.  The workspace holds a control
+ *     area on top of it (status words, merge-path splits, tile descriptors,
+ *     run directions and run samples, plan tables): for the single-array
+ *     sorts under 0.25% of the data at 2^28 keys (about 18 bytes per 1024
+ *     keys), more for small n, where its fixed part dominates.  %RAM
+ *     (ram_fraction in the report) counts both, so it exceeds 1 + p by that
+ *     overhead.
  *     p >= 0.5 selects Frogsort1 (buffer floor(n/2); never more).  For p in
  *     [1/64, 0.5) the fraction is rounded down to q/65536 (q = floor(65536 p))
  *     and the sort runs Frogsort3 ("Frogsort3 and 6": one buffer of floor(q n/65536)

@@ -138,6 +138,15 @@ struct Forest {
     // 2^d - 1 + i), and the packed mode of every node of the current round
     uint8_t *dirs;
     uint8_t *modes;
+    // Run samples (the single Frogsort1 tree only, else null): for every run
+    // a round produces, one key per stretch of samp_tile ranks at slot
+    // (node * stretches per node + stretch): the stretch's first key for a
+    // left child (the run its parent's merge takes first), its last key for a
+    // right child.  The next round's partition reads them before its merge
+    // overwrites them with its own.  The leaves have samp_leaf_tiles
+    // stretches each.
+    void *samp;
+    int samp_tile, samp_leaf_tiles;
 };
 
 GS_HD int64_t forest_nodes(const Forest &F, const Prob &P, int round)
@@ -221,7 +230,11 @@ struct TileDesc {
     int64_t o;        // logical slot of its first output
     unsigned dlo, dhi;       // dependency window (tickets, inclusive; empty if dlo > dhi)
     int la, cnt;      // view-a inputs, total inputs (= outputs)
-    int prob;         // its problem (row of the table; 0 for the inline problem)
+    // its problem (row of the table) in a table run; for the single tree
+    // with run samples, 2 * (its sample slot) + (1: the node is a right child,
+    // its sample is the stretch's last key; 0: a left child, the first key),
+    // or -1
+    int prob;
     int flags;        // TF_*; TF_SKIP: empty, or every output already sits in its slot
 };
 

@@ -87,6 +87,8 @@ struct ForestPlan {
     int64_t dir_nodes;
     int64_t off_splits;
     int64_t off_desc;     // tile descriptors of the current round
+    int64_t off_samp;     // run samples, samp_slots key pairs (0 slots = none)
+    int64_t samp_slots;
     int64_t off_probs;    // problem table (table runs only)
     int64_t off_tbase, off_sbase;   // per-round prefix rows (table runs only)
     int64_t off_f2, f2_bytes;       // Frogsort2 tree tables (imbalanced plans only)

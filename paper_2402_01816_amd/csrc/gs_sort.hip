@@ -266,6 +266,18 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
         }
         __syncthreads();
 
+        // run samples of the leaf's run: per stretch of samp_tile ranks its
+        // first key (a left child) or its last (a right child)
+        if constexpr (!F2) {
+            if (F.samp && !F.probs) {
+                const int nst = (len + F.samp_tile - 1) / F.samp_tile;
+                if (tid < nst) {
+                    const int f = tid * F.samp_tile, l = min(f + F.samp_tile, len) - 1;
+                    reinterpret_cast<K *>(F.samp)[leaf * F.samp_leaf_tiles + tid] = sk[lpad(leaf & 1 ? l : f)];
+                }
+            }
+        }
+
         // the destination lies in one space unless it straddles the end of
         // the caller's array
         const bool in_d = dst + len <= P.n, in_h = dst >= P.n;
@@ -418,7 +430,8 @@ __device__ __forceinline__ int node_kind(const Space<typename KT::T> &keys, cons
 }
 
 // Merge-path split of the views' stable merge: the number of view-a
-// elements among the first kk outputs.
+// elements among the first kk outputs.  (The searches are bound by the rate
+// of random reads: one probe per step beats several probes per step.)
 template <class KT>
 __device__ __forceinline__ int64_t view_split(const Space<typename KT::T> &keys, const NodeViews &v, int64_t kk)
 {
@@ -432,6 +445,39 @@ __device__ __forceinline__ int64_t view_split(const Space<typename KT::T> &keys,
     return lo;
 }
 
+// The same split for a plain merge of two ascending runs whose run samples
+// the previous round left (sa: the first keys of the first run's stretches of
+// T ranks, sb: the last keys of the second run's) and kk a multiple of T below the node's
+// size.  The merge-path predicate (the first run's element i comes before the
+// output's element kk - 1 - i of the second run) is monotone in i, and at
+// i = c T it compares the first key of the first run's stretch c with the last
+// key of the second run's stretch j - c - 1 (kk = j T): both are samples.  A
+// search over the samples brackets the split within T + 1 positions, and a
+// search over the keys finishes it.
+template <class KT>
+__device__ __forceinline__ int64_t sampled_split(const Space<typename KT::T> &keys, const NodeViews &v, int64_t kk,
+                                                 const typename KT::T *sa, const typename KT::T *sb, int64_t T)
+{
+    const int64_t lo = kk > v.b.n ? kk - v.b.n : 0, hi = kk < v.a.n ? kk : v.a.n;
+    if (lo >= hi) return lo;
+    const int64_t j = kk / T;
+    const int64_t clo = (lo + T - 1) / T, chi = (hi + T - 1) / T;   // c T in [lo, hi)
+    int64_t a = clo, b = chi;
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if (KT::less(sb[j - mid - 1], sa[mid])) b = mid;
+        else a = mid + 1;
+    }
+    int64_t flo = a > clo ? (a - 1) * T + 1 : lo;
+    int64_t fhi = a < chi ? a * T : hi;
+    while (flo < fhi) {
+        const int64_t mid = (flo + fhi) >> 1;
+        if (KT::less(*keys.at(view_slot(v.b, kk - 1 - mid)), *keys.at(view_slot(v.a, mid)))) fhi = mid;
+        else flo = mid + 1;
+    }
+    return flo;
+}
+
 // One thread per (node, boundary j): the number of view-a elements among the
 // first j*TILE outputs of the node's merge (no search for a concatenation).
 // For the single Frogsort1 tree the node's mode is decided here from its
@@ -439,8 +485,7 @@ __device__ __forceinline__ int64_t view_split(const Space<typename KT::T> &keys,
 // with j = 0 records the mode and the node's direction, and flags the round
 // if the node's outer run has to be turned around before the merge).  The
 // splits read a descending run from its end, the sequence it holds once
-// turned.  (The searches are bound by the rate of random reads, so one probe
-// per step is the cheapest form.)
+// turned.
 template <class KT, int TILE>
 __global__ __launch_bounds__(256) void partition_kernel(typename KT::T *Dk, typename KT::T *Hk, Forest F,
                                                         int round, int64_t *splits, unsigned *turn_flag, Gate gate)
@@ -493,7 +538,20 @@ __global__ __launch_bounds__(256) void partition_kernel(typename KT::T *Dk, type
         const int64_t nn = m.nl + m.nr;
         int64_t kk = j * TILE;
         if (kk > nn) kk = nn;
-        splits[w] = v.copy ? (kk < v.a.n ? kk : v.a.n) : view_split<KT>(keys, v, kk);
+        // two ascending children of the single tree: their run samples
+        // (written by the previous round, node 2 node and 2 node + 1 at the
+        // depth below) bracket the split
+        const bool sampled = F.samp && !F.probs && !F.use_f2 && kind == NODE_MERGE && dL == DIR_ASC &&
+                             dR == DIR_ASC && kk < nn && F.samp_tile == TILE;
+        if (v.copy) {
+            splits[w] = kk < v.a.n ? kk : v.a.n;
+        } else if (sampled) {
+            const int64_t ct = round == 1 ? F.samp_leaf_tiles : forest_tpn<TILE>(F, P, round - 1);
+            const K *sb0 = reinterpret_cast<const K *>(F.samp);
+            splits[w] = sampled_split<KT>(keys, v, kk, sb0 + (2 * node) * ct, sb0 + (2 * node + 1) * ct, TILE);
+        } else {
+            splits[w] = view_split<KT>(keys, v, kk);
+        }
     }
 }
 
@@ -598,11 +656,12 @@ __global__ __launch_bounds__(256) void tiles_kernel(K *Dk, K *Hk, V *Dv, V *Hv, 
         const int64_t nn = m.nl + m.nr;
         const int64_t j = m.left ? (tpn - 1 - q) : q;
         int64_t k0 = j * TILE;
+        const int samp = F.samp && !F.probs && !F.use_f2 ? (int)(2 * (node * tpn + j) + (node & 1)) : -1;
         if (k0 > nn) k0 = nn;
         int64_t k1 = k0 + TILE;
         if (k1 > nn) k1 = nn;
         TileDesc T;
-        T.prob = (int)s;
+        T.prob = F.probs ? (int)s : samp;
         T.cnt = (int)(k1 - k0);
         T.la = 0;
         T.pa = T.pb = T.o = 0;
@@ -832,6 +891,17 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
             nxt_p = prob_of(nxt.prob);
             if (!(nxt.flags & TF_SKIP)) issue_loads(nxt, nxt_p);
         }
+        // the run sample of this tile's outputs (first or last key), for the
+        // next round's partition: from the register of the thread that merged
+        // it (a whole tile), from LDS (a short tile or a concatenation), or
+        // from memory (outputs already in their slots)
+        K *const samp_p = F.samp && cur.prob >= 0 && out_cnt > 0 ? reinterpret_cast<K *>(F.samp) + (cur.prob >> 1)
+                                                                 : nullptr;
+        const int samp_i = cur.prob & 1 ? out_cnt - 1 : 0;
+        if (skip && samp_p && tid == 0) {
+            const Space<K> ks{Dk + cur_p.doff, Hk + cur_p.hoff, cur_p.n};
+            *samp_p = *ks.at(out_o + samp_i);
+        }
         if (!skip) {
             my_moved += (unsigned)cur.cnt;
             lds_barrier();             // the merge's reads are done and the window has been waited for
@@ -845,6 +915,14 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
                 }
             }
             lds_barrier();
+            if (samp_p) {
+                const bool in_regs = !copy && (samp_i == 0 || out_cnt == TILE);
+                if (in_regs) {
+                    if (samp_i == 0 ? tid == 0 : tid == NT - 1) *samp_p = samp_i == 0 ? k[0] : k[IPT - 1];
+                } else if (tid == 0) {
+                    *samp_p = sk[lpad(samp_i)];
+                }
+            }
 #pragma unroll
             for (int r = 0; r < IPT; ++r) {
                 const int i = tid + r * NT;
@@ -949,7 +1027,8 @@ static int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 // Control block, status words, splits, tile descriptors and (for a problem
 // table) the per-round prefix rows, laid out from offset 0.
 static ForestPlan layout_forest(int64_t max_probs, int rounds, int64_t max_tickets, int64_t max_status,
-                                int64_t max_splits, int64_t leaf, int64_t tile, int64_t dir_nodes = 0)
+                                int64_t max_splits, int64_t leaf, int64_t tile, int64_t dir_nodes = 0,
+                                int64_t samp_slots = 0)
 {
     ForestPlan f{};
     f.max_probs = max_probs;
@@ -967,7 +1046,9 @@ static ForestPlan layout_forest(int64_t max_probs, int rounds, int64_t max_ticke
     f.off_modes = f.off_dirs + align256(dir_nodes);
     f.off_splits = f.off_modes + align256(dir_nodes / 2);
     f.off_desc = f.off_splits + align256(max_splits * 8);
-    f.off_probs = f.off_desc + align256(max_tickets * (int64_t)sizeof(TileDesc));
+    f.samp_slots = samp_slots;
+    f.off_samp = f.off_desc + align256(max_tickets * (int64_t)sizeof(TileDesc));
+    f.off_probs = f.off_samp + align256(samp_slots * 8);
     f.off_tbase = f.off_probs + (max_probs > 0 ? align256(max_probs * (int64_t)sizeof(Prob)) : 0);
     f.off_sbase = f.off_tbase + (max_probs > 0 ? align256((rounds + 1) * f.stride * 4) : 0);
     f.bytes = f.off_sbase + (max_probs > 0 ? align256((rounds + 1) * f.stride * 4) : 0);
@@ -990,8 +1071,11 @@ ForestPlan forest_plan_one(int64_t n)
         if (t > mt) mt = t;
         if (s > ms) ms = s;
     }
-    // Squidsort directions of every node (heap order, 2^(D+1) - 1 of them)
-    return layout_forest(0, D, mt, mt > leaves ? mt : leaves, ms, LEAF, TILE, (int64_t)2 << D);
+    // Squidsort directions of every node (heap order, 2^(D+1) - 1 of them);
+    // run samples of the leaves and of every merge round
+    const int64_t leaf_slots = leaves * ((LEAF + TILE - 1) / TILE);
+    return layout_forest(0, D, mt, mt > leaves ? mt : leaves, ms, LEAF, TILE, (int64_t)2 << D,
+                         mt > leaf_slots ? mt : leaf_slots);
 }
 
 // Capacity for any set of at most max_probs problems of at most max_len keys
@@ -1093,6 +1177,11 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
     if (squid) {
         F.dirs = (uint8_t *)(fw + fp.off_dirs);
         F.modes = (uint8_t *)(fw + fp.off_modes);
+        if (fp.samp_slots > 0 && fp.tile == TILE) {
+            F.samp = fw + fp.off_samp;
+            F.samp_tile = TILE;
+            F.samp_leaf_tiles = (int)((fp.leaf + TILE - 1) / TILE);
+        }
     }
     if (table) {
         F.tbase = (const unsigned *)(fw + fp.off_tbase);

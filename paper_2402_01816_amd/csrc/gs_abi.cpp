@@ -857,10 +857,8 @@ gs_status gs_mlp_train(float *params, float *adam_m, float *adam_v, const float 
     gs_status s = check_device();
     if (s != GS_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
-    unsigned *ctl = (unsigned *)((char *)work + (size_t)(batch / 32) * (gs::kMlpParams + 1) * 4);
-    gs::launch_fill_u32(ctl, 64, 0u, st);
     hipError_t e = gs::mlp_train(params, adam_m, adam_v, u, t, count, steps, batch, lr, seed, full_batch,
-                                 (float *)work, losses, ctl, ctl + 1, nullptr, st);
+                                 (float *)work, losses, nullptr, st);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_mlp_train");
 }
 

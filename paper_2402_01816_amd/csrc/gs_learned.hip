@@ -53,8 +53,7 @@ constexpr int L_FALLBACK = 0;            // 1: take the plain path
 constexpr int L_ORDER = 1;               // table not monotone
 constexpr int L_OVERFLOW = 2;            // buckets above the limit
 constexpr int L_MAXB = 3;                // largest bucket
-constexpr int L_BAR = 4;                 // training grid barrier
-constexpr int L_ERR = 5;
+constexpr int L_ERR = 5;                 // training's error word (it has no waits: stays 0)
 constexpr int L_BIGB = 6;                // buckets larger than one LDS tile
 constexpr int L_FEAT = 7;                // chosen feature
 constexpr int L_SCREENED = 8;              // the sample predicted too uneven buckets
@@ -875,7 +874,7 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
             if (e != hipSuccess) return e;
             if (prm.train_steps > 0) {
                 e = mlp_train(params, m, v, u, t, L.S, (int)prm.train_steps, L.batch, prm.lr, prm.seed, 0, partial,
-                              losses, ctrl + L_BAR, ctrl + L_ERR, ctrl + L_FALLBACK, st);
+                              losses, ctrl + L_FALLBACK, st);
                 if (e != hipSuccess) return e;
             }
         }

@@ -6,13 +6,12 @@
 //   hidden-2 unit i) b2[64] w3[64] b3
 //   y(u) = w3 . relu(W2 relu(W1 u + b1) + b2) + b3,   loss = mean (y - t)^2
 //
-// Training is data parallel over work-groups of one cooperative launch: every
-// work-group takes 32 samples per step, computes its partial gradient in LDS
-// with every sum in a fixed order, writes it out; after a grid barrier every
-// work-group sums a slice of the parameters over all partials in work-group
-// order and applies Adam (Kingma & Ba) to it; a second barrier publishes the
-// new parameters.  No floating-point atomics anywhere, so a run is bit
-// reproducible.
+// Training is data parallel over work-groups, two launches per step: every
+// work-group takes 32 samples, computes its partial gradient in LDS with every
+// sum in a fixed order and writes it out; then every work-group of the second
+// launch sums a slice of the parameters over all partials in work-group order
+// and applies Adam (Kingma & Ba) to it.  No floating-point atomics anywhere,
+// so a run is bit reproducible.
 #include <hip/hip_runtime.h>
 
 #include "gs_device.h"
@@ -197,28 +196,6 @@ __device__ void wg_loss_grad(TrainLds &L, float inv_batch)
     __syncthreads();
 }
 
-// Grid barrier for a cooperative launch: agent-scope fences on both sides so
-// the partial gradients and parameters written before it are visible after
-// it on every XCD.  Bounded: a barrier that does not complete sets *err.
-__device__ void grid_barrier(unsigned *bar, unsigned nwg, unsigned &gen, unsigned *err)
-{
-    __threadfence();                    // every thread releases its own writes
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        ++gen;
-        atomicAdd(bar, 1u);
-        const unsigned target = gen * nwg;
-        unsigned spins = 0;
-        while (ld_status(bar) < target && spins < kSpinLimit) {
-            __builtin_amdgcn_s_sleep(2);
-            ++spins;
-        }
-        if (spins >= kSpinLimit) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    __threadfence();                    // and acquires everyone else's
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -252,89 +229,84 @@ __global__ void mlp_init_kernel(float *params, uint64_t seed)
 }
 
 // ---------------------------------------------------------------------------
-// cooperative training kernel
+// training: two ordinary launches per step
 // ---------------------------------------------------------------------------
-// Grid: nwg work-groups of TR_NT threads; batch = nwg * 32.  If full_batch,
-// step samples are the first `batch` samples in order, else 32 per group are
-// drawn (with replacement) by a counter-based hash of (seed, step, slot).
-__global__ __launch_bounds__(TR_NT) void mlp_train_kernel(float *params, float *adam_m, float *adam_v,
-                                                          const float *su, const float *st, int64_t S,
-                                                          int steps, float lr, uint64_t seed,
-                                                          int full_batch, float *partial,
-                                                          float *losses, unsigned *bar, unsigned *err,
-                                                          const unsigned *gate)
+// Step part 1, nwg work-groups of TR_NT threads (batch = nwg * 32): every
+// work-group's partial gradient and loss of its 32 samples.  If full_batch,
+// the samples are the first `batch` in order, else 32 per group are drawn
+// (with replacement) by a counter-based hash of (seed, step, slot).
+__global__ __launch_bounds__(TR_NT) void mlp_step_grad_kernel(const float *params, const float *su,
+                                                              const float *st, int64_t S, int step,
+                                                              uint64_t seed, int full_batch, float *partial,
+                                                              const unsigned *gate)
 {
     __shared__ TrainLds L;
     if (gate && *gate) return;
-    const unsigned nwg = gridDim.x;
-    const int wg = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int batch = (int)nwg * SPW;
-    const float inv_batch = 1.f / (float)batch;
-    const int per = (kMlpParams + (int)nwg - 1) / (int)nwg;
-    const int p0 = wg * per, p1 = min(p0 + per, kMlpParams);
-    unsigned gen = 0;
+    const int wg = blockIdx.x, tid = threadIdx.x;
+    const int batch = (int)gridDim.x * SPW;
+    for (int k = tid; k < kMlpParams; k += TR_NT) L.p[k] = params[k];
+    if (tid < SPW) {
+        const int slot = wg * SPW + tid;
+        int64_t idx;
+        if (full_batch) idx = slot < S ? slot : S - 1;
+        else idx = (int64_t)(mix64(seed ^ ((uint64_t)(step + 1) << 32) ^ (uint64_t)slot) % (uint64_t)S);
+        L.u[tid] = su[idx];
+        L.t[tid] = st[idx];
+    }
+    __syncthreads();
+    wg_loss_grad(L, 1.f / (float)batch);
+    float *pw = partial + (size_t)wg * (kMlpParams + 1);
+    for (int k = tid; k < kMlpParams; k += TR_NT) pw[k] = L.g[k];
+    if (tid == 0) pw[kMlpParams] = L.loss;
+}
+
+// Step part 2: every work-group sums a 64-parameter slice of the gradient
+// over the nwg partials -- lane k of quarter q sums the partials of groups
+// [q*nq, (q+1)*nq) in group order, then the four quarter sums are added in
+// quarter order (a fixed order, so a run is bit reproducible) -- and applies
+// Adam (Kingma & Ba) to it.  Work-group 0 also records the mean loss of the
+// first and the last step.
+__global__ __launch_bounds__(TR_NT) void mlp_step_adam_kernel(float *params, float *adam_m, float *adam_v,
+                                                              const float *partial, int nwg, int step, int steps,
+                                                              float lr, float *losses, const unsigned *gate)
+{
+    __shared__ float red[TR_NT / 64][64];
+    if (gate && *gate) return;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-
-    for (int step = 0; step < steps; ++step) {
-        for (int k = tid; k < kMlpParams; k += TR_NT) L.p[k] = params[k];
-        if (tid < SPW) {
-            const int slot = wg * SPW + tid;
-            int64_t idx;
-            if (full_batch) idx = slot < S ? slot : S - 1;
-            else idx = (int64_t)(mix64(seed ^ ((uint64_t)(step + 1) << 32) ^ (uint64_t)slot) % (uint64_t)S);
-            L.u[tid] = su[idx];
-            L.t[tid] = st[idx];
-        }
-        __syncthreads();
-        wg_loss_grad(L, inv_batch);
-        float *pw = partial + (size_t)wg * (kMlpParams + 1);
-        for (int k = tid; k < kMlpParams; k += TR_NT) pw[k] = L.g[k];
-        if (tid == 0) pw[kMlpParams] = L.loss;
-        grid_barrier(bar, nwg, gen, err);
-
-        // reduce this group's parameter slice over all groups: lane k of
-        // quarter q sums the partials of groups [q*nq, (q+1)*nq) in group
-        // order, then the four quarter sums are added in quarter order (a
-        // fixed order either way, so the result is reproducible)
-        const float c1 = 1.f - powf(b1, (float)(step + 1));
-        const float c2 = 1.f - powf(b2, (float)(step + 1));
-        const int q = tid >> 6, kl = tid & 63;
-        const int nq = ((int)nwg + 3) / 4;
-        const int w0 = q * nq, w1 = min(w0 + nq, (int)nwg);
-        for (int kb = p0; kb < p1; kb += 64) {
-            const int k = kb + kl;
-            float g = 0.f;
-            if (k < p1) {
-                int w = w0;
-                for (; w + 8 <= w1; w += 8) {
-                    float v8[8];
+    const float c1 = 1.f - powf(b1, (float)(step + 1));
+    const float c2 = 1.f - powf(b2, (float)(step + 1));
+    const int tid = threadIdx.x, q = tid >> 6, kl = tid & 63;
+    const int nq = (nwg + 3) / 4;
+    const int w0 = q * nq, w1 = min(w0 + nq, nwg);
+    const int k = blockIdx.x * 64 + kl;
+    float g = 0.f;
+    if (k < kMlpParams) {
+        int w = w0;
+        for (; w + 8 <= w1; w += 8) {
+            float v8[8];
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) v8[r] = partial[(size_t)(w + r) * (kMlpParams + 1) + k];
+            for (int r = 0; r < 8; ++r) v8[r] = partial[(size_t)(w + r) * (kMlpParams + 1) + k];
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) g += v8[r];
-                }
-                for (; w < w1; ++w) g += partial[(size_t)w * (kMlpParams + 1) + k];
-            }
-            L.red[q][kl] = g;
-            __syncthreads();
-            if (q == 0 && k < p1) {
-                const float gs = ((L.red[0][kl] + L.red[1][kl]) + L.red[2][kl]) + L.red[3][kl];
-                const float m = b1 * adam_m[k] + (1.f - b1) * gs;
-                const float v = b2 * adam_v[k] + (1.f - b2) * gs * gs;
-                adam_m[k] = m;
-                adam_v[k] = v;
-                params[k] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
-            }
-            __syncthreads();
+            for (int r = 0; r < 8; ++r) g += v8[r];
         }
-        if (wg == 0 && tid == 0 && losses && (step == 0 || step == steps - 1)) {
-            float l = 0.f;
-            for (unsigned w = 0; w < nwg; ++w) l += partial[(size_t)w * (kMlpParams + 1) + kMlpParams];
-            losses[step == 0 ? 0 : 1] = l * inv_batch;
-            if (steps == 1) losses[1] = losses[0];
-        }
-        grid_barrier(bar, nwg, gen, err);
+        for (; w < w1; ++w) g += partial[(size_t)w * (kMlpParams + 1) + k];
+    }
+    red[q][kl] = g;
+    __syncthreads();
+    if (q == 0 && k < kMlpParams) {
+        const float gs = ((red[0][kl] + red[1][kl]) + red[2][kl]) + red[3][kl];
+        const float m = b1 * adam_m[k] + (1.f - b1) * gs;
+        const float v = b2 * adam_v[k] + (1.f - b2) * gs * gs;
+        adam_m[k] = m;
+        adam_v[k] = v;
+        params[k] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+    }
+    if (blockIdx.x == 0 && tid == 0 && losses && (step == 0 || step == steps - 1)) {
+        float l = 0.f;
+        for (int w = 0; w < nwg; ++w) l += partial[(size_t)w * (kMlpParams + 1) + kMlpParams];
+        l /= (float)(nwg * SPW);
+        losses[step == 0 ? 0 : 1] = l;
+        if (steps == 1) losses[1] = l;
     }
 }
 
@@ -414,12 +386,16 @@ hipError_t mlp_init(float *params, uint64_t seed, hipStream_t st)
 
 hipError_t mlp_train(float *params, float *m, float *v, const float *su, const float *stgt, int64_t S,
                      int steps, int batch, float lr, uint64_t seed, int full_batch, float *partial,
-                     float *losses, unsigned *bar, unsigned *err, const unsigned *gate, hipStream_t st)
+                     float *losses, const unsigned *gate, hipStream_t st)
 {
     const int nwg = batch / SPW;
-    void *args[] = {&params, &m, &v, (void *)&su, (void *)&stgt, &S, &steps, &lr, &seed,
-                    &full_batch, &partial, &losses, &bar, &err, (void *)&gate};
-    return hipLaunchCooperativeKernel((const void *)mlp_train_kernel, dim3(nwg), dim3(TR_NT), args, 0, st);
+    for (int step = 0; step < steps; ++step) {
+        hipLaunchKernelGGL(mlp_step_grad_kernel, dim3(nwg), dim3(TR_NT), 0, st, (const float *)params, su, stgt, S,
+                           step, seed, full_batch, partial, gate);
+        hipLaunchKernelGGL(mlp_step_adam_kernel, dim3((kMlpParams + 63) / 64), dim3(TR_NT), 0, st, params, m, v,
+                           (const float *)partial, nwg, step, steps, lr, losses, gate);
+    }
+    return hipGetLastError();
 }
 
 hipError_t mlp_loss_grad(const float *params, const float *u, const float *t, int batch, float *partial,

@@ -51,20 +51,52 @@ def log(msg):
     sys.stderr.flush()
 
 
-def cpu_baseline(n_sample: int, pattern: str):
-    """The CPU oracle (single thread) on a bounded contiguous sample."""
-    import numpy as np
+def _host():
+    """The host the CPU baselines ran on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = None
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
+
+def cpu_baseline(n_sample: int, pattern: str, full_n: int = 0):
+    """The CPU oracle (single thread) on a bounded contiguous sample, with the
+    C++ standard library's stable sort (single thread) on the same sample
+    beside it; with full_n, both once more on the whole input."""
     import oracle
     import workloads as W
+
+    def timed(fn, x):
+        t0 = time.perf_counter()
+        fn(x)
+        return time.perf_counter() - t0
+
     x = W.f64_pattern(pattern, n_sample, seed=0)
-    t0 = time.perf_counter()
-    oracle.sort_f64(x)
-    dt = time.perf_counter() - t0
-    return {"value": n_sample / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_sample} keys ({pattern}, seed 0), one single-threaded call of the "
-                      f"oracle's stable mergesort, {dt:.2f} s",
-            "seconds": dt}
+    dt = timed(oracle.sort_f64, x)
+    ds = timed(oracle.std_stable_sort_f64, x)
+    del x
+    out = {"value": n_sample / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n_sample} keys ({pattern}, seed 0), one single-threaded call of the "
+                     f"oracle's stable mergesort, {dt:.2f} s",
+           "seconds": dt, "host": _host(),
+           "std_stable_sort": {"value": n_sample / ds / 1e9, "unit": "Gkeys/s", "cores": 1,
+                               "seconds": ds, "sample": "the same keys, one std::stable_sort call"}}
+    if full_n:
+        x = W.f64_pattern(pattern, full_n, seed=0)
+        df = timed(oracle.sort_f64, x)
+        dsf = timed(oracle.std_stable_sort_f64, x)
+        out["full_input"] = {"n": full_n, "oracle_s": df, "oracle_gkeys_per_s": full_n / df / 1e9,
+                             "std_stable_sort_s": dsf, "std_stable_sort_gkeys_per_s": full_n / dsf / 1e9}
+    return out
 
 
 def _time_calls(torch, stream, fn, reps):
@@ -246,8 +278,8 @@ def _extras_segmented(gs, torch, W, n, dev, stream, workloads, per_array):
         if not per_array:
             del x, buf, o, ws
             continue
-        # per-array plain launches on the first arrays, scaled to all
-        k = min(nseg, 2000)
+        # one plain call per array, every array
+        k = nseg
         sub = [buf[int(off[i]):int(off[i + 1])] for i in range(k)]
         wsmax = max(gs.gs_workspace_bytes_f64(t.numel()) for t in sub)
         ws1 = torch.empty(wsmax + 256, dtype=torch.uint8, device=dev)
@@ -260,9 +292,9 @@ def _extras_segmented(gs, torch, W, n, dev, stream, workloads, per_array):
                 for a in sub:
                     if a.numel() > 1:
                         gs.gs_sort_f64(a, workspace=ws1[: gs.gs_workspace_bytes_f64(a.numel())])
-        ms_each = _time_calls(torch, stream, fn_each, 1) * (nseg / k)
-        row["per_array_launches_ms_est"] = round(ms_each, 1)
-        row["per_array_note"] = f"{k} separate gs_sort_f64 calls timed, scaled to {nseg}"
+        ms_each = _time_calls(torch, stream, fn_each, 1)
+        row["per_array_launches_ms"] = round(ms_each, 1)
+        row["per_array_note"] = f"{k} separate gs_sort_f64 calls, one per array, timed together"
         del x, buf, o, sub, ws, ws1
     return segres
 
@@ -344,7 +376,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--pattern", default="uniform")
-    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time both CPU references on the whole input (about a minute)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the learned / segmented / key-value side measurements")
@@ -518,7 +552,8 @@ def main():
         out["extras"] = run_extras(args, gs, torch, W, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2, args.pattern)
+        out["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2, args.pattern,
+                                           n if args.cpu_full else 0)
     print(json.dumps(out))
 
 

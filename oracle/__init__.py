@@ -3,7 +3,9 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The GPU library never calls it, and the
 two share no code.  The C source is ``oracle.c``; this module compiles it with
-gcc into ``liboracle.so`` next to it and wraps it with ctypes.
+gcc into ``liboracle.so`` next to it and wraps it with ctypes.  ``stdsort.cpp``
+(g++, ``libstdsort.so``) holds a second reference: the C++ standard library's
+stable sort under the same key order.
 
 Every function computes what the paper's definition of sorting fixes (stable,
 ascending, ties in input order) by the plainest available route; see the header
@@ -20,21 +22,61 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_STD_SRC = os.path.join(_HERE, "stdsort.cpp")
+_STD_LIB = os.path.join(_HERE, "libstdsort.so")
 _lib = None
+_stdlib = None
 
 MLP_HIDDEN = 64
 MLP_NUM_PARAMS = 4353
 
 
 def build(force: bool = True) -> str:
-    """Compile ``oracle.c`` with gcc (fp64, no fast-math)."""
+    """Compile ``oracle.c`` with gcc (fp64, no fast-math) and ``stdsort.cpp``
+    with g++."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11",
              "-shared", "-fPIC", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_STD_LIB):
+        tmp = _STD_LIB + ".tmp"
+        subprocess.check_call(
+            ["g++", "-O2", "-fno-fast-math", "-std=c++17", "-shared", "-fPIC", "-Wall", "-Wextra",
+             "-o", tmp, _STD_SRC])
+        os.replace(tmp, _STD_LIB)
     return _LIB
+
+
+def _load_std():
+    global _stdlib
+    if _stdlib is not None:
+        return _stdlib
+    if not os.path.exists(_STD_LIB) or os.path.getmtime(_STD_LIB) < os.path.getmtime(_STD_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_STD_LIB)
+    lib.stdsort_stable_f64.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    lib.stdsort_stable_f64.restype = None
+    lib.stdsort_stable_kv.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    lib.stdsort_stable_kv.restype = None
+    _stdlib = lib
+    return lib
+
+
+def std_stable_sort_f64(x: np.ndarray) -> np.ndarray:
+    """std::stable_sort of a copy of x under the oracle's key order."""
+    y = np.ascontiguousarray(x, dtype=np.float64).copy()
+    _load_std().stdsort_stable_f64(y.ctypes.data, y.size)
+    return y
+
+
+def std_stable_sort_kv(k: np.ndarray, v: np.ndarray):
+    """std::stable_sort of copies of (k, v) by unsigned key."""
+    kk = np.ascontiguousarray(k, dtype=np.uint64).copy()
+    vv = np.ascontiguousarray(v, dtype=np.uint32).copy()
+    _load_std().stdsort_stable_kv(kk.ctypes.data, vv.ctypes.data, kk.size)
+    return kk, vv
 
 
 def _load():

@@ -120,6 +120,30 @@ def test_matches_library_stable_sort(orc, pattern, n):
     assert np.array_equal(y.view(np.uint64), ref.view(np.uint64))
 
 
+@pytest.mark.parametrize("pattern", ["uniform", "tied", "presorted", "reversed",
+                                     "perturbed", "zeros_signed"])
+@pytest.mark.parametrize("n", [0, 1, 2, 1000, 4097, 1 << 16])
+def test_matches_std_stable_sort(orc, pattern, n):
+    """The C++ standard library's stable sort under the same key order gives
+    the same bits (NaN payloads and signed zeros included)."""
+    x = W.f64_pattern(pattern, n, seed=4)
+    if n > 8:
+        rng = np.random.default_rng(n)
+        x[rng.integers(0, n, 5)] = np.nan
+        x[rng.integers(0, n, 5)] = np.frombuffer(np.uint64(0x7FF8000000000077).tobytes(), dtype=np.float64)[0]
+    y = orc.sort_f64(x)
+    ref = orc.std_stable_sort_f64(x)
+    assert np.array_equal(y.view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("pattern", ["uniform", "zipf", "few"])
+def test_kv_matches_std_stable_sort(orc, pattern):
+    k0, v0 = W.kv_pattern(pattern, 50_000, seed=2)
+    k, v = orc.sort_kv(k0, v0)
+    rk, rv = orc.std_stable_sort_kv(k0, v0)
+    assert np.array_equal(k, rk) and np.array_equal(v, rv)
+
+
 def test_nan_inf_denormal_order(orc):
     x = np.array([np.nan, 1.0, -np.inf, 5e-324, -0.0, np.inf, 0.0, -5e-324,
                   np.float64(np.nan), -0.0, 1.0], dtype=np.float64)

@@ -56,8 +56,12 @@ void launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st)
 // which is never before its input offset.  A leaf's output can therefore only
 // cover input chunks of leaves with a larger index: leaves take tickets in
 // descending index order, and each waits for the leaves whose chunks its
-// output covers.  Every work-group takes one ticket; with a problem table the
-// grid is the capacity and work-groups past the device's leaf count exit.
+// output covers.  One leaf per work-group, or with PERSIST (a problem table,
+// whose leaf count is on the device) work-groups take tickets until none is
+// left (a leaf waits only on smaller tickets, held by work-groups already
+// running), so the grid need not exceed the resident work-groups.  (The
+// loop's register pressure costs the one-leaf form spills, so it stays a
+// separate instance.)
 // The value held by the next lane of the 16-lane row (DPP row shift; the
 // last lane of a row gets its own value back).
 template <class K>
@@ -98,7 +102,7 @@ __device__ __forceinline__ int chunk_order(const typename KT::T *sk, int len)
     return !not_up ? 1 : !not_down ? 2 : 0;
 }
 
-template <class KT, class V, int NT, int IPT, int WAVES, bool F2>
+template <class KT, class V, int NT, int IPT, int WAVES, bool F2, bool PERSIST>
 __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *Hv,
                                                   Forest F, unsigned *ticket_ctr, unsigned *status,
                                                   unsigned epoch, unsigned *err, uint64_t *moved, Gate gate)
@@ -115,10 +119,14 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
     __shared__ unsigned s_ticket, s_order;
     if (gate.closed()) return;
 
-    const int tid = threadIdx.x;
     const int64_t L = F.probs ? (int64_t)*F.nprob : 1;
     const int64_t total = F2 ? F.f2.nleaves : F.probs ? (int64_t)F.tbase[L] : ((int64_t)1 << F.p0.depth);
-    do {
+    for (;;) {
+        // (with PERSIST the thread index is made opaque on every pass, so that
+        // values derived from it are not hoisted out of the loop, where they
+        // would stay live through the whole sort and spill)
+        int tid = threadIdx.x;
+        if constexpr (PERSIST) asm volatile("" : "+v"(tid));
         if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
         __syncthreads();
         const int64_t t = __builtin_amdgcn_readfirstlane(s_ticket);
@@ -313,7 +321,8 @@ __global__ __launch_bounds__(NT, WAVES) void leaf_kernel(typename KT::T *Dk, typ
                 }
             }
         }
-    } while (false);
+        if constexpr (!PERSIST) break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1232,18 +1241,20 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         if (tr) trace_end(st);
     }
 
-    auto leaf_fn = f2 ? leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, true>
-                      : leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, false>;
+    auto leaf_fn = f2 ? leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, true, false>
+                      : leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, false, false>;
+    auto leaf_table_fn = leaf_kernel<KT, V, C::LEAF_NT, C::LEAF_IPT, C::LEAF_WAVES, false, true>;
     auto merge_fn = merge_kernel<KT, V, C::MERGE_NT, C::MERGE_IPT, C::MERGE_WAVES>;
-    static int64_t merge_groups = 0;
+    static int64_t merge_groups = 0, leaf_groups = 0;
     unsigned epoch = 1;
     if (leaves) {
         if (tr) trace_begin(TK_LEAF, st);
         if (table) {
-            // one leaf per work-group; work-groups past the device's leaf
-            // count exit at once
-            hipLaunchKernelGGL(leaf_fn, dim3((unsigned)fp.max_status), dim3(C::LEAF_NT), 0, st, Dk, Hk, Dv, Hv, F,
-                               ctrl + 0, status, epoch, errw, moved, gate);
+            // the leaf count is on the device: the resident work-groups take
+            // its leaves in turn
+            const int64_t lres = resident_groups(leaf_table_fn, C::LEAF_NT, leaf_groups);
+            hipLaunchKernelGGL(leaf_table_fn, dim3((unsigned)(fp.max_status < lres ? fp.max_status : lres)),
+                               dim3(C::LEAF_NT), 0, st, Dk, Hk, Dv, Hv, F, ctrl + 0, status, epoch, errw, moved, gate);
         } else {
             const int64_t nl = f2 ? f2->nleaves : ((int64_t)1 << F.p0.depth);
             hipLaunchKernelGGL(leaf_fn, dim3((unsigned)nl), dim3(C::LEAF_NT), 0, st, Dk, Hk, Dv, Hv, F, ctrl + 0,

@@ -198,8 +198,8 @@ __device__ __forceinline__ void lane_merge_rounds(double (&k)[IPT], int rounds)
 
 // The register phase of the block sort for float64 blocks whose equal keys are
 // bit for bit identical, 16 keys per thread: Batcher's network on each
-// thread's keys, then up to three bitonic merge levels across 2, 4 and 8
-// lanes, so that runs of w = min(maxw, 128) keys end up sorted -- in the
+// thread's keys, then up to four bitonic merge levels across 2, 4, 8 and 16
+// lanes, so that runs of w = min(maxw, 256) keys end up sorted -- in the
 // order DIR where w == maxw, else alternately in order and reversed (run r
 // reversed when r is odd), the layout the LDS rounds take.
 //
@@ -213,16 +213,19 @@ __device__ __forceinline__ void lane_merge_rounds(double (&k)[IPT], int rounds)
 // their keys (a multiply by -1, exact for the finite and infinite keys these
 // blocks hold).  The merge levels: 2 lanes (half-cleaner on lane bit 0, then
 // in-register half-cleaners), 4 lanes (half-cleaners on lane bits 1 and 0; its
-// runs all ascend, which the next level needs) and 8 lanes (a flip that pairs
+// runs all ascend, which the next level needs), 8 lanes (a flip that pairs
 // lane t with 7 - t and register r with 15 - r, then half-cleaners on lane
-// bits 1 and 0).  Position bit 4 + j is lane bit j.  Every lane of the wave
+// bits 1 and 0) and 16 lanes (half-cleaners on lane bits 3 to 0; lane t ^ 8
+// is a rotation of the 16-lane row by 8, lane t ^ 4 the quad reversal of the
+// 8-lane mirror).  Position bit 4 + j is lane bit j.  Every lane of the wave
 // must execute this (DPP reads neighbours).
 template <int DIR, int IPT>
 __device__ __forceinline__ void register_sort_identical(double (&k)[IPT], int maxw)
 {
     static_assert(IPT == 16, "lane bit j is position bit 4 + j");
     const unsigned lane = threadIdx.x & 63;
-    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1,
+               b4 = (lane >> 4) & 1;
     const bool neg = DIR < 0;
     bool cur = false;
     auto set_mode = [&](bool m) {
@@ -245,9 +248,20 @@ __device__ __forceinline__ void register_sort_identical(double (&k)[IPT], int ma
 #pragma unroll
         for (int r = 0; r < IPT; ++r) k[r] = __builtin_fmin(k[r], -o[r]);
     };
+    // keep min(own, -partner) with the partner two DPP moves away (register r)
+    auto cross2 = [&](auto qp1, auto qp2) {
+        constexpr int QP1 = decltype(qp1)::value, QP2 = decltype(qp2)::value;
+        double o[IPT];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) o[r] = quad_swap<QP2>(quad_swap<QP1>(k[r]));
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) k[r] = __builtin_fmin(k[r], -o[r]);
+    };
     using X1 = std::integral_constant<int, 0xB1>;    // lane t ^ 1
     using X2 = std::integral_constant<int, 0x4E>;    // lane t ^ 2
+    using QR = std::integral_constant<int, 0x1B>;    // lane reversal within a quad
     using M8 = std::integral_constant<int, 0x141>;   // lane 7 - t within eight
+    using R8 = std::integral_constant<int, 0x128>;   // lane t ^ 8 (a row of 16 rotated by 8)
     using Same = std::false_type;
     using Mirror = std::true_type;
 
@@ -281,6 +295,19 @@ __device__ __forceinline__ void register_sort_identical(double (&k)[IPT], int ma
         const bool d = maxw > 128 && b3;
         set_mode(neg ^ b2 ^ d);
         cross(M8{}, Mirror{});
+        set_mode(neg ^ b1 ^ d);
+        cross(X2{}, Same{});
+        set_mode(neg ^ b0 ^ d);
+        cross(X1{}, Same{});
+        set_mode(neg ^ d);
+        bitonic_clean_regs<1, IPT>(k);
+    }
+    if (maxw >= 256) {                   // level 7: runs alternate with bit 8 unless last
+        const bool d = maxw > 256 && b4;
+        set_mode(neg ^ b3 ^ d);
+        cross(R8{}, Same{});
+        set_mode(neg ^ b2 ^ d);
+        cross2(M8{}, QR{});
         set_mode(neg ^ b1 ^ d);
         cross(X2{}, Same{});
         set_mode(neg ^ b0 ^ d);
@@ -438,7 +465,7 @@ __device__ __forceinline__ void block_sort_lds(typename KT::T *sk, VS *sv, int m
         if (network) {
             register_sort_identical<NetMinMax<KT>::dir, IPT>(k, maxw);
             __syncthreads();
-            block_merge_rounds_identical<KT, NetMinMax<KT>::dir, NT, IPT>(sk, k, maxw < 128 ? maxw : 128, maxw,
+            block_merge_rounds_identical<KT, NetMinMax<KT>::dir, NT, IPT>(sk, k, maxw < 256 ? maxw : 256, maxw,
                                                                            active);
             return;
         }

@@ -117,7 +117,7 @@ def _time_calls(torch, stream, fn, reps):
 
 SECTIONS = ("patterns", "learned", "segmented", "kv", "buffer")
 LEARNED_PATTERNS = ("lognormal", "gaussmix", "zipf_ints")
-LEARNED_CALLS = ("plain", "learned", "learned_untrained")
+LEARNED_CALLS = ("plain", "learned", "learned_untrained", "learned_sample_table")
 KV_PATTERNS = ("uniform", "zipf")
 SEG_WORKLOADS = ("100k_arrays", "until_total_16_to_2^20")
 
@@ -185,7 +185,8 @@ def _extras_learned(gs, torch, W, n, dev, stream, patterns, calls):
     """Learned vs plain on the learned workloads."""
     every = {"plain": lambda b: gs.gs_sort_f64(b),
              "learned": lambda b: gs.gs_learned_sort(b),
-             "learned_untrained": lambda b: gs.gs_learned_sort(b, mode=1)}
+             "learned_untrained": lambda b: gs.gs_learned_sort(b, mode=1),
+             "learned_sample_table": lambda b: gs.gs_learned_sort(b, mode=2)}
     lr = {}
     for pat in patterns:
         log(f"extras: learned {pat}")
@@ -206,7 +207,8 @@ def _extras_learned(gs, torch, W, n, dev, stream, patterns, calls):
         buf.copy_(x)
         rep = gs.gs_learned_sort(buf, report=True)
         row["learned_report"] = {k: rep[k] for k in ("fallback", "max_bucket", "overflow_buckets",
-                                                    "train_loss_first", "train_loss_last", "feature")}
+                                                    "train_loss_first", "train_loss_last", "feature",
+                                                    "heavy_values")}
         row["learned_sorted"] = bool((buf[1:] >= buf[:-1]).all().item())
         lr[pat] = row
         del x, buf

@@ -85,12 +85,15 @@ typedef struct {
     uint32_t max_bucket;            /* learned: largest bucket (keys) */
     float    train_loss_first;      /* learned: training loss of the first / last step */
     float    train_loss_last;
-    uint32_t feature;               /* learned: 0 = linear in x, 1 = linear in the key bits */
+    uint32_t feature;               /* learned: bit 0: 0 = linear in x, 1 = linear in the key bits;
+                                       bit 1: the knot table is the sample's CDF (mode 2, or the
+                                       trained table failed the sample screening) */
     uint32_t invalid_offsets;       /* segsort: 1 if the device check rejected the offsets */
     double   elapsed_ms;            /* wall time of the call measured with HIP events */
     uint32_t order;                 /* plain sorts: 0 sorted, 1 input already in order (nothing
                                        moved), 2 input strictly reversed (one reversal pass) */
-    uint32_t reserved;
+    uint32_t heavy_values;          /* learned: key values of the sample's long runs of equal keys
+                                       given buckets of their own (not sorted further) */
     uint64_t keys_moved;            /* plain sorts: element moves of the call (leaf stores, merge
                                        and concatenation stores, reversals), the bytes a pass
                                        writes divided by the element size */
@@ -105,10 +108,11 @@ typedef struct {
     uint32_t knots;          /* knots of the tabulated model, in [2, 16384]; default 4096 */
     float    lr;             /* Adam learning rate; default 2e-2 */
     uint64_t seed;           /* sample positions, weight init and minibatches */
-    uint32_t mode;           /* 0 = trained network, 1 = untrained linear CDF (table[i] = i/knots) */
-    uint32_t screen;         /* 0 = trained mode lets the plain path screen the table on the
-                                sample before any key moves (default); 1 = skip that early
-                                screening (the checks on the full bucket totals still apply) */
+    uint32_t mode;           /* 0 = trained network, 1 = untrained linear CDF (table[i] = i/knots),
+                                2 = the sorted sample's CDF at the knots (no network) */
+    uint32_t screen;         /* 0 = trained mode screens its table on the sample before any key
+                                moves (default); 1 = skip that early screening (the checks on
+                                the full bucket totals still apply) */
     const float *weights_override;    /* device, 4353 floats: skip training, use these weights; may be NULL */
     const float *test_bucket_table;   /* device, `knots`+1 floats: raw table, bypasses the running max
                                          (test hook to force an order violation); may be NULL */
@@ -251,7 +255,13 @@ gs_status gs_segsort_autotune(const double *keys, int64_t num_keys, const int64_
    half), or the sample has no usable range, the plain path sorts the
    untouched input (report.fallback = 1).  Before that, the trained table
    buckets the sorted sample: a bucket predicted above max(2^19, 16 x the
-   average) sends the call to the plain path at once (report.fallback = 2).
+   average) replaces the table by the sample's CDF at the knots, and if that
+   one fails too (keys packed closer than a knot resolves) the call goes to
+   the plain path at once (report.fallback = 2), as it does when a run of
+   equal sample keys too long for one bucket is not among the heavy values.
+   Heavy values: the values of the longest runs of equal keys in the sorted
+   sample (at least 4 average buckets' share; at most 31 and num_buckets/8)
+   get buckets of their own, which are not sorted (report.heavy_values).
    Unless the stream is capturing a graph, the call synchronises the stream
    once, after training, to read that decision and enqueue only the path that
    runs; under capture both paths are enqueued, gated on the device.  Inputs

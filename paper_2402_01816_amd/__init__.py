@@ -51,7 +51,7 @@ class GsReport(ctypes.Structure):
         ("invalid_offsets", ctypes.c_uint32),
         ("elapsed_ms", ctypes.c_double),
         ("order", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("heavy_values", ctypes.c_uint32),
         ("keys_moved", ctypes.c_uint64),
     ]
 

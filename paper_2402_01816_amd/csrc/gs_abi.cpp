@@ -766,7 +766,7 @@ static gs_status check_learned_params(const gs_learned_params &p)
     if (p.sample_size < 1024 || p.sample_size > (1u << 24)) return fail(GS_EINVAL, "sample_size out of [1024, 2^24]");
     if (p.knots < 2 || p.knots > 16384) return fail(GS_EINVAL, "knots out of [2, 16384]");
     if (p.batch < 32 || p.batch % 32 || p.batch > 8192) return fail(GS_EINVAL, "batch must be a multiple of 32 in [32, 8192]");
-    if (p.mode > 1) return fail(GS_EINVAL, "mode must be 0 or 1");
+    if (p.mode > 2) return fail(GS_EINVAL, "mode must be 0, 1 or 2");
     if (p.screen > 1) return fail(GS_EINVAL, "screen must be 0 or 1");
     if (!(p.lr > 0.f) || !(p.lr < 1.f)) return fail(GS_EINVAL, "lr out of (0, 1)");
     if (p.train_steps > 100000) return fail(GS_EINVAL, "train_steps above 100000");
@@ -823,6 +823,7 @@ gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p, v
         rep->train_loss_first = lr.loss_first;
         rep->train_loss_last = lr.loss_last;
         rep->feature = lr.feature;
+        rep->heavy_values = lr.heavy;
         unsigned any = 0;
         hipError_t e3 = gs::learned_errors((const char *)ws, L, &any);
         if (e3 != hipSuccess) return hip_fail(e3, "reading the error words");

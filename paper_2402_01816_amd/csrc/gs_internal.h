@@ -192,10 +192,14 @@ hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan
                              hipStream_t st);
 // The same with every buffer given: hbuf holds floor((offsets[nseg]-offsets[0])/2)
 // doubles, ctrl 64 words, cls/rank/list nseg ints each, forest an area laid
-// out by fp (from plan_forest_seg for these sizes).
+// out by fp (from plan_forest_seg for these sizes).  With preset_codes the
+// caller has written every segment's order code into rank[] (0: to be sorted,
+// kSegDone: already in order) on the stream before the call.
+constexpr int kSegDone = -1;
 hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys,
                               double *hbuf, unsigned *ctrl, int *cls, int *rank, int *list, char *forest,
-                              const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st);
+                              const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st,
+                              bool preset_codes = false);
 
 struct Prob;
 // Capacity of a forest area for up to max_probs f64 problems of at most

@@ -31,13 +31,15 @@ struct LearnedPlan {
     int64_t off_params, off_m, off_v, off_partial, off_losses, off_raw, off_tab;
     int64_t off_totals, off_starts, off_offsets, off_dstart, off_tilecnt;
     int64_t off_segctrl, off_seglists;
+    int64_t off_heavy;          // the sample's heavy values (kHeavyMax doubles, ascending, NaN past the count)
+    int64_t off_runs;           // the sample's long runs of equal keys (start, length)
     int64_t off_segforest;      // forest area of the bucket sorts (both halves in turn)
     ForestPlan segforest;
     int64_t bytes;
 };
 
 struct LearnedReport {
-    unsigned fallback, order_violation, overflow_buckets, max_bucket, big_buckets, err, feature;
+    unsigned fallback, order_violation, overflow_buckets, max_bucket, big_buckets, err, feature, heavy;
     float loss_first, loss_last;
 };
 

@@ -19,6 +19,10 @@
 //      than every key in a lower one; the table is checked for monotonicity
 //      before any key moves (a non-monotone table -- only possible through the
 //      test hook -- sends the call to the plain path on the untouched input);
+//      values that fill long runs of the sorted sample (heavy values: equal
+//      keys always share a bucket, so no network can spread them) get buckets
+//      of their own, which need no sort -- the stable distribution leaves
+//      their keys in input order;
 //   6. bucket totals of both halves before any key moves (the overflow
 //      check sends the call to the plain path on the untouched input); then
 //      for the second half and then the first: per-tile digit counts, a
@@ -57,6 +61,23 @@ constexpr int L_ERR = 5;                 // training's error word (it has no wai
 constexpr int L_BIGB = 6;                // buckets larger than one LDS tile
 constexpr int L_FEAT = 7;                // chosen feature
 constexpr int L_SCREENED = 8;              // the sample predicted too uneven buckets
+constexpr int L_HEAVY = 9;                 // heavy values found in the sample
+constexpr int L_RUNS = 10;                 // long runs of equal keys recorded in the sample
+constexpr int L_RESCUE = 11;               // the trained table failed the screening: sample table
+constexpr int L_SAMPTAB = 12;              // the knot table is the sample's CDF
+
+// Heavy values: at most kHeavyMax, kept ascending in kHeavySlots doubles with
+// NaN past the count (a NaN slot compares as greater than every key).  A
+// heavy value fills a run of at least kHeavySkew x the average bucket's share
+// of the sorted sample.
+#ifndef GS_HEAVY_SLOTS
+#define GS_HEAVY_SLOTS 32
+#endif
+constexpr int kHeavySlots = GS_HEAVY_SLOTS;              // a power of two
+static_assert((kHeavySlots & (kHeavySlots - 1)) == 0 && kHeavySlots <= 256, "heavy slots");
+constexpr int kHeavyMax = kHeavySlots - 1;
+constexpr int64_t kHeavySkew = 4;
+constexpr int kHeavyCand = 256;           // long runs of the sample recorded at most
 
 // The plain path screens the learned form before any key moves: a bucket
 // predicted (from the sample, scaled to a half) above max(kScreenMin, 16 x the
@@ -94,13 +115,33 @@ __device__ __forceinline__ double phi_of(double x, const Feature &F)
     return (x - F.lo) * F.inv;
 }
 
+// With hc heavy values h_1 < ... < h_hc (hv, ascending), key x's bucket is
+// its table bucket t(x) (the table spread over B - 2 hc buckets) plus
+// c(x) + c'(x), where c(x) counts the heavy values at or below x and c'(x)
+// those below it.  That stays monotone (t and both counts are), gives h_k the
+// bucket t(h_k) + 2k - 1, and no other key can land there: a key below h_k
+// has at most k - 1 heavy values at or below it and t no larger, a key above
+// it at least k and t no smaller, and both offsets 2c are even.
+// heavy_shift returns c(x) + c'(x) (x not NaN): a search over the kHeavySlots
+// slots in powers of two, the NaN slots past the count never at or below x.
+__device__ __forceinline__ int heavy_shift(double x, const double *hv)
+{
+    int pos = 0;
+#pragma unroll
+    for (int step = kHeavySlots / 2; step >= 1; step >>= 1) pos += hv[pos + step - 1] <= x ? step : 0;
+    const bool eq = pos > 0 && hv[pos - 1] == x;
+    return 2 * pos - (eq ? 1 : 0);
+}
+
 // Bucket of key x.  Monotone non-decreasing in x whenever `tab` is
 // non-decreasing: the knot coordinate u is monotone (correctly rounded
 // subtraction, conversion, multiplication by a positive constant and
 // rounding to float), the knot index and the fraction are monotone in u, the
 // interpolation is clamped to the next knot.  NaN keys take the last bucket
-// (they sort last).
-__device__ __forceinline__ int bucket_of(double x, const Feature &F, const float *tab, int G, int B)
+// (they sort last).  With heavy values (hc > 0) the table spreads over
+// B - 2 hc buckets and heavy_shift places the rest.
+// Knot coordinate of key x, clamped to [0, G] (a NaN coordinate becomes 0).
+__device__ __forceinline__ float knot_coord(double x, const Feature &F, int G)
 {
     float u;
     if (F.bits) {
@@ -110,14 +151,22 @@ __device__ __forceinline__ int bucket_of(double x, const Feature &F, const float
     } else {
         u = (float)((x - F.lo) * F.scale);
     }
-    // clamp to [0, G] (a NaN u becomes 0), knot index and fraction
-    const float uc = fminf(fmaxf(u, 0.f), (float)G);
+    return fminf(fmaxf(u, 0.f), (float)G);
+}
+
+__device__ __forceinline__ int bucket_of(double x, const Feature &F, const float *tab, int G, int B,
+                                         const double *hv = nullptr, int hc = 0)
+{
+    // knot index and fraction
+    const float uc = knot_coord(x, F, G);
     const int i = min((int)uc, G - 1);
     const float f = uc - (float)i;
     const float a = tab[i], b = tab[i + 1];
     const float v = fminf(fmaf(f, b - a, a), b);
-    int bk = (int)(v * (float)B);
-    bk = bk < 0 ? 0 : (bk > B - 1 ? B - 1 : bk);
+    const int Bt = B - 2 * hc;
+    int bk = (int)(v * (float)Bt);
+    bk = bk < 0 ? 0 : (bk > Bt - 1 ? Bt - 1 : bk);
+    if (hc > 0 && x == x) bk += heavy_shift(x, hv);
     return x != x ? B - 1 : bk;
 }
 
@@ -125,7 +174,8 @@ __device__ __forceinline__ int bucket_of(double x, const Feature &F, const float
 // knot coordinate first, then all table reads, then the interpolations, so
 // that the keys' LDS reads are in flight together.
 template <int N>
-__device__ __forceinline__ void buckets_of(const double *x, int *bk, const Feature &F, const float *tab, int G, int B)
+__device__ __forceinline__ void buckets_of(const double *x, int *bk, const Feature &F, const float *tab, int G, int B,
+                                           const double *hv = nullptr, int hc = 0)
 {
     float uc[N];
     if (F.bits) {
@@ -151,14 +201,22 @@ __device__ __forceinline__ void buckets_of(const double *x, int *bk, const Featu
         a[r] = tab[ix[r]];
         b[r] = tab[ix[r] + 1];
     }
+    const int Bt = B - 2 * hc;
 #pragma unroll
     for (int r = 0; r < N; ++r) {
         const float f = uc[r] - (float)ix[r];
         const float v = fminf(fmaf(f, b[r] - a[r], a[r]), b[r]);
-        int k = (int)(v * (float)B);
-        k = k < 0 ? 0 : (k > B - 1 ? B - 1 : k);
-        bk[r] = x[r] != x[r] ? B - 1 : k;
+        int k = (int)(v * (float)Bt);
+        k = k < 0 ? 0 : (k > Bt - 1 ? Bt - 1 : k);
+        bk[r] = k;
     }
+    if (hc > 0) {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+            if (x[r] == x[r]) bk[r] += heavy_shift(x[r], hv);
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) bk[r] = x[r] != x[r] ? B - 1 : bk[r];
 }
 
 }  // namespace
@@ -183,42 +241,98 @@ __global__ void learned_sample_kernel(const double *keys, int64_t n, int64_t S, 
 // smaller largest bin wins (ties: linear).  (The training inputs and targets
 // follow in learned_targets_kernel.)
 //
-// With `screen_half` > 0 (the half size the screening scales to) the sorted
-// sample's equal keys are screened first: equal keys (and all NaNs) always
-// share a bucket, so a run of equal keys long enough that it alone scales to
-// more than the screening limit fails the screening whatever the network
-// learns.  Such an input takes the plain path before any training (the
-// training and tabulation launches are gated on the fallback word).
+// The sorted sample's runs of equal keys come first.  A run of at least
+// kHeavySkew x the average bucket's share of the sample is a heavy value:
+// equal keys always share a bucket, so no network can spread them, and the
+// kHeavyMax longest (NaN excepted) get buckets of their own (hv, ascending,
+// NaN past the count; the count in ctrl[L_HEAVY]), which need no sort.  Every
+// such run found (at most kHeavyCand) is recorded for the density targets
+// (runs: start, length; the count in ctrl[L_RUNS]).  With `screen_half` > 0 (the half size the screening scales to) a run that is not
+// among them -- or NaNs -- long enough that it alone scales past the screening
+// limit sends the call to the plain path before any training (the training
+// and tabulation launches are gated on the fallback word).
 __global__ __launch_bounds__(1024) void learned_prep_kernel(const double *xs, int64_t S, int G, Feature *feat,
-                                                            unsigned *ctrl, int64_t screen_half, int B)
+                                                            unsigned *ctrl, int64_t screen_half, int B, double *hv,
+                                                            int64_t *runs)
 {
-    if (screen_half > 0) {
-        __shared__ unsigned s_run;
-        const int64_t avg = screen_half / B;
+    {
+        __shared__ unsigned s_cnt, s_fail;
+        __shared__ int64_t s_len[kHeavyCand], s_start[kHeavyCand];
+        __shared__ double s_val[kHeavyCand];
+        const int64_t half = screen_half > 0 ? screen_half : S;
+        const int64_t avg = half / B;
         const int64_t limit = kScreenSkew * avg > kScreenMin ? kScreenSkew * avg : kScreenMin;
         // shortest run whose scaled size run * half / S exceeds the limit
-        const int64_t m = ((limit + 1) * S + screen_half - 1) / screen_half;
-        if (threadIdx.x == 0) s_run = 0u;
+        const int64_t m = ((limit + 1) * S + half - 1) / half;
+        // shortest heavy run
+        int64_t mh = (kHeavySkew * S + B - 1) / B;
+        mh = mh < 2 ? 2 : mh;
+        if (threadIdx.x == 0) s_cnt = s_fail = 0u;
         __syncthreads();
         auto same = [&](double a, double b) { return a == b || (a != a && b != b); };
-        for (int64_t i = threadIdx.x; m >= 1 && i + m - 1 < S; i += 1024) {
+        for (int64_t i = threadIdx.x; i + mh - 1 < S; i += 1024) {
             // a long run starting here: measure it (its end by binary search)
-            if (same(xs[i], xs[i + m - 1]) && (i == 0 || !same(xs[i - 1], xs[i]))) {
-                int64_t lo = i + m - 1, hi = S;          // last index of the run: lo
+            if (same(xs[i], xs[i + mh - 1]) && (i == 0 || !same(xs[i - 1], xs[i]))) {
+                int64_t lo = i + mh - 1, hi = S;         // last index of the run: lo
                 while (hi - lo > 1) {
                     const int64_t mid = (lo + hi) >> 1;
                     if (same(xs[i], xs[mid])) lo = mid;
                     else hi = mid;
                 }
-                atomicMax(&s_run, (unsigned)(lo - i + 1));
+                const int64_t len = lo - i + 1;
+                if (xs[i] != xs[i]) {
+                    if (screen_half > 0 && len >= m) atomicOr(&s_fail, 1u);
+                } else {
+                    const unsigned c = atomicAdd(&s_cnt, 1u);
+                    if (c < (unsigned)kHeavyCand) {
+                        s_len[c] = len;
+                        s_start[c] = i;
+                        s_val[c] = xs[i];
+                    }
+                }
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0 && s_run) {
-            const int64_t predicted = (int64_t)s_run * screen_half / S;
-            ctrl[L_SCREENED] = 1u;
-            ctrl[L_MAXB] = (unsigned)(predicted < 0xffffffffll ? predicted : 0xffffffffll);
-            ctrl[L_FALLBACK] = 1u;
+        if (threadIdx.x == 0) {
+            const int nc = s_cnt < (unsigned)kHeavyCand ? (int)s_cnt : kHeavyCand;
+            for (int c = 0; c < nc; ++c) {
+                runs[2 * c] = s_start[c];
+                runs[2 * c + 1] = s_len[c];
+            }
+            ctrl[L_RUNS] = (unsigned)nc;
+            const int hmax = kHeavyMax < B / 8 ? kHeavyMax : B / 8;
+            // the hmax longest runs (selection), then the remaining ones screened
+            int hc = 0;
+            for (; hc < hmax && hc < nc; ++hc) {
+                int best = hc;
+                for (int c = hc + 1; c < nc; ++c)
+                    if (s_len[c] > s_len[best]) best = c;
+                const int64_t tl = s_len[hc];
+                const double tv = s_val[hc];
+                s_len[hc] = s_len[best];
+                s_val[hc] = s_val[best];
+                s_len[best] = tl;
+                s_val[best] = tv;
+            }
+            int64_t rest = 0;                           // longest run left out
+            for (int c = hc; c < nc; ++c) rest = s_len[c] > rest ? s_len[c] : rest;
+            const bool lost = s_cnt > (unsigned)kHeavyCand;   // candidates not recorded
+            // ascending values of the chosen ones
+            for (int c = 1; c < hc; ++c)
+                for (int d = c; d > 0 && s_val[d] < s_val[d - 1]; --d) {
+                    const double t = s_val[d];
+                    s_val[d] = s_val[d - 1];
+                    s_val[d - 1] = t;
+                }
+            for (int c = 0; c < kHeavySlots; ++c) hv[c] = c < hc ? s_val[c] : __builtin_nan("");
+            ctrl[L_HEAVY] = (unsigned)hc;
+            if (screen_half > 0 && (s_fail || lost || rest >= m)) {
+                const int64_t worst = rest > m ? rest : m;
+                const int64_t predicted = worst * screen_half / S;
+                ctrl[L_SCREENED] = 1u;
+                ctrl[L_MAXB] = (unsigned)(predicted < 0xffffffffll ? predicted : 0xffffffffll);
+                ctrl[L_FALLBACK] = 1u;
+            }
         }
         __syncthreads();
     }
@@ -294,28 +408,109 @@ __device__ __forceinline__ float train_input(double x, const Feature &F)
     return (float)p;
 }
 
-// Inputs and log-density targets (from the rank differences of the
-// non-decreasing inputs over +-kDensH ranks), one thread per sample key; the
-// two neighbours' inputs are recomputed from their keys, so no pass waits on
-// another.
+// Inputs and log-density targets, one thread per sample key: the sample keys
+// in a window of +-kDensH ranks over the width of their inputs (the two ends'
+// inputs recomputed from their keys, so no pass waits on another).  The runs
+// of equal keys recorded by the prep kernel do not count: a run is a point
+// mass that no density expresses (its keys share one bucket whatever the
+// table does), and counted it would crowd the rest of the table.  A key
+// inside a run takes the window around the whole run, so the run's value
+// gets the density of the keys next to it.  Without runs this is the plain
+// window density.
 __global__ __launch_bounds__(256) void learned_targets_kernel(const double *xs, int64_t S, const Feature *feat,
-                                                              float *u, float *t)
+                                                              float *u, float *t, const int64_t *runs,
+                                                              const unsigned *ctrl)
 {
+    __shared__ int64_t s_run[2 * kHeavyCand];
+    const unsigned nrec = ctrl[L_RUNS];
+    const int nr = nrec < (unsigned)kHeavyCand ? (int)nrec : kHeavyCand;
+    for (int k = threadIdx.x; k < 2 * nr; k += blockDim.x) s_run[k] = runs[k];
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S) return;
     const Feature F = *feat;
     u[i] = train_input(xs[i], F);
-    const int64_t lo = i - kDensH > 0 ? i - kDensH : 0;
-    const int64_t hi = i + kDensH < S - 1 ? i + kDensH : S - 1;
+    int64_t lo = i - kDensH, hi = i + kDensH, in_runs = 0;
+    for (int k = 0; k < nr; ++k) {
+        const int64_t st = s_run[2 * k], ln = s_run[2 * k + 1];
+        in_runs += ln;
+        if (i >= st && i < st + ln) {
+            lo = st - kDensH;
+            hi = st + ln - 1 + kDensH;
+        }
+    }
+    lo = lo > 0 ? lo : 0;
+    hi = hi < S - 1 ? hi : S - 1;
+    // sample keys in [lo, hi) outside the runs
+    int64_t cnt = hi - lo;
+    for (int k = 0; k < nr; ++k) {
+        const int64_t st = s_run[2 * k], en = st + s_run[2 * k + 1];
+        const int64_t a = st > lo ? st : lo, b = en < hi ? en : hi;
+        cnt -= b > a ? b - a : 0;
+    }
+    const int64_t rest = S - in_runs > 1 ? S - in_runs : 1;
     double w = (double)train_input(xs[hi], F) - (double)train_input(xs[lo], F);
     w = w > 1e-7 ? w : 1e-7;
-    t[i] = (float)log((double)(hi - lo) / ((double)S * w));
+    t[i] = (float)log((double)(cnt > 1 ? cnt : 1) / ((double)rest * w));
 }
 
 // ---------------------------------------------------------------------------
 // 4. knot table: normalised cumulative integral of exp(network) (or the
-//    linear CDF, or the raw test table); verified monotone
+//    linear CDF, or the sample's own CDF, or the raw test table); verified
+//    monotone
 // ---------------------------------------------------------------------------
+// The sample's CDF at the knots: table[i] is the share of the sample keys
+// whose knot coordinate lies below i, counted without NaNs and without the
+// recorded runs of equal keys (as the density targets), so the keys of every
+// knot interval spread evenly over the table's share of buckets.  Monotone by
+// construction (counts of a sorted sample below rising bounds).  With
+// `rescue` the kernel runs only if the screening rejected the trained table.
+// Sets ctrl[L_SAMPTAB].
+__global__ __launch_bounds__(1024) void learned_sample_table_kernel(const double *xs, int64_t S, const Feature *feat,
+                                                                    int G, float *tab, const int64_t *runs,
+                                                                    unsigned *ctrl, int rescue)
+{
+    __shared__ int64_t s_run[2 * kHeavyCand];
+    __shared__ int64_t s_nn;
+    if (ctrl[L_FALLBACK] || (rescue && !ctrl[L_RESCUE])) return;
+    const int tid = threadIdx.x;
+    const unsigned nrec = ctrl[L_RUNS];
+    const int nr = nrec < (unsigned)kHeavyCand ? (int)nrec : kHeavyCand;
+    for (int k = tid; k < 2 * nr; k += 1024) s_run[k] = runs[k];
+    if (tid == 0) {
+        int64_t a = 0, b = S;                      // first NaN (NaNs sort last)
+        while (a < b) {
+            const int64_t m = (a + b) >> 1;
+            if (xs[m] != xs[m]) b = m;
+            else a = m + 1;
+        }
+        s_nn = a;
+    }
+    __syncthreads();
+    const Feature F = *feat;
+    const int64_t nn = s_nn;
+    auto outside = [&](int64_t j) {               // keys of [0, j) in no run
+        int64_t c = j;
+        for (int k = 0; k < nr; ++k) {
+            const int64_t st = s_run[2 * k], en = st + s_run[2 * k + 1];
+            const int64_t e = en < j ? en : j;
+            c -= e > st ? e - st : 0;
+        }
+        return c;
+    };
+    const int64_t total = outside(nn);
+    if (tid == 0) ctrl[L_SAMPTAB] = 1u;
+    for (int i = tid; i <= G; i += 1024) {
+        int64_t a = 0, b = nn;                     // first key with coordinate >= i
+        while (a < b) {
+            const int64_t m = (a + b) >> 1;
+            if (knot_coord(xs[m], F, G) < (float)i) a = m + 1;
+            else b = m;
+        }
+        tab[i] = i == G || total <= 0 ? (i == G ? 1.0f : 0.0f) : (float)((double)outside(a) / (double)total);
+    }
+}
+
 __global__ __launch_bounds__(1024) void learned_table_kernel(const float *raw, const float *test_table, int mode,
                                                              int G, float *tab, unsigned *ctrl, const Feature *feat)
 {
@@ -332,6 +527,8 @@ __global__ __launch_bounds__(1024) void learned_table_kernel(const float *raw, c
         for (int i = b0; i < b1; ++i) tab[i] = test_table[i];
     } else if (mode == 1) {
         for (int i = b0; i < b1; ++i) tab[i] = (float)((double)i / (double)G);
+    } else if (mode == 2) {
+        // written by learned_sample_table_kernel: only verified here
     } else {
         // largest log density (NaN counts as very small)
         float mx = -3.0e38f;
@@ -414,25 +611,34 @@ constexpr int SW_TILE = SW_NT * SW_ROUNDS;           // 4096 keys by default
 #define GS_LEARN_SCATTER_WAVES (SW_ROUNDS >= 16 ? 2 : SW_ROUNDS >= 12 ? 3 : 4)
 #endif
 
-// The sorted sample through the trained knot table: its largest bucket,
-// scaled to a half of the input, decides whether the call goes on with the
-// learned form or takes the plain path at once.
+// The sorted sample through the knot table: its largest bucket, scaled to a
+// half of the input, decides whether the call goes on with the learned form.
+// First pass (the trained table): a table that fails is replaced by the
+// sample's CDF (ctrl[L_RESCUE]).  Second pass, only after such a rescue: a
+// table that still fails (keys no knot resolves) sends the call to the plain
+// path at once.
 __global__ __launch_bounds__(1024) void learned_screen_kernel(const double *sample, int64_t S, const Feature *feat,
                                                              const float *tab, int G, int B, int64_t half,
-                                                             unsigned *ctrl)
+                                                             unsigned *ctrl, const double *hv, int second)
 {
     extern __shared__ unsigned char s_raw[];
     float *s_tab = (float *)s_raw;                       // G + 1 knots
     unsigned *s_hist = (unsigned *)(s_tab + G + 1);      // B buckets
     __shared__ unsigned s_max;
-    if (ctrl[L_FALLBACK]) return;
+    __shared__ double s_hv[kHeavySlots];
+    if (ctrl[L_FALLBACK] || (second && !ctrl[L_RESCUE])) return;
     const int tid = threadIdx.x;
+    const int hc = (int)ctrl[L_HEAVY];
     for (int i = tid; i <= G; i += 1024) s_tab[i] = tab[i];
     for (int i = tid; i < B; i += 1024) s_hist[i] = 0u;
+    if (tid < kHeavySlots) s_hv[tid] = hv[tid];
     if (tid == 0) s_max = 0u;
     __syncthreads();
     const Feature F = *feat;
-    for (int64_t i = tid; i < S; i += 1024) atomicAdd(&s_hist[bucket_of(sample[i], F, s_tab, G, B)], 1u);
+    for (int64_t i = tid; i < S; i += 1024) atomicAdd(&s_hist[bucket_of(sample[i], F, s_tab, G, B, s_hv, hc)], 1u);
+    __syncthreads();
+    // the heavy values' own buckets need no sort: they do not count
+    if (tid < hc) s_hist[bucket_of(s_hv[tid], F, s_tab, G, B, s_hv, hc)] = 0u;
     __syncthreads();
     unsigned m = 0u;
     for (int i = tid; i < B; i += 1024) m = s_hist[i] > m ? s_hist[i] : m;
@@ -442,7 +648,9 @@ __global__ __launch_bounds__(1024) void learned_screen_kernel(const double *samp
         const int64_t predicted = (int64_t)s_max * half / S;
         const int64_t avg = half / B;
         const int64_t limit = kScreenSkew * avg > kScreenMin ? kScreenSkew * avg : kScreenMin;
-        if (predicted > limit) {
+        if (predicted > limit && !second) {
+            ctrl[L_RESCUE] = 1u;
+        } else if (predicted > limit) {
             ctrl[L_SCREENED] = 1u;
             ctrl[L_MAXB] = (unsigned)(predicted < 0xffffffffll ? predicted : 0xffffffffll);
             ctrl[L_FALLBACK] = 1u;
@@ -453,18 +661,21 @@ __global__ __launch_bounds__(1024) void learned_screen_kernel(const double *samp
 __global__ __launch_bounds__(SW_NT, 4) void learned_count_kernel(const double *src, int64_t len, const Feature *feat,
                                                               const float *tab, int G, int B, int shift, int dbits,
                                                               unsigned *tilecnt, unsigned *totals,
-                                                              const unsigned *ctrl)
+                                                              const unsigned *ctrl, const double *hv)
 {
     extern __shared__ unsigned char lds_raw[];
     float *s_tab = (float *)lds_raw;
     unsigned *s_tot = (unsigned *)(lds_raw + (size_t)(G + 1) * 4);
     __shared__ unsigned s_dc[64];
+    __shared__ double s_hv[kHeavySlots];
     if (ctrl[L_FALLBACK] || len <= 0) return;
     const Feature F = *feat;
     const int tid = threadIdx.x;
     const int D = 1 << dbits;
+    const int hc = (int)ctrl[L_HEAVY];
     const int64_t ntiles = (len + SW_TILE - 1) / SW_TILE;
     for (int i = tid; i <= G; i += SW_NT) s_tab[i] = tab[i];
+    if (tid < kHeavySlots) s_hv[tid] = hv[tid];
     if (totals)
         for (int i = tid; i < B; i += SW_NT) s_tot[i] = 0u;
     // keys of tile t (indices past the input read its last key)
@@ -488,8 +699,8 @@ __global__ __launch_bounds__(SW_NT, 4) void learned_count_kernel(const double *s
         __syncthreads();
         const int64_t base = t * SW_TILE;
         int bk[SW_ROUNDS];
-        buckets_of<SW_ROUNDS / 2>(x, bk, F, s_tab, G, B);    // two halves: fewer live registers
-        buckets_of<SW_ROUNDS / 2>(x + SW_ROUNDS / 2, bk + SW_ROUNDS / 2, F, s_tab, G, B);
+        buckets_of<SW_ROUNDS / 2>(x, bk, F, s_tab, G, B, s_hv, hc);    // two halves: fewer live registers
+        buckets_of<SW_ROUNDS / 2>(x + SW_ROUNDS / 2, bk + SW_ROUNDS / 2, F, s_tab, G, B, s_hv, hc);
 #pragma unroll
         for (int r = 0; r < SW_ROUNDS; ++r) {
             if (base + r * SW_NT + tid < len) {
@@ -560,20 +771,36 @@ __global__ __launch_bounds__(1024) void learned_tilescan_kernel(unsigned *tilecn
 
 // Bucket starts (exclusive scan of totals) of both halves, the segment
 // offsets for the bucket sorts, the digit starts of the two distribution
-// passes, the largest bucket and the overflow decision.  A bucket id is
-// (high digit << lbits) | low digit.
+// passes, the largest bucket and the overflow decision (the heavy values' own
+// buckets are not sorted, so no size limit applies to them).  A bucket id is
+// (high digit << lbits) | low digit.  Also the bucket sorts' order codes
+// (codes: one row of B per half): the heavy values' buckets are done.
 __global__ __launch_bounds__(1024) void learned_bucket_scan_kernel(const unsigned *totals, int B, int lbits,
                                                                    int halves, unsigned *starts, int64_t *offsets,
-                                                                   unsigned *dstart, int64_t limit, unsigned *ctrl)
+                                                                   unsigned *dstart, int64_t limit, unsigned *ctrl,
+                                                                   const Feature *feat, const float *tab, int G,
+                                                                   const double *hv, int *codes0, int *codes1)
 {
     __shared__ int64_t s_part[1024];
     __shared__ unsigned s_max, s_over, s_big;
     __shared__ unsigned s_low[64];
+    __shared__ unsigned char s_heavy[4096];
+    __shared__ double s_hv[kHeavySlots];
     if (ctrl[L_FALLBACK]) return;
     const int tid = threadIdx.x;
     const int DL = 1 << lbits, DH = B >> lbits;
+    const int hc = (int)ctrl[L_HEAVY];
     if (tid == 0) s_max = s_over = s_big = 0u;
+    for (int b = tid; b < B; b += 1024) s_heavy[b] = 0;
+    if (tid < kHeavySlots) s_hv[tid] = hv[tid];
     __syncthreads();
+    if (tid < hc) s_heavy[bucket_of(s_hv[tid], *feat, tab, G, B, s_hv, hc)] = 1;
+    __syncthreads();
+    for (int b = tid; b < B; b += 1024) {
+        const int code = s_heavy[b] ? kSegDone : 0;
+        codes0[b] = code;
+        codes1[b] = code;
+    }
     for (int h = 0; h < halves; ++h) {
         const unsigned *tt = totals + (size_t)h * B;
         const int per = (B + 1023) / 1024;
@@ -581,6 +808,7 @@ __global__ __launch_bounds__(1024) void learned_bucket_scan_kernel(const unsigne
         int64_t acc = 0;
         for (int b = b0; b < b1; ++b) {
             acc += tt[b];
+            if (s_heavy[b]) continue;
             atomicMax(&s_max, tt[b]);
             if ((int64_t)tt[b] > limit) atomicAdd(&s_over, 1u);
             if (tt[b] > 4096u) atomicAdd(&s_big, 1u);
@@ -637,10 +865,11 @@ __global__ __launch_bounds__(1024) void learned_bucket_scan_kernel(const unsigne
 __global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter_kernel(const double *src, double *dst, int64_t len,
                                                                 const Feature *feat, const float *tab, int G, int B,
                                                                 int shift, int dbits, const unsigned *tileoff,
-                                                                const unsigned *ctrl)
+                                                                const unsigned *ctrl, const double *hv)
 {
     extern __shared__ unsigned char lds_raw[];
     float *s_tab = (float *)lds_raw;
+    __shared__ double s_hv[kHeavySlots];
     double *s_key = (double *)(lds_raw + (((size_t)(G + 1) * 4 + 15) & ~(size_t)15));
     unsigned char *s_dig = (unsigned char *)(s_key + SW_TILE);
     __shared__ unsigned s_wcnt[SW_NT / 64][64];
@@ -650,6 +879,8 @@ __global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter
     const Feature F = *feat;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int D = 1 << dbits;
+    const int hc = (int)ctrl[L_HEAVY];
+    if (tid < kHeavySlots) s_hv[tid] = hv[tid];
     const int64_t ntiles = (len + SW_TILE - 1) / SW_TILE;
     // this wave's [round][digit] scratch: lane masks, then prefixes
     unsigned long long *wm = (unsigned long long *)s_key + wave * (SW_ROUNDS * 64);
@@ -683,7 +914,7 @@ __global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter
         if (tid < D) s_goff[tid] = goff;
         __syncthreads();
         int dg[SW_ROUNDS];
-        buckets_of<SW_ROUNDS>(x, dg, F, s_tab, G, B);
+        buckets_of<SW_ROUNDS>(x, dg, F, s_tab, G, B, s_hv, hc);
 #pragma unroll
         for (int r = 0; r < SW_ROUNDS; ++r) {
             const bool valid = base + r * 64 + lane < len;
@@ -816,6 +1047,8 @@ LearnedPlan plan_learned(int64_t n, const gs_learned_params &prm)
     L.off_tilecnt = o; o = al256(o + 2 * L.ntiles * 64 * 4);
     L.off_segctrl = o; o = al256(o + 2 * 64 * 4);
     L.off_seglists = o; o = al256(o + 2 * 3 * (int64_t)L.B * 4);
+    L.off_heavy = o; o = al256(o + kHeavySlots * 8);
+    L.off_runs = o; o = al256(o + kHeavyCand * 16);
     L.segforest = plan_forest_seg(half, half < L.limit ? half : L.limit, L.B);
     L.off_segforest = o; o = al256(o + L.segforest.bytes);
     L.bytes = o;
@@ -841,6 +1074,8 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
     int64_t *offsets = (int64_t *)(ws + L.off_offsets);
     unsigned *segctrl = (unsigned *)(ws + L.off_segctrl);
     int *seglists = (int *)(ws + L.off_seglists);
+    double *hv = (double *)(ws + L.off_heavy);
+    int64_t *runs = (int64_t *)(ws + L.off_runs);
     const bool tr = trace_on();
 
     launch_fill_u32(ctrl, 64, 0u, st);
@@ -858,9 +1093,10 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
     if (tr) trace_begin(TK_LEARN_PREP, st);
     const bool screening = prm.mode == 0 && !prm.test_bucket_table && prm.screen == 0;
     hipLaunchKernelGGL(learned_prep_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample, L.S, G, feat, ctrl,
-                       screening ? n - n / 2 : (int64_t)0, B);
+                       screening ? n - n / 2 : (int64_t)0, B, hv, runs);
     hipLaunchKernelGGL(learned_targets_kernel, dim3((unsigned)((L.S + 255) / 256)), dim3(256), 0, st,
-                       (const double *)sample, L.S, (const Feature *)feat, u, t);
+                       (const double *)sample, L.S, (const Feature *)feat, u, t, (const int64_t *)runs,
+                       (const unsigned *)ctrl);
     if (tr) trace_end(st);
 
     // 3-4. network and knot table
@@ -882,14 +1118,23 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
         if (e != hipSuccess) return e;
     }
     if (tr) trace_end(st);
+    if (prm.mode == 2 && !prm.test_bucket_table)
+        hipLaunchKernelGGL(learned_sample_table_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample, L.S,
+                           (const Feature *)feat, G, tab, (const int64_t *)runs, ctrl, 0);
     hipLaunchKernelGGL(learned_table_kernel, dim3(1), dim3(1024), 0, st, (const float *)raw, prm.test_bucket_table,
                        (int)prm.mode, G, tab, ctrl, (const Feature *)feat);
     if (screening) {
         const size_t jlds = (size_t)(G + 1) * 4 + (size_t)B * 4;
         (void)hipFuncSetAttribute((const void *)learned_screen_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)jlds);
-        hipLaunchKernelGGL(learned_screen_kernel, dim3(1), dim3(1024), jlds, st, (const double *)sample, L.S,
-                           (const Feature *)feat, (const float *)tab, G, B, n - n / 2, ctrl);
+        for (int second = 0; second < 2; ++second) {
+            hipLaunchKernelGGL(learned_screen_kernel, dim3(1), dim3(1024), jlds, st, (const double *)sample, L.S,
+                               (const Feature *)feat, (const float *)tab, G, B, n - n / 2, ctrl,
+                               (const double *)hv, second);
+            if (!second)
+                hipLaunchKernelGGL(learned_sample_table_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample,
+                                   L.S, (const Feature *)feat, G, tab, (const int64_t *)runs, ctrl, 1);
+        }
     }
     // Unless the stream is being captured, the host reads the decision once
     // and enqueues only the path that runs (the gated launches of the other
@@ -933,12 +1178,14 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
     launch_fill_u32(totals, 2 * (int64_t)B, 0u, st);
     hipLaunchKernelGGL(learned_count_kernel, dim3(cgrid), dim3(SW_NT), clds, st, (const double *)keys, nA,
                        (const Feature *)feat, (const float *)tab, G, B, 0, lbits, cntA, totals,
-                       (const unsigned *)ctrl);
+                       (const unsigned *)ctrl, (const double *)hv);
     hipLaunchKernelGGL(learned_count_kernel, dim3(cgrid), dim3(SW_NT), clds, st, (const double *)(keys + nA), nB,
                        (const Feature *)feat, (const float *)tab, G, B, 0, lbits, cntB, totals + B,
-                       (const unsigned *)ctrl);
+                       (const unsigned *)ctrl, (const double *)hv);
+    // (order codes of the bucket sorts: rank rows of both halves' segment lists)
     hipLaunchKernelGGL(learned_bucket_scan_kernel, dim3(1), dim3(1024), 0, st, (const unsigned *)totals, B, lbits,
-                       2, starts, offsets, dstart, L.limit, ctrl);
+                       2, starts, offsets, dstart, L.limit, ctrl, (const Feature *)feat, (const float *)tab, G,
+                       (const double *)hv, seglists + B, seglists + 4 * B);
     if (tr) trace_end(st);
 
     // 7. each half: two stable distribution passes (low digit into the half
@@ -952,28 +1199,28 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
                            (const unsigned *)(dstart + h * 128), (const unsigned *)ctrl);
         hipLaunchKernelGGL(learned_scatter_kernel, dim3(sgrid), dim3(SW_NT), slds, st,
                            (const double *)region, H, len, (const Feature *)feat, (const float *)tab, G, B, 0, lbits,
-                           (const unsigned *)cnt, (const unsigned *)ctrl);
+                           (const unsigned *)cnt, (const unsigned *)ctrl, (const double *)hv);
         hipLaunchKernelGGL(learned_count_kernel, dim3(cgrid), dim3(SW_NT), clds, st, (const double *)H, len,
                            (const Feature *)feat, (const float *)tab, G, B, lbits, hbits, cnt, (unsigned *)nullptr,
-                           (const unsigned *)ctrl);
+                           (const unsigned *)ctrl, (const double *)hv);
         hipLaunchKernelGGL(learned_tilescan_kernel, dim3(1u << hbits), dim3(1024), tslds, st, cnt, ntiles,
                            (const unsigned *)(dstart + h * 128 + 64), (const unsigned *)ctrl);
         hipLaunchKernelGGL(learned_scatter_kernel, dim3(sgrid), dim3(SW_NT), slds, st, (const double *)H,
                            region, len, (const Feature *)feat, (const float *)tab, G, B, lbits, hbits,
-                           (const unsigned *)cnt, (const unsigned *)ctrl);
+                           (const unsigned *)cnt, (const unsigned *)ctrl, (const double *)hv);
     };
     if (tr) trace_begin(TK_LEARN_BUCKET, st);
     distribute(keys + nA, nB, tB, cntB, 1);
     if (tr) trace_end(st);
     e = segsort_core_async(keys + nA, offsets + (B + 1), B, nB, H, segctrl + 64, seglists + 3 * B,
                            seglists + 4 * B, seglists + 5 * B, ws + L.off_segforest, L.segforest,
-                           ctrl + L_FALLBACK, 0u, st);
+                           ctrl + L_FALLBACK, 0u, st, true);
     if (e != hipSuccess) return e;
     if (tr) trace_begin(TK_LEARN_BUCKET, st);
     distribute(keys, nA, tA, cntA, 0);
     if (tr) trace_end(st);
     e = segsort_core_async(keys, offsets, B, nA, H, segctrl, seglists, seglists + B, seglists + 2 * B,
-                           ws + L.off_segforest, L.segforest, ctrl + L_FALLBACK, 0u, st);
+                           ws + L.off_segforest, L.segforest, ctrl + L_FALLBACK, 0u, st, true);
     if (e != hipSuccess) return e;
 
     // 8. merge: the sorted first half moves to the half buffer (logical
@@ -1056,7 +1303,8 @@ hipError_t learned_read_report(const char *ws, const LearnedPlan &L, LearnedRepo
     r->max_bucket = c[L_MAXB];
     r->big_buckets = c[L_BIGB];
     r->err = c[L_ERR];
-    r->feature = c[L_FEAT];
+    r->feature = c[L_FEAT] | (c[L_SAMPTAB] ? 2u : 0u);
+    r->heavy = c[L_FALLBACK] ? 0u : c[L_HEAVY];
     r->loss_first = loss[0];
     r->loss_last = loss[1];
     return hipSuccess;

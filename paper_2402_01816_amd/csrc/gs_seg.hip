@@ -47,7 +47,7 @@ __device__ __forceinline__ int seg_class(int64_t len, int logt)
 // overwrites it (ranks are never negative): sort it, nothing to do, reverse
 // it, or still to be decided from the order bits in its class word.
 constexpr int SEG_SORT = 0;
-constexpr int SEG_DONE = -1;
+constexpr int SEG_DONE = kSegDone;
 constexpr int SEG_REVERSE = -2;
 constexpr int SEG_CANDIDATE = -3;
 constexpr int64_t SEG_RANGE = 16384;                // keys per work-group of the range passes
@@ -479,7 +479,7 @@ static unsigned seg_groups(int64_t nseg)
 static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys, double *hbuf,
                               unsigned *ctrl, int *cls, int *rank, int *list, char *forest, const ForestPlan &fp,
                               const SegConfig &cfg, bool order_check, const unsigned *gate, unsigned run_if,
-                              hipStream_t st)
+                              hipStream_t st, bool preset_codes = false)
 {
     if (nseg <= 0) return hipSuccess;
     const Gate g{gate, run_if};
@@ -497,7 +497,7 @@ static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg
                                (const double *)keys, offsets, nseg, num_keys, cls, (const int *)rank, g);
     }
     hipLaunchKernelGGL(seg_classify_kernel, dim3(grid), dim3(256), 0, st, offsets, nseg, num_keys, logt, ctrl, cls,
-                       rank, order_check ? 1 : 0, g);
+                       rank, order_check || preset_codes ? 1 : 0, g);
     if (order_check && ranges > 0)
         hipLaunchKernelGGL((seg_reverse_kernel<double>), dim3(ranges), dim3(256), 0, st, keys, offsets, nseg,
                            num_keys, (const unsigned *)ctrl, (const int *)cls, (const int *)rank, g);
@@ -525,10 +525,11 @@ static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg
 
 hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys,
                               double *hbuf, unsigned *ctrl, int *cls, int *rank, int *list, char *forest,
-                              const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st)
+                              const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st,
+                              bool preset_codes)
 {
     return segsort_run(keys, offsets, nseg, num_keys, hbuf, ctrl, cls, rank, list, forest, fp,
-                       seg_default_config(), false, gate, run_if, st);
+                       seg_default_config(), false, gate, run_if, st, preset_codes);
 }
 
 hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan &p, char *ws,

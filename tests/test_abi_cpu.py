@@ -49,6 +49,25 @@ def test_workspace_sizes():
     assert g.gs_workspace_bytes_f64(-1) == g.SIZE_MAX
 
 
+@pytest.mark.parametrize("field,value,ok", [("mode", 2, True), ("mode", 3, False), ("num_buckets", 3, False),
+                                             ("num_buckets", 8192, False), ("knots", 1, False),
+                                             ("batch", 48, False), ("screen", 2, False)])
+def test_learned_params_checked(field, value, ok):
+    """Learned-path parameters are validated on the host: an invalid set has no
+    workspace size (SIZE_MAX) and the call returns GS_EINVAL before any device
+    work; mode 2 (the sample's CDF as the knot table) is valid."""
+    p = g.gs_learned_default_params()
+    setattr(p, field, value)
+    n = 1 << 20
+    b = g.gs_workspace_bytes_learned(n, p)
+    if ok:
+        assert 8 * (n // 2) <= b < g.SIZE_MAX
+    else:
+        assert b == g.SIZE_MAX
+        fake = ctypes.c_void_p(0x100000)
+        assert g.lib.gs_learned_sort(fake, n, ctypes.byref(p), fake, 1 << 30, None, None) == g.GS_EINVAL
+
+
 def _call_f64(keys, n, frac, ws, wsb):
     return g.lib.gs_sort_f64(keys, n, frac, ws, wsb, None, None)
 

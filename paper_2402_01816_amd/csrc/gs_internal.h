@@ -180,6 +180,7 @@ struct SegPlan {
     int64_t off_h;        // half buffer: floor(num_keys/2) doubles
     int64_t off_ctrl;     // 64 control words
     int64_t off_cls, off_rank, off_list;   // per-segment class, rank in class, class-ordered list
+    int64_t off_maps;     // order-check range maps (2 bytes per range of keys)
     int64_t off_forest;   // forest area for the long segments
     ForestPlan forest;
     int64_t bytes;

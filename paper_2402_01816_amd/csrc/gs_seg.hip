@@ -28,6 +28,8 @@ constexpr int SEG_MAX_POS = 16;                     // work-list positions (long
 // control words at the start of the segment workspace
 constexpr int C_INVALID = 0;
 constexpr int C_TICKET = 1;
+constexpr int C_CAND = 2;                           // some segment is an order candidate
+constexpr int C_REV = 3;                            // some segment is to be reversed
 constexpr int C_HIST = 16;                          // 16 class counters
 constexpr int C_NLONG = 48;                         // long segments handed to the forest
 
@@ -51,6 +53,9 @@ constexpr int SEG_DONE = kSegDone;
 constexpr int SEG_REVERSE = -2;
 constexpr int SEG_CANDIDATE = -3;
 constexpr int64_t SEG_RANGE = 16384;                // keys per work-group of the range passes
+constexpr int64_t SEG_WAVE_CHECK = 8192;            // pairs of a segment its wave checks itself
+
+__host__ __device__ inline int64_t seg_ranges(int64_t num_keys) { return (num_keys + SEG_RANGE - 1) / SEG_RANGE; }
 
 // Work-list order: the long class first, then the short classes from the
 // largest blocks down.
@@ -69,42 +74,54 @@ __device__ __forceinline__ int num_pos(int logt) { return logt - 2; }
 // Nothing moves in these passes (the offsets are validated only by the
 // classification; a segment with bad offsets reads nothing).
 //
-// 0a. One work-group per segment: a segment of at most 1024 pairs is checked
-// whole; a longer one on 1024 evenly spaced pairs, which rules out almost
-// every unsorted segment at once, and otherwise becomes a candidate whose
-// order bits (in cls[s]) the range pass completes.
+// 0a. One wave per segment reads its first SEG_WAVE_CHECK pairs in order,
+// 512 at a time, and stops as soon as the pairs seen rule out both orders
+// (for unsorted data, after the first 512).  A segment still possibly in
+// order past those pairs becomes a candidate: its order bits so far are in
+// cls[s], the range pass completes them, and cand[r] marks every range r of
+// SEG_RANGE keys that holds some of its remaining pairs (ctrl[C_CAND]: some
+// segment is a candidate).
 template <class KT>
 __global__ __launch_bounds__(256) void seg_order_sample_kernel(const typename KT::T *keys, const int64_t *offsets,
                                                                int64_t nseg, int64_t num_keys, int *cls,
-                                                               int *rank, Gate gate)
+                                                               int *rank, unsigned *ctrl, unsigned char *cand,
+                                                               Gate gate)
 {
-    constexpr int SAMPLE = 1024;
-    __shared__ unsigned s_bits;
     if (gate.closed()) return;
-    for (int64_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); s < nseg; s += waves) {
         const int64_t lo = offsets[s], hi = offsets[s + 1];
         if (lo < 0 || hi < lo || hi > num_keys) {
-            if (threadIdx.x == 0) rank[s] = SEG_SORT;
+            if (lane == 0) rank[s] = SEG_SORT;
             continue;
         }
         const int64_t pairs = hi - lo - 1;
-        if (threadIdx.x == 0) s_bits = 15u;
-        __syncthreads();
-        unsigned bits = 15u;
-        for (int j = threadIdx.x; j < SAMPLE; j += 256) {
-            if (j < pairs) {
-                const int64_t i = lo + (pairs <= SAMPLE ? (int64_t)j : (int64_t)j * pairs / SAMPLE);
-                bits &= order_bits<KT>(keys[i], keys[i + 1]);
+        const int64_t lim = pairs < SEG_WAVE_CHECK ? pairs : SEG_WAVE_CHECK;
+        unsigned all = 15u;
+        for (int64_t base = 0; base < lim; base += 512) {
+            unsigned bits = 15u;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int64_t j = base + r * 64 + lane;
+                if (j < lim) bits &= order_bits<KT>(keys[lo + j], keys[lo + j + 1]);
             }
+            // and of the four order bits over the wave
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (__ballot(((bits >> b) & 1u) == 0u) != 0ull) all &= ~(1u << b);
+            if (!order_decisive<KT>(all, true)) break;
         }
-        atomicAnd(&s_bits, bits);
-        __syncthreads();
-        const unsigned all = s_bits;
-        __syncthreads();                            // read before the next segment resets it
-        if (threadIdx.x == 0) {
-            int code;
-            if (pairs > SAMPLE && order_decisive<KT>(all, true)) code = SEG_CANDIDATE;
-            else code = (all & 1u) ? SEG_DONE : ((all & 2u) || ((all & 4u) && (all & 8u))) ? SEG_REVERSE : SEG_SORT;
+        int code;
+        if (pairs > lim && order_decisive<KT>(all, true)) {
+            code = SEG_CANDIDATE;
+            const int64_t r0 = (lo + lim) / SEG_RANGE, r1 = (hi - 2) / SEG_RANGE;   // ranges of pairs [lo+lim, hi-1)
+            for (int64_t r = r0 + lane; r <= r1; r += 64) cand[r] = 1;
+            if (lane == 0) atomicOr(ctrl + C_CAND, 1u);
+        } else {
+            code = (all & 1u) ? SEG_DONE : ((all & 2u) || ((all & 4u) && (all & 8u))) ? SEG_REVERSE : SEG_SORT;
+        }
+        if (lane == 0) {
             rank[s] = code;
             cls[s] = (int)all;
         }
@@ -133,16 +150,19 @@ __device__ __forceinline__ int64_t seg_skip_empty(const int64_t *offsets, int64_
     return next - 1 > s ? next - 1 : s;
 }
 
-// 0b. One work-group per SEG_RANGE keys of the array: every candidate
-// segment's pairs that start in the range are checked and their order bits
-// and-ed into cls[s], so a long segment is read by many work-groups at once.
+// 0b. One work-group per SEG_RANGE keys of the array: the pairs of every
+// candidate segment past the ones its wave checked that start in the range
+// are checked and their order bits and-ed into cls[s], so a long segment is
+// read by many work-groups at once.  A range that holds no such pairs
+// (cand[range] clear) has nothing to do.
 template <class KT>
 __global__ __launch_bounds__(256) void seg_order_range_kernel(const typename KT::T *keys, const int64_t *offsets,
                                                               int64_t nseg, int64_t num_keys, int *cls,
-                                                              const int *rank, Gate gate)
+                                                              const int *rank, const unsigned *ctrl,
+                                                              const unsigned char *cand, Gate gate)
 {
     __shared__ unsigned s_bits;
-    if (gate.closed()) return;
+    if (gate.closed() || !ctrl[C_CAND] || !cand[blockIdx.x]) return;
     const int64_t r0 = (int64_t)blockIdx.x * SEG_RANGE;
     const int64_t r1 = r0 + SEG_RANGE < num_keys ? r0 + SEG_RANGE : num_keys;
     for (int64_t s = seg_first_after(offsets, nseg, r0); s < nseg; ++s) {
@@ -153,13 +173,21 @@ __global__ __launch_bounds__(256) void seg_order_range_kernel(const typename KT:
             continue;
         }
         if (rank[s] != SEG_CANDIDATE || lo < 0 || hi < lo || hi > num_keys) continue;
-        const int64_t a = lo > r0 ? lo : r0;
+        const int64_t pairs = hi - lo - 1;
+        const int64_t from = lo + (pairs < SEG_WAVE_CHECK ? pairs : SEG_WAVE_CHECK);   // past the wave's pairs
+        const int64_t a = from > r0 ? from : r0;
         const int64_t b = hi - 1 < r1 ? hi - 1 : r1;  // pairs (i, i+1) with i in [a, b)
         if (a >= b) continue;
         if (threadIdx.x == 0) s_bits = 15u;
         __syncthreads();
         unsigned bits = 15u;
-        for (int64_t i = a + threadIdx.x; i < b; i += 256) bits &= order_bits<KT>(keys[i], keys[i + 1]);
+        for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += 4 * 256) {   // four pairs in flight per thread
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + r * 256;
+                if (i < b) bits &= order_bits<KT>(keys[i], keys[i + 1]);
+            }
+        }
         atomicAnd(&s_bits, bits);
         __syncthreads();
         if (threadIdx.x == 0 && s_bits != 15u) atomicAnd((unsigned *)cls + s, s_bits);
@@ -172,46 +200,69 @@ __global__ __launch_bounds__(256) void seg_order_range_kernel(const typename KT:
 // ---------------------------------------------------------------------------
 // With the order codes (order_codes != 0), a candidate's code is decided from
 // its order bits, and a segment already in order or to be reversed takes
-// class 0 (no sorting work) and keeps its code.
+// class 0 (no sorting work) and keeps its code (ctrl[C_REV] says some segment
+// is reversed, revmap[r] that range r holds pairs of one to swap; order codes
+// come with a revmap).  A segment's rank is its place among its class: counted per
+// work-group in LDS, then one device atomic per class and work-group.
 __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t *offsets, int64_t nseg,
                                                            int64_t num_keys, int logt, unsigned *ctrl,
-                                                           int *cls, int *rank, int order_codes, Gate gate)
+                                                           int *cls, int *rank, int order_codes,
+                                                           unsigned char *revmap, Gate gate)
 {
+    __shared__ unsigned s_cnt[SEG_MAX_POS], s_base[SEG_MAX_POS];
     if (gate.closed()) return;
+    if (threadIdx.x < SEG_MAX_POS) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nseg) return;
-    const int64_t lo = offsets[s], hi = offsets[s + 1];
-    if (lo < 0 || hi < lo || hi > num_keys) {
-        atomicOr(ctrl + C_INVALID, 1u);
-        cls[s] = 0;
-        return;
-    }
-    if (order_codes) {
-        int code = rank[s];
-        if (code == SEG_CANDIDATE) {
-            const unsigned b = (unsigned)cls[s];
-            code = (b & 1u) ? SEG_DONE : ((b & 2u) || ((b & 4u) && (b & 8u))) ? SEG_REVERSE : SEG_SORT;
-            rank[s] = code;
-        }
-        if (code != SEG_SORT) {
+    int c = -1;                                     // class of a segment that needs sorting
+    unsigned local = 0u;
+    if (s < nseg) {
+        const int64_t lo = offsets[s], hi = offsets[s + 1];
+        if (lo < 0 || hi < lo || hi > num_keys) {
+            atomicOr(ctrl + C_INVALID, 1u);
             cls[s] = 0;
-            return;
+        } else {
+            int code = SEG_SORT;
+            if (order_codes) {
+                code = rank[s];
+                if (code == SEG_CANDIDATE) {
+                    const unsigned b = (unsigned)cls[s];
+                    code = (b & 1u) ? SEG_DONE : ((b & 2u) || ((b & 4u) && (b & 8u))) ? SEG_REVERSE : SEG_SORT;
+                    rank[s] = code;
+                }
+                if (code == SEG_REVERSE && hi - lo > 1) {
+                    // the ranges that hold the lower half [lo, mid), whose pairs the reversal swaps
+                    atomicOr(ctrl + C_REV, 1u);
+                    const int64_t mid = lo + (hi - lo) / 2;
+                    for (int64_t r = lo / SEG_RANGE; r <= (mid - 1) / SEG_RANGE; ++r) revmap[r] = 1;
+                }
+            }
+            if (code != SEG_SORT) {
+                cls[s] = 0;
+            } else {
+                c = seg_class(hi - lo, logt);
+                cls[s] = c;
+                local = atomicAdd(&s_cnt[c], 1u);
+            }
         }
     }
-    const int c = seg_class(hi - lo, logt);
-    cls[s] = c;
-    rank[s] = (int)atomicAdd(ctrl + C_HIST + c, 1u);
+    __syncthreads();
+    if (threadIdx.x < SEG_MAX_POS && s_cnt[threadIdx.x])
+        s_base[threadIdx.x] = atomicAdd(ctrl + C_HIST + threadIdx.x, s_cnt[threadIdx.x]);
+    __syncthreads();
+    if (c >= 0) rank[s] = (int)(s_base[c] + local);
 }
 
 // Reverses, in place, every segment whose code says so, once every segment's
 // offsets passed the classification.  One work-group per SEG_RANGE keys
 // swaps the pairs (i, lo + hi - 1 - i) whose lower index i lies in its range.
+// Nothing to do in a range without such pairs (revmap[range] clear).
 template <class K>
 __global__ __launch_bounds__(256) void seg_reverse_kernel(K *keys, const int64_t *offsets, int64_t nseg,
                                                           int64_t num_keys, const unsigned *ctrl, const int *cls,
-                                                          const int *rank, Gate gate)
+                                                          const int *rank, const unsigned char *revmap, Gate gate)
 {
-    if (gate.closed() || ctrl[C_INVALID]) return;
+    if (gate.closed() || ctrl[C_INVALID] || !ctrl[C_REV] || !revmap[blockIdx.x]) return;
     const int64_t r0 = (int64_t)blockIdx.x * SEG_RANGE;
     const int64_t r1 = r0 + SEG_RANGE < num_keys ? r0 + SEG_RANGE : num_keys;
     for (int64_t s = seg_first_after(offsets, nseg, r0); s < nseg; ++s) {
@@ -225,11 +276,24 @@ __global__ __launch_bounds__(256) void seg_reverse_kernel(K *keys, const int64_t
         const int64_t mid = lo + (hi - lo) / 2;     // lower halves: [lo, mid)
         const int64_t a = lo > r0 ? lo : r0;
         const int64_t b = mid < r1 ? mid : r1;
-        for (int64_t i = a + threadIdx.x; i < b; i += 256) {
-            const int64_t j = lo + hi - 1 - i;
-            const K x = keys[i], y = keys[j];
-            keys[i] = y;
-            keys[j] = x;
+        for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += 4 * 256) {   // four swaps in flight per thread
+            K x[4], y[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + r * 256;
+                if (i < b) {
+                    x[r] = keys[i];
+                    y[r] = keys[lo + hi - 1 - i];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + r * 256;
+                if (i < b) {
+                    keys[i] = y[r];
+                    keys[lo + hi - 1 - i] = x[r];
+                }
+            }
         }
     }
 }
@@ -436,7 +500,8 @@ SegPlan plan_seg(int64_t num_keys, int64_t nseg, const SegConfig &cfg)
     p.off_cls = p.off_ctrl + 256;
     p.off_rank = p.off_cls + align256s(nseg * 4);
     p.off_list = p.off_rank + align256s(nseg * 4);
-    p.off_forest = p.off_list + align256s(nseg * 4);
+    p.off_maps = p.off_list + align256s(nseg * 4);
+    p.off_forest = p.off_maps + align256s(2 * seg_ranges(num_keys));
     p.forest = plan_forest_f64(num_keys, num_keys, max_long(num_keys, nseg, p.tile), cfg.merge_ipt);
     p.bytes = p.off_forest + p.forest.bytes;
     return p;
@@ -476,10 +541,12 @@ static unsigned seg_groups(int64_t nseg)
     return (unsigned)(nseg < 65536 ? nseg : 65536);
 }
 
+// maps: 2 x seg_ranges(num_keys) bytes (candidate and reversal range maps),
+// needed with order_check only.
 static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys, double *hbuf,
-                              unsigned *ctrl, int *cls, int *rank, int *list, char *forest, const ForestPlan &fp,
-                              const SegConfig &cfg, bool order_check, const unsigned *gate, unsigned run_if,
-                              hipStream_t st, bool preset_codes = false)
+                              unsigned *ctrl, int *cls, int *rank, int *list, unsigned char *maps, char *forest,
+                              const ForestPlan &fp, const SegConfig &cfg, bool order_check, const unsigned *gate,
+                              unsigned run_if, hipStream_t st, bool preset_codes = false)
 {
     if (nseg <= 0) return hipSuccess;
     const Gate g{gate, run_if};
@@ -489,18 +556,22 @@ static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg
     launch_fill_u32(ctrl, 64, 0u, st);
     const unsigned grid = (unsigned)((nseg + 255) / 256);
     const unsigned ranges = (unsigned)((num_keys + SEG_RANGE - 1) / SEG_RANGE);
+    unsigned char *cand = maps, *revmap = maps ? maps + ranges : nullptr;
     if (order_check) {
-        hipLaunchKernelGGL((seg_order_sample_kernel<KeyF64>), dim3(seg_groups(nseg)), dim3(256), 0, st,
-                           (const double *)keys, offsets, nseg, num_keys, cls, rank, g);
+        if (ranges > 0) launch_fill_u32((unsigned *)maps, (2 * (int64_t)ranges + 3) / 4, 0u, st);
+        hipLaunchKernelGGL((seg_order_sample_kernel<KeyF64>), dim3(seg_groups((nseg + 3) / 4)), dim3(256), 0, st,
+                           (const double *)keys, offsets, nseg, num_keys, cls, rank, ctrl, cand, g);
         if (ranges > 0)
             hipLaunchKernelGGL((seg_order_range_kernel<KeyF64>), dim3(ranges), dim3(256), 0, st,
-                               (const double *)keys, offsets, nseg, num_keys, cls, (const int *)rank, g);
+                               (const double *)keys, offsets, nseg, num_keys, cls, (const int *)rank,
+                               (const unsigned *)ctrl, (const unsigned char *)cand, g);
     }
     hipLaunchKernelGGL(seg_classify_kernel, dim3(grid), dim3(256), 0, st, offsets, nseg, num_keys, logt, ctrl, cls,
-                       rank, order_check || preset_codes ? 1 : 0, g);
+                       rank, order_check || preset_codes ? 1 : 0, revmap, g);
     if (order_check && ranges > 0)
         hipLaunchKernelGGL((seg_reverse_kernel<double>), dim3(ranges), dim3(256), 0, st, keys, offsets, nseg,
-                           num_keys, (const unsigned *)ctrl, (const int *)cls, (const int *)rank, g);
+                           num_keys, (const unsigned *)ctrl, (const int *)cls, (const int *)rank,
+                           (const unsigned char *)revmap, g);
     hipLaunchKernelGGL(seg_scatter_kernel, dim3(grid), dim3(256), 0, st, nseg, logt, (const unsigned *)ctrl,
                        (const int *)cls, (const int *)rank, list, g);
     Prob *probs = (Prob *)(forest + fp.off_probs);
@@ -528,7 +599,7 @@ hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg
                               const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st,
                               bool preset_codes)
 {
-    return segsort_run(keys, offsets, nseg, num_keys, hbuf, ctrl, cls, rank, list, forest, fp,
+    return segsort_run(keys, offsets, nseg, num_keys, hbuf, ctrl, cls, rank, list, nullptr, forest, fp,
                        seg_default_config(), false, gate, run_if, st, preset_codes);
 }
 
@@ -543,7 +614,7 @@ hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan
     if (e != hipSuccess) return e;
     e = segsort_run(keys, offsets, p.nseg, p.num_keys, (double *)(ws + p.off_h), (unsigned *)(ws + p.off_ctrl),
                     (int *)(ws + p.off_cls), (int *)(ws + p.off_rank), (int *)(ws + p.off_list),
-                    ws + p.off_forest, p.forest, p.cfg, true, nullptr, 0u, st);
+                    (unsigned char *)(ws + p.off_maps), ws + p.off_forest, p.forest, p.cfg, true, nullptr, 0u, st);
     if (e != hipSuccess) return e;
     ew.add((unsigned *)(ws + p.off_ctrl), DEVERR_OFFSETS);
     return err_words_end(ew, st);

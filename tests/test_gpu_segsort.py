@@ -159,7 +159,7 @@ def test_segsort_invalid_offsets_reported(gs, bad):
     assert np.array_equal(bits(t), bits(x))
 
 
-ORDER_LENGTHS = [2, 3, 17, 1000, 4097, 20000, 70001]
+ORDER_LENGTHS = [2, 3, 17, 1000, 4097, 8193, 8194, 20000, 70001]
 
 
 def _ordered_segment(kind, m, rng):
@@ -200,7 +200,9 @@ def test_segsort_ordered_segments(gs, orc, kind):
     """Segments already in order are left alone and reversed ones reversed
     (the order check's shortcut); near misses in the last pair, signed-zero
     ties and tied NaNs must still be sorted.  Lengths span the short classes
-    and the forest; a uniform segment sits between every two."""
+    and the forest, and 8193 / 8194 keys put the last pair at the end of the
+    pairs a segment's wave checks (8192) and just past it, where the range
+    pass takes over; a uniform segment sits between every two."""
     announce("segsort ordered", kind)
     rng = np.random.default_rng(11)
     parts, lens = [], []

@@ -139,15 +139,21 @@ struct Forest {
     uint8_t *dirs;
     uint8_t *modes;
     // Run samples (the single Frogsort1 tree only, else null): for every run
-    // a round produces, one key per stretch of samp_tile ranks at slot
-    // (node * stretches per node + stretch): the stretch's first key for a
-    // left child (the run its parent's merge takes first), its last key for a
-    // right child.  The next round's partition reads them before its merge
-    // overwrites them with its own.  The leaves have samp_leaf_tiles
-    // stretches each.
+    // a round produces, one key per stretch of samp_tile ranks (kSampPerTile
+    // stretches per merge tile) at slot (node * stretches per node +
+    // stretch): the stretch's first key for a left child (the run its
+    // parent's merge takes first), its last key for a right child.  The next
+    // round's partition reads them before its merge overwrites them with its
+    // own.  The leaves have samp_leaf_tiles stretches each.
     void *samp;
     int samp_tile, samp_leaf_tiles;
 };
+
+// Run-sample stretches per merge tile (a power of two).
+#ifndef GS_SAMP_PER_TILE
+#define GS_SAMP_PER_TILE 1
+#endif
+constexpr int kSampPerTile = GS_SAMP_PER_TILE;
 
 GS_HD int64_t forest_nodes(const Forest &F, const Prob &P, int round)
 {

@@ -592,19 +592,18 @@ __global__ __launch_bounds__(1024) void learned_table_kernel(const float *raw, c
 // added into totals[] with integer atomics at the end (the totals do not
 // depend on the order of the additions).
 constexpr int SW_NT = 256;
-// work-groups of a distribution pass (each walks tiles with a stride of the grid)
-#ifndef GS_LEARN_SGRID
-#define GS_LEARN_SGRID 1024
-#endif
 // work-groups of a counting pass
 #ifndef GS_LEARN_CGRID
 #define GS_LEARN_CGRID 1024
 #endif
+// keys per thread of a tile: 14 (3584-key tiles) lets the distribution pass's
+// knot table and staged tile fit three work-groups into a compute unit's LDS
 #ifndef GS_LEARN_ROUNDS
-#define GS_LEARN_ROUNDS 16
+#define GS_LEARN_ROUNDS 14
 #endif
 constexpr int SW_ROUNDS = GS_LEARN_ROUNDS;
-constexpr int SW_TILE = SW_NT * SW_ROUNDS;           // 4096 keys by default
+static_assert(SW_ROUNDS % 2 == 0, "the counting pass computes buckets in two halves of the rounds");
+constexpr int SW_TILE = SW_NT * SW_ROUNDS;           // 3584 keys by default
 // waves per SIMD the distribution pass's registers are sized for: as many
 // work-groups as its LDS (knot table + staged tile) lets a compute unit hold
 #ifndef GS_LEARN_SCATTER_WAVES
@@ -987,6 +986,25 @@ __global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter
     }
 }
 
+// Work-groups of a distribution pass: as many as the device holds at once
+// with `slds` bytes of dynamic LDS each (each walks tiles with a stride of the
+// grid, so none waits for a slot behind the others), cached per device.
+static int64_t scatter_groups(size_t slds)
+{
+    static int64_t cache[16] = {};
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+    const int slot = dev < 16 ? dev : 15;
+    if (dev < 16 && cache[slot] > 0) return cache[slot];
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, learned_scatter_kernel, SW_NT, slds) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    const int64_t g = (int64_t)cus * per_cu;
+    if (dev < 16) cache[slot] = g;
+    return g;
+}
+
 // gated copy (the sorted first half into the half buffer for the final merge)
 __global__ __launch_bounds__(256) void learned_copy_kernel(const double *src, double *dst, int64_t n,
                                                            const unsigned *ctrl)
@@ -1192,9 +1210,10 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
     //    buffer, high digit back), which leave its keys grouped by bucket in
     //    input order in place; then every bucket sorted, with the half buffer
     //    as frog buffer.  Second half first, then the first.
+    const int64_t sres = scatter_groups(slds);
     auto distribute = [&](double *region, int64_t len, int64_t ntiles, unsigned *cnt, int h) {
         if (ntiles == 0) return;
-        const unsigned sgrid = (unsigned)(ntiles < GS_LEARN_SGRID ? ntiles : GS_LEARN_SGRID);
+        const unsigned sgrid = (unsigned)(ntiles < sres ? ntiles : sres);
         hipLaunchKernelGGL(learned_tilescan_kernel, dim3(1u << lbits), dim3(1024), tslds, st, cnt, ntiles,
                            (const unsigned *)(dstart + h * 128), (const unsigned *)ctrl);
         hipLaunchKernelGGL(learned_scatter_kernel, dim3(sgrid), dim3(SW_NT), slds, st,

@@ -551,13 +551,14 @@ __global__ __launch_bounds__(256) void partition_kernel(typename KT::T *Dk, type
         // (written by the previous round, node 2 node and 2 node + 1 at the
         // depth below) bracket the split
         const bool sampled = F.samp && !F.probs && !F.use_f2 && kind == NODE_MERGE && dL == DIR_ASC &&
-                             dR == DIR_ASC && kk < nn && F.samp_tile == TILE;
+                             dR == DIR_ASC && kk < nn && F.samp_tile * kSampPerTile == TILE;
         if (v.copy) {
             splits[w] = kk < v.a.n ? kk : v.a.n;
         } else if (sampled) {
-            const int64_t ct = round == 1 ? F.samp_leaf_tiles : forest_tpn<TILE>(F, P, round - 1);
+            const int64_t ct = round == 1 ? F.samp_leaf_tiles : forest_tpn<TILE>(F, P, round - 1) * kSampPerTile;
             const K *sb0 = reinterpret_cast<const K *>(F.samp);
-            splits[w] = sampled_split<KT>(keys, v, kk, sb0 + (2 * node) * ct, sb0 + (2 * node + 1) * ct, TILE);
+            splits[w] = sampled_split<KT>(keys, v, kk, sb0 + (2 * node) * ct, sb0 + (2 * node + 1) * ct,
+                                          F.samp_tile);
         } else {
             splits[w] = view_split<KT>(keys, v, kk);
         }
@@ -900,16 +901,23 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
             nxt_p = prob_of(nxt.prob);
             if (!(nxt.flags & TF_SKIP)) issue_loads(nxt, nxt_p);
         }
-        // the run sample of this tile's outputs (first or last key), for the
-        // next round's partition: from the register of the thread that merged
-        // it (a whole tile), from LDS (a short tile or a concatenation), or
-        // from memory (outputs already in their slots)
-        K *const samp_p = F.samp && cur.prob >= 0 && out_cnt > 0 ? reinterpret_cast<K *>(F.samp) + (cur.prob >> 1)
-                                                                 : nullptr;
-        const int samp_i = cur.prob & 1 ? out_cnt - 1 : 0;
-        if (skip && samp_p && tid == 0) {
+        // the run samples of this tile's outputs (first or last key of each
+        // stretch of samp_tile ranks), for the next round's partition: from
+        // the registers of the threads that merged them (a whole tile), from
+        // LDS (a short tile or a concatenation), or from memory (outputs
+        // already in their slots)
+        K *const samp_p = F.samp && cur.prob >= 0 && out_cnt > 0
+                              ? reinterpret_cast<K *>(F.samp) + (int64_t)(cur.prob >> 1) * kSampPerTile
+                              : nullptr;
+        const bool samp_last = cur.prob & 1;
+        const int samp_n = (out_cnt + F.samp_tile - 1) / F.samp_tile;     // stretches of this tile
+        // rank of stretch s's sample (s < samp_n)
+        auto samp_rank = [&](int s) {
+            return samp_last ? min((s + 1) * F.samp_tile, out_cnt) - 1 : s * F.samp_tile;
+        };
+        if (skip && samp_p && tid < samp_n) {
             const Space<K> ks{Dk + cur_p.doff, Hk + cur_p.hoff, cur_p.n};
-            *samp_p = *ks.at(out_o + samp_i);
+            samp_p[tid] = *ks.at(out_o + samp_rank(tid));
         }
         if (!skip) {
             my_moved += (unsigned)cur.cnt;
@@ -925,11 +933,15 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
             }
             lds_barrier();
             if (samp_p) {
-                const bool in_regs = !copy && (samp_i == 0 || out_cnt == TILE);
+                // a whole merged tile: the thread of rank s T holds it in k[0],
+                // the one of rank (s + 1) T - 1 in k[IPT - 1]
+                constexpr int TPS = NT / kSampPerTile;                      // threads per stretch
+                const bool in_regs = !copy && out_cnt == TILE;
                 if (in_regs) {
-                    if (samp_i == 0 ? tid == 0 : tid == NT - 1) *samp_p = samp_i == 0 ? k[0] : k[IPT - 1];
-                } else if (tid == 0) {
-                    *samp_p = sk[lpad(samp_i)];
+                    if (samp_last ? tid % TPS == TPS - 1 : tid % TPS == 0)
+                        samp_p[tid / TPS] = samp_last ? k[IPT - 1] : k[0];
+                } else if (tid < samp_n) {
+                    samp_p[tid] = sk[lpad(samp_rank(tid))];
                 }
             }
 #pragma unroll
@@ -1082,9 +1094,10 @@ ForestPlan forest_plan_one(int64_t n)
     }
     // Squidsort directions of every node (heap order, 2^(D+1) - 1 of them);
     // run samples of the leaves and of every merge round
-    const int64_t leaf_slots = leaves * ((LEAF + TILE - 1) / TILE);
+    constexpr int64_t ST = TILE / kSampPerTile;                  // ranks per sample stretch
+    const int64_t leaf_slots = leaves * ((LEAF + ST - 1) / ST), merge_slots = mt * kSampPerTile;
     return layout_forest(0, D, mt, mt > leaves ? mt : leaves, ms, LEAF, TILE, (int64_t)2 << D,
-                         mt > leaf_slots ? mt : leaf_slots);
+                         merge_slots > leaf_slots ? merge_slots : leaf_slots);
 }
 
 // Capacity for any set of at most max_probs problems of at most max_len keys
@@ -1188,8 +1201,8 @@ static hipError_t run_forest(typename KT::T *Dk, typename KT::T *Hk, V *Dv, V *H
         F.modes = (uint8_t *)(fw + fp.off_modes);
         if (fp.samp_slots > 0 && fp.tile == TILE) {
             F.samp = fw + fp.off_samp;
-            F.samp_tile = TILE;
-            F.samp_leaf_tiles = (int)((fp.leaf + TILE - 1) / TILE);
+            F.samp_tile = TILE / kSampPerTile;
+            F.samp_leaf_tiles = (int)((fp.leaf + F.samp_tile - 1) / F.samp_tile);
         }
     }
     if (table) {

@@ -103,10 +103,10 @@ typedef struct {
 typedef struct {
     uint32_t num_buckets;    /* buckets, power of two in [2, 4096]; default 4096 */
     uint32_t sample_size;    /* keys sampled for training, in [1024, 2^24]; default 65536 */
-    uint32_t train_steps;    /* Adam steps; default 25 */
+    uint32_t train_steps;    /* Adam steps; default 8 */
     uint32_t batch;          /* minibatch per step, multiple of 32 in [32, 8192]; default 2048 */
     uint32_t knots;          /* knots of the tabulated model, in [2, 16384]; default 4096 */
-    float    lr;             /* Adam learning rate; default 2e-2 */
+    float    lr;             /* Adam learning rate; default 4e-2 */
     uint64_t seed;           /* sample positions, weight init and minibatches */
     uint32_t mode;           /* 0 = trained network, 1 = untrained linear CDF (table[i] = i/knots),
                                 2 = the sorted sample's CDF at the knots (no network) */

@@ -750,10 +750,10 @@ void gs_learned_default_params(gs_learned_params *p)
     memset(p, 0, sizeof *p);
     p->num_buckets = 4096;
     p->sample_size = 65536;
-    p->train_steps = 25;
+    p->train_steps = 8;
     p->batch = 2048;
     p->knots = 4096;
-    p->lr = 2e-2f;
+    p->lr = 4e-2f;
     p->seed = 0x5eed;
     p->mode = 0;
 }

@@ -293,38 +293,38 @@ __global__ __launch_bounds__(1024) void learned_prep_kernel(const double *xs, in
             }
         }
         __syncthreads();
+        const int nc = s_cnt < (unsigned)kHeavyCand ? (int)s_cnt : kHeavyCand;
+        const int hmax = kHeavyMax < B / 8 ? kHeavyMax : B / 8;
+        const int hc = nc < hmax ? nc : hmax;
+        // the hmax longest runs: candidate c's place among all by length
+        // (longer first, ties by the smaller value: the choice does not depend
+        // on the order the candidates were recorded in), then the chosen ones'
+        // place by value (candidates hold distinct values)
+        __shared__ int s_pick[kHeavyCand];
+        __shared__ int64_t s_rest;
+        if (threadIdx.x == 0) s_rest = 0;
+        __syncthreads();
+        for (int c = threadIdx.x; c < nc; c += 1024) {
+            runs[2 * c] = s_start[c];
+            runs[2 * c + 1] = s_len[c];
+            int place = 0;
+            for (int e = 0; e < nc; ++e)
+                place += (s_len[e] > s_len[c] || (s_len[e] == s_len[c] && s_val[e] < s_val[c])) ? 1 : 0;
+            s_pick[c] = place;
+            if (place >= hc) atomicMax((unsigned long long *)&s_rest, (unsigned long long)s_len[c]);
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < nc; c += 1024) {
+            if (s_pick[c] >= hc) continue;
+            int place = 0;
+            for (int e = 0; e < nc; ++e) place += (s_pick[e] < hc && s_val[e] < s_val[c]) ? 1 : 0;
+            hv[place] = s_val[c];
+        }
+        for (int c = hc + (int)threadIdx.x; c < kHeavySlots; c += 1024) hv[c] = __builtin_nan("");
         if (threadIdx.x == 0) {
-            const int nc = s_cnt < (unsigned)kHeavyCand ? (int)s_cnt : kHeavyCand;
-            for (int c = 0; c < nc; ++c) {
-                runs[2 * c] = s_start[c];
-                runs[2 * c + 1] = s_len[c];
-            }
             ctrl[L_RUNS] = (unsigned)nc;
-            const int hmax = kHeavyMax < B / 8 ? kHeavyMax : B / 8;
-            // the hmax longest runs (selection), then the remaining ones screened
-            int hc = 0;
-            for (; hc < hmax && hc < nc; ++hc) {
-                int best = hc;
-                for (int c = hc + 1; c < nc; ++c)
-                    if (s_len[c] > s_len[best]) best = c;
-                const int64_t tl = s_len[hc];
-                const double tv = s_val[hc];
-                s_len[hc] = s_len[best];
-                s_val[hc] = s_val[best];
-                s_len[best] = tl;
-                s_val[best] = tv;
-            }
-            int64_t rest = 0;                           // longest run left out
-            for (int c = hc; c < nc; ++c) rest = s_len[c] > rest ? s_len[c] : rest;
+            const int64_t rest = s_rest;                // longest run left out
             const bool lost = s_cnt > (unsigned)kHeavyCand;   // candidates not recorded
-            // ascending values of the chosen ones
-            for (int c = 1; c < hc; ++c)
-                for (int d = c; d > 0 && s_val[d] < s_val[d - 1]; --d) {
-                    const double t = s_val[d];
-                    s_val[d] = s_val[d - 1];
-                    s_val[d - 1] = t;
-                }
-            for (int c = 0; c < kHeavySlots; ++c) hv[c] = c < hc ? s_val[c] : __builtin_nan("");
             ctrl[L_HEAVY] = (unsigned)hc;
             if (screen_half > 0 && (s_fail || lost || rest >= m)) {
                 const int64_t worst = rest > m ? rest : m;
@@ -461,22 +461,37 @@ __global__ __launch_bounds__(256) void learned_targets_kernel(const double *xs, 
 // ---------------------------------------------------------------------------
 // The sample's CDF at the knots: table[i] is the share of the sample keys
 // whose knot coordinate lies below i, counted without NaNs and without the
-// recorded runs of equal keys (as the density targets), so the keys of every
-// knot interval spread evenly over the table's share of buckets.  Monotone by
+// heavy values' runs (their keys have buckets of their own), so the keys of
+// every knot interval spread evenly over the table's share of buckets.  The
+// other long runs count: each keeps the table's room for its keys, which
+// stops two of them close in value from sharing a bucket.  Monotone by
 // construction (counts of a sorted sample below rising bounds).  With
 // `rescue` the kernel runs only if the screening rejected the trained table.
 // Sets ctrl[L_SAMPTAB].
 __global__ __launch_bounds__(1024) void learned_sample_table_kernel(const double *xs, int64_t S, const Feature *feat,
                                                                     int G, float *tab, const int64_t *runs,
-                                                                    unsigned *ctrl, int rescue)
+                                                                    const double *hv, unsigned *ctrl, int rescue)
 {
-    __shared__ int64_t s_run[2 * kHeavyCand];
+    __shared__ int64_t s_run[2 * kHeavyCand];     // the heavy values' runs: start, length
     __shared__ int64_t s_nn;
+    __shared__ unsigned s_nh;
     if (ctrl[L_FALLBACK] || (rescue && !ctrl[L_RESCUE])) return;
     const int tid = threadIdx.x;
     const unsigned nrec = ctrl[L_RUNS];
-    const int nr = nrec < (unsigned)kHeavyCand ? (int)nrec : kHeavyCand;
-    for (int k = tid; k < 2 * nr; k += 1024) s_run[k] = runs[k];
+    const int nrall = nrec < (unsigned)kHeavyCand ? (int)nrec : kHeavyCand;
+    const int hc = (int)ctrl[L_HEAVY];
+    if (tid == 0) s_nh = 0u;
+    __syncthreads();
+    for (int k = tid; k < nrall; k += 1024) {
+        const int64_t st = runs[2 * k];
+        bool heavy = false;
+        for (int h = 0; h < hc; ++h) heavy = heavy || hv[h] == xs[st];
+        if (heavy) {
+            const unsigned slot = atomicAdd(&s_nh, 1u);
+            s_run[2 * slot] = st;
+            s_run[2 * slot + 1] = runs[2 * k + 1];
+        }
+    }
     if (tid == 0) {
         int64_t a = 0, b = S;                      // first NaN (NaNs sort last)
         while (a < b) {
@@ -489,7 +504,8 @@ __global__ __launch_bounds__(1024) void learned_sample_table_kernel(const double
     __syncthreads();
     const Feature F = *feat;
     const int64_t nn = s_nn;
-    auto outside = [&](int64_t j) {               // keys of [0, j) in no run
+    const int nr = (int)s_nh;
+    auto outside = [&](int64_t j) {               // keys of [0, j) in no heavy value's run
         int64_t c = j;
         for (int k = 0; k < nr; ++k) {
             const int64_t st = s_run[2 * k], en = st + s_run[2 * k + 1];
@@ -1138,7 +1154,7 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
     if (tr) trace_end(st);
     if (prm.mode == 2 && !prm.test_bucket_table)
         hipLaunchKernelGGL(learned_sample_table_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample, L.S,
-                           (const Feature *)feat, G, tab, (const int64_t *)runs, ctrl, 0);
+                           (const Feature *)feat, G, tab, (const int64_t *)runs, (const double *)hv, ctrl, 0);
     hipLaunchKernelGGL(learned_table_kernel, dim3(1), dim3(1024), 0, st, (const float *)raw, prm.test_bucket_table,
                        (int)prm.mode, G, tab, ctrl, (const Feature *)feat);
     if (screening) {
@@ -1151,7 +1167,8 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
                                (const double *)hv, second);
             if (!second)
                 hipLaunchKernelGGL(learned_sample_table_kernel, dim3(1), dim3(1024), 0, st, (const double *)sample,
-                                   L.S, (const Feature *)feat, G, tab, (const int64_t *)runs, ctrl, 1);
+                                   L.S, (const Feature *)feat, G, tab, (const int64_t *)runs, (const double *)hv,
+                                   ctrl, 1);
         }
     }
     // Unless the stream is being captured, the host reads the decision once

@@ -129,11 +129,15 @@ def test_learned_sort_parity(gs, orc, pattern):
     t, rep = _learned(gs, x, sample_size=16384)
     assert rep["fallback"] == 0
     assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
-    assert rep["train_loss_last"] < rep["train_loss_first"]
     if pattern == "zipf_ints":
-        # the most frequent integers fill long runs of the sorted sample
+        # the most frequent integers fill long runs of the sorted sample; with
+        # the runs left out of the density targets the rest is nearly flat
+        # (the untrained network's zero output already fits it: no spikes)
         assert rep["heavy_values"] == 31
-    elif pattern == "lognormal":
+        assert rep["train_loss_last"] < 1.0
+    else:
+        assert rep["train_loss_last"] < rep["train_loss_first"]
+    if pattern == "lognormal":
         assert rep["heavy_values"] == 0
 
 

@@ -306,9 +306,12 @@ const char *gs_version(void);
 
 /* ---- measurement ---------------------------------------------------------- */
 
-/* Launch tracing for profiling tools: while enabled on the calling thread,
-   every kernel launch made by the calls above is bracketed by HIP events on
-   the call's stream.  Returns the previous setting. */
+/* Launch tracing for profiling tools: while enabled on the calling thread
+   (on = 1), every kernel launch made by the calls above is bracketed by HIP
+   events on the call's stream; with on = 2 only the merge launches are (the
+   fewest events for timing the dominant kernel inside a timed run).  The
+   events skip the system-scope fence, so they do not write back the caches
+   between the launches they bracket.  Returns the previous setting. */
 int gs_trace_enable(int on);
 /* Waits for the recorded events, writes up to `max` records (host arrays):
    kinds[i] (0 fill, 1 leaf sort, 2 partition, 3 merge, 4 other, 5 dependency windows) and ms[i]

@@ -179,23 +179,33 @@ struct TraceRec {
     int kind;
     hipEvent_t a, b;
 };
-thread_local bool g_trace = false;
+thread_local int g_trace = 0;          // 0 off, 1 every launch, 2 merge launches only
+thread_local bool g_open = false;      // a record waits for its end event
 thread_local std::vector<TraceRec> g_recs;
 
 }  // namespace
 
 namespace gs {
-bool trace_on() { return g_trace; }
+bool trace_on() { return g_trace != 0; }
+// Timing-only events: without the system-scope fence an event record would
+// write back and invalidate the caches between the launches it brackets,
+// slowing the work it measures.
 void trace_begin(int kind, hipStream_t st)
 {
+    g_open = false;
+    if (g_trace == 2 && kind != TK_MERGE) return;
     TraceRec r{kind, nullptr, nullptr};
-    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&r.a, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&r.b, hipEventDisableSystemFence) != hipSuccess)
+        return;
     (void)hipEventRecord(r.a, st);
     g_recs.push_back(r);
+    g_open = true;
 }
 void trace_end(hipStream_t st)
 {
-    if (!g_recs.empty()) (void)hipEventRecord(g_recs.back().b, st);
+    if (g_open && !g_recs.empty()) (void)hipEventRecord(g_recs.back().b, st);
+    g_open = false;
 }
 }  // namespace gs
 
@@ -203,8 +213,8 @@ extern "C" {
 
 int gs_trace_enable(int on)
 {
-    int was = g_trace ? 1 : 0;
-    g_trace = on != 0;
+    const int was = g_trace;
+    g_trace = on == 2 ? 2 : on != 0 ? 1 : 0;
     return was;
 }
 

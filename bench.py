@@ -447,20 +447,24 @@ def main():
         rep = gs.gs_sort_f64(buf, frac, workspace=ws, report=True, algo=algo)
     del buf
 
-    # empirical ceiling: a device-to-device copy moves the same 16n bytes as
-    # one merge pass (8n read + 8n write)
+    # empirical ceilings: a copy moves the same 16n bytes as one merge pass
+    # (8n read + 8n write): the library's streaming copy kernel and the
+    # runtime's device-to-device copy
     dst = torch.empty_like(pristine)
-    for _ in range(2):
-        dst.copy_(pristine)
-    c0 = torch.cuda.Event(enable_timing=True)
-    c1 = torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
-    for _ in range(5):
-        dst.copy_(pristine)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_ms = c0.elapsed_time(c1) / 5
-    copy_gbs = 16.0 * n / (copy_ms * 1e-3) / 1e9
+
+    def copy_rate(fn):
+        for _ in range(2):
+            fn()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(5):
+            fn()
+        c1.record(stream)
+        torch.cuda.synchronize()
+        return 16.0 * n / (c0.elapsed_time(c1) / 5 * 1e-3) / 1e9
+    copy_gbs = copy_rate(lambda: gs.gs_copy_f64(pristine, dst))
+    runtime_copy_gbs = copy_rate(lambda: dst.copy_(pristine))
     del dst
 
     log(f"preparing {args.steps} input copies")
@@ -557,6 +561,8 @@ def main():
                      "bytes_per_launch": merge_bytes, "avg_launch_ms": round(merge_avg, 5)},
         "copy_ceiling_gbs": round(copy_gbs, 1),
         "merge_frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None,
+        "runtime_copy_gbs": round(runtime_copy_gbs, 1),
+        "merge_frac_of_runtime_copy": round(achieved / runtime_copy_gbs, 4) if runtime_copy_gbs > 0 else None,
         "ram_fraction": round(ram, 5),
         "t_footprint_ram_s": round(ram * ms_per_step * 1e-3, 6),
         "whole_sort_hbm_frac": round(whole_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -313,6 +313,12 @@ const char *gs_version(void);
    events skip the system-scope fence, so they do not write back the caches
    between the launches they bracket.  Returns the previous setting. */
 int gs_trace_enable(int on);
+/* Streaming copy of n float64 values from src to dst (device, not
+   overlapping), asynchronous on the stream: the empirical bandwidth ceiling a
+   sorting pass is measured against (a pass reads and writes every key once;
+   16-byte non-temporal loads and stores when both pointers are 16-byte
+   aligned).  GS_EINVAL for n < 0 or a NULL pointer with n > 0. */
+gs_status gs_copy_f64(const double *src, double *dst, int64_t n, void *hip_stream);
 /* Waits for the recorded events, writes up to `max` records (host arrays):
    kinds[i] (0 fill, 1 leaf sort, 2 partition, 3 merge, 4 other, 5 dependency windows) and ms[i]
    (launch duration), clears the record list and returns the count written. */

@@ -152,6 +152,7 @@ _OPTIONAL = {
     "gs_device_errors": ([ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int], ctypes.c_int),
     "gs_test_fail_waits": ([ctypes.c_int], ctypes.c_int),
     "gs_trace_enable": ([ctypes.c_int], ctypes.c_int),
+    "gs_copy_f64": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p], ctypes.c_int),
     "gs_trace_read": ([ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), ctypes.c_int],
                       ctypes.c_int),
 }
@@ -485,6 +486,17 @@ def gs_learned_sort(keys, params: GsLearnedParams | None = None, workspace=None,
 # ---------------------------------------------------------------------------
 GS_DEVERR_WAIT = 1
 GS_DEVERR_OFFSETS = 2
+
+
+def gs_copy_f64(src, dst, stream=None):
+    """Streaming copy of a float64 device tensor into another of the same size
+    (the bandwidth ceiling a sorting pass is measured against)."""
+    torch = _torch()
+    sp = _dev_ptr(src, "src", (torch.float64,))
+    dp = _dev_ptr(dst, "dst", (torch.float64,))
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in size")
+    _check(_lib.gs_copy_f64(sp, dp, src.numel(), _stream_ptr(stream, src.device)), "gs_copy_f64")
 
 
 def gs_device_errors(device=0, clear=False) -> int:

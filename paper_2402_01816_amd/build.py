@@ -17,7 +17,7 @@ OBJDIR = os.environ.get("GS_OBJ_DIR", os.path.join(HERE, "_build"))
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["gs_abi.cpp", "gs_plan.cpp", "gs_sort.hip", "gs_seg.hip", "gs_mlp.hip", "gs_learned.hip",
-           "gs_errors.hip", "gs_noalloc.hip"]
+           "gs_errors.hip", "gs_noalloc.hip", "gs_measure.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [

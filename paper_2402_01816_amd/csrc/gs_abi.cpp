@@ -218,6 +218,18 @@ int gs_trace_enable(int on)
     return was;
 }
 
+gs_status gs_copy_f64(const double *src, double *dst, int64_t n, void *hip_stream)
+{
+    g_detail.clear();
+    if (n < 0) return fail(GS_EINVAL, "n < 0");
+    if (n == 0) return GS_OK;
+    if (!src || !dst) return fail(GS_EINVAL, "src or dst is NULL");
+    gs_status s = check_device();
+    if (s != GS_OK) return s;
+    hipError_t e = gs::copy_f64_async(src, dst, n, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_copy_f64 launch");
+}
+
 int gs_trace_read(int *kinds, double *ms, int max)
 {
     int k = 0;

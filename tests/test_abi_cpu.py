@@ -86,6 +86,11 @@ def test_argument_errors_before_device():
     assert _call_f64(fake, 1000, 0.5, ctypes.c_void_p(0x100010), need) == g.GS_EINVAL
     assert "aligned" in g.lib.gs_last_error_detail().decode()
     assert g.lib.gs_sort_kv(fake, None, 10, 0.5, fake, 1 << 20, None, None) == g.GS_EINVAL
+    # the streaming copy: argument errors before any device work
+    assert g.lib.gs_copy_f64(fake, fake, -1, None) == g.GS_EINVAL
+    assert g.lib.gs_copy_f64(None, fake, 10, None) == g.GS_EINVAL
+    assert g.lib.gs_copy_f64(fake, None, 10, None) == g.GS_EINVAL
+    assert g.lib.gs_copy_f64(None, None, 0, None) == g.GS_OK
     # n <= 1 is a no-op that needs no workspace and no device
     assert _call_f64(None, 0, 0.5, None, 0) == g.GS_OK
     assert _call_f64(fake, 1, 0.5, None, 0) == g.GS_OK

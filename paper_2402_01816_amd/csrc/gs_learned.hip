@@ -869,14 +869,14 @@ __global__ __launch_bounds__(1024) void learned_bucket_scan_kernel(const unsigne
 // ---------------------------------------------------------------------------
 // 6b. one stable distribution pass by a digit of the bucket id
 // ---------------------------------------------------------------------------
-// One tile per work-group.  Wave w ranks its 1024 keys (16 rounds of 64 in
-// input order): all digits first, equal digits of a round finding each other
-// with one ballot per digit bit; the group leaders record per-round digit
-// counts, lane d turns the counts of digit d into prefixes over the rounds,
-// and a key's rank is its round's prefix plus its place among its round's
-// equals.  The tile then stages its keys in LDS grouped by digit and writes
-// every digit's run contiguously at the tile's offset for that digit (from
-// the tile scan).  The rank scratch shares LDS with the staging area.
+// One tile per work-group iteration.  Wave w ranks its keys (SW_ROUNDS rounds
+// of 64 in input order): every lane of a round sets its bit in its digit's
+// lane mask (LDS atomic or), so a key's place among its round's equals is a
+// population count; lane d turns the counts of digit d into prefixes over
+// the rounds, and a key's rank is its round's prefix plus its place among its
+// round's equals.  The tile then stages its keys in LDS grouped by digit and
+// writes every digit's run contiguously at the tile's offset for that digit
+// (from the tile scan).  The rank scratch shares LDS with the staging area.
 __global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter_kernel(const double *src, double *dst, int64_t len,
                                                                 const Feature *feat, const float *tab, int G, int B,
                                                                 int shift, int dbits, const unsigned *tileoff,

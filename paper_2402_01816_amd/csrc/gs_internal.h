@@ -197,9 +197,10 @@ hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan
 // caller has written every segment's order code into rank[] (0: to be sorted,
 // kSegDone: already in order) on the stream before the call.
 constexpr int kSegDone = -1;
-// Streaming copy of n doubles (measurement helper; 16-byte non-temporal
-// accesses when both pointers allow them).
-hipError_t copy_f64_async(const double *src, double *dst, int64_t n, hipStream_t st);
+// Streaming copy of n doubles (16-byte non-temporal accesses when both
+// pointers allow them); skipped on the device while *skip_if != 0.
+hipError_t copy_f64_async(const double *src, double *dst, int64_t n, hipStream_t st,
+                          const unsigned *skip_if = nullptr);
 hipError_t segsort_core_async(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys,
                               double *hbuf, unsigned *ctrl, int *cls, int *rank, int *list, char *forest,
                               const ForestPlan &fp, const unsigned *gate, unsigned run_if, hipStream_t st,

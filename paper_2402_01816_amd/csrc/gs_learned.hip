@@ -1021,15 +1021,6 @@ static int64_t scatter_groups(size_t slds)
     return g;
 }
 
-// gated copy (the sorted first half into the half buffer for the final merge)
-__global__ __launch_bounds__(256) void learned_copy_kernel(const double *src, double *dst, int64_t n,
-                                                           const unsigned *ctrl)
-{
-    if (ctrl[L_FALLBACK]) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -1263,8 +1254,8 @@ static hipError_t learned_sort_body(double *keys, int64_t n, const gs_learned_pa
     //    [n, n+nA)); the second run stays at [nA, n) inside the output [0, n),
     //    which is written bottom-up
     if (tr) trace_begin(TK_LEARN_BUCKET, st);
-    hipLaunchKernelGGL(learned_copy_kernel, dim3(2048), dim3(256), 0, st, (const double *)keys, H, nA,
-                       (const unsigned *)ctrl);
+    e = copy_f64_async(keys, H, nA, st, ctrl + L_FALLBACK);
+    if (e != hipSuccess) return e;
     if (tr) trace_end(st);
     FrogMerge fm{};
     fm.l0 = n;

@@ -28,7 +28,7 @@
  *     and of values) as a fraction of the data.  The workspace holds a control
  *     area on top of it (status words, merge-path splits, tile descriptors,
  *     run directions and run samples, plan tables): for the single-array
- *     sorts under 0.25% of the data at 2^28 keys (about 18 bytes per 1024
+ *     sorts under 0.4% of the data at 2^28 keys (about 32 bytes per 1024
  *     keys), more for small n, where its fixed part dominates.  %RAM
  *     (ram_fraction in the report) counts both, so it exceeds 1 + p by that
  *     overhead.

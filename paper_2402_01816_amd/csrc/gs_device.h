@@ -151,7 +151,7 @@ struct Forest {
 
 // Run-sample stretches per merge tile (a power of two).
 #ifndef GS_SAMP_PER_TILE
-#define GS_SAMP_PER_TILE 1
+#define GS_SAMP_PER_TILE 8
 #endif
 constexpr int kSampPerTile = GS_SAMP_PER_TILE;
 

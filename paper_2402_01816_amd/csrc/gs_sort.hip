@@ -558,7 +558,7 @@ __global__ __launch_bounds__(256) void partition_kernel(typename KT::T *Dk, type
             const int64_t ct = round == 1 ? F.samp_leaf_tiles : forest_tpn<TILE>(F, P, round - 1) * kSampPerTile;
             const K *sb0 = reinterpret_cast<const K *>(F.samp);
             splits[w] = sampled_split<KT>(keys, v, kk, sb0 + (2 * node) * ct, sb0 + (2 * node + 1) * ct,
-                                          F.samp_tile);
+                                          (int64_t)(TILE / kSampPerTile));
         } else {
             splits[w] = view_split<KT>(keys, v, kk);
         }
@@ -910,11 +910,10 @@ __global__ __launch_bounds__(NT, WAVES) void merge_kernel(typename KT::T *Dk, ty
                               ? reinterpret_cast<K *>(F.samp) + (int64_t)(cur.prob >> 1) * kSampPerTile
                               : nullptr;
         const bool samp_last = cur.prob & 1;
-        const int samp_n = (out_cnt + F.samp_tile - 1) / F.samp_tile;     // stretches of this tile
+        constexpr int ST = TILE / kSampPerTile;                              // ranks per stretch
+        const int samp_n = (out_cnt + ST - 1) / ST;                              // stretches of this tile
         // rank of stretch s's sample (s < samp_n)
-        auto samp_rank = [&](int s) {
-            return samp_last ? min((s + 1) * F.samp_tile, out_cnt) - 1 : s * F.samp_tile;
-        };
+        auto samp_rank = [&](int s) { return samp_last ? min((s + 1) * ST, out_cnt) - 1 : s * ST; };
         if (skip && samp_p && tid < samp_n) {
             const Space<K> ks{Dk + cur_p.doff, Hk + cur_p.hoff, cur_p.n};
             samp_p[tid] = *ks.at(out_o + samp_rank(tid));

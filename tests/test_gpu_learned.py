@@ -202,6 +202,27 @@ def test_learned_sort_special_values(gs, orc):
     assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
 
 
+def test_learned_many_long_runs(gs, orc):
+    """300 values holding 0.25 % of the keys each: more long runs of equal keys
+    than the sample pass records (256).  With the screening on, the runs it
+    could not see send the call to the plain path (fallback 2); with it off,
+    31 of the recorded runs become heavy values and the rest are sorted in
+    ordinary buckets.  Bit for bit the definition's result either way."""
+    announce("learned many runs")
+    n = N_SMALL + 99
+    rng = np.random.default_rng(23)
+    x = rng.random(n)
+    vals = rng.random(300)
+    pick = rng.random(n) < 0.75
+    x[pick] = vals[rng.integers(0, 300, int(pick.sum()))]
+    t, rep = _learned(gs, x, sample_size=16384)
+    assert rep["fallback"] == 2
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+    t, rep = _learned(gs, x, sample_size=16384, screen=1)
+    assert rep["fallback"] == 0 and rep["heavy_values"] == 31
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
 @pytest.mark.parametrize("pattern", ["lognormal", "gaussmix", "zipf_ints"])
 def test_learned_sample_table_parity(gs, orc, pattern):
     """Mode 2: the knot table is the sorted sample's CDF at the knots (no

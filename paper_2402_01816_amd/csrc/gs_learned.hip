@@ -887,9 +887,9 @@ __global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter
     __shared__ double s_hv[kHeavySlots];
     double *s_key = (double *)(lds_raw + (((size_t)(G + 1) * 4 + 15) & ~(size_t)15));
     unsigned char *s_dig = (unsigned char *)(s_key + SW_TILE);
-    __shared__ unsigned s_wcnt[SW_NT / 64][64];
-    __shared__ unsigned s_toff[64];
+    __shared__ unsigned s_wcnt[SW_NT / 64][64];     // per wave and digit: keys, then staging base
     __shared__ unsigned s_goff[64];
+    __shared__ int64_t s_delta[64];                 // per digit: destination minus staged position
     if (ctrl[L_FALLBACK] || len <= 0) return;
     const Feature F = *feat;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -966,10 +966,11 @@ __global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter
         if (tid < 64) {
             const int d = tid;
             unsigned run = 0;
+            unsigned woff[SW_NT / 64];
+#pragma unroll
             for (int w = 0; w < SW_NT / 64; ++w) {          // wave offsets per digit
-                const unsigned v = s_wcnt[w][d];
-                s_wcnt[w][d] = run;
-                run += v;
+                woff[w] = run;
+                run += s_wcnt[w][d];
             }
             // tile-local start of every digit: exclusive scan over the digits
             unsigned inc = run;
@@ -977,13 +978,18 @@ __global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter
                 const unsigned v = __shfl_up(inc, o);
                 if (lane >= o) inc += v;
             }
-            s_toff[d] = inc - run;
+            const unsigned toff = inc - run;
+            // staging base of each wave's keys of digit d, and the shift from a
+            // staged position to the destination
+#pragma unroll
+            for (int w = 0; w < SW_NT / 64; ++w) s_wcnt[w][d] = toff + woff[w];
+            s_delta[d] = (int64_t)s_goff[d] - (int64_t)toff;
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < SW_ROUNDS; ++r) {
             if (dg[r] >= 0) {
-                const unsigned pos = s_toff[dg[r]] + s_wcnt[wave][dg[r]] + rk[r];
+                const unsigned pos = s_wcnt[wave][dg[r]] + rk[r];
                 s_key[pos] = x[r];
                 s_dig[pos] = (unsigned char)dg[r];
             }
@@ -994,8 +1000,7 @@ __global__ __launch_bounds__(SW_NT, GS_LEARN_SCATTER_WAVES) void learned_scatter
         const int64_t rem = len - t * SW_TILE;
         const int nvalid = rem < SW_TILE ? (int)rem : SW_TILE;
         for (int i = tid; i < nvalid; i += SW_NT) {
-            const int d = s_dig[i];
-            const int64_t g = (int64_t)s_goff[d] + (i - (int)s_toff[d]);
+            const int64_t g = s_delta[s_dig[i]] + i;
             if ((uint64_t)g < (uint64_t)len) dst[g] = s_key[i];
         }
         __syncthreads();                                    // LDS free for the next tile

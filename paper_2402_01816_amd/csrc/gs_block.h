@@ -223,7 +223,10 @@ template <int DIR, int IPT>
 __device__ __forceinline__ void register_sort_identical(double (&k)[IPT], int maxw)
 {
     static_assert(IPT == 16, "lane bit j is position bit 4 + j");
-    const unsigned lane = threadIdx.x & 63;
+    // (the lane is made opaque: inside a loop over leaves the values derived
+    // from it would otherwise be hoisted out of the loop and spilled)
+    unsigned lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
     const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1,
                b4 = (lane >> 4) & 1;
     const bool neg = DIR < 0;
@@ -360,7 +363,9 @@ __device__ __forceinline__ void block_merge_rounds_identical(typename KT::T *sk,
     static_assert(IPT == 16, "the address arithmetic assumes 16 keys per thread, the pad period");
     using K = typename KT::T;
     char *lb = reinterpret_cast<char *>(sk);
-    const unsigned base = threadIdx.x * IPT;
+    unsigned tix = threadIdx.x;
+    asm volatile("" : "+v"(tix));                   // (not hoisted out of a loop over leaves)
+    const unsigned base = tix * IPT;
     const bool work = base < (((unsigned)active + maxw - 1) & ~(unsigned)(maxw - 1));
     if (work) {
         const unsigned b8 = lpad8(base);

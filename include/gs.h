@@ -38,7 +38,8 @@
  *     elements serving the branches in turn) unless gs_sort_*_ex asks for
  *     Frogsort2 ("Frogsort2": every inner branch, and the buffer, the fraction
  *     p).  p in (0, 1/64) -> GS_EUNSUPPORTED (the trees get hundreds of levels
- *     deep); NaN, <= 0 -> GS_EINVAL.  The segmented sort takes p >= 0.5 only.
+ *     deep); NaN, <= 0 -> GS_EINVAL.  The segmented sort below 0.5: see
+ *     gs_segsort.
  *   - A call with p < 0.5 plans its tree on the host and copies the plan's
  *     tables into the workspace on the stream (hipMemcpyAsync from host
  *     memory the library keeps), so it returns GS_EUNSUPPORTED while the
@@ -206,7 +207,19 @@ gs_status gs_sort_kv_ex(uint64_t *keys, uint32_t *vals, int64_t n, int target, d
    "Squidsort"): one already in order is left as it is, one whose neighbours
    all strictly decrease (or do not increase and tie only bit-identical keys)
    is reversed in place -- in both cases the stable result -- and only the
-   others are sorted. */
+   others are sorted.
+   buffer_fraction >= 0.5: every segment is frog-sorted (Frogsort1) with a
+   half buffer of its own, all in one pass.  buffer_fraction p in [1/64, 0.5):
+   one buffer of floor(q num_keys / 2^16) doubles (q = floor(65536 p)) serves
+   the segments in turn, the way Frogsort3 lets one buffer serve its branches
+   in turn ("Frogsort3 and 6"): each pass takes consecutive segments while the
+   half buffers of its long ones (placed side by side) fit, and a segment whose
+   own half buffer does not fit is sorted alone by the plain sort (Frogsort3)
+   with the largest fraction whose buffer fits.  Such a call first copies the
+   offsets to the host (it waits for the stream's earlier work), checks them
+   there (a violation returns GS_EINVAL before anything runs, with
+   invalid_offsets = 1 in the report), and returns GS_EUNSUPPORTED while the
+   stream is capturing a graph. */
 gs_status gs_segsort(double *keys, int64_t num_keys, const int64_t *offsets,
                      int64_t num_segments, double buffer_fraction,
                      void *ws, size_t ws_bytes, void *hip_stream, gs_report *rep);
@@ -382,6 +395,14 @@ int gs_plan_frog2(int64_t n, double buffer_fraction, int is_kv, int64_t *leaves,
 int gs_plan_frog3(int64_t n, double buffer_fraction, double sub_fraction, int is_kv, int64_t *trees,
                   int64_t max_trees, int64_t *spine, int64_t max_spine, int64_t *leaves, int64_t max_leaves,
                   int64_t *counts);
+/* The steps of gs_segsort at buffer_fraction < 0.5 with the default shape,
+   for host offsets[0..num_segments] (checked as gs_segsort checks them):
+   steps[3*i..] = first segment, one past the last, 1 if that one segment is
+   sorted alone by the plain sort (0: a pass).  *buffer receives the buffer's
+   elements.  Returns the number of steps (steps filled up to max_steps), -1
+   on bad arguments or offsets, -2 for a fraction of 0.5 or more (one pass). */
+int64_t gs_plan_seg_steps(const int64_t *offsets, int64_t num_segments, int64_t num_keys, double buffer_fraction,
+                          int64_t *steps, int64_t max_steps, int64_t *buffer);
 
 #ifdef __cplusplus
 }

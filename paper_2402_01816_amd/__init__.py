@@ -122,6 +122,7 @@ _SIGS = {
                        ctypes.c_void_p], ctypes.c_int),
     "gs_plan_frog3": ([_I64, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64,
                        ctypes.c_void_p, _I64, ctypes.c_void_p, _I64, ctypes.c_void_p], ctypes.c_int),
+    "gs_plan_seg_steps": ([ctypes.c_void_p, _I64, _I64, _D, ctypes.c_void_p, _I64, ctypes.c_void_p], _I64),
     "gs_workspace_bytes_f64_ex": ([_I64, _D, ctypes.c_int, _D], _SZ),
     "gs_workspace_bytes_kv_ex": ([_I64, _D, ctypes.c_int, _D], _SZ),
     "gs_sort_f64_ex": ([_P, _I64, ctypes.c_int, _D, ctypes.c_int, _D, _P, _SZ, _P, ctypes.POINTER(GsReport)],
@@ -262,6 +263,22 @@ def plan_frog3(n: int, buffer_fraction: float, kv: bool = False, sub_fraction: f
                        spine.ctypes.data, int(counts[1]), leaves.ctypes.data, leaves.shape[0],
                        counts.ctypes.data)
     return trees, spine[: int(counts[1])], leaves, tuple(int(c) for c in counts)
+
+
+def plan_seg_steps(offsets, num_keys: int, buffer_fraction: float):
+    """The segmented sort's steps below buffer fraction 0.5 (host only): rows
+    (first segment, one past the last, 1 if sorted alone by the plain sort)
+    and the buffer's elements, for host int64 offsets."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    nseg = max(off.shape[0] - 1, 0)
+    buf = _I64(0)
+    cnt = _lib.gs_plan_seg_steps(off.ctypes.data, nseg, num_keys, buffer_fraction, None, 0, ctypes.byref(buf))
+    if cnt < 0:
+        raise ValueError("no segmented steps for these arguments")
+    rows = np.zeros((max(cnt, 1), 3), dtype=np.int64)
+    _lib.gs_plan_seg_steps(off.ctypes.data, nseg, num_keys, buffer_fraction, rows.ctypes.data, cnt, None)
+    return rows[:cnt], buf.value
 
 
 # ---------------------------------------------------------------------------

@@ -87,15 +87,16 @@ gs_status resolve_algo(double f, int algo, double sub, int *out, int64_t *q, int
     return GS_OK;
 }
 
-// The segmented sort has Frogsort1 only.
-gs_status check_fraction_seg(double f)
+// The segmented sort's buffer: q = 0 at buffer_fraction >= 0.5 (Frogsort1 on
+// every segment in one pass); below, q/2^16 and the plain sort's algorithm
+// for a segment sorted alone.
+struct SegFraction {
+    int64_t q = 0, q2 = 32768;
+    int algo = gs::kAlgoFrog1;
+};
+gs_status seg_fraction(double f, SegFraction *out)
 {
-    int64_t q = 0, q2 = 0;
-    int a = 0;
-    gs_status s = resolve_algo(f, GS_ALGO_AUTO, 0.5, &a, &q, &q2);
-    if (s == GS_OK && a != gs::kAlgoFrog1)
-        return fail(GS_EUNSUPPORTED, "segmented sort: buffer_fraction %g < 0.5 is not built", f);
-    return s;
+    return resolve_algo(f, GS_ALGO_AUTO, 0.5, &out->algo, &out->q, &out->q2);
 }
 
 // A Frogsort2 call copies its host-built tree tables into the workspace, which
@@ -457,6 +458,27 @@ int gs_plan_frog3(int64_t n, double buffer_fraction, double sub_fraction, int is
     return 0;
 }
 
+int64_t gs_plan_seg_steps(const int64_t *offsets, int64_t num_segments, int64_t num_keys, double buffer_fraction,
+                          int64_t *steps, int64_t max_steps, int64_t *buffer)
+{
+    if (num_segments < 0 || num_keys < 0 || (num_segments > 0 && !offsets) || (max_steps > 0 && !steps))
+        return -1;
+    SegFraction fr;
+    if (seg_fraction(buffer_fraction, &fr) != GS_OK) return -1;
+    if (!fr.q) return -2;
+    for (int64_t i = 0; i < num_segments; ++i)
+        if (offsets[i] < 0 || offsets[i + 1] < offsets[i] || offsets[i + 1] > num_keys) return -1;
+    const gs::SegPlan p = gs::plan_seg(num_keys, num_segments, gs::seg_default_config(), fr.q, fr.algo, fr.q2);
+    if (buffer) *buffer = p.hlen;
+    const std::vector<gs::SegStep> st = gs::seg_schedule(offsets, num_segments, p.tile, p.hlen);
+    for (size_t k = 0; k < st.size() && (int64_t)k < max_steps; ++k) {
+        steps[3 * k + 0] = st[k].s0;
+        steps[3 * k + 1] = st[k].s1;
+        steps[3 * k + 2] = st[k].alone ? 1 : 0;
+    }
+    return (int64_t)st.size();
+}
+
 gs_status gs_sort_f64(double *keys, int64_t n, double buffer_fraction, void *ws, size_t ws_bytes,
                       void *hip_stream, gs_report *rep)
 {
@@ -565,19 +587,23 @@ size_t gs_workspace_bytes_seg_ex(int64_t num_keys, int64_t num_segments, double 
                                  const gs_seg_config *cfg)
 {
     if (num_keys < 0 || num_segments < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
+    SegFraction fr;
+    if (seg_fraction(buffer_fraction, &fr) != GS_OK) return SIZE_MAX;
     if (num_segments == 0) return 0;
     gs::SegConfig c;
     if (!to_seg_config(cfg, &c)) return SIZE_MAX;
-    return (size_t)gs::plan_seg(num_keys, num_segments, c).bytes;
+    return (size_t)gs::plan_seg(num_keys, num_segments, c, fr.q, fr.algo, fr.q2).bytes;
 }
 
 size_t gs_workspace_bytes_seg(int64_t num_keys, int64_t num_segments, double buffer_fraction)
 {
     if (num_keys < 0 || num_segments < 0 || !(buffer_fraction > 0.0)) return SIZE_MAX;
+    SegFraction fr;
+    if (seg_fraction(buffer_fraction, &fr) != GS_OK) return SIZE_MAX;
     if (num_segments == 0) return 0;
     int64_t most = 0;
     for (int i = 0; i < gs::seg_config_count(); ++i) {
-        const int64_t b = gs::plan_seg(num_keys, num_segments, gs::seg_config_at(i)).bytes;
+        const int64_t b = gs::plan_seg(num_keys, num_segments, gs::seg_config_at(i), fr.q, fr.algo, fr.q2).bytes;
         if (b > most) most = b;
     }
     return (size_t)most;
@@ -591,18 +617,93 @@ static gs_status seg_checks(double *keys, int64_t num_keys, const int64_t *offse
     if (num_keys < 0 || num_segments < 0) return fail(GS_EINVAL, "num_keys or num_segments < 0");
     if (num_segments > ((int64_t)1 << 31) - 2) return fail(GS_EINVAL, "num_segments above 2^31-2");
     if (num_keys > ((int64_t)1 << 40)) return fail(GS_EINVAL, "num_keys above 2^40");
-    gs_status s = check_fraction_seg(buffer_fraction);
+    SegFraction fr;
+    gs_status s = seg_fraction(buffer_fraction, &fr);
     if (s != GS_OK) return s;
     gs::SegConfig c;
     if (!to_seg_config(cfg, &c)) return fail(GS_EINVAL, "unknown segmented-sort shape");
     if (num_segments == 0) return GS_OK;
     if (!offsets) return fail(GS_EINVAL, "offsets is NULL");
     if (num_keys > 0 && !keys) return fail(GS_EINVAL, "keys is NULL");
-    *p = gs::plan_seg(num_keys, num_segments, c);
+    *p = gs::plan_seg(num_keys, num_segments, c, fr.q, fr.algo, fr.q2);
     if ((int64_t)ws_bytes < p->bytes || !ws)
         return fail(GS_EWORKSPACE, "workspace %zu bytes, need %lld", ws_bytes, (long long)p->bytes);
     if (!aligned256(ws)) return fail(GS_EINVAL, "workspace not 256-byte aligned");
     return GS_OK;
+}
+
+// buffer_fraction < 0.5: the offsets come to the host (the call waits for
+// the work queued before it on the stream), the buffer serves runs of
+// consecutive segments in turn, and a segment whose half buffer does not fit
+// is sorted alone by the plain sort, with the largest fraction whose buffer
+// fits in the workspace.
+static gs_status segsort_small_buffer(double *keys, int64_t num_keys, const int64_t *offsets, int64_t nseg,
+                                      const gs::SegPlan &p, void *ws, size_t ws_bytes, hipStream_t st,
+                                      gs_report *rep)
+{
+    gs_status s = check_not_capturing(st);
+    if (s != GS_OK) return s;
+    std::vector<int64_t> off((size_t)nseg + 1);
+    hipError_t e = hipMemcpyAsync(off.data(), offsets, (size_t)(nseg + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                  st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading the segment offsets");
+    for (int64_t i = 0; i < nseg; ++i) {
+        if (off[i] < 0 || off[i + 1] < off[i] || off[i + 1] > num_keys) {
+            if (rep) {
+                memset(rep, 0, sizeof *rep);
+                rep->ram_fraction = 1.0;
+                rep->invalid_offsets = 1u;
+            }
+            return fail(GS_EINVAL, "offsets not non-decreasing within [0, num_keys]");
+        }
+    }
+    const std::vector<gs::SegStep> steps = gs::seg_schedule(off.data(), nseg, p.tile, p.hlen);
+    // every plan of a segment sorted alone is made before anything runs
+    std::vector<gs::SortPlan> alone;
+    int64_t used = p.off_forest + p.forest.bytes;
+    for (const gs::SegStep &t : steps) {
+        if (!t.alone) continue;
+        const int64_t len = off[(size_t)t.s0 + 1] - off[(size_t)t.s0];
+        const int64_t qa = (int64_t)(((__int128)p.hlen << 16) / len);   // floor(qa len / 2^16) <= hlen
+        gs::SortPlan a{};
+        bool fits = false;
+        if (qa >= gs::kF2MinQ && qa < 32768) {
+            a = gs::plan_f64(len, qa, p.algo, p.q2);
+            fits = a.bytes <= (int64_t)ws_bytes;
+        }
+        if (!fits) {
+            a = gs::plan_f64(len, p.q, p.algo, p.q2);
+            if (a.bytes > (int64_t)ws_bytes)
+                return fail(GS_EWORKSPACE, "workspace %zu bytes, a segment of %lld keys needs %lld", ws_bytes,
+                            (long long)len, (long long)a.bytes);
+        }
+        if (a.bytes > used) used = a.bytes;
+        alone.push_back(std::move(a));
+    }
+    Reporter r(rep, st);
+    size_t k = 0;
+    for (const gs::SegStep &t : steps) {
+        if (!t.alone) continue;
+        const gs::SortPlan &a = alone[k++];
+        e = gs::sort_f64_target_async(keys + off[(size_t)t.s0], a.n, GS_ASC_LEFT, (char *)ws, a, st);
+        if (e != hipSuccess) return r.finish(hip_fail(e, "gs_segsort launch"));
+        if (rep) {
+            // the passes below reuse this sort's control area
+            e = hipStreamSynchronize(st);
+            s = e != hipSuccess ? hip_fail(e, "hipStreamSynchronize") : check_err_word((const char *)ws, a);
+            if (s != GS_OK) return r.finish(s);
+        }
+    }
+    e = gs::segsort_passes_async(keys, offsets, p, steps, (char *)ws, st);
+    if (e != hipSuccess) return r.finish(hip_fail(e, "gs_segsort launch"));
+    s = r.finish(GS_OK);
+    if (rep && s == GS_OK) {
+        rep->workspace_bytes_used = (uint64_t)used;
+        rep->ram_fraction = num_keys > 0 ? 1.0 + (double)used / (8.0 * (double)num_keys) : 1.0;
+        s = check_err_word((const char *)ws + p.off_forest + p.forest.off_ctrl);
+    }
+    return s;
 }
 
 gs_status gs_segsort_ex(double *keys, int64_t num_keys, const int64_t *offsets, int64_t num_segments,
@@ -619,6 +720,7 @@ gs_status gs_segsort_ex(double *keys, int64_t num_keys, const int64_t *offsets, 
     }
     if ((s = check_device()) != GS_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
+    if (p.q) return segsort_small_buffer(keys, num_keys, offsets, num_segments, p, ws, ws_bytes, st, rep);
     Reporter r(rep, st);
     hipError_t e = gs::segsort_f64_async(keys, offsets, p, (char *)ws, st);
     if (e != hipSuccess) return r.finish(hip_fail(e, "gs_segsort launch"));

@@ -172,20 +172,50 @@ SegConfig seg_config_at(int i);
 SegConfig seg_default_config();
 bool seg_config_valid(const SegConfig &c);
 
-// Workspace layout of one segmented sort.
+// Workspace layout of one segmented sort.  With q = 0 every segment is
+// sorted in one pass over a half buffer of floor(num_keys/2) doubles.  With a
+// buffer fraction q/2^16 below one half the buffer holds
+// floor(q num_keys / 2^16) doubles and serves runs of consecutive segments in
+// turn (the passes of seg_schedule); a segment whose own half buffer does not
+// fit is sorted alone by the plain sort (algo and q2 as for a plain sort at
+// that fraction), which needs at most alone_bytes.
 struct SegPlan {
     int64_t num_keys, nseg;
     SegConfig cfg;
     int64_t tile;         // keys per short LDS tile
-    int64_t off_h;        // half buffer: floor(num_keys/2) doubles
+    int64_t q;            // 0, or the buffer fraction q/2^16 < 1/2
+    int algo;             // plain-sort algorithm of a segment sorted alone
+    int64_t q2;           // its sub-fraction (Frogsort6)
+    int64_t hlen;         // buffer elements
+    int64_t pass_keys;    // most keys the long segments of one pass can hold
+    int64_t alone_bytes;  // workspace of the largest segment sorted alone (0: none can be)
+    int64_t off_h;        // the buffer: hlen doubles
     int64_t off_ctrl;     // 64 control words
     int64_t off_cls, off_rank, off_list;   // per-segment class, rank in class, class-ordered list
     int64_t off_maps;     // order-check range maps (2 bytes per range of keys)
-    int64_t off_forest;   // forest area for the long segments
+    int64_t off_forest;   // forest area for the long segments of one pass
     ForestPlan forest;
     int64_t bytes;
 };
-SegPlan plan_seg(int64_t num_keys, int64_t nseg, const SegConfig &cfg);
+SegPlan plan_seg(int64_t num_keys, int64_t nseg, const SegConfig &cfg, int64_t q = 0, int algo = 0,
+                 int64_t q2 = 0);
+// One step of a segmented sort with a buffer below one half: the segments
+// [s0, s1) sorted together in one pass, the long ones' half buffers side by
+// side in the buffer, or (alone) the one segment s0 too long for that, sorted
+// by the plain sort.
+struct SegStep {
+    int64_t s0, s1;
+    bool alone;
+};
+// The steps for host offsets off[0..nseg] (validated) and a buffer of hlen
+// doubles: greedy, each pass taking consecutive segments while every long
+// segment's half buffer, placed at (its first key - the pass's first key) / 2,
+// ends within the buffer.
+std::vector<SegStep> seg_schedule(const int64_t *off, int64_t nseg, int64_t tile, int64_t hlen);
+// Runs the passes of a schedule (the steps that are not alone) with one
+// error-word bracket; offsets stays the caller's device array.
+hipError_t segsort_passes_async(double *keys, const int64_t *offsets, const SegPlan &p,
+                                const std::vector<SegStep> &steps, char *ws, hipStream_t st);
 // Forest area for the long segments of up to nseg segments of at most max_len
 // keys each, num_keys keys in total.
 ForestPlan plan_forest_seg(int64_t num_keys, int64_t max_len, int64_t nseg);

@@ -488,24 +488,72 @@ static int64_t max_long(int64_t num_keys, int64_t nseg, int64_t tile)
     return m < nseg ? m : nseg;
 }
 
-SegPlan plan_seg(int64_t num_keys, int64_t nseg, const SegConfig &cfg)
+SegPlan plan_seg(int64_t num_keys, int64_t nseg, const SegConfig &cfg, int64_t q, int algo, int64_t q2)
 {
     SegPlan p{};
     p.num_keys = num_keys;
     p.nseg = nseg;
     p.cfg = cfg;
     p.tile = (int64_t)cfg.short_threads * cfg.short_ipt;
+    p.q = q > 0 && q < 32768 ? q : 0;
+    p.algo = algo;
+    p.q2 = q2;
+    p.hlen = p.q ? (int64_t)(((__int128)p.q * num_keys) >> 16) : num_keys / 2;
+    // The long segments of one pass have disjoint half buffers inside the
+    // buffer, so they hold at most 2 hlen keys plus one per segment, and each
+    // holds more than a tile: at most 2 hlen + 2 hlen / tile + 1 keys.
+    p.pass_keys = p.q ? 2 * p.hlen + 2 * p.hlen / p.tile + 1 : num_keys;
+    if (p.pass_keys > num_keys) p.pass_keys = num_keys;
     p.off_h = 0;
-    p.off_ctrl = align256s((num_keys / 2) * 8);
+    p.off_ctrl = align256s(p.hlen * 8);
     p.off_cls = p.off_ctrl + 256;
     p.off_rank = p.off_cls + align256s(nseg * 4);
     p.off_list = p.off_rank + align256s(nseg * 4);
     p.off_maps = p.off_list + align256s(nseg * 4);
     p.off_forest = p.off_maps + align256s(2 * seg_ranges(num_keys));
-    p.forest = plan_forest_f64(num_keys, num_keys, max_long(num_keys, nseg, p.tile), cfg.merge_ipt);
+    p.forest = plan_forest_f64(p.pass_keys, p.pass_keys, max_long(p.pass_keys, nseg, p.tile), cfg.merge_ipt);
     p.bytes = p.off_forest + p.forest.bytes;
+    // a segment sorted alone is longer than a tile and than 2 hlen + 1 keys.
+    // The plain sort's workspace at the call's fraction grows with the keys,
+    // but not strictly: its control area for a length just below a power of
+    // two can exceed that of the power by a few KiB.  The whole array's, with
+    // its control area grown by 1/8 + 8 KiB, bounds every segment's (and the
+    // call checks each segment's own before anything runs).
+    p.alone_bytes = 0;
+    if (p.q && num_keys > p.tile && num_keys > 2 * p.hlen + 1) {
+        const SortPlan a = plan_f64(num_keys, p.q, algo, q2);
+        const int64_t ctrl = a.bytes - align256s(a.hlen * 8);
+        p.alone_bytes = align256s(a.bytes + ctrl / 8 + 8192);
+    }
+    if (p.alone_bytes > p.bytes) p.bytes = p.alone_bytes;
     return p;
 }
+
+std::vector<SegStep> seg_schedule(const int64_t *off, int64_t nseg, int64_t tile, int64_t hlen)
+{
+    std::vector<SegStep> steps;
+    int64_t s0 = 0;
+    while (s0 < nseg) {
+        int64_t s = s0;
+        const int64_t base = off[s0];
+        for (; s < nseg; ++s) {
+            const int64_t len = off[s + 1] - off[s];
+            if (len <= tile) continue;                       // sorted in LDS: no buffer
+            if ((off[s] - base) / 2 + len / 2 <= hlen) continue;
+            break;
+        }
+        if (s > s0) {
+            steps.push_back(SegStep{s0, s, false});
+            s0 = s;
+        } else {
+            // the first segment alone overflows the buffer
+            steps.push_back(SegStep{s0, s0 + 1, true});
+            s0 = s0 + 1;
+        }
+    }
+    return steps;
+}
+
 
 // The forest of segsort_core_async, which runs the default shape.
 ForestPlan plan_forest_seg(int64_t num_keys, int64_t max_len, int64_t nseg)
@@ -617,6 +665,24 @@ hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan
                     (unsigned char *)(ws + p.off_maps), ws + p.off_forest, p.forest, p.cfg, true, nullptr, 0u, st);
     if (e != hipSuccess) return e;
     ew.add((unsigned *)(ws + p.off_ctrl), DEVERR_OFFSETS);
+    return err_words_end(ew, st);
+}
+
+hipError_t segsort_passes_async(double *keys, const int64_t *offsets, const SegPlan &p,
+                                const std::vector<SegStep> &steps, char *ws, hipStream_t st)
+{
+    ErrWords ew{};
+    ew.add((unsigned *)(ws + p.off_forest + p.forest.off_ctrl) + kErrWord, DEVERR_WAIT);
+    hipError_t e = err_words_begin(ew, st);
+    if (e != hipSuccess) return e;
+    for (const SegStep &t : steps) {
+        if (t.alone) continue;
+        e = segsort_run(keys, offsets + t.s0, t.s1 - t.s0, p.num_keys, (double *)(ws + p.off_h),
+                        (unsigned *)(ws + p.off_ctrl), (int *)(ws + p.off_cls), (int *)(ws + p.off_rank),
+                        (int *)(ws + p.off_list), (unsigned char *)(ws + p.off_maps), ws + p.off_forest, p.forest,
+                        p.cfg, true, nullptr, 0u, st);
+        if (e != hipSuccess) return e;
+    }
     return err_words_end(ew, st);
 }
 

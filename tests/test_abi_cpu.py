@@ -130,7 +130,11 @@ def test_segsort_argument_errors():
     assert f(fake, 1000, None, 10, 0.5, fake, need, None, None) == g.GS_EINVAL
     assert f(fake, 1000, fake, -1, 0.5, fake, need, None, None) == g.GS_EINVAL
     assert f(fake, -5, fake, 10, 0.5, fake, need, None, None) == g.GS_EINVAL
-    assert f(fake, 1000, fake, 10, 0.3, fake, need, None, None) == g.GS_EUNSUPPORTED
+    assert f(fake, 1000, fake, 10, 0.01, fake, need, None, None) == g.GS_EUNSUPPORTED
+    need3 = g.gs_workspace_bytes_seg(1000, 10, 0.3)
+    assert need3 != g.SIZE_MAX
+    assert f(fake, 1000, fake, 10, 0.3, fake, need3 - 1, None, None) == g.GS_EWORKSPACE
+    assert f(fake, 1000, fake, 10, 0.3, fake, need3, None, None) == g.GS_ENODEVICE
     assert f(fake, 1000, fake, 10, 0.5, fake, need - 1, None, None) == g.GS_EWORKSPACE
     assert f(None, 0, None, 0, 0.5, None, 0, None, None) == g.GS_OK
     assert g.gs_workspace_bytes_seg(10, 0) == 0
@@ -264,7 +268,81 @@ def test_frog2_fraction_bounds():
     assert g.gs_workspace_bytes_f64(1 << 20, 0.5) == g.gs_workspace_bytes_f64(1 << 20, 0.9)
     fake = ctypes.c_void_p(0x100000)
     need = g.gs_workspace_bytes_seg(1000, 10)
-    assert g.lib.gs_segsort(fake, 1000, fake, 10, 0.25, fake, need, None, None) == g.GS_EUNSUPPORTED
+    assert g.lib.gs_segsort(fake, 1000, fake, 10, 1 / 64 - 1e-9, fake, need, None, None) == g.GS_EUNSUPPORTED
+    assert g.gs_workspace_bytes_seg(1 << 20, 10, 1 / 64 - 1e-9) == g.SIZE_MAX
+    assert g.gs_workspace_bytes_seg(1 << 20, 10, 1 / 64) != g.SIZE_MAX
+
+
+def _default_tile():
+    c = g.GsSegConfig()
+    g.lib.gs_seg_default_config(ctypes.byref(c))
+    return c.short_threads * c.short_ipt
+
+
+def _seg_offsets(rng, n_target, tile, giant=False):
+    """Segment lengths mixing empty, short (at most a tile), long and, with
+    giant, one segment of 60 % of the keys."""
+    lens = []
+    while sum(lens) < n_target:
+        u = rng.random()
+        lens.append(0 if u < 0.05 else int(rng.integers(1, tile + 1)) if u < 0.6
+                    else int(rng.integers(tile + 1, 6 * tile)))
+    if giant:
+        lens.insert(int(rng.integers(0, len(lens))), int(1.5 * sum(lens)))
+    return np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("p", [1 / 64, 0.1, 0.25, 0.45])
+def test_seg_small_buffer_steps(seed, p):
+    """Below buffer fraction 0.5 the segmented sort's steps cover every
+    segment once, in order; every pass's long segments have their half
+    buffers, placed at (first key - the pass's first key) / 2, inside the
+    buffer; a pass ends only at a long segment that would overflow it; a
+    segment sorted alone is long and its own half buffer overflows it."""
+    rng = np.random.default_rng(seed)
+    tile = _default_tile()
+    off = _seg_offsets(rng, 40 * tile, tile, giant=seed % 2 == 1)
+    n = int(off[-1]) + int(rng.integers(0, 50))
+    rows, hlen = g.plan_seg_steps(off, n, p)
+    assert hlen == (int(p * 65536) * n) >> 16
+    nseg = off.shape[0] - 1
+    assert rows[0, 0] == 0 and rows[-1, 1] == nseg
+    assert (rows[1:, 0] == rows[:-1, 1]).all() and (rows[:, 1] > rows[:, 0]).all()
+    ln = np.diff(off)
+    for s0, s1, alone in rows:
+        if alone:
+            assert s1 == s0 + 1 and ln[s0] > tile and ln[s0] // 2 > hlen
+            continue
+        for s in range(s0, s1):
+            if ln[s] > tile:
+                assert (off[s] - off[s0]) // 2 + ln[s] // 2 <= hlen
+        if s1 < nseg:
+            assert ln[s1] > tile and (off[s1] - off[s0]) // 2 + ln[s1] // 2 > hlen
+    if seed % 2 == 1 and p < 0.3:
+        assert rows[:, 2].any()
+    bad = off.copy()
+    bad[3] = bad[2] - 1
+    with pytest.raises(ValueError):
+        g.plan_seg_steps(bad, n, p)
+    with pytest.raises(ValueError):
+        g.plan_seg_steps(off, n, 0.5)
+
+
+@pytest.mark.parametrize("p", [1 / 64, 0.1, 0.25, 0.45])
+def test_seg_small_buffer_workspace(p):
+    """The segmented workspace below 0.5 is the buffer plus control, smaller
+    than the half buffer's, and covers the plain sort's workspace of any
+    segment that may have to be sorted alone (any length up to the keys)."""
+    n = 1 << 24
+    ws = g.gs_workspace_bytes_seg(n, 5000, p)
+    assert ws < g.gs_workspace_bytes_seg(n, 5000, 0.5)
+    assert ws / (8 * n) < p + 0.01
+    rng = np.random.default_rng(7)
+    for N in [100003, 1 << 20, 3000017]:
+        top = g.gs_workspace_bytes_seg(N, 9, p)
+        lens = np.unique(np.concatenate([rng.integers(2, N + 1, 40), N - np.arange(40)]))
+        assert max(g.gs_workspace_bytes_f64(int(L), p) for L in lens) <= top
 
 
 @pytest.mark.parametrize("kv", [False, True])

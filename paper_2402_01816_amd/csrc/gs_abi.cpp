@@ -695,7 +695,7 @@ static gs_status segsort_small_buffer(double *keys, int64_t num_keys, const int6
             if (s != GS_OK) return r.finish(s);
         }
     }
-    e = gs::segsort_passes_async(keys, offsets, p, steps, (char *)ws, st);
+    e = gs::segsort_passes_async(keys, offsets, off.data(), p, steps, (char *)ws, st);
     if (e != hipSuccess) return r.finish(hip_fail(e, "gs_segsort launch"));
     s = r.finish(GS_OK);
     if (rep && s == GS_OK) {

@@ -213,8 +213,9 @@ struct SegStep {
 // ends within the buffer.
 std::vector<SegStep> seg_schedule(const int64_t *off, int64_t nseg, int64_t tile, int64_t hlen);
 // Runs the passes of a schedule (the steps that are not alone) with one
-// error-word bracket; offsets stays the caller's device array.
-hipError_t segsort_passes_async(double *keys, const int64_t *offsets, const SegPlan &p,
+// error-word bracket; offsets stays the caller's device array, h_off is its
+// host copy.
+hipError_t segsort_passes_async(double *keys, const int64_t *offsets, const int64_t *h_off, const SegPlan &p,
                                 const std::vector<SegStep> &steps, char *ws, hipStream_t st);
 // Forest area for the long segments of up to nseg segments of at most max_len
 // keys each, num_keys keys in total.

@@ -159,11 +159,12 @@ template <class KT>
 __global__ __launch_bounds__(256) void seg_order_range_kernel(const typename KT::T *keys, const int64_t *offsets,
                                                               int64_t nseg, int64_t num_keys, int *cls,
                                                               const int *rank, const unsigned *ctrl,
-                                                              const unsigned char *cand, Gate gate)
+                                                              const unsigned char *cand, int64_t range0, Gate gate)
 {
     __shared__ unsigned s_bits;
-    if (gate.closed() || !ctrl[C_CAND] || !cand[blockIdx.x]) return;
-    const int64_t r0 = (int64_t)blockIdx.x * SEG_RANGE;
+    const int64_t range = range0 + blockIdx.x;
+    if (gate.closed() || !ctrl[C_CAND] || !cand[range]) return;
+    const int64_t r0 = range * SEG_RANGE;
     const int64_t r1 = r0 + SEG_RANGE < num_keys ? r0 + SEG_RANGE : num_keys;
     for (int64_t s = seg_first_after(offsets, nseg, r0); s < nseg; ++s) {
         const int64_t lo = offsets[s], hi = offsets[s + 1];
@@ -260,10 +261,12 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const int64_t *offset
 template <class K>
 __global__ __launch_bounds__(256) void seg_reverse_kernel(K *keys, const int64_t *offsets, int64_t nseg,
                                                           int64_t num_keys, const unsigned *ctrl, const int *cls,
-                                                          const int *rank, const unsigned char *revmap, Gate gate)
+                                                          const int *rank, const unsigned char *revmap,
+                                                          int64_t range0, Gate gate)
 {
-    if (gate.closed() || ctrl[C_INVALID] || !ctrl[C_REV] || !revmap[blockIdx.x]) return;
-    const int64_t r0 = (int64_t)blockIdx.x * SEG_RANGE;
+    const int64_t range = range0 + blockIdx.x;
+    if (gate.closed() || ctrl[C_INVALID] || !ctrl[C_REV] || !revmap[range]) return;
+    const int64_t r0 = range * SEG_RANGE;
     const int64_t r1 = r0 + SEG_RANGE < num_keys ? r0 + SEG_RANGE : num_keys;
     for (int64_t s = seg_first_after(offsets, nseg, r0); s < nseg; ++s) {
         const int64_t lo = offsets[s], hi = offsets[s + 1];
@@ -594,7 +597,8 @@ static unsigned seg_groups(int64_t nseg)
 static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg, int64_t num_keys, double *hbuf,
                               unsigned *ctrl, int *cls, int *rank, int *list, unsigned char *maps, char *forest,
                               const ForestPlan &fp, const SegConfig &cfg, bool order_check, const unsigned *gate,
-                              unsigned run_if, hipStream_t st, bool preset_codes = false)
+                              unsigned run_if, hipStream_t st, bool preset_codes = false, int64_t key_lo = 0,
+                              int64_t key_hi = -1)
 {
     if (nseg <= 0) return hipSuccess;
     const Gate g{gate, run_if};
@@ -605,21 +609,27 @@ static hipError_t segsort_run(double *keys, const int64_t *offsets, int64_t nseg
     const unsigned grid = (unsigned)((nseg + 255) / 256);
     const unsigned ranges = (unsigned)((num_keys + SEG_RANGE - 1) / SEG_RANGE);
     unsigned char *cand = maps, *revmap = maps ? maps + ranges : nullptr;
+    // the range passes cover the ranges of keys [key_lo, key_hi) the
+    // segments hold (all of them by default)
+    if (key_hi < 0) key_hi = num_keys;
+    const int64_t range0 = key_lo / SEG_RANGE;
+    const int64_t range1 = (key_hi + SEG_RANGE - 1) / SEG_RANGE;
+    const unsigned span = (unsigned)(range1 > range0 ? range1 - range0 : 0);
     if (order_check) {
         if (ranges > 0) launch_fill_u32((unsigned *)maps, (2 * (int64_t)ranges + 3) / 4, 0u, st);
         hipLaunchKernelGGL((seg_order_sample_kernel<KeyF64>), dim3(seg_groups((nseg + 3) / 4)), dim3(256), 0, st,
                            (const double *)keys, offsets, nseg, num_keys, cls, rank, ctrl, cand, g);
-        if (ranges > 0)
-            hipLaunchKernelGGL((seg_order_range_kernel<KeyF64>), dim3(ranges), dim3(256), 0, st,
+        if (span > 0)
+            hipLaunchKernelGGL((seg_order_range_kernel<KeyF64>), dim3(span), dim3(256), 0, st,
                                (const double *)keys, offsets, nseg, num_keys, cls, (const int *)rank,
-                               (const unsigned *)ctrl, (const unsigned char *)cand, g);
+                               (const unsigned *)ctrl, (const unsigned char *)cand, range0, g);
     }
     hipLaunchKernelGGL(seg_classify_kernel, dim3(grid), dim3(256), 0, st, offsets, nseg, num_keys, logt, ctrl, cls,
                        rank, order_check || preset_codes ? 1 : 0, revmap, g);
-    if (order_check && ranges > 0)
-        hipLaunchKernelGGL((seg_reverse_kernel<double>), dim3(ranges), dim3(256), 0, st, keys, offsets, nseg,
+    if (order_check && span > 0)
+        hipLaunchKernelGGL((seg_reverse_kernel<double>), dim3(span), dim3(256), 0, st, keys, offsets, nseg,
                            num_keys, (const unsigned *)ctrl, (const int *)cls, (const int *)rank,
-                           (const unsigned char *)revmap, g);
+                           (const unsigned char *)revmap, range0, g);
     hipLaunchKernelGGL(seg_scatter_kernel, dim3(grid), dim3(256), 0, st, nseg, logt, (const unsigned *)ctrl,
                        (const int *)cls, (const int *)rank, list, g);
     Prob *probs = (Prob *)(forest + fp.off_probs);
@@ -668,19 +678,33 @@ hipError_t segsort_f64_async(double *keys, const int64_t *offsets, const SegPlan
     return err_words_end(ew, st);
 }
 
-hipError_t segsort_passes_async(double *keys, const int64_t *offsets, const SegPlan &p,
+hipError_t segsort_passes_async(double *keys, const int64_t *offsets, const int64_t *h_off, const SegPlan &p,
                                 const std::vector<SegStep> &steps, char *ws, hipStream_t st)
 {
+    // every pass's forest shares one control block, so its error word
     ErrWords ew{};
     ew.add((unsigned *)(ws + p.off_forest + p.forest.off_ctrl) + kErrWord, DEVERR_WAIT);
     hipError_t e = err_words_begin(ew, st);
     if (e != hipSuccess) return e;
     for (const SegStep &t : steps) {
         if (t.alone) continue;
+        // the forest sized to this pass's long segments (fewer rounds and
+        // smaller launches than the capacity of any pass); its areas lie
+        // inside the reserved one, whose control block comes first
+        int64_t keys_long = 0, max_len = 0, nlong = 0;
+        for (int64_t s = t.s0; s < t.s1; ++s) {
+            const int64_t len = h_off[s + 1] - h_off[s];
+            if (len <= p.tile) continue;
+            keys_long += len;
+            nlong += 1;
+            if (len > max_len) max_len = len;
+        }
+        ForestPlan fp = plan_forest_f64(keys_long, max_len, nlong, p.cfg.merge_ipt);
+        if (fp.bytes > p.forest.bytes || fp.off_ctrl != p.forest.off_ctrl) fp = p.forest;
         e = segsort_run(keys, offsets + t.s0, t.s1 - t.s0, p.num_keys, (double *)(ws + p.off_h),
                         (unsigned *)(ws + p.off_ctrl), (int *)(ws + p.off_cls), (int *)(ws + p.off_rank),
-                        (int *)(ws + p.off_list), (unsigned char *)(ws + p.off_maps), ws + p.off_forest, p.forest,
-                        p.cfg, true, nullptr, 0u, st);
+                        (int *)(ws + p.off_list), (unsigned char *)(ws + p.off_maps), ws + p.off_forest, fp,
+                        p.cfg, true, nullptr, 0u, st, false, h_off[t.s0], h_off[t.s1]);
         if (e != hipSuccess) return e;
     }
     return err_words_end(ew, st);

@@ -65,6 +65,10 @@ def test_gradient_matches_oracle(gs, orc, batch):
     g = grad.cpu().numpy().astype(np.float64)
     for name, sl in orc.mlp_slices().items():
         assert _relerr(g[sl], ref_grad[sl]) <= 1e-4, name
+        # entry by entry too, so that a wrong entry cannot hide in the norm
+        # of a large tensor (W2 has 4,096): fp32 sums of at most 2048 terms
+        scale = np.max(np.abs(ref_grad[sl]))
+        assert np.max(np.abs(g[sl] - ref_grad[sl])) <= 1e-4 * scale, name
 
 
 def test_forward_matches_oracle(gs, orc):

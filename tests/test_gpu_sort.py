@@ -94,6 +94,21 @@ def test_repeated_calls_share_workspace(gs, orc):
     assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
 
 
+@pytest.mark.parametrize("n", [1 << 24, (1 << 24) + 4097])
+def test_sort_f64_many_tiles_visible_ties(gs, orc, n):
+    """Element by element at sizes whose top merges hold thousands of tiles,
+    more than the merge launch's resident work-groups, so every work-group
+    takes several tiles in turn; ±0 ties and NaNs with different payloads
+    make every tie order visible."""
+    announce("sort_f64 many tiles ties", n)
+    x = W.f64_pattern("zeros_signed", n, seed=n % 977)
+    x[::509] = np.float64(np.nan)
+    x[::1021] = -np.float64(np.nan)
+    t = to_dev(x)
+    gs.gs_sort_f64(t)
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
 FULL_N = 1 << 28
 
 

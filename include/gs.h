@@ -81,7 +81,8 @@ typedef struct {
     uint64_t workspace_bytes_used;  /* bytes of ws the call may touch */
     uint32_t levels;                /* merge levels (tree depth) of the largest sort done */
     uint32_t fallback;              /* learned: 1 the bucket table failed verification (order,
-                                       overflow), 2 the sample predicted too uneven buckets */
+                                       overflow), 2 the sample predicted too uneven buckets,
+                                       3 a buffer fraction below 0.5 */
     uint32_t overflow_buckets;      /* learned: buckets above the in-LDS capacity */
     uint32_t max_bucket;            /* learned: largest bucket (keys) */
     float    train_loss_first;      /* learned: training loss of the first / last step */
@@ -117,6 +118,11 @@ typedef struct {
     const float *weights_override;    /* device, 4353 floats: skip training, use these weights; may be NULL */
     const float *test_bucket_table;   /* device, `knots`+1 floats: raw table, bypasses the running max
                                          (test hook to force an order violation); may be NULL */
+    double   buffer_fraction; /* 0 or >= 0.5 (default 0.5): the learned path, whose distribution
+                                 passes write each half out of place into the half buffer;
+                                 [1/64, 0.5): that buffer does not fit, and the call sorts with the
+                                 plain path at this fraction instead (Frogsort3, as gs_sort_f64
+                                 does; report.fallback = 3); below 1/64 GS_EUNSUPPORTED */
 } gs_learned_params;
 
 /* Fills `p` with the defaults above. */

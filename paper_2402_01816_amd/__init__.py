@@ -72,6 +72,7 @@ class GsLearnedParams(ctypes.Structure):
         ("screen", ctypes.c_uint32),
         ("weights_override", ctypes.c_void_p),
         ("test_bucket_table", ctypes.c_void_p),
+        ("buffer_fraction", ctypes.c_double),
     ]
 
 

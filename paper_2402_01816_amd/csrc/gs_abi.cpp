@@ -880,6 +880,16 @@ void gs_learned_default_params(gs_learned_params *p)
     p->lr = 4e-2f;
     p->seed = 0x5eed;
     p->mode = 0;
+    p->buffer_fraction = 0.5;
+}
+
+// The learned path at buffer fraction 0 (the default) or >= 0.5; below, the
+// plain sort's algorithm and q (*q = 0: the learned path).
+static gs_status learned_fraction(const gs_learned_params &p, int *algo, int64_t *q, int64_t *q2)
+{
+    *q = 0;
+    if (p.buffer_fraction == 0.0 || p.buffer_fraction >= 0.5) return GS_OK;
+    return resolve_algo(p.buffer_fraction, GS_ALGO_AUTO, 0.5, algo, q, q2);
 }
 
 static gs_status check_learned_params(const gs_learned_params &p)
@@ -894,7 +904,9 @@ static gs_status check_learned_params(const gs_learned_params &p)
     if (p.screen > 1) return fail(GS_EINVAL, "screen must be 0 or 1");
     if (!(p.lr > 0.f) || !(p.lr < 1.f)) return fail(GS_EINVAL, "lr out of (0, 1)");
     if (p.train_steps > 100000) return fail(GS_EINVAL, "train_steps above 100000");
-    return GS_OK;
+    int a = 0;
+    int64_t q = 0, q2 = 0;
+    return learned_fraction(p, &a, &q, &q2);
 }
 
 size_t gs_workspace_bytes_learned(int64_t n, const gs_learned_params *p)
@@ -905,6 +917,10 @@ size_t gs_workspace_bytes_learned(int64_t n, const gs_learned_params *p)
     if (n < 0) return SIZE_MAX;
     if (n <= 1) return 0;
     if (check_learned_params(q) != GS_OK) return SIZE_MAX;
+    int a = 0;
+    int64_t fq = 0, fq2 = 0;
+    (void)learned_fraction(q, &a, &fq, &fq2);
+    if (fq) return (size_t)gs::plan_f64(n, fq, a, fq2).bytes;
     return (size_t)gs::plan_learned(n, q).bytes;
 }
 
@@ -923,6 +939,17 @@ gs_status gs_learned_sort(double *keys, int64_t n, const gs_learned_params *p, v
     if (n <= 1) {
         if (rep) { memset(rep, 0, sizeof *rep); rep->ram_fraction = 1.0; }
         return GS_OK;
+    }
+    int fa = 0;
+    int64_t fq = 0, fq2 = 0;
+    (void)learned_fraction(q, &fa, &fq, &fq2);
+    if (fq) {
+        // the distribution passes need a half buffer: the plain path at the
+        // caller's fraction sorts instead
+        s = gs_sort_f64_ex(keys, n, GS_ASC_LEFT, q.buffer_fraction, GS_ALGO_AUTO, 0.5, ws, ws_bytes, hip_stream,
+                           rep);
+        if (rep && s == GS_OK) rep->fallback = 3;
+        return s;
     }
     gs::LearnedPlan L = gs::plan_learned(n, q);
     if ((int64_t)ws_bytes < L.bytes || !ws)

@@ -69,6 +69,31 @@ def test_learned_params_checked(field, value, ok):
         assert g.lib.gs_learned_sort(fake, n, ctypes.byref(p), fake, 1 << 30, None, None) == g.GS_EINVAL
 
 
+def test_learned_buffer_fraction():
+    """The learned call's buffer fraction: 0 and >= 0.5 keep the learned
+    path's half buffer; [1/64, 0.5) sizes the plain sort's workspace at that
+    fraction; below 1/64 is unsupported, negative or NaN invalid."""
+    n = 1 << 22
+    p = g.gs_learned_default_params()
+    assert p.buffer_fraction == 0.5
+    half = g.gs_workspace_bytes_learned(n, p)
+    p.buffer_fraction = 0.0
+    assert g.gs_workspace_bytes_learned(n, p) == half
+    p.buffer_fraction = 0.9
+    assert g.gs_workspace_bytes_learned(n, p) == half
+    for f in (0.25, 0.1, 1 / 64):
+        p.buffer_fraction = f
+        assert g.gs_workspace_bytes_learned(n, p) == g.gs_workspace_bytes_f64(n, f)
+    fake = ctypes.c_void_p(0x100000)
+    for f, st in ((1 / 64 - 1e-9, g.GS_EUNSUPPORTED), (-0.5, g.GS_EINVAL), (float("nan"), g.GS_EINVAL)):
+        p.buffer_fraction = f
+        assert g.gs_workspace_bytes_learned(n, p) == g.SIZE_MAX
+        assert g.lib.gs_learned_sort(fake, n, ctypes.byref(p), fake, 1 << 30, None, None) == st
+    p.buffer_fraction = 0.25
+    need = g.gs_workspace_bytes_learned(n, p)
+    assert g.lib.gs_learned_sort(fake, n, ctypes.byref(p), fake, need - 1, None, None) == g.GS_EWORKSPACE
+
+
 def _call_f64(keys, n, frac, ws, wsb):
     return g.lib.gs_sort_f64(keys, n, frac, ws, wsb, None, None)
 

@@ -374,6 +374,21 @@ def test_learned_small_input_runs_plain(gs, orc):
         assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
 
 
+@pytest.mark.parametrize("p", [0.25, 1 / 64])
+def test_learned_small_buffer_runs_plain(gs, orc, p):
+    """Below buffer fraction 0.5 the distribution passes' half buffer does not
+    fit: the plain sort at that fraction sorts (fallback 3), within the
+    caller's memory bound."""
+    announce("learned small buffer", p)
+    x = W.learned_pattern("lognormal", (1 << 21) + 77, seed=12)
+    x[::301] = -0.0
+    x[::307] = 0.0
+    t, rep = _learned(gs, x, buffer_fraction=p)
+    assert rep["fallback"] == 3
+    assert rep["ram_fraction"] < 1 + p + 0.02
+    assert np.array_equal(bits(t), bits(orc.sort_f64(x)))
+
+
 def test_learned_gain_over_untrained(gs):
     """On lognormal keys the trained network spreads keys over the buckets
     far more evenly than the untrained linear CDF on the same feature."""

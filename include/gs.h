@@ -267,6 +267,31 @@ gs_status gs_segsort_autotune(const double *keys, int64_t num_keys, const int64_
                               int64_t num_segments, double *scratch, void *ws, size_t ws_bytes,
                               void *hip_stream, int reps, gs_seg_config *best, float *times_ms);
 
+/* Tuning cache (host only): the shape gs_segsort_autotune found, kept per
+   device architecture (e.g. "gfx950") and size class (floor(log2) of
+   num_keys and of num_segments) for the life of the process.  gs_segsort and
+   gs_segsort_ex without a shape use the cached shape of the current device's
+   architecture and the call's size class when there is one and the workspace
+   fits it (gs_workspace_bytes_seg covers every shape); the result never
+   depends on the shape.  When the environment variable GS_TUNE_CACHE names a
+   file, the cache is read from it on first use and written back (JSON:
+   {"entries": [{"arch", "log2_keys", "log2_segments", "short_threads",
+   "short_ipt", "merge_ipt"}, ...]}) after every tuning run. */
+/* 1 and *out filled if the cache holds a shape for arch (NULL: the current
+   device's) and the size class of (num_keys, num_segments), 0 if not, -1 on
+   bad arguments. */
+int gs_tune_cache_get(const char *arch, int64_t num_keys, int64_t num_segments, gs_seg_config *out);
+/* Records a shape (one of gs_seg_config_get's; else GS_EINVAL). */
+gs_status gs_tune_cache_put(const char *arch, int64_t num_keys, int64_t num_segments, const gs_seg_config *cfg);
+/* Reads entries from a file written by gs_tune_cache_save (or the
+   GS_TUNE_CACHE file) into the cache; returns the valid entries read, -1 if
+   the file cannot be read.  Entries that are not valid shapes are skipped. */
+int gs_tune_cache_load(const char *path);
+/* Writes the whole cache; returns the entries written, -1 on failure. */
+int gs_tune_cache_save(const char *path);
+/* Empties the cache (GS_TUNE_CACHE is not read again). */
+void gs_tune_cache_clear(void);
+
 /* Stable ascending sort of n float64 keys with the same result as
    gs_sort_f64, using a small FP32 CDF network trained on the device to bucket
    the keys first.  The key-to-bucket map is verified monotone before any key

@@ -123,6 +123,11 @@ _SIGS = {
                        ctypes.c_void_p], ctypes.c_int),
     "gs_plan_frog3": ([_I64, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p, _I64,
                        ctypes.c_void_p, _I64, ctypes.c_void_p, _I64, ctypes.c_void_p], ctypes.c_int),
+    "gs_tune_cache_get": ([ctypes.c_char_p, _I64, _I64, ctypes.POINTER(GsSegConfig)], ctypes.c_int),
+    "gs_tune_cache_put": ([ctypes.c_char_p, _I64, _I64, ctypes.POINTER(GsSegConfig)], ctypes.c_int),
+    "gs_tune_cache_load": ([ctypes.c_char_p], ctypes.c_int),
+    "gs_tune_cache_save": ([ctypes.c_char_p], ctypes.c_int),
+    "gs_tune_cache_clear": ([], None),
     "gs_plan_seg_steps": ([ctypes.c_void_p, _I64, _I64, _D, ctypes.c_void_p, _I64, ctypes.c_void_p], _I64),
     "gs_workspace_bytes_f64_ex": ([_I64, _D, ctypes.c_int, _D], _SZ),
     "gs_workspace_bytes_kv_ex": ([_I64, _D, ctypes.c_int, _D], _SZ),
@@ -264,6 +269,21 @@ def plan_frog3(n: int, buffer_fraction: float, kv: bool = False, sub_fraction: f
                        spine.ctypes.data, int(counts[1]), leaves.ctypes.data, leaves.shape[0],
                        counts.ctypes.data)
     return trees, spine[: int(counts[1])], leaves, tuple(int(c) for c in counts)
+
+
+def gs_tune_cache_get(num_keys: int, num_segments: int, arch: str | None = None):
+    """The segmented-sort shape the tuning cache holds for this size class
+    (arch None: the current device's), as a dict, or None."""
+    c = GsSegConfig()
+    r = _lib.gs_tune_cache_get(arch.encode() if arch else None, num_keys, num_segments, ctypes.byref(c))
+    if r < 0:
+        raise ValueError("bad tuning-cache query")
+    return dict(short_threads=c.short_threads, short_ipt=c.short_ipt, merge_ipt=c.merge_ipt) if r else None
+
+
+def gs_tune_cache_put(arch: str, num_keys: int, num_segments: int, config):
+    _check(_lib.gs_tune_cache_put(arch.encode(), num_keys, num_segments, ctypes.byref(_seg_config(config))),
+           "gs_tune_cache_put")
 
 
 def plan_seg_steps(offsets, num_keys: int, buffer_fraction: float):

@@ -5,8 +5,11 @@
 #include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -564,6 +567,198 @@ static bool to_seg_config(const gs_seg_config *c, gs::SegConfig *out)
     return c->reserved == 0 && gs::seg_config_valid(*out);
 }
 
+}  // extern "C"
+
+// ---- tuning cache: the shape gs_segsort_autotune found, per device
+// architecture and size class (floor(log2) of the keys and of the segments);
+// kept for the process and, when GS_TUNE_CACHE names a file, read from it on
+// first use and written back after every tuning run -------------------------
+namespace {
+struct TuneKey {
+    std::string arch;
+    int lk, ls;
+    bool operator<(const TuneKey &o) const
+    {
+        return arch != o.arch ? arch < o.arch : lk != o.lk ? lk < o.lk : ls < o.ls;
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, gs_seg_config> g_tune;
+bool g_tune_env_read = false;
+
+int floor_log2(int64_t v)
+{
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+// the current device's architecture name without its feature suffixes
+std::string current_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return std::string();
+    }
+    std::string a(prop.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// value of "key": <int> inside one JSON object's text; false if absent
+bool json_int(const std::string &obj, const char *key, long long *out)
+{
+    const std::string k = std::string("\"") + key + "\"";
+    size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    p = obj.find(':', p + k.size());
+    if (p == std::string::npos) return false;
+    char *end = nullptr;
+    const long long v = strtoll(obj.c_str() + p + 1, &end, 10);
+    if (end == obj.c_str() + p + 1) return false;
+    *out = v;
+    return true;
+}
+
+bool json_str(const std::string &obj, const char *key, std::string *out)
+{
+    const std::string k = std::string("\"") + key + "\"";
+    size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    p = obj.find('"', obj.find(':', p + k.size()));
+    if (p == std::string::npos) return false;
+    const size_t q = obj.find('"', p + 1);
+    if (q == std::string::npos) return false;
+    *out = obj.substr(p + 1, q - p - 1);
+    return true;
+}
+
+// reads {"entries": [{...}, ...]} (every valid entry; others are skipped);
+// caller holds the lock
+int tune_load_locked(const char *path)
+{
+    FILE *f = fopen(path, "rb");
+    if (!f) return -1;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    fclose(f);
+    int n = 0;
+    size_t p = text.find('[');
+    while (p != std::string::npos) {
+        const size_t a = text.find('{', p);
+        if (a == std::string::npos) break;
+        const size_t b = text.find('}', a);
+        if (b == std::string::npos) break;
+        const std::string obj = text.substr(a, b - a + 1);
+        p = b + 1;
+        std::string arch;
+        long long lk, ls, st, si, mi;
+        if (!json_str(obj, "arch", &arch) || !json_int(obj, "log2_keys", &lk) ||
+            !json_int(obj, "log2_segments", &ls) || !json_int(obj, "short_threads", &st) ||
+            !json_int(obj, "short_ipt", &si) || !json_int(obj, "merge_ipt", &mi))
+            continue;
+        gs_seg_config c{(uint32_t)st, (uint32_t)si, (uint32_t)mi, 0u};
+        gs::SegConfig sc;
+        if (!to_seg_config(&c, &sc) || lk < 0 || lk > 62 || ls < 0 || ls > 62) continue;
+        g_tune[TuneKey{arch, (int)lk, (int)ls}] = c;
+        ++n;
+    }
+    return n;
+}
+
+int tune_save_locked(const char *path)
+{
+    FILE *f = fopen(path, "wb");
+    if (!f) return -1;
+    fprintf(f, "{\"entries\": [");
+    bool first = true;
+    for (const auto &kv : g_tune) {
+        fprintf(f, "%s\n  {\"arch\": \"%s\", \"log2_keys\": %d, \"log2_segments\": %d, \"short_threads\": %u, "
+                   "\"short_ipt\": %u, \"merge_ipt\": %u}",
+                first ? "" : ",", kv.first.arch.c_str(), kv.first.lk, kv.first.ls, kv.second.short_threads,
+                kv.second.short_ipt, kv.second.merge_ipt);
+        first = false;
+    }
+    fprintf(f, "\n]}\n");
+    return fclose(f) == 0 ? (int)g_tune.size() : -1;
+}
+
+void tune_env_locked()
+{
+    if (g_tune_env_read) return;
+    g_tune_env_read = true;
+    const char *path = getenv("GS_TUNE_CACHE");
+    if (path && *path) (void)tune_load_locked(path);
+}
+
+bool tune_lookup(const std::string &arch, int64_t n, int64_t nseg, gs_seg_config *out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_locked();
+    const auto it = g_tune.find(TuneKey{arch, floor_log2(n), floor_log2(nseg)});
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_record(const std::string &arch, int64_t n, int64_t nseg, const gs_seg_config &c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_locked();
+    g_tune[TuneKey{arch, floor_log2(n), floor_log2(nseg)}] = c;
+    const char *path = getenv("GS_TUNE_CACHE");
+    if (path && *path) (void)tune_save_locked(path);
+}
+}  // namespace
+
+extern "C" {
+
+int gs_tune_cache_get(const char *arch, int64_t num_keys, int64_t num_segments, gs_seg_config *out)
+{
+    if (!out || num_keys < 1 || num_segments < 1) return -1;
+    const std::string a = arch ? std::string(arch) : current_arch();
+    return tune_lookup(a, num_keys, num_segments, out) ? 1 : 0;
+}
+
+gs_status gs_tune_cache_put(const char *arch, int64_t num_keys, int64_t num_segments, const gs_seg_config *cfg)
+{
+    g_detail.clear();
+    gs::SegConfig sc;
+    if (!arch || !*arch || !cfg || num_keys < 1 || num_segments < 1 || !to_seg_config(cfg, &sc))
+        return fail(GS_EINVAL, "bad tuning-cache entry");
+    tune_record(arch, num_keys, num_segments, *cfg);
+    return GS_OK;
+}
+
+int gs_tune_cache_load(const char *path)
+{
+    if (!path) return -1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_env_read = true;
+    return tune_load_locked(path);
+}
+
+int gs_tune_cache_save(const char *path)
+{
+    if (!path) return -1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return tune_save_locked(path);
+}
+
+void gs_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_env_read = true;
+}
+
 int gs_seg_config_count(void) { return gs::seg_config_count(); }
 
 gs_status gs_seg_config_get(int i, gs_seg_config *out)
@@ -711,6 +906,13 @@ gs_status gs_segsort_ex(double *keys, int64_t num_keys, const int64_t *offsets, 
                         void *hip_stream, gs_report *rep)
 {
     g_detail.clear();
+    // no shape given: the tuned one of this architecture and size class, if
+    // the tuning cache holds one and the workspace fits it
+    gs_seg_config tuned;
+    if (!cfg && num_keys > 0 && num_segments > 0 && tune_lookup(current_arch(), num_keys, num_segments, &tuned)) {
+        const size_t need = gs_workspace_bytes_seg_ex(num_keys, num_segments, buffer_fraction, &tuned);
+        if (need != SIZE_MAX && need <= ws_bytes) cfg = &tuned;
+    }
     gs::SegPlan p{};
     gs_status s = seg_checks(keys, num_keys, offsets, num_segments, buffer_fraction, cfg, ws, ws_bytes, &p);
     if (s != GS_OK) return s;
@@ -810,6 +1012,10 @@ gs_status gs_segsort_autotune(const double *keys, int64_t num_keys, const int64_
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (s == GS_OK && num_keys > 0 && num_segments > 0) {
+        const std::string arch = current_arch();
+        if (!arch.empty()) tune_record(arch, num_keys, num_segments, *best);
+    }
     return s;
 }
 

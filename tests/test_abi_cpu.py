@@ -605,3 +605,51 @@ def test_tile_windows_check_sees_a_wrong_layout():
                 lo, hi = int(got[2 * t]), int(got[2 * t + 1])
                 bad += (((lo, hi) != (w[0], w[-1])) if w else lo <= hi)
     assert bad > 0
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    """The tuning cache keys shapes by architecture and size class
+    (floor(log2) of keys and segments), rejects shapes that are not the
+    tuner's, and survives a save / clear / load round trip; a file's invalid
+    entries are skipped."""
+    g.lib.gs_tune_cache_clear()
+    shapes = g.gs_seg_configs()
+    g.gs_tune_cache_put("gfx950", 1 << 20, 5000, shapes[3])
+    assert g.gs_tune_cache_get((1 << 21) - 1, 4096, arch="gfx950") == shapes[3]   # same class
+    assert g.gs_tune_cache_get(1 << 21, 5000, arch="gfx950") is None               # next class
+    assert g.gs_tune_cache_get(1 << 20, 5000, arch="gfx942") is None
+    bad = g.GsSegConfig(); bad.short_threads, bad.short_ipt, bad.merge_ipt = 512, 16, 12
+    assert g.lib.gs_tune_cache_put(b"gfx950", 1 << 20, 5000, ctypes.byref(bad)) == g.GS_EINVAL
+    path = str(tmp_path / "tune.json")
+    assert g.lib.gs_tune_cache_save(path.encode()) == 1
+    g.lib.gs_tune_cache_clear()
+    assert g.gs_tune_cache_get(1 << 20, 5000, arch="gfx950") is None
+    assert g.lib.gs_tune_cache_load(path.encode()) == 1
+    assert g.gs_tune_cache_get(1 << 20, 5000, arch="gfx950") == shapes[3]
+    with open(path, "w") as f:
+        f.write('{"entries": [{"arch": "gfx950", "log2_keys": 10, "log2_segments": 2, "short_threads": 512, '
+                '"short_ipt": 16, "merge_ipt": 12}, {"arch": "gfx950", "log2_keys": 11, "log2_segments": 2, '
+                '"short_threads": %d, "short_ipt": %d, "merge_ipt": %d}]}'
+                % (shapes[1]["short_threads"], shapes[1]["short_ipt"], shapes[1]["merge_ipt"]))
+    assert g.lib.gs_tune_cache_load(path.encode()) == 1
+    assert g.gs_tune_cache_get(1 << 11, 4, arch="gfx950") == shapes[1]
+    assert g.gs_tune_cache_get(1 << 10, 4, arch="gfx950") is None
+    assert g.lib.gs_tune_cache_load(str(tmp_path / "missing.json").encode()) == -1
+    g.lib.gs_tune_cache_clear()
+
+
+def test_tune_cache_read_from_environment(tmp_path):
+    """GS_TUNE_CACHE names a file read on the cache's first use."""
+    import subprocess
+    import sys
+    shapes = g.gs_seg_configs()
+    path = tmp_path / "tune.json"
+    s = shapes[2]
+    path.write_text('{"entries": [{"arch": "gfx950", "log2_keys": 24, "log2_segments": 12, "short_threads": %d, '
+                    '"short_ipt": %d, "merge_ipt": %d}]}' % (s["short_threads"], s["short_ipt"], s["merge_ipt"]))
+    code = ("import paper_2402_01816_amd as g; c = g.gs_tune_cache_get(1 << 24, 5000, arch='gfx950'); "
+            "print(c['short_threads'], c['short_ipt'], c['merge_ipt'])")
+    env = dict(os.environ, GS_TUNE_CACHE=str(path), PYTHONPATH=ROOT)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == [str(s["short_threads"]), str(s["short_ipt"]), str(s["merge_ipt"])]

@@ -109,6 +109,12 @@ def test_segsort_autotune(gs, orc):
     assert times[gs.gs_seg_configs().index(best)] == min(times.values())
     gs.gs_segsort(keys, offs, config=best)
     _check(orc, keys, x, off)
+    # the tuned shape is kept for this architecture and size class, and a
+    # call without a shape takes it
+    assert gs.gs_tune_cache_get(x.size, off.size - 1) == best
+    keys2 = to_dev(x)
+    gs.gs_segsort(keys2, offs)
+    _check(orc, keys2, x, off)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])

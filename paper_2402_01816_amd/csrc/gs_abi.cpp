@@ -597,17 +597,29 @@ int floor_log2(int64_t v)
 }
 
 // the current device's architecture name without its feature suffixes
+// (queried once per device)
 std::string current_arch()
 {
+    static std::mutex mu;
+    static std::map<int, std::string> names;
     int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return std::string();
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    const auto it = names.find(dev);
+    if (it != names.end()) return it->second;
     hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
         (void)hipGetLastError();
         return std::string();
     }
     std::string a(prop.gcnArchName);
     const size_t c = a.find(':');
-    return c == std::string::npos ? a : a.substr(0, c);
+    if (c != std::string::npos) a = a.substr(0, c);
+    names[dev] = a;
+    return a;
 }
 
 // value of "key": <int> inside one JSON object's text; false if absent

@@ -68,10 +68,11 @@ def _host():
     return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
-def cpu_baseline(n_sample: int, pattern: str, full_n: int = 0):
+def cpu_baseline(n_sample: int, pattern: str, full_n: int = 0, full_reps: int = 1):
     """The CPU oracle (single thread) on a bounded contiguous sample, with the
     C++ standard library's stable sort (single thread) on the same sample
-    beside it; with full_n, both once more on the whole input."""
+    beside it; with full_n, both on the whole input as well, full_reps times
+    each (median reported)."""
     import oracle
     import workloads as W
 
@@ -92,10 +93,17 @@ def cpu_baseline(n_sample: int, pattern: str, full_n: int = 0):
                                "seconds": ds, "sample": "the same keys, one std::stable_sort call"}}
     if full_n:
         x = W.f64_pattern(pattern, full_n, seed=0)
-        df = timed(oracle.sort_f64, x)
-        dsf = timed(oracle.std_stable_sort_f64, x)
-        out["full_input"] = {"n": full_n, "oracle_s": df, "oracle_gkeys_per_s": full_n / df / 1e9,
-                             "std_stable_sort_s": dsf, "std_stable_sort_gkeys_per_s": full_n / dsf / 1e9}
+        dfs, dss = [], []
+        for r in range(max(1, full_reps)):
+            dfs.append(timed(oracle.sort_f64, x))
+            dss.append(timed(oracle.std_stable_sort_f64, x))
+            print(f"cpu full input, run {r + 1}: oracle {dfs[-1]:.2f} s, std::stable_sort {dss[-1]:.2f} s",
+                  file=sys.stderr, flush=True)
+        df = sorted(dfs)[len(dfs) // 2]
+        dsf = sorted(dss)[len(dss) // 2]
+        out["full_input"] = {"n": full_n, "runs": len(dfs), "oracle_s": df, "oracle_s_all": dfs,
+                             "oracle_gkeys_per_s": full_n / df / 1e9, "std_stable_sort_s": dsf,
+                             "std_stable_sort_s_all": dss, "std_stable_sort_gkeys_per_s": full_n / dsf / 1e9}
     return out
 
 
@@ -381,6 +389,8 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time both CPU references on the whole input (about a minute)")
+    ap.add_argument("--cpu-full-reps", type=int, default=1,
+                    help="runs of each CPU reference on the whole input with --cpu-full (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the learned / segmented / key-value side measurements")
@@ -577,7 +587,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2, args.pattern,
-                                           n if args.cpu_full else 0)
+                                           n if args.cpu_full else 0, args.cpu_full_reps)
     print(json.dumps(out))
 
 

@@ -128,6 +128,7 @@ LEARNED_PATTERNS = ("lognormal", "gaussmix", "zipf_ints")
 LEARNED_CALLS = ("plain", "learned", "learned_untrained", "learned_sample_table")
 KV_PATTERNS = ("uniform", "zipf")
 SEG_WORKLOADS = ("100k_arrays", "until_total_16_to_2^20")
+SEG_FRACTIONS = (0.25, 0.1, 1 / 64)     # the segmented sort below the half buffer
 
 
 def extras(gs, torch, W, log2n, dev, sections=SECTIONS, learned_patterns=LEARNED_PATTERNS,
@@ -268,6 +269,24 @@ def _extras_segmented(gs, torch, W, n, dev, stream, workloads, per_array):
             else:
                 graph.replay()
         ms_graph = _time_calls(torch, stream, fn_graph, 3)
+        # smaller buffers: one buffer serving runs of segments in turn
+        fractions = {}
+        for frac in SEG_FRACTIONS:
+            need_f = gs.gs_workspace_bytes_seg(n, nseg, frac)
+            ws_f = torch.empty(need_f + 256, dtype=torch.uint8, device=dev)
+            ws_f = ws_f[(-ws_f.data_ptr()) % 256:][:need_f]
+
+            def fn_frac(i, t, ws_f=ws_f, frac=frac):
+                if t is None:
+                    buf.copy_(x)
+                else:
+                    gs.gs_segsort(buf, o, buffer_fraction=frac, workspace=ws_f)
+            gs.gs_segsort(buf.copy_(x), o, buffer_fraction=frac, workspace=ws_f)
+            ms_f = _time_calls(torch, stream, fn_frac, 3)
+            rep_f = gs.gs_segsort(buf.copy_(x), o, buffer_fraction=frac, workspace=ws_f, report=True)
+            fractions[f"{frac:.4g}"] = {"ms": round(ms_f, 3), "ram_fraction": round(rep_f["ram_fraction"], 5),
+                                        "steps": int(gs.plan_seg_steps(off, n, frac)[0].shape[0])}
+            del ws_f
         buf.copy_(x)
         graph.replay()
         torch.cuda.synchronize()
@@ -283,7 +302,7 @@ def _extras_segmented(gs, torch, W, n, dev, stream, workloads, per_array):
             "ms_tuned_graph": round(ms_graph, 3),
             "gkeys_per_s_tuned": round(n / (ms_best * 1e-3) / 1e9, 3),
             "tuned_shape": best, "shape_ms": {str(i): round(v, 3) for i, v in times.items()},
-            "sorted_spot_check": ok}
+            "buffer_fractions": fractions, "sorted_spot_check": ok}
         segres[name] = row
         if not per_array:
             del x, buf, o, ws
